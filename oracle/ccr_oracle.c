@@ -1,0 +1,569 @@
+/*
+ * Oracle for the resampled cross-correlation statistic rho.
+ *
+ * TEST INFRASTRUCTURE ONLY: loaded by the test suite, the smoke check and the
+ * CPU-baseline leg of the benchmark, never by the product path.  It shares no
+ * code with the HIP library.
+ *
+ * Steps follow the paper in its own order (Meadors et al., "Resampling to
+ * accelerate cross-correlation searches for continuous gravitational waves
+ * from binary systems"):
+ *   plan      Sec. III.B.2 (eqs. n-fft-final, delta lambda_f), App. B (eq. delta-f-load)
+ *   time base Sec. II.A.2 (eqs. t-ssb-equation, tau-equation, circular R/c), Sec. III.A.2
+ *   interp    Sec. III.A.1 (eq. shannon-interp-formula), Sec. III.A.2 (eqs. delta-q-eq,
+ *             q-prime-eq, resampled-time-series-q-eq)
+ *   spectra   Sec. III.B.3-4 (zero-padded DFT of each T_short segment with Phi_in)
+ *   pairs     Sec. III.B.1 (pair selection {L|K})
+ *   rho       Sec. III.B.5 (eq. final-formatted-rho) with App. A normalisation
+ *
+ * Precision: long double (x87, 64-bit mantissa) for the time base and all
+ * phases, double for interpolation, the direct DFT and the pair sum.  Nothing
+ * is blocked, fused or reordered beyond the definitions.
+ *
+ * Parity status per function is listed in the pin tests; every function here
+ * is pinned by at least one closed form, special case or printed value.
+ */
+#include "ccr_oracle.h"
+
+#include <math.h>
+#include <stdlib.h>
+#include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+static const long double PI_L = 3.141592653589793238462643383279502884L;
+
+int cco_num_threads(void) {
+#ifdef _OPENMP
+    return omp_get_max_threads();
+#else
+    return 1;
+#endif
+}
+
+/* ------------------------------------------------------------------ plan */
+
+/* Band plan.
+ *  - load bandwidth, App. B eq. delta-f-load, T_sft read as T_short; drift width from
+ *    eqs. f-drift-eq and delta-f-obs taken at the top of the band with v/c = 1e-4;
+ *  - the series must be sampled at dt = T_short / N_K with N_K >= T_short * df_load;
+ *  - T_coh = 2 T_max + T_short (eq. lag-time-constraint), T_max = R T_short;
+ *  - delta lambda_f = sqrt(6 mu_f / pi) / T_coh (Sec. III.B.2);
+ *  - N_FFT0 = (df_load / delta lambda_f) ceil(delta lambda_f T_coh), N_FFT the next power
+ *    of two (eq. n-fft-final), never below the power of two holding N_K;
+ *  - nu_R = delta lambda_f dt N_FFT; N_f = floor(f_band / delta lambda_f);
+ *  - output bins sit on the FFT grid: kbar(i) = k_lo + floor(nu_R i) with
+ *    k_lo = ceil(-(f_band / 2) T_FFT), frequency f_het + kbar / T_FFT.
+ */
+int cco_plan_band(const cco_problem *p, cco_plan *o) {
+    const cco_band *b = &p->band;
+    if (!(b->t_short > 0.0) || !(b->f_band > 0.0) || b->dirichlet_D < 1 || b->max_lag < 0 ||
+        !(p->dt > 0.0) || !(b->mu_f > 0.0) || !(b->orbit_period > 0.0) || b->a_p_max < 0.0 ||
+        p->n_det < 1 || p->n_det > CCO_MAX_DET || (b->pairs & 3) == 0)
+        return CCO_EINVAL;
+    const double pi = 3.14159265358979323846;
+    double f_top = b->f_min + b->f_band;
+    double omega = 2.0 * pi / b->orbit_period;
+    double drift = 2.0 * (f_top * 1e-4 + b->a_p_max * omega * f_top);
+    double dfl = (1.0 + 4.0 / (2.0 * b->dirichlet_D + 1.0)) * (b->f_band + drift + 16.0 / b->t_short);
+    double ratio = b->t_short / p->dt;
+    int64_t nk = (int64_t)llround(ratio);
+    if (nk < 1 || fabs(ratio - (double)nk) > 1e-9 * ratio) return CCO_EINVAL;
+    if ((double)nk < b->t_short * dfl * (1.0 - 1e-12)) return CCO_ERANGE;
+    double fh = b->f_min + 0.5 * b->f_band;
+    if (fabs(p->f_het - fh) > 1e-9 * fabs(fh) + 1e-12) return CCO_EINVAL;
+    int64_t n_seg = p->n / nk;
+    if (n_seg < 1) return CCO_EINVAL;
+    double t_coh = (2.0 * b->max_lag + 1.0) * b->t_short;
+    double dlf = sqrt(6.0 * b->mu_f / pi) / t_coh;
+    double nfft0 = (dfl / dlf) * ceil(dlf * t_coh);
+    int64_t ns = 1;
+    while (ns < nk) ns *= 2;
+    int64_t nfft = 1;
+    if (b->n_fft_override > 0) {
+        nfft = b->n_fft_override;
+        if (nfft % ns != 0) return CCO_EINVAL;
+    } else {
+        while ((double)nfft < nfft0) nfft *= 2;
+        if (nfft < ns) nfft = ns;
+    }
+    double t_fft = p->dt * (double)nfft;
+    double nu_r = dlf * t_fft;
+    int64_t n_f = (int64_t)floor(b->f_band / dlf);
+    if (n_f < 1) return CCO_ERANGE;
+    int64_t k_lo = (int64_t)ceil(-0.5 * b->f_band * t_fft);
+    o->n_k = nk;
+    o->n_seg = n_seg;
+    o->n_fft = nfft;
+    o->n_f = n_f;
+    o->k_lo = k_lo;
+    o->dt = p->dt;
+    o->f_het = fh;
+    o->df_load = dfl;
+    o->t_coh = t_coh;
+    o->dlambda_f = dlf;
+    o->t_fft = t_fft;
+    o->nu_r = nu_r;
+    return CCO_OK;
+}
+
+int64_t cco_bin_index(const cco_plan *pl, int64_t i) {
+    return pl->k_lo + (int64_t)floor(pl->nu_r * (double)i);
+}
+
+static int validate(const cco_problem *p, cco_plan *pl) {
+    int st = cco_plan_band(p, pl);
+    if (st != CCO_OK) return st;
+    for (int X = 0; X < p->n_det; ++X) {
+        if (!p->x[X] || !p->a[X] || !p->b[X] || !p->noise_var[X]) return CCO_EINVAL;
+        for (int64_t K = 0; K < pl->n_seg; ++K)
+            if (!(p->noise_var[X][K] > 0.0)) return CCO_EINVAL;
+    }
+    return CCO_OK;
+}
+
+/* ------------------------------------------------------------- time base */
+
+/* Detector position r(t) and velocity, light-seconds, equatorial frame:
+ * circular Earth orbit in the ecliptic (tilted by the obliquity about x) plus
+ * rotation of a site on a spherical Earth.  e(t) = r(t).n enters
+ * t_SSB = t + r.n (eq. t-ssb-equation). */
+static void earth_delay_l(const cco_problem *p, int det, long double t, long double *e, long double *ed) {
+    const cco_sky *s = &p->sky;
+    long double n[3] = {cosl(s->ra) * cosl(s->dec), sinl(s->ra) * cosl(s->dec), sinl(s->dec)};
+    long double wo = 2.0L * PI_L / s->year_s;
+    long double lam = s->orbit_phase0 + wo * t;
+    long double ce = cosl(s->obliquity), se = sinl(s->obliquity);
+    long double cl = cosl(lam), sl = sinl(lam);
+    long double ro[3] = {s->au_s * cl, s->au_s * sl * ce, s->au_s * sl * se};
+    long double vo[3] = {-s->au_s * wo * sl, s->au_s * wo * cl * ce, s->au_s * wo * cl * se};
+    long double wd = 2.0L * PI_L / s->sidereal_day_s;
+    long double g = s->gmst0 + wd * t + p->lon[det];
+    long double cla = cosl(p->lat[det]), sla = sinl(p->lat[det]);
+    long double rr[3] = {s->re_s * cla * cosl(g), s->re_s * cla * sinl(g), s->re_s * sla};
+    long double vr[3] = {-s->re_s * wd * cla * sinl(g), s->re_s * wd * cla * cosl(g), 0.0L};
+    *e = n[0] * (ro[0] + rr[0]) + n[1] * (ro[1] + rr[1]) + n[2] * (ro[2] + rr[2]);
+    if (ed) *ed = n[0] * (vo[0] + vr[0]) + n[1] * (vo[1] + vr[1]) + n[2] * (vo[2] + vr[2]);
+}
+
+double cco_earth_delay(const cco_problem *p, int det, double t) {
+    long double e;
+    earth_delay_l(p, det, t, &e, NULL);
+    return (double)e;
+}
+
+/* Forward map tau(t) - t = r.n - a_p sin(Omega (t_SSB - T_asc)), circular orbit,
+ * orbital phase taken at the SSB time (eqs. t-ssb-equation, tau-equation). */
+static long double forward_offset_l(const cco_problem *p, int det, long double ap, long double tasc,
+                                    long double period, long double t) {
+    long double e;
+    earth_delay_l(p, det, t, &e, NULL);
+    long double om = 2.0L * PI_L / period;
+    return e - ap * sinl(om * (t + e - tasc));
+}
+
+double cco_forward_offset(const cco_problem *p, int det, const double tmpl[3], double t) {
+    return (double)forward_offset_l(p, det, tmpl[0], tmpl[1], tmpl[2], t);
+}
+
+/* Inverse map (Sec. III.A.2, t(tau) as the functional inverse of tau(t)): the
+ * delay Delta = t - tau of source time tau solves
+ *   G(Delta) = Delta + e(tau + Delta) - a_p sin(Omega (tau + Delta + e(tau + Delta) - T_asc)) = 0
+ * by Newton iteration in long double, started from guess, iterated until the
+ * step is below 1e-15 s and then twice more. */
+static long double solve_delay(const cco_problem *p, int det, long double ap, long double tasc,
+                               long double period, long double tau, long double guess) {
+    long double om = 2.0L * PI_L / period;
+    long double D = guess;
+    int extra = 0;
+    for (int it = 0; it < 100; ++it) {
+        long double t = tau + D, e, ed;
+        earth_delay_l(p, det, t, &e, &ed);
+        long double th = om * (t + e - tasc);
+        long double G = D + e - ap * sinl(th);
+        long double Gp = 1.0L + ed - ap * om * cosl(th) * (1.0L + ed);
+        long double step = G / Gp;
+        D -= step;
+        if (fabsl(step) < 1e-15L) {
+            if (++extra >= 2) break;
+        }
+    }
+    return D;
+}
+
+static long double crude_guess(const cco_problem *p, int det, long double ap, long double tasc,
+                               long double period, long double tau) {
+    long double e;
+    earth_delay_l(p, det, tau, &e, NULL);
+    return -e + ap * sinl(2.0L * PI_L / period * (tau - tasc));
+}
+
+int cco_delay(const cco_problem *p, int det, const double tmpl[3], int64_t r, double *hi, double *lo) {
+    if (det < 0 || det >= p->n_det) return CCO_EINVAL;
+    long double tau = (long double)p->t0 + (long double)r * (long double)p->dt;
+    long double g = crude_guess(p, det, tmpl[0], tmpl[1], tmpl[2], tau);
+    long double D = solve_delay(p, det, tmpl[0], tmpl[1], tmpl[2], tau, g);
+    *hi = (double)D;
+    *lo = (double)(D - (long double)*hi);
+    return CCO_OK;
+}
+
+/* Gap mask (reading of Sec. III.B: gaps are zero-padded and get zero weight):
+ * m_r = valid(j*_r) with j*_r taken on the Earth-only map (a_p = 0), so the mask
+ * and the normalisation do not depend on the template. */
+static void earth_only_mask(const cco_problem *p, const cco_plan *pl, int det, uint8_t *m) {
+    int64_t nr = pl->n_seg * pl->n_k;
+    long double guess = 0.0L;
+    for (int64_t r = 0; r < nr; ++r) {
+        long double tau = (long double)p->t0 + (long double)r * (long double)p->dt;
+        if (r == 0) guess = crude_guess(p, det, 0.0L, 0.0L, 1.0L, tau);
+        long double D = solve_delay(p, det, 0.0L, 0.0L, 1.0L, tau, guess);
+        guess = D;
+        int64_t j = r + (int64_t)floorl(D / (long double)p->dt + 0.5L);
+        uint8_t v = 0;
+        if (j >= 0 && j < p->n) v = p->valid[det] ? (p->valid[det][j] ? 1 : 0) : 1;
+        m[r] = v;
+    }
+}
+
+int cco_valid_fraction(const cco_problem *p, double *phi) {
+    cco_plan pl;
+    int st = cco_plan_band(p, &pl);
+    if (st) return st;
+    int64_t nr = pl.n_seg * pl.n_k;
+    for (int X = 0; X < p->n_det; ++X) {
+        uint8_t *m = (uint8_t *)malloc((size_t)nr);
+        if (!m) return CCO_ENOMEM;
+        earth_only_mask(p, &pl, X, m);
+        for (int64_t K = 0; K < pl.n_seg; ++K) {
+            int64_t c = 0;
+            for (int64_t s = 0; s < pl.n_k; ++s) c += m[K * pl.n_k + s];
+            phi[X * pl.n_seg + K] = (double)c / (double)pl.n_k;
+        }
+        free(m);
+    }
+    return CCO_OK;
+}
+
+/* --------------------------------------------------------- interpolation */
+
+/* Window of the Shannon formula (Sec. III.A.1): Hamming of length 2D+1.
+ * window 0: indexed by tap n = j - j* in [-D, D], w = 0.54 - 0.46 cos(2 pi (n + D) / (2D));
+ * window 1: evaluated at the continuous offset d, w = 0.54 + 0.46 cos(pi d / (D + 1)). */
+static long double window_w(int D, int win, int n, long double d) {
+    if (win == 0) return 0.54L - 0.46L * cosl(2.0L * PI_L * (long double)(n + D) / (2.0L * D));
+    return 0.54L + 0.46L * cosl(PI_L * d / (D + 1.0L));
+}
+
+/* sinc(d) = sin(pi d) / (pi d), sinc(0) = 1. */
+static long double sinc_l(long double d) {
+    if (d == 0.0L) return 1.0L;
+    return sinl(PI_L * d) / (PI_L * d);
+}
+
+/* Resampled series of detector det for one template (eqs. delta-q-eq, q-prime-eq,
+ * resampled-time-series-q-eq):
+ *   tau_r = t0 + r dt on the source lattice (same spacing and origin as the input);
+ *   Delta_r = t(tau_r) - tau_r;  j* = round-half-up((t_r - t0) / dt) = r + floor(Delta_r/dt + 1/2);
+ *   delta_j = (t_r - t_j) / dt;  xhat = sum_{j=j*-D}^{j*+D} w sinc(delta_j) x'_j  (taps outside
+ *   the data or in gaps read zero);
+ *   y_r = m_r exp(+2 pi i f_h Delta_r) xhat  (heterodyne correction exp(-i 2 pi f_h Dt*),
+ *   Dt* = tau - t(tau)). */
+static int resample_det(const cco_problem *p, const cco_plan *pl, int det, const double tmpl[3],
+                        const uint8_t *mask, double *y, int64_t *jstar, double *offset) {
+    int64_t nr = pl->n_seg * pl->n_k;
+    int D = p->band.dirichlet_D, win = p->band.window;
+    const float *x = p->x[det];
+    const uint8_t *val = p->valid[det];
+    long double guess = 0.0L;
+    for (int64_t r = 0; r < nr; ++r) {
+        long double tau = (long double)p->t0 + (long double)r * (long double)p->dt;
+        if (r == 0) guess = crude_guess(p, det, tmpl[0], tmpl[1], tmpl[2], tau);
+        long double Dl = solve_delay(p, det, tmpl[0], tmpl[1], tmpl[2], tau, guess);
+        guess = Dl;
+        long double q = Dl / (long double)p->dt;
+        int64_t k = (int64_t)floorl(q + 0.5L);
+        int64_t js = r + k;
+        long double dc = q - (long double)k;
+        double re = 0.0, im = 0.0;
+        for (int n = -D; n <= D; ++n) {
+            int64_t j = js + n;
+            if (j < 0 || j >= p->n) continue;
+            if (val && !val[j]) continue;
+            long double d = dc - (long double)n;
+            double w = (double)(window_w(D, win, n, d) * sinc_l(d));
+            re += w * (double)x[2 * j];
+            im += w * (double)x[2 * j + 1];
+        }
+        long double psi = (long double)p->f_het * Dl;
+        psi -= floorl(psi);
+        double c = (double)cosl(2.0L * PI_L * psi), s = (double)sinl(2.0L * PI_L * psi);
+        double m = mask[r] ? 1.0 : 0.0;
+        y[2 * r] = m * (c * re - s * im);
+        y[2 * r + 1] = m * (s * re + c * im);
+        if (jstar) jstar[r] = js;
+        if (offset) offset[r] = (double)dc;
+    }
+    return CCO_OK;
+}
+
+int cco_resample(const cco_problem *p, int det, const double tmpl[3], double *y,
+                 int64_t *jstar, double *offset, uint8_t *mask_out) {
+    cco_plan pl;
+    int st = validate(p, &pl);
+    if (st) return st;
+    if (det < 0 || det >= p->n_det) return CCO_EINVAL;
+    int64_t nr = pl.n_seg * pl.n_k;
+    uint8_t *m = (uint8_t *)malloc((size_t)nr);
+    if (!m) return CCO_ENOMEM;
+    earth_only_mask(p, &pl, det, m);
+    st = resample_det(p, &pl, det, tmpl, m, y, jstar, offset);
+    if (mask_out) memcpy(mask_out, m, (size_t)nr);
+    free(m);
+    return st;
+}
+
+/* ---------------------------------------------------------------- spectra */
+
+static double *twiddles(int64_t nfft) {
+    double *tw = (double *)malloc(sizeof(double) * 2 * (size_t)nfft);
+    if (!tw) return NULL;
+    for (int64_t j = 0; j < nfft; ++j) {
+        long double a = -2.0L * PI_L * (long double)j / (long double)nfft;
+        tw[2 * j] = (double)cosl(a);
+        tw[2 * j + 1] = (double)sinl(a);
+    }
+    return tw;
+}
+
+static int64_t bin_mod(const cco_plan *pl, int64_t i) {
+    int64_t k = cco_bin_index(pl, i) % pl->n_fft;
+    return k < 0 ? k + pl->n_fft : k;
+}
+
+/* Tier R spectra (Sec. III.B.3-4): zero-padded DFT of segment K starting at
+ * r_B = K N_K, referenced to the series origin (Phi_in folded into the kernel):
+ *   F_XK(i) = (sigma_XK sqrt(N_K))^-1 sum_{s<N_K} y_{r_B+s} exp(-2 pi i kbar_i (r_B + s) / N_FFT),
+ * the phase index (kbar (r_B + s)) mod N_FFT kept as an exact integer. */
+static void spectra_from_series(const cco_problem *p, const cco_plan *pl, int det, const double *y,
+                                const double *tw, const int64_t *bins, int64_t nb, double *F) {
+    int64_t nk = pl->n_k, nfft = pl->n_fft;
+    for (int64_t K = 0; K < pl->n_seg; ++K) {
+        double scale = 1.0 / (sqrt(p->noise_var[det][K]) * sqrt((double)nk));
+        int64_t rb = K * nk;
+        for (int64_t ii = 0; ii < nb; ++ii) {
+            int64_t kb = bin_mod(pl, bins ? bins[ii] : ii);
+            int64_t idx = (kb * rb) % nfft;
+            double re = 0.0, im = 0.0;
+            for (int64_t s = 0; s < nk; ++s) {
+                const double *yy = y + 2 * (rb + s);
+                double c = tw[2 * idx], sn = tw[2 * idx + 1];
+                re += yy[0] * c - yy[1] * sn;
+                im += yy[0] * sn + yy[1] * c;
+                idx += kb;
+                if (idx >= nfft) idx -= nfft;
+            }
+            double *o = F + 2 * ((det * pl->n_seg + K) * nb + ii);
+            o[0] = re * scale;
+            o[1] = im * scale;
+        }
+    }
+}
+
+/* Tier D spectra (App. A, eq. from-here-resamp; Sec. III.B.5 frame invariance):
+ * no interpolation; each raw detector sample j is demodulated with the exact
+ * phase model and assigned to the segment holding its source time:
+ *   F^D_XK(i) = (sigma sqrt(N_K))^-1 sum_{j: tau(t_j) in K} valid_j x'_j
+ *               exp(-2 pi i [nu_i (tau(t_j) - t0) - f_h Delta_j]),  nu_i = kbar_i / T_FFT. */
+static void spectra_direct(const cco_problem *p, const cco_plan *pl, int det, const double tmpl[3],
+                           const int64_t *bins, int64_t nb, double *F) {
+    int64_t nk = pl->n_k, nfft = pl->n_fft;
+    memset(F + 2 * det * pl->n_seg * nb, 0, sizeof(double) * 2 * (size_t)(pl->n_seg * nb));
+    for (int64_t j = 0; j < p->n; ++j) {
+        if (p->valid[det] && !p->valid[det][j]) continue;
+        long double t = (long double)p->t0 + (long double)j * (long double)p->dt;
+        long double off = forward_offset_l(p, det, tmpl[0], tmpl[1], tmpl[2], t); /* tau - t */
+        long double u = (long double)j + off / (long double)p->dt;                /* (tau - t0)/dt */
+        int64_t K = (int64_t)floorl(u / (long double)nk);
+        if (K < 0 || K >= pl->n_seg) continue;
+        double scale = 1.0 / (sqrt(p->noise_var[det][K]) * sqrt((double)nk));
+        double xr = p->x[det][2 * j], xi = p->x[det][2 * j + 1];
+        for (int64_t ii = 0; ii < nb; ++ii) {
+            int64_t kb = bin_mod(pl, bins ? bins[ii] : ii);
+            int64_t kfull = cco_bin_index(pl, bins ? bins[ii] : ii);
+            /* cycles = kbar j / N_FFT + kbar off / (N_FFT dt) + f_h off, with Delta_j = -off */
+            long double cyc = (long double)((kb * (j % nfft)) % nfft) / (long double)nfft +
+                              (long double)kfull * off / ((long double)nfft * (long double)p->dt) +
+                              (long double)p->f_het * off;
+            cyc -= floorl(cyc);
+            double c = (double)cosl(2.0L * PI_L * cyc), s = -(double)sinl(2.0L * PI_L * cyc);
+            double *o = F + 2 * ((det * pl->n_seg + K) * nb + ii);
+            o[0] += scale * (xr * c - xi * s);
+            o[1] += scale * (xr * s + xi * c);
+        }
+    }
+}
+
+int cco_spectra(const cco_problem *p, const double tmpl[3], int tier, const int64_t *bins,
+                int64_t n_bins, double *F) {
+    cco_plan pl;
+    int st = validate(p, &pl);
+    if (st) return st;
+    int64_t nb = bins ? n_bins : pl.n_f;
+    for (int64_t ii = 0; ii < nb; ++ii)
+        if (bins && (bins[ii] < 0 || bins[ii] >= pl.n_f)) return CCO_EINVAL;
+    int64_t nr = pl.n_seg * pl.n_k;
+    double *tw = twiddles(pl.n_fft);
+    double *y = (double *)malloc(sizeof(double) * 2 * (size_t)nr);
+    uint8_t *m = (uint8_t *)malloc((size_t)nr);
+    if (!tw || !y || !m) {
+        free(tw); free(y); free(m);
+        return CCO_ENOMEM;
+    }
+    for (int X = 0; X < p->n_det; ++X) {
+        if (tier == 0) {
+            earth_only_mask(p, &pl, X, m);
+            resample_det(p, &pl, X, tmpl, m, y, NULL, NULL);
+            spectra_from_series(p, &pl, X, y, tw, bins, nb, F);
+        } else {
+            spectra_direct(p, &pl, X, tmpl, bins, nb, F);
+        }
+    }
+    free(tw); free(y); free(m);
+    return CCO_OK;
+}
+
+/* ------------------------------------------------------------------ pairs */
+
+/* Pair set P (Sec. III.B.1): cross-detector pairs X < Y with |K - L| <= R, and
+ * same-detector pairs with K < L <= K + R (no auto-correlation); each unordered
+ * pair once. */
+static int pair_in_set(int pairs, int R, int X, int64_t K, int Y, int64_t L) {
+    if ((pairs & CCO_PAIRS_CROSS) && X < Y && llabs(K - L) <= R) return 1;
+    if ((pairs & CCO_PAIRS_SAME) && X == Y && L > K && L <= K + R) return 1;
+    return 0;
+}
+
+int64_t cco_pair_count(const cco_problem *p) {
+    cco_plan pl;
+    if (cco_plan_band(p, &pl)) return -1;
+    int R = p->band.max_lag;
+    int64_t c = 0;
+    for (int X = 0; X < p->n_det; ++X)
+        for (int64_t K = 0; K < pl.n_seg; ++K)
+            for (int Y = 0; Y < p->n_det; ++Y)
+                for (int64_t L = K - R; L <= K + R; ++L)
+                    if (L >= 0 && L < pl.n_seg && pair_in_set(p->band.pairs, R, X, K, Y, L)) ++c;
+    return c;
+}
+
+/* Normalisation (Sec. III.B.5 and App. A): N^2 = sum_P A_XK A_YL + 2 C_XK C_YL + B_XK B_YL
+ * with hat a = a / sigma, A = hat a^2 phi, B = hat b^2 phi, C = hat a hat b phi, where phi is
+ * the valid fraction of the segment (gaps carry zero weight).  This gives Var rho = 1 for
+ * unit-variance segment spectra. */
+static double norm_from_phi(const cco_problem *p, const cco_plan *pl, const double *phi) {
+    int R = p->band.max_lag;
+    long double acc = 0.0L;
+    for (int X = 0; X < p->n_det; ++X)
+        for (int64_t K = 0; K < pl->n_seg; ++K)
+            for (int Y = 0; Y < p->n_det; ++Y)
+                for (int64_t L = K - R; L <= K + R; ++L) {
+                    if (L < 0 || L >= pl->n_seg || !pair_in_set(p->band.pairs, R, X, K, Y, L)) continue;
+                    double sK = sqrt(p->noise_var[X][K]), sL = sqrt(p->noise_var[Y][L]);
+                    double aK = p->a[X][K] / sK, bK = p->b[X][K] / sK;
+                    double aL = p->a[Y][L] / sL, bL = p->b[Y][L] / sL;
+                    double fK = phi[X * pl->n_seg + K], fL = phi[Y * pl->n_seg + L];
+                    double AK = aK * aK * fK, BK = bK * bK * fK, CK = aK * bK * fK;
+                    double AL = aL * aL * fL, BL = bL * bL * fL, CL = aL * bL * fL;
+                    acc += (long double)AK * AL + 2.0L * CK * CL + (long double)BK * BL;
+                }
+    return (double)sqrtl(acc);
+}
+
+double cco_norm(const cco_problem *p) {
+    cco_plan pl;
+    if (validate(p, &pl)) return -1.0;
+    double *phi = (double *)malloc(sizeof(double) * (size_t)(p->n_det * pl.n_seg));
+    if (!phi) return -1.0;
+    cco_valid_fraction(p, phi);
+    double N = norm_from_phi(p, &pl, phi);
+    free(phi);
+    return N;
+}
+
+/* rho_i = sqrt(2) Re sum_P (hat a_XK hat a_YL + hat b_XK hat b_YL) conj(F_XK(i)) F_YL(i) / N
+ * (eq. final-formatted-rho with the geometric weight of eq. geometric-filter; the 1/10 and
+ * the 2/S factors cancel against the normalisation).  rho = 0 when N = 0. */
+static void rho_from_spectra(const cco_problem *p, const cco_plan *pl, const double *F, int64_t nb,
+                             double N, double *rho) {
+    int R = p->band.max_lag;
+    for (int64_t ii = 0; ii < nb; ++ii) {
+        double acc = 0.0;
+        for (int X = 0; X < p->n_det; ++X)
+            for (int64_t K = 0; K < pl->n_seg; ++K)
+                for (int Y = 0; Y < p->n_det; ++Y)
+                    for (int64_t L = K - R; L <= K + R; ++L) {
+                        if (L < 0 || L >= pl->n_seg || !pair_in_set(p->band.pairs, R, X, K, Y, L)) continue;
+                        double sK = sqrt(p->noise_var[X][K]), sL = sqrt(p->noise_var[Y][L]);
+                        double W = (p->a[X][K] / sK) * (p->a[Y][L] / sL) + (p->b[X][K] / sK) * (p->b[Y][L] / sL);
+                        const double *fk = F + 2 * ((X * pl->n_seg + K) * nb + ii);
+                        const double *fl = F + 2 * ((Y * pl->n_seg + L) * nb + ii);
+                        acc += W * (fk[0] * fl[0] + fk[1] * fl[1]);
+                    }
+        rho[ii] = (N > 0.0) ? sqrt(2.0) * acc / N : 0.0;
+    }
+}
+
+int cco_rho(const cco_problem *p, const double *tmpl, int64_t n_tmpl, int tier,
+            const int64_t *bins, int64_t n_bins, double *rho) {
+    cco_plan pl;
+    int st = validate(p, &pl);
+    if (st) return st;
+    int64_t nb = bins ? n_bins : pl.n_f;
+    for (int64_t ii = 0; ii < nb; ++ii)
+        if (bins && (bins[ii] < 0 || bins[ii] >= pl.n_f)) return CCO_EINVAL;
+    int64_t nr = pl.n_seg * pl.n_k;
+    int Q = p->n_det;
+    uint8_t *masks = (uint8_t *)malloc((size_t)(Q * nr));
+    double *phi = (double *)malloc(sizeof(double) * (size_t)(Q * pl.n_seg));
+    double *tw = twiddles(pl.n_fft);
+    if (!masks || !phi || !tw) {
+        free(masks); free(phi); free(tw);
+        return CCO_ENOMEM;
+    }
+#pragma omp parallel for schedule(static)
+    for (int X = 0; X < Q; ++X) earth_only_mask(p, &pl, X, masks + X * nr);
+    for (int X = 0; X < Q; ++X)
+        for (int64_t K = 0; K < pl.n_seg; ++K) {
+            int64_t c = 0;
+            for (int64_t s = 0; s < pl.n_k; ++s) c += masks[X * nr + K * pl.n_k + s];
+            phi[X * pl.n_seg + K] = (double)c / (double)pl.n_k;
+        }
+    double N = norm_from_phi(p, &pl, phi);
+    int fail = 0;
+#pragma omp parallel for schedule(dynamic, 1)
+    for (int64_t t = 0; t < n_tmpl; ++t) {
+        double *y = (double *)malloc(sizeof(double) * 2 * (size_t)nr);
+        double *F = (double *)malloc(sizeof(double) * 2 * (size_t)(Q * pl.n_seg * nb));
+        if (!y || !F) {
+            free(y); free(F);
+#pragma omp atomic write
+            fail = 1;
+            continue;
+        }
+        for (int X = 0; X < Q; ++X) {
+            if (tier == 0) {
+                resample_det(p, &pl, X, tmpl + 3 * t, masks + X * nr, y, NULL, NULL);
+                spectra_from_series(p, &pl, X, y, tw, bins, nb, F);
+            } else {
+                spectra_direct(p, &pl, X, tmpl + 3 * t, bins, nb, F);
+            }
+        }
+        rho_from_spectra(p, &pl, F, nb, N, rho + t * nb);
+        free(y);
+        free(F);
+    }
+    free(masks); free(phi); free(tw);
+    return fail ? CCO_ENOMEM : CCO_OK;
+}

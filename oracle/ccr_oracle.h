@@ -1,0 +1,101 @@
+/*
+ * Oracle for the resampled cross-correlation statistic rho (test infrastructure).
+ *
+ * THIS IS TEST INFRASTRUCTURE, NOT PART OF THE PRODUCT.  Only the test suite,
+ * the smoke check and the CPU-baseline leg of the benchmark may load it.  It
+ * shares no code with the HIP library.
+ *
+ * A plain, slow, obviously-correct CPU implementation: long double for the
+ * time base and every phase, double for interpolation, the DFT (a direct sum,
+ * no FFT) and the pair sum (explicit pair loops).  Each function names the
+ * passage of the paper it follows.  Times are seconds after a common epoch.
+ */
+#ifndef CCR_ORACLE_H
+#define CCR_ORACLE_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define CCO_MAX_DET 8
+#define CCO_PAIRS_CROSS 1
+#define CCO_PAIRS_SAME 2
+
+enum { CCO_OK = 0, CCO_EINVAL = -1, CCO_ENOMEM = -2, CCO_ERANGE = -5 };
+
+typedef struct {
+    double ra, dec;                 /* source direction (rad) */
+    double au_s, re_s;              /* orbit radius, Earth radius (light-seconds) */
+    double obliquity;               /* rad */
+    double year_s, sidereal_day_s;  /* orbital and rotation periods (s) */
+    double orbit_phase0, gmst0;     /* ecliptic longitude and sidereal angle at the epoch (rad) */
+} cco_sky;
+
+typedef struct {
+    double f_min, f_band, t_short;
+    int max_lag;          /* R: T_max = R * T_short */
+    int dirichlet_D;      /* D taps each side */
+    int window;           /* 0: Hamming indexed by tap; 1: Hamming at the continuous offset */
+    int n_fft_override;   /* 0: eq. n-fft-final; else N_FFT (multiple of the pow2 >= N_K) */
+    double mu_f;          /* frequency mismatch */
+    int pairs;            /* CCO_PAIRS_CROSS | CCO_PAIRS_SAME */
+    double a_p_max;       /* largest a_p (sizes the Doppler wings) */
+    double orbit_period;  /* P used for the wing width */
+} cco_band;
+
+typedef struct {
+    int64_t n_k, n_seg, n_fft, n_f, k_lo;
+    double dt, f_het, df_load, t_coh, dlambda_f, t_fft, nu_r;
+} cco_plan;
+
+typedef struct {
+    cco_sky sky;
+    cco_band band;
+    int n_det;
+    double lat[CCO_MAX_DET], lon[CCO_MAX_DET];
+    double t0, dt;                          /* common sample lattice t_q = t0 + q dt */
+    int64_t n;                              /* samples per detector */
+    double f_het;
+    const float *x[CCO_MAX_DET];            /* interleaved complex, n each */
+    const uint8_t *valid[CCO_MAX_DET];      /* n each, or NULL = all valid */
+    const double *a[CCO_MAX_DET], *b[CCO_MAX_DET], *noise_var[CCO_MAX_DET];  /* n_seg each */
+} cco_problem;
+
+int cco_plan_band(const cco_problem *p, cco_plan *out);
+/* frequency index kbar of output bin i (may be negative) */
+int64_t cco_bin_index(const cco_plan *pl, int64_t i);
+
+/* Earth Roemer delay r(t).n for detector det at time t. */
+double cco_earth_delay(const cco_problem *p, int det, double t);
+/* Forward map: tau(t) - t for the template (a_p, T_asc, P) (eqs. t-ssb-equation, tau-equation). */
+double cco_forward_offset(const cco_problem *p, int det, const double tmpl[3], double t);
+/* Delay Delta_r = t_r - tau_r of source sample r (inverse map, long double Newton).
+   Writes Delta as hi + lo doubles. */
+int cco_delay(const cco_problem *p, int det, const double tmpl[3], int64_t r, double *hi, double *lo);
+
+/* Resampled series of one detector for one template: y (2 * n_seg * n_k doubles,
+   interleaved), optional jstar / offset / mask per sample (may be NULL). */
+int cco_resample(const cco_problem *p, int det, const double tmpl[3], double *y,
+                 int64_t *jstar, double *offset, uint8_t *mask);
+/* Segment valid fractions phi[det][K] (n_det * n_seg). */
+int cco_valid_fraction(const cco_problem *p, double *phi);
+/* Per-segment spectra F[det][K][i] (2 * n_det * n_seg * n_bins doubles), tier 0 = resampled
+   (method steps), tier 1 = direct detector-frame demodulation with no interpolation.
+   bins: indices into 0..n_f-1, or NULL for all. */
+int cco_spectra(const cco_problem *p, const double tmpl[3], int tier, const int64_t *bins,
+                int64_t n_bins, double *F);
+/* Normalisation sqrt(sum_P A A + 2 C C + B B). */
+double cco_norm(const cco_problem *p);
+/* Number of pairs in P. */
+int64_t cco_pair_count(const cco_problem *p);
+/* rho[t][i] for n_tmpl templates (rows a_p, T_asc, P), OpenMP over templates. */
+int cco_rho(const cco_problem *p, const double *tmpl, int64_t n_tmpl, int tier,
+            const int64_t *bins, int64_t n_bins, double *rho);
+int cco_num_threads(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif
