@@ -1,0 +1,232 @@
+"""Throughput of the resampled cross-correlation hot path on one MI355X.
+
+One step = one ccr_compute_rho over every orbital template and output bin of the workload
+(time base, resampling, segment FFTs, pair sum), inputs resident in HBM, output on device.
+
+Workload "band" (default): 2 detectors, 120 days with 30 % seeded gaps, T_short = 600 s,
+0.1 Hz band at 200 Hz, 4096 orbital templates (64 a_p in [1, 2] lt-s x 64 T_asc over
++-1000 s), lag-0 cross-detector pairs, Gaussian noise + 10 injections.  The value is
+rho evaluations (templates x bins) per second of the split-precision path (FP64 time base and
+phases, FP32 interpolation / FFT / pair products); the plain FP64 path (one template per
+launch sequence) is timed beside it on a bounded template subset.
+
+Prints one JSON line.  Also: --profile-steps N runs N untimed steps only (for rocprofv3),
+--copy-calibration runs a 1 GiB device copy (for scaling HBM counters).
+"""
+
+import argparse
+import hashlib
+import json
+import os
+import re
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "ρ evaluations (templates×freq bins)/s, FP32-batched vs plain FP64 at ≤1e-4 rel err"
+HBM_PEAK_GBS = 8000.0
+FP64_PEAK_TFLOPS = 78.6
+FP32_PEAK_TFLOPS = 157.3
+
+WORKLOADS = {
+    "band": "2 detectors, 120 d, 30% gaps, T_short 600 s, 0.1 Hz at 200 Hz, 4096 templates "
+            "(64 a_p x 64 T_asc), lag 0 cross-detector pairs, noise + 10 injections",
+    "tiny": "2 detectors, 2 d, T_short 360 s, 0.25 Hz at 100 Hz, 64 templates, same-time pairs",
+    "large": "2 detectors, 240 d, T_short 1440 s, lag 4, 0.25 Hz at 400 Hz, 100200 templates",
+}
+
+
+def kernel_source_hash():
+    h = hashlib.sha256()
+    for f in ("ccr_kernels.hip", "ccr_internal.h"):
+        h.update(open(os.path.join(ROOT, "paper_1712_06515_amd", "csrc", f), "rb").read())
+    return h.hexdigest()[:16]
+
+
+def read_traffic(kernel, workload):
+    """HBM bytes per launch from the committed rocprofv3 counter summary, if it was taken on the
+    current kernel source; else None."""
+    path = os.path.join(ROOT, "profiles", f"traffic_{kernel}_{workload}.txt")
+    if not os.path.exists(path):
+        return None
+    kv = {}
+    for line in open(path):
+        m = re.match(r"^(\w+)\s*=\s*(\S+)", line)
+        if m:
+            kv[m.group(1)] = m.group(2)
+    if kv.get("kernel_source_sha") != kernel_source_hash():
+        return None
+    try:
+        return float(kv["hbm_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
+
+
+def cpu_baseline(ds, seconds_target=20.0):
+    """The oracle timed on the host's cores over a bounded sample of templates (all bins)."""
+    import numpy as np
+    import oracle
+    o = oracle.Oracle(ds)
+    nthreads = oracle.num_threads()
+    n_f = o.plan().n_f
+    rng = np.random.default_rng(5)
+    idx = rng.choice(len(ds.templates), size=min(len(ds.templates), max(1, nthreads)), replace=False)
+    t0 = time.perf_counter()
+    o.rho(ds.templates[idx[:1]])
+    one = time.perf_counter() - t0
+    n = len(idx)
+    if one * n / max(1, min(n, nthreads)) > 2.0 * seconds_target:
+        n = 1
+    t0 = time.perf_counter()
+    o.rho(ds.templates[idx[:n]])
+    dt = time.perf_counter() - t0
+    return {"value": n * n_f / dt, "unit": "rho-evals/s", "cores": int(min(nthreads, n)) if n > 1 else 1,
+            "kind": "oracle",
+            "sample": f"{n} random templates x all {n_f} bins of the same workload ({dt:.1f} s wall)"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", default="band", choices=sorted(WORKLOADS))
+    ap.add_argument("--fp64-templates", type=int, default=256,
+                    help="templates timed on the plain FP64 path")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--profile-steps", type=int, default=0)
+    ap.add_argument("--copy-calibration", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py measures one GPU: this build has no multi-GPU path "
+              "(templates shard across GPUs with no exchange; see DESIGN.md)", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    if args.copy_calibration:
+        a = torch.ones(1 << 28, dtype=torch.float32, device="cuda")
+        b = torch.empty_like(a)
+        for _ in range(3):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes": a.numel() * 4}))
+        return
+
+    import synth
+    from paper_1712_06515_amd import Context, PREC_FP64, PREC_SPLIT
+
+    t_gen = time.perf_counter()
+    ds = synth.make_dataset(synth.config(args.workload))
+    print(f"[bench] dataset {args.workload}: {ds.n_det} det x {ds.n} samples, {len(ds.templates)} templates "
+          f"({time.perf_counter() - t_gen:.1f} s)", file=sys.stderr, flush=True)
+    ctx = Context(ds.sky, device=0)
+    bid = ctx.load(ds)
+    info = ctx.band_info(bid)
+    n_t, n_f = info["n_templates"], info["n_f"]
+    out = torch.empty((n_t, n_f), dtype=torch.float32, device="cuda")
+    stream = torch.cuda.current_stream()
+
+    def step(prec=PREC_SPLIT, band=bid, o=out):
+        ctx.compute_rho(band, prec=prec, out_fp64=False, outputs=[o.data_ptr()], stream=stream.cuda_stream)
+
+    if args.profile_steps:
+        for i in range(args.profile_steps):
+            step()
+            torch.cuda.synchronize()
+            print(f"[bench] profile step {i} done", file=sys.stderr, flush=True)
+        return
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    print("[bench] warm-up done", file=sys.stderr, flush=True)
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        step()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ms_per_step = 1e3 * wall / args.steps
+    value = n_t * n_f / (wall / args.steps)
+    print(f"[bench] split path {ms_per_step:.2f} ms/step", file=sys.stderr, flush=True)
+
+    # per-kernel device time (events on the launch stream), separate pass
+    ctx.set_option("timing", 1)
+    ctx.kernel_times(reset=True)
+    for _ in range(args.steps):
+        step()
+    kt = ctx.kernel_times(reset=True)
+    ctx.set_option("timing", 0)
+
+    # plain FP64 path: one template per launch sequence, on a bounded subset
+    nsub = min(args.fp64_templates, n_t)
+    ctx2 = Context(ds.sky, device=0)
+    ctx2.set_option("template_batch", 1)
+    bid2 = ctx2.load(ds, templates=ds.templates[:nsub])
+    out2 = torch.empty((nsub, n_f), dtype=torch.float64, device="cuda")
+
+    def step64():
+        ctx2.compute_rho(bid2, prec=PREC_FP64, out_fp64=True, outputs=[out2.data_ptr()], stream=stream.cuda_stream)
+
+    step64()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    step64()
+    torch.cuda.synchronize()
+    w64 = time.perf_counter() - t0
+    value64 = nsub * n_f / w64
+    print(f"[bench] fp64 plain {1e3 * w64:.1f} ms for {nsub} templates", file=sys.stderr, flush=True)
+
+    # roofline of the dominant kernel
+    name, (ms_tot, nl) = max(kt.items(), key=lambda kv: kv[1][0])
+    avg_ms = ms_tot / max(nl, 1)
+    tb = n_t // max(1, kt["resample"][1] // args.steps) if kt["resample"][1] else n_t
+    # work units per launch: active (detector, segment) entries x templates per launch
+    n_active = info["n_active"]
+    roof = None
+    if name == "resample" and n_active:
+        samples = n_active * info["n_k"] * tb
+        byts = samples * 8.0  # algorithmic: one complex64 written per resampled sample
+        ach = byts / (avg_ms * 1e-3) / 1e9
+        roof = {"kernel": "k_resample", "bound": "hbm", "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": ach / HBM_PEAK_GBS, "traffic": read_traffic("resample", args.workload),
+                "avg_launch_ms": avg_ms, "algorithmic_bytes_per_launch": byts}
+    elif name == "spectra" and n_active:
+        nseg = n_active * tb
+        ns = 1 << (int(info["n_k"]) - 1).bit_length()
+        P = info["n_fft"] // ns
+        flops = nseg * P * (5.0 * ns * np.log2(ns) + 6.0 * ns)
+        ach = flops / (avg_ms * 1e-3) / 1e12
+        roof = {"kernel": "k_spectra", "bound": "alu", "achieved": ach, "peak": FP32_PEAK_TFLOPS,
+                "unit": "TFLOP/s", "frac": ach / FP32_PEAK_TFLOPS, "traffic": read_traffic("spectra", args.workload),
+                "avg_launch_ms": avg_ms, "algorithmic_flops_per_launch": flops}
+    result = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "rho-evals/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_per_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32 (f64 time base and phases)",
+        "data": "synthetic",
+        "config": {"workload": f"{args.workload}: {WORKLOADS[args.workload]}", "templates": n_t, "bins": n_f,
+                   "n_k": info["n_k"], "n_seg": info["n_seg"], "n_fft": info["n_fft"]},
+        "fp64_plain": {"value": value64, "unit": "rho-evals/s", "templates_timed": nsub,
+                       "speedup_split_batched_over_fp64_plain": value / value64},
+        "kernels_ms_per_step": {k: v[0] / args.steps for k, v in kt.items()},
+        "roofline": roof,
+    }
+    if not args.no_cpu_baseline:
+        result["cpu_baseline"] = cpu_baseline(ds)
+    print(json.dumps(result))
+
+
+if __name__ == "__main__":
+    main()

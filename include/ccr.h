@@ -1,0 +1,204 @@
+/*
+ * ccr.h -- C ABI of the MI355X (gfx950) resampled cross-correlation library.
+ *
+ * The library computes the resampled cross-correlation statistic rho of
+ * Meadors, Krishnan, Papa, Whelan and Zhang, "Resampling to accelerate
+ * cross-correlation searches for continuous gravitational waves from binary
+ * systems" (Phys. Rev. D 97, 044017), eq. final-formatted-rho, for every
+ * orbital template (a_p, T_asc, P) of a band and every decimated output
+ * frequency bin at once:
+ *
+ *   1. time base      per source sample tau_r = t0 + r dt: the detector time
+ *                     t_r with tau(t_r) = tau_r, where t_SSB = t + r(t).n
+ *                     (eq. t-ssb-equation) and tau = t_SSB - a_p sin(Omega
+ *                     (t_SSB - T_asc)) (eq. tau-equation, circular orbit);
+ *                     the delay Delta_r = t_r - tau_r;
+ *   2. resampling     windowed-sinc interpolation of the heterodyned series
+ *                     at t_r (eq. shannon-interp-formula, D taps each side,
+ *                     Hamming window of length 2D+1) and the heterodyne
+ *                     correction exp(+2 pi i f_h Delta_r)
+ *                     (eq. resampled-time-series-q-eq);
+ *   3. spectra        zero-padded FFT of each T_short segment, decimated bins
+ *                     kbar = k_lo + floor(nu_R i), phase referenced to the
+ *                     series origin (Phi_in, Sec. III.B.3-4);
+ *   4. pair sum       rho_i = sqrt(2) Re sum_{pairs} W_KL conj(F_K) F_L / N with
+ *                     W_KL = hat a_K hat a_L + hat b_K hat b_L (eq.
+ *                     geometric-filter) over the pair set of Sec. III.B.1 and
+ *                     the normalisation N of App. A.
+ *
+ * Conventions
+ *   - Times are seconds after the context epoch (time 0); angles in radians.
+ *   - Complex samples are interleaved float32 (re, im).
+ *   - Every ccr_set_* call copies its inputs: caller buffers may be freed on
+ *     return.  Outputs are caller-allocated.
+ *   - Every call returns a status; on failure nothing is written to caller
+ *     outputs and ccr_last_error() holds a message.  No C++ exception crosses
+ *     this boundary.
+ *   - One context is not thread-safe; separate contexts are independent.
+ *   - Device work is queued on the given HIP stream (or the context's own
+ *     stream when NULL); outputs are complete after ccr_sync().
+ *   - FP64 results are bitwise reproducible for a given input and plan.
+ */
+#ifndef CCR_H
+#define CCR_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define CCR_ABI_VERSION 1
+#define CCR_MAX_DET 8
+#define CCR_PAIRS_CROSS 1 /* pairs across detectors, |K - L| <= R        */
+#define CCR_PAIRS_SAME 2  /* pairs within a detector, 0 < L - K <= R     */
+
+typedef struct ccr_ctx ccr_ctx;
+
+typedef enum {
+    CCR_OK = 0,
+    CCR_EINVAL = -1,  /* bad argument: null pointer, NaN/Inf, inconsistent sizes or lattices */
+    CCR_ENOMEM = -2,  /* host or device allocation failed */
+    CCR_EDEVICE = -3, /* HIP runtime error */
+    CCR_ESTATE = -4,  /* call order: data, weights or templates missing */
+    CCR_ERANGE = -5,  /* a plan quantity outside what the kernels support */
+    CCR_EUNSUP = -6   /* option not supported */
+} ccr_status;
+
+typedef enum {
+    CCR_PREC_FP64 = 0,  /* time base, interpolation, FFT and pair sum in FP64 */
+    CCR_PREC_SPLIT = 1  /* FP64 time base and phases; FP32 interpolation, FFT and pair products
+                           (pair sums accumulated in FP64) */
+} ccr_precision;
+
+/* Source direction and the analytic Earth model of the detector position r(t):
+ * circular orbit of radius au_s light-seconds in the ecliptic plane (ecliptic
+ * longitude orbit_phase0 + 2 pi t / year_s), ecliptic tilted by `obliquity`;
+ * rotation of a spherical Earth of radius re_s light-seconds with sidereal
+ * angle gmst0 + 2 pi t / sidereal_day_s (Sec. II.A.2, eq. t-ssb-equation,
+ * Roemer term only). */
+typedef struct {
+    double ra, dec;
+    double au_s, re_s;
+    double obliquity;
+    double year_s, sidereal_day_s;
+    double orbit_phase0, gmst0;
+} ccr_sky;
+
+/* Detector site on the spherical Earth (radians). */
+typedef struct {
+    double lat, lon;
+} ccr_site;
+
+/* One analysis band.
+ *   f_min, f_band  output band [f_min, f_min + f_band] (Hz); f_h = f_min + f_band / 2
+ *   t_short        segment length T_short (s)
+ *   max_lag        R, T_max = R T_short (eq. lag-time-constraint)
+ *   dirichlet_D    D interpolation taps on each side (typ. 8)
+ *   window         0: Hamming indexed by tap, w_n = 0.54 - 0.46 cos(2 pi (n + D) / 2D);
+ *                  1: Hamming at the continuous offset d, w = 0.54 + 0.46 cos(pi d / (D + 1))
+ *   n_fft_override 0: N_FFT from eq. n-fft-final; otherwise N_FFT (a multiple of the power of
+ *                  two holding N_K)
+ *   mu_f           frequency mismatch (delta lambda_f = sqrt(6 mu_f / pi) / T_coh)
+ *   pairs          CCR_PAIRS_CROSS | CCR_PAIRS_SAME
+ *   a_p_max, orbit_period  size the Doppler wings of the load bandwidth (App. B,
+ *                  eq. delta-f-load with eqs. f-drift-eq, delta-f-obs, v/c = 1e-4). */
+typedef struct {
+    double f_min, f_band, t_short;
+    int32_t max_lag, dirichlet_D, window, n_fft_override;
+    double mu_f;
+    int32_t pairs;
+    double a_p_max, orbit_period;
+} ccr_band;
+
+/* Plan of a band.  Fields after n_k / dt are valid once every detector has data. */
+typedef struct {
+    int64_t n_k;          /* samples per segment; the series must be sampled at dt = t_short / n_k */
+    int64_t n_seg;        /* M segments (floor(n / n_k)) */
+    int64_t n_fft;        /* N_FFT */
+    int64_t n_f;          /* decimated output bins per template */
+    int64_t k_lo;         /* first FFT bin (signed) */
+    int64_t n_pairs;      /* |P| */
+    int64_t n_det;        /* detectors with data */
+    int64_t n_templates;  /* templates set */
+    int64_t n_active;     /* (detector, segment) entries that take part in a pair and are computed */
+    double dt, f_het, df_load, t_coh, dlambda_f, t_fft, nu_r;
+    double norm;          /* N of App. A (0 when no pair carries weight) */
+} ccr_band_info;
+
+int ccr_abi_version(void);
+
+/* Create a context on HIP device `hip_device`.  `sky` is copied.  hip_device = -1 creates a
+ * host-only context: bands, data, weights, templates and band plans work, every call that
+ * needs a device returns CCR_EDEVICE. */
+ccr_status ccr_create(ccr_ctx **out, int hip_device, const ccr_sky *sky);
+/* Free every host and device resource of the context (waits for queued work). */
+void ccr_destroy(ccr_ctx *ctx);
+/* Message of the last failing call on this context ("" if none).  Valid until the next call. */
+const char *ccr_last_error(const ccr_ctx *ctx);
+
+/* Set a tuning option.  Names: "template_batch" (templates per launch, 0 = auto),
+ * "workspace_mb" (device workspace budget), "fused" (1: fused resample+FFT+pair kernel
+ * when the band allows it, 0: staged kernels), "k_chunk" (segments per pair-sum chunk).
+ * Returns CCR_EUNSUP for an unknown name. */
+ccr_status ccr_set_option(ccr_ctx *ctx, const char *name, int64_t value);
+
+/* Add a band; returns its id and the part of the plan known before data (n_k, dt, f_het,
+ * df_load).  Bands are independent. */
+ccr_status ccr_add_band(ccr_ctx *ctx, const ccr_band *band, int *band_id, ccr_band_info *info);
+
+/* Heterodyned, downsampled complex series of detector `det` (0 <= det < CCR_MAX_DET) for a
+ * band (Sec. III, App. B): x[2q], x[2q+1] = Re, Im of x'(t0 + q dt), q < n.
+ * dt must equal t_short / n_k of the band and satisfy n_k >= t_short df_load (else
+ * CCR_ERANGE); t0 and dt must be the same for every detector of the band; f_het must equal
+ * f_min + f_band / 2; n >= n_k.  `valid` (n bytes, NULL = all valid) marks gaps: invalid
+ * samples are read as zero.  NaN/Inf samples give CCR_EINVAL. */
+ccr_status ccr_set_data(ccr_ctx *ctx, int band_id, int det, const ccr_site *site, double t0,
+                        double dt, int64_t n, double f_het, const float *x, const uint8_t *valid);
+
+/* Per-segment weights of detector `det` (n_seg = floor(n / n_k) entries each): antenna
+ * functions a_K, b_K at the segment mid-time and the noise variance E|x'|^2 of the
+ * segment (> 0).  hat a = a / sigma (Sec. II.B, eq. geometric-filter). */
+ccr_status ccr_set_weights(ccr_ctx *ctx, int band_id, int det, int64_t n_seg, const double *a,
+                           const double *b, const double *noise_var);
+
+/* Orbital templates of a band: n triples (a_p [s], T_asc [s after epoch], P [s]).
+ * a_p >= 0, P > 0, all finite. */
+ccr_status ccr_set_templates(ccr_ctx *ctx, int band_id, int64_t n, const double *a_p,
+                             const double *t_asc, const double *period);
+
+/* Full plan of a band; bin_freqs (n_f doubles, may be NULL) receives f_het + kbar_i / T_FFT. */
+ccr_status ccr_get_band_info(ccr_ctx *ctx, int band_id, ccr_band_info *info, double *bin_freqs);
+
+/* rho for every template and bin of each listed band.  rho_out[b] points to
+ * n_templates * n_f values (row-major, template-major) of double (out_fp64 = 1) or float,
+ * in device memory (out_on_device = 1, must stay valid until ccr_sync) or host memory
+ * (written before the call returns).  hip_stream: a hipStream_t or NULL. */
+ccr_status ccr_compute_rho(ccr_ctx *ctx, ccr_precision prec, int n_bands, const int *band_ids,
+                           void *const *rho_out, int out_on_device, int out_fp64, void *hip_stream);
+
+/* Wait for all work queued by this context. */
+ccr_status ccr_sync(ccr_ctx *ctx);
+
+/* Device time of the kernels ccr_compute_rho launched while option "timing" was 1, summed
+ * since the last ccr_reset_kernel_times (HIP events recorded on the launch stream around each
+ * launch).  kernel: 0 time base + resampling, 1 segment spectra, 2 pair sum, 3 final scaling.
+ * Waits for the recorded launches to finish. */
+ccr_status ccr_kernel_time(ccr_ctx *ctx, int kernel, double *ms, int64_t *launches);
+ccr_status ccr_reset_kernel_times(ccr_ctx *ctx);
+
+/* Stage outputs of one template, for kernel-level checks.  Host buffers.
+ * ccr_resample_series: y of detector det, n_seg * n_k complex values (double pairs for
+ *   CCR_PREC_FP64, float pairs for CCR_PREC_SPLIT) -- step 2 including the gap mask.
+ *   Segments that no pair uses are returned as zeros.
+ * ccr_segment_spectra: F[det][K][i], n_det * n_seg * n_f complex values, normalised by
+ *   1 / (sigma_XK sqrt(n_k)) -- step 3.  Segments that no pair uses are zeros. */
+ccr_status ccr_resample_series(ccr_ctx *ctx, ccr_precision prec, int band_id,
+                               int64_t template_index, int det, void *y_out);
+ccr_status ccr_segment_spectra(ccr_ctx *ctx, ccr_precision prec, int band_id,
+                               int64_t template_index, void *f_out);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* CCR_H */

@@ -1,0 +1,991 @@
+// Host side of the C ABI (include/ccr.h): argument validation, the band planner,
+// template-independent set-up tables (Earth anchors, gap masks, weights, normalisation,
+// work lists), device memory and kernel sequencing.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <memory>
+#include <new>
+#include <string>
+#include <thread>
+#include <vector>
+
+#include "ccr.h"
+#include "ccr_internal.h"
+
+using namespace ccr;
+
+namespace {
+
+constexpr double kPi = 3.14159265358979323846;
+constexpr long double kPiL = 3.141592653589793238462643383279502884L;
+
+// ------------------------------------------------------------------ device buffers
+
+struct DevBuf {
+    void *p = nullptr;
+    size_t bytes = 0;
+    DevBuf() = default;
+    DevBuf(const DevBuf &) = delete;
+    DevBuf &operator=(const DevBuf &) = delete;
+    ~DevBuf() { release(); }
+    void release() {
+        if (p) (void)hipFree(p);
+        p = nullptr;
+        bytes = 0;
+    }
+    hipError_t ensure(size_t n) {
+        if (n <= bytes && p) return hipSuccess;
+        release();
+        if (n == 0) return hipSuccess;
+        hipError_t e = hipMalloc(&p, n);
+        if (e != hipSuccess) {
+            p = nullptr;
+            return e;
+        }
+        bytes = n;
+        return hipSuccess;
+    }
+    template <typename T> T *as() const { return static_cast<T *>(p); }
+};
+
+struct DetData {
+    bool has_data = false, has_weights = false;
+    ccr_site site{};
+    double t0 = 0, dt = 0, f_het = 0;
+    int64_t n = 0;
+    std::vector<float> x;        // interleaved, zero where invalid
+    std::vector<uint8_t> valid;  // empty = all valid
+    std::vector<double> a, b, nv;
+};
+
+struct Plan {
+    int64_t n_k = 0, n_seg = 0, n_fft = 0, n_f = 0, k_lo = 0, n_s = 0, P = 0, n_pairs = 0;
+    double dt = 0, f_het = 0, df_load = 0, t_coh = 0, dlf = 0, t_fft = 0, nu_r = 0, norm = 0;
+};
+
+struct Band {
+    ccr_band p{};
+    double df_load = 0;
+    int64_t n_k_min = 0;
+    DetData det[CCR_MAX_DET];
+    std::vector<double> tmpl;  // kTmplStride per template
+    std::vector<double> tmpl_raw;
+    int64_t n_tmpl = 0;
+    bool prepared = false;
+    Plan plan;
+    int Q = 0;
+    // device tables
+    DevBuf d_x, d_mask, d_anchor, d_earth, d_win64, d_win32, d_tw64, d_tw32, d_bin_m, d_bin_p,
+        d_bin_kb, d_segw, d_active, d_work, d_tmpl;
+    int n_work = 0;
+    std::vector<double> freqs;
+    std::vector<uint8_t> active;
+};
+
+}  // namespace
+
+struct ccr_ctx {
+    int device = 0;
+    ccr_sky sky{};
+    std::vector<std::unique_ptr<Band>> bands;
+    std::string err;
+    hipStream_t stream = nullptr;
+    int64_t opt_template_batch = 0;
+    int64_t opt_workspace_mb = 16384;
+    int64_t opt_k_chunk = 0;
+    int64_t opt_fused = 1;
+    int64_t opt_timing = 0;
+    DevBuf ws_y, ws_F, ws_part, ws_out;
+    struct Timed {
+        int kind;
+        hipEvent_t a, b;
+    };
+    std::vector<Timed> timed;
+    double kt_ms[4] = {0, 0, 0, 0};
+    int64_t kt_n[4] = {0, 0, 0, 0};
+};
+
+namespace {
+
+ccr_status fail(ccr_ctx *c, ccr_status st, const char *fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    if (c) c->err = buf;
+    return st;
+}
+
+#define HIP_OK(ctx, expr)                                                                    \
+    do {                                                                                     \
+        hipError_t e_ = (expr);                                                              \
+        if (e_ != hipSuccess)                                                                \
+            return fail(ctx, e_ == hipErrorOutOfMemory ? CCR_ENOMEM : CCR_EDEVICE, "%s: %s", \
+                        #expr, hipGetErrorString(e_));                                       \
+    } while (0)
+
+bool finite_all(const double *v, int64_t n) {
+    for (int64_t i = 0; i < n; ++i)
+        if (!std::isfinite(v[i])) return false;
+    return true;
+}
+
+template <typename F> void parallel_for(int64_t n, F &&f) {
+    unsigned hw = std::thread::hardware_concurrency();
+    int64_t nt = std::max<int64_t>(1, std::min<int64_t>(hw ? hw : 4, 16));
+    if (n < 4 * nt) nt = 1;
+    if (nt == 1) {
+        for (int64_t i = 0; i < n; ++i) f(i);
+        return;
+    }
+    std::vector<std::thread> th;
+    for (int64_t t = 0; t < nt; ++t)
+        th.emplace_back([&, t] {
+            for (int64_t i = t; i < n; i += nt) f(i);
+        });
+    for (auto &x : th) x.join();
+}
+
+// ------------------------------------------------------------------ planner
+
+// Load bandwidth of App. B (eq. delta-f-load) with T_sft read as T_short, the Doppler wings of
+// eqs. f-drift-eq and delta-f-obs at the top of the band, v/c = 1e-4.
+double load_bandwidth(const ccr_band &b) {
+    double f_top = b.f_min + b.f_band;
+    double omega = 2.0 * kPi / b.orbit_period;
+    double drift = 2.0 * (f_top * 1e-4 + b.a_p_max * omega * f_top);
+    return (1.0 + 4.0 / (2.0 * b.dirichlet_D + 1.0)) * (b.f_band + drift + 16.0 / b.t_short);
+}
+
+// Plan of Sec. III.B.2: T_coh = (2R+1) T_short, delta lambda_f = sqrt(6 mu_f / pi) / T_coh,
+// N_FFT0 = (df_load / dlf) ceil(dlf T_coh), N_FFT the next power of two (at least the power of
+// two n_s holding N_K), nu_R = dlf T_FFT, N_f = floor(f_band / dlf), output bins on the FFT grid
+// kbar_i = k_lo + floor(nu_R i), k_lo = ceil(-f_band T_FFT / 2).
+ccr_status make_plan(ccr_ctx *c, const Band &B, Plan &pl) {
+    const ccr_band &b = B.p;
+    pl.n_k = B.det[0].dt > 0 ? llround(b.t_short / B.det[0].dt) : 0;
+    pl.dt = B.det[0].dt;
+    pl.n_seg = B.det[0].n / pl.n_k;
+    pl.f_het = b.f_min + 0.5 * b.f_band;
+    pl.df_load = B.df_load;
+    pl.t_coh = (2.0 * b.max_lag + 1.0) * b.t_short;
+    pl.dlf = std::sqrt(6.0 * b.mu_f / kPi) / pl.t_coh;
+    double nfft0 = (pl.df_load / pl.dlf) * std::ceil(pl.dlf * pl.t_coh);
+    int64_t ns = 1;
+    while (ns < pl.n_k) ns *= 2;
+    int64_t nfft = 1;
+    if (b.n_fft_override > 0) {
+        nfft = b.n_fft_override;
+        if (nfft % ns != 0)
+            return fail(c, CCR_EINVAL, "n_fft_override %lld is not a multiple of %lld", (long long)nfft,
+                        (long long)ns);
+    } else {
+        while ((double)nfft < nfft0) nfft *= 2;
+        if (nfft < ns) nfft = ns;
+    }
+    pl.n_s = ns;
+    pl.n_fft = nfft;
+    pl.P = nfft / ns;
+    pl.t_fft = pl.dt * (double)nfft;
+    pl.nu_r = pl.dlf * pl.t_fft;
+    pl.n_f = (int64_t)std::floor(b.f_band / pl.dlf);
+    pl.k_lo = (int64_t)std::ceil(-0.5 * b.f_band * pl.t_fft);
+    if (pl.n_f < 1) return fail(c, CCR_ERANGE, "band holds no output bin");
+    if (ns > 2048) return fail(c, CCR_ERANGE, "segment of %lld samples exceeds the 2048-point LDS FFT", (long long)pl.n_k);
+    if (nfft > (1 << 22)) return fail(c, CCR_ERANGE, "N_FFT %lld too large", (long long)nfft);
+    if (pl.n_seg < 1) return fail(c, CCR_EINVAL, "fewer samples than one segment");
+    if (pl.n_seg * (int64_t)CCR_MAX_DET >= (1ll << 31) || pl.n_seg * pl.n_k >= (1ll << 40))
+        return fail(c, CCR_ERANGE, "too many segments");
+    return CCR_OK;
+}
+
+int64_t bin_index(const Plan &pl, int64_t i) { return pl.k_lo + (int64_t)std::floor(pl.nu_r * (double)i); }
+
+// ------------------------------------------------------------------ Earth model
+
+// r(t).n = C + A_o cos(theta_o) + A_d cos(theta_d):
+//   orbit:    au [n_x cos(lam) + (n_y cos eps + n_z sin eps) sin(lam)] = A_o cos(lam - lam_n)
+//   rotation: re [cos(lat) cos(dec) cos(g + lon - ra) + sin(lat) sin(dec)]
+struct EarthModel {
+    long double A_o, lam_n, w_o, ph_o, A_d, w_d, ph_d, C;
+    long double theta_o(long double t) const { return ph_o + w_o * t - lam_n; }
+    long double theta_d(long double t) const { return ph_d + w_d * t; }
+    long double e(long double t) const { return C + A_o * cosl(theta_o(t)) + A_d * cosl(theta_d(t)); }
+    long double ed(long double t) const {
+        return -A_o * w_o * sinl(theta_o(t)) - A_d * w_d * sinl(theta_d(t));
+    }
+};
+
+EarthModel earth_model(const ccr_sky &s, const ccr_site &site) {
+    EarthModel m;
+    long double nx = cosl(s.ra) * cosl(s.dec), ny = sinl(s.ra) * cosl(s.dec), nz = sinl(s.dec);
+    long double q = ny * cosl(s.obliquity) + nz * sinl(s.obliquity);
+    m.A_o = s.au_s * sqrtl(nx * nx + q * q);
+    m.lam_n = atan2l(q, nx);
+    m.w_o = 2.0L * kPiL / s.year_s;
+    m.ph_o = s.orbit_phase0;
+    m.A_d = s.re_s * cosl(site.lat) * cosl(s.dec);
+    m.w_d = 2.0L * kPiL / s.sidereal_day_s;
+    m.ph_d = s.gmst0 + site.lon - s.ra;
+    m.C = s.re_s * sinl(site.lat) * sinl(s.dec);
+    return m;
+}
+
+// Detector time t with t + r(t).n = tau (Earth-only inverse), long double Newton.
+long double earth_inverse(const EarthModel &m, long double tau) {
+    long double t = tau - m.e(tau);
+    for (int it = 0; it < 8; ++it) {
+        long double g = t + m.e(t) - tau;
+        long double step = g / (1.0L + m.ed(t));
+        t -= step;
+        if (fabsl(step) < 1e-16L) break;
+    }
+    return t;
+}
+
+// Host copy of the anchored Earth-only delay (a_p = 0) used for the gap mask: eta solves
+// eta + de(u + eta) = 0 where de(x) = r(t_a + x).n - r(t_a).n.
+void sincos_small_h(double x, double &s, double &cm1) {
+    const double x2 = x * x;
+    s = x * (1.0 - x2 * (1.0 / 6.0) * (1.0 - x2 * (1.0 / 20.0) * (1.0 - x2 * (1.0 / 42.0) *
+             (1.0 - x2 * (1.0 / 72.0) * (1.0 - x2 * (1.0 / 110.0))))));
+    cm1 = -x2 * 0.5 * (1.0 - x2 * (1.0 / 12.0) * (1.0 - x2 * (1.0 / 30.0) * (1.0 - x2 * (1.0 / 56.0) *
+             (1.0 - x2 * (1.0 / 90.0) * (1.0 - x2 * (1.0 / 132.0))))));
+}
+
+double earth_only_eta(const EarthConst &ec, const Anchor &an, double u) {
+    double eta = 0.0;
+    for (int it = 0; it < 3; ++it) {
+        const double x = u + eta;
+        double so, co, sd, cd;
+        sincos_small_h(ec.w_o * x, so, co);
+        sincos_small_h(ec.w_d * x, sd, cd);
+        const double de = ec.A_o * (an.c_o * co - an.s_o * so) + ec.A_d * (an.c_d * cd - an.s_d * sd) + an.rho_a;
+        const double dep = -ec.A_o * ec.w_o * (an.c_o * so + std::fma(an.s_o, co, an.s_o)) -
+                           ec.A_d * ec.w_d * (an.c_d * sd + std::fma(an.s_d, cd, an.s_d));
+        eta -= (eta + de) / (1.0 + dep);
+    }
+    return eta;
+}
+
+// ------------------------------------------------------------------ band preparation
+
+template <typename T>
+ccr_status upload(ccr_ctx *c, DevBuf &d, const std::vector<T> &h) {
+    HIP_OK(c, d.ensure(std::max<size_t>(sizeof(T), h.size() * sizeof(T))));
+    if (!h.empty()) HIP_OK(c, hipMemcpy(d.p, h.data(), h.size() * sizeof(T), hipMemcpyHostToDevice));
+    return CCR_OK;
+}
+
+ccr_status check_ready(ccr_ctx *c, Band &B) {
+    int Q = 0;
+    for (int X = 0; X < CCR_MAX_DET; ++X)
+        if (B.det[X].has_data) Q = X + 1;
+    if (Q == 0) return fail(c, CCR_ESTATE, "no detector data set");
+    for (int X = 0; X < Q; ++X) {
+        if (!B.det[X].has_data) return fail(c, CCR_ESTATE, "detector %d has no data", X);
+        if (!B.det[X].has_weights) return fail(c, CCR_ESTATE, "detector %d has no weights", X);
+        if (B.det[X].n != B.det[0].n)
+            return fail(c, CCR_EINVAL, "detectors hold different sample counts");
+    }
+    B.Q = Q;
+    return CCR_OK;
+}
+
+ccr_status prepare(ccr_ctx *c, Band &B) {
+    if (B.prepared) return CCR_OK;
+    ccr_status st = check_ready(c, B);
+    if (st) return st;
+    Plan pl;
+    st = make_plan(c, B, pl);
+    if (st) return st;
+    const int Q = B.Q;
+    const int64_t M = pl.n_seg, nk = pl.n_k, nr = M * nk;
+    for (int X = 0; X < Q; ++X)
+        if ((int64_t)B.det[X].a.size() != M)
+            return fail(c, CCR_EINVAL, "detector %d weights hold %zu segments, plan has %lld", X,
+                        B.det[X].a.size(), (long long)M);
+    const double dt = pl.dt, t0 = B.det[0].t0;
+    // Earth constants and per-segment anchors
+    std::vector<EarthConst> earth(Q);
+    std::vector<Anchor> anchors((size_t)Q * M);
+    std::vector<EarthModel> em(Q);
+    for (int X = 0; X < Q; ++X) {
+        em[X] = earth_model(c->sky, B.det[X].site);
+        earth[X] = EarthConst{(double)em[X].A_o, (double)em[X].w_o, (double)em[X].A_d, (double)em[X].w_d};
+    }
+    parallel_for((int64_t)Q * M, [&](int64_t e) {
+        const int X = (int)(e / M);
+        const int64_t K = e % M;
+        const EarthModel &m = em[X];
+        long double tau_a = (long double)t0 + ((long double)(K * nk) + 0.5L * (long double)nk) * (long double)dt;
+        // t_a and tau_a are representable long doubles, so D_a = tau_a - t_a is exact; the
+        // rounding of t_a leaves the residual rho_a = r(t_a).n - D_a, kept explicitly.
+        long double ta = earth_inverse(m, tau_a);
+        long double Da = tau_a - ta;
+        long double rho = m.e(ta) - Da;
+        long double psi = -(long double)pl.f_het * Da;
+        psi -= floorl(psi);
+        long double tho = m.theta_o(ta), thd = m.theta_d(ta);
+        anchors[e] = Anchor{(double)cosl(tho), (double)sinl(tho), (double)cosl(thd), (double)sinl(thd),
+                            (double)Da, (double)rho, (double)psi};
+    });
+    // gap mask of source samples (Earth-only centre tap) and valid fractions
+    std::vector<uint8_t> mask((size_t)Q * nr);
+    std::vector<double> phi((size_t)Q * M);
+    const int64_t n = B.det[0].n;
+    parallel_for((int64_t)Q * M, [&](int64_t e) {
+        const int X = (int)(e / M);
+        const int64_t K = e % M;
+        const Anchor &an = anchors[e];
+        const std::vector<uint8_t> &val = B.det[X].valid;
+        int64_t cnt = 0;
+        for (int64_t s = 0; s < nk; ++s) {
+            const int64_t r = K * nk + s;
+            const double u = ((double)s - 0.5 * (double)nk) * dt;
+            const double eta = earth_only_eta(earth[X], an, u);
+            const double q = (eta - an.D_a) / dt;
+            const int64_t j = r + (int64_t)std::floor(q + 0.5);
+            uint8_t m = 0;
+            if (j >= 0 && j < n) m = val.empty() ? 1 : (val[j] ? 1 : 0);
+            mask[(size_t)X * nr + r] = m;
+            cnt += m;
+        }
+        phi[e] = (double)cnt / (double)nk;
+    });
+    // weights, pair set, normalisation, activity
+    std::vector<SegWeight> segw((size_t)Q * M);
+    for (int X = 0; X < Q; ++X)
+        for (int64_t K = 0; K < M; ++K) {
+            const double sg = std::sqrt(B.det[X].nv[K]);
+            segw[X * M + K] = SegWeight{B.det[X].a[K] / sg, B.det[X].b[K] / sg, 1.0 / (sg * std::sqrt((double)nk))};
+        }
+    const int R = B.p.max_lag;
+    const bool cross = B.p.pairs & CCR_PAIRS_CROSS, same = B.p.pairs & CCR_PAIRS_SAME;
+    std::vector<uint8_t> active((size_t)Q * M, 0);
+    long double nacc = 0.0L;
+    int64_t npairs = 0;
+    for (int X = 0; X < Q; ++X)
+        for (int64_t K = 0; K < M; ++K)
+            for (int Y = 0; Y < Q; ++Y)
+                for (int64_t L = std::max<int64_t>(0, K - R); L <= std::min<int64_t>(M - 1, K + R); ++L) {
+                    bool in = (cross && X < Y) || (same && X == Y && L > K);
+                    if (!in) continue;
+                    ++npairs;
+                    const SegWeight &wk = segw[X * M + K], &wl = segw[Y * M + L];
+                    const double fk = phi[X * M + K], fl = phi[Y * M + L];
+                    if (fk > 0.0 && fl > 0.0) {
+                        active[X * M + K] = 1;
+                        active[Y * M + L] = 1;
+                    }
+                    const double AK = wk.ahat * wk.ahat * fk, BK = wk.bhat * wk.bhat * fk, CK = wk.ahat * wk.bhat * fk;
+                    const double AL = wl.ahat * wl.ahat * fl, BL = wl.bhat * wl.bhat * fl, CL = wl.ahat * wl.bhat * fl;
+                    nacc += (long double)AK * AL + 2.0L * CK * CL + (long double)BK * BL;
+                }
+    pl.norm = (double)sqrtl(nacc);
+    pl.n_pairs = npairs;
+    std::vector<int> work;
+    for (int X = 0; X < Q; ++X)
+        for (int64_t K = 0; K < M; ++K)
+            if (active[X * M + K]) work.push_back((int)(X * M + K));
+    // bins and twiddles
+    std::vector<int> bm(pl.n_f), bp(pl.n_f), bkb(pl.n_f);
+    B.freqs.resize(pl.n_f);
+    for (int64_t i = 0; i < pl.n_f; ++i) {
+        int64_t kb = bin_index(pl, i);
+        B.freqs[i] = pl.f_het + (double)kb / pl.t_fft;
+        int64_t km = kb % pl.n_fft;
+        if (km < 0) km += pl.n_fft;
+        bkb[i] = (int)km;
+        bp[i] = (int)(km % pl.P);
+        bm[i] = (int)(km / pl.P);
+    }
+    std::vector<double2> tw64(pl.n_fft);
+    std::vector<float2> tw32(pl.n_fft);
+    for (int64_t j = 0; j < pl.n_fft; ++j) {
+        long double a = -2.0L * kPiL * (long double)j / (long double)pl.n_fft;
+        tw64[j] = make_double2((double)cosl(a), (double)sinl(a));
+        tw32[j] = make_float2((float)cosl(a), (float)sinl(a));
+    }
+    const int D = B.p.dirichlet_D;
+    std::vector<double> w64(2 * D + 1);
+    std::vector<float> w32(2 * D + 1);
+    for (int nn = -D; nn <= D; ++nn) {
+        long double w = 0.54L - 0.46L * cosl(2.0L * kPiL * (long double)(nn + D) / (2.0L * D));
+        w64[nn + D] = (double)w;
+        w32[nn + D] = (float)w;
+    }
+    B.n_work = (int)work.size();
+    B.active = std::move(active);
+    B.plan = pl;
+    if (c->device < 0) {  // host-only context: planning and validation without device tables
+        B.prepared = true;
+        return CCR_OK;
+    }
+    // device upload
+    std::vector<float2> xs((size_t)Q * n);
+    for (int X = 0; X < Q; ++X)
+        std::memcpy(&xs[(size_t)X * n], B.det[X].x.data(), sizeof(float2) * (size_t)n);
+    if ((st = upload(c, B.d_x, xs))) return st;
+    if ((st = upload(c, B.d_mask, mask))) return st;
+    if ((st = upload(c, B.d_anchor, anchors))) return st;
+    if ((st = upload(c, B.d_earth, earth))) return st;
+    if ((st = upload(c, B.d_win64, w64))) return st;
+    if ((st = upload(c, B.d_win32, w32))) return st;
+    if ((st = upload(c, B.d_tw64, tw64))) return st;
+    if ((st = upload(c, B.d_tw32, tw32))) return st;
+    if ((st = upload(c, B.d_bin_m, bm))) return st;
+    if ((st = upload(c, B.d_bin_p, bp))) return st;
+    if ((st = upload(c, B.d_bin_kb, bkb))) return st;
+    if ((st = upload(c, B.d_segw, segw))) return st;
+    if ((st = upload(c, B.d_active, B.active))) return st;
+    if ((st = upload(c, B.d_work, work))) return st;
+    B.prepared = true;
+    return CCR_OK;
+}
+
+ccr_status prepare_templates(ccr_ctx *c, Band &B) {
+    const Plan &pl = B.plan;
+    const int64_t T = B.n_tmpl;
+    const long double t0 = B.det[0].t0, dt = pl.dt;
+    const long double tseg = (long double)pl.n_k * dt;
+    const long double tau_a0 = t0 + 0.5L * tseg;
+    // Series validity of the in-kernel small-angle expansions (|angle| <= 0.3).
+    const double ld = 0.5 * (double)tseg + 1.0;
+    for (int64_t t = 0; t < T; ++t) {
+        const double ap = B.tmpl_raw[3 * t], P = B.tmpl_raw[3 * t + 2];
+        const double Om = 2.0 * kPi / P;
+        if (Om * (ld + 2.0 * ap + 2.0) > 0.3)
+            return fail(c, CCR_ERANGE, "template %lld: orbit too short for the segment length", (long long)t);
+    }
+    {
+        EarthModel m = earth_model(c->sky, B.det[0].site);
+        if ((double)m.w_d * (ld + 4.0) > 0.3) return fail(c, CCR_ERANGE, "segment too long for the time base");
+    }
+    B.tmpl.assign((size_t)T * kTmplStride, 0.0);
+    for (int64_t t = 0; t < T; ++t) {
+        const long double ap = B.tmpl_raw[3 * t], tasc = B.tmpl_raw[3 * t + 1], P = B.tmpl_raw[3 * t + 2];
+        long double c0 = (tau_a0 - tasc) / P;
+        c0 -= floorl(c0);
+        long double c1 = tseg / P;
+        double *o = &B.tmpl[(size_t)t * kTmplStride];
+        o[0] = (double)ap;
+        o[1] = (double)(2.0L * kPiL / P);
+        o[2] = (double)c0;
+        o[3] = (double)(c0 - (long double)o[2]);
+        o[4] = (double)c1;
+        o[5] = (double)(c1 - (long double)o[4]);
+    }
+    if (c->device < 0) return CCR_OK;
+    return upload(c, B.d_tmpl, B.tmpl);
+}
+
+BandDev band_dev(const Band &B) {
+    const Plan &pl = B.plan;
+    BandDev d;
+    d.Q = B.Q;
+    d.n = B.det[0].n;
+    d.n_k = (int)pl.n_k;
+    d.n_seg = (int)pl.n_seg;
+    d.n_fft = (int)pl.n_fft;
+    d.n_s = (int)pl.n_s;
+    d.P = (int)pl.P;
+    d.n_f = (int)pl.n_f;
+    d.D = B.p.dirichlet_D;
+    d.window = B.p.window;
+    d.R = B.p.max_lag;
+    d.pairs = B.p.pairs;
+    d.dt = pl.dt;
+    d.f_het = pl.f_het;
+    d.x = B.d_x.as<float2>();
+    d.mask = B.d_mask.as<uint8_t>();
+    d.anchors = B.d_anchor.as<Anchor>();
+    d.earth = B.d_earth.as<EarthConst>();
+    d.win64 = B.d_win64.as<double>();
+    d.win32 = B.d_win32.as<float>();
+    d.tw64 = B.d_tw64.as<double2>();
+    d.tw32 = B.d_tw32.as<float2>();
+    d.bin_m = B.d_bin_m.as<int>();
+    d.bin_p = B.d_bin_p.as<int>();
+    d.bin_kb = B.d_bin_kb.as<int>();
+    d.segw = B.d_segw.as<SegWeight>();
+    d.active = B.d_active.as<uint8_t>();
+    d.work = B.d_work.as<int>();
+    d.n_work = B.n_work;
+    return d;
+}
+
+Band *get_band(ccr_ctx *c, int id) {
+    if (id < 0 || id >= (int)c->bands.size()) return nullptr;
+    return c->bands[id].get();
+}
+
+ccr_status ensure_ready(ccr_ctx *c, Band &B) {
+    if (B.n_tmpl == 0 || B.tmpl_raw.empty()) return fail(c, CCR_ESTATE, "no templates set");
+    bool was = B.prepared;
+    ccr_status st = prepare(c, B);
+    if (st) return st;
+    if (!was || B.tmpl.empty()) {
+        st = prepare_templates(c, B);
+        if (st) return st;
+    }
+    return CCR_OK;
+}
+
+// Templates per launch so that the staged buffers stay within the workspace budget.
+int64_t template_batch(ccr_ctx *c, const Band &B, bool fp64) {
+    const Plan &pl = B.plan;
+    const size_t cs = fp64 ? 16 : 8;
+    const size_t per = (size_t)B.Q * pl.n_seg * pl.n_k * cs + (size_t)B.Q * pl.n_seg * pl.n_f * cs;
+    int64_t tb = c->opt_template_batch;
+    if (tb <= 0) {
+        size_t budget = (size_t)c->opt_workspace_mb << 20;
+        tb = (int64_t)std::max<size_t>(1, budget / std::max<size_t>(per, 1));
+    }
+    tb = std::min<int64_t>(tb, 65535);
+    tb = std::min<int64_t>(tb, B.n_tmpl);
+    return std::max<int64_t>(tb, 1);
+}
+
+// Optional per-kernel device timing: events around a launch on its own stream.
+struct LaunchTimer {
+    ccr_ctx *c;
+    int kind;
+    hipStream_t s;
+    hipEvent_t a = nullptr, b = nullptr;
+    LaunchTimer(ccr_ctx *c_, int k, hipStream_t s_) : c(c_), kind(k), s(s_) {
+        if (!c->opt_timing) return;
+        if (hipEventCreate(&a) != hipSuccess || hipEventCreate(&b) != hipSuccess) {
+            a = b = nullptr;
+            return;
+        }
+        (void)hipEventRecord(a, s);
+    }
+    ~LaunchTimer() {
+        if (!a) return;
+        (void)hipEventRecord(b, s);
+        c->timed.push_back({kind, a, b});
+    }
+};
+
+void collect_times(ccr_ctx *c) {
+    for (auto &t : c->timed) {
+        float ms = 0.0f;
+        if (hipEventSynchronize(t.b) == hipSuccess && hipEventElapsedTime(&ms, t.a, t.b) == hipSuccess) {
+            c->kt_ms[t.kind] += ms;
+            c->kt_n[t.kind] += 1;
+        }
+        (void)hipEventDestroy(t.a);
+        (void)hipEventDestroy(t.b);
+    }
+    c->timed.clear();
+}
+
+int k_chunk_for(ccr_ctx *c, const Plan &pl) {
+    int64_t kc = c->opt_k_chunk > 0 ? c->opt_k_chunk : std::min<int64_t>(pl.n_seg, 256);
+    // keep the chunk count within the launch grid's y extent
+    kc = std::max<int64_t>(kc, (pl.n_seg + 65534) / 65535);
+    return (int)kc;
+}
+
+}  // namespace
+
+// ====================================================================== ABI
+
+extern "C" {
+
+int ccr_abi_version(void) { return CCR_ABI_VERSION; }
+
+ccr_status ccr_create(ccr_ctx **out, int hip_device, const ccr_sky *sky) {
+    if (!out || !sky) return CCR_EINVAL;
+    *out = nullptr;
+    const double *sv = &sky->ra;
+    if (!finite_all(sv, sizeof(ccr_sky) / sizeof(double))) return CCR_EINVAL;
+    if (!(sky->year_s > 0) || !(sky->sidereal_day_s > 0) || sky->au_s < 0 || sky->re_s < 0) return CCR_EINVAL;
+    if (hip_device == -1) {  // host-only context
+        ccr_ctx *h = new (std::nothrow) ccr_ctx();
+        if (!h) return CCR_ENOMEM;
+        h->device = -1;
+        h->sky = *sky;
+        *out = h;
+        return CCR_OK;
+    }
+    int ndev = 0;
+    if (hipGetDeviceCount(&ndev) != hipSuccess || ndev == 0) return CCR_EDEVICE;
+    if (hip_device < 0 || hip_device >= ndev) return CCR_EINVAL;
+    if (hipSetDevice(hip_device) != hipSuccess) return CCR_EDEVICE;
+    ccr_ctx *c = new (std::nothrow) ccr_ctx();
+    if (!c) return CCR_ENOMEM;
+    c->device = hip_device;
+    c->sky = *sky;
+    if (hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking) != hipSuccess) {
+        delete c;
+        return CCR_EDEVICE;
+    }
+    *out = c;
+    return CCR_OK;
+}
+
+void ccr_destroy(ccr_ctx *c) {
+    if (!c) return;
+    if (c->device < 0) {
+        delete c;
+        return;
+    }
+    (void)hipSetDevice(c->device);
+    (void)hipDeviceSynchronize();
+    collect_times(c);
+    c->bands.clear();
+    c->ws_y.release();
+    c->ws_F.release();
+    c->ws_part.release();
+    c->ws_out.release();
+    if (c->stream) (void)hipStreamDestroy(c->stream);
+    delete c;
+}
+
+const char *ccr_last_error(const ccr_ctx *c) { return c ? c->err.c_str() : "null context"; }
+
+ccr_status ccr_set_option(ccr_ctx *c, const char *name, int64_t value) {
+    if (!c || !name) return CCR_EINVAL;
+    c->err.clear();
+    std::string k(name);
+    if (value < 0) return fail(c, CCR_EINVAL, "negative option value");
+    if (k == "template_batch") c->opt_template_batch = value;
+    else if (k == "workspace_mb") c->opt_workspace_mb = std::max<int64_t>(value, 64);
+    else if (k == "k_chunk") c->opt_k_chunk = value;
+    else if (k == "fused") c->opt_fused = value;
+    else if (k == "timing") c->opt_timing = value;
+    else return fail(c, CCR_EUNSUP, "unknown option '%s'", name);
+    return CCR_OK;
+}
+
+ccr_status ccr_add_band(ccr_ctx *c, const ccr_band *band, int *band_id, ccr_band_info *info) {
+    if (!c || !band || !band_id) return c ? fail(c, CCR_EINVAL, "null argument") : CCR_EINVAL;
+    c->err.clear();
+    const ccr_band &b = *band;
+    const double dv[] = {b.f_min, b.f_band, b.t_short, b.mu_f, b.a_p_max, b.orbit_period};
+    if (!finite_all(dv, 6)) return fail(c, CCR_EINVAL, "non-finite band field");
+    if (!(b.f_band > 0) || !(b.t_short > 0) || !(b.mu_f > 0) || !(b.orbit_period > 0) || b.a_p_max < 0 ||
+        b.f_min < 0)
+        return fail(c, CCR_EINVAL, "band fields out of range");
+    if (b.dirichlet_D < 1 || b.dirichlet_D > 64) return fail(c, CCR_ERANGE, "dirichlet_D must be 1..64");
+    if (b.max_lag < 0 || b.max_lag > 1024) return fail(c, CCR_ERANGE, "max_lag must be 0..1024");
+    if (b.window != 0 && b.window != 1) return fail(c, CCR_EINVAL, "window must be 0 or 1");
+    if ((b.pairs & 3) == 0 || (b.pairs & ~3)) return fail(c, CCR_EINVAL, "pairs must be a nonzero mask of CROSS|SAME");
+    if (b.n_fft_override < 0) return fail(c, CCR_EINVAL, "negative n_fft_override");
+    try {
+        auto B = std::make_unique<Band>();
+        B->p = b;
+        B->df_load = load_bandwidth(b);
+        B->n_k_min = (int64_t)std::ceil(b.t_short * B->df_load);
+        if (info) {
+            std::memset(info, 0, sizeof *info);
+            info->n_k = B->n_k_min;
+            info->dt = b.t_short / (double)B->n_k_min;
+            info->f_het = b.f_min + 0.5 * b.f_band;
+            info->df_load = B->df_load;
+        }
+        c->bands.push_back(std::move(B));
+        *band_id = (int)c->bands.size() - 1;
+    } catch (const std::bad_alloc &) {
+        return fail(c, CCR_ENOMEM, "out of host memory");
+    }
+    return CCR_OK;
+}
+
+ccr_status ccr_set_data(ccr_ctx *c, int band_id, int det, const ccr_site *site, double t0, double dt,
+                        int64_t n, double f_het, const float *x, const uint8_t *valid) {
+    if (!c) return CCR_EINVAL;
+    c->err.clear();
+    Band *B = get_band(c, band_id);
+    if (!B) return fail(c, CCR_EINVAL, "bad band id %d", band_id);
+    if (det < 0 || det >= CCR_MAX_DET) return fail(c, CCR_EINVAL, "detector index %d out of range", det);
+    if (!site || !x) return fail(c, CCR_EINVAL, "null site or data");
+    if (!std::isfinite(site->lat) || !std::isfinite(site->lon) || !std::isfinite(t0) || !std::isfinite(dt) ||
+        !std::isfinite(f_het))
+        return fail(c, CCR_EINVAL, "non-finite scalar argument");
+    if (!(dt > 0)) return fail(c, CCR_EINVAL, "dt must be positive");
+    const double ratio = B->p.t_short / dt;
+    const int64_t nk = llround(ratio);
+    if (nk < 1 || std::fabs(ratio - (double)nk) > 1e-9 * ratio)
+        return fail(c, CCR_EINVAL, "t_short / dt = %.12g is not an integer", ratio);
+    if ((double)nk < B->p.t_short * B->df_load * (1.0 - 1e-12))
+        return fail(c, CCR_ERANGE, "dt undersamples the load band (%lld < %.6g samples per segment)",
+                    (long long)nk, B->p.t_short * B->df_load);
+    const double fh = B->p.f_min + 0.5 * B->p.f_band;
+    if (std::fabs(f_het - fh) > 1e-9 * std::fabs(fh) + 1e-12)
+        return fail(c, CCR_EINVAL, "f_het %.12g differs from f_min + f_band / 2 = %.12g", f_het, fh);
+    if (n < nk) return fail(c, CCR_EINVAL, "fewer than one segment of samples");
+    if (n > (int64_t)1 << 34) return fail(c, CCR_ERANGE, "series too long");
+    for (int X = 0; X < CCR_MAX_DET; ++X) {
+        if (X == det || !B->det[X].has_data) continue;
+        if (B->det[X].t0 != t0 || B->det[X].dt != dt)
+            return fail(c, CCR_EINVAL, "t0/dt differ from detector %d", X);
+    }
+    for (int64_t i = 0; i < 2 * n; ++i)
+        if (!std::isfinite(x[i])) return fail(c, CCR_EINVAL, "non-finite sample at %lld", (long long)(i / 2));
+    try {
+        DetData &d = B->det[det];
+        d.x.assign(x, x + 2 * n);
+        if (valid) {
+            d.valid.assign(valid, valid + n);
+            for (int64_t i = 0; i < n; ++i)
+                if (!valid[i]) d.x[2 * i] = d.x[2 * i + 1] = 0.0f;
+        } else {
+            d.valid.clear();
+        }
+        d.site = *site;
+        d.t0 = t0;
+        d.dt = dt;
+        d.n = n;
+        d.f_het = f_het;
+        d.has_data = true;
+    } catch (const std::bad_alloc &) {
+        return fail(c, CCR_ENOMEM, "out of host memory");
+    }
+    B->prepared = false;
+    B->tmpl.clear();
+    return CCR_OK;
+}
+
+ccr_status ccr_set_weights(ccr_ctx *c, int band_id, int det, int64_t n_seg, const double *a, const double *b,
+                           const double *noise_var) {
+    if (!c) return CCR_EINVAL;
+    c->err.clear();
+    Band *B = get_band(c, band_id);
+    if (!B) return fail(c, CCR_EINVAL, "bad band id %d", band_id);
+    if (det < 0 || det >= CCR_MAX_DET) return fail(c, CCR_EINVAL, "detector index %d out of range", det);
+    if (!a || !b || !noise_var || n_seg < 1) return fail(c, CCR_EINVAL, "null or empty weights");
+    if (!finite_all(a, n_seg) || !finite_all(b, n_seg) || !finite_all(noise_var, n_seg))
+        return fail(c, CCR_EINVAL, "non-finite weight");
+    for (int64_t k = 0; k < n_seg; ++k)
+        if (!(noise_var[k] > 0)) return fail(c, CCR_EINVAL, "noise variance of segment %lld not positive", (long long)k);
+    try {
+        DetData &d = B->det[det];
+        d.a.assign(a, a + n_seg);
+        d.b.assign(b, b + n_seg);
+        d.nv.assign(noise_var, noise_var + n_seg);
+        d.has_weights = true;
+    } catch (const std::bad_alloc &) {
+        return fail(c, CCR_ENOMEM, "out of host memory");
+    }
+    B->prepared = false;
+    B->tmpl.clear();
+    return CCR_OK;
+}
+
+ccr_status ccr_set_templates(ccr_ctx *c, int band_id, int64_t n, const double *a_p, const double *t_asc,
+                             const double *period) {
+    if (!c) return CCR_EINVAL;
+    c->err.clear();
+    Band *B = get_band(c, band_id);
+    if (!B) return fail(c, CCR_EINVAL, "bad band id %d", band_id);
+    if (n < 1 || !a_p || !t_asc || !period) return fail(c, CCR_EINVAL, "null or empty template arrays");
+    if (!finite_all(a_p, n) || !finite_all(t_asc, n) || !finite_all(period, n))
+        return fail(c, CCR_EINVAL, "non-finite template parameter");
+    for (int64_t i = 0; i < n; ++i)
+        if (a_p[i] < 0 || !(period[i] > 0)) return fail(c, CCR_EINVAL, "template %lld: a_p < 0 or P <= 0", (long long)i);
+    try {
+        B->tmpl_raw.resize((size_t)n * 3);
+        for (int64_t i = 0; i < n; ++i) {
+            B->tmpl_raw[3 * i] = a_p[i];
+            B->tmpl_raw[3 * i + 1] = t_asc[i];
+            B->tmpl_raw[3 * i + 2] = period[i];
+        }
+        B->n_tmpl = n;
+        B->tmpl.clear();
+    } catch (const std::bad_alloc &) {
+        return fail(c, CCR_ENOMEM, "out of host memory");
+    }
+    return CCR_OK;
+}
+
+ccr_status ccr_get_band_info(ccr_ctx *c, int band_id, ccr_band_info *info, double *bin_freqs) {
+    if (!c || !info) return CCR_EINVAL;
+    c->err.clear();
+    Band *B = get_band(c, band_id);
+    if (!B) return fail(c, CCR_EINVAL, "bad band id %d", band_id);
+    if (c->device >= 0) HIP_OK(c, hipSetDevice(c->device));
+    ccr_status st = prepare(c, *B);
+    if (st) return st;
+    const Plan &pl = B->plan;
+    std::memset(info, 0, sizeof *info);
+    info->n_k = pl.n_k;
+    info->n_seg = pl.n_seg;
+    info->n_fft = pl.n_fft;
+    info->n_f = pl.n_f;
+    info->k_lo = pl.k_lo;
+    info->n_pairs = pl.n_pairs;
+    info->n_det = B->Q;
+    info->n_templates = B->n_tmpl;
+    info->n_active = B->n_work;
+    info->dt = pl.dt;
+    info->f_het = pl.f_het;
+    info->df_load = pl.df_load;
+    info->t_coh = pl.t_coh;
+    info->dlambda_f = pl.dlf;
+    info->t_fft = pl.t_fft;
+    info->nu_r = pl.nu_r;
+    info->norm = pl.norm;
+    if (bin_freqs) std::memcpy(bin_freqs, B->freqs.data(), sizeof(double) * (size_t)pl.n_f);
+    return CCR_OK;
+}
+
+ccr_status ccr_compute_rho(ccr_ctx *c, ccr_precision prec, int n_bands, const int *band_ids, void *const *rho_out,
+                           int out_on_device, int out_fp64, void *hip_stream) {
+    if (!c) return CCR_EINVAL;
+    c->err.clear();
+    if (n_bands < 1 || !band_ids || !rho_out) return fail(c, CCR_EINVAL, "no bands or outputs");
+    if (prec != CCR_PREC_FP64 && prec != CCR_PREC_SPLIT) return fail(c, CCR_EINVAL, "bad precision");
+    if (c->device < 0) return fail(c, CCR_EDEVICE, "host-only context");
+    HIP_OK(c, hipSetDevice(c->device));
+    hipStream_t s = hip_stream ? (hipStream_t)hip_stream : c->stream;
+    const bool fp64 = prec == CCR_PREC_FP64;
+    ccr_status st;
+    for (int bi = 0; bi < n_bands; ++bi) {
+        Band *B = get_band(c, band_ids[bi]);
+        if (!B) return fail(c, CCR_EINVAL, "bad band id %d", band_ids[bi]);
+        if (!rho_out[bi]) return fail(c, CCR_EINVAL, "null output for band %d", band_ids[bi]);
+        if ((st = ensure_ready(c, *B))) return st;
+    }
+    for (int bi = 0; bi < n_bands; ++bi) {
+        Band &B = *get_band(c, band_ids[bi]);
+        const Plan &pl = B.plan;
+        const BandDev bd = band_dev(B);
+        const int64_t tb = template_batch(c, B, fp64);
+        const size_t cs = fp64 ? 16 : 8;
+        const int kc = k_chunk_for(c, pl);
+        const int nch = (int)((pl.n_seg + kc - 1) / kc);
+        HIP_OK(c, c->ws_y.ensure((size_t)tb * B.Q * pl.n_seg * pl.n_k * cs));
+        HIP_OK(c, c->ws_F.ensure((size_t)tb * B.Q * pl.n_seg * pl.n_f * cs));
+        HIP_OK(c, c->ws_part.ensure((size_t)tb * nch * pl.n_f * sizeof(double)));
+        const size_t osz = out_fp64 ? sizeof(double) : sizeof(float);
+        const size_t out_bytes = (size_t)B.n_tmpl * pl.n_f * osz;
+        void *dst = rho_out[bi];
+        if (!out_on_device) {
+            HIP_OK(c, c->ws_out.ensure(out_bytes));
+            dst = c->ws_out.p;
+        }
+        const double factor = pl.norm > 0.0 ? std::sqrt(2.0) / pl.norm : 0.0;
+        for (int64_t t = 0; t < B.n_tmpl; t += tb) {
+            const int nb = (int)std::min<int64_t>(tb, B.n_tmpl - t);
+            const double *dtm = B.d_tmpl.as<double>() + (size_t)t * kTmplStride;
+            {
+                LaunchTimer lt(c, 0, s);
+                HIP_OK(c, launch_resample(bd, dtm, nb, fp64, c->ws_y.p, s));
+            }
+            {
+                LaunchTimer lt(c, 1, s);
+                HIP_OK(c, launch_spectra(bd, nb, fp64, c->ws_y.p, c->ws_F.p, s));
+            }
+            {
+                LaunchTimer lt(c, 2, s);
+                HIP_OK(c, launch_pairsum(bd, nb, fp64, c->ws_F.p, c->ws_part.as<double>(), kc, nch, s));
+            }
+            {
+                LaunchTimer lt(c, 3, s);
+                HIP_OK(c, launch_finish(bd, nb, c->ws_part.as<double>(), nch, factor,
+                                        static_cast<char *>(dst) + (size_t)t * pl.n_f * osz, out_fp64 != 0, s));
+            }
+        }
+        if (!out_on_device) {
+            HIP_OK(c, hipMemcpyAsync(rho_out[bi], dst, out_bytes, hipMemcpyDeviceToHost, s));
+            HIP_OK(c, hipStreamSynchronize(s));
+        }
+    }
+    return CCR_OK;
+}
+
+ccr_status ccr_kernel_time(ccr_ctx *c, int kernel, double *ms, int64_t *launches) {
+    if (!c || !ms || !launches) return CCR_EINVAL;
+    if (kernel < 0 || kernel > 3) return fail(c, CCR_EINVAL, "kernel id %d out of range", kernel);
+    collect_times(c);
+    *ms = c->kt_ms[kernel];
+    *launches = c->kt_n[kernel];
+    return CCR_OK;
+}
+
+ccr_status ccr_reset_kernel_times(ccr_ctx *c) {
+    if (!c) return CCR_EINVAL;
+    collect_times(c);
+    for (int k = 0; k < 4; ++k) {
+        c->kt_ms[k] = 0.0;
+        c->kt_n[k] = 0;
+    }
+    return CCR_OK;
+}
+
+ccr_status ccr_sync(ccr_ctx *c) {
+    if (!c) return CCR_EINVAL;
+    if (c->device < 0) return CCR_OK;
+    HIP_OK(c, hipSetDevice(c->device));
+    HIP_OK(c, hipDeviceSynchronize());
+    return CCR_OK;
+}
+
+ccr_status ccr_resample_series(ccr_ctx *c, ccr_precision prec, int band_id, int64_t template_index, int det,
+                               void *y_out) {
+    if (!c) return CCR_EINVAL;
+    c->err.clear();
+    Band *B = get_band(c, band_id);
+    if (!B || !y_out) return fail(c, CCR_EINVAL, "bad band id or null output");
+    if (prec != CCR_PREC_FP64 && prec != CCR_PREC_SPLIT) return fail(c, CCR_EINVAL, "bad precision");
+    if (c->device < 0) return fail(c, CCR_EDEVICE, "host-only context");
+    HIP_OK(c, hipSetDevice(c->device));
+    ccr_status st = ensure_ready(c, *B);
+    if (st) return st;
+    if (template_index < 0 || template_index >= B->n_tmpl) return fail(c, CCR_EINVAL, "template index out of range");
+    if (det < 0 || det >= B->Q) return fail(c, CCR_EINVAL, "detector index out of range");
+    const bool fp64 = prec == CCR_PREC_FP64;
+    const Plan &pl = B->plan;
+    const size_t cs = fp64 ? 16 : 8;
+    const size_t bytes = (size_t)B->Q * pl.n_seg * pl.n_k * cs;
+    DevBuf y;
+    HIP_OK(c, y.ensure(bytes));
+    hipStream_t s = c->stream;
+    HIP_OK(c, launch_zero(y.p, bytes, s));
+    const BandDev bd = band_dev(*B);
+    HIP_OK(c, launch_resample(bd, B->d_tmpl.as<double>() + (size_t)template_index * kTmplStride, 1, fp64, y.p, s));
+    const size_t per = (size_t)pl.n_seg * pl.n_k * cs;
+    HIP_OK(c, hipMemcpyAsync(y_out, y.as<char>() + det * per, per, hipMemcpyDeviceToHost, s));
+    HIP_OK(c, hipStreamSynchronize(s));
+    return CCR_OK;
+}
+
+ccr_status ccr_segment_spectra(ccr_ctx *c, ccr_precision prec, int band_id, int64_t template_index, void *f_out) {
+    if (!c) return CCR_EINVAL;
+    c->err.clear();
+    Band *B = get_band(c, band_id);
+    if (!B || !f_out) return fail(c, CCR_EINVAL, "bad band id or null output");
+    if (prec != CCR_PREC_FP64 && prec != CCR_PREC_SPLIT) return fail(c, CCR_EINVAL, "bad precision");
+    if (c->device < 0) return fail(c, CCR_EDEVICE, "host-only context");
+    HIP_OK(c, hipSetDevice(c->device));
+    ccr_status st = ensure_ready(c, *B);
+    if (st) return st;
+    if (template_index < 0 || template_index >= B->n_tmpl) return fail(c, CCR_EINVAL, "template index out of range");
+    const bool fp64 = prec == CCR_PREC_FP64;
+    const Plan &pl = B->plan;
+    const size_t cs = fp64 ? 16 : 8;
+    DevBuf y, F;
+    const size_t ybytes = (size_t)B->Q * pl.n_seg * pl.n_k * cs, fbytes = (size_t)B->Q * pl.n_seg * pl.n_f * cs;
+    HIP_OK(c, y.ensure(ybytes));
+    HIP_OK(c, F.ensure(fbytes));
+    hipStream_t s = c->stream;
+    HIP_OK(c, launch_zero(y.p, ybytes, s));
+    HIP_OK(c, launch_zero(F.p, fbytes, s));
+    const BandDev bd = band_dev(*B);
+    HIP_OK(c, launch_resample(bd, B->d_tmpl.as<double>() + (size_t)template_index * kTmplStride, 1, fp64, y.p, s));
+    HIP_OK(c, launch_spectra(bd, 1, fp64, y.p, F.p, s));
+    HIP_OK(c, hipMemcpyAsync(f_out, F.p, fbytes, hipMemcpyDeviceToHost, s));
+    HIP_OK(c, hipStreamSynchronize(s));
+    return CCR_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,75 @@
+// Internal types shared by the host library and the gfx950 kernels.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+namespace ccr {
+
+// Earth Roemer delay of one detector in closed form:
+//   r(t).n = C + A_o cos(theta_o(t)) + A_d cos(theta_d(t)),
+//   theta_o advancing at w_o (orbit), theta_d at w_d (sidereal rotation).
+struct EarthConst {
+    double A_o, w_o, A_d, w_d;
+};
+
+// Per (detector, segment) anchor, template independent.  t_a is a detector time close to
+// the Earth-only arrival of the segment mid-time tau_a (t_a + r(t_a).n ~ tau_a):
+//   c_o, s_o, c_d, s_d  cos/sin of theta_o(t_a), theta_d(t_a)
+//   D_a                 tau_a - t_a, exact difference of the two representable times
+//   rho_a               r(t_a).n - D_a, the residual left because t_a is itself rounded
+//   psi_a               frac(-f_het D_a), cycles
+struct Anchor {
+    double c_o, s_o, c_d, s_d, D_a, rho_a, psi_a;
+};
+
+// Per (detector, segment) weights: hat a = a / sigma, hat b = b / sigma,
+// scale = 1 / (sigma sqrt(N_K)) for the segment spectra.
+struct SegWeight {
+    double ahat, bhat, scale;
+};
+
+// Per template, six doubles: a_p, Omega = 2 pi / P, and the binary orbital phase (cycles)
+// of segment K's mid-time as c0 + K c1 in double-double: c0h, c0l, c1h, c1l.
+constexpr int kTmplStride = 6;
+
+// Everything a kernel needs about a band (device pointers + scalars).
+struct BandDev {
+    int Q;              // detectors
+    int64_t n;          // samples per detector
+    int n_k, n_seg;     // samples per segment, segments
+    int n_fft, n_s, P;  // N_FFT = P * n_s, n_s = 2^ceil(log2 n_k)
+    int n_f;            // output bins
+    int D, window;      // taps each side, window kind
+    int R, pairs;       // max lag, pair kinds
+    double dt, f_het;
+    const float2 *x;          // [Q][n] complex64, zero where invalid
+    const uint8_t *mask;      // [Q][n_seg * n_k] gap mask of source samples
+    const Anchor *anchors;    // [Q][n_seg]
+    const EarthConst *earth;  // [Q]
+    const double *win64;      // [2D+1] tap window (window == 0)
+    const float *win32;
+    const double2 *tw64;      // [n_fft] exp(-2 pi i j / n_fft)
+    const float2 *tw32;
+    const int *bin_m;         // [n_f] FFT output index within residue class
+    const int *bin_p;         // [n_f] residue class kbar mod P
+    const int *bin_kb;        // [n_f] kbar mod n_fft
+    const SegWeight *segw;    // [Q][n_seg]
+    const uint8_t *active;    // [Q][n_seg] 1 when the segment takes part in a pair
+    const int *work;          // [n_work] det * n_seg + K of active segments
+    int n_work;
+};
+
+// Launchers (ccr_kernels.hip).  All queue work on `stream` and return the launch status.
+hipError_t launch_resample(const BandDev &B, const double *d_tmpl, int n_tmpl, bool fp64, void *y,
+                           hipStream_t stream);
+hipError_t launch_spectra(const BandDev &B, int n_tmpl, bool fp64, const void *y, void *F,
+                          hipStream_t stream);
+hipError_t launch_pairsum(const BandDev &B, int n_tmpl, bool fp64, const void *F, double *part,
+                          int k_chunk, int n_chunks, hipStream_t stream);
+hipError_t launch_finish(const BandDev &B, int n_tmpl, const double *part, int n_chunks,
+                         double factor, void *out, bool out_fp64, hipStream_t stream);
+hipError_t launch_zero(void *p, size_t bytes, hipStream_t stream);
+
+}  // namespace ccr

@@ -1,0 +1,171 @@
+"""Host-side checks of the C ABI that need no GPU: the library loads, exports every symbol
+include/ccr.h declares, validates arguments, and (in a host-only context, device -1) plans
+bands exactly like the oracle."""
+
+import ctypes
+import math
+import os
+import re
+
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from conftest import small_config
+from paper_1712_06515_amd import ccr
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    if not os.path.exists(ccr.LIB_PATH):
+        from paper_1712_06515_amd import build
+        build.build()
+    return ccr.load_library()
+
+
+def header_functions():
+    txt = open(os.path.join(ROOT, "include", "ccr.h")).read()
+    txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+    return sorted(set(re.findall(r"\b(ccr_[a-z_0-9]+)\s*\(", txt)))
+
+
+def test_exports_every_declared_symbol(lib):
+    names = header_functions()
+    assert len(names) >= 14
+    for n in names:
+        assert hasattr(lib, n), n
+    assert set(names) == set(ccr.SIGNATURES), set(names) ^ set(ccr.SIGNATURES)
+    assert lib.ccr_abi_version() == 1
+
+
+def test_struct_layouts_match_header(lib):
+    # sizes implied by the header field lists
+    assert ctypes.sizeof(ccr.Sky) == 9 * 8
+    assert ctypes.sizeof(ccr.Site) == 16
+    assert ctypes.sizeof(ccr.Band) == 3 * 8 + 4 * 4 + 8 + 8 + 8 + 8  # int32 pairs padded to 8
+    assert ctypes.sizeof(ccr.BandInfo) == 9 * 8 + 8 * 8
+
+
+def test_null_and_bad_arguments(lib):
+    assert lib.ccr_create(None, 0, None) == ccr.EINVAL
+    h = ctypes.c_void_p()
+    bad = ccr.Sky(0, 0, 499.0, 0.02, 0.4, -1.0, 86164.0, 0, 0)
+    assert lib.ccr_create(ctypes.byref(h), -1, ctypes.byref(bad)) == ccr.EINVAL
+    nan = ccr.Sky(float("nan"), 0, 499.0, 0.02, 0.4, 3e7, 86164.0, 0, 0)
+    assert lib.ccr_create(ctypes.byref(h), -1, ctypes.byref(nan)) == ccr.EINVAL
+    assert lib.ccr_set_option(None, b"fused", 1) == ccr.EINVAL
+    assert lib.ccr_sync(None) == ccr.EINVAL
+    assert lib.ccr_last_error(None) == b"null context"
+
+
+def _host_ctx(ds):
+    ctx = ccr.Context(ds.sky, device=-1)
+    return ctx
+
+
+def test_host_only_context_rejects_device_work(lib):
+    ds = synth.make_dataset(small_config(n_seg=4), signal=False)
+    ctx = _host_ctx(ds)
+    bid = ctx.load(ds)
+    with pytest.raises(ccr.CcrError) as e:
+        ctx.compute_rho(bid)
+    assert e.value.status == ccr.EDEVICE
+
+
+def test_validation_errors(lib):
+    ds = synth.make_dataset(small_config(n_seg=4), signal=False)
+    ctx = _host_ctx(ds)
+    bid, info = ctx.add_band(ds.band)
+    assert info["n_k"] == ds.n_k and abs(info["dt"] - ds.dt) < 1e-15
+    site = ds.sites[0]
+
+    def err(fn, *a, **k):
+        with pytest.raises(ccr.CcrError) as e:
+            fn(*a, **k)
+        return e.value.status
+
+    # call order: no data yet
+    assert err(ctx.band_info, bid) == ccr.ESTATE
+    # dt that is not T_short / integer
+    assert err(ctx.set_data, bid, 0, site, 0.0, ds.dt * 1.01, ds.x[0], ds.f_het) == ccr.EINVAL
+    # dt that undersamples the load band
+    assert err(ctx.set_data, bid, 0, site, 0.0, ds.band["t_short"] / (ds.n_k - 5), ds.x[0], ds.f_het) == ccr.ERANGE
+    # wrong heterodyne frequency
+    assert err(ctx.set_data, bid, 0, site, 0.0, ds.dt, ds.x[0], ds.f_het + 0.01) == ccr.EINVAL
+    # NaN sample
+    xb = ds.x[0].copy()
+    xb[7] = np.nan
+    assert err(ctx.set_data, bid, 0, site, 0.0, ds.dt, xb, ds.f_het) == ccr.EINVAL
+    # bad detector index, too short
+    assert err(ctx.set_data, bid, 9, site, 0.0, ds.dt, ds.x[0], ds.f_het) == ccr.EINVAL
+    assert err(ctx.set_data, bid, 0, site, 0.0, ds.dt, ds.x[0][: ds.n_k - 1], ds.f_het) == ccr.EINVAL
+    ctx.set_data(bid, 0, site, 0.0, ds.dt, ds.x[0], ds.f_het)
+    # mismatched lattice origin for a second detector
+    assert err(ctx.set_data, bid, 1, ds.sites[1], 1.0, ds.dt, ds.x[1], ds.f_het) == ccr.EINVAL
+    # weights: non-positive noise, NaN
+    nv = ds.noise_var[0].copy()
+    nv[2] = 0.0
+    assert err(ctx.set_weights, bid, 0, ds.a[0], ds.b[0], nv) == ccr.EINVAL
+    aa = ds.a[0].copy()
+    aa[1] = np.inf
+    assert err(ctx.set_weights, bid, 0, aa, ds.b[0], ds.noise_var[0]) == ccr.EINVAL
+    # weights of the wrong length are caught when the band is planned
+    ctx.set_weights(bid, 0, ds.a[0][:-1], ds.b[0][:-1], ds.noise_var[0][:-1])
+    assert err(ctx.band_info, bid) == ccr.EINVAL
+    # templates
+    assert err(ctx.set_templates, bid, np.array([[1.0, 0.0, -5.0]])) == ccr.EINVAL
+    assert err(ctx.set_templates, bid, np.array([[-1.0, 0.0, 68023.7]])) == ccr.EINVAL
+    # options
+    assert err(ctx.set_option, "no_such_option", 1) == ccr.EUNSUP
+    # band fields
+    b2 = dict(ds.band, pairs=0)
+    assert err(ctx.add_band, b2) == ccr.EINVAL
+    b3 = dict(ds.band, dirichlet_D=0)
+    assert err(ctx.add_band, b3) == ccr.ERANGE
+    b4 = dict(ds.band, n_fft_override=3 * 128 + 1)
+    bid4, _ = ctx.add_band(b4)
+    for X in range(2):
+        ctx.set_data(bid4, X, ds.sites[X], 0.0, ds.dt, ds.x[X], ds.f_het)
+        ctx.set_weights(bid4, X, ds.a[X], ds.b[X], ds.noise_var[X])
+    assert err(ctx.band_info, bid4) == ccr.EINVAL
+
+
+@pytest.mark.parametrize("kw", [
+    dict(),
+    dict(max_lag=2, gap_fraction=0.25, n_seg=24),
+    dict(max_lag=3, pairs=1, q=3, n_seg=20, gap_fraction=0.1),
+    dict(max_lag=1, pairs=2, n_seg=12, mu_f=0.3),
+    dict(n_fft_override=3 * 128, max_lag=1),
+])
+def test_plan_and_normalisation_match_oracle(lib, kw):
+    """Band plan integers are bit-identical to the oracle's; the normalisation (weights, gap
+    mask fractions, pair set) agrees to rounding."""
+    ds = synth.make_dataset(small_config(**kw), sigma_wander=0.2)
+    ctx = _host_ctx(ds)
+    bid = ctx.load(ds)
+    info, freqs = ctx.band_info(bid, freqs=True)
+    o = oracle.Oracle(ds)
+    pl = o.plan()
+    for k in ("n_k", "n_seg", "n_fft", "n_f", "k_lo"):
+        assert info[k] == getattr(pl, k), k
+    for k in ("dt", "f_het", "df_load", "t_coh", "t_fft", "nu_r"):
+        assert info[k] == getattr(pl, k), k
+    assert info["dlambda_f"] == pl.dlambda_f
+    assert info["n_pairs"] == o.pair_count()
+    np.testing.assert_array_equal(freqs, o.frequencies())
+    assert abs(info["norm"] / o.norm() - 1.0) < 1e-12
+
+
+def test_plan_of_named_workloads(lib):
+    """The library's recommended sampling matches the generator's App. B sizing for every named
+    workload (three independent implementations of the load bandwidth)."""
+    ctx = ccr.Context(synth.default_sky(), device=-1)
+    for name in ("tiny", "band", "large"):
+        band = synth.config(name)["band"]
+        _, info = ctx.add_band(band)
+        assert info["n_k"] == synth.samples_per_segment(band)
+        assert abs(info["df_load"] - synth.load_bandwidth(band["f_min"], band["f_band"], band["t_short"],
+                                                          band["a_p_max"])) < 1e-12
