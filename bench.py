@@ -98,6 +98,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--profile-steps", type=int, default=0)
     ap.add_argument("--copy-calibration", action="store_true")
+    ap.add_argument("--fused", type=int, default=0, help="1: fused kernel, 0: staged kernels (default)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: this build has no multi-GPU path "
@@ -124,6 +125,7 @@ def main():
     print(f"[bench] dataset {args.workload}: {ds.n_det} det x {ds.n} samples, {len(ds.templates)} templates "
           f"({time.perf_counter() - t_gen:.1f} s)", file=sys.stderr, flush=True)
     ctx = Context(ds.sky, device=0)
+    ctx.set_option("fused", args.fused)
     bid = ctx.load(ds)
     info = ctx.band_info(bid)
     n_t, n_f = info["n_templates"], info["n_f"]
@@ -165,6 +167,7 @@ def main():
     nsub = min(args.fp64_templates, n_t)
     ctx2 = Context(ds.sky, device=0)
     ctx2.set_option("template_batch", 1)
+    ctx2.set_option("fused", 0)
     bid2 = ctx2.load(ds, templates=ds.templates[:nsub])
     out2 = torch.empty((nsub, n_f), dtype=torch.float64, device="cuda")
 
@@ -180,29 +183,33 @@ def main():
     value64 = nsub * n_f / w64
     print(f"[bench] fp64 plain {1e3 * w64:.1f} ms for {nsub} templates", file=sys.stderr, flush=True)
 
-    # roofline of the dominant kernel
+    # roofline of the dominant kernel (device time per launch from HIP events on the launch
+    # stream; algorithmic work per launch = per-unit figure x units per launch)
     name, (ms_tot, nl) = max(kt.items(), key=lambda kv: kv[1][0])
     avg_ms = ms_tot / max(nl, 1)
-    tb = n_t // max(1, kt["resample"][1] // args.steps) if kt["resample"][1] else n_t
-    # work units per launch: active (detector, segment) entries x templates per launch
+    launches_per_step = max(1, nl // args.steps)
+    tb = n_t / launches_per_step  # templates per launch (mean)
     n_active = info["n_active"]
+    samples = n_active * info["n_k"] * tb  # resampled samples per launch
+    ns = 1 << (int(info["n_k"]) - 1).bit_length()
+    P = info["n_fft"] // ns
+    fft_flops = n_active * tb * P * (5.0 * ns * np.log2(ns) + 6.0 * ns)
     roof = None
-    if name == "resample" and n_active:
-        samples = n_active * info["n_k"] * tb
-        byts = samples * 8.0  # algorithmic: one complex64 written per resampled sample
+    if name == "resample":
+        # one complex64 sample written and one input sample read per resampled sample
+        byts = samples * 16.0
         ach = byts / (avg_ms * 1e-3) / 1e9
         roof = {"kernel": "k_resample", "bound": "hbm", "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": ach / HBM_PEAK_GBS, "traffic": read_traffic("resample", args.workload),
-                "avg_launch_ms": avg_ms, "algorithmic_bytes_per_launch": byts}
-    elif name == "spectra" and n_active:
-        nseg = n_active * tb
-        ns = 1 << (int(info["n_k"]) - 1).bit_length()
-        P = info["n_fft"] // ns
-        flops = nseg * P * (5.0 * ns * np.log2(ns) + 6.0 * ns)
-        ach = flops / (avg_ms * 1e-3) / 1e12
-        roof = {"kernel": "k_spectra", "bound": "alu", "achieved": ach, "peak": FP32_PEAK_TFLOPS,
-                "unit": "TFLOP/s", "frac": ach / FP32_PEAK_TFLOPS, "traffic": read_traffic("spectra", args.workload),
-                "avg_launch_ms": avg_ms, "algorithmic_flops_per_launch": flops}
+                "avg_launch_ms": avg_ms, "algorithmic_bytes_per_launch": byts,
+                "per_unit": "16 B per resampled sample (8 B written, 8 B input)"}
+    elif name in ("spectra", "spectra_pairs", "fused"):
+        ach = fft_flops / (avg_ms * 1e-3) / 1e12
+        kern = {"spectra": "k_spectra16", "spectra_pairs": "k_spectra_pairs16", "fused": "k_fused"}[name]
+        roof = {"kernel": kern, "bound": "alu", "achieved": ach, "peak": FP32_PEAK_TFLOPS, "unit": "TFLOP/s",
+                "frac": ach / FP32_PEAK_TFLOPS, "traffic": read_traffic(name, args.workload),
+                "avg_launch_ms": avg_ms, "algorithmic_flops_per_launch": fft_flops,
+                "per_unit": f"P (5 n_s log2 n_s + 6 n_s) FP32 flop per (template, detector, segment), n_s={ns}, P={P}"}
     result = {
         "metric": METRIC,
         "value": value,

@@ -80,8 +80,9 @@ struct Band {
     Plan plan;
     int Q = 0;
     // device tables
-    DevBuf d_x, d_mask, d_anchor, d_earth, d_win64, d_win32, d_tw64, d_tw32, d_bin_m, d_bin_p,
-        d_bin_kb, d_segw, d_active, d_work, d_tmpl;
+    DevBuf d_x, d_mask, d_anchor, d_earth, d_win64, d_win32, d_cheb_x, d_cheb_T, d_tw64, d_tw32, d_bin_m, d_bin_p,
+        d_bin_kb, d_bin_pos, d_segw, d_active, d_work, d_seg_work, d_tmpl;
+    int bins_unique = 0;
     int n_work = 0;
     std::vector<double> freqs;
     std::vector<uint8_t> active;
@@ -98,16 +99,16 @@ struct ccr_ctx {
     int64_t opt_template_batch = 0;
     int64_t opt_workspace_mb = 16384;
     int64_t opt_k_chunk = 0;
-    int64_t opt_fused = 1;
+    int64_t opt_fused = 0;
     int64_t opt_timing = 0;
-    DevBuf ws_y, ws_F, ws_part, ws_out;
+    DevBuf ws_y, ws_F, ws_part, ws_out, ws_coef;
     struct Timed {
         int kind;
         hipEvent_t a, b;
     };
     std::vector<Timed> timed;
-    double kt_ms[4] = {0, 0, 0, 0};
-    int64_t kt_n[4] = {0, 0, 0, 0};
+    double kt_ms[7] = {0, 0, 0, 0, 0, 0, 0};
+    int64_t kt_n[7] = {0, 0, 0, 0, 0, 0, 0};
 };
 
 namespace {
@@ -390,10 +391,13 @@ ccr_status prepare(ccr_ctx *c, Band &B) {
                 }
     pl.norm = (double)sqrtl(nacc);
     pl.n_pairs = npairs;
-    std::vector<int> work;
+    std::vector<int> work, seg_work((size_t)Q * M, -1);
     for (int X = 0; X < Q; ++X)
         for (int64_t K = 0; K < M; ++K)
-            if (active[X * M + K]) work.push_back((int)(X * M + K));
+            if (active[X * M + K]) {
+                seg_work[X * M + K] = (int)work.size();
+                work.push_back((int)(X * M + K));
+            }
     // bins and twiddles
     std::vector<int> bm(pl.n_f), bp(pl.n_f), bkb(pl.n_f);
     B.freqs.resize(pl.n_f);
@@ -405,6 +409,12 @@ ccr_status prepare(ccr_ctx *c, Band &B) {
         bkb[i] = (int)km;
         bp[i] = (int)(km % pl.P);
         bm[i] = (int)(km / pl.P);
+    }
+    std::vector<int> bpos(pl.n_fft, -1);
+    int unique = 1;
+    for (int64_t i = 0; i < pl.n_f; ++i) {
+        if (bpos[bkb[i]] >= 0) unique = 0;
+        bpos[bkb[i]] = (int)i;
     }
     std::vector<double2> tw64(pl.n_fft);
     std::vector<float2> tw32(pl.n_fft);
@@ -428,6 +438,13 @@ ccr_status prepare(ccr_ctx *c, Band &B) {
         B.prepared = true;
         return CCR_OK;
     }
+    // Chebyshev nodes and the cosine matrix of the coefficient transform
+    std::vector<double> cx(kCheb), cT(kCheb * kCheb);
+    for (int j = 0; j < kCheb; ++j) {
+        cx[j] = (double)cosl(kPiL * ((long double)j + 0.5L) / kCheb);
+        for (int k = 0; k < kCheb; ++k)
+            cT[k * kCheb + j] = (double)cosl(kPiL * (long double)k * ((long double)j + 0.5L) / kCheb);
+    }
     // device upload
     std::vector<float2> xs((size_t)Q * n);
     for (int X = 0; X < Q; ++X)
@@ -438,14 +455,19 @@ ccr_status prepare(ccr_ctx *c, Band &B) {
     if ((st = upload(c, B.d_earth, earth))) return st;
     if ((st = upload(c, B.d_win64, w64))) return st;
     if ((st = upload(c, B.d_win32, w32))) return st;
+    if ((st = upload(c, B.d_cheb_x, cx))) return st;
+    if ((st = upload(c, B.d_cheb_T, cT))) return st;
     if ((st = upload(c, B.d_tw64, tw64))) return st;
     if ((st = upload(c, B.d_tw32, tw32))) return st;
     if ((st = upload(c, B.d_bin_m, bm))) return st;
     if ((st = upload(c, B.d_bin_p, bp))) return st;
     if ((st = upload(c, B.d_bin_kb, bkb))) return st;
+    if ((st = upload(c, B.d_bin_pos, bpos))) return st;
+    B.bins_unique = unique;
     if ((st = upload(c, B.d_segw, segw))) return st;
     if ((st = upload(c, B.d_active, B.active))) return st;
     if ((st = upload(c, B.d_work, work))) return st;
+    if ((st = upload(c, B.d_seg_work, seg_work))) return st;
     B.prepared = true;
     return CCR_OK;
 }
@@ -496,12 +518,14 @@ BandDev band_dev(const Band &B) {
     d.n_fft = (int)pl.n_fft;
     d.n_s = (int)pl.n_s;
     d.P = (int)pl.P;
+    d.nfft_mask = (pl.n_fft & (pl.n_fft - 1)) == 0 ? (int)(pl.n_fft - 1) : 0;
     d.n_f = (int)pl.n_f;
     d.D = B.p.dirichlet_D;
     d.window = B.p.window;
     d.R = B.p.max_lag;
     d.pairs = B.p.pairs;
     d.dt = pl.dt;
+    d.inv_dt = 1.0 / pl.dt;
     d.f_het = pl.f_het;
     d.x = B.d_x.as<float2>();
     d.mask = B.d_mask.as<uint8_t>();
@@ -509,14 +533,19 @@ BandDev band_dev(const Band &B) {
     d.earth = B.d_earth.as<EarthConst>();
     d.win64 = B.d_win64.as<double>();
     d.win32 = B.d_win32.as<float>();
+    d.cheb_x = B.d_cheb_x.as<double>();
+    d.cheb_T = B.d_cheb_T.as<double>();
     d.tw64 = B.d_tw64.as<double2>();
     d.tw32 = B.d_tw32.as<float2>();
     d.bin_m = B.d_bin_m.as<int>();
     d.bin_p = B.d_bin_p.as<int>();
     d.bin_kb = B.d_bin_kb.as<int>();
+    d.bin_pos = B.d_bin_pos.as<int>();
+    d.bins_unique = B.bins_unique;
     d.segw = B.d_segw.as<SegWeight>();
     d.active = B.d_active.as<uint8_t>();
     d.work = B.d_work.as<int>();
+    d.seg_work = B.d_seg_work.as<int>();
     d.n_work = B.n_work;
     return d;
 }
@@ -539,10 +568,12 @@ ccr_status ensure_ready(ccr_ctx *c, Band &B) {
 }
 
 // Templates per launch so that the staged buffers stay within the workspace budget.
-int64_t template_batch(ccr_ctx *c, const Band &B, bool fp64) {
+int64_t template_batch(ccr_ctx *c, const Band &B, bool fp64, bool no_spectra_buffer) {
     const Plan &pl = B.plan;
     const size_t cs = fp64 ? 16 : 8;
-    const size_t per = (size_t)B.Q * pl.n_seg * pl.n_k * cs + (size_t)B.Q * pl.n_seg * pl.n_f * cs;
+    const size_t per = (size_t)B.Q * pl.n_seg * pl.n_k * cs +
+                       (no_spectra_buffer ? 0 : (size_t)B.Q * pl.n_seg * pl.n_f * cs) +
+                       (size_t)std::max(B.n_work, 1) * kCheb * sizeof(double);
     int64_t tb = c->opt_template_batch;
     if (tb <= 0) {
         size_t budget = (size_t)c->opt_workspace_mb << 20;
@@ -592,6 +623,56 @@ int k_chunk_for(ccr_ctx *c, const Plan &pl) {
     // keep the chunk count within the launch grid's y extent
     kc = std::max<int64_t>(kc, (pl.n_seg + 65534) / 65535);
     return (int)kc;
+}
+
+constexpr size_t kMaxLds = 65536;
+
+// Fused path: one launch per template batch computes partial rho per (template, segment chunk)
+// with every intermediate in LDS, then the chunk partials are summed in order.
+ccr_status compute_fused(ccr_ctx *c, Band &B, const BandDev &bd, bool fp64, int S, void *rho_out,
+                         int out_on_device, int out_fp64, hipStream_t s) {
+    const Plan &pl = B.plan;
+    int64_t kc = c->opt_k_chunk > 0 ? c->opt_k_chunk : std::min<int64_t>(pl.n_seg, 256);
+    kc = std::max<int64_t>(kc, (pl.n_seg + 65534) / 65535);
+    const int nch = (int)((pl.n_seg + kc - 1) / kc);
+    int64_t tb = c->opt_template_batch;
+    if (tb <= 0) {
+        const int64_t per = (int64_t)nch * pl.n_f * 8 + (int64_t)std::max(B.n_work, 1) * kCheb * 8;
+        tb = std::max<int64_t>(1, ((int64_t)2 << 30) / per);
+    }
+    tb = std::max<int64_t>(1, std::min<int64_t>({tb, (int64_t)65535, B.n_tmpl}));
+    HIP_OK(c, c->ws_part.ensure((size_t)tb * nch * pl.n_f * sizeof(double)));
+    HIP_OK(c, c->ws_coef.ensure((size_t)tb * std::max(B.n_work, 1) * kCheb * sizeof(double)));
+    const size_t osz = out_fp64 ? sizeof(double) : sizeof(float);
+    const size_t out_bytes = (size_t)B.n_tmpl * pl.n_f * osz;
+    void *dst = rho_out;
+    if (!out_on_device) {
+        HIP_OK(c, c->ws_out.ensure(out_bytes));
+        dst = c->ws_out.p;
+    }
+    const double factor = pl.norm > 0.0 ? std::sqrt(2.0) / pl.norm : 0.0;
+    for (int64_t t = 0; t < B.n_tmpl; t += tb) {
+        const int nb = (int)std::min<int64_t>(tb, B.n_tmpl - t);
+        const double *dtm = B.d_tmpl.as<double>() + (size_t)t * kTmplStride;
+        {
+            LaunchTimer lt(c, 5, s);
+            HIP_OK(c, launch_timebase(bd, dtm, nb, c->ws_coef.as<double>(), s));
+        }
+        {
+            LaunchTimer lt(c, 4, s);
+            HIP_OK(c, launch_fused(bd, c->ws_coef.as<double>(), nb, fp64, c->ws_part.as<double>(), (int)kc, nch, S, s));
+        }
+        {
+            LaunchTimer lt(c, 3, s);
+            HIP_OK(c, launch_finish(bd, nb, c->ws_part.as<double>(), nch, factor,
+                                    static_cast<char *>(dst) + (size_t)t * pl.n_f * osz, out_fp64 != 0, s));
+        }
+    }
+    if (!out_on_device) {
+        HIP_OK(c, hipMemcpyAsync(rho_out, dst, out_bytes, hipMemcpyDeviceToHost, s));
+        HIP_OK(c, hipStreamSynchronize(s));
+    }
+    return CCR_OK;
 }
 
 }  // namespace
@@ -646,6 +727,7 @@ void ccr_destroy(ccr_ctx *c) {
     c->ws_F.release();
     c->ws_part.release();
     c->ws_out.release();
+    c->ws_coef.release();
     if (c->stream) (void)hipStreamDestroy(c->stream);
     delete c;
 }
@@ -859,13 +941,20 @@ ccr_status ccr_compute_rho(ccr_ctx *c, ccr_precision prec, int n_bands, const in
         Band &B = *get_band(c, band_ids[bi]);
         const Plan &pl = B.plan;
         const BandDev bd = band_dev(B);
-        const int64_t tb = template_batch(c, B, fp64);
+        const int S = c->opt_fused ? fused_steps(bd, fp64, kMaxLds) : 0;
+        if (S > 0) {
+            if ((st = compute_fused(c, B, bd, fp64, S, rho_out[bi], out_on_device, out_fp64, s))) return st;
+            continue;
+        }
+        const bool sp = spectra_pairs_ok(bd, fp64, kMaxLds);
+        const int64_t tb = template_batch(c, B, fp64, sp);
         const size_t cs = fp64 ? 16 : 8;
         const int kc = k_chunk_for(c, pl);
         const int nch = (int)((pl.n_seg + kc - 1) / kc);
         HIP_OK(c, c->ws_y.ensure((size_t)tb * B.Q * pl.n_seg * pl.n_k * cs));
-        HIP_OK(c, c->ws_F.ensure((size_t)tb * B.Q * pl.n_seg * pl.n_f * cs));
+        if (!sp) HIP_OK(c, c->ws_F.ensure((size_t)tb * B.Q * pl.n_seg * pl.n_f * cs));
         HIP_OK(c, c->ws_part.ensure((size_t)tb * nch * pl.n_f * sizeof(double)));
+        HIP_OK(c, c->ws_coef.ensure((size_t)tb * std::max(B.n_work, 1) * kCheb * sizeof(double)));
         const size_t osz = out_fp64 ? sizeof(double) : sizeof(float);
         const size_t out_bytes = (size_t)B.n_tmpl * pl.n_f * osz;
         void *dst = rho_out[bi];
@@ -878,16 +967,25 @@ ccr_status ccr_compute_rho(ccr_ctx *c, ccr_precision prec, int n_bands, const in
             const int nb = (int)std::min<int64_t>(tb, B.n_tmpl - t);
             const double *dtm = B.d_tmpl.as<double>() + (size_t)t * kTmplStride;
             {
+                LaunchTimer lt(c, 5, s);
+                HIP_OK(c, launch_timebase(bd, dtm, nb, c->ws_coef.as<double>(), s));
+            }
+            {
                 LaunchTimer lt(c, 0, s);
-                HIP_OK(c, launch_resample(bd, dtm, nb, fp64, c->ws_y.p, s));
+                HIP_OK(c, launch_resample(bd, c->ws_coef.as<double>(), nb, fp64, c->ws_y.p, s));
             }
-            {
-                LaunchTimer lt(c, 1, s);
-                HIP_OK(c, launch_spectra(bd, nb, fp64, c->ws_y.p, c->ws_F.p, s));
-            }
-            {
-                LaunchTimer lt(c, 2, s);
-                HIP_OK(c, launch_pairsum(bd, nb, fp64, c->ws_F.p, c->ws_part.as<double>(), kc, nch, s));
+            if (sp) {
+                LaunchTimer lt(c, 6, s);
+                HIP_OK(c, launch_spectra_pairs(bd, nb, c->ws_y.p, c->ws_part.as<double>(), kc, nch, s));
+            } else {
+                {
+                    LaunchTimer lt(c, 1, s);
+                    HIP_OK(c, launch_spectra(bd, nb, fp64, c->ws_y.p, c->ws_F.p, s));
+                }
+                {
+                    LaunchTimer lt(c, 2, s);
+                    HIP_OK(c, launch_pairsum(bd, nb, fp64, c->ws_F.p, c->ws_part.as<double>(), kc, nch, s));
+                }
             }
             {
                 LaunchTimer lt(c, 3, s);
@@ -905,7 +1003,7 @@ ccr_status ccr_compute_rho(ccr_ctx *c, ccr_precision prec, int n_bands, const in
 
 ccr_status ccr_kernel_time(ccr_ctx *c, int kernel, double *ms, int64_t *launches) {
     if (!c || !ms || !launches) return CCR_EINVAL;
-    if (kernel < 0 || kernel > 3) return fail(c, CCR_EINVAL, "kernel id %d out of range", kernel);
+    if (kernel < 0 || kernel > 6) return fail(c, CCR_EINVAL, "kernel id %d out of range", kernel);
     collect_times(c);
     *ms = c->kt_ms[kernel];
     *launches = c->kt_n[kernel];
@@ -915,7 +1013,7 @@ ccr_status ccr_kernel_time(ccr_ctx *c, int kernel, double *ms, int64_t *launches
 ccr_status ccr_reset_kernel_times(ccr_ctx *c) {
     if (!c) return CCR_EINVAL;
     collect_times(c);
-    for (int k = 0; k < 4; ++k) {
+    for (int k = 0; k < 7; ++k) {
         c->kt_ms[k] = 0.0;
         c->kt_n[k] = 0;
     }
@@ -947,12 +1045,14 @@ ccr_status ccr_resample_series(ccr_ctx *c, ccr_precision prec, int band_id, int6
     const Plan &pl = B->plan;
     const size_t cs = fp64 ? 16 : 8;
     const size_t bytes = (size_t)B->Q * pl.n_seg * pl.n_k * cs;
-    DevBuf y;
+    DevBuf y, cf;
     HIP_OK(c, y.ensure(bytes));
+    HIP_OK(c, cf.ensure((size_t)std::max(B->n_work, 1) * kCheb * sizeof(double)));
     hipStream_t s = c->stream;
     HIP_OK(c, launch_zero(y.p, bytes, s));
     const BandDev bd = band_dev(*B);
-    HIP_OK(c, launch_resample(bd, B->d_tmpl.as<double>() + (size_t)template_index * kTmplStride, 1, fp64, y.p, s));
+    HIP_OK(c, launch_timebase(bd, B->d_tmpl.as<double>() + (size_t)template_index * kTmplStride, 1, cf.as<double>(), s));
+    HIP_OK(c, launch_resample(bd, cf.as<double>(), 1, fp64, y.p, s));
     const size_t per = (size_t)pl.n_seg * pl.n_k * cs;
     HIP_OK(c, hipMemcpyAsync(y_out, y.as<char>() + det * per, per, hipMemcpyDeviceToHost, s));
     HIP_OK(c, hipStreamSynchronize(s));
@@ -973,7 +1073,8 @@ ccr_status ccr_segment_spectra(ccr_ctx *c, ccr_precision prec, int band_id, int6
     const bool fp64 = prec == CCR_PREC_FP64;
     const Plan &pl = B->plan;
     const size_t cs = fp64 ? 16 : 8;
-    DevBuf y, F;
+    DevBuf y, F, cf;
+    HIP_OK(c, cf.ensure((size_t)std::max(B->n_work, 1) * kCheb * sizeof(double)));
     const size_t ybytes = (size_t)B->Q * pl.n_seg * pl.n_k * cs, fbytes = (size_t)B->Q * pl.n_seg * pl.n_f * cs;
     HIP_OK(c, y.ensure(ybytes));
     HIP_OK(c, F.ensure(fbytes));
@@ -981,7 +1082,8 @@ ccr_status ccr_segment_spectra(ccr_ctx *c, ccr_precision prec, int band_id, int6
     HIP_OK(c, launch_zero(y.p, ybytes, s));
     HIP_OK(c, launch_zero(F.p, fbytes, s));
     const BandDev bd = band_dev(*B);
-    HIP_OK(c, launch_resample(bd, B->d_tmpl.as<double>() + (size_t)template_index * kTmplStride, 1, fp64, y.p, s));
+    HIP_OK(c, launch_timebase(bd, B->d_tmpl.as<double>() + (size_t)template_index * kTmplStride, 1, cf.as<double>(), s));
+    HIP_OK(c, launch_resample(bd, cf.as<double>(), 1, fp64, y.p, s));
     HIP_OK(c, launch_spectra(bd, 1, fp64, y.p, F.p, s));
     HIP_OK(c, hipMemcpyAsync(f_out, F.p, fbytes, hipMemcpyDeviceToHost, s));
     HIP_OK(c, hipStreamSynchronize(s));

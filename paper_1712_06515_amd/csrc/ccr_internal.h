@@ -34,40 +34,64 @@ struct SegWeight {
 // of segment K's mid-time as c0 + K c1 in double-double: c0h, c0l, c1h, c1l.
 constexpr int kTmplStride = 6;
 
+// Chebyshev nodes per segment for the time base, and the detector limit of the kernels.
+constexpr int kCheb = 10;
+#define CCR_MAX_DET_K 8
+
 // Everything a kernel needs about a band (device pointers + scalars).
 struct BandDev {
     int Q;              // detectors
     int64_t n;          // samples per detector
     int n_k, n_seg;     // samples per segment, segments
     int n_fft, n_s, P;  // N_FFT = P * n_s, n_s = 2^ceil(log2 n_k)
+    int nfft_mask;      // N_FFT - 1 when N_FFT is a power of two, else 0
     int n_f;            // output bins
     int D, window;      // taps each side, window kind
     int R, pairs;       // max lag, pair kinds
-    double dt, f_het;
+    double dt, inv_dt, f_het;
     const float2 *x;          // [Q][n] complex64, zero where invalid
     const uint8_t *mask;      // [Q][n_seg * n_k] gap mask of source samples
     const Anchor *anchors;    // [Q][n_seg]
     const EarthConst *earth;  // [Q]
     const double *win64;      // [2D+1] tap window (window == 0)
     const float *win32;
+    const double *cheb_x;     // [kCheb] cos(pi (j + 1/2) / kCheb)
+    const double *cheb_T;     // [kCheb][kCheb] cos(pi k (j + 1/2) / kCheb)
     const double2 *tw64;      // [n_fft] exp(-2 pi i j / n_fft)
     const float2 *tw32;
     const int *bin_m;         // [n_f] FFT output index within residue class
     const int *bin_p;         // [n_f] residue class kbar mod P
     const int *bin_kb;        // [n_f] kbar mod n_fft
+    const int *bin_pos;       // [n_fft] output bin i of FFT index kbar mod n_fft, -1 if none
+    int bins_unique;          // 1 when every output bin has its own FFT index
     const SegWeight *segw;    // [Q][n_seg]
     const uint8_t *active;    // [Q][n_seg] 1 when the segment takes part in a pair
     const int *work;          // [n_work] det * n_seg + K of active segments
+    const int *seg_work;      // [Q][n_seg] position of (det, K) in `work`, -1 if inactive
     int n_work;
 };
 
 // Launchers (ccr_kernels.hip).  All queue work on `stream` and return the launch status.
-hipError_t launch_resample(const BandDev &B, const double *d_tmpl, int n_tmpl, bool fp64, void *y,
+// Chebyshev coefficients of the time base, coef[n_tmpl][n_work][kCheb].
+hipError_t launch_timebase(const BandDev &B, const double *d_tmpl, int n_tmpl, double *coef,
+                           hipStream_t stream);
+hipError_t launch_resample(const BandDev &B, const double *coef, int n_tmpl, bool fp64, void *y,
                            hipStream_t stream);
 hipError_t launch_spectra(const BandDev &B, int n_tmpl, bool fp64, const void *y, void *F,
                           hipStream_t stream);
 hipError_t launch_pairsum(const BandDev &B, int n_tmpl, bool fp64, const void *F, double *part,
                           int k_chunk, int n_chunks, hipStream_t stream);
+// Fused resample + FFT + pair sum, one workgroup per (template, chunk of k_chunk segments),
+// S segments per step; fused_steps() picks S for an LDS budget (0: does not fit).
+int fused_steps(const BandDev &B, bool fp64, size_t limit);
+size_t fused_lds_bytes(const BandDev &B, bool fp64, int S);
+hipError_t launch_fused(const BandDev &B, const double *coef, int n_tmpl, bool fp64, double *part,
+                        int k_chunk, int n_chunks, int S, hipStream_t stream);
+// Split-precision spectra + pair sum in one kernel (256-point segments, distinct bins): writes
+// chunk partials directly; spectra_pairs_ok() says whether a band qualifies.
+bool spectra_pairs_ok(const BandDev &B, bool fp64, size_t limit);
+hipError_t launch_spectra_pairs(const BandDev &B, int n_tmpl, const void *y, double *part, int k_chunk,
+                                int n_chunks, hipStream_t stream);
 hipError_t launch_finish(const BandDev &B, int n_tmpl, const double *part, int n_chunks,
                          double factor, void *out, bool out_fp64, hipStream_t stream);
 hipError_t launch_zero(void *p, size_t bytes, hipStream_t stream);

@@ -63,18 +63,15 @@ __device__ __forceinline__ void binary_anchor(const double *tp, int K, double &s
 // time t = t_a + u + eta, the source-time equation tau(t) = tau_a + u becomes
 //   G(eta) = eta + rho_a + de(u + eta) - a_p sin(theta_b + Omega (u + eta + rho_a + de)) = 0,
 // de(x) = r(t_a + x).n - r(t_a).n, theta_b the binary phase at tau_a; Delta = eta - D_a.
-// Two Newton steps from eta_0 = a_p sin(theta_b + Omega u).
-// Outputs the interpolation centre j* = r + round-half-up(Delta / dt), the offset
-// delta_c = Delta / dt - round(.) in [-1/2, 1/2) and the heterodyne phase frac(f_h Delta).
-__device__ __forceinline__ void time_base(double u, double a_p, double Om, double sb, double cb,
-                                          const EarthConst &ec, const Anchor &an, double dt,
-                                          double f_het, int64_t r, int64_t &jstar, double &dc,
-                                          double &psi) {
+// Three Newton steps from eta_0 = a_p sin(theta_b + Omega u) (quadratic convergence from an
+// initial error below 0.1 s leaves < 1e-25 s).
+__device__ __forceinline__ double node_eta(double u, double a_p, double Om, double sb, double cb,
+                                           const EarthConst &ec, const Anchor &an) {
     double s, cm;
     sincos_small(Om * u, s, cm);
     double eta = a_p * (fma(sb, cm, sb) + cb * s);
 #pragma unroll
-    for (int it = 0; it < 2; ++it) {
+    for (int it = 0; it < 3; ++it) {
         const double x = u + eta;
         double so, co, sd, cd;
         sincos_small(ec.w_o * x, so, co);
@@ -90,12 +87,69 @@ __device__ __forceinline__ void time_base(double u, double a_p, double Om, doubl
         const double Gp = (1.0 + dep) * (1.0 - a_p * Om * cosb);
         eta -= G / Gp;
     }
-    const double q = (eta - an.D_a) / dt;
+    return eta;
+}
+
+// eta(u) over a segment, u in [-h, h] with h = N_K dt / 2, as a Chebyshev series of degree
+// kCheb - 1: node values at u_j = h cos(pi (j + 1/2) / kCheb), coefficients
+// c_k = (2 / kCheb) sum_j eta_j cos(pi k (j + 1/2) / kCheb), c_0 stored halved.  eta is an
+// entire function whose k-th coefficient is bounded by a_p (Omega h / 2)^k / k!, so degree 9
+// keeps the truncation below 1e-16 s for segments up to ~6000 s.
+// Threads 0..kCheb-1 of `lanes` compute the nodes of one (detector, segment).
+__device__ __forceinline__ double cheb_coef(const double *eta, const double *T, int k) {
+    double c = 0.0;
+#pragma unroll
+    for (int j = 0; j < kCheb; ++j) c = fma(eta[j], T[k * kCheb + j], c);
+    c *= 2.0 / kCheb;
+    return k == 0 ? 0.5 * c : c;
+}
+
+// Per sample: eta by Clenshaw at x = u / h, then the interpolation centre j* = r +
+// round-half-up(Delta / dt), the offset delta_c = Delta / dt - round(.) in [-1/2, 1/2) and the
+// heterodyne phase frac(f_h Delta) = frac(psi_a + f_h eta), cycles.
+__device__ __forceinline__ void sample_time(const double *coef, double x, const Anchor &an, double inv_dt,
+                                            double f_het, int64_t r, int64_t &jstar, double &dc, double &psi) {
+    double b1 = 0.0, b2 = 0.0;
+    const double x2 = 2.0 * x;
+#pragma unroll
+    for (int k = kCheb - 1; k >= 1; --k) {
+        const double b0 = fma(x2, b1, coef[k] - b2);
+        b2 = b1;
+        b1 = b0;
+    }
+    const double eta = fma(x, b1, coef[0] - b2);
+    const double q = (eta - an.D_a) * inv_dt;
     const double k = floor(q + 0.5);
     jstar = r + (int64_t)k;
     dc = q - k;
-    double ps = an.psi_a + f_het * eta;
+    const double ps = fma(f_het, eta, an.psi_a);
     psi = ps - floor(ps);
+}
+
+// Time base kernel: one thread per (template, active segment entry, Chebyshev node).  Writes the
+// kCheb coefficients of eta(u) for every (template, entry): coef[tb][entry][k].  16 entries x
+// kCheb nodes per workgroup; node values meet in LDS for the coefficient transform.
+constexpr int kTbEntries = 16;
+
+__global__ void __launch_bounds__(kTbEntries * kCheb) k_timebase(BandDev B, const double *tmpl, double *coef) {
+    __shared__ double sh_eta[kTbEntries * kCheb];
+    const int le = threadIdx.x / kCheb;           // entry within the workgroup
+    const int j = threadIdx.x - le * kCheb;       // node (and later coefficient) index
+    const int w = blockIdx.x * kTbEntries + le;   // entry in the work list
+    const int tb = blockIdx.y;
+    const bool on = w < B.n_work;
+    if (on) {
+        const int entry = B.work[w];
+        const int det = entry / B.n_seg;
+        const int K = entry - det * B.n_seg;
+        const double *tp = tmpl + (size_t)kTmplStride * tb;
+        double sb, cb;
+        binary_anchor(tp, K, sb, cb);
+        const double h = 0.5 * (double)B.n_k * B.dt;
+        sh_eta[threadIdx.x] = node_eta(h * B.cheb_x[j], tp[0], tp[1], sb, cb, B.earth[det], B.anchors[entry]);
+    }
+    __syncthreads();
+    if (on) coef[((size_t)tb * B.n_work + w) * kCheb + j] = cheb_coef(sh_eta + le * kCheb, B.cheb_T, j);
 }
 
 // ------------------------------------------------------------------ resampling
@@ -110,90 +164,167 @@ template <typename T> __device__ __forceinline__ const T *win_table(const BandDe
 template <> __device__ __forceinline__ const float *win_table<float>(const BandDev &B) { return B.win32; }
 template <> __device__ __forceinline__ const double *win_table<double>(const BandDev &B) { return B.win64; }
 
-// sum_{n=-D}^{D} w sinc(delta_c - n) x'_{j*+n}, with sin(pi (dc - n)) = (-1)^n sin(pi dc);
-// taps outside [0, n) read zero.
-template <typename T>
-__device__ __forceinline__ c2<T> interpolate(const BandDev &B, const float2 *xd, int64_t jstar,
-                                             double dcd) {
+template <typename T> __device__ __forceinline__ T recip(T v);
+// v_rcp_f32 (1 ulp) for the split path; IEEE division for FP64.
+template <> __device__ __forceinline__ float recip<float>(float v) { return __builtin_amdgcn_rcpf(v); }
+template <> __device__ __forceinline__ double recip<double>(double v) { return 1.0 / v; }
+
+// sin(pi v) and (cos, sin)(2 pi v): OCML sinpi / sincospi in FP64; in FP32 the hardware
+// v_sin_f32 / v_cos_f32, which take their argument in revolutions (|v| <= 1 here).
+template <typename T> __device__ __forceinline__ T sin_pi(T v);
+template <> __device__ __forceinline__ double sin_pi<double>(double v) { return sinpi(v); }
+template <> __device__ __forceinline__ float sin_pi<float>(float v) { return __builtin_amdgcn_sinf(0.5f * v); }
+template <typename T> __device__ __forceinline__ void sincos_rev(double v, T &s, T &c);
+template <> __device__ __forceinline__ void sincos_rev<double>(double v, double &s, double &c) {
+    sincospi(2.0 * v, &s, &c);
+}
+template <> __device__ __forceinline__ void sincos_rev<float>(double v, float &s, float &c) {
+    const float f = (float)v;
+    s = __builtin_amdgcn_sinf(f);
+    c = __builtin_amdgcn_cosf(f);
+}
+// cos(pi v) for the continuous window
+template <typename T> __device__ __forceinline__ T cos_pi(T v);
+template <> __device__ __forceinline__ double cos_pi<double>(double v) { return cospi(v); }
+template <> __device__ __forceinline__ float cos_pi<float>(float v) { return __builtin_amdgcn_cosf(0.5f * v); }
+
+// Weight of tap n for centre offset dc: w sinc(dc - n) with sin(pi (dc - n)) = (-1)^n sin(pi dc),
+// s = sin(pi dc) / pi.  WIN 0: Hamming indexed by tap (table); WIN 1: Hamming at the offset.
+template <typename T, int WIN>
+__device__ __forceinline__ T tap_weight(const T *wt, int D, T inv_d1, T dc, T s, int n) {
+    const T d = dc - (T)n;
+    T tap;
+    if (n == 0) {
+        tap = (dc == (T)0) ? (T)1 : s * recip<T>(dc);
+    } else {
+        tap = ((n & 1) ? -s : s) * recip<T>(d);
+    }
+    const T w = (WIN == 0) ? wt[n + D] : (T)0.54 + (T)0.46 * cos_pi<T>(d * inv_d1);
+    return w * tap;
+}
+
+// sum_{n=-D}^{D} w sinc(delta_c - n) x'_{j*+n}; taps outside [0, n) read zero.  DT > 0 fixes D
+// at compile time (unrolled taps).  The bounds checks are taken only near the data edges.
+template <typename T, int DT, int WIN>
+__device__ __forceinline__ c2<T> interpolate(const BandDev &B, const float2 *xd, int64_t jstar, double dcd) {
     const T dc = (T)dcd;
-    const T s = sinpi_t<T>(dc) * (T)0.318309886183790671537767526745;  // sin(pi dc) / pi
+    const T s = sin_pi<T>(dc) * (T)0.318309886183790671537767526745;
     const T *wt = win_table<T>(B);
-    const int D = B.D;
+    const int D = DT > 0 ? DT : B.D;
+    const T inv_d1 = (T)1 / (T)(D + 1);
     T re = 0, im = 0;
-    for (int n = -D; n <= D; ++n) {
-        const int64_t j = jstar + n;
-        if (j < 0 || j >= B.n) continue;
-        const T d = dc - (T)n;
-        T tap;
-        if (d == (T)0) {
-            tap = (T)1;
+    if (jstar - D >= 0 && jstar + D < B.n) {
+        const float2 *xc = xd + jstar;
+        if constexpr (DT > 0) {
+#pragma unroll
+            for (int n = -DT; n <= DT; ++n) {
+                const T wv = tap_weight<T, WIN>(wt, D, inv_d1, dc, s, n);
+                const float2 xv = xc[n];
+                re = fma(wv, (T)xv.x, re);
+                im = fma(wv, (T)xv.y, im);
+            }
         } else {
-            tap = ((n & 1) ? -s : s) / d;
+            for (int n = -D; n <= D; ++n) {
+                const T wv = tap_weight<T, WIN>(wt, D, inv_d1, dc, s, n);
+                const float2 xv = xc[n];
+                re = fma(wv, (T)xv.x, re);
+                im = fma(wv, (T)xv.y, im);
+            }
         }
-        const T w = (B.window == 0) ? wt[n + D] : (T)0.54 + (T)0.46 * cospi_t<T>(d / (T)(D + 1));
-        const float2 xv = xd[j];
-        re += (w * tap) * (T)xv.x;
-        im += (w * tap) * (T)xv.y;
+    } else {
+        for (int n = -D; n <= D; ++n) {
+            const int64_t j = jstar + n;
+            if (j < 0 || j >= B.n) continue;
+            const T wv = tap_weight<T, WIN>(wt, D, inv_d1, dc, s, n);
+            const float2 xv = xd[j];
+            re = fma(wv, (T)xv.x, re);
+            im = fma(wv, (T)xv.y, im);
+        }
     }
     return mk<T>(re, im);
 }
 
-template <typename T>
-__global__ void __launch_bounds__(256) k_resample(BandDev B, const double *tmpl, c2<T> *y) {
-    const int entry = B.work[blockIdx.x];
+// The same tap sum over an LDS window w[] holding x'_{j* - off + m}; the caller guarantees
+// off - D >= 0 and off + D < W.
+template <typename T, int DT, int WIN>
+__device__ __forceinline__ c2<T> interpolate_window(const BandDev &B, const float2 *w, int off, double dcd) {
+    const T dc = (T)dcd;
+    const T s = sin_pi<T>(dc) * (T)0.318309886183790671537767526745;
+    const T *wt = win_table<T>(B);
+    const int D = DT > 0 ? DT : B.D;
+    const T inv_d1 = (T)1 / (T)(D + 1);
+    T re = 0, im = 0;
+    if constexpr (DT > 0) {
+#pragma unroll
+        for (int n = -DT; n <= DT; ++n) {
+            const T wv = tap_weight<T, WIN>(wt, D, inv_d1, dc, s, n);
+            const float2 xv = w[off + n];
+            re = fma(wv, (T)xv.x, re);
+            im = fma(wv, (T)xv.y, im);
+        }
+    } else {
+        for (int n = -D; n <= D; ++n) {
+            const T wv = tap_weight<T, WIN>(wt, D, inv_d1, dc, s, n);
+            const float2 xv = w[off + n];
+            re = fma(wv, (T)xv.x, re);
+            im = fma(wv, (T)xv.y, im);
+        }
+    }
+    return mk<T>(re, im);
+}
+
+// Resampler: one 64-thread workgroup per (template, active segment, 64 samples); the segment's
+// Chebyshev coefficients and anchor are uniform over the workgroup (scalar loads).
+template <typename T, int DT, int WIN>
+__global__ void __launch_bounds__(64) k_resample(BandDev B, const double *coef, c2<T> *y, int cps) {
+    const int w = blockIdx.x / cps;
+    const int s = (blockIdx.x - w * cps) * 64 + threadIdx.x;
+    const int tb = blockIdx.y;
+    const int entry = B.work[w];
     const int det = entry / B.n_seg;
     const int K = entry - det * B.n_seg;
-    const int tb = blockIdx.y;
-    const double *tp = tmpl + (size_t)kTmplStride * tb;
-    __shared__ double sh_sc[2];
-    if (threadIdx.x == 0) {
-        double sb, cb;
-        binary_anchor(tp, K, sb, cb);
-        sh_sc[0] = sb;
-        sh_sc[1] = cb;
-    }
-    __syncthreads();
-    const double sb = sh_sc[0], cb = sh_sc[1];
-    const double a_p = tp[0], Om = tp[1];
-    const Anchor an = B.anchors[entry];
-    const EarthConst ec = B.earth[det];
+    if (s >= B.n_k) return;
     const int64_t nr = (int64_t)B.n_seg * B.n_k;
-    const float2 *xd = B.x + (size_t)det * B.n;
-    const uint8_t *mk_ = B.mask + (size_t)det * nr;
+    const int64_t r = (int64_t)K * B.n_k + s;
     c2<T> *yo = y + ((size_t)tb * B.Q + det) * nr;
-    const double half = 0.5 * (double)B.n_k;
-    for (int s = threadIdx.x; s < B.n_k; s += blockDim.x) {
-        const int64_t r = (int64_t)K * B.n_k + s;
-        if (!mk_[r]) {
-            yo[r] = mk<T>((T)0, (T)0);
-            continue;
-        }
-        const double u = ((double)s - half) * B.dt;
-        int64_t jstar;
-        double dc, psi;
-        time_base(u, a_p, Om, sb, cb, ec, an, B.dt, B.f_het, r, jstar, dc, psi);
-        const c2<T> acc = interpolate<T>(B, xd, jstar, dc);
-        T c, sn;
-        if constexpr (sizeof(T) == 8) {
-            sincospi(2.0 * psi, &sn, &c);
-        } else {
-            sincospif(2.0f * (float)psi, &sn, &c);
-        }
-        yo[r] = mk<T>(c * acc.x - sn * acc.y, sn * acc.x + c * acc.y);
+    if (!B.mask[(size_t)det * nr + r]) {
+        yo[r] = mk<T>((T)0, (T)0);
+        return;
     }
+    const double *cf = coef + ((size_t)tb * B.n_work + w) * kCheb;
+    double cl[kCheb];
+#pragma unroll
+    for (int k = 0; k < kCheb; ++k) cl[k] = cf[k];
+    const Anchor an = B.anchors[entry];
+    int64_t jstar;
+    double dc, psi;
+    sample_time(cl, (double)(2 * s - B.n_k) * (1.0 / (double)B.n_k), an, B.inv_dt, B.f_het, r, jstar, dc, psi);
+    const c2<T> acc = interpolate<T, DT, WIN>(B, B.x + (size_t)det * B.n, jstar, dc);
+    T c, sn;
+    sincos_rev<T>(psi, sn, c);
+    yo[r] = mk<T>(c * acc.x - sn * acc.y, sn * acc.x + c * acc.y);
+}
+
+// v mod N_FFT for 0 <= v (a mask when N_FFT is a power of two).
+__device__ __forceinline__ int mod_fft(const BandDev &B, int64_t v) {
+    return B.nfft_mask ? (int)(v & B.nfft_mask) : (int)(v % B.n_fft);
 }
 
 // ------------------------------------------------------------------ FFT in LDS
 
 // Self-sorting Stockham passes (radix 4, a final radix 2 when log2 n is odd) over n points
 // held in LDS; twiddles exp(-2 pi i k r / (Ns R)) read from the N_FFT-entry table.
+// Threads g0, g0 + gs, ... of the block work on this transform; every thread of the block
+// must call it the same number of times (it holds block-wide barriers); `active` = false lets
+// a thread group skip the arithmetic while keeping the barriers.
 template <typename T>
-__device__ c2<T> *stockham(c2<T> *a, c2<T> *b, int n, const c2<T> *tw, int n_fft) {
+__device__ c2<T> *stockham(c2<T> *a, c2<T> *b, int n, const c2<T> *tw, int n_fft, int g0, int gs,
+                           bool active = true) {
     for (int Ns = 1; Ns < n;) {
         const int R = (Ns * 4 <= n) ? 4 : 2;
         const int stride = n / R;
         const int twstep = n_fft / (Ns * R);
-        for (int j = threadIdx.x; j < stride; j += blockDim.x) {
+        for (int j = g0; active && j < stride; j += gs) {
             const int k = j & (Ns - 1);
             const int idxD = (j - k) * R + k;
             if (R == 4) {
@@ -228,6 +359,243 @@ __device__ c2<T> *stockham(c2<T> *a, c2<T> *b, int n, const c2<T> *tw, int n_fft
 // Spectrum of one (template, detector, segment): for each residue class p of the output
 // bins, twiddle the zero-padded segment by exp(-2 pi i p s / N_FFT), n_s-point FFT, pick
 // bins kbar = m P + p, apply Phi_in = exp(-2 pi i kbar r_B / N_FFT) and 1 / (sigma sqrt N_K).
+// ------------------------------------------------------------------ register FFT (256 points)
+
+// 4-point forward DFT in place: (a0, a1, a2, a3) -> sum_n a_n exp(-2 pi i n k / 4).
+template <typename T>
+__device__ __forceinline__ void dft4(c2<T> &a0, c2<T> &a1, c2<T> &a2, c2<T> &a3) {
+    const c2<T> t0 = cadd<T>(a0, a2), t1 = csub<T>(a0, a2);
+    const c2<T> t2 = cadd<T>(a1, a3), t3 = cmul_mi<T>(csub<T>(a1, a3));
+    a0 = cadd<T>(t0, t2);
+    a2 = csub<T>(t0, t2);
+    a1 = cadd<T>(t1, t3);
+    a3 = csub<T>(t1, t3);
+}
+
+// 16-point forward DFT in registers, n = 4a + b, k = c + 4d: 4-point DFTs over a, twiddles
+// W16^(b c), 4-point DFTs over b.  On return A[k] is held in v[4 (k % 4) + k / 4].
+template <typename T>
+__device__ __forceinline__ void dft16(c2<T> *v) {
+    const T c1 = (T)0.92387953251128675613, s1 = (T)0.38268343236508977173, h = (T)0.70710678118654752440;
+#pragma unroll
+    for (int b = 0; b < 4; ++b) dft4<T>(v[b], v[4 + b], v[8 + b], v[12 + b]);
+    // v[4c + b] *= W16^(b c)
+    v[5] = cmul<T>(v[5], mk<T>(c1, -s1));    // b1 c1: W^1
+    v[6] = cmul<T>(v[6], mk<T>(h, -h));      // b2 c1: W^2
+    v[7] = cmul<T>(v[7], mk<T>(s1, -c1));    // b3 c1: W^3
+    v[9] = cmul<T>(v[9], mk<T>(h, -h));      // b1 c2: W^2
+    v[10] = cmul_mi<T>(v[10]);               // b2 c2: W^4 = -i
+    v[11] = cmul<T>(v[11], mk<T>(-h, -h));   // b3 c2: W^6
+    v[13] = cmul<T>(v[13], mk<T>(s1, -c1));  // b1 c3: W^3
+    v[14] = cmul<T>(v[14], mk<T>(-h, -h));   // b2 c3: W^6
+    v[15] = cmul<T>(v[15], mk<T>(-c1, s1));  // b3 c3: W^9
+#pragma unroll
+    for (int c = 0; c < 4; ++c) dft4<T>(v[4 * c], v[4 * c + 1], v[4 * c + 2], v[4 * c + 3]);
+}
+
+// 256-point FFT held by 16 lanes (lane t = threadIdx.x % 16 of the group), n = 16 n1 + n2,
+// k = k1 + 16 k2: lane t holds x[16 n1 + t] in v[n1]; 16-point DFTs over n1, twiddles
+// W256^(t k1) from the N_FFT-entry table (stride N_FFT / 256), transpose through `sc`
+// (16 x 17 padded), 16-point DFTs over n2.  On return lane t holds X[t + 16 k2] in
+// v[4 (k2 % 4) + k2 / 4].  Every thread of the block calls it (it holds one barrier).
+template <typename T>
+__device__ __forceinline__ void fft256_lanes(c2<T> *v, int t, c2<T> *sc, const c2<T> *tw, int tw_stride,
+                                             bool on) {
+    if (on) {
+        dft16<T>(v);
+#pragma unroll
+        for (int k1 = 1; k1 < 16; ++k1) {
+            const int pos = 4 * (k1 & 3) + (k1 >> 2);
+            v[pos] = cmul<T>(v[pos], tw[t * k1 * tw_stride]);
+        }
+#pragma unroll
+        for (int k1 = 0; k1 < 16; ++k1) sc[k1 * 17 + t] = v[4 * (k1 & 3) + (k1 >> 2)];
+    }
+    __syncthreads();
+    if (on) {
+#pragma unroll
+        for (int n2 = 0; n2 < 16; ++n2) v[n2] = sc[t * 17 + n2];
+        dft16<T>(v);
+    }
+    __syncthreads();
+}
+
+// Spectra of 256-point segments (n_s = 256, distinct output bins): one 16-lane group per
+// (template, detector, segment), 8 groups per 128-thread workgroup.  For each residue class p:
+// twiddle the zero-padded segment by exp(-2 pi i p s / N_FFT), FFT in registers, and write the
+// decimated bins kbar = m P + p with Phi_in and 1 / (sigma sqrt N_K).
+template <typename T>
+__global__ void __launch_bounds__(128) __attribute__((amdgpu_waves_per_eu(3)))
+k_spectra16(BandDev B, const c2<T> *y, c2<T> *F) {
+    __shared__ c2<T> sc_all[8 * 16 * 17];
+    const int grp = threadIdx.x >> 4, t = threadIdx.x & 15;
+    const int w = blockIdx.x * 8 + grp;
+    const int tb = blockIdx.y;
+    const bool on = w < B.n_work;
+    const int entry = on ? B.work[w] : 0;
+    const int det = entry / B.n_seg;
+    const int K = entry - det * B.n_seg;
+    const int64_t nr = (int64_t)B.n_seg * B.n_k;
+    const c2<T> *ys = y + ((size_t)tb * B.Q + det) * nr + (size_t)K * B.n_k;
+    const c2<T> *tw = twiddles<T>(B);
+    const int rb_mod = mod_fft(B, (int64_t)K * B.n_k);
+    const T scale = on ? (T)B.segw[entry].scale : (T)0;
+    c2<T> *Fo = F + (((size_t)tb * B.Q + det) * B.n_seg + K) * B.n_f;
+    c2<T> *sc = sc_all + grp * 16 * 17;
+    for (int p = 0; p < B.P; ++p) {
+        c2<T> v[16];
+#pragma unroll
+        for (int n1 = 0; n1 < 16; ++n1) {
+            const int sidx = 16 * n1 + t;
+            c2<T> x = (on && sidx < B.n_k) ? ys[sidx] : mk<T>((T)0, (T)0);
+            v[n1] = p ? cmul<T>(x, tw[p * sidx]) : x;
+        }
+        fft256_lanes<T>(v, t, sc, tw, B.n_fft >> 8, on);
+        if (on) {
+#pragma unroll
+            for (int k2 = 0; k2 < 16; ++k2) {
+                const int kb = (t + 16 * k2) * B.P + p;
+                const int i = B.bin_pos[kb];
+                if (i < 0) continue;
+                const int ph = mod_fft(B, (int64_t)kb * rb_mod);
+                Fo[i] = cscale<T>(cmul<T>(v[4 * (k2 & 3) + (k2 >> 2)], tw[ph]), scale);
+            }
+        }
+    }
+}
+
+// Spectra + pair sum for 256-point segments (split precision, distinct bins): one workgroup =
+// one template x one chunk of segments [K0, K1) (plus R halo segments before K0).  Each step
+// transforms S = 8 / Q consecutive segments of every detector, one 16-lane group per
+// (segment, detector), into an LDS ring of R + S decimated spectra, then accumulates each
+// bin's pair sum for the step's segments in the same order as k_pairs.  The segment spectra
+// never leave LDS; one partial per (template, chunk, bin) is written.
+struct SpairLayout {
+    int S, slots;
+    size_t off_acc, off_ring, off_flag, total;
+};
+
+__host__ __device__ inline SpairLayout spair_layout(int Q, int n_f, int R) {
+    SpairLayout L;
+    L.S = 8 / Q < 1 ? 1 : 8 / Q;
+    L.slots = R + L.S;
+    size_t o = 8 * 16 * 17 * sizeof(float2);  // transpose scratch
+    L.off_acc = o;
+    o += (size_t)n_f * 8;
+    L.off_ring = o;
+    o += (size_t)L.slots * Q * n_f * sizeof(float2);
+    L.off_flag = o;
+    o += (size_t)L.slots * Q;
+    L.total = (o + 15) & ~(size_t)15;
+    return L;
+}
+
+__global__ void __launch_bounds__(128) __attribute__((amdgpu_waves_per_eu(3)))
+k_spectra_pairs16(BandDev B, const float2 *y, double *part, int k_chunk, int n_chunks) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    const int Q = B.Q, n_f = B.n_f, n_k = B.n_k;
+    const SpairLayout Ly = spair_layout(Q, n_f, B.R);
+    float2 *sc_all = reinterpret_cast<float2 *>(smem);
+    double *acc = reinterpret_cast<double *>(smem + Ly.off_acc);
+    float2 *ring = reinterpret_cast<float2 *>(smem + Ly.off_ring);
+    uint8_t *flag = smem + Ly.off_flag;
+    const int tid = threadIdx.x;
+    const int grp = tid >> 4, t = tid & 15;
+    const int c = blockIdx.x, tb = blockIdx.y;
+    const int K0 = c * k_chunk;
+    const int K1 = min(B.n_seg, K0 + k_chunk);
+    const int Kh = max(0, K0 - B.R);
+    const int S = Ly.S, slots = Ly.slots;
+    const int64_t nr = (int64_t)B.n_seg * n_k;
+    const float2 *tw = B.tw32;
+    const int tws = B.n_fft >> 8;
+    const bool cross = (B.pairs & 1) != 0, same = (B.pairs & 2) != 0;
+    float2 *sc = sc_all + grp * 16 * 17;
+    const int sd = grp / Q, X = grp - sd * Q;  // this group's (segment in step, detector)
+    const float2 *ybase = y + ((size_t)tb * Q + X) * nr;
+
+    for (int i = tid; i < n_f; i += 128) acc[i] = 0.0;
+    for (int i = tid; i < slots * Q; i += 128) flag[i] = 0;
+    __syncthreads();
+
+    int slot_b = Kh % slots;  // ring slot of segment Kb
+    for (int Kb = Kh; Kb < K1; Kb += S) {
+        const int ns = min(S, K1 - Kb);
+        const int K = Kb + sd;
+        const bool mine = sd < ns;
+        const bool on = mine && B.seg_work[X * B.n_seg + K] >= 0;
+        int myslot = slot_b + sd;
+        if (myslot >= slots) myslot -= slots;
+        if (mine && t == 0) flag[myslot * Q + X] = on ? 1 : 0;
+        const float2 *ys = ybase + (size_t)K * n_k;
+        const int rb_mod = on ? mod_fft(B, (int64_t)K * n_k) : 0;
+        const float scale = on ? (float)B.segw[X * B.n_seg + K].scale : 0.f;
+        float2 *Fo = ring + ((size_t)myslot * Q + X) * n_f;
+        for (int p = 0; p < B.P; ++p) {
+            float2 v[16];
+#pragma unroll
+            for (int n1 = 0; n1 < 16; ++n1) {
+                const int sidx = 16 * n1 + t;
+                float2 x = (on && sidx < n_k) ? ys[sidx] : make_float2(0.f, 0.f);
+                v[n1] = p ? cmul<float>(x, tw[p * sidx]) : x;
+            }
+            fft256_lanes<float>(v, t, sc, tw, tws, on);
+            if (on) {
+#pragma unroll
+                for (int k2 = 0; k2 < 16; ++k2) {
+                    const int kb = (t + 16 * k2) * B.P + p;
+                    const int i = B.bin_pos[kb];
+                    if (i < 0) continue;
+                    const int ph = mod_fft(B, (int64_t)kb * rb_mod);
+                    Fo[i] = cscale<float>(cmul<float>(v[4 * (k2 & 3) + (k2 >> 2)], tw[ph]), scale);
+                }
+            }
+        }
+        __syncthreads();
+        for (int i = tid; i < n_f; i += 128) {
+            double a = acc[i];
+            for (int s2 = 0; s2 < ns; ++s2) {
+                const int Kc = Kb + s2;
+                if (Kc < K0) continue;
+                int slot = slot_b + s2;
+                if (slot >= slots) slot -= slots;
+                const int Lmin = max(0, Kc - B.R);
+                for (int Xc = 0; Xc < Q; ++Xc) {
+                    if (!flag[slot * Q + Xc]) continue;
+                    float2 ga = make_float2(0.f, 0.f), gb = make_float2(0.f, 0.f);
+                    int sl = slot - (Kc - Lmin);
+                    if (sl < 0) sl += slots;
+                    for (int L = Lmin; L <= Kc; ++L) {
+                        for (int Y = 0; Y < Q; ++Y) {
+                            const bool inc = (L < Kc) ? ((Y != Xc) ? cross : same) : (cross && Y > Xc);
+                            if (!inc || !flag[sl * Q + Y]) continue;
+                            const float2 g = ring[((size_t)sl * Q + Y) * n_f + i];
+                            const SegWeight &w = B.segw[Y * B.n_seg + L];
+                            const float wa = (float)w.ahat, wb = (float)w.bhat;
+                            ga.x += wa * g.x; ga.y += wa * g.y;
+                            gb.x += wb * g.x; gb.y += wb * g.y;
+                        }
+                        if (++sl == slots) sl = 0;
+                    }
+                    const float2 f = ring[((size_t)slot * Q + Xc) * n_f + i];
+                    const SegWeight &wk = B.segw[Xc * B.n_seg + Kc];
+                    const float aK = (float)wk.ahat, bK = (float)wk.bhat;
+                    const float hx = aK * ga.x + bK * gb.x, hy = aK * ga.y + bK * gb.y;
+                    a += (double)(f.x * hx + f.y * hy);
+                }
+            }
+            acc[i] = a;
+        }
+        __syncthreads();
+        slot_b += S;
+        if (slot_b >= slots) slot_b -= slots;
+    }
+    for (int i = tid; i < n_f; i += 128) part[((size_t)tb * n_chunks + c) * n_f + i] = acc[i];
+}
+
+// The fused kernel keeps the activity bits of a step (S segments x Q detectors) in 64 bits.
+__host__ __device__ inline bool Q_ok(const BandDev &B) { return B.Q >= 1 && B.Q * 4 <= 64; }
+
 template <typename T>
 __global__ void __launch_bounds__(256) k_spectra(BandDev B, const c2<T> *y, c2<T> *F) {
     extern __shared__ __align__(16) unsigned char smem[];
@@ -240,7 +608,7 @@ __global__ void __launch_bounds__(256) k_spectra(BandDev B, const c2<T> *y, c2<T
     const int64_t nr = (int64_t)B.n_seg * B.n_k;
     const c2<T> *ys = y + ((size_t)tb * B.Q + det) * nr + (size_t)K * B.n_k;
     const c2<T> *tw = twiddles<T>(B);
-    const int rb_mod = (int)(((int64_t)K * B.n_k) % B.n_fft);
+    const int rb_mod = mod_fft(B, (int64_t)K * B.n_k);
     const T scale = (T)B.segw[entry].scale;
     c2<T> *Fo = F + (((size_t)tb * B.Q + det) * B.n_seg + K) * B.n_f;
     for (int p = 0; p < B.P; ++p) {
@@ -253,10 +621,10 @@ __global__ void __launch_bounds__(256) k_spectra(BandDev B, const c2<T> *y, c2<T
             buf0[s] = v;
         }
         __syncthreads();
-        const c2<T> *res = stockham<T>(buf0, buf1, B.n_s, tw, B.n_fft);
+        const c2<T> *res = stockham<T>(buf0, buf1, B.n_s, tw, B.n_fft, threadIdx.x, blockDim.x);
         for (int i = threadIdx.x; i < B.n_f; i += blockDim.x) {
             if (B.bin_p[i] != p) continue;
-            const int ph = (int)(((int64_t)B.bin_kb[i] * rb_mod) % B.n_fft);
+            const int ph = mod_fft(B, (int64_t)B.bin_kb[i] * rb_mod);
             Fo[i] = cscale<T>(cmul<T>(res[B.bin_m[i]], tw[ph]), scale);
         }
         __syncthreads();
@@ -306,6 +674,248 @@ __global__ void __launch_bounds__(256) k_pairs(BandDev B, const c2<T> *F, double
     part[((size_t)tb * n_chunks + c) * B.n_f + i] = acc;
 }
 
+// ------------------------------------------------------------------ fused path
+
+// Threads per FFT group: n_s / 4 (one radix-4 butterfly each), at most the whole block.
+__host__ __device__ inline int fused_group(int n_s) {
+    const int q = n_s / 4;
+    return q < 1 ? 1 : (q > 256 ? 256 : q);
+}
+
+// Input window per (segment, detector) staged in LDS: the taps of every sample of a segment
+// lie within n_k + 2D + 2 * margin samples around the segment's centre offset; taps outside
+// (never for the workloads here) are read from global memory.
+__host__ __device__ inline int fused_margin(int n_k, double dt) {
+    return 3 + (int)(4e-4 * 0.5 * (double)n_k);
+}
+
+// LDS layout of the fused kernel: per-bin accumulators acc[n_f] (double), per (step segment,
+// detector) time-base coefficients and anchor terms, window starts, input windows
+// xwin[S][Q][W] (float2), resampled segments ybuf[S][Q][n_s], FFT work buffers [G][2][n_s],
+// ring of decimated spectra [R+S][Q][n_f] and its activity flags.
+struct FusedLayout {
+    int G, S, W, slots;
+    size_t off_acc, off_coef, off_ws, off_x, off_y, off_work, off_ring, off_flag, total;
+};
+
+__host__ __device__ inline FusedLayout fused_layout(int Q, int n_s, int n_k, int n_f, int R, int D, double dt,
+                                                    size_t cs, int S) {
+    FusedLayout L;
+    L.G = 256 / fused_group(n_s);
+    L.S = S;
+    L.W = n_k + 2 * D + 2 * fused_margin(n_k, dt) + 1;
+    L.slots = R + S;
+    size_t o = 0;
+    L.off_acc = o;
+    o += (size_t)n_f * 8;
+    L.off_coef = o;
+    o += (size_t)S * Q * (kCheb + 2) * 8;
+    L.off_ws = o;
+    o += (size_t)S * Q * 8;
+    L.off_x = o;
+    o += (size_t)S * Q * L.W * 8;
+    o = (o + 15) & ~(size_t)15;
+    L.off_y = o;
+    o += (size_t)S * Q * n_s * cs;
+    L.off_work = o;
+    o += (size_t)L.G * 2 * n_s * cs;
+    L.off_ring = o;
+    o += (size_t)L.slots * Q * n_f * cs;
+    L.off_flag = o;
+    o += (size_t)L.slots * Q;
+    L.total = (o + 15) & ~(size_t)15;
+    return L;
+}
+
+// One workgroup = one template x one chunk of segments [K0, K1), processed S segments per step
+// (plus the R segments before K0 as a halo): stage the coefficients, anchors and input windows
+// of the step's (segment, detector) pairs in LDS with one batch of loads, resample them, FFT
+// them (Q P S transforms, G at a time), keep the decimated spectra in a ring of R + S segments,
+// and accumulate each bin's pair sum for the chunk's segments in the same order as k_pairs.
+// Writes one partial per (template, chunk, bin).
+template <typename T, int DT>
+__global__ void __launch_bounds__(256) k_fused(BandDev B, const double *coef, const int *seg_work,
+                                              double *part, int k_chunk, int n_chunks, int S) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    const int Q = B.Q, n_s = B.n_s, n_k = B.n_k, n_f = B.n_f;
+    const FusedLayout Ly = fused_layout(Q, n_s, n_k, n_f, B.R, B.D, B.dt, sizeof(c2<T>), S);
+    double *acc = reinterpret_cast<double *>(smem + Ly.off_acc);
+    double *scoef = reinterpret_cast<double *>(smem + Ly.off_coef);   // [S*Q][kCheb + 2]
+    int64_t *wstart = reinterpret_cast<int64_t *>(smem + Ly.off_ws);  // [S*Q]
+    float2 *xwin = reinterpret_cast<float2 *>(smem + Ly.off_x);       // [S*Q][W]
+    c2<T> *ybuf = reinterpret_cast<c2<T> *>(smem + Ly.off_y);
+    c2<T> *work = reinterpret_cast<c2<T> *>(smem + Ly.off_work);
+    c2<T> *ring = reinterpret_cast<c2<T> *>(smem + Ly.off_ring);
+    uint8_t *flag = smem + Ly.off_flag;
+
+    const int c = blockIdx.x;
+    const int tb = blockIdx.y;
+    const int K0 = c * k_chunk;
+    const int K1 = min(B.n_seg, K0 + k_chunk);
+    const int Kh = max(0, K0 - B.R);
+    const int tid = threadIdx.x;
+    const int nth = blockDim.x;
+    const int W = Ly.W, slots = Ly.slots;
+    const int64_t nr = (int64_t)B.n_seg * n_k;
+    const c2<T> *tw = twiddles<T>(B);
+    const bool cross = (B.pairs & 1) != 0, same = (B.pairs & 2) != 0;
+    const int per = fused_group(n_s);
+    const double inv_nk = 1.0 / (double)n_k;  // same expression as k_resample
+    const int margin = fused_margin(n_k, B.dt);
+    const int D = DT > 0 ? DT : B.D;
+
+    for (int i = tid; i < n_f; i += nth) acc[i] = 0.0;
+    for (int i = tid; i < slots * Q; i += nth) flag[i] = 0;
+    for (int i = tid; i < S * Q * n_s; i += nth) ybuf[i] = mk<T>((T)0, (T)0);
+    __syncthreads();
+
+    for (int Kb = Kh; Kb < K1; Kb += S) {
+        const int ns = min(S, K1 - Kb);  // segments in this step
+        // activity bits of the step: bit (sd * Q + X)
+        uint64_t act = 0;
+        for (int sd = 0; sd < ns; ++sd)
+            for (int X = 0; X < Q; ++X)
+                if (B.active[X * B.n_seg + Kb + sd]) act |= 1ull << (sd * Q + X);
+        // phase A: coefficients, anchor terms, window starts
+        if (tid < ns * Q) {
+            const int sd = tid / Q, X = tid - sd * Q;
+            const int K = Kb + sd;
+            double *sc = scoef + (size_t)tid * (kCheb + 2);
+            const int ws = seg_work[X * B.n_seg + K];
+            int64_t start = 0;
+            if (ws >= 0) {
+                const double *cf = coef + ((size_t)tb * B.n_work + ws) * kCheb;
+                double cl[kCheb];
+#pragma unroll
+                for (int k = 0; k < kCheb; ++k) {
+                    cl[k] = cf[k];
+                    sc[k] = cl[k];
+                }
+                const Anchor &an = B.anchors[X * B.n_seg + K];
+                sc[kCheb] = an.D_a;
+                sc[kCheb + 1] = an.psi_a;
+                // eta at the segment centre: sum_k c_k T_k(0), T_k(0) = cos(k pi / 2)
+                double em = cl[0];
+#pragma unroll
+                for (int k = 2; k < kCheb; k += 2) em += (k & 2) ? -cl[k] : cl[k];
+                const int64_t kc = (int64_t)floor((em - an.D_a) * B.inv_dt + 0.5);
+                start = (int64_t)K * n_k + kc - D - margin;
+            }
+            wstart[tid] = start;
+            flag[((Kb + sd) % slots) * Q + X] = (ws >= 0) ? 1 : 0;
+        }
+        __syncthreads();
+        // phase B: input windows (out-of-range samples read zero)
+        for (int idx = tid; idx < ns * Q * W; idx += nth) {
+            const int e = idx / W;
+            if (!((act >> e) & 1ull)) continue;
+            const int X = e % Q;
+            const int64_t j = wstart[e] + (idx - e * W);
+            xwin[idx] = (j >= 0 && j < B.n) ? B.x[(size_t)X * B.n + j] : make_float2(0.f, 0.f);
+        }
+        __syncthreads();
+        // phase C: resample into ybuf (the zero padding beyond n_k was written at the start)
+        for (int idx = tid; idx < ns * Q * n_k; idx += nth) {
+            const int e = idx / n_k;
+            const int s = idx - e * n_k;
+            if (!((act >> e) & 1ull)) continue;
+            const int sd = e / Q, X = e - sd * Q;
+            const int K = Kb + sd;
+            const int64_t r = (int64_t)K * n_k + s;
+            c2<T> v = mk<T>((T)0, (T)0);
+            if (B.mask[(size_t)X * nr + r]) {
+                const double *sc = scoef + (size_t)e * (kCheb + 2);
+                Anchor an;
+                an.D_a = sc[kCheb];
+                an.psi_a = sc[kCheb + 1];
+                int64_t jstar;
+                double dc, psi;
+                sample_time(sc, (double)(2 * s - n_k) * inv_nk, an, B.inv_dt, B.f_het, r, jstar, dc, psi);
+                const int64_t off = jstar - wstart[e];
+                c2<T> accv;
+                if (off - D >= 0 && off + D < W) {
+                    accv = B.window == 0 ? interpolate_window<T, DT, 0>(B, xwin + (size_t)e * W, (int)off, dc)
+                                         : interpolate_window<T, DT, 1>(B, xwin + (size_t)e * W, (int)off, dc);
+                } else {
+                    accv = B.window == 0 ? interpolate<T, DT, 0>(B, B.x + (size_t)X * B.n, jstar, dc)
+                                         : interpolate<T, DT, 1>(B, B.x + (size_t)X * B.n, jstar, dc);
+                }
+                T cs_, sn_;
+                sincos_rev<T>(psi, sn_, cs_);
+                v = mk<T>(cs_ * accv.x - sn_ * accv.y, sn_ * accv.x + cs_ * accv.y);
+            }
+            ybuf[e * n_s + s] = v;
+        }
+        __syncthreads();
+        // phase D: FFT jobs (segment, detector, residue), G at a time
+        const int jobs = ns * Q * B.P;
+        const int grp = tid / per, g0 = tid - grp * per;
+        for (int jb = 0; jb < jobs; jb += Ly.G) {
+            const int job = jb + grp;
+            const int e = job / B.P;
+            const bool on = grp < Ly.G && job < jobs && ((act >> e) & 1ull);
+            const int p = on ? job - e * B.P : 0;
+            const int sd = on ? e / Q : 0, X = on ? e - sd * Q : 0;
+            const int K = Kb + sd;
+            c2<T> *w0 = work + (size_t)(grp < Ly.G ? grp : 0) * 2 * n_s;
+            c2<T> *w1 = w0 + n_s;
+            if (on) {
+                for (int s2 = g0; s2 < n_s; s2 += per) {
+                    c2<T> v = ybuf[e * n_s + s2];
+                    if (p && s2 < n_k) v = cmul<T>(v, tw[p * s2]);
+                    w0[s2] = v;
+                }
+            }
+            __syncthreads();
+            const c2<T> *res = stockham<T>(w0, w1, n_s, tw, B.n_fft, g0, per, on);
+            if (on) {
+                const int rb_mod = mod_fft(B, (int64_t)K * n_k);
+                const T scale = (T)B.segw[X * B.n_seg + K].scale;
+                c2<T> *Fo = ring + ((size_t)(K % slots) * Q + X) * n_f;
+                for (int i = g0; i < n_f; i += per) {
+                    if (B.bin_p[i] != p) continue;
+                    const int ph = mod_fft(B, (int64_t)B.bin_kb[i] * rb_mod);
+                    Fo[i] = cscale<T>(cmul<T>(res[B.bin_m[i]], tw[ph]), scale);
+                }
+            }
+            __syncthreads();
+        }
+        // phase E: pair sums of the step's segments that belong to the chunk, in order
+        for (int i = tid; i < n_f; i += nth) {
+            double a = acc[i];
+            for (int sd = 0; sd < ns; ++sd) {
+                const int K = Kb + sd;
+                if (K < K0) continue;
+                const int slot = K % slots;
+                for (int X = 0; X < Q; ++X) {
+                    if (!flag[slot * Q + X]) continue;
+                    c2<T> ga = mk<T>((T)0, (T)0), gb = mk<T>((T)0, (T)0);
+                    for (int L = max(0, K - B.R); L <= K; ++L) {
+                        const int sl = L % slots;
+                        for (int Y = 0; Y < Q; ++Y) {
+                            const bool inc = (L < K) ? ((Y != X) ? cross : same) : (cross && Y > X);
+                            if (!inc || !flag[sl * Q + Y]) continue;
+                            const c2<T> g = ring[((size_t)sl * Q + Y) * n_f + i];
+                            const SegWeight &w = B.segw[Y * B.n_seg + L];
+                            const T wa = (T)w.ahat, wb = (T)w.bhat;
+                            ga.x += wa * g.x; ga.y += wa * g.y;
+                            gb.x += wb * g.x; gb.y += wb * g.y;
+                        }
+                    }
+                    const c2<T> f = ring[((size_t)slot * Q + X) * n_f + i];
+                    const SegWeight &wk = B.segw[X * B.n_seg + K];
+                    const T aK = (T)wk.ahat, bK = (T)wk.bhat;
+                    const T hx = aK * ga.x + bK * gb.x, hy = aK * ga.y + bK * gb.y;
+                    a += (double)(f.x * hx + f.y * hy);
+                }
+            }
+            acc[i] = a;
+        }
+        __syncthreads();
+    }
+    for (int i = tid; i < n_f; i += nth) part[((size_t)tb * n_chunks + c) * n_f + i] = acc[i];
+}
+
 __global__ void k_finish(int n_f, int n_tmpl, const double *part, int n_chunks, double factor,
                          void *out, int out_fp64) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
@@ -328,20 +938,45 @@ __global__ void k_zero(uint32_t *p, size_t n_words) {
 
 }  // namespace
 
-hipError_t launch_resample(const BandDev &B, const double *d_tmpl, int n_tmpl, bool fp64, void *y,
+hipError_t launch_timebase(const BandDev &B, const double *d_tmpl, int n_tmpl, double *coef,
                            hipStream_t stream) {
     if (B.n_work == 0 || n_tmpl == 0) return hipSuccess;
-    dim3 grid(B.n_work, n_tmpl), block(256);
-    if (fp64)
-        hipLaunchKernelGGL(k_resample<double>, grid, block, 0, stream, B, d_tmpl, (double2 *)y);
+    dim3 grid((B.n_work + kTbEntries - 1) / kTbEntries, n_tmpl), block(kTbEntries * kCheb);
+    hipLaunchKernelGGL(k_timebase, grid, block, 0, stream, B, d_tmpl, coef);
+    return hipGetLastError();
+}
+
+template <typename T, int DT>
+static void launch_resample_t(const BandDev &B, const double *coef, int n_tmpl, void *y, hipStream_t stream) {
+    const int cps = (B.n_k + 63) / 64;
+    dim3 grid((unsigned)((int64_t)B.n_work * cps), n_tmpl), block(64);
+    if (B.window == 0)
+        hipLaunchKernelGGL((k_resample<T, DT, 0>), grid, block, 0, stream, B, coef, (c2<T> *)y, cps);
     else
-        hipLaunchKernelGGL(k_resample<float>, grid, block, 0, stream, B, d_tmpl, (float2 *)y);
+        hipLaunchKernelGGL((k_resample<T, DT, 1>), grid, block, 0, stream, B, coef, (c2<T> *)y, cps);
+}
+
+hipError_t launch_resample(const BandDev &B, const double *coef, int n_tmpl, bool fp64, void *y,
+                           hipStream_t stream) {
+    if (B.n_work == 0 || n_tmpl == 0) return hipSuccess;
+    if (fp64) {
+        if (B.D == 8) launch_resample_t<double, 8>(B, coef, n_tmpl, y, stream);
+        else launch_resample_t<double, 0>(B, coef, n_tmpl, y, stream);
+    } else {
+        if (B.D == 8) launch_resample_t<float, 8>(B, coef, n_tmpl, y, stream);
+        else launch_resample_t<float, 0>(B, coef, n_tmpl, y, stream);
+    }
     return hipGetLastError();
 }
 
 hipError_t launch_spectra(const BandDev &B, int n_tmpl, bool fp64, const void *y, void *F,
                           hipStream_t stream) {
     if (B.n_work == 0 || n_tmpl == 0) return hipSuccess;
+    if (!fp64 && B.n_s == 256 && B.bins_unique) {
+        dim3 grid((B.n_work + 7) / 8, n_tmpl), block(128);
+        hipLaunchKernelGGL(k_spectra16<float>, grid, block, 0, stream, B, (const float2 *)y, (float2 *)F);
+        return hipGetLastError();
+    }
     const int threads = B.n_s / 4 >= 256 ? 256 : (B.n_s / 4 < 64 ? 64 : B.n_s / 4);
     dim3 grid(B.n_work, n_tmpl), block(threads);
     const size_t lds = 2 * (size_t)B.n_s * (fp64 ? sizeof(double2) : sizeof(float2));
@@ -349,6 +984,19 @@ hipError_t launch_spectra(const BandDev &B, int n_tmpl, bool fp64, const void *y
         hipLaunchKernelGGL(k_spectra<double>, grid, block, lds, stream, B, (const double2 *)y, (double2 *)F);
     else
         hipLaunchKernelGGL(k_spectra<float>, grid, block, lds, stream, B, (const float2 *)y, (float2 *)F);
+    return hipGetLastError();
+}
+
+bool spectra_pairs_ok(const BandDev &B, bool fp64, size_t limit) {
+    return !fp64 && B.n_s == 256 && B.bins_unique && spair_layout(B.Q, B.n_f, B.R).total <= limit;
+}
+
+hipError_t launch_spectra_pairs(const BandDev &B, int n_tmpl, const void *y, double *part, int k_chunk,
+                                int n_chunks, hipStream_t stream) {
+    if (n_tmpl == 0) return hipSuccess;
+    dim3 grid(n_chunks, n_tmpl), block(128);
+    const size_t lds = spair_layout(B.Q, B.n_f, B.R).total;
+    hipLaunchKernelGGL(k_spectra_pairs16, grid, block, lds, stream, B, (const float2 *)y, part, k_chunk, n_chunks);
     return hipGetLastError();
 }
 
@@ -360,6 +1008,39 @@ hipError_t launch_pairsum(const BandDev &B, int n_tmpl, bool fp64, const void *F
         hipLaunchKernelGGL(k_pairs<double>, grid, block, 0, stream, B, (const double2 *)F, part, k_chunk, n_chunks);
     else
         hipLaunchKernelGGL(k_pairs<float>, grid, block, 0, stream, B, (const float2 *)F, part, k_chunk, n_chunks);
+    return hipGetLastError();
+}
+
+// Segments per step: the largest of 4, 2, 1 whose LDS footprint fits in `limit` bytes
+// (0 if even one segment per step does not fit).
+int fused_steps(const BandDev &B, bool fp64, size_t limit) {
+    const size_t cs = fp64 ? sizeof(double2) : sizeof(float2);
+    for (int S = 4; S >= 1; S /= 2)
+        if (Q_ok(B) && fused_layout(B.Q, B.n_s, B.n_k, B.n_f, B.R, B.D, B.dt, cs, S).total <= limit) return S;
+    return 0;
+}
+
+size_t fused_lds_bytes(const BandDev &B, bool fp64, int S) {
+    return fused_layout(B.Q, B.n_s, B.n_k, B.n_f, B.R, B.D, B.dt, fp64 ? sizeof(double2) : sizeof(float2), S).total;
+}
+
+hipError_t launch_fused(const BandDev &B, const double *coef, int n_tmpl, bool fp64, double *part,
+                        int k_chunk, int n_chunks, int S, hipStream_t stream) {
+    if (n_tmpl == 0) return hipSuccess;
+    if (S < 1 || !Q_ok(B)) return hipErrorInvalidValue;
+    dim3 grid(n_chunks, n_tmpl), block(256);
+    const size_t lds = fused_lds_bytes(B, fp64, S);
+    if (fp64) {
+        if (B.D == 8)
+            hipLaunchKernelGGL((k_fused<double, 8>), grid, block, lds, stream, B, coef, B.seg_work, part, k_chunk, n_chunks, S);
+        else
+            hipLaunchKernelGGL((k_fused<double, 0>), grid, block, lds, stream, B, coef, B.seg_work, part, k_chunk, n_chunks, S);
+    } else {
+        if (B.D == 8)
+            hipLaunchKernelGGL((k_fused<float, 8>), grid, block, lds, stream, B, coef, B.seg_work, part, k_chunk, n_chunks, S);
+        else
+            hipLaunchKernelGGL((k_fused<float, 0>), grid, block, lds, stream, B, coef, B.seg_work, part, k_chunk, n_chunks, S);
+    }
     return hipGetLastError();
 }
 

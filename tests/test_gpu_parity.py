@@ -54,17 +54,18 @@ SMALL_CASES = {
 }
 
 
+@pytest.mark.parametrize("fused", [0, 1])
 @pytest.mark.parametrize("case", sorted(SMALL_CASES))
-def test_rho_small_cases(ccr, case):
+def test_rho_small_cases(ccr, case, fused):
     kw = SMALL_CASES[case]
     cfg = small_config(**kw, injections=[dict(f0=50.21, a_p=1.25, t_asc_off=0.0, period=68023.7, h0=0.35,
                                               cosi=0.5, psi=0.3, phi0=1.0)])
     ds = synth.make_dataset(cfg, sigma_wander=0.2)
     tm = ds.templates
     ref = oracle.Oracle(ds).rho(tm)
-    r64, r32 = run_both(ccr, ds, tm)
+    r64, r32 = run_both(ccr, ds, tm, fused=fused, k_chunk=5)
     e64, e32 = rho_err(r64, ref), rho_err(r32, ref)
-    print(f"{case}: fp64 {e64:.2e} split {e32:.2e} max|rho| {np.abs(ref).max():.2f}")
+    print(f"{case} fused={fused}: fp64 {e64:.2e} split {e32:.2e} max|rho| {np.abs(ref).max():.2f}")
     assert e64 < TOL64
     assert e32 < TOL32
 
@@ -124,6 +125,17 @@ def test_batching_and_determinism(ccr):
     assert np.max(np.abs(a - c)) < 1e-12 * max(1.0, np.abs(a).max())
     d, _ = run_both(ccr, ds, ds.templates)
     assert np.array_equal(b, d)
+
+
+def test_fused_matches_staged(ccr):
+    """The fused kernel (spectra kept in an LDS ring, halo of R segments recomputed at chunk
+    starts) reproduces the staged kernels' FP64 rho for any chunking."""
+    ds = synth.make_dataset(small_config(q=3, n_seg=30, max_lag=3, gap_fraction=0.2, pairs=3))
+    staged, s32 = run_both(ccr, ds, ds.templates, fused=0, k_chunk=256)
+    for kc in (1, 4, 7, 256):
+        f64, f32 = run_both(ccr, ds, ds.templates, fused=1, k_chunk=kc)
+        assert np.max(np.abs(f64 - staged)) < 1e-13 * max(1.0, np.abs(staged).max()), kc
+        assert np.max(np.abs(f32 - s32)) < 1e-5 * max(1.0, np.abs(s32).max()), kc
 
 
 def test_device_output_and_stream(ccr):
