@@ -403,10 +403,14 @@ __device__ __forceinline__ void fft256_lanes(c2<T> *v, int t, c2<T> *sc, const c
                                              bool on) {
     if (on) {
         dft16<T>(v);
+        // W256^(t k1) by recurrence from W256^t (FP32 rounding grows to ~1e-6 by k1 = 15)
+        const c2<T> w1 = tw[t * tw_stride];
+        c2<T> wk = w1;
 #pragma unroll
         for (int k1 = 1; k1 < 16; ++k1) {
             const int pos = 4 * (k1 & 3) + (k1 >> 2);
-            v[pos] = cmul<T>(v[pos], tw[t * k1 * tw_stride]);
+            v[pos] = cmul<T>(v[pos], wk);
+            wk = cmul<T>(wk, w1);
         }
 #pragma unroll
         for (int k1 = 0; k1 < 16; ++k1) sc[k1 * 17 + t] = v[4 * (k1 & 3) + (k1 >> 2)];
@@ -471,26 +475,32 @@ k_spectra16(BandDev B, const c2<T> *y, c2<T> *F) {
 // bin's pair sum for the step's segments in the same order as k_pairs.  The segment spectra
 // never leave LDS; one partial per (template, chunk, bin) is written.
 struct SpairLayout {
-    int S, slots;
-    size_t off_acc, off_ring, off_flag, total;
+    int S, slots, cand;
+    size_t off_acc, off_ring, off_list, off_flag, total;
 };
 
+// cand = candidate pairs per step: S segments x Q detectors x (R+1) partner segments x Q.
 __host__ __device__ inline SpairLayout spair_layout(int Q, int n_f, int R) {
     SpairLayout L;
     L.S = 8 / Q < 1 ? 1 : 8 / Q;
     L.slots = R + L.S;
+    L.cand = L.S * Q * (R + 1) * Q;
     size_t o = 8 * 16 * 17 * sizeof(float2);  // transpose scratch
     L.off_acc = o;
     o += (size_t)n_f * 8;
+    o = (o + 15) & ~(size_t)15;
     L.off_ring = o;
     o += (size_t)L.slots * Q * n_f * sizeof(float2);
+    o = (o + 15) & ~(size_t)15;
+    L.off_list = o;
+    o += (size_t)(L.cand + 1) * 16;  // (ring offset 1, ring offset 2, weight, pad) + count
     L.off_flag = o;
     o += (size_t)L.slots * Q;
     L.total = (o + 15) & ~(size_t)15;
     return L;
 }
 
-__global__ void __launch_bounds__(128) __attribute__((amdgpu_waves_per_eu(3)))
+__global__ void __launch_bounds__(128) __attribute__((amdgpu_waves_per_eu(2)))
 k_spectra_pairs16(BandDev B, const float2 *y, double *part, int k_chunk, int n_chunks) {
     extern __shared__ __align__(16) unsigned char smem[];
     const int Q = B.Q, n_f = B.n_f, n_k = B.n_k;
@@ -519,6 +529,17 @@ k_spectra_pairs16(BandDev B, const float2 *y, double *part, int k_chunk, int n_c
     __syncthreads();
 
     int slot_b = Kh % slots;  // ring slot of segment Kb
+    float2 yn[16];
+    {
+        const int Kf = Kh + sd;
+        const bool fst = Kf < K1 && B.seg_work[X * B.n_seg + Kf] >= 0;
+        const float2 *ysf = ybase + (size_t)Kf * n_k;
+#pragma unroll
+        for (int n1 = 0; n1 < 16; ++n1) {
+            const int sidx = 16 * n1 + t;
+            yn[n1] = (fst && sidx < n_k) ? ysf[sidx] : make_float2(0.f, 0.f);
+        }
+    }
     for (int Kb = Kh; Kb < K1; Kb += S) {
         const int ns = min(S, K1 - Kb);
         const int K = Kb + sd;
@@ -527,17 +548,37 @@ k_spectra_pairs16(BandDev B, const float2 *y, double *part, int k_chunk, int n_c
         int myslot = slot_b + sd;
         if (myslot >= slots) myslot -= slots;
         if (mine && t == 0) flag[myslot * Q + X] = on ? 1 : 0;
-        const float2 *ys = ybase + (size_t)K * n_k;
+        // this step's samples (prefetched during the previous step) and the next step's
+        float2 yv[16];
+#pragma unroll
+        for (int n1 = 0; n1 < 16; ++n1) yv[n1] = on ? yn[n1] : make_float2(0.f, 0.f);
+        {
+            const int Kn = K + S;
+            const bool nxt = Kn < K1 && B.seg_work[X * B.n_seg + Kn] >= 0;
+            const float2 *ysn = ybase + (size_t)Kn * n_k;
+#pragma unroll
+            for (int n1 = 0; n1 < 16; ++n1) {
+                const int sidx = 16 * n1 + t;
+                yn[n1] = (nxt && sidx < n_k) ? ysn[sidx] : make_float2(0.f, 0.f);
+            }
+        }
         const int rb_mod = on ? mod_fft(B, (int64_t)K * n_k) : 0;
         const float scale = on ? (float)B.segw[X * B.n_seg + K].scale : 0.f;
         float2 *Fo = ring + ((size_t)myslot * Q + X) * n_f;
         for (int p = 0; p < B.P; ++p) {
             float2 v[16];
+            if (p == 0) {
 #pragma unroll
-            for (int n1 = 0; n1 < 16; ++n1) {
-                const int sidx = 16 * n1 + t;
-                float2 x = (on && sidx < n_k) ? ys[sidx] : make_float2(0.f, 0.f);
-                v[n1] = p ? cmul<float>(x, tw[p * sidx]) : x;
+                for (int n1 = 0; n1 < 16; ++n1) v[n1] = yv[n1];
+            } else {
+                // exp(-2 pi i p (16 n1 + t) / N_FFT) by recurrence over n1
+                const float2 step = tw[16 * p];
+                float2 wv = tw[p * t];
+#pragma unroll
+                for (int n1 = 0; n1 < 16; ++n1) {
+                    v[n1] = cmul<float>(yv[n1], wv);
+                    wv = cmul<float>(wv, step);
+                }
             }
             fft256_lanes<float>(v, t, sc, tw, tws, on);
             if (on) {
@@ -552,39 +593,61 @@ k_spectra_pairs16(BandDev B, const float2 *y, double *part, int k_chunk, int n_c
             }
         }
         __syncthreads();
-        for (int i = tid; i < n_f; i += 128) {
-            double a = acc[i];
-            for (int s2 = 0; s2 < ns; ++s2) {
-                const int Kc = Kb + s2;
-                if (Kc < K0) continue;
-                int slot = slot_b + s2;
-                if (slot >= slots) slot -= slots;
-                const int Lmin = max(0, Kc - B.R);
-                for (int Xc = 0; Xc < Q; ++Xc) {
-                    if (!flag[slot * Q + Xc]) continue;
-                    float2 ga = make_float2(0.f, 0.f), gb = make_float2(0.f, 0.f);
-                    int sl = slot - (Kc - Lmin);
-                    if (sl < 0) sl += slots;
-                    for (int L = Lmin; L <= Kc; ++L) {
-                        for (int Y = 0; Y < Q; ++Y) {
-                            const bool inc = (L < Kc) ? ((Y != Xc) ? cross : same) : (cross && Y > Xc);
-                            if (!inc || !flag[sl * Q + Y]) continue;
-                            const float2 g = ring[((size_t)sl * Q + Y) * n_f + i];
-                            const SegWeight &w = B.segw[Y * B.n_seg + L];
-                            const float wa = (float)w.ahat, wb = (float)w.bhat;
-                            ga.x += wa * g.x; ga.y += wa * g.y;
-                            gb.x += wb * g.x; gb.y += wb * g.y;
+        // pair list of the step (the first wave compacts the candidates with a ballot):
+        // segment Kc of the step with detector Xc, partner (Y, L = Kc - dl): L < Kc any detector
+        // allowed by the pair kinds, L = Kc only Y > Xc across detectors; both spectra present.
+        if (tid < 64) {
+            int base = 0;
+            for (int c0 = 0; c0 < Ly.cand; c0 += 64) {
+                const int cd = c0 + tid;
+                bool valid = false;
+                int o1 = 0, o2 = 0;
+                float W = 0.f;
+                if (cd < Ly.cand) {
+                    const int Y = cd % Q;
+                    const int dl = (cd / Q) % (B.R + 1);
+                    const int Xc = (cd / (Q * (B.R + 1))) % Q;
+                    const int s2 = cd / (Q * (B.R + 1) * Q);
+                    const int Kc = Kb + s2, L = Kc - dl;
+                    if (s2 < ns && Kc >= K0 && L >= 0) {
+                        int slot = slot_b + s2;
+                        if (slot >= slots) slot -= slots;
+                        int sl = slot - dl;
+                        if (sl < 0) sl += slots;
+                        const bool inc = (dl > 0) ? ((Y != Xc) ? cross : same) : (cross && Y > Xc);
+                        if (inc && flag[slot * Q + Xc] && flag[sl * Q + Y]) {
+                            valid = true;
+                            const SegWeight &wk = B.segw[Xc * B.n_seg + Kc];
+                            const SegWeight &wl = B.segw[Y * B.n_seg + L];
+                            W = (float)(wk.ahat * wl.ahat + wk.bhat * wl.bhat);
+                            o1 = (slot * Q + Xc) * n_f;
+                            o2 = (sl * Q + Y) * n_f;
                         }
-                        if (++sl == slots) sl = 0;
                     }
-                    const float2 f = ring[((size_t)slot * Q + Xc) * n_f + i];
-                    const SegWeight &wk = B.segw[Xc * B.n_seg + Kc];
-                    const float aK = (float)wk.ahat, bK = (float)wk.bhat;
-                    const float hx = aK * ga.x + bK * gb.x, hy = aK * ga.y + bK * gb.y;
-                    a += (double)(f.x * hx + f.y * hy);
                 }
+                const uint64_t m = __ballot(valid);
+                if (valid) {
+                    const int pos = base + __popcll(m & ((1ull << tid) - 1ull));
+                    int4 *ent = reinterpret_cast<int4 *>(smem + Ly.off_list) + 1 + pos;
+                    *ent = make_int4(o1, o2, __float_as_int(W), 0);
+                }
+                base += __popcll(m);
             }
-            acc[i] = a;
+            if (tid == 0) reinterpret_cast<int4 *>(smem + Ly.off_list)[0] = make_int4(base, 0, 0, 0);
+        }
+        __syncthreads();
+        {
+            const int4 *lst = reinterpret_cast<const int4 *>(smem + Ly.off_list);
+            const int ne = lst[0].x;
+            for (int i = tid; i < n_f; i += 128) {
+                float st = 0.f;
+                for (int e = 0; e < ne; ++e) {
+                    const int4 en = lst[1 + e];
+                    const float2 f1 = ring[en.x + i], f2 = ring[en.y + i];
+                    st = fma(__int_as_float(en.z), f1.x * f2.x + f1.y * f2.y, st);
+                }
+                acc[i] += (double)st;
+            }
         }
         __syncthreads();
         slot_b += S;
