@@ -205,12 +205,37 @@ __device__ __forceinline__ T tap_weight(const T *wt, int D, T inv_d1, T dc, T s,
 
 // sum_{n=-D}^{D} w sinc(delta_c - n) x'_{j*+n}; taps outside [0, n) read zero.  DT > 0 fixes D
 // at compile time (unrolled taps).  The bounds checks are taken only near the data edges.
+// Fast form for the tap-indexed window (WIN 0) with every tap inside the data: the common
+// factor sin(pi dc) / pi leaves the sum, y = s sum_n (-1)^n w_n x'_{j*+n} / (dc - n), and an
+// on-grid sample (dc = 0) is x'_{j*} exactly (w_0 = 1).
+template <typename T, int DT>
+__device__ __forceinline__ c2<T> interpolate_w0_inside(const BandDev &B, const float2 *xc, T dc) {
+    const T *wt = win_table<T>(B);
+    if (dc == (T)0) {
+        const float2 x0 = xc[0];
+        return mk<T>((T)x0.x, (T)x0.y);
+    }
+    const T s = sin_pi<T>(dc) * (T)0.318309886183790671537767526745;
+    T re = 0, im = 0;
+#pragma unroll
+    for (int n = -DT; n <= DT; ++n) {
+        const T q = ((n & 1) ? -wt[n + DT] : wt[n + DT]) * recip<T>(dc - (T)n);
+        const float2 xv = xc[n];
+        re = fma(q, (T)xv.x, re);
+        im = fma(q, (T)xv.y, im);
+    }
+    return mk<T>(re * s, im * s);
+}
+
 template <typename T, int DT, int WIN>
 __device__ __forceinline__ c2<T> interpolate(const BandDev &B, const float2 *xd, int64_t jstar, double dcd) {
     const T dc = (T)dcd;
+    const int D = DT > 0 ? DT : B.D;
+    if constexpr (WIN == 0 && DT > 0) {
+        if (jstar - D >= 0 && jstar + D < B.n) return interpolate_w0_inside<T, DT>(B, xd + jstar, dc);
+    }
     const T s = sin_pi<T>(dc) * (T)0.318309886183790671537767526745;
     const T *wt = win_table<T>(B);
-    const int D = DT > 0 ? DT : B.D;
     const T inv_d1 = (T)1 / (T)(D + 1);
     T re = 0, im = 0;
     if (jstar - D >= 0 && jstar + D < B.n) {
@@ -273,36 +298,39 @@ __device__ __forceinline__ c2<T> interpolate_window(const BandDev &B, const floa
     return mk<T>(re, im);
 }
 
-// Resampler: one 64-thread workgroup per (template, active segment, 64 samples); the segment's
-// Chebyshev coefficients and anchor are uniform over the workgroup (scalar loads).
+// Resampler: one 64-thread workgroup per (template, active segment), looping over the segment's
+// samples; the segment's Chebyshev coefficients and anchor are uniform (scalar loads).
 template <typename T, int DT, int WIN>
-__global__ void __launch_bounds__(64) k_resample(BandDev B, const double *coef, c2<T> *y, int cps) {
-    const int w = blockIdx.x / cps;
-    const int s = (blockIdx.x - w * cps) * 64 + threadIdx.x;
+__global__ void __launch_bounds__(64) k_resample(BandDev B, const double *coef, c2<T> *y) {
+    const int w = blockIdx.x;
     const int tb = blockIdx.y;
     const int entry = B.work[w];
     const int det = entry / B.n_seg;
     const int K = entry - det * B.n_seg;
-    if (s >= B.n_k) return;
     const int64_t nr = (int64_t)B.n_seg * B.n_k;
-    const int64_t r = (int64_t)K * B.n_k + s;
-    c2<T> *yo = y + ((size_t)tb * B.Q + det) * nr;
-    if (!B.mask[(size_t)det * nr + r]) {
-        yo[r] = mk<T>((T)0, (T)0);
-        return;
-    }
+    c2<T> *yo = y + ((size_t)tb * B.Q + det) * nr + (size_t)K * B.n_k;
+    const uint8_t *mk_ = B.mask + (size_t)det * nr + (size_t)K * B.n_k;
+    const float2 *xd = B.x + (size_t)det * B.n;
     const double *cf = coef + ((size_t)tb * B.n_work + w) * kCheb;
     double cl[kCheb];
 #pragma unroll
     for (int k = 0; k < kCheb; ++k) cl[k] = cf[k];
     const Anchor an = B.anchors[entry];
-    int64_t jstar;
-    double dc, psi;
-    sample_time(cl, (double)(2 * s - B.n_k) * (1.0 / (double)B.n_k), an, B.inv_dt, B.f_het, r, jstar, dc, psi);
-    const c2<T> acc = interpolate<T, DT, WIN>(B, B.x + (size_t)det * B.n, jstar, dc);
-    T c, sn;
-    sincos_rev<T>(psi, sn, c);
-    yo[r] = mk<T>(c * acc.x - sn * acc.y, sn * acc.x + c * acc.y);
+    const double inv_nk = 1.0 / (double)B.n_k;
+    const int64_t r0 = (int64_t)K * B.n_k;
+    for (int s = threadIdx.x; s < B.n_k; s += 64) {
+        if (!mk_[s]) {
+            yo[s] = mk<T>((T)0, (T)0);
+            continue;
+        }
+        int64_t jstar;
+        double dc, psi;
+        sample_time(cl, (double)(2 * s - B.n_k) * inv_nk, an, B.inv_dt, B.f_het, r0 + s, jstar, dc, psi);
+        const c2<T> acc = interpolate<T, DT, WIN>(B, xd, jstar, dc);
+        T c, sn;
+        sincos_rev<T>(psi, sn, c);
+        yo[s] = mk<T>(c * acc.x - sn * acc.y, sn * acc.x + c * acc.y);
+    }
 }
 
 // v mod N_FFT for 0 <= v (a mask when N_FFT is a power of two).
@@ -398,14 +426,17 @@ __device__ __forceinline__ void dft16(c2<T> *v) {
 // W256^(t k1) from the N_FFT-entry table (stride N_FFT / 256), transpose through `sc`
 // (16 x 17 padded), 16-point DFTs over n2.  On return lane t holds X[t + 16 k2] in
 // v[4 (k2 % 4) + k2 / 4].  Every thread of the block calls it (it holds one barrier).
+// `pre` (applied when `has_pre`) multiplies every stage-1 output of the lane: the per-lane part
+// of a residue-class input twiddle, folded into the W256 twiddles.
 template <typename T>
 __device__ __forceinline__ void fft256_lanes(c2<T> *v, int t, c2<T> *sc, const c2<T> *tw, int tw_stride,
-                                             bool on) {
+                                             bool on, bool has_pre = false, c2<T> pre = c2<T>{}) {
     if (on) {
         dft16<T>(v);
-        // W256^(t k1) by recurrence from W256^t (FP32 rounding grows to ~1e-6 by k1 = 15)
+        // pre * W256^(t k1) by recurrence from W256^t (FP32 rounding grows to ~1e-6 by k1 = 15)
         const c2<T> w1 = tw[t * tw_stride];
-        c2<T> wk = w1;
+        c2<T> wk = has_pre ? cmul<T>(pre, w1) : w1;
+        if (has_pre) v[0] = cmul<T>(v[0], pre);
 #pragma unroll
         for (int k1 = 1; k1 < 16; ++k1) {
             const int pos = 4 * (k1 & 3) + (k1 >> 2);
@@ -476,7 +507,7 @@ k_spectra16(BandDev B, const c2<T> *y, c2<T> *F) {
 // never leave LDS; one partial per (template, chunk, bin) is written.
 struct SpairLayout {
     int S, slots, cand;
-    size_t off_acc, off_ring, off_list, off_flag, total;
+    size_t off_acc, off_ring, off_list, off_meta, off_flag, total;
 };
 
 // cand = candidate pairs per step: S segments x Q detectors x (R+1) partner segments x Q.
@@ -490,10 +521,12 @@ __host__ __device__ inline SpairLayout spair_layout(int Q, int n_f, int R) {
     o += (size_t)n_f * 8;
     o = (o + 15) & ~(size_t)15;
     L.off_ring = o;
-    o += (size_t)L.slots * Q * n_f * sizeof(float2);
+    o += (size_t)L.slots * Q * (n_f + 1) * sizeof(float2);
     o = (o + 15) & ~(size_t)15;
     L.off_list = o;
     o += (size_t)(L.cand + 1) * 16;  // (ring offset 1, ring offset 2, weight, pad) + count
+    L.off_meta = o;
+    o += (size_t)L.slots * Q * 16;   // (hat a, hat b) of the spectrum in each ring slot
     L.off_flag = o;
     o += (size_t)L.slots * Q;
     L.total = (o + 15) & ~(size_t)15;
@@ -522,73 +555,67 @@ k_spectra_pairs16(BandDev B, const float2 *y, double *part, int k_chunk, int n_c
     const bool cross = (B.pairs & 1) != 0, same = (B.pairs & 2) != 0;
     float2 *sc = sc_all + grp * 16 * 17;
     const int sd = grp / Q, X = grp - sd * Q;  // this group's (segment in step, detector)
+    const int n_f1 = n_f + 1;                    // ring rows hold a dummy entry for unused outputs
     const float2 *ybase = y + ((size_t)tb * Q + X) * nr;
 
     for (int i = tid; i < n_f; i += 128) acc[i] = 0.0;
     for (int i = tid; i < slots * Q; i += 128) flag[i] = 0;
     __syncthreads();
 
+    double2 *meta = reinterpret_cast<double2 *>(smem + Ly.off_meta);
     int slot_b = Kh % slots;  // ring slot of segment Kb
+    // the next segment of this group: activity, weights and samples, loaded one step ahead
     float2 yn[16];
-    {
-        const int Kf = Kh + sd;
-        const bool fst = Kf < K1 && B.seg_work[X * B.n_seg + Kf] >= 0;
-        const float2 *ysf = ybase + (size_t)Kf * n_k;
+    bool on_n;
+    SegWeight sw_n;
+    auto prefetch = [&](int Kn) {
+        const bool in = Kn < K1;
+        on_n = in && B.seg_work[X * B.n_seg + Kn] >= 0;
+        sw_n = in ? B.segw[X * B.n_seg + Kn] : SegWeight{0.0, 0.0, 0.0};
+        const float2 *ysn = ybase + (size_t)(in ? Kn : 0) * n_k;
 #pragma unroll
         for (int n1 = 0; n1 < 16; ++n1) {
             const int sidx = 16 * n1 + t;
-            yn[n1] = (fst && sidx < n_k) ? ysf[sidx] : make_float2(0.f, 0.f);
+            yn[n1] = (in && sidx < n_k) ? ysn[sidx] : make_float2(0.f, 0.f);
         }
-    }
+    };
+    prefetch(Kh + sd);
     for (int Kb = Kh; Kb < K1; Kb += S) {
         const int ns = min(S, K1 - Kb);
         const int K = Kb + sd;
         const bool mine = sd < ns;
-        const bool on = mine && B.seg_work[X * B.n_seg + K] >= 0;
+        const bool on = mine && on_n;
+        const SegWeight sw = sw_n;
         int myslot = slot_b + sd;
         if (myslot >= slots) myslot -= slots;
-        if (mine && t == 0) flag[myslot * Q + X] = on ? 1 : 0;
-        // this step's samples (prefetched during the previous step) and the next step's
+        if (mine && t == 0) {
+            flag[myslot * Q + X] = on ? 1 : 0;
+            meta[myslot * Q + X] = make_double2(sw.ahat, sw.bhat);
+        }
         float2 yv[16];
 #pragma unroll
         for (int n1 = 0; n1 < 16; ++n1) yv[n1] = on ? yn[n1] : make_float2(0.f, 0.f);
-        {
-            const int Kn = K + S;
-            const bool nxt = Kn < K1 && B.seg_work[X * B.n_seg + Kn] >= 0;
-            const float2 *ysn = ybase + (size_t)Kn * n_k;
-#pragma unroll
-            for (int n1 = 0; n1 < 16; ++n1) {
-                const int sidx = 16 * n1 + t;
-                yn[n1] = (nxt && sidx < n_k) ? ysn[sidx] : make_float2(0.f, 0.f);
-            }
-        }
+        prefetch(K + S);
         const int rb_mod = on ? mod_fft(B, (int64_t)K * n_k) : 0;
-        const float scale = on ? (float)B.segw[X * B.n_seg + K].scale : 0.f;
-        float2 *Fo = ring + ((size_t)myslot * Q + X) * n_f;
+        const float scale = on ? (float)sw.scale : 0.f;
+        float2 *Fo = ring + ((size_t)myslot * Q + X) * n_f1;
         for (int p = 0; p < B.P; ++p) {
+            // residue class p: x_p[16 n1 + t] = y[16 n1 + t] W^(16 p n1) W^(p t), W = exp(-2 pi i / N);
+            // W^(16 p n1) is uniform over lanes, W^(p t) folds into the stage-1 twiddles
             float2 v[16];
-            if (p == 0) {
 #pragma unroll
-                for (int n1 = 0; n1 < 16; ++n1) v[n1] = yv[n1];
-            } else {
-                // exp(-2 pi i p (16 n1 + t) / N_FFT) by recurrence over n1
-                const float2 step = tw[16 * p];
-                float2 wv = tw[p * t];
-#pragma unroll
-                for (int n1 = 0; n1 < 16; ++n1) {
-                    v[n1] = cmul<float>(yv[n1], wv);
-                    wv = cmul<float>(wv, step);
-                }
-            }
-            fft256_lanes<float>(v, t, sc, tw, tws, on);
+            for (int n1 = 0; n1 < 16; ++n1) v[n1] = p ? cmul<float>(yv[n1], tw[mod_fft(B, (int64_t)16 * p * n1)]) : yv[n1];
+            fft256_lanes<float>(v, t, sc, tw, tws, on, p != 0, tw[p * t]);
             if (on) {
+                // Phi_in and the normalisation: scale exp(-2 pi i kbar r_B / N) with
+                // kbar = (t + 16 k2) P + p, by recurrence over k2
+                float2 wo = cscale<float>(tw[mod_fft(B, (int64_t)(t * B.P + p) * rb_mod)], scale);
+                const float2 wst = tw[mod_fft(B, (int64_t)16 * B.P * rb_mod)];
 #pragma unroll
                 for (int k2 = 0; k2 < 16; ++k2) {
-                    const int kb = (t + 16 * k2) * B.P + p;
-                    const int i = B.bin_pos[kb];
-                    if (i < 0) continue;
-                    const int ph = mod_fft(B, (int64_t)kb * rb_mod);
-                    Fo[i] = cscale<float>(cmul<float>(v[4 * (k2 & 3) + (k2 >> 2)], tw[ph]), scale);
+                    const int i = B.bin_pos[(t + 16 * k2) * B.P + p];
+                    Fo[i >= 0 ? i : n_f] = cmul<float>(v[4 * (k2 & 3) + (k2 >> 2)], wo);
+                    wo = cmul<float>(wo, wst);
                 }
             }
         }
@@ -617,11 +644,10 @@ k_spectra_pairs16(BandDev B, const float2 *y, double *part, int k_chunk, int n_c
                         const bool inc = (dl > 0) ? ((Y != Xc) ? cross : same) : (cross && Y > Xc);
                         if (inc && flag[slot * Q + Xc] && flag[sl * Q + Y]) {
                             valid = true;
-                            const SegWeight &wk = B.segw[Xc * B.n_seg + Kc];
-                            const SegWeight &wl = B.segw[Y * B.n_seg + L];
-                            W = (float)(wk.ahat * wl.ahat + wk.bhat * wl.bhat);
-                            o1 = (slot * Q + Xc) * n_f;
-                            o2 = (sl * Q + Y) * n_f;
+                            const double2 wk = meta[slot * Q + Xc], wl = meta[sl * Q + Y];
+                            W = (float)(wk.x * wl.x + wk.y * wl.y);
+                            o1 = (slot * Q + Xc) * n_f1;
+                            o2 = (sl * Q + Y) * n_f1;
                         }
                     }
                 }
@@ -1011,12 +1037,11 @@ hipError_t launch_timebase(const BandDev &B, const double *d_tmpl, int n_tmpl, d
 
 template <typename T, int DT>
 static void launch_resample_t(const BandDev &B, const double *coef, int n_tmpl, void *y, hipStream_t stream) {
-    const int cps = (B.n_k + 63) / 64;
-    dim3 grid((unsigned)((int64_t)B.n_work * cps), n_tmpl), block(64);
+    dim3 grid((unsigned)B.n_work, n_tmpl), block(64);
     if (B.window == 0)
-        hipLaunchKernelGGL((k_resample<T, DT, 0>), grid, block, 0, stream, B, coef, (c2<T> *)y, cps);
+        hipLaunchKernelGGL((k_resample<T, DT, 0>), grid, block, 0, stream, B, coef, (c2<T> *)y);
     else
-        hipLaunchKernelGGL((k_resample<T, DT, 1>), grid, block, 0, stream, B, coef, (c2<T> *)y, cps);
+        hipLaunchKernelGGL((k_resample<T, DT, 1>), grid, block, 0, stream, B, coef, (c2<T> *)y);
 }
 
 hipError_t launch_resample(const BandDev &B, const double *coef, int n_tmpl, bool fp64, void *y,

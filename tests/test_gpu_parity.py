@@ -103,6 +103,23 @@ def test_segment_spectra_parity(ccr):
             assert np.abs(F32 - F_ref)[used].max() < 1e-5 * scale
 
 
+def test_segment_spectra_256_point(ccr):
+    """Segment spectra through the 16-lane register FFT (256-point segments, split precision)
+    and the LDS Stockham FFT (FP64) against the oracle's direct DFT."""
+    ds = synth.make_dataset(synth.config("tiny", t_obs=30 * 360.0))
+    o = oracle.Oracle(ds)
+    with ccr.Context(ds.sky, device=0) as ctx:
+        bid = ctx.load(ds)
+        assert ctx.band_info(bid)["n_k"] > 128
+        for t in (0, 9):
+            F_ref = o.spectra(ds.templates[t])
+            F64 = ctx.segment_spectra(bid, t, prec=ccr.PREC_FP64)
+            F32 = ctx.segment_spectra(bid, t, prec=ccr.PREC_SPLIT)
+            scale = np.abs(F_ref).max()
+            assert np.abs(F64 - F_ref).max() < 1e-11 * scale
+            assert np.abs(F32 - F_ref).max() < 1e-5 * scale
+
+
 def test_tiny_workload_full(ccr):
     """2 detectors, 2 days, T_short 360 s, 0.25 Hz at 100 Hz, 64 templates, same-time pairs."""
     ds = synth.make_dataset(synth.config("tiny"))
