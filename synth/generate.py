@@ -5,7 +5,7 @@ from dataclasses import dataclass, field
 
 import numpy as np
 
-from .model import SITES, antenna_ab, default_sky, forward_delay, samples_per_segment
+from .model import SITES, antenna_ab, default_sky, earth_roemer, forward_delay, samples_per_segment
 
 
 @dataclass
@@ -154,8 +154,9 @@ def make_dataset(cfg, seed=None, signal=True, noise=True, sky=None, antenna_piec
                 tj = t0 + np.arange(lo, hi, dtype=np.float64) * dt
                 if not antenna_piecewise:
                     at, bt = antenna_ab(tj, s, skyd)
+                ej = earth_roemer(tj, s, skyd)
                 for inj in injections:
-                    d = forward_delay(tj, s, skyd, inj["a_p"], inj["t_asc"], inj["period"])
+                    d = forward_delay(tj, s, skyd, inj["a_p"], inj["t_asc"], inj["period"], e=ej)
                     if antenna_piecewise:
                         # hold a, b at the value of the source-frame segment the sample lands in
                         kidx = np.clip(np.floor((tj + d - t0) / t_short).astype(np.int64), 0, n_seg - 1)

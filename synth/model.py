@@ -88,9 +88,11 @@ def earth_roemer(t, s, sky):
     return n[0] * r[0] + n[1] * r[1] + n[2] * r[2]
 
 
-def forward_delay(t, s, sky, a_p, t_asc, period):
-    """tau(t) - t for detector time t (forward map, explicit, no solve)."""
-    e = earth_roemer(t, s, sky)
+def forward_delay(t, s, sky, a_p, t_asc, period, e=None):
+    """tau(t) - t for detector time t (forward map, explicit, no solve).  ``e`` may pass in
+    earth_roemer(t, s, sky) when it is already at hand (several injections on one lattice)."""
+    if e is None:
+        e = earth_roemer(t, s, sky)
     t_ssb_minus_t = e
     omega = 2.0 * math.pi / period
     # Omega (t_SSB - T_asc) evaluated as Omega (t - T_asc) + Omega e; t is at
