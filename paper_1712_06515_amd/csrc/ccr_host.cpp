@@ -485,6 +485,9 @@ ccr_status prepare_templates(ccr_ctx *c, Band &B) {
         const double Om = 2.0 * kPi / P;
         if (Om * (ld + 2.0 * ap + 2.0) > 0.3)
             return fail(c, CCR_ERANGE, "template %lld: orbit too short for the segment length", (long long)t);
+        // the kernels hold the sample shift of a delay (Earth + binary) in 32 bits
+        if ((c->sky.au_s + c->sky.re_s + ap + 1.0) / (double)dt > (double)(1 << 30))
+            return fail(c, CCR_ERANGE, "template %lld: delay too long for the sampling interval", (long long)t);
     }
     {
         EarthModel m = earth_model(c->sky, B.det[0].site);

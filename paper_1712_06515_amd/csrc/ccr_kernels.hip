@@ -120,7 +120,7 @@ __device__ __forceinline__ void sample_time(const double *coef, double x, const 
     const double eta = fma(x, b1, coef[0] - b2);
     const double q = (eta - an.D_a) * inv_dt;
     const double k = floor(q + 0.5);
-    jstar = r + (int64_t)k;
+    jstar = r + (int64_t)(int)k;  // |delay| / dt < 2^31 (the host bounds dt and the delay)
     dc = q - k;
     const double ps = fma(f_het, eta, an.psi_a);
     psi = ps - floor(ps);
@@ -208,9 +208,9 @@ __device__ __forceinline__ T tap_weight(const T *wt, int D, T inv_d1, T dc, T s,
 // Fast form for the tap-indexed window (WIN 0) with every tap inside the data: the common
 // factor sin(pi dc) / pi leaves the sum, y = s sum_n (-1)^n w_n x'_{j*+n} / (dc - n), and an
 // on-grid sample (dc = 0) is x'_{j*} exactly (w_0 = 1).
+// `cw[n + D]` = (-1)^n w_n, loaded once per workgroup.
 template <typename T, int DT>
-__device__ __forceinline__ c2<T> interpolate_w0_inside(const BandDev &B, const float2 *xc, T dc) {
-    const T *wt = win_table<T>(B);
+__device__ __forceinline__ c2<T> interpolate_w0_inside(const T *cw, const float2 *xc, T dc) {
     if (dc == (T)0) {
         const float2 x0 = xc[0];
         return mk<T>((T)x0.x, (T)x0.y);
@@ -219,7 +219,7 @@ __device__ __forceinline__ c2<T> interpolate_w0_inside(const BandDev &B, const f
     T re = 0, im = 0;
 #pragma unroll
     for (int n = -DT; n <= DT; ++n) {
-        const T q = ((n & 1) ? -wt[n + DT] : wt[n + DT]) * recip<T>(dc - (T)n);
+        const T q = cw[n + DT] * recip<T>(dc - (T)n);
         const float2 xv = xc[n];
         re = fma(q, (T)xv.x, re);
         im = fma(q, (T)xv.y, im);
@@ -227,12 +227,22 @@ __device__ __forceinline__ c2<T> interpolate_w0_inside(const BandDev &B, const f
     return mk<T>(re * s, im * s);
 }
 
+// Signed tap coefficients (-1)^n w_n of the tap-indexed window for interpolate_w0_inside.
+template <typename T, int DT>
+__device__ __forceinline__ void load_signed_window(const BandDev &B, T *cw) {
+    const T *wt = win_table<T>(B);
+#pragma unroll
+    for (int n = -DT; n <= DT; ++n) cw[n + DT] = (n & 1) ? -wt[n + DT] : wt[n + DT];
+}
+
+// `cw` (signed window, see load_signed_window) is read only when WIN == 0 and DT > 0.
 template <typename T, int DT, int WIN>
-__device__ __forceinline__ c2<T> interpolate(const BandDev &B, const float2 *xd, int64_t jstar, double dcd) {
+__device__ __forceinline__ c2<T> interpolate(const BandDev &B, const float2 *xd, int64_t jstar, double dcd,
+                                             const T *cw) {
     const T dc = (T)dcd;
     const int D = DT > 0 ? DT : B.D;
     if constexpr (WIN == 0 && DT > 0) {
-        if (jstar - D >= 0 && jstar + D < B.n) return interpolate_w0_inside<T, DT>(B, xd + jstar, dc);
+        if (jstar - D >= 0 && jstar + D < B.n) return interpolate_w0_inside<T, DT>(cw, xd + jstar, dc);
     }
     const T s = sin_pi<T>(dc) * (T)0.318309886183790671537767526745;
     const T *wt = win_table<T>(B);
@@ -318,6 +328,8 @@ __global__ void __launch_bounds__(64) k_resample(BandDev B, const double *coef, 
     const Anchor an = B.anchors[entry];
     const double inv_nk = 1.0 / (double)B.n_k;
     const int64_t r0 = (int64_t)K * B.n_k;
+    T cw[2 * (DT > 0 ? DT : 0) + 1];
+    if constexpr (WIN == 0 && DT > 0) load_signed_window<T, DT>(B, cw);
     for (int s = threadIdx.x; s < B.n_k; s += 64) {
         if (!mk_[s]) {
             yo[s] = mk<T>((T)0, (T)0);
@@ -326,7 +338,7 @@ __global__ void __launch_bounds__(64) k_resample(BandDev B, const double *coef, 
         int64_t jstar;
         double dc, psi;
         sample_time(cl, (double)(2 * s - B.n_k) * inv_nk, an, B.inv_dt, B.f_het, r0 + s, jstar, dc, psi);
-        const c2<T> acc = interpolate<T, DT, WIN>(B, xd, jstar, dc);
+        const c2<T> acc = interpolate<T, DT, WIN>(B, xd, jstar, dc, cw);
         T c, sn;
         sincos_rev<T>(psi, sn, c);
         yo[s] = mk<T>(c * acc.x - sn * acc.y, sn * acc.x + c * acc.y);
@@ -389,6 +401,14 @@ __device__ c2<T> *stockham(c2<T> *a, c2<T> *b, int n, const c2<T> *tw, int n_fft
 // bins kbar = m P + p, apply Phi_in = exp(-2 pi i kbar r_B / N_FFT) and 1 / (sigma sqrt N_K).
 // ------------------------------------------------------------------ register FFT (256 points)
 
+// Orders the LDS accesses of one wavefront around this point (compiler ordering only: the
+// hardware executes a wavefront's LDS operations in issue order).
+__device__ __forceinline__ void wave_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
 // 4-point forward DFT in place: (a0, a1, a2, a3) -> sum_n a_n exp(-2 pi i n k / 4).
 template <typename T>
 __device__ __forceinline__ void dft4(c2<T> &a0, c2<T> &a1, c2<T> &a2, c2<T> &a3) {
@@ -425,7 +445,9 @@ __device__ __forceinline__ void dft16(c2<T> *v) {
 // k = k1 + 16 k2: lane t holds x[16 n1 + t] in v[n1]; 16-point DFTs over n1, twiddles
 // W256^(t k1) from the N_FFT-entry table (stride N_FFT / 256), transpose through `sc`
 // (16 x 17 padded), 16-point DFTs over n2.  On return lane t holds X[t + 16 k2] in
-// v[4 (k2 % 4) + k2 / 4].  Every thread of the block calls it (it holds one barrier).
+// v[4 (k2 % 4) + k2 / 4].  A group never straddles a wavefront and `sc` is private to the
+// group, so the transpose needs wave-level ordering only (LDS operations of one wavefront
+// execute in issue order); every lane of the wave calls it.
 // `pre` (applied when `has_pre`) multiplies every stage-1 output of the lane: the per-lane part
 // of a residue-class input twiddle, folded into the W256 twiddles.
 template <typename T>
@@ -446,13 +468,13 @@ __device__ __forceinline__ void fft256_lanes(c2<T> *v, int t, c2<T> *sc, const c
 #pragma unroll
         for (int k1 = 0; k1 < 16; ++k1) sc[k1 * 17 + t] = v[4 * (k1 & 3) + (k1 >> 2)];
     }
-    __syncthreads();
+    wave_sync();
     if (on) {
 #pragma unroll
         for (int n2 = 0; n2 < 16; ++n2) v[n2] = sc[t * 17 + n2];
         dft16<T>(v);
     }
-    __syncthreads();
+    wave_sync();
 }
 
 // Spectra of 256-point segments (n_s = 256, distinct output bins): one 16-lane group per
@@ -499,51 +521,56 @@ k_spectra16(BandDev B, const c2<T> *y, c2<T> *F) {
     }
 }
 
-// Spectra + pair sum for 256-point segments (split precision, distinct bins): one workgroup =
+// Spectra + pair sum for 256-point segments (split precision, distinct bins): one wavefront =
 // one template x one chunk of segments [K0, K1) (plus R halo segments before K0).  Each step
-// transforms S = 8 / Q consecutive segments of every detector, one 16-lane group per
+// transforms S = 4 / Q consecutive segments of every detector, one 16-lane group per
 // (segment, detector), into an LDS ring of R + S decimated spectra, then accumulates each
 // bin's pair sum for the step's segments in the same order as k_pairs.  The segment spectra
-// never leave LDS; one partial per (template, chunk, bin) is written.
+// never leave LDS and the workgroup is a single wavefront, so no step needs a block barrier;
+// one partial per (template, chunk, bin) is written.
+constexpr int kSpairMaxRounds = 8;  // bins per lane: n_f <= 64 * kSpairMaxRounds (NR: 3 or 8)
+
 struct SpairLayout {
     int S, slots, cand;
-    size_t off_acc, off_ring, off_list, off_meta, off_flag, total;
+    size_t off_ring, off_list, off_meta, off_flag, off_pos, total;
 };
 
 // cand = candidate pairs per step: S segments x Q detectors x (R+1) partner segments x Q.
-__host__ __device__ inline SpairLayout spair_layout(int Q, int n_f, int R) {
+__host__ __device__ inline SpairLayout spair_layout(int Q, int n_f, int R, int n_fft) {
     SpairLayout L;
-    L.S = 8 / Q < 1 ? 1 : 8 / Q;
+    L.S = 4 / Q < 1 ? 1 : 4 / Q;
     L.slots = R + L.S;
     L.cand = L.S * Q * (R + 1) * Q;
-    size_t o = 8 * 16 * 17 * sizeof(float2);  // transpose scratch
-    L.off_acc = o;
-    o += (size_t)n_f * 8;
-    o = (o + 15) & ~(size_t)15;
+    size_t o = 4 * 16 * 17 * sizeof(float2);  // transpose scratch of the 4 groups
     L.off_ring = o;
     o += (size_t)L.slots * Q * (n_f + 1) * sizeof(float2);
     o = (o + 15) & ~(size_t)15;
     L.off_list = o;
-    o += (size_t)(L.cand + 1) * 16;  // (ring offset 1, ring offset 2, weight, pad) + count
+    o += (size_t)(L.cand + 1) * 16;  // count, then (ring offset 1, ring offset 2, weight, pad)
     L.off_meta = o;
     o += (size_t)L.slots * Q * 16;   // (hat a, hat b) of the spectrum in each ring slot
     L.off_flag = o;
     o += (size_t)L.slots * Q;
+    o = (o + 15) & ~(size_t)15;
+    L.off_pos = o;                    // ring column of FFT output (p, k2, t), n_f if unused
+    o += (size_t)n_fft * sizeof(int16_t);
     L.total = (o + 15) & ~(size_t)15;
     return L;
 }
 
-__global__ void __launch_bounds__(128) __attribute__((amdgpu_waves_per_eu(2)))
-k_spectra_pairs16(BandDev B, const float2 *y, double *part, int k_chunk, int n_chunks) {
+template <int NR>
+__global__ void __launch_bounds__(64) k_spectra_pairs16(BandDev B, const float2 *y, double *part, int k_chunk,
+                                                       int n_chunks) {
     extern __shared__ __align__(16) unsigned char smem[];
-    const int Q = B.Q, n_f = B.n_f, n_k = B.n_k;
-    const SpairLayout Ly = spair_layout(Q, n_f, B.R);
-    float2 *sc_all = reinterpret_cast<float2 *>(smem);
-    double *acc = reinterpret_cast<double *>(smem + Ly.off_acc);
+    const int Q = B.Q, n_f = B.n_f, n_k = B.n_k, P = B.P;
+    const SpairLayout Ly = spair_layout(Q, n_f, B.R, B.n_fft);
     float2 *ring = reinterpret_cast<float2 *>(smem + Ly.off_ring);
+    int4 *lst = reinterpret_cast<int4 *>(smem + Ly.off_list);
+    double2 *meta = reinterpret_cast<double2 *>(smem + Ly.off_meta);
     uint8_t *flag = smem + Ly.off_flag;
-    const int tid = threadIdx.x;
-    const int grp = tid >> 4, t = tid & 15;
+    int16_t *opos = reinterpret_cast<int16_t *>(smem + Ly.off_pos);
+    const int lane = threadIdx.x;
+    const int grp = lane >> 4, t = lane & 15;
     const int c = blockIdx.x, tb = blockIdx.y;
     const int K0 = c * k_chunk;
     const int K1 = min(B.n_seg, K0 + k_chunk);
@@ -553,53 +580,54 @@ k_spectra_pairs16(BandDev B, const float2 *y, double *part, int k_chunk, int n_c
     const float2 *tw = B.tw32;
     const int tws = B.n_fft >> 8;
     const bool cross = (B.pairs & 1) != 0, same = (B.pairs & 2) != 0;
-    float2 *sc = sc_all + grp * 16 * 17;
+    float2 *sc = reinterpret_cast<float2 *>(smem) + grp * 16 * 17;
     const int sd = grp / Q, X = grp - sd * Q;  // this group's (segment in step, detector)
-    const int n_f1 = n_f + 1;                    // ring rows hold a dummy entry for unused outputs
-    const float2 *ybase = y + ((size_t)tb * Q + X) * nr;
+    const bool used = sd < S;                  // Q = 3: the fourth group idles
+    const int n_f1 = n_f + 1;                  // ring rows hold a dummy entry for unused outputs
+    const float2 *ybase = y + ((size_t)tb * Q + (used ? X : 0)) * nr;
 
-    for (int i = tid; i < n_f; i += 128) acc[i] = 0.0;
-    for (int i = tid; i < slots * Q; i += 128) flag[i] = 0;
-    __syncthreads();
+    // FFT output (p, k2, lane t) holds kbar = (t + 16 k2) P + p; its ring column
+    for (int e = lane; e < B.n_fft; e += 64) {
+        const int tt = e & 15, k2 = (e >> 4) & 15, pp = e >> 8;
+        const int i = B.bin_pos[(tt + 16 * k2) * P + pp];
+        opos[e] = (int16_t)(i >= 0 ? i : n_f);
+    }
+    for (int e = lane; e < slots * Q; e += 64) flag[e] = 0;
+    double acc[NR];
+#pragma unroll
+    for (int r = 0; r < NR; ++r) acc[r] = 0.0;
+    const int rounds = (n_f + 63) >> 6;
 
-    double2 *meta = reinterpret_cast<double2 *>(smem + Ly.off_meta);
     int slot_b = Kh % slots;  // ring slot of segment Kb
-    // the next segment of this group: activity, weights and samples, loaded one step ahead
-    float2 yn[16];
-    bool on_n;
-    SegWeight sw_n;
-    auto prefetch = [&](int Kn) {
-        const bool in = Kn < K1;
-        on_n = in && B.seg_work[X * B.n_seg + Kn] >= 0;
-        sw_n = in ? B.segw[X * B.n_seg + Kn] : SegWeight{0.0, 0.0, 0.0};
+    // this group's samples for the next step, loaded while the current step's pairs are summed
+    float2 yv[16];
+    auto load_y = [&](int Kn) {
+        const bool in = used && Kn < K1;
         const float2 *ysn = ybase + (size_t)(in ? Kn : 0) * n_k;
 #pragma unroll
         for (int n1 = 0; n1 < 16; ++n1) {
             const int sidx = 16 * n1 + t;
-            yn[n1] = (in && sidx < n_k) ? ysn[sidx] : make_float2(0.f, 0.f);
+            yv[n1] = (in && sidx < n_k) ? ysn[sidx] : make_float2(0.f, 0.f);
         }
     };
-    prefetch(Kh + sd);
+    load_y(Kh + sd);
+    wave_sync();
     for (int Kb = Kh; Kb < K1; Kb += S) {
         const int ns = min(S, K1 - Kb);
         const int K = Kb + sd;
-        const bool mine = sd < ns;
-        const bool on = mine && on_n;
-        const SegWeight sw = sw_n;
+        const bool mine = used && sd < ns;
+        const bool on = mine && B.seg_work[X * B.n_seg + K] >= 0;
         int myslot = slot_b + sd;
         if (myslot >= slots) myslot -= slots;
         if (mine && t == 0) {
+            const SegWeight sw = B.segw[X * B.n_seg + K];
             flag[myslot * Q + X] = on ? 1 : 0;
             meta[myslot * Q + X] = make_double2(sw.ahat, sw.bhat);
         }
-        float2 yv[16];
-#pragma unroll
-        for (int n1 = 0; n1 < 16; ++n1) yv[n1] = on ? yn[n1] : make_float2(0.f, 0.f);
-        prefetch(K + S);
+        const float scale = on ? (float)B.segw[X * B.n_seg + K].scale : 0.f;
         const int rb_mod = on ? mod_fft(B, (int64_t)K * n_k) : 0;
-        const float scale = on ? (float)sw.scale : 0.f;
         float2 *Fo = ring + ((size_t)myslot * Q + X) * n_f1;
-        for (int p = 0; p < B.P; ++p) {
+        for (int p = 0; p < P; ++p) {
             // residue class p: x_p[16 n1 + t] = y[16 n1 + t] W^(16 p n1) W^(p t), W = exp(-2 pi i / N);
             // W^(16 p n1) is uniform over lanes, W^(p t) folds into the stage-1 twiddles
             float2 v[16];
@@ -609,77 +637,79 @@ k_spectra_pairs16(BandDev B, const float2 *y, double *part, int k_chunk, int n_c
             if (on) {
                 // Phi_in and the normalisation: scale exp(-2 pi i kbar r_B / N) with
                 // kbar = (t + 16 k2) P + p, by recurrence over k2
-                float2 wo = cscale<float>(tw[mod_fft(B, (int64_t)(t * B.P + p) * rb_mod)], scale);
-                const float2 wst = tw[mod_fft(B, (int64_t)16 * B.P * rb_mod)];
+                float2 wo = cscale<float>(tw[mod_fft(B, (int64_t)(t * P + p) * rb_mod)], scale);
+                const float2 wst = tw[mod_fft(B, (int64_t)16 * P * rb_mod)];
+                const int16_t *op = opos + p * 256 + t;
 #pragma unroll
                 for (int k2 = 0; k2 < 16; ++k2) {
-                    const int i = B.bin_pos[(t + 16 * k2) * B.P + p];
-                    Fo[i >= 0 ? i : n_f] = cmul<float>(v[4 * (k2 & 3) + (k2 >> 2)], wo);
+                    Fo[op[16 * k2]] = cmul<float>(v[4 * (k2 & 3) + (k2 >> 2)], wo);
                     wo = cmul<float>(wo, wst);
                 }
             }
         }
-        __syncthreads();
-        // pair list of the step (the first wave compacts the candidates with a ballot):
-        // segment Kc of the step with detector Xc, partner (Y, L = Kc - dl): L < Kc any detector
-        // allowed by the pair kinds, L = Kc only Y > Xc across detectors; both spectra present.
-        if (tid < 64) {
-            int base = 0;
-            for (int c0 = 0; c0 < Ly.cand; c0 += 64) {
-                const int cd = c0 + tid;
-                bool valid = false;
-                int o1 = 0, o2 = 0;
-                float W = 0.f;
-                if (cd < Ly.cand) {
-                    const int Y = cd % Q;
-                    const int dl = (cd / Q) % (B.R + 1);
-                    const int Xc = (cd / (Q * (B.R + 1))) % Q;
-                    const int s2 = cd / (Q * (B.R + 1) * Q);
-                    const int Kc = Kb + s2, L = Kc - dl;
-                    if (s2 < ns && Kc >= K0 && L >= 0) {
-                        int slot = slot_b + s2;
-                        if (slot >= slots) slot -= slots;
-                        int sl = slot - dl;
-                        if (sl < 0) sl += slots;
-                        const bool inc = (dl > 0) ? ((Y != Xc) ? cross : same) : (cross && Y > Xc);
-                        if (inc && flag[slot * Q + Xc] && flag[sl * Q + Y]) {
-                            valid = true;
-                            const double2 wk = meta[slot * Q + Xc], wl = meta[sl * Q + Y];
-                            W = (float)(wk.x * wl.x + wk.y * wl.y);
-                            o1 = (slot * Q + Xc) * n_f1;
-                            o2 = (sl * Q + Y) * n_f1;
-                        }
+        load_y(K + S);
+        wave_sync();
+        // pair list of the step, compacted with a ballot: segment Kc of the step with detector
+        // Xc, partner (Y, L = Kc - dl): L < Kc any detector allowed by the pair kinds, L = Kc
+        // only Y > Xc across detectors; both spectra present
+        int ne = 0;
+        for (int c0 = 0; c0 < Ly.cand; c0 += 64) {
+            const int cd = c0 + lane;
+            bool valid = false;
+            int o1 = 0, o2 = 0;
+            float W = 0.f;
+            if (cd < Ly.cand) {
+                const int Y = cd % Q;
+                const int dl = (cd / Q) % (B.R + 1);
+                const int Xc = (cd / (Q * (B.R + 1))) % Q;
+                const int s2 = cd / (Q * (B.R + 1) * Q);
+                const int Kc = Kb + s2, L = Kc - dl;
+                if (s2 < ns && Kc >= K0 && L >= 0) {
+                    int slot = slot_b + s2;
+                    if (slot >= slots) slot -= slots;
+                    int sl = slot - dl;
+                    if (sl < 0) sl += slots;
+                    const bool inc = (dl > 0) ? ((Y != Xc) ? cross : same) : (cross && Y > Xc);
+                    if (inc && flag[slot * Q + Xc] && flag[sl * Q + Y]) {
+                        valid = true;
+                        const double2 wk = meta[slot * Q + Xc], wl = meta[sl * Q + Y];
+                        W = (float)(wk.x * wl.x + wk.y * wl.y);
+                        o1 = (slot * Q + Xc) * n_f1;
+                        o2 = (sl * Q + Y) * n_f1;
                     }
                 }
-                const uint64_t m = __ballot(valid);
-                if (valid) {
-                    const int pos = base + __popcll(m & ((1ull << tid) - 1ull));
-                    int4 *ent = reinterpret_cast<int4 *>(smem + Ly.off_list) + 1 + pos;
-                    *ent = make_int4(o1, o2, __float_as_int(W), 0);
-                }
-                base += __popcll(m);
             }
-            if (tid == 0) reinterpret_cast<int4 *>(smem + Ly.off_list)[0] = make_int4(base, 0, 0, 0);
+            const uint64_t m = __ballot(valid);
+            if (valid) lst[ne + __popcll(m & ((1ull << lane) - 1ull))] = make_int4(o1, o2, __float_as_int(W), 0);
+            ne += __popcll(m);
         }
-        __syncthreads();
-        {
-            const int4 *lst = reinterpret_cast<const int4 *>(smem + Ly.off_list);
-            const int ne = lst[0].x;
-            for (int i = tid; i < n_f; i += 128) {
-                float st = 0.f;
-                for (int e = 0; e < ne; ++e) {
-                    const int4 en = lst[1 + e];
+        wave_sync();
+        float st[NR];
+#pragma unroll
+        for (int r = 0; r < NR; ++r) st[r] = 0.f;
+        for (int e = 0; e < ne; ++e) {
+            const int4 en = lst[e];
+            const float W = __int_as_float(en.z);
+#pragma unroll
+            for (int r = 0; r < NR; ++r) {
+                const int i = 64 * r + lane;
+                if (r < rounds && i < n_f) {
                     const float2 f1 = ring[en.x + i], f2 = ring[en.y + i];
-                    st = fma(__int_as_float(en.z), f1.x * f2.x + f1.y * f2.y, st);
+                    st[r] = fma(W, f1.x * f2.x + f1.y * f2.y, st[r]);
                 }
-                acc[i] += (double)st;
             }
         }
-        __syncthreads();
+#pragma unroll
+        for (int r = 0; r < NR; ++r) acc[r] += (double)st[r];
+        wave_sync();
         slot_b += S;
         if (slot_b >= slots) slot_b -= slots;
     }
-    for (int i = tid; i < n_f; i += 128) part[((size_t)tb * n_chunks + c) * n_f + i] = acc[i];
+#pragma unroll
+    for (int r = 0; r < NR; ++r) {
+        const int i = 64 * r + lane;
+        if (r < rounds && i < n_f) part[((size_t)tb * n_chunks + c) * n_f + i] = acc[r];
+    }
 }
 
 // The fused kernel keeps the activity bits of a step (S segments x Q detectors) in 64 bits.
@@ -926,8 +956,12 @@ __global__ void __launch_bounds__(256) k_fused(BandDev B, const double *coef, co
                     accv = B.window == 0 ? interpolate_window<T, DT, 0>(B, xwin + (size_t)e * W, (int)off, dc)
                                          : interpolate_window<T, DT, 1>(B, xwin + (size_t)e * W, (int)off, dc);
                 } else {
-                    accv = B.window == 0 ? interpolate<T, DT, 0>(B, B.x + (size_t)X * B.n, jstar, dc)
-                                         : interpolate<T, DT, 1>(B, B.x + (size_t)X * B.n, jstar, dc);
+                    T cw[2 * (DT > 0 ? DT : 0) + 1];
+                    if constexpr (DT > 0) {
+                        if (B.window == 0) load_signed_window<T, DT>(B, cw);
+                    }
+                    accv = B.window == 0 ? interpolate<T, DT, 0>(B, B.x + (size_t)X * B.n, jstar, dc, cw)
+                                         : interpolate<T, DT, 1>(B, B.x + (size_t)X * B.n, jstar, dc, cw);
                 }
                 T cs_, sn_;
                 sincos_rev<T>(psi, sn_, cs_);
@@ -1076,15 +1110,20 @@ hipError_t launch_spectra(const BandDev &B, int n_tmpl, bool fp64, const void *y
 }
 
 bool spectra_pairs_ok(const BandDev &B, bool fp64, size_t limit) {
-    return !fp64 && B.n_s == 256 && B.bins_unique && spair_layout(B.Q, B.n_f, B.R).total <= limit;
+    return !fp64 && B.n_s == 256 && B.bins_unique && B.Q <= 4 && B.n_f <= 64 * kSpairMaxRounds &&
+           spair_layout(B.Q, B.n_f, B.R, B.n_fft).total <= limit;
 }
 
 hipError_t launch_spectra_pairs(const BandDev &B, int n_tmpl, const void *y, double *part, int k_chunk,
                                 int n_chunks, hipStream_t stream) {
     if (n_tmpl == 0) return hipSuccess;
-    dim3 grid(n_chunks, n_tmpl), block(128);
-    const size_t lds = spair_layout(B.Q, B.n_f, B.R).total;
-    hipLaunchKernelGGL(k_spectra_pairs16, grid, block, lds, stream, B, (const float2 *)y, part, k_chunk, n_chunks);
+    dim3 grid(n_chunks, n_tmpl), block(64);
+    const size_t lds = spair_layout(B.Q, B.n_f, B.R, B.n_fft).total;
+    if (B.n_f <= 64 * 3)
+        hipLaunchKernelGGL(k_spectra_pairs16<3>, grid, block, lds, stream, B, (const float2 *)y, part, k_chunk, n_chunks);
+    else
+        hipLaunchKernelGGL(k_spectra_pairs16<kSpairMaxRounds>, grid, block, lds, stream, B, (const float2 *)y, part,
+                           k_chunk, n_chunks);
     return hipGetLastError();
 }
 
