@@ -212,12 +212,11 @@ int cco_delay(const cco_problem *p, int det, const double tmpl[3], int64_t r, do
 /* Gap mask (reading of Sec. III.B: gaps are zero-padded and get zero weight):
  * m_r = valid(j*_r) with j*_r taken on the Earth-only map (a_p = 0), so the mask
  * and the normalisation do not depend on the template. */
-static void earth_only_mask(const cco_problem *p, const cco_plan *pl, int det, uint8_t *m) {
-    int64_t nr = pl->n_seg * pl->n_k;
+static void earth_only_mask_segment(const cco_problem *p, const cco_plan *pl, int det, int64_t K, uint8_t *m) {
     long double guess = 0.0L;
-    for (int64_t r = 0; r < nr; ++r) {
+    for (int64_t r = K * pl->n_k; r < (K + 1) * pl->n_k; ++r) {
         long double tau = (long double)p->t0 + (long double)r * (long double)p->dt;
-        if (r == 0) guess = crude_guess(p, det, 0.0L, 0.0L, 1.0L, tau);
+        if (r == K * pl->n_k) guess = crude_guess(p, det, 0.0L, 0.0L, 1.0L, tau);
         long double D = solve_delay(p, det, 0.0L, 0.0L, 1.0L, tau, guess);
         guess = D;
         int64_t j = r + (int64_t)floorl(D / (long double)p->dt + 0.5L);
@@ -225,6 +224,10 @@ static void earth_only_mask(const cco_problem *p, const cco_plan *pl, int det, u
         if (j >= 0 && j < p->n) v = p->valid[det] ? (p->valid[det][j] ? 1 : 0) : 1;
         m[r] = v;
     }
+}
+
+static void earth_only_mask(const cco_problem *p, const cco_plan *pl, int det, uint8_t *m) {
+    for (int64_t K = 0; K < pl->n_seg; ++K) earth_only_mask_segment(p, pl, det, K, m);
 }
 
 int cco_valid_fraction(const cco_problem *p, double *phi) {
@@ -270,16 +273,20 @@ static long double sinc_l(long double d) {
  *   the data or in gaps read zero);
  *   y_r = m_r exp(+2 pi i f_h Delta_r) xhat  (heterodyne correction exp(-i 2 pi f_h Dt*),
  *   Dt* = tau - t(tau)). */
-static int resample_det(const cco_problem *p, const cco_plan *pl, int det, const double tmpl[3],
-                        const uint8_t *mask, double *y, int64_t *jstar, double *offset) {
-    int64_t nr = pl->n_seg * pl->n_k;
+/* Resampled samples r of segment K (r in [K N_K, (K+1) N_K)), written to ys[2 s], ys[2 s + 1]
+ * with s = r - K N_K (jstar and offset, if given, are indexed by r):
+ * delay by the Newton solve (started from crude_guess at the segment's first sample, then
+ * from the previous sample's delay), windowed sinc over the valid input samples, heterodyne
+ * correction, gap mask. */
+static void resample_segment(const cco_problem *p, const cco_plan *pl, int det, const double tmpl[3],
+                             const uint8_t *mask, int64_t K, double *ys, int64_t *jstar, double *offset) {
     int D = p->band.dirichlet_D, win = p->band.window;
     const float *x = p->x[det];
     const uint8_t *val = p->valid[det];
     long double guess = 0.0L;
-    for (int64_t r = 0; r < nr; ++r) {
+    for (int64_t r = K * pl->n_k; r < (K + 1) * pl->n_k; ++r) {
         long double tau = (long double)p->t0 + (long double)r * (long double)p->dt;
-        if (r == 0) guess = crude_guess(p, det, tmpl[0], tmpl[1], tmpl[2], tau);
+        if (r == K * pl->n_k) guess = crude_guess(p, det, tmpl[0], tmpl[1], tmpl[2], tau);
         long double Dl = solve_delay(p, det, tmpl[0], tmpl[1], tmpl[2], tau, guess);
         guess = Dl;
         long double q = Dl / (long double)p->dt;
@@ -300,11 +307,17 @@ static int resample_det(const cco_problem *p, const cco_plan *pl, int det, const
         psi -= floorl(psi);
         double c = (double)cosl(2.0L * PI_L * psi), s = (double)sinl(2.0L * PI_L * psi);
         double m = mask[r] ? 1.0 : 0.0;
-        y[2 * r] = m * (c * re - s * im);
-        y[2 * r + 1] = m * (s * re + c * im);
+        ys[2 * (r - K * pl->n_k)] = m * (c * re - s * im);
+        ys[2 * (r - K * pl->n_k) + 1] = m * (s * re + c * im);
         if (jstar) jstar[r] = js;
         if (offset) offset[r] = (double)dc;
     }
+}
+
+static int resample_det(const cco_problem *p, const cco_plan *pl, int det, const double tmpl[3],
+                        const uint8_t *mask, double *y, int64_t *jstar, double *offset) {
+    for (int64_t K = 0; K < pl->n_seg; ++K)
+        resample_segment(p, pl, det, tmpl, mask, K, y + 2 * K * pl->n_k, jstar, offset);
     return CCO_OK;
 }
 
@@ -346,29 +359,34 @@ static int64_t bin_mod(const cco_plan *pl, int64_t i) {
  * r_B = K N_K, referenced to the series origin (Phi_in folded into the kernel):
  *   F_XK(i) = (sigma_XK sqrt(N_K))^-1 sum_{s<N_K} y_{r_B+s} exp(-2 pi i kbar_i (r_B + s) / N_FFT),
  * the phase index (kbar (r_B + s)) mod N_FFT kept as an exact integer. */
+/* Direct DFT of segment K from its resampled samples ys[2 s], s < N_K, decimated bins, Phi_in
+ * through the exact integer phase index (kbar (r_B + s) mod N_FFT), 1 / (sigma sqrt N_K). */
+static void spectra_segment(const cco_problem *p, const cco_plan *pl, int det, int64_t K, const double *ys,
+                            const double *tw, const int64_t *bins, int64_t nb, double *F) {
+    int64_t nk = pl->n_k, nfft = pl->n_fft;
+    double scale = 1.0 / (sqrt(p->noise_var[det][K]) * sqrt((double)nk));
+    int64_t rb = K * nk;
+    for (int64_t ii = 0; ii < nb; ++ii) {
+        int64_t kb = bin_mod(pl, bins ? bins[ii] : ii);
+        int64_t idx = (kb * rb) % nfft;
+        double re = 0.0, im = 0.0;
+        for (int64_t s = 0; s < nk; ++s) {
+            const double *yy = ys + 2 * s;
+            double c = tw[2 * idx], sn = tw[2 * idx + 1];
+            re += yy[0] * c - yy[1] * sn;
+            im += yy[0] * sn + yy[1] * c;
+            idx += kb;
+            if (idx >= nfft) idx -= nfft;
+        }
+        double *o = F + 2 * ((det * pl->n_seg + K) * nb + ii);
+        o[0] = re * scale;
+        o[1] = im * scale;
+    }
+}
+
 static void spectra_from_series(const cco_problem *p, const cco_plan *pl, int det, const double *y,
                                 const double *tw, const int64_t *bins, int64_t nb, double *F) {
-    int64_t nk = pl->n_k, nfft = pl->n_fft;
-    for (int64_t K = 0; K < pl->n_seg; ++K) {
-        double scale = 1.0 / (sqrt(p->noise_var[det][K]) * sqrt((double)nk));
-        int64_t rb = K * nk;
-        for (int64_t ii = 0; ii < nb; ++ii) {
-            int64_t kb = bin_mod(pl, bins ? bins[ii] : ii);
-            int64_t idx = (kb * rb) % nfft;
-            double re = 0.0, im = 0.0;
-            for (int64_t s = 0; s < nk; ++s) {
-                const double *yy = y + 2 * (rb + s);
-                double c = tw[2 * idx], sn = tw[2 * idx + 1];
-                re += yy[0] * c - yy[1] * sn;
-                im += yy[0] * sn + yy[1] * c;
-                idx += kb;
-                if (idx >= nfft) idx -= nfft;
-            }
-            double *o = F + 2 * ((det * pl->n_seg + K) * nb + ii);
-            o[0] = re * scale;
-            o[1] = im * scale;
-        }
-    }
+    for (int64_t K = 0; K < pl->n_seg; ++K) spectra_segment(p, pl, det, K, y + 2 * K * pl->n_k, tw, bins, nb, F);
 }
 
 /* Tier D spectra (App. A, eq. from-here-resamp; Sec. III.B.5 frame invariance):
@@ -532,8 +550,9 @@ int cco_rho(const cco_problem *p, const double *tmpl, int64_t n_tmpl, int tier,
         free(masks); free(phi); free(tw);
         return CCO_ENOMEM;
     }
-#pragma omp parallel for schedule(static)
-    for (int X = 0; X < Q; ++X) earth_only_mask(p, &pl, X, masks + X * nr);
+#pragma omp parallel for schedule(dynamic, 64)
+    for (int64_t w = 0; w < Q * pl.n_seg; ++w)
+        earth_only_mask_segment(p, &pl, (int)(w / pl.n_seg), w % pl.n_seg, masks + (w / pl.n_seg) * nr);
     for (int X = 0; X < Q; ++X)
         for (int64_t K = 0; K < pl.n_seg; ++K) {
             int64_t c = 0;
@@ -542,28 +561,44 @@ int cco_rho(const cco_problem *p, const double *tmpl, int64_t n_tmpl, int tier,
         }
     double N = norm_from_phi(p, &pl, phi);
     int fail = 0;
-#pragma omp parallel for schedule(dynamic, 1)
-    for (int64_t t = 0; t < n_tmpl; ++t) {
-        double *y = (double *)malloc(sizeof(double) * 2 * (size_t)nr);
-        double *F = (double *)malloc(sizeof(double) * 2 * (size_t)(Q * pl.n_seg * nb));
-        if (!y || !F) {
-            free(y); free(F);
-#pragma omp atomic write
-            fail = 1;
-            continue;
-        }
-        for (int X = 0; X < Q; ++X) {
-            if (tier == 0) {
-                resample_det(p, &pl, X, tmpl + 3 * t, masks + X * nr, y, NULL, NULL);
-                spectra_from_series(p, &pl, X, y, tw, bins, nb, F);
-            } else {
-                spectra_direct(p, &pl, X, tmpl + 3 * t, bins, nb, F);
-            }
-        }
-        rho_from_spectra(p, &pl, F, nb, N, rho + t * nb);
-        free(y);
-        free(F);
+    /* templates in groups; within a group every (template, detector, segment) is an independent
+     * work item (tier R) or every (template, detector) (tier D); the pair sum per template */
+    int64_t G = cco_num_threads();
+    if (G < 1) G = 1;
+    size_t fsz = (size_t)(Q * pl.n_seg * nb) * 2;
+    double *F = (double *)malloc(sizeof(double) * fsz * (size_t)G);
+    int nth = cco_num_threads();
+    double *y = (tier == 0) ? (double *)malloc(sizeof(double) * 2 * (size_t)pl.n_k * (size_t)nth) : NULL;
+    if (!F || (tier == 0 && !y)) {
+        free(F); free(y); free(masks); free(phi); free(tw);
+        return CCO_ENOMEM;
     }
+    for (int64_t g = 0; g < n_tmpl; g += G) {
+        int64_t gn = (n_tmpl - g < G) ? n_tmpl - g : G;
+        if (tier == 0) {
+#pragma omp parallel for schedule(dynamic, 16)
+            for (int64_t w = 0; w < gn * Q * pl.n_seg; ++w) {
+                int64_t tl = w / (Q * pl.n_seg);
+                int X = (int)((w / pl.n_seg) % Q);
+                int64_t K = w % pl.n_seg;
+#ifdef _OPENMP
+                double *yt = y + 2 * (size_t)pl.n_k * (size_t)omp_get_thread_num();
+#else
+                double *yt = y;
+#endif
+                resample_segment(p, &pl, X, tmpl + 3 * (g + tl), masks + X * nr, K, yt, NULL, NULL);
+                spectra_segment(p, &pl, X, K, yt, tw, bins, nb, F + fsz * (size_t)tl);
+            }
+        } else {
+#pragma omp parallel for schedule(dynamic, 1)
+            for (int64_t w = 0; w < gn * Q; ++w)
+                spectra_direct(p, &pl, (int)(w % Q), tmpl + 3 * (g + w / Q), bins, nb, F + fsz * (size_t)(w / Q));
+        }
+#pragma omp parallel for schedule(dynamic, 1)
+        for (int64_t tl = 0; tl < gn; ++tl) rho_from_spectra(p, &pl, F + fsz * (size_t)tl, nb, N, rho + (g + tl) * nb);
+    }
+    free(F);
+    free(y);
     free(masks); free(phi); free(tw);
     return fail ? CCO_ENOMEM : CCO_OK;
 }

@@ -26,4 +26,4 @@ from .model import (  # noqa: F401
     antenna_ab, load_bandwidth, samples_per_segment,
 )
 from .configs import CONFIGS, config  # noqa: F401
-from .generate import Dataset, make_dataset, template_grid  # noqa: F401
+from .generate import Dataset, make_dataset, make_multiband, multiband_bands, template_grid  # noqa: F401

@@ -45,6 +45,24 @@ CONFIGS = {
         injections="random10",
         seed=2002,
     ),
+    # Batching form: 3 detectors with uneven coverage (100 / 120 / 80 days of a 120-day span,
+    # independent gap times), 64 bands between 50 and 400 Hz of 0.05-0.2 Hz, T_short from 1400 s
+    # (50 Hz) to 240 s (400 Hz), lag 1, 32 x 32 templates per band, an injection in every
+    # fourth band.  Built by make_multiband (one dataset per band).
+    "multiband": dict(
+        detectors=["H", "L", "V"],
+        t_obs=120 * DAY,
+        gap_fraction=0.15,
+        coverage=[(0.0, 100.0 / 120.0), (0.0, 1.0), (20.0 / 120.0, 80.0 / 120.0)],
+        sigma=[1.0, 1.1, 1.3],
+        bands=dict(count=64, f_lo=50.0, f_hi=400.0, f_band=[0.05, 0.10, 0.15, 0.20],
+                   t_short_lo=1400.0, t_short_hi=240.0, max_lag=1, pairs=3, a_p_max=2.0),
+        templates=dict(a_p=(1.0, 2.0, 32), t_asc=(-1000.0, 1000.0, 32), period=[P0]),
+        t_asc0=60 * DAY + 555.0,
+        inject_every=4,
+        seed=4004,
+        name="multiband",
+    ),
     # Largest: 240 days, T_short 1440 s, lag 4, 0.25 Hz at 400 Hz, 200 x 167 x 3 templates.
     "large": dict(
         detectors=["H", "L"],
