@@ -198,6 +198,7 @@ def main():
     nsub = min(args.fp64_templates, n_t)
     ctx2 = Context(ds.sky, device=0)
     ctx2.set_option("template_batch", 1)
+    ctx2.set_option("items_per_launch", 1)
     ctx2.set_option("fused", 0)
     bid2 = ctx2.load(ds, templates=ds.templates[:nsub])
     out2 = torch.empty((nsub, n_f), dtype=torch.float64, device="cuda")

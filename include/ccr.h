@@ -137,11 +137,31 @@ void ccr_destroy(ccr_ctx *ctx);
 /* Message of the last failing call on this context ("" if none).  Valid until the next call. */
 const char *ccr_last_error(const ccr_ctx *ctx);
 
-/* Set a tuning option.  Names: "template_batch" (templates per launch, 0 = auto),
- * "workspace_mb" (device workspace budget), "fused" (1: fused resample+FFT+pair kernel
- * when the band allows it, 0: staged kernels), "k_chunk" (segments per pair-sum chunk).
+/* Set an option (value >= 0).  Names:
+ *   "template_batch"  templates per work item (one band's share of a launch), 0 = as many as
+ *                     the workspace budget holds;
+ *   "workspace_mb"    device workspace budget in MiB (resampled series, spectra, partials);
+ *   "k_chunk"         segments per pair-sum chunk, 0 = min(M, 256) or the tuned value;
+ *   "fused"           1: fused resample + FFT + pair kernel where a band fits it, 0: staged;
+ *   "items_per_launch" work items per launch, 0 = as many as the workspace holds (1 with
+ *                     template_batch 1: one template per launch sequence, no batching);
+ *   "timing"          1: time every kernel launch with HIP events (see ccr_kernel_time);
+ *   "graph"           1: capture each distinct compute call (bands, precision, device
+ *                     outputs) as a HIP graph on first use and replay it afterwards; a change
+ *                     of data, templates, weights, workspace or launch options re-captures;
+ *                     applies to device outputs only;
+ *   "autotune"        1: on the first call for a given band list and precision, time the
+ *                     first launch round for k_chunk = 32 ... 1024 and keep the fastest
+ *                     (an explicit "k_chunk" disables tuning).
+ * All bands of a compute call run in shared launches: one launch per stage covers the work
+ * items of many bands (grouped by kernel variant, packed to the workspace budget).
  * Returns CCR_EUNSUP for an unknown name. */
 ccr_status ccr_set_option(ccr_ctx *ctx, const char *name, int64_t value);
+
+/* Read an option set with ccr_set_option, or "tuned_k_chunk" / "tuned_template_batch": the
+ * launch shape the autotuner chose last (0 before any tuning).  CCR_EUNSUP for an unknown
+ * name. */
+ccr_status ccr_get_option(ccr_ctx *ctx, const char *name, int64_t *value);
 
 /* Add a band; returns its id and the part of the plan known before data (n_k, dt, f_het,
  * df_load).  Bands are independent. */
@@ -173,7 +193,9 @@ ccr_status ccr_get_band_info(ccr_ctx *ctx, int band_id, ccr_band_info *info, dou
 /* rho for every template and bin of each listed band.  rho_out[b] points to
  * n_templates * n_f values (row-major, template-major) of double (out_fp64 = 1) or float,
  * in device memory (out_on_device = 1, must stay valid until ccr_sync) or host memory
- * (written before the call returns).  hip_stream: a hipStream_t or NULL. */
+ * (written before the call returns).  hip_stream: a hipStream_t, or NULL for the context's
+ * own stream.  The calls of one context share its workspace: queue them on one stream (or
+ * synchronise between streams); calls that overlap on different streams race. */
 ccr_status ccr_compute_rho(ccr_ctx *ctx, ccr_precision prec, int n_bands, const int *band_ids,
                            void *const *rho_out, int out_on_device, int out_fp64, void *hip_stream);
 

@@ -63,6 +63,7 @@ SIGNATURES = {
     "ccr_destroy": ([_vp], None),
     "ccr_last_error": ([_vp], ctypes.c_char_p),
     "ccr_set_option": ([_vp, ctypes.c_char_p, ctypes.c_int64], ctypes.c_int),
+    "ccr_get_option": ([_vp, ctypes.c_char_p, ctypes.POINTER(ctypes.c_int64)], ctypes.c_int),
     "ccr_add_band": ([_vp, ctypes.POINTER(Band), ctypes.POINTER(ctypes.c_int), ctypes.POINTER(BandInfo)], ctypes.c_int),
     "ccr_set_data": ([_vp, ctypes.c_int, ctypes.c_int, ctypes.POINTER(Site), ctypes.c_double, ctypes.c_double,
                       ctypes.c_int64, ctypes.c_double, _vp, _vp], ctypes.c_int),
@@ -140,6 +141,11 @@ class Context:
 
     def set_option(self, name, value):
         self._check(self.L.ccr_set_option(self.h, name.encode(), int(value)))
+
+    def get_option(self, name):
+        v = ctypes.c_int64()
+        self._check(self.L.ccr_get_option(self.h, name.encode(), ctypes.byref(v)))
+        return v.value
 
     def add_band(self, band):
         b = Band(float(band["f_min"]), float(band["f_band"]), float(band["t_short"]), int(band["max_lag"]),

@@ -102,6 +102,24 @@ struct ccr_ctx {
     int64_t opt_fused = 0;
     int64_t opt_timing = 0;
     DevBuf ws_y, ws_F, ws_part, ws_out, ws_coef;
+    int64_t opt_graph = 0, opt_autotune = 0, opt_items_per_launch = 0;
+    // bumped whenever device memory a captured launch sequence refers to may have moved
+    uint64_t gen = 1;
+    // device copies of the band and work-item tables of the last eager call, their pinned
+    // staging buffer and the event after which the staging buffer may be rewritten
+    DevBuf d_tables;
+    void *h_tables = nullptr;
+    size_t h_tables_bytes = 0;
+    hipEvent_t tables_copied = nullptr;
+    struct GraphEntry;
+    std::vector<std::unique_ptr<GraphEntry>> graphs;
+    struct Tuned {
+        std::vector<int> band_ids;
+        int prec;
+        int64_t k_chunk, template_batch;
+    };
+    std::vector<Tuned> tuned;
+    int64_t last_tuned_k_chunk = 0, last_tuned_template_batch = 0;
     struct Timed {
         int kind;
         hipEvent_t a, b;
@@ -109,6 +127,23 @@ struct ccr_ctx {
     std::vector<Timed> timed;
     double kt_ms[7] = {0, 0, 0, 0, 0, 0, 0};
     int64_t kt_n[7] = {0, 0, 0, 0, 0, 0, 0};
+};
+
+// A compute call captured as a HIP graph: replayed while the call's arguments and the
+// context's device memory are unchanged (`gen`).
+struct ccr_ctx::GraphEntry {
+    std::vector<int> band_ids;
+    std::vector<void *> outs;
+    int prec = 0, out_fp64 = 0;
+    uint64_t gen = 0;
+    void *tables = nullptr;  // device copy of the band and work-item tables
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    ~GraphEntry() {
+        if (exec) (void)hipGraphExecDestroy(exec);
+        if (graph) (void)hipGraphDestroy(graph);
+        if (tables) (void)hipFree(tables);
+    }
 };
 
 namespace {
@@ -303,6 +338,9 @@ ccr_status prepare(ccr_ctx *c, Band &B) {
     if (B.prepared) return CCR_OK;
     ccr_status st = check_ready(c, B);
     if (st) return st;
+    // the band's device tables are about to be replaced: finish work that may read them
+    if (c->device >= 0) HIP_OK(c, hipDeviceSynchronize());
+    c->gen++;
     Plan pl;
     st = make_plan(c, B, pl);
     if (st) return st;
@@ -474,6 +512,8 @@ ccr_status prepare(ccr_ctx *c, Band &B) {
 
 ccr_status prepare_templates(ccr_ctx *c, Band &B) {
     const Plan &pl = B.plan;
+    if (c->device >= 0) HIP_OK(c, hipDeviceSynchronize());
+    c->gen++;
     const int64_t T = B.n_tmpl;
     const long double t0 = B.det[0].t0, dt = pl.dt;
     const long double tseg = (long double)pl.n_k * dt;
@@ -550,6 +590,7 @@ BandDev band_dev(const Band &B) {
     d.work = B.d_work.as<int>();
     d.seg_work = B.d_seg_work.as<int>();
     d.n_work = B.n_work;
+    d.tmpl = B.d_tmpl.as<double>();
     return d;
 }
 
@@ -593,8 +634,8 @@ struct LaunchTimer {
     int kind;
     hipStream_t s;
     hipEvent_t a = nullptr, b = nullptr;
-    LaunchTimer(ccr_ctx *c_, int k, hipStream_t s_) : c(c_), kind(k), s(s_) {
-        if (!c->opt_timing) return;
+    LaunchTimer(ccr_ctx *c_, int k, hipStream_t s_, bool on = true) : c(c_), kind(k), s(s_) {
+        if (!c->opt_timing || !on) return;
         if (hipEventCreate(&a) != hipSuccess || hipEventCreate(&b) != hipSuccess) {
             a = b = nullptr;
             return;
@@ -678,6 +719,402 @@ ccr_status compute_fused(ccr_ctx *c, Band &B, const BandDev &bd, bool fp64, int 
     return CCR_OK;
 }
 
+
+// ------------------------------------------------------------------ batched execution
+//
+// One ccr_compute_rho call becomes a list of work items (runs of consecutive templates of one
+// band), grouped by kernel variant and packed into rounds that fit the workspace.  Each round
+// is one launch per stage (time base, resampling, spectra [+ pair sum], [pair sum,] finish)
+// covering every item of the round, whatever band it belongs to.
+
+// Kernel variant shared by the items of one round.
+struct Variant {
+    bool sp = false;     // spectra + pair sum in one kernel
+    bool reg16 = false;  // otherwise: 256-point register FFT (else the LDS Stockham FFT on n_s points)
+    int DT = 0, window = 0, n_s = 0, nr = 0;
+    bool operator==(const Variant &o) const {
+        return sp == o.sp && reg16 == o.reg16 && DT == o.DT && window == o.window && n_s == o.n_s && nr == o.nr;
+    }
+};
+
+struct Round {
+    int i0 = 0, n = 0;  // items [i0, i0 + n) of the call's item table
+    Variant v;
+    size_t lds = 0;     // dynamic LDS of the spectra + pair-sum kernel
+    int64_t blocks[kStages] = {0, 0, 0, 0, 0};
+    size_t y_bytes = 0, F_bytes = 0, part_bytes = 0, coef_bytes = 0;
+};
+
+struct CallPlan {
+    std::vector<BandDev> bands;  // by position in the call
+    std::vector<WorkItem> items;
+    std::vector<Round> rounds;
+    size_t y_bytes = 0, F_bytes = 0, part_bytes = 0, coef_bytes = 0;  // largest round
+    std::vector<size_t> out_off;  // host outputs: byte offset of each band's rho in ws_out
+    size_t out_bytes = 0;
+};
+
+// Launch shape parameters (0 = default): templates per item and segments per pair-sum chunk.
+struct BatchParams {
+    int64_t template_batch = 0, k_chunk = 0;
+};
+
+Variant variant_of(const BandDev &bd, bool fp64) {
+    Variant v;
+    v.sp = spectra_pairs_ok(bd, fp64, kMaxLds);
+    v.DT = bd.D == 8 ? 8 : 0;
+    v.window = bd.window;
+    if (v.sp) {
+        v.nr = spectra_pairs_rounds(bd);
+    } else {
+        v.reg16 = !fp64 && bd.n_s == 256 && bd.bins_unique;
+        if (!v.reg16) v.n_s = bd.n_s;
+    }
+    return v;
+}
+
+constexpr int64_t kMaxBlocks = ((int64_t)1 << 31) - 1;
+
+// Grow a workspace buffer; device work that may still use the old allocation is finished
+// first, and captured launch sequences that refer to it are invalidated.
+ccr_status grow(ccr_ctx *c, DevBuf &b, size_t bytes) {
+    if (bytes <= b.bytes && b.p) return CCR_OK;
+    HIP_OK(c, hipDeviceSynchronize());
+    HIP_OK(c, b.ensure(bytes));
+    c->gen++;
+    return CCR_OK;
+}
+
+ccr_status build_plan(ccr_ctx *c, bool fp64, int n_bands, const int *band_ids, void *const *rho_out,
+                      int out_on_device, int out_fp64, const BatchParams &bp, CallPlan &cp) {
+    const size_t cs = fp64 ? 16 : 8;
+    const size_t osz = out_fp64 ? sizeof(double) : sizeof(float);
+    const size_t budget = (size_t)c->opt_workspace_mb << 20;
+    cp = CallPlan();
+    cp.out_off.assign((size_t)n_bands, 0);
+    for (int bi = 0; bi < n_bands; ++bi) {
+        const Band &B = *get_band(c, band_ids[bi]);
+        cp.out_off[bi] = cp.out_bytes;
+        cp.out_bytes += ((size_t)B.n_tmpl * B.plan.n_f * osz + 255) & ~(size_t)255;
+    }
+    if (!out_on_device) {
+        ccr_status st = grow(c, c->ws_out, cp.out_bytes);
+        if (st) return st;
+    }
+    struct Pending {
+        WorkItem it;
+        Variant v;
+        size_t y, F, part, coef, lds;
+        int64_t blk[kStages];
+    };
+    std::vector<Pending> pend;
+    std::vector<Variant> variants;
+    for (int bi = 0; bi < n_bands; ++bi) {
+        const Band &B = *get_band(c, band_ids[bi]);
+        const Plan &pl = B.plan;
+        const BandDev bd = band_dev(B);
+        cp.bands.push_back(bd);
+        const Variant v = variant_of(bd, fp64);
+        if (std::find(variants.begin(), variants.end(), v) == variants.end()) variants.push_back(v);
+        int64_t kc = bp.k_chunk > 0 ? bp.k_chunk : std::min<int64_t>(pl.n_seg, 256);
+        kc = std::max<int64_t>(1, std::min<int64_t>(kc, pl.n_seg));
+        const int nch = (int)((pl.n_seg + kc - 1) / kc);
+        const size_t y1 = (size_t)B.Q * pl.n_seg * pl.n_k * cs;
+        const size_t F1 = v.sp ? 0 : (size_t)B.Q * pl.n_seg * pl.n_f * cs;
+        const size_t part1 = (size_t)nch * pl.n_f * sizeof(double);
+        const size_t coef1 = (size_t)std::max(B.n_work, 1) * kCheb * sizeof(double);
+        WorkItem proto;
+        std::memset(&proto, 0, sizeof proto);
+        proto.band = bi;
+        proto.k_chunk = (int)kc;
+        proto.n_chunks = nch;
+        proto.factor = pl.norm > 0.0 ? std::sqrt(2.0) / pl.norm : 0.0;
+        proto.out_fp64 = out_fp64 ? 1 : 0;
+        proto.gx[kStTimebase] = (B.n_work + kTbEntries - 1) / kTbEntries;
+        proto.gx[kStResample] = B.n_work;
+        proto.gx[kStSpectra] = v.sp ? nch : (v.reg16 ? (B.n_work + kSpec16Groups - 1) / kSpec16Groups : B.n_work);
+        proto.gx[kStPairs] = v.sp ? 0 : (int)((pl.n_f + kPairsThreads - 1) / kPairsThreads);
+        proto.gx[kStFinish] = (int)((pl.n_f + kFinishThreads - 1) / kFinishThreads);
+        const int64_t per_t[kStages] = {proto.gx[0], proto.gx[1], proto.gx[2], (int64_t)proto.gx[3] * nch, proto.gx[4]};
+        int64_t tb = bp.template_batch > 0 ? bp.template_batch : c->opt_template_batch;
+        if (tb <= 0) tb = (int64_t)std::max<size_t>(1, budget / std::max<size_t>(y1 + F1 + part1 + coef1, 1));
+        for (int st = 0; st < kStages; ++st) tb = std::min<int64_t>(tb, kMaxBlocks / std::max<int64_t>(per_t[st], 1));
+        tb = std::max<int64_t>(1, std::min<int64_t>(tb, B.n_tmpl));
+        char *dst = out_on_device ? static_cast<char *>(rho_out[bi]) : c->ws_out.as<char>() + cp.out_off[bi];
+        for (int64_t t = 0; t < B.n_tmpl; t += tb) {
+            Pending q;
+            q.it = proto;
+            const int nb = (int)std::min<int64_t>(tb, B.n_tmpl - t);
+            q.it.n_tmpl = nb;
+            q.it.tmpl_off = t;
+            q.it.out = dst + (size_t)t * pl.n_f * osz;
+            q.v = v;
+            q.y = y1 * nb;
+            q.F = F1 * nb;
+            q.part = part1 * nb;
+            q.coef = coef1 * nb;
+            q.lds = v.sp ? spectra_pairs_lds(bd) : 0;
+            for (int st = 0; st < kStages; ++st) q.blk[st] = per_t[st] * nb;
+            pend.push_back(q);
+        }
+    }
+    // rounds: items of one variant in call order, packed while the workspace and the grid allow
+    for (const Variant &v : variants) {
+        Round r;
+        auto close = [&]() {
+            if (r.n == 0) return;
+            cp.rounds.push_back(r);
+            cp.y_bytes = std::max(cp.y_bytes, r.y_bytes);
+            cp.F_bytes = std::max(cp.F_bytes, r.F_bytes);
+            cp.part_bytes = std::max(cp.part_bytes, r.part_bytes);
+            cp.coef_bytes = std::max(cp.coef_bytes, r.coef_bytes);
+        };
+        r.v = v;
+        r.i0 = (int)cp.items.size();
+        for (const Pending &q : pend) {
+            if (!(q.v == v)) continue;
+            bool full = r.y_bytes + r.F_bytes + r.part_bytes + r.coef_bytes + q.y + q.F + q.part + q.coef > budget;
+            for (int st = 0; st < kStages; ++st) full = full || r.blocks[st] + q.blk[st] > kMaxBlocks;
+            if (c->opt_items_per_launch > 0 && r.n >= c->opt_items_per_launch) full = true;
+            if (r.n > 0 && full) {
+                close();
+                r = Round();
+                r.v = v;
+                r.i0 = (int)cp.items.size();
+            }
+            WorkItem it = q.it;
+            it.coef_off = (int64_t)(r.coef_bytes / sizeof(double));
+            it.y_off = (int64_t)(r.y_bytes / cs);
+            it.F_off = (int64_t)(r.F_bytes / cs);
+            it.part_off = (int64_t)(r.part_bytes / sizeof(double));
+            for (int st = 0; st < kStages; ++st) {
+                it.first[st] = (int)r.blocks[st];
+                r.blocks[st] += q.blk[st];
+            }
+            r.y_bytes += q.y;
+            r.F_bytes += q.F;
+            r.part_bytes += q.part;
+            r.coef_bytes += q.coef;
+            r.lds = std::max(r.lds, q.lds);
+            r.n++;
+            cp.items.push_back(it);
+        }
+        close();
+    }
+    return CCR_OK;
+}
+
+ccr_status ensure_workspace(ccr_ctx *c, const CallPlan &cp) {
+    ccr_status st;
+    if ((st = grow(c, c->ws_y, std::max<size_t>(cp.y_bytes, 16)))) return st;
+    if ((st = grow(c, c->ws_F, std::max<size_t>(cp.F_bytes, 16)))) return st;
+    if ((st = grow(c, c->ws_part, std::max<size_t>(cp.part_bytes, 16)))) return st;
+    return grow(c, c->ws_coef, std::max<size_t>(cp.coef_bytes, 16));
+}
+
+// Bytes of the device table (band descriptors, then work items, 256-byte aligned).
+size_t tables_bytes(const CallPlan &cp, size_t *items_off) {
+    *items_off = (cp.bands.size() * sizeof(BandDev) + 255) & ~(size_t)255;
+    return *items_off + cp.items.size() * sizeof(WorkItem);
+}
+
+void fill_tables(const CallPlan &cp, void *dst, size_t items_off) {
+    std::memcpy(dst, cp.bands.data(), cp.bands.size() * sizeof(BandDev));
+    std::memcpy(static_cast<char *>(dst) + items_off, cp.items.data(), cp.items.size() * sizeof(WorkItem));
+}
+
+// Queue the rounds [r0, r1) of a plan on `s` (tables already on the device).
+ccr_status run_rounds(ccr_ctx *c, const CallPlan &cp, size_t r0, size_t r1, bool fp64, const void *d_tables,
+                      size_t items_off, hipStream_t s, bool timing) {
+    const BandDev *db = static_cast<const BandDev *>(d_tables);
+    const WorkItem *ditems = reinterpret_cast<const WorkItem *>(static_cast<const char *>(d_tables) + items_off);
+    double *coef = c->ws_coef.as<double>(), *part = c->ws_part.as<double>();
+    for (size_t ri = r0; ri < r1; ++ri) {
+        const Round &r = cp.rounds[ri];
+        const WorkItem *di = ditems + r.i0;
+        {
+            LaunchTimer lt(c, 5, s, timing);
+            HIP_OK(c, launch_timebase_m(db, di, r.n, (int)r.blocks[kStTimebase], coef, s));
+        }
+        {
+            LaunchTimer lt(c, 0, s, timing);
+            HIP_OK(c, launch_resample_m(db, di, r.n, (int)r.blocks[kStResample], fp64, r.v.DT, r.v.window, coef,
+                                        c->ws_y.p, s));
+        }
+        if (r.v.sp) {
+            LaunchTimer lt(c, 6, s, timing);
+            HIP_OK(c, launch_spectra_pairs_m(db, di, r.n, (int)r.blocks[kStSpectra], r.v.nr, r.lds, c->ws_y.p, part, s));
+        } else {
+            {
+                LaunchTimer lt(c, 1, s, timing);
+                HIP_OK(c, launch_spectra_m(db, di, r.n, (int)r.blocks[kStSpectra], fp64, r.v.reg16,
+                                           spectra_threads(r.v.n_s), r.v.n_s, c->ws_y.p, c->ws_F.p, s));
+            }
+            {
+                LaunchTimer lt(c, 2, s, timing);
+                HIP_OK(c, launch_pairs_m(db, di, r.n, (int)r.blocks[kStPairs], fp64, c->ws_F.p, part, s));
+            }
+        }
+        {
+            LaunchTimer lt(c, 3, s, timing);
+            HIP_OK(c, launch_finish_m(db, di, r.n, (int)r.blocks[kStFinish], part, s));
+        }
+    }
+    return CCR_OK;
+}
+
+// Eager upload of a plan's tables through the pinned staging buffer (stream ordered).
+ccr_status upload_tables(ccr_ctx *c, const CallPlan &cp, hipStream_t s, size_t *items_off) {
+    const size_t bytes = tables_bytes(cp, items_off);
+    if (c->tables_copied) HIP_OK(c, hipEventSynchronize(c->tables_copied));
+    else HIP_OK(c, hipEventCreateWithFlags(&c->tables_copied, hipEventDisableTiming));
+    if (c->h_tables_bytes < bytes) {
+        if (c->h_tables) HIP_OK(c, hipHostFree(c->h_tables));
+        c->h_tables = nullptr;
+        c->h_tables_bytes = 0;
+        HIP_OK(c, hipHostMalloc(&c->h_tables, bytes));
+        c->h_tables_bytes = bytes;
+    }
+    fill_tables(cp, c->h_tables, *items_off);
+    ccr_status st = grow(c, c->d_tables, bytes);
+    if (st) return st;
+    HIP_OK(c, hipMemcpyAsync(c->d_tables.p, c->h_tables, bytes, hipMemcpyHostToDevice, s));
+    HIP_OK(c, hipEventRecord(c->tables_copied, s));
+    return CCR_OK;
+}
+
+
+// Launch shapes for a call: the tuned ones when autotuning is on (tuning on first use: the
+// first round of the call is timed for each candidate k_chunk and the fastest is kept).
+ccr_status choose_params(ccr_ctx *c, ccr_precision prec, int n_bands, const int *band_ids, void *const *rho_out,
+                         int out_on_device, int out_fp64, hipStream_t s, BatchParams &bp) {
+    bp = BatchParams();
+    bp.k_chunk = c->opt_k_chunk;
+    bp.template_batch = c->opt_template_batch;
+    if (!c->opt_autotune || c->opt_k_chunk > 0) return CCR_OK;
+    const std::vector<int> ids(band_ids, band_ids + n_bands);
+    for (const auto &t : c->tuned)
+        if (t.band_ids == ids && t.prec == (int)prec) {
+            bp.k_chunk = t.k_chunk;
+            bp.template_batch = t.template_batch;
+            return CCR_OK;
+        }
+    int64_t max_seg = 1;
+    for (int bi = 0; bi < n_bands; ++bi) max_seg = std::max<int64_t>(max_seg, get_band(c, band_ids[bi])->plan.n_seg);
+    const bool fp64 = prec == CCR_PREC_FP64;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    HIP_OK(c, hipEventCreate(&e0));
+    HIP_OK(c, hipEventCreate(&e1));
+    float best = -1.0f;
+    int64_t best_kc = 0;
+    ccr_status st = CCR_OK;
+    for (int64_t kc = 32; kc <= 1024; kc *= 2) {
+        if (kc > 2 * max_seg && kc > 32) break;
+        BatchParams cand = bp;
+        cand.k_chunk = kc;
+        CallPlan cp;
+        size_t items_off = 0;
+        if ((st = build_plan(c, fp64, n_bands, band_ids, rho_out, out_on_device, out_fp64, cand, cp))) break;
+        if ((st = ensure_workspace(c, cp))) break;
+        if ((st = upload_tables(c, cp, s, &items_off))) break;
+        // one untimed pass of the round, then the timed one
+        for (int rep = 0; rep < 2 && !st; ++rep) {
+            if (rep == 1 && hipEventRecord(e0, s) != hipSuccess) st = fail(c, CCR_EDEVICE, "event record failed");
+            if (!st) st = run_rounds(c, cp, 0, std::min<size_t>(1, cp.rounds.size()), fp64, c->d_tables.p, items_off, s, false);
+        }
+        if (st) break;
+        HIP_OK(c, hipEventRecord(e1, s));
+        HIP_OK(c, hipEventSynchronize(e1));
+        float ms = 0.0f;
+        HIP_OK(c, hipEventElapsedTime(&ms, e0, e1));
+        // normalise by the templates the first round covers
+        int64_t nt = 0;
+        if (!cp.rounds.empty())
+            for (int i = 0; i < cp.rounds[0].n; ++i) nt += cp.items[cp.rounds[0].i0 + i].n_tmpl;
+        const float per = ms / (float)std::max<int64_t>(nt, 1);
+        if (best < 0.0f || per < best) {
+            best = per;
+            best_kc = kc;
+        }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (st) return st;
+    bp.k_chunk = best_kc;
+    c->tuned.push_back({ids, (int)prec, bp.k_chunk, bp.template_batch});
+    c->last_tuned_k_chunk = bp.k_chunk;
+    c->last_tuned_template_batch = bp.template_batch;
+    return CCR_OK;
+}
+
+ccr_status compute_batched(ccr_ctx *c, ccr_precision prec, int n_bands, const int *band_ids, void *const *rho_out,
+                           int out_on_device, int out_fp64, hipStream_t s) {
+    const bool fp64 = prec == CCR_PREC_FP64;
+    ccr_status st;
+    BatchParams bp;
+    if ((st = choose_params(c, prec, n_bands, band_ids, rho_out, out_on_device, out_fp64, s, bp))) return st;
+    const bool graph = c->opt_graph && out_on_device;
+    if (graph) {
+        const std::vector<int> ids(band_ids, band_ids + n_bands);
+        const std::vector<void *> outs(rho_out, rho_out + n_bands);
+        for (auto &g : c->graphs)
+            if (g->band_ids == ids && g->outs == outs && g->prec == (int)prec && g->out_fp64 == out_fp64 &&
+                g->gen == c->gen) {
+                HIP_OK(c, hipGraphLaunch(g->exec, s));
+                return CCR_OK;
+            }
+    }
+    CallPlan cp;
+    if ((st = build_plan(c, fp64, n_bands, band_ids, rho_out, out_on_device, out_fp64, bp, cp))) return st;
+    if ((st = ensure_workspace(c, cp))) return st;
+    if (graph) {
+        // capture on the context's own stream (the caller's may be the null stream), replay on `s`
+        auto g = std::make_unique<ccr_ctx::GraphEntry>();
+        g->band_ids.assign(band_ids, band_ids + n_bands);
+        g->outs.assign(rho_out, rho_out + n_bands);
+        g->prec = (int)prec;
+        g->out_fp64 = out_fp64;
+        size_t items_off = 0;
+        const size_t bytes = tables_bytes(cp, &items_off);
+        std::vector<char> host(bytes);
+        fill_tables(cp, host.data(), items_off);
+        HIP_OK(c, hipMalloc(&g->tables, bytes));
+        HIP_OK(c, hipMemcpy(g->tables, host.data(), bytes, hipMemcpyHostToDevice));
+        HIP_OK(c, hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal));
+        st = run_rounds(c, cp, 0, cp.rounds.size(), fp64, g->tables, items_off, c->stream, false);
+        hipGraph_t gr = nullptr;
+        const hipError_t ec = hipStreamEndCapture(c->stream, &gr);
+        if (st) {
+            if (gr) (void)hipGraphDestroy(gr);
+            return st;
+        }
+        if (ec != hipSuccess) return fail(c, CCR_EDEVICE, "graph capture failed: %s", hipGetErrorString(ec));
+        g->graph = gr;
+        HIP_OK(c, hipGraphInstantiate(&g->exec, g->graph, nullptr, nullptr, 0));
+        g->gen = c->gen;
+        HIP_OK(c, hipGraphLaunch(g->exec, s));
+        // keep a handful of graphs; the oldest go first
+        if (c->graphs.size() >= 16) {
+            HIP_OK(c, hipDeviceSynchronize());
+            c->graphs.erase(c->graphs.begin());
+        }
+        c->graphs.push_back(std::move(g));
+        return CCR_OK;
+    }
+    size_t items_off = 0;
+    if ((st = upload_tables(c, cp, s, &items_off))) return st;
+    if ((st = run_rounds(c, cp, 0, cp.rounds.size(), fp64, c->d_tables.p, items_off, s, true))) return st;
+    if (!out_on_device) {
+        for (int bi = 0; bi < n_bands; ++bi) {
+            const Band &B = *get_band(c, band_ids[bi]);
+            const size_t bytes = (size_t)B.n_tmpl * B.plan.n_f * (out_fp64 ? sizeof(double) : sizeof(float));
+            HIP_OK(c, hipMemcpyAsync(rho_out[bi], c->ws_out.as<char>() + cp.out_off[bi], bytes, hipMemcpyDeviceToHost, s));
+        }
+        HIP_OK(c, hipStreamSynchronize(s));
+    }
+    return CCR_OK;
+}
+
 }  // namespace
 
 // ====================================================================== ABI
@@ -731,6 +1168,10 @@ void ccr_destroy(ccr_ctx *c) {
     c->ws_part.release();
     c->ws_out.release();
     c->ws_coef.release();
+    c->graphs.clear();
+    c->d_tables.release();
+    if (c->h_tables) (void)hipHostFree(c->h_tables);
+    if (c->tables_copied) (void)hipEventDestroy(c->tables_copied);
     if (c->stream) (void)hipStreamDestroy(c->stream);
     delete c;
 }
@@ -747,6 +1188,28 @@ ccr_status ccr_set_option(ccr_ctx *c, const char *name, int64_t value) {
     else if (k == "k_chunk") c->opt_k_chunk = value;
     else if (k == "fused") c->opt_fused = value;
     else if (k == "timing") c->opt_timing = value;
+    else if (k == "graph") c->opt_graph = value;
+    else if (k == "autotune") c->opt_autotune = value;
+    else if (k == "items_per_launch") c->opt_items_per_launch = value;
+    else return fail(c, CCR_EUNSUP, "unknown option '%s'", name);
+    if (k == "template_batch" || k == "workspace_mb" || k == "k_chunk" || k == "items_per_launch") c->gen++;
+    return CCR_OK;
+}
+
+ccr_status ccr_get_option(ccr_ctx *c, const char *name, int64_t *value) {
+    if (!c || !name || !value) return CCR_EINVAL;
+    c->err.clear();
+    std::string k(name);
+    if (k == "template_batch") *value = c->opt_template_batch;
+    else if (k == "workspace_mb") *value = c->opt_workspace_mb;
+    else if (k == "k_chunk") *value = c->opt_k_chunk;
+    else if (k == "fused") *value = c->opt_fused;
+    else if (k == "timing") *value = c->opt_timing;
+    else if (k == "graph") *value = c->opt_graph;
+    else if (k == "autotune") *value = c->opt_autotune;
+    else if (k == "items_per_launch") *value = c->opt_items_per_launch;
+    else if (k == "tuned_k_chunk") *value = c->last_tuned_k_chunk;
+    else if (k == "tuned_template_batch") *value = c->last_tuned_template_batch;
     else return fail(c, CCR_EUNSUP, "unknown option '%s'", name);
     return CCR_OK;
 }
@@ -940,68 +1403,25 @@ ccr_status ccr_compute_rho(ccr_ctx *c, ccr_precision prec, int n_bands, const in
         if (!rho_out[bi]) return fail(c, CCR_EINVAL, "null output for band %d", band_ids[bi]);
         if ((st = ensure_ready(c, *B))) return st;
     }
-    for (int bi = 0; bi < n_bands; ++bi) {
-        Band &B = *get_band(c, band_ids[bi]);
-        const Plan &pl = B.plan;
-        const BandDev bd = band_dev(B);
-        const int S = c->opt_fused ? fused_steps(bd, fp64, kMaxLds) : 0;
-        if (S > 0) {
-            if ((st = compute_fused(c, B, bd, fp64, S, rho_out[bi], out_on_device, out_fp64, s))) return st;
-            continue;
-        }
-        const bool sp = spectra_pairs_ok(bd, fp64, kMaxLds);
-        const int64_t tb = template_batch(c, B, fp64, sp);
-        const size_t cs = fp64 ? 16 : 8;
-        const int kc = k_chunk_for(c, pl);
-        const int nch = (int)((pl.n_seg + kc - 1) / kc);
-        HIP_OK(c, c->ws_y.ensure((size_t)tb * B.Q * pl.n_seg * pl.n_k * cs));
-        if (!sp) HIP_OK(c, c->ws_F.ensure((size_t)tb * B.Q * pl.n_seg * pl.n_f * cs));
-        HIP_OK(c, c->ws_part.ensure((size_t)tb * nch * pl.n_f * sizeof(double)));
-        HIP_OK(c, c->ws_coef.ensure((size_t)tb * std::max(B.n_work, 1) * kCheb * sizeof(double)));
-        const size_t osz = out_fp64 ? sizeof(double) : sizeof(float);
-        const size_t out_bytes = (size_t)B.n_tmpl * pl.n_f * osz;
-        void *dst = rho_out[bi];
-        if (!out_on_device) {
-            HIP_OK(c, c->ws_out.ensure(out_bytes));
-            dst = c->ws_out.p;
-        }
-        const double factor = pl.norm > 0.0 ? std::sqrt(2.0) / pl.norm : 0.0;
-        for (int64_t t = 0; t < B.n_tmpl; t += tb) {
-            const int nb = (int)std::min<int64_t>(tb, B.n_tmpl - t);
-            const double *dtm = B.d_tmpl.as<double>() + (size_t)t * kTmplStride;
-            {
-                LaunchTimer lt(c, 5, s);
-                HIP_OK(c, launch_timebase(bd, dtm, nb, c->ws_coef.as<double>(), s));
-            }
-            {
-                LaunchTimer lt(c, 0, s);
-                HIP_OK(c, launch_resample(bd, c->ws_coef.as<double>(), nb, fp64, c->ws_y.p, s));
-            }
-            if (sp) {
-                LaunchTimer lt(c, 6, s);
-                HIP_OK(c, launch_spectra_pairs(bd, nb, c->ws_y.p, c->ws_part.as<double>(), kc, nch, s));
+    if (c->opt_fused) {
+        // optional fused kernel, per band (bands it cannot hold use the batched path below)
+        std::vector<int> rest;
+        std::vector<void *> rest_out;
+        for (int bi = 0; bi < n_bands; ++bi) {
+            Band &B = *get_band(c, band_ids[bi]);
+            const BandDev bd = band_dev(B);
+            const int S = fused_steps(bd, fp64, kMaxLds);
+            if (S > 0) {
+                if ((st = compute_fused(c, B, bd, fp64, S, rho_out[bi], out_on_device, out_fp64, s))) return st;
             } else {
-                {
-                    LaunchTimer lt(c, 1, s);
-                    HIP_OK(c, launch_spectra(bd, nb, fp64, c->ws_y.p, c->ws_F.p, s));
-                }
-                {
-                    LaunchTimer lt(c, 2, s);
-                    HIP_OK(c, launch_pairsum(bd, nb, fp64, c->ws_F.p, c->ws_part.as<double>(), kc, nch, s));
-                }
-            }
-            {
-                LaunchTimer lt(c, 3, s);
-                HIP_OK(c, launch_finish(bd, nb, c->ws_part.as<double>(), nch, factor,
-                                        static_cast<char *>(dst) + (size_t)t * pl.n_f * osz, out_fp64 != 0, s));
+                rest.push_back(band_ids[bi]);
+                rest_out.push_back(rho_out[bi]);
             }
         }
-        if (!out_on_device) {
-            HIP_OK(c, hipMemcpyAsync(rho_out[bi], dst, out_bytes, hipMemcpyDeviceToHost, s));
-            HIP_OK(c, hipStreamSynchronize(s));
-        }
+        if (rest.empty()) return CCR_OK;
+        return compute_batched(c, prec, (int)rest.size(), rest.data(), rest_out.data(), out_on_device, out_fp64, s);
     }
-    return CCR_OK;
+    return compute_batched(c, prec, n_bands, band_ids, rho_out, out_on_device, out_fp64, s);
 }
 
 ccr_status ccr_kernel_time(ccr_ctx *c, int kernel, double *ms, int64_t *launches) {

@@ -69,7 +69,34 @@ struct BandDev {
     const int *work;          // [n_work] det * n_seg + K of active segments
     const int *seg_work;      // [Q][n_seg] position of (det, K) in `work`, -1 if inactive
     int n_work;
+    const double *tmpl;       // [n_templates][kTmplStride] template table
 };
+
+// One work item of a batched launch: a run of consecutive templates of one band.  A batched
+// launch covers a list of items of several bands; each stage's grid is the concatenation of
+// the items' grids (item i owns blocks [first[stage], next item's first[stage])).
+enum Stage { kStTimebase = 0, kStResample = 1, kStSpectra = 2, kStPairs = 3, kStFinish = 4, kStages = 5 };
+struct WorkItem {
+    int band;               // index into the launch's BandDev table
+    int n_tmpl;             // templates in the item
+    int k_chunk, n_chunks;  // segment chunks of the pair sums
+    int64_t tmpl_off;       // first template of the item (row of the band's template table)
+    int64_t coef_off;       // doubles into the time-base coefficient workspace
+    int64_t y_off;          // complex samples into the resampled-series workspace
+    int64_t F_off;          // complex values into the segment-spectra workspace
+    int64_t part_off;       // doubles into the chunk-partial workspace
+    void *out;              // rho of the item's first template: n_tmpl x n_f, f32 or f64
+    double factor;          // sqrt(2) / N
+    int out_fp64;
+    int first[kStages];     // first block of the item in each stage's grid
+    int gx[kStages];        // blocks per template along the stage's first dimension
+};
+
+// Block geometry shared by the host planner and the kernels.
+constexpr int kTbEntries = 16;       // time base: work entries per workgroup (x kCheb threads)
+constexpr int kSpec16Groups = 8;     // 256-point register FFT: segments per 128-thread workgroup
+constexpr int kPairsThreads = 128;   // pair sum: bins per workgroup
+constexpr int kFinishThreads = 256;  // finish: bins per workgroup
 
 // Launchers (ccr_kernels.hip).  All queue work on `stream` and return the launch status.
 // Chebyshev coefficients of the time base, coef[n_tmpl][n_work][kCheb].
@@ -94,6 +121,26 @@ hipError_t launch_spectra_pairs(const BandDev &B, int n_tmpl, const void *y, dou
                                 int n_chunks, hipStream_t stream);
 hipError_t launch_finish(const BandDev &B, int n_tmpl, const double *part, int n_chunks,
                          double factor, void *out, bool out_fp64, hipStream_t stream);
+
+// Batched launches: `blocks` = total blocks of the stage over the items; bands and items are
+// device tables.  Every item of one launch shares the kernel variant chosen by the arguments.
+size_t spectra_pairs_lds(const BandDev &B);
+int spectra_pairs_rounds(const BandDev &B);  // bins per lane of the spectra+pairs kernel (3 or 8)
+int spectra_threads(int n_s);               // threads of the LDS Stockham FFT workgroup
+hipError_t launch_timebase_m(const BandDev *bands, const WorkItem *items, int n_items, int blocks, double *coef,
+                             hipStream_t stream);
+hipError_t launch_resample_m(const BandDev *bands, const WorkItem *items, int n_items, int blocks, bool fp64, int D,
+                             int window, const double *coef, void *y, hipStream_t stream);
+hipError_t launch_spectra_pairs_m(const BandDev *bands, const WorkItem *items, int n_items, int blocks, int rounds,
+                                  size_t lds, const void *y, double *part, hipStream_t stream);
+// reg16: the 256-point register FFT (split precision, distinct bins); else the LDS Stockham FFT
+// with `threads` threads and 2 n_s complex values of LDS.
+hipError_t launch_spectra_m(const BandDev *bands, const WorkItem *items, int n_items, int blocks, bool fp64,
+                            bool reg16, int threads, int n_s, const void *y, void *F, hipStream_t stream);
+hipError_t launch_pairs_m(const BandDev *bands, const WorkItem *items, int n_items, int blocks, bool fp64,
+                          const void *F, double *part, hipStream_t stream);
+hipError_t launch_finish_m(const BandDev *bands, const WorkItem *items, int n_items, int blocks, const double *part,
+                           hipStream_t stream);
 hipError_t launch_zero(void *p, size_t bytes, hipStream_t stream);
 
 }  // namespace ccr

@@ -129,14 +129,11 @@ __device__ __forceinline__ void sample_time(const double *coef, double x, const 
 // Time base kernel: one thread per (template, active segment entry, Chebyshev node).  Writes the
 // kCheb coefficients of eta(u) for every (template, entry): coef[tb][entry][k].  16 entries x
 // kCheb nodes per workgroup; node values meet in LDS for the coefficient transform.
-constexpr int kTbEntries = 16;
-
-__global__ void __launch_bounds__(kTbEntries * kCheb) k_timebase(BandDev B, const double *tmpl, double *coef) {
+__device__ __forceinline__ void timebase_body(const BandDev &B, const double *tmpl, double *coef, int bx, int tb) {
     __shared__ double sh_eta[kTbEntries * kCheb];
     const int le = threadIdx.x / kCheb;           // entry within the workgroup
     const int j = threadIdx.x - le * kCheb;       // node (and later coefficient) index
-    const int w = blockIdx.x * kTbEntries + le;   // entry in the work list
-    const int tb = blockIdx.y;
+    const int w = bx * kTbEntries + le;           // entry in the work list
     const bool on = w < B.n_work;
     if (on) {
         const int entry = B.work[w];
@@ -150,6 +147,10 @@ __global__ void __launch_bounds__(kTbEntries * kCheb) k_timebase(BandDev B, cons
     }
     __syncthreads();
     if (on) coef[((size_t)tb * B.n_work + w) * kCheb + j] = cheb_coef(sh_eta + le * kCheb, B.cheb_T, j);
+}
+
+__global__ void __launch_bounds__(kTbEntries * kCheb) k_timebase(BandDev B, const double *tmpl, double *coef) {
+    timebase_body(B, tmpl, coef, blockIdx.x, blockIdx.y);
 }
 
 // ------------------------------------------------------------------ resampling
@@ -311,9 +312,7 @@ __device__ __forceinline__ c2<T> interpolate_window(const BandDev &B, const floa
 // Resampler: one 64-thread workgroup per (template, active segment), looping over the segment's
 // samples; the segment's Chebyshev coefficients and anchor are uniform (scalar loads).
 template <typename T, int DT, int WIN>
-__global__ void __launch_bounds__(64) k_resample(BandDev B, const double *coef, c2<T> *y) {
-    const int w = blockIdx.x;
-    const int tb = blockIdx.y;
+__device__ __forceinline__ void resample_body(const BandDev &B, const double *coef, c2<T> *y, int w, int tb) {
     const int entry = B.work[w];
     const int det = entry / B.n_seg;
     const int K = entry - det * B.n_seg;
@@ -343,6 +342,11 @@ __global__ void __launch_bounds__(64) k_resample(BandDev B, const double *coef, 
         sincos_rev<T>(psi, sn, c);
         yo[s] = mk<T>(c * acc.x - sn * acc.y, sn * acc.x + c * acc.y);
     }
+}
+
+template <typename T, int DT, int WIN>
+__global__ void __launch_bounds__(64) k_resample(BandDev B, const double *coef, c2<T> *y) {
+    resample_body<T, DT, WIN>(B, coef, y, blockIdx.x, blockIdx.y);
 }
 
 // v mod N_FFT for 0 <= v (a mask when N_FFT is a power of two).
@@ -482,12 +486,10 @@ __device__ __forceinline__ void fft256_lanes(c2<T> *v, int t, c2<T> *sc, const c
 // twiddle the zero-padded segment by exp(-2 pi i p s / N_FFT), FFT in registers, and write the
 // decimated bins kbar = m P + p with Phi_in and 1 / (sigma sqrt N_K).
 template <typename T>
-__global__ void __launch_bounds__(128) __attribute__((amdgpu_waves_per_eu(3)))
-k_spectra16(BandDev B, const c2<T> *y, c2<T> *F) {
+__device__ __forceinline__ void spectra16_body(const BandDev &B, const c2<T> *y, c2<T> *F, int bx, int tb) {
     __shared__ c2<T> sc_all[8 * 16 * 17];
     const int grp = threadIdx.x >> 4, t = threadIdx.x & 15;
-    const int w = blockIdx.x * 8 + grp;
-    const int tb = blockIdx.y;
+    const int w = bx * 8 + grp;
     const bool on = w < B.n_work;
     const int entry = on ? B.work[w] : 0;
     const int det = entry / B.n_seg;
@@ -519,6 +521,12 @@ k_spectra16(BandDev B, const c2<T> *y, c2<T> *F) {
             }
         }
     }
+}
+
+template <typename T>
+__global__ void __launch_bounds__(128) __attribute__((amdgpu_waves_per_eu(3)))
+k_spectra16(BandDev B, const c2<T> *y, c2<T> *F) {
+    spectra16_body<T>(B, y, F, blockIdx.x, blockIdx.y);
 }
 
 // Spectra + pair sum for 256-point segments (split precision, distinct bins): one wavefront =
@@ -559,8 +567,8 @@ __host__ __device__ inline SpairLayout spair_layout(int Q, int n_f, int R, int n
 }
 
 template <int NR>
-__global__ void __launch_bounds__(64) k_spectra_pairs16(BandDev B, const float2 *y, double *part, int k_chunk,
-                                                       int n_chunks) {
+__device__ __forceinline__ void spectra_pairs_body(const BandDev &B, const float2 *y, double *part, int k_chunk,
+                                                   int n_chunks, int c, int tb) {
     extern __shared__ __align__(16) unsigned char smem[];
     const int Q = B.Q, n_f = B.n_f, n_k = B.n_k, P = B.P;
     const SpairLayout Ly = spair_layout(Q, n_f, B.R, B.n_fft);
@@ -571,7 +579,6 @@ __global__ void __launch_bounds__(64) k_spectra_pairs16(BandDev B, const float2 
     int16_t *opos = reinterpret_cast<int16_t *>(smem + Ly.off_pos);
     const int lane = threadIdx.x;
     const int grp = lane >> 4, t = lane & 15;
-    const int c = blockIdx.x, tb = blockIdx.y;
     const int K0 = c * k_chunk;
     const int K1 = min(B.n_seg, K0 + k_chunk);
     const int Kh = max(0, K0 - B.R);
@@ -712,18 +719,23 @@ __global__ void __launch_bounds__(64) k_spectra_pairs16(BandDev B, const float2 
     }
 }
 
+template <int NR>
+__global__ void __launch_bounds__(64) k_spectra_pairs16(BandDev B, const float2 *y, double *part, int k_chunk,
+                                                       int n_chunks) {
+    spectra_pairs_body<NR>(B, y, part, k_chunk, n_chunks, blockIdx.x, blockIdx.y);
+}
+
 // The fused kernel keeps the activity bits of a step (S segments x Q detectors) in 64 bits.
 __host__ __device__ inline bool Q_ok(const BandDev &B) { return B.Q >= 1 && B.Q * 4 <= 64; }
 
 template <typename T>
-__global__ void __launch_bounds__(256) k_spectra(BandDev B, const c2<T> *y, c2<T> *F) {
+__device__ __forceinline__ void spectra_body(const BandDev &B, const c2<T> *y, c2<T> *F, int w, int tb) {
     extern __shared__ __align__(16) unsigned char smem[];
     c2<T> *buf0 = reinterpret_cast<c2<T> *>(smem);
     c2<T> *buf1 = buf0 + B.n_s;
-    const int entry = B.work[blockIdx.x];
+    const int entry = B.work[w];
     const int det = entry / B.n_seg;
     const int K = entry - det * B.n_seg;
-    const int tb = blockIdx.y;
     const int64_t nr = (int64_t)B.n_seg * B.n_k;
     const c2<T> *ys = y + ((size_t)tb * B.Q + det) * nr + (size_t)K * B.n_k;
     const c2<T> *tw = twiddles<T>(B);
@@ -750,6 +762,11 @@ __global__ void __launch_bounds__(256) k_spectra(BandDev B, const c2<T> *y, c2<T
     }
 }
 
+template <typename T>
+__global__ void __launch_bounds__(256) k_spectra(BandDev B, const c2<T> *y, c2<T> *F) {
+    spectra_body<T>(B, y, F, blockIdx.x, blockIdx.y);
+}
+
 // ------------------------------------------------------------------ pair sum
 
 // Partial rho of one (template, bin, chunk of segments): for each segment K and detector X,
@@ -757,11 +774,9 @@ __global__ void __launch_bounds__(256) k_spectra(BandDev B, const c2<T> *y, c2<T
 // [K - R, K - 1] (other detectors if cross pairs, the same detector if same pairs) and
 // L = K with Y > X (cross pairs) -- so each unordered pair of the set enters once.
 template <typename T>
-__global__ void __launch_bounds__(256) k_pairs(BandDev B, const c2<T> *F, double *part, int k_chunk,
-                                               int n_chunks) {
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    const int c = blockIdx.y;
-    const int tb = blockIdx.z;
+__device__ __forceinline__ void pairs_body(const BandDev &B, const c2<T> *F, double *part, int k_chunk, int n_chunks,
+                                           int bx, int c, int tb) {
+    const int i = bx * blockDim.x + threadIdx.x;
     if (i >= B.n_f) return;
     const bool cross = (B.pairs & 1) != 0, same = (B.pairs & 2) != 0;
     const c2<T> *Ft = F + (size_t)tb * B.Q * B.n_seg * B.n_f;
@@ -791,6 +806,12 @@ __global__ void __launch_bounds__(256) k_pairs(BandDev B, const c2<T> *F, double
         }
     }
     part[((size_t)tb * n_chunks + c) * B.n_f + i] = acc;
+}
+
+template <typename T>
+__global__ void __launch_bounds__(256) k_pairs(BandDev B, const c2<T> *F, double *part, int k_chunk,
+                                               int n_chunks) {
+    pairs_body<T>(B, F, part, k_chunk, n_chunks, blockIdx.x, blockIdx.y, blockIdx.z);
 }
 
 // ------------------------------------------------------------------ fused path
@@ -1039,10 +1060,9 @@ __global__ void __launch_bounds__(256) k_fused(BandDev B, const double *coef, co
     for (int i = tid; i < n_f; i += nth) part[((size_t)tb * n_chunks + c) * n_f + i] = acc[i];
 }
 
-__global__ void k_finish(int n_f, int n_tmpl, const double *part, int n_chunks, double factor,
-                         void *out, int out_fp64) {
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    const int t = blockIdx.y;
+__device__ __forceinline__ void finish_body(int n_f, int n_tmpl, const double *part, int n_chunks, double factor,
+                                            void *out, int out_fp64, int bx, int t) {
+    const int i = bx * blockDim.x + threadIdx.x;
     if (i >= n_f || t >= n_tmpl) return;
     double s = 0.0;
     for (int c = 0; c < n_chunks; ++c) s += part[((size_t)t * n_chunks + c) * n_f + i];
@@ -1053,10 +1073,135 @@ __global__ void k_finish(int n_f, int n_tmpl, const double *part, int n_chunks, 
         static_cast<float *>(out)[(size_t)t * n_f + i] = (float)s;
 }
 
+__global__ void k_finish(int n_f, int n_tmpl, const double *part, int n_chunks, double factor,
+                         void *out, int out_fp64) {
+    finish_body(n_f, n_tmpl, part, n_chunks, factor, out, out_fp64, blockIdx.x, blockIdx.y);
+}
+
 __global__ void k_zero(uint32_t *p, size_t n_words) {
     for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n_words;
          i += (size_t)gridDim.x * blockDim.x)
         p[i] = 0u;
+}
+
+// ------------------------------------------------------------------ batched launches
+
+// Pointers loaded from a device table are generic, and loads through generic pointers are
+// slower than global loads (and hold more registers).  as_global() re-derives such a pointer
+// from `base`, a kernel argument in global memory, as base + (p - base): the same 64-bit
+// address, now known to the compiler to be global memory.
+typedef __attribute__((address_space(1))) char gchar;
+template <typename T> __device__ __forceinline__ T *as_global(T *p, const gchar *base) {
+    const gchar *q = base + ((const char *)p - (const char *)base);
+    return (T *)q;
+}
+
+// A copy of a band descriptor from the device band table with every pointer re-derived as a
+// global-memory pointer.
+__device__ __forceinline__ BandDev global_view(const BandDev &b, const void *base_) {
+    const gchar *base = (const gchar *)base_;
+    BandDev g = b;
+    g.x = as_global(b.x, base);
+    g.mask = as_global(b.mask, base);
+    g.anchors = as_global(b.anchors, base);
+    g.earth = as_global(b.earth, base);
+    g.win64 = as_global(b.win64, base);
+    g.win32 = as_global(b.win32, base);
+    g.cheb_x = as_global(b.cheb_x, base);
+    g.cheb_T = as_global(b.cheb_T, base);
+    g.tw64 = as_global(b.tw64, base);
+    g.tw32 = as_global(b.tw32, base);
+    g.bin_m = as_global(b.bin_m, base);
+    g.bin_p = as_global(b.bin_p, base);
+    g.bin_kb = as_global(b.bin_kb, base);
+    g.bin_pos = as_global(b.bin_pos, base);
+    g.segw = as_global(b.segw, base);
+    g.active = as_global(b.active, base);
+    g.work = as_global(b.work, base);
+    g.seg_work = as_global(b.seg_work, base);
+    g.tmpl = as_global(b.tmpl, base);
+    return g;
+}
+
+// The item owning block b of a stage: the last item whose first block is <= b.
+__device__ __forceinline__ int find_item(const WorkItem *__restrict__ items, int n_items, int stage, int b) {
+    int lo = 0, hi = n_items - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (items[mid].first[stage] <= b) lo = mid;
+        else hi = mid - 1;
+    }
+    return lo;
+}
+
+__global__ void __launch_bounds__(kTbEntries * kCheb)
+k_timebase_m(const BandDev *__restrict__ bands, const WorkItem *__restrict__ items, int n_items, double *__restrict__ coef) {
+    const WorkItem &it = items[find_item(items, n_items, kStTimebase, blockIdx.x)];
+    const BandDev B = global_view(bands[it.band], bands);
+    const int l = blockIdx.x - it.first[kStTimebase], gx = it.gx[kStTimebase];
+    timebase_body(B, B.tmpl + (size_t)it.tmpl_off * kTmplStride, coef + it.coef_off, l % gx, l / gx);
+}
+
+template <typename T, int DT, int WIN>
+__global__ void __launch_bounds__(64)
+k_resample_m(const BandDev *__restrict__ bands, const WorkItem *__restrict__ items, int n_items,
+             const double *__restrict__ coef, c2<T> *__restrict__ y) {
+    const WorkItem &it = items[find_item(items, n_items, kStResample, blockIdx.x)];
+    const BandDev B = global_view(bands[it.band], bands);
+    const int l = blockIdx.x - it.first[kStResample], gx = it.gx[kStResample];
+    resample_body<T, DT, WIN>(B, coef + it.coef_off, y + it.y_off, l % gx, l / gx);
+}
+
+template <int NR>
+__global__ void __launch_bounds__(64)
+k_spectra_pairs_m(const BandDev *__restrict__ bands, const WorkItem *__restrict__ items, int n_items,
+                  const float2 *__restrict__ y, double *__restrict__ part) {
+    const WorkItem &it = items[find_item(items, n_items, kStSpectra, blockIdx.x)];
+    const BandDev B = global_view(bands[it.band], bands);
+    const int l = blockIdx.x - it.first[kStSpectra], gx = it.gx[kStSpectra];
+    spectra_pairs_body<NR>(B, y + it.y_off, part + it.part_off, it.k_chunk, it.n_chunks, l % gx, l / gx);
+}
+
+template <typename T>
+__global__ void __launch_bounds__(128) __attribute__((amdgpu_waves_per_eu(3)))
+k_spectra16_m(const BandDev *__restrict__ bands, const WorkItem *__restrict__ items, int n_items,
+              const c2<T> *__restrict__ y, c2<T> *__restrict__ F) {
+    const WorkItem &it = items[find_item(items, n_items, kStSpectra, blockIdx.x)];
+    const BandDev B = global_view(bands[it.band], bands);
+    const int l = blockIdx.x - it.first[kStSpectra], gx = it.gx[kStSpectra];
+    spectra16_body<T>(B, y + it.y_off, F + it.F_off, l % gx, l / gx);
+}
+
+template <typename T>
+__global__ void __launch_bounds__(256)
+k_spectra_m(const BandDev *__restrict__ bands, const WorkItem *__restrict__ items, int n_items,
+            const c2<T> *__restrict__ y, c2<T> *__restrict__ F) {
+    const WorkItem &it = items[find_item(items, n_items, kStSpectra, blockIdx.x)];
+    const BandDev B = global_view(bands[it.band], bands);
+    const int l = blockIdx.x - it.first[kStSpectra], gx = it.gx[kStSpectra];
+    spectra_body<T>(B, y + it.y_off, F + it.F_off, l % gx, l / gx);
+}
+
+template <typename T>
+__global__ void __launch_bounds__(kPairsThreads)
+k_pairs_m(const BandDev *__restrict__ bands, const WorkItem *__restrict__ items, int n_items,
+          const c2<T> *__restrict__ F, double *__restrict__ part) {
+    const WorkItem &it = items[find_item(items, n_items, kStPairs, blockIdx.x)];
+    const BandDev B = global_view(bands[it.band], bands);
+    const int l = blockIdx.x - it.first[kStPairs], gx = it.gx[kStPairs];
+    const int bx = l % gx, rest = l / gx;
+    pairs_body<T>(B, F + it.F_off, part + it.part_off, it.k_chunk, it.n_chunks, bx, rest % it.n_chunks,
+                  rest / it.n_chunks);
+}
+
+__global__ void __launch_bounds__(kFinishThreads)
+k_finish_m(const BandDev *__restrict__ bands, const WorkItem *__restrict__ items, int n_items,
+           const double *__restrict__ part) {
+    const WorkItem &it = items[find_item(items, n_items, kStFinish, blockIdx.x)];
+    const BandDev B = global_view(bands[it.band], bands);
+    const int l = blockIdx.x - it.first[kStFinish], gx = it.gx[kStFinish];
+    finish_body(B.n_f, it.n_tmpl, part + it.part_off, it.n_chunks, it.factor, as_global(it.out, (const gchar *)part),
+                it.out_fp64, l % gx, l / gx);
 }
 
 }  // namespace
@@ -1099,8 +1244,7 @@ hipError_t launch_spectra(const BandDev &B, int n_tmpl, bool fp64, const void *y
         hipLaunchKernelGGL(k_spectra16<float>, grid, block, 0, stream, B, (const float2 *)y, (float2 *)F);
         return hipGetLastError();
     }
-    const int threads = B.n_s / 4 >= 256 ? 256 : (B.n_s / 4 < 64 ? 64 : B.n_s / 4);
-    dim3 grid(B.n_work, n_tmpl), block(threads);
+    dim3 grid(B.n_work, n_tmpl), block(spectra_threads(B.n_s));
     const size_t lds = 2 * (size_t)B.n_s * (fp64 ? sizeof(double2) : sizeof(float2));
     if (fp64)
         hipLaunchKernelGGL(k_spectra<double>, grid, block, lds, stream, B, (const double2 *)y, (double2 *)F);
@@ -1186,6 +1330,95 @@ hipError_t launch_zero(void *p, size_t bytes, hipStream_t stream) {
     const size_t words = bytes / 4;
     const unsigned blocks = (unsigned)((words + 255) / 256 < 4096 ? (words + 255) / 256 : 4096);
     hipLaunchKernelGGL(k_zero, dim3(blocks), dim3(256), 0, stream, (uint32_t *)p, words);
+    return hipGetLastError();
+}
+
+
+// ------------------------------------------------------------------ batched launchers
+
+size_t spectra_pairs_lds(const BandDev &B) { return spair_layout(B.Q, B.n_f, B.R, B.n_fft).total; }
+
+int spectra_pairs_rounds(const BandDev &B) { return B.n_f <= 64 * 3 ? 3 : kSpairMaxRounds; }
+
+int spectra_threads(int n_s) { return n_s / 4 >= 256 ? 256 : (n_s / 4 < 64 ? 64 : n_s / 4); }
+
+hipError_t launch_timebase_m(const BandDev *bands, const WorkItem *items, int n_items, int blocks, double *coef,
+                             hipStream_t stream) {
+    if (blocks == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_timebase_m, dim3(blocks), dim3(kTbEntries * kCheb), 0, stream, bands, items, n_items, coef);
+    return hipGetLastError();
+}
+
+template <typename T, int DT>
+static void launch_resample_m_t(const BandDev *bands, const WorkItem *items, int n_items, int blocks, int window,
+                                const double *coef, void *y, hipStream_t stream) {
+    if (window == 0)
+        hipLaunchKernelGGL((k_resample_m<T, DT, 0>), dim3(blocks), dim3(64), 0, stream, bands, items, n_items, coef,
+                           (c2<T> *)y);
+    else
+        hipLaunchKernelGGL((k_resample_m<T, DT, 1>), dim3(blocks), dim3(64), 0, stream, bands, items, n_items, coef,
+                           (c2<T> *)y);
+}
+
+hipError_t launch_resample_m(const BandDev *bands, const WorkItem *items, int n_items, int blocks, bool fp64, int D,
+                             int window, const double *coef, void *y, hipStream_t stream) {
+    if (blocks == 0) return hipSuccess;
+    if (fp64) {
+        if (D == 8) launch_resample_m_t<double, 8>(bands, items, n_items, blocks, window, coef, y, stream);
+        else launch_resample_m_t<double, 0>(bands, items, n_items, blocks, window, coef, y, stream);
+    } else {
+        if (D == 8) launch_resample_m_t<float, 8>(bands, items, n_items, blocks, window, coef, y, stream);
+        else launch_resample_m_t<float, 0>(bands, items, n_items, blocks, window, coef, y, stream);
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_spectra_pairs_m(const BandDev *bands, const WorkItem *items, int n_items, int blocks, int rounds,
+                                  size_t lds, const void *y, double *part, hipStream_t stream) {
+    if (blocks == 0) return hipSuccess;
+    if (rounds == 3)
+        hipLaunchKernelGGL(k_spectra_pairs_m<3>, dim3(blocks), dim3(64), lds, stream, bands, items, n_items,
+                           (const float2 *)y, part);
+    else
+        hipLaunchKernelGGL(k_spectra_pairs_m<kSpairMaxRounds>, dim3(blocks), dim3(64), lds, stream, bands, items,
+                           n_items, (const float2 *)y, part);
+    return hipGetLastError();
+}
+
+hipError_t launch_spectra_m(const BandDev *bands, const WorkItem *items, int n_items, int blocks, bool fp64,
+                            bool reg16, int threads, int n_s, const void *y, void *F, hipStream_t stream) {
+    if (blocks == 0) return hipSuccess;
+    if (reg16 && !fp64) {
+        hipLaunchKernelGGL(k_spectra16_m<float>, dim3(blocks), dim3(16 * kSpec16Groups), 0, stream, bands, items,
+                           n_items, (const float2 *)y, (float2 *)F);
+        return hipGetLastError();
+    }
+    const size_t lds = 2 * (size_t)n_s * (fp64 ? sizeof(double2) : sizeof(float2));
+    if (fp64)
+        hipLaunchKernelGGL(k_spectra_m<double>, dim3(blocks), dim3(threads), lds, stream, bands, items, n_items,
+                           (const double2 *)y, (double2 *)F);
+    else
+        hipLaunchKernelGGL(k_spectra_m<float>, dim3(blocks), dim3(threads), lds, stream, bands, items, n_items,
+                           (const float2 *)y, (float2 *)F);
+    return hipGetLastError();
+}
+
+hipError_t launch_pairs_m(const BandDev *bands, const WorkItem *items, int n_items, int blocks, bool fp64,
+                          const void *F, double *part, hipStream_t stream) {
+    if (blocks == 0) return hipSuccess;
+    if (fp64)
+        hipLaunchKernelGGL(k_pairs_m<double>, dim3(blocks), dim3(kPairsThreads), 0, stream, bands, items, n_items,
+                           (const double2 *)F, part);
+    else
+        hipLaunchKernelGGL(k_pairs_m<float>, dim3(blocks), dim3(kPairsThreads), 0, stream, bands, items, n_items,
+                           (const float2 *)F, part);
+    return hipGetLastError();
+}
+
+hipError_t launch_finish_m(const BandDev *bands, const WorkItem *items, int n_items, int blocks, const double *part,
+                           hipStream_t stream) {
+    if (blocks == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_finish_m, dim3(blocks), dim3(kFinishThreads), 0, stream, bands, items, n_items, part);
     return hipGetLastError();
 }
 
