@@ -221,6 +221,14 @@ ccr_status ccr_resample_series(ccr_ctx *ctx, ccr_precision prec, int band_id,
                                int64_t template_index, int det, void *y_out);
 ccr_status ccr_segment_spectra(ccr_ctx *ctx, ccr_precision prec, int band_id,
                                int64_t template_index, void *f_out);
+/* ccr_time_base: step 1 for every source sample r of segments [k0, k0 + n_seg_out) of
+ *   detector det (active segments only; others are left untouched), as the resampler uses it:
+ *   eta_out[r - k0 n_k] = eta_r (s) with the delay Delta_r = t_r - tau_r = eta_r - anchor_out[K - k0],
+ *   anchor_out (n_seg_out doubles, may be NULL) = the segment's anchor offset D_a (s), and
+ *   psi_out[r - k0 n_k] (may be NULL) = frac(f_het Delta_r) (cycles), the heterodyne phase.
+ *   Host buffers of n_seg_out * n_k doubles (anchor_out: n_seg_out). */
+ccr_status ccr_time_base(ccr_ctx *ctx, int band_id, int64_t template_index, int det, int64_t k0,
+                         int64_t n_seg_out, double *eta_out, double *anchor_out, double *psi_out);
 
 #ifdef __cplusplus
 }

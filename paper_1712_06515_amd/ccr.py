@@ -77,6 +77,8 @@ SIGNATURES = {
     "ccr_reset_kernel_times": ([_vp], ctypes.c_int),
     "ccr_resample_series": ([_vp, ctypes.c_int, ctypes.c_int, ctypes.c_int64, ctypes.c_int, _vp], ctypes.c_int),
     "ccr_segment_spectra": ([_vp, ctypes.c_int, ctypes.c_int, ctypes.c_int64, _vp], ctypes.c_int),
+    "ccr_time_base": ([_vp, ctypes.c_int, ctypes.c_int64, ctypes.c_int, ctypes.c_int64, ctypes.c_int64, _dp, _dp, _dp],
+                      ctypes.c_int),
 }
 
 _lib = None
@@ -228,6 +230,18 @@ class Context:
         self._check(self.L.ccr_resample_series(self.h, int(prec), band_id, int(template_index), int(det),
                                                out.ctypes.data))
         return out
+
+    def time_base(self, band_id, template_index, det, k0=0, n_seg=None):
+        """(eta [n_seg, n_k], anchor D_a [n_seg], psi [n_seg, n_k]) of segments k0.. of one
+        detector: the delay of sample r is eta - D_a (NaN rows: segments not computed)."""
+        info = self.band_info(band_id)
+        n = info["n_seg"] - k0 if n_seg is None else n_seg
+        eta = np.full((n, info["n_k"]), np.nan)
+        psi = np.full((n, info["n_k"]), np.nan)
+        anc = np.zeros(n)
+        self._check(self.L.ccr_time_base(self.h, band_id, int(template_index), int(det), int(k0), int(n),
+                                         eta.ctypes.data_as(_dp), anc.ctypes.data_as(_dp), psi.ctypes.data_as(_dp)))
+        return eta, anc, psi
 
     def segment_spectra(self, band_id, template_index, prec=PREC_FP64):
         info = self.band_info(band_id)

@@ -1482,6 +1482,44 @@ ccr_status ccr_resample_series(ccr_ctx *c, ccr_precision prec, int band_id, int6
     return CCR_OK;
 }
 
+ccr_status ccr_time_base(ccr_ctx *c, int band_id, int64_t template_index, int det, int64_t k0, int64_t n_seg_out,
+                         double *eta_out, double *anchor_out, double *psi_out) {
+    if (!c) return CCR_EINVAL;
+    c->err.clear();
+    Band *B = get_band(c, band_id);
+    if (!B || !eta_out) return fail(c, CCR_EINVAL, "bad band id or null output");
+    if (c->device < 0) return fail(c, CCR_EDEVICE, "host-only context");
+    HIP_OK(c, hipSetDevice(c->device));
+    ccr_status st = ensure_ready(c, *B);
+    if (st) return st;
+    if (template_index < 0 || template_index >= B->n_tmpl) return fail(c, CCR_EINVAL, "template index out of range");
+    if (det < 0 || det >= B->Q) return fail(c, CCR_EINVAL, "detector index out of range");
+    const Plan &pl = B->plan;
+    if (k0 < 0 || n_seg_out < 1 || k0 + n_seg_out > pl.n_seg) return fail(c, CCR_EINVAL, "segment range out of range");
+    const size_t ns = (size_t)n_seg_out * pl.n_k;
+    DevBuf cf, de, dp;
+    HIP_OK(c, cf.ensure((size_t)std::max(B->n_work, 1) * kCheb * sizeof(double)));
+    HIP_OK(c, de.ensure(ns * sizeof(double)));
+    HIP_OK(c, dp.ensure(ns * sizeof(double)));
+    hipStream_t s = c->stream;
+    HIP_OK(c, hipMemcpyAsync(de.p, eta_out, ns * sizeof(double), hipMemcpyHostToDevice, s));
+    if (psi_out) HIP_OK(c, hipMemcpyAsync(dp.p, psi_out, ns * sizeof(double), hipMemcpyHostToDevice, s));
+    const BandDev bd = band_dev(*B);
+    HIP_OK(c, launch_timebase(bd, B->d_tmpl.as<double>() + (size_t)template_index * kTmplStride, 1, cf.as<double>(), s));
+    HIP_OK(c, launch_time_samples(bd, cf.as<double>(), det, (int)k0, (int)n_seg_out, de.as<double>(), dp.as<double>(), s));
+    HIP_OK(c, hipMemcpyAsync(eta_out, de.p, ns * sizeof(double), hipMemcpyDeviceToHost, s));
+    if (psi_out) HIP_OK(c, hipMemcpyAsync(psi_out, dp.p, ns * sizeof(double), hipMemcpyDeviceToHost, s));
+    HIP_OK(c, hipStreamSynchronize(s));
+    if (anchor_out) {
+        // the anchors as the device holds them
+        std::vector<Anchor> an((size_t)n_seg_out);
+        HIP_OK(c, hipMemcpy(an.data(), B->d_anchor.as<Anchor>() + (size_t)det * pl.n_seg + k0,
+                            an.size() * sizeof(Anchor), hipMemcpyDeviceToHost));
+        for (int64_t k = 0; k < n_seg_out; ++k) anchor_out[k] = an[(size_t)k].D_a;
+    }
+    return CCR_OK;
+}
+
 ccr_status ccr_segment_spectra(ccr_ctx *c, ccr_precision prec, int band_id, int64_t template_index, void *f_out) {
     if (!c) return CCR_EINVAL;
     c->err.clear();

@@ -142,5 +142,9 @@ hipError_t launch_pairs_m(const BandDev *bands, const WorkItem *items, int n_ite
 hipError_t launch_finish_m(const BandDev *bands, const WorkItem *items, int n_items, int blocks, const double *part,
                            hipStream_t stream);
 hipError_t launch_zero(void *p, size_t bytes, hipStream_t stream);
+// eta and the heterodyne phase of every sample of active segments [k0, k0 + n) of one detector
+// (one template, coefficients from launch_timebase): eta[(K - k0) n_k + s], psi likewise.
+hipError_t launch_time_samples(const BandDev &B, const double *coef, int det, int k0, int n, double *eta,
+                               double *psi, hipStream_t stream);
 
 }  // namespace ccr

@@ -50,6 +50,9 @@ __device__ __forceinline__ void sincos_small(double x, double &s, double &cm1) {
 // Binary orbital phase (cycles in [0,1)) of segment K's mid-time: frac(c0 + K c1), both in
 // double-double, then (sin, cos) of 2 pi times it.
 __device__ __forceinline__ void binary_anchor(const double *tp, int K, double &sb, double &cb) {
+    // The product error eA must be added once: contraction of A - floor(A) into an FMA would
+    // fold it in a second time (an error of up to half an ulp of K c1, growing with K).
+#pragma clang fp contract(off)
     const double kd = (double)K;
     const double A = kd * tp[4];
     const double eA = fma(kd, tp[4], -A);
@@ -347,6 +350,33 @@ __device__ __forceinline__ void resample_body(const BandDev &B, const double *co
 template <typename T, int DT, int WIN>
 __global__ void __launch_bounds__(64) k_resample(BandDev B, const double *coef, c2<T> *y) {
     resample_body<T, DT, WIN>(B, coef, y, blockIdx.x, blockIdx.y);
+}
+
+// Time base samples of one detector's segments [k0, k0 + n) for one template (stage output).
+__global__ void __launch_bounds__(64) k_time_samples(BandDev B, const double *coef, int det, int k0, int n,
+                                                     double *eta, double *psi) {
+    const int K = k0 + (int)blockIdx.x;
+    if ((int)blockIdx.x >= n) return;
+    const int w = B.seg_work[det * B.n_seg + K];
+    if (w < 0) return;
+    const Anchor an = B.anchors[det * B.n_seg + K];
+    const double *cf = coef + (size_t)w * kCheb;
+    const double inv_nk = 1.0 / (double)B.n_k;
+    for (int s = threadIdx.x; s < B.n_k; s += 64) {
+        const double x = (double)(2 * s - B.n_k) * inv_nk;
+        double b1 = 0.0, b2 = 0.0;
+        for (int k = kCheb - 1; k >= 1; --k) {
+            const double b0 = fma(2.0 * x, b1, cf[k] - b2);
+            b2 = b1;
+            b1 = b0;
+        }
+        int64_t jstar;
+        double dc, ps;
+        sample_time(cf, x, an, B.inv_dt, B.f_het, (int64_t)K * B.n_k + s, jstar, dc, ps);
+        const size_t o = (size_t)blockIdx.x * B.n_k + s;
+        eta[o] = fma(x, b1, cf[0] - b2);
+        psi[o] = ps;
+    }
 }
 
 // v mod N_FFT for 0 <= v (a mask when N_FFT is a power of two).
@@ -1321,6 +1351,13 @@ hipError_t launch_finish(const BandDev &B, int n_tmpl, const double *part, int n
     dim3 grid((B.n_f + 255) / 256, n_tmpl), block(256);
     hipLaunchKernelGGL(k_finish, grid, block, 0, stream, B.n_f, n_tmpl, part, n_chunks, factor, out,
                        out_fp64 ? 1 : 0);
+    return hipGetLastError();
+}
+
+hipError_t launch_time_samples(const BandDev &B, const double *coef, int det, int k0, int n, double *eta,
+                               double *psi, hipStream_t stream) {
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_time_samples, dim3(n), dim3(64), 0, stream, B, coef, det, k0, n, eta, psi);
     return hipGetLastError();
 }
 

@@ -213,3 +213,156 @@ def test_band_workload_sampled(ccr, band_workload):
     # properties at full size: finite everywhere, noise-dominated bins near unit variance
     assert np.all(np.isfinite(r32)) and np.all(np.isfinite(r64))
     assert 0.8 < np.median(np.abs(r64)) / 0.6745 < 1.25
+
+
+@pytest.fixture(scope="module")
+def large_workload():
+    return synth.make_dataset(synth.config("large"))
+
+
+def test_large_workload_sampled(ccr, large_workload):
+    """Largest workload (2 detectors, 240 days, T_short 1440 s, lags up to 4 segments, 0.25 Hz
+    at 400 Hz: N_K = 870, N_FFT = 32768 = 32 x 1024, 7413 bins, 2.4e5 pairs) on the general
+    path: templates nearest two injections plus random ones, every bin on the GPU; the oracle
+    evaluates a seeded spread of bins plus the bins nearest the injected frequencies."""
+    ds = large_workload
+    print("large: data ready", flush=True)
+    rng = np.random.default_rng(17)
+    pick = set(rng.choice(len(ds.templates), 2, replace=False).tolist())
+    for inj in ds.injections[:2]:
+        d = ((ds.templates[:, 0] - inj["a_p"]) ** 2 + ((ds.templates[:, 1] - inj["t_asc"]) / 1000.0) ** 2
+             + ((ds.templates[:, 2] - inj["period"]) / 0.04) ** 2)
+        pick.add(int(np.argmin(d)))
+    pick = sorted(pick)
+    with ccr.Context(ds.sky, device=0) as ctx:
+        bid = ctx.load(ds, templates=ds.templates[pick])
+        info, freqs = ctx.band_info(bid, freqs=True)
+        assert (info["n_k"], info["n_fft"], info["n_f"]) == (870, 32768, 7413)
+        r32 = ctx.compute_rho(bid, prec=ccr.PREC_SPLIT, out_fp64=False)
+        r64 = ctx.compute_rho(bid, prec=ccr.PREC_FP64)
+    bins = set(rng.choice(info["n_f"], 40, replace=False).tolist())
+    for inj in ds.injections[:2]:
+        bins.add(int(np.argmin(np.abs(freqs - inj["f0"]))))
+    bins = sorted(bins)
+    print("large: device rho done", flush=True)
+    ref = oracle.Oracle(ds).rho(ds.templates[pick], bins=bins)
+    e64, e32 = rho_err(r64[:, bins], ref), rho_err(r32[:, bins], ref)
+    print(f"large: fp64 {e64:.2e} split {e32:.2e} over {len(pick)} templates x {len(bins)} bins, "
+          f"max|rho| {np.abs(ref).max():.2f}")
+    assert e64 < TOL64 and e32 < TOL32
+    # every bin at full size: finite, and the split path within its bar of the FP64 path
+    # (100 injections fill the band, so noise-only statistics do not apply here)
+    assert np.all(np.isfinite(r32)) and np.all(np.isfinite(r64))
+    assert rho_err(r32, r64) < TOL32
+
+
+def test_time_base_parity(ccr, large_workload):
+    """Step 1 alone at the largest span (240 days, 400 Hz): the FP64 delay eta - D_a and the
+    heterodyne phase frac(f_het Delta) of samples spread over the whole observation against the
+    oracle's long-double Newton solve of the full time map.  The delay of sample r is returned
+    as a small eta and the anchor offset D_a (|D_a| <= 500 s, stored in FP64: half an ulp is
+    2.8e-14 s); the phase is carried without that rounding.  Bars from the FP64 arithmetic:
+    |eta| <= a_p + A_o w_o T_short / 2 ~ 2.1 s, so the ten-term Chebyshev evaluation rounds to
+    ~10 eps |eta| ~ 2.3e-15 s, i.e. 1e-12 cycles at 400 Hz; the delay adds the D_a rounding."""
+    ds = large_workload
+    o = oracle.Oracle(ds)
+    LD = np.longdouble
+    n_k, M = ds.n_k, ds.n_seg
+    tm = ds.templates[[7, 50000, 100199]]
+    worst_d = worst_p = 0.0
+    with ccr.Context(ds.sky, device=0) as ctx:
+        bid = ctx.load(ds, templates=tm)
+        for t in range(len(tm)):
+            for X in range(ds.n_det):
+                for K in (0, 1, M // 3, M // 2, M - 2, M - 1):
+                    eta, anc, psi = ctx.time_base(bid, t, X, k0=K, n_seg=1)
+                    for s in (0, 1, n_k // 2, n_k - 1):
+                        hi, lo = o.delay(X, tm[t], K * n_k + s)
+                        dref = LD(hi) + LD(lo)
+                        worst_d = max(worst_d, abs(float(LD(eta[0, s]) - LD(anc[0]) - dref)))
+                        pref = LD(ds.f_het) * dref
+                        dp = float(LD(psi[0, s]) - (pref - np.floor(pref)))
+                        worst_p = max(worst_p, abs(dp - round(dp)))
+    print(f"time base: delay {worst_d:.2e} s, phase {worst_p:.2e} cycles")
+    assert worst_d < 5e-14
+    assert worst_p < 2e-12
+
+
+@pytest.fixture(scope="module")
+def multiband_small():
+    """Eight bands of the batching workload (3 detectors with uneven coverage, gaps fixed in
+    time, T_short 1400 s at 50 Hz down to 247 s at 395 Hz, N_K 150-400, lag 1) over 10 days."""
+    return synth.make_multiband(synth.config("multiband"), bands=[0, 9, 18, 27, 36, 45, 54, 63],
+                                t_obs=10 * 86400.0)
+
+
+def test_multiband_one_call(ccr, multiband_small):
+    """All bands in one compute call (shared launches across bands, mixed kernel variants):
+    FP64 rho bitwise equal to one call per band, and both precisions against the oracle."""
+    dss = multiband_small
+    pick = [0, 531]
+    with ccr.Context(dss[0].sky, device=0) as ctx:
+        ids = [ctx.load(ds, templates=ds.templates[pick]) for ds in dss]
+        nks = sorted({ctx.band_info(b)["n_k"] for b in ids})
+        assert nks[0] <= 256 < nks[-1]  # both the 256-point and the general FFT path
+        r64 = ctx.compute_rho(ids, prec=ccr.PREC_FP64)
+        r32 = ctx.compute_rho(ids, prec=ccr.PREC_SPLIT, out_fp64=False)
+        singles = [ctx.compute_rho(b, prec=ccr.PREC_FP64) for b in ids]
+    for a, b in zip(r64, singles):
+        assert np.array_equal(a, b)
+    worst64 = worst32 = 0.0
+    for ds, a, b in zip(dss, r64, r32):
+        ref = oracle.Oracle(ds).rho(ds.templates[pick])
+        worst64, worst32 = max(worst64, rho_err(a, ref)), max(worst32, rho_err(b, ref))
+    print(f"multiband: fp64 {worst64:.2e} split {worst32:.2e} over {len(dss)} bands")
+    assert worst64 < TOL64 and worst32 < TOL32
+
+
+def test_graph_capture_replays(ccr, multiband_small):
+    """With option graph = 1 a compute call is captured once and replayed: every replay, with
+    eager work and synchronisations between them, equals the eager result bitwise; changing the
+    templates re-captures."""
+    import torch
+    dss = multiband_small[:3]
+    with ccr.Context(dss[0].sky, device=0) as ctx:
+        ids = [ctx.load(ds, templates=ds.templates[:6]) for ds in dss]
+        eager = ctx.compute_rho(ids, prec=ccr.PREC_SPLIT, out_fp64=False)
+        outs = [torch.empty(e.shape, dtype=torch.float32, device="cuda") for e in eager]
+        ctx.set_option("graph", 1)
+        for rep in range(3):
+            for o in outs:
+                o.fill_(float("nan"))
+            torch.cuda.synchronize()
+            ctx.compute_rho(ids, prec=ccr.PREC_SPLIT, out_fp64=False, outputs=[o.data_ptr() for o in outs])
+            ctx.sync()
+            for o, e in zip(outs, eager):
+                assert np.array_equal(o.cpu().numpy(), e), rep
+            ctx.compute_rho(ids[0], prec=ccr.PREC_FP64)  # eager work between replays
+        ctx.set_templates(ids[1], dss[1].templates[10:16])
+        for o in outs:
+            o.fill_(float("nan"))
+        torch.cuda.synchronize()
+        ctx.compute_rho(ids, prec=ccr.PREC_SPLIT, out_fp64=False, outputs=[o.data_ptr() for o in outs])
+        ctx.sync()
+        ctx.set_option("graph", 0)
+        fresh = ctx.compute_rho(ids, prec=ccr.PREC_SPLIT, out_fp64=False)
+        for o, e in zip(outs, fresh):
+            assert np.array_equal(o.cpu().numpy(), e)
+        assert not np.array_equal(fresh[1], eager[1])
+
+
+def test_autotune_picks_chunk(ccr):
+    """Option autotune = 1 times the candidate pair-sum chunk lengths on the first call, keeps
+    the fastest, and gives the untuned rho up to summation order."""
+    ds = synth.make_dataset(small_config(n_seg=64, max_lag=1, gap_fraction=0.1))
+    with ccr.Context(ds.sky, device=0) as ctx:
+        bid = ctx.load(ds)
+        base = ctx.compute_rho(bid, prec=ccr.PREC_FP64)
+        ctx.set_option("autotune", 1)
+        tuned = ctx.compute_rho(bid, prec=ccr.PREC_FP64)
+        kc = ctx.get_option("tuned_k_chunk")
+        assert kc in (32, 64, 128)
+        assert np.max(np.abs(tuned - base)) < 1e-12 * max(1.0, np.abs(base).max())
+        again = ctx.compute_rho(bid, prec=ccr.PREC_FP64)
+        assert np.array_equal(again, tuned)
+        assert ctx.get_option("tuned_k_chunk") == kc
