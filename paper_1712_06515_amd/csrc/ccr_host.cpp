@@ -611,23 +611,6 @@ ccr_status ensure_ready(ccr_ctx *c, Band &B) {
     return CCR_OK;
 }
 
-// Templates per launch so that the staged buffers stay within the workspace budget.
-int64_t template_batch(ccr_ctx *c, const Band &B, bool fp64, bool no_spectra_buffer) {
-    const Plan &pl = B.plan;
-    const size_t cs = fp64 ? 16 : 8;
-    const size_t per = (size_t)B.Q * pl.n_seg * pl.n_k * cs +
-                       (no_spectra_buffer ? 0 : (size_t)B.Q * pl.n_seg * pl.n_f * cs) +
-                       (size_t)std::max(B.n_work, 1) * kCheb * sizeof(double);
-    int64_t tb = c->opt_template_batch;
-    if (tb <= 0) {
-        size_t budget = (size_t)c->opt_workspace_mb << 20;
-        tb = (int64_t)std::max<size_t>(1, budget / std::max<size_t>(per, 1));
-    }
-    tb = std::min<int64_t>(tb, 65535);
-    tb = std::min<int64_t>(tb, B.n_tmpl);
-    return std::max<int64_t>(tb, 1);
-}
-
 // Optional per-kernel device timing: events around a launch on its own stream.
 struct LaunchTimer {
     ccr_ctx *c;
@@ -662,12 +645,6 @@ void collect_times(ccr_ctx *c) {
     c->timed.clear();
 }
 
-int k_chunk_for(ccr_ctx *c, const Plan &pl) {
-    int64_t kc = c->opt_k_chunk > 0 ? c->opt_k_chunk : std::min<int64_t>(pl.n_seg, 256);
-    // keep the chunk count within the launch grid's y extent
-    kc = std::max<int64_t>(kc, (pl.n_seg + 65534) / 65535);
-    return (int)kc;
-}
 
 constexpr size_t kMaxLds = 65536;
 
@@ -906,7 +883,8 @@ ccr_status build_plan(ccr_ctx *c, bool fp64, int n_bands, const int *band_ids, v
 
 ccr_status ensure_workspace(ccr_ctx *c, const CallPlan &cp) {
     ccr_status st;
-    if ((st = grow(c, c->ws_y, std::max<size_t>(cp.y_bytes, 16)))) return st;
+    // 256 samples of tail pad: the spectra kernels read whole 256-sample rows of the last segment
+    if ((st = grow(c, c->ws_y, cp.y_bytes + 256 * sizeof(double2)))) return st;
     if ((st = grow(c, c->ws_F, std::max<size_t>(cp.F_bytes, 16)))) return st;
     if ((st = grow(c, c->ws_part, std::max<size_t>(cp.part_bytes, 16)))) return st;
     return grow(c, c->ws_coef, std::max<size_t>(cp.coef_bytes, 16));

@@ -106,19 +106,15 @@ hipError_t launch_resample(const BandDev &B, const double *coef, int n_tmpl, boo
                            hipStream_t stream);
 hipError_t launch_spectra(const BandDev &B, int n_tmpl, bool fp64, const void *y, void *F,
                           hipStream_t stream);
-hipError_t launch_pairsum(const BandDev &B, int n_tmpl, bool fp64, const void *F, double *part,
-                          int k_chunk, int n_chunks, hipStream_t stream);
 // Fused resample + FFT + pair sum, one workgroup per (template, chunk of k_chunk segments),
 // S segments per step; fused_steps() picks S for an LDS budget (0: does not fit).
 int fused_steps(const BandDev &B, bool fp64, size_t limit);
 size_t fused_lds_bytes(const BandDev &B, bool fp64, int S);
 hipError_t launch_fused(const BandDev &B, const double *coef, int n_tmpl, bool fp64, double *part,
                         int k_chunk, int n_chunks, int S, hipStream_t stream);
-// Split-precision spectra + pair sum in one kernel (256-point segments, distinct bins): writes
-// chunk partials directly; spectra_pairs_ok() says whether a band qualifies.
+// Split-precision spectra + pair sum in one kernel (256-point segments, distinct bins, at most
+// 4 detectors and 512 bins): whether a band qualifies for it.
 bool spectra_pairs_ok(const BandDev &B, bool fp64, size_t limit);
-hipError_t launch_spectra_pairs(const BandDev &B, int n_tmpl, const void *y, double *part, int k_chunk,
-                                int n_chunks, hipStream_t stream);
 hipError_t launch_finish(const BandDev &B, int n_tmpl, const double *part, int n_chunks,
                          double factor, void *out, bool out_fp64, hipStream_t stream);
 

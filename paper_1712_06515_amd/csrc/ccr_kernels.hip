@@ -638,13 +638,16 @@ __device__ __forceinline__ void spectra_pairs_body(const BandDev &B, const float
     int slot_b = Kh % slots;  // ring slot of segment Kb
     // this group's samples for the next step, loaded while the current step's pairs are summed
     float2 yv[16];
+    // unconditional loads, then a select (no branches): samples past n_k belong to the next
+    // segment or, after the last one, to the workspace's 256-sample tail pad
     auto load_y = [&](int Kn) {
         const bool in = used && Kn < K1;
-        const float2 *ysn = ybase + (size_t)(in ? Kn : 0) * n_k;
+        const float2 *ysn = ybase + (size_t)(in ? Kn : 0) * n_k + t;
 #pragma unroll
         for (int n1 = 0; n1 < 16; ++n1) {
-            const int sidx = 16 * n1 + t;
-            yv[n1] = (in && sidx < n_k) ? ysn[sidx] : make_float2(0.f, 0.f);
+            const float2 v = ysn[16 * n1];
+            const bool keep = in && 16 * n1 + t < n_k;
+            yv[n1] = make_float2(keep ? v.x : 0.f, keep ? v.y : 0.f);
         }
     };
     load_y(Kh + sd);
@@ -666,10 +669,12 @@ __device__ __forceinline__ void spectra_pairs_body(const BandDev &B, const float
         float2 *Fo = ring + ((size_t)myslot * Q + X) * n_f1;
         for (int p = 0; p < P; ++p) {
             // residue class p: x_p[16 n1 + t] = y[16 n1 + t] W^(16 p n1) W^(p t), W = exp(-2 pi i / N);
-            // W^(16 p n1) is uniform over lanes, W^(p t) folds into the stage-1 twiddles
+            // W^(16 p n1) is uniform over lanes (16 p n1 < 256 P = N needs no reduction), W^(p t)
+            // folds into the stage-1 twiddles
             float2 v[16];
+            const int tstride = 16 * p;
 #pragma unroll
-            for (int n1 = 0; n1 < 16; ++n1) v[n1] = p ? cmul<float>(yv[n1], tw[mod_fft(B, (int64_t)16 * p * n1)]) : yv[n1];
+            for (int n1 = 0; n1 < 16; ++n1) v[n1] = p ? cmul<float>(yv[n1], tw[tstride * n1]) : yv[n1];
             fft256_lanes<float>(v, t, sc, tw, tws, on, p != 0, tw[p * t]);
             if (on) {
                 // Phi_in and the normalisation: scale exp(-2 pi i kbar r_B / N) with
@@ -749,11 +754,6 @@ __device__ __forceinline__ void spectra_pairs_body(const BandDev &B, const float
     }
 }
 
-template <int NR>
-__global__ void __launch_bounds__(64) k_spectra_pairs16(BandDev B, const float2 *y, double *part, int k_chunk,
-                                                       int n_chunks) {
-    spectra_pairs_body<NR>(B, y, part, k_chunk, n_chunks, blockIdx.x, blockIdx.y);
-}
 
 // The fused kernel keeps the activity bits of a step (S segments x Q detectors) in 64 bits.
 __host__ __device__ inline bool Q_ok(const BandDev &B) { return B.Q >= 1 && B.Q * 4 <= 64; }
@@ -838,11 +838,6 @@ __device__ __forceinline__ void pairs_body(const BandDev &B, const c2<T> *F, dou
     part[((size_t)tb * n_chunks + c) * B.n_f + i] = acc;
 }
 
-template <typename T>
-__global__ void __launch_bounds__(256) k_pairs(BandDev B, const c2<T> *F, double *part, int k_chunk,
-                                               int n_chunks) {
-    pairs_body<T>(B, F, part, k_chunk, n_chunks, blockIdx.x, blockIdx.y, blockIdx.z);
-}
 
 // ------------------------------------------------------------------ fused path
 
@@ -1288,29 +1283,7 @@ bool spectra_pairs_ok(const BandDev &B, bool fp64, size_t limit) {
            spair_layout(B.Q, B.n_f, B.R, B.n_fft).total <= limit;
 }
 
-hipError_t launch_spectra_pairs(const BandDev &B, int n_tmpl, const void *y, double *part, int k_chunk,
-                                int n_chunks, hipStream_t stream) {
-    if (n_tmpl == 0) return hipSuccess;
-    dim3 grid(n_chunks, n_tmpl), block(64);
-    const size_t lds = spair_layout(B.Q, B.n_f, B.R, B.n_fft).total;
-    if (B.n_f <= 64 * 3)
-        hipLaunchKernelGGL(k_spectra_pairs16<3>, grid, block, lds, stream, B, (const float2 *)y, part, k_chunk, n_chunks);
-    else
-        hipLaunchKernelGGL(k_spectra_pairs16<kSpairMaxRounds>, grid, block, lds, stream, B, (const float2 *)y, part,
-                           k_chunk, n_chunks);
-    return hipGetLastError();
-}
 
-hipError_t launch_pairsum(const BandDev &B, int n_tmpl, bool fp64, const void *F, double *part,
-                          int k_chunk, int n_chunks, hipStream_t stream) {
-    if (n_tmpl == 0) return hipSuccess;
-    dim3 grid((B.n_f + 127) / 128, n_chunks, n_tmpl), block(128);
-    if (fp64)
-        hipLaunchKernelGGL(k_pairs<double>, grid, block, 0, stream, B, (const double2 *)F, part, k_chunk, n_chunks);
-    else
-        hipLaunchKernelGGL(k_pairs<float>, grid, block, 0, stream, B, (const float2 *)F, part, k_chunk, n_chunks);
-    return hipGetLastError();
-}
 
 // Segments per step: the largest of 4, 2, 1 whose LDS footprint fits in `limit` bytes
 // (0 if even one segment per step does not fit).
