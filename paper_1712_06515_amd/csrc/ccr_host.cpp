@@ -81,9 +81,10 @@ struct Band {
     int Q = 0;
     // device tables
     DevBuf d_x, d_mask, d_anchor, d_earth, d_win64, d_win32, d_cheb_x, d_cheb_T, d_tw64, d_tw32, d_bin_m, d_bin_p,
-        d_bin_kb, d_bin_pos, d_segw, d_active, d_work, d_seg_work, d_tmpl;
+        d_bin_kb, d_bin_pos, d_segw, d_active, d_work, d_seg_work, d_tmpl, d_lagph;
     int bins_unique = 0;
     int n_work = 0;
+    int newton_steps = 3, cheb_split = kCheb;
     std::vector<double> freqs;
     std::vector<uint8_t> active;
 };
@@ -461,6 +462,15 @@ ccr_status prepare(ccr_ctx *c, Band &B) {
         tw64[j] = make_double2((double)cosl(a), (double)sinl(a));
         tw32[j] = make_float2((float)cosl(a), (float)sinl(a));
     }
+    // lag phases of the pair sum (spectra taken without Phi_in)
+    const int64_t Rl = B.p.max_lag;
+    std::vector<float2> lagph((size_t)(Rl + 1) * pl.n_f);
+    for (int64_t dl = 0; dl <= Rl; ++dl)
+        for (int64_t i = 0; i < pl.n_f; ++i) {
+            const int64_t e = (int64_t)(((__int128)bkb[i] * dl * pl.n_k) % pl.n_fft);
+            const long double a = 2.0L * kPiL * (long double)e / (long double)pl.n_fft;
+            lagph[(size_t)(dl * pl.n_f + i)] = make_float2((float)cosl(a), (float)sinl(a));
+        }
     const int D = B.p.dirichlet_D;
     std::vector<double> w64(2 * D + 1);
     std::vector<float> w32(2 * D + 1);
@@ -497,6 +507,7 @@ ccr_status prepare(ccr_ctx *c, Band &B) {
     if ((st = upload(c, B.d_cheb_T, cT))) return st;
     if ((st = upload(c, B.d_tw64, tw64))) return st;
     if ((st = upload(c, B.d_tw32, tw32))) return st;
+    if ((st = upload(c, B.d_lagph, lagph))) return st;
     if ((st = upload(c, B.d_bin_m, bm))) return st;
     if ((st = upload(c, B.d_bin_p, bp))) return st;
     if ((st = upload(c, B.d_bin_kb, bkb))) return st;
@@ -532,6 +543,50 @@ ccr_status prepare_templates(ccr_ctx *c, Band &B) {
     {
         EarthModel m = earth_model(c->sky, B.det[0].site);
         if ((double)m.w_d * (ld + 4.0) > 0.3) return fail(c, CCR_ERANGE, "segment too long for the time base");
+    }
+    // Newton steps of the node solve and Chebyshev terms of the split path, from bounds over the
+    // templates and detectors.  Newton: the binary-only start is off by at most
+    // e0 = de + a_p Omega (a_p + de) (de: Earth-delay change over the segment), and each step
+    // maps e -> K e^2 with K = G''/(2 G'); two steps suffice when K^3 e0^4 < 1e-20 s.
+    // Chebyshev: the series of A sin(omega u + phi) on [-h, h] has coefficients 2A J_k(omega h)
+    // <= 2A (omega h / 2)^k / k!; the split path drops terms 7..9 when their sum stays below
+    // 1e-9 cycles of the top frequency and 1e-9 samples.
+    {
+        double Aw = 0.0, Aw2 = 0.0;
+        std::vector<std::pair<double, double>> comps;  // (amplitude, angular rate) of the Earth terms
+        for (int X = 0; X < B.Q; ++X) {
+            const EarthModel m = earth_model(c->sky, B.det[X].site);
+            Aw = std::max(Aw, (double)(m.A_o * m.w_o + m.A_d * m.w_d));
+            Aw2 = std::max(Aw2, (double)(m.A_o * m.w_o * m.w_o + m.A_d * m.w_d * m.w_d));
+            comps.push_back({(double)m.A_o, (double)m.w_o});
+            comps.push_back({(double)m.A_d, (double)m.w_d});
+        }
+        const double h = 0.5 * (double)tseg;
+        double worst_e2 = 0.0, worst_tail = 0.0;
+        for (int64_t t = 0; t < T; ++t) {
+            const double ap = B.tmpl_raw[3 * t], Om = 2.0 * kPi / B.tmpl_raw[3 * t + 2];
+            const double X = h + ap + 1.0;
+            const double de = 1.01 * Aw * X + 1e-9;
+            const double e0 = de + ap * Om * (ap + de);
+            const double K = (1.1 * ap * Om * Om + 1.1 * Aw2) / (2.0 * (1.0 - ap * Om) * (1.0 - Aw));
+            const double e1 = K * e0 * e0, e2 = K * e1 * e1;
+            worst_e2 = std::max(worst_e2, e2);
+            double tail = 0.0;
+            std::vector<std::pair<double, double>> all = comps;
+            all.push_back({ap, Om});
+            for (const auto &cw : all) {
+                const double z = 0.5 * cw.second * 1.01 * h;
+                double term = 2.0 * cw.first;
+                for (int k = 1; k <= 20; ++k) {
+                    term *= z / k;
+                    if (k >= kChebSplit) tail += term;
+                }
+            }
+            worst_tail = std::max(worst_tail, tail);
+        }
+        const double f_top = B.p.f_min + B.p.f_band;
+        B.newton_steps = worst_e2 < 1e-20 ? 2 : 3;
+        B.cheb_split = (worst_tail * f_top < 1e-9 && worst_tail / (double)dt < 1e-9) ? kChebSplit : kCheb;
     }
     B.tmpl.assign((size_t)T * kTmplStride, 0.0);
     for (int64_t t = 0; t < T; ++t) {
@@ -591,6 +646,9 @@ BandDev band_dev(const Band &B) {
     d.seg_work = B.d_seg_work.as<int>();
     d.n_work = B.n_work;
     d.tmpl = B.d_tmpl.as<double>();
+    d.lagph = B.d_lagph.as<float2>();
+    d.newton_steps = B.newton_steps;
+    d.cheb_split = B.cheb_split;
     return d;
 }
 
@@ -708,9 +766,10 @@ ccr_status compute_fused(ccr_ctx *c, Band &B, const BandDev &bd, bool fp64, int 
 struct Variant {
     bool sp = false;     // spectra + pair sum in one kernel
     bool reg16 = false;  // otherwise: 256-point register FFT (else the LDS Stockham FFT on n_s points)
-    int DT = 0, window = 0, n_s = 0, nr = 0;
+    int DT = 0, window = 0, n_s = 0, nr = 0, n_cheb = kCheb;
     bool operator==(const Variant &o) const {
-        return sp == o.sp && reg16 == o.reg16 && DT == o.DT && window == o.window && n_s == o.n_s && nr == o.nr;
+        return sp == o.sp && reg16 == o.reg16 && DT == o.DT && window == o.window && n_s == o.n_s && nr == o.nr &&
+               n_cheb == o.n_cheb;
     }
 };
 
@@ -741,6 +800,7 @@ Variant variant_of(const BandDev &bd, bool fp64) {
     v.sp = spectra_pairs_ok(bd, fp64, kMaxLds);
     v.DT = bd.D == 8 ? 8 : 0;
     v.window = bd.window;
+    v.n_cheb = fp64 ? kCheb : bd.cheb_split;
     if (v.sp) {
         v.nr = spectra_pairs_rounds(bd);
     } else {
@@ -916,8 +976,8 @@ ccr_status run_rounds(ccr_ctx *c, const CallPlan &cp, size_t r0, size_t r1, bool
         }
         {
             LaunchTimer lt(c, 0, s, timing);
-            HIP_OK(c, launch_resample_m(db, di, r.n, (int)r.blocks[kStResample], fp64, r.v.DT, r.v.window, coef,
-                                        c->ws_y.p, s));
+            HIP_OK(c, launch_resample_m(db, di, r.n, (int)r.blocks[kStResample], fp64, r.v.DT, r.v.window,
+                                        r.v.n_cheb, coef, c->ws_y.p, s));
         }
         if (r.v.sp) {
             LaunchTimer lt(c, 6, s, timing);

@@ -34,8 +34,10 @@ struct SegWeight {
 // of segment K's mid-time as c0 + K c1 in double-double: c0h, c0l, c1h, c1l.
 constexpr int kTmplStride = 6;
 
-// Chebyshev nodes per segment for the time base, and the detector limit of the kernels.
+// Chebyshev nodes per segment for the time base; the split path may sum only the first
+// kChebSplit coefficients when the host's bound on the rest allows; detector limit.
 constexpr int kCheb = 10;
+constexpr int kChebSplit = 7;
 #define CCR_MAX_DET_K 8
 
 // Everything a kernel needs about a band (device pointers + scalars).
@@ -70,6 +72,11 @@ struct BandDev {
     const int *seg_work;      // [Q][n_seg] position of (det, K) in `work`, -1 if inactive
     int n_work;
     const double *tmpl;       // [n_templates][kTmplStride] template table
+    // lag phases of the pair sum, lagph[dl n_f + i] = exp(+2 pi i kbar_i dl n_k / N_FFT), dl <= R:
+    // F*_XK F_YL = lagph(K - L) conj(F~_XK) F~_YL for spectra F~ taken without Phi_in
+    const float2 *lagph;
+    int newton_steps;         // Newton steps of the time-base node solve (2 or 3)
+    int cheb_split;           // Chebyshev terms the split path sums (kChebSplit or kCheb)
 };
 
 // One work item of a batched launch: a run of consecutive templates of one band.  A batched
@@ -126,7 +133,7 @@ int spectra_threads(int n_s);               // threads of the LDS Stockham FFT w
 hipError_t launch_timebase_m(const BandDev *bands, const WorkItem *items, int n_items, int blocks, double *coef,
                              hipStream_t stream);
 hipError_t launch_resample_m(const BandDev *bands, const WorkItem *items, int n_items, int blocks, bool fp64, int D,
-                             int window, const double *coef, void *y, hipStream_t stream);
+                             int window, int n_cheb, const double *coef, void *y, hipStream_t stream);
 hipError_t launch_spectra_pairs_m(const BandDev *bands, const WorkItem *items, int n_items, int blocks, int rounds,
                                   size_t lds, const void *y, double *part, hipStream_t stream);
 // reg16: the 256-point register FFT (split precision, distinct bins); else the LDS Stockham FFT

@@ -69,12 +69,14 @@ __device__ __forceinline__ void binary_anchor(const double *tp, int K, double &s
 // Three Newton steps from eta_0 = a_p sin(theta_b + Omega u) (quadratic convergence from an
 // initial error below 0.1 s leaves < 1e-25 s).
 __device__ __forceinline__ double node_eta(double u, double a_p, double Om, double sb, double cb,
-                                           const EarthConst &ec, const Anchor &an) {
+                                           const EarthConst &ec, const Anchor &an, int steps) {
     double s, cm;
     sincos_small(Om * u, s, cm);
     double eta = a_p * (fma(sb, cm, sb) + cb * s);
+    // Newton from the binary-only value; `steps` (2 or 3) comes from the host's convergence bound
 #pragma unroll
     for (int it = 0; it < 3; ++it) {
+        if (it >= steps) break;
         const double x = u + eta;
         double so, co, sd, cd;
         sincos_small(ec.w_o * x, so, co);
@@ -110,12 +112,14 @@ __device__ __forceinline__ double cheb_coef(const double *eta, const double *T, 
 // Per sample: eta by Clenshaw at x = u / h, then the interpolation centre j* = r +
 // round-half-up(Delta / dt), the offset delta_c = Delta / dt - round(.) in [-1/2, 1/2) and the
 // heterodyne phase frac(f_h Delta) = frac(psi_a + f_h eta), cycles.
+// NC <= kCheb leading coefficients are summed (the split path drops a tail the host bounds).
+template <int NC = kCheb>
 __device__ __forceinline__ void sample_time(const double *coef, double x, const Anchor &an, double inv_dt,
                                             double f_het, int64_t r, int64_t &jstar, double &dc, double &psi) {
     double b1 = 0.0, b2 = 0.0;
     const double x2 = 2.0 * x;
 #pragma unroll
-    for (int k = kCheb - 1; k >= 1; --k) {
+    for (int k = NC - 1; k >= 1; --k) {
         const double b0 = fma(x2, b1, coef[k] - b2);
         b2 = b1;
         b1 = b0;
@@ -146,7 +150,8 @@ __device__ __forceinline__ void timebase_body(const BandDev &B, const double *tm
         double sb, cb;
         binary_anchor(tp, K, sb, cb);
         const double h = 0.5 * (double)B.n_k * B.dt;
-        sh_eta[threadIdx.x] = node_eta(h * B.cheb_x[j], tp[0], tp[1], sb, cb, B.earth[det], B.anchors[entry]);
+        sh_eta[threadIdx.x] = node_eta(h * B.cheb_x[j], tp[0], tp[1], sb, cb, B.earth[det], B.anchors[entry],
+                                       B.newton_steps);
     }
     __syncthreads();
     if (on) coef[((size_t)tb * B.n_work + w) * kCheb + j] = cheb_coef(sh_eta + le * kCheb, B.cheb_T, j);
@@ -158,12 +163,6 @@ __global__ void __launch_bounds__(kTbEntries * kCheb) k_timebase(BandDev B, cons
 
 // ------------------------------------------------------------------ resampling
 
-template <typename T> __device__ __forceinline__ T sinpi_t(T v);
-template <> __device__ __forceinline__ float sinpi_t<float>(float v) { return sinpif(v); }
-template <> __device__ __forceinline__ double sinpi_t<double>(double v) { return sinpi(v); }
-template <typename T> __device__ __forceinline__ T cospi_t(T v);
-template <> __device__ __forceinline__ float cospi_t<float>(float v) { return cospif(v); }
-template <> __device__ __forceinline__ double cospi_t<double>(double v) { return cospi(v); }
 template <typename T> __device__ __forceinline__ const T *win_table(const BandDev &B);
 template <> __device__ __forceinline__ const float *win_table<float>(const BandDev &B) { return B.win32; }
 template <> __device__ __forceinline__ const double *win_table<double>(const BandDev &B) { return B.win64; }
@@ -229,6 +228,32 @@ __device__ __forceinline__ c2<T> interpolate_w0_inside(const T *cw, const float2
         im = fma(q, (T)xv.y, im);
     }
     return mk<T>(re * s, im * s);
+}
+
+// FP32 form: taps n and -n share one reciprocal, 1/(dc - n) = (dc + n) r and 1/(dc + n) =
+// (dc - n) r with r = 1/(dc^2 - n^2) (|dc^2 - n^2| >= 3/4), and the window is symmetric
+// (cw[D + n] = cw[D - n]).
+template <>
+__device__ __forceinline__ float2 interpolate_w0_inside<float, 8>(const float *cw, const float2 *xc, float dc) {
+    if (dc == 0.f) return xc[0];
+    const float s = sin_pi<float>(dc) * 0.318309886183790671537767526745f;
+    const float q0 = cw[8] * recip<float>(dc);
+    const float2 x0 = xc[0];
+    float re = q0 * x0.x, im = q0 * x0.y;
+#pragma unroll
+    for (int n = 1; n <= 8; ++n) {
+        const float r = recip<float>(fmaf(dc, dc, -(float)(n * n)));
+        const float cr = cw[8 + n] * r;
+        const float t = cr * dc;
+        const float qp = fmaf(cr, (float)n, t);   // weight of x'_{j* + n}
+        const float qm = fmaf(-cr, (float)n, t);  // weight of x'_{j* - n}
+        const float2 xp = xc[n], xm = xc[-n];
+        re = fmaf(qp, xp.x, re);
+        im = fmaf(qp, xp.y, im);
+        re = fmaf(qm, xm.x, re);
+        im = fmaf(qm, xm.y, im);
+    }
+    return make_float2(re * s, im * s);
 }
 
 // Signed tap coefficients (-1)^n w_n of the tap-indexed window for interpolate_w0_inside.
@@ -314,7 +339,7 @@ __device__ __forceinline__ c2<T> interpolate_window(const BandDev &B, const floa
 
 // Resampler: one 64-thread workgroup per (template, active segment), looping over the segment's
 // samples; the segment's Chebyshev coefficients and anchor are uniform (scalar loads).
-template <typename T, int DT, int WIN>
+template <typename T, int DT, int WIN, int NC = kCheb>
 __device__ __forceinline__ void resample_body(const BandDev &B, const double *coef, c2<T> *y, int w, int tb) {
     const int entry = B.work[w];
     const int det = entry / B.n_seg;
@@ -339,7 +364,7 @@ __device__ __forceinline__ void resample_body(const BandDev &B, const double *co
         }
         int64_t jstar;
         double dc, psi;
-        sample_time(cl, (double)(2 * s - B.n_k) * inv_nk, an, B.inv_dt, B.f_het, r0 + s, jstar, dc, psi);
+        sample_time<NC>(cl, (double)(2 * s - B.n_k) * inv_nk, an, B.inv_dt, B.f_het, r0 + s, jstar, dc, psi);
         const c2<T> acc = interpolate<T, DT, WIN>(B, xd, jstar, dc, cw);
         T c, sn;
         sincos_rev<T>(psi, sn, c);
@@ -511,6 +536,7 @@ __device__ __forceinline__ void fft256_lanes(c2<T> *v, int t, c2<T> *sc, const c
     wave_sync();
 }
 
+
 // Spectra of 256-point segments (n_s = 256, distinct output bins): one 16-lane group per
 // (template, detector, segment), 8 groups per 128-thread workgroup.  For each residue class p:
 // twiddle the zero-padded segment by exp(-2 pi i p s / N_FFT), FFT in registers, and write the
@@ -615,7 +641,6 @@ __device__ __forceinline__ void spectra_pairs_body(const BandDev &B, const float
     const int S = Ly.S, slots = Ly.slots;
     const int64_t nr = (int64_t)B.n_seg * n_k;
     const float2 *tw = B.tw32;
-    const int tws = B.n_fft >> 8;
     const bool cross = (B.pairs & 1) != 0, same = (B.pairs & 2) != 0;
     float2 *sc = reinterpret_cast<float2 *>(smem) + grp * 16 * 17;
     const int sd = grp / Q, X = grp - sd * Q;  // this group's (segment in step, detector)
@@ -660,12 +685,11 @@ __device__ __forceinline__ void spectra_pairs_body(const BandDev &B, const float
         int myslot = slot_b + sd;
         if (myslot >= slots) myslot -= slots;
         if (mine && t == 0) {
+            // weights with the spectrum normalisation 1 / (sigma sqrt N_K) folded in
             const SegWeight sw = B.segw[X * B.n_seg + K];
             flag[myslot * Q + X] = on ? 1 : 0;
-            meta[myslot * Q + X] = make_double2(sw.ahat, sw.bhat);
+            meta[myslot * Q + X] = make_double2(sw.ahat * sw.scale, sw.bhat * sw.scale);
         }
-        const float scale = on ? (float)B.segw[X * B.n_seg + K].scale : 0.f;
-        const int rb_mod = on ? mod_fft(B, (int64_t)K * n_k) : 0;
         float2 *Fo = ring + ((size_t)myslot * Q + X) * n_f1;
         for (int p = 0; p < P; ++p) {
             // residue class p: x_p[16 n1 + t] = y[16 n1 + t] W^(16 p n1) W^(p t), W = exp(-2 pi i / N);
@@ -675,18 +699,13 @@ __device__ __forceinline__ void spectra_pairs_body(const BandDev &B, const float
             const int tstride = 16 * p;
 #pragma unroll
             for (int n1 = 0; n1 < 16; ++n1) v[n1] = p ? cmul<float>(yv[n1], tw[tstride * n1]) : yv[n1];
-            fft256_lanes<float>(v, t, sc, tw, tws, on, p != 0, tw[p * t]);
+            fft256_lanes<float>(v, t, sc, tw, B.n_fft >> 8, on, p != 0, tw[p * t]);
             if (on) {
-                // Phi_in and the normalisation: scale exp(-2 pi i kbar r_B / N) with
-                // kbar = (t + 16 k2) P + p, by recurrence over k2
-                float2 wo = cscale<float>(tw[mod_fft(B, (int64_t)(t * P + p) * rb_mod)], scale);
-                const float2 wst = tw[mod_fft(B, (int64_t)16 * P * rb_mod)];
+                // the spectrum without Phi_in and normalisation: both enter the pair sum (the
+                // normalisation through the weights, Phi_in as the lag phase of each pair)
                 const int16_t *op = opos + p * 256 + t;
 #pragma unroll
-                for (int k2 = 0; k2 < 16; ++k2) {
-                    Fo[op[16 * k2]] = cmul<float>(v[4 * (k2 & 3) + (k2 >> 2)], wo);
-                    wo = cmul<float>(wo, wst);
-                }
+                for (int k2 = 0; k2 < 16; ++k2) Fo[op[16 * k2]] = v[4 * (k2 & 3) + (k2 >> 2)];
             }
         }
         load_y(K + S);
@@ -698,7 +717,7 @@ __device__ __forceinline__ void spectra_pairs_body(const BandDev &B, const float
         for (int c0 = 0; c0 < Ly.cand; c0 += 64) {
             const int cd = c0 + lane;
             bool valid = false;
-            int o1 = 0, o2 = 0;
+            int o1 = 0, o2 = 0, dl_c = 0;
             float W = 0.f;
             if (cd < Ly.cand) {
                 const int Y = cd % Q;
@@ -718,11 +737,12 @@ __device__ __forceinline__ void spectra_pairs_body(const BandDev &B, const float
                         W = (float)(wk.x * wl.x + wk.y * wl.y);
                         o1 = (slot * Q + Xc) * n_f1;
                         o2 = (sl * Q + Y) * n_f1;
+                        dl_c = dl;
                     }
                 }
             }
             const uint64_t m = __ballot(valid);
-            if (valid) lst[ne + __popcll(m & ((1ull << lane) - 1ull))] = make_int4(o1, o2, __float_as_int(W), 0);
+            if (valid) lst[ne + __popcll(m & ((1ull << lane) - 1ull))] = make_int4(o1, o2, __float_as_int(W), dl_c);
             ne += __popcll(m);
         }
         wave_sync();
@@ -732,12 +752,27 @@ __device__ __forceinline__ void spectra_pairs_body(const BandDev &B, const float
         for (int e = 0; e < ne; ++e) {
             const int4 en = lst[e];
             const float W = __int_as_float(en.z);
+            if (en.w == 0) {
+                // same-time pair: the Phi_in factors cancel
 #pragma unroll
-            for (int r = 0; r < NR; ++r) {
-                const int i = 64 * r + lane;
-                if (r < rounds && i < n_f) {
-                    const float2 f1 = ring[en.x + i], f2 = ring[en.y + i];
-                    st[r] = fma(W, f1.x * f2.x + f1.y * f2.y, st[r]);
+                for (int r = 0; r < NR; ++r) {
+                    const int i = 64 * r + lane;
+                    if (r < rounds && i < n_f) {
+                        const float2 f1 = ring[en.x + i], f2 = ring[en.y + i];
+                        st[r] = fma(W, f1.x * f2.x + f1.y * f2.y, st[r]);
+                    }
+                }
+            } else {
+                // lag dl = K - L: Re(exp(2 pi i kbar dl n_k / N) conj(F~_K) F~_L)
+                const float2 *E = B.lagph + (size_t)en.w * n_f;
+#pragma unroll
+                for (int r = 0; r < NR; ++r) {
+                    const int i = 64 * r + lane;
+                    if (r < rounds && i < n_f) {
+                        const float2 f1 = ring[en.x + i], f2 = ring[en.y + i], ph = E[i];
+                        const float a = f1.x * f2.x + f1.y * f2.y, b = f1.x * f2.y - f1.y * f2.x;
+                        st[r] = fma(W, ph.x * a - ph.y * b, st[r]);
+                    }
                 }
             }
         }
@@ -1145,6 +1180,7 @@ __device__ __forceinline__ BandDev global_view(const BandDev &b, const void *bas
     g.work = as_global(b.work, base);
     g.seg_work = as_global(b.seg_work, base);
     g.tmpl = as_global(b.tmpl, base);
+    g.lagph = as_global(b.lagph, base);
     return g;
 }
 
@@ -1167,14 +1203,14 @@ k_timebase_m(const BandDev *__restrict__ bands, const WorkItem *__restrict__ ite
     timebase_body(B, B.tmpl + (size_t)it.tmpl_off * kTmplStride, coef + it.coef_off, l % gx, l / gx);
 }
 
-template <typename T, int DT, int WIN>
+template <typename T, int DT, int WIN, int NC>
 __global__ void __launch_bounds__(64)
 k_resample_m(const BandDev *__restrict__ bands, const WorkItem *__restrict__ items, int n_items,
              const double *__restrict__ coef, c2<T> *__restrict__ y) {
     const WorkItem &it = items[find_item(items, n_items, kStResample, blockIdx.x)];
     const BandDev B = global_view(bands[it.band], bands);
     const int l = blockIdx.x - it.first[kStResample], gx = it.gx[kStResample];
-    resample_body<T, DT, WIN>(B, coef + it.coef_off, y + it.y_off, l % gx, l / gx);
+    resample_body<T, DT, WIN, NC>(B, coef + it.coef_off, y + it.y_off, l % gx, l / gx);
 }
 
 template <int NR>
@@ -1359,26 +1395,29 @@ hipError_t launch_timebase_m(const BandDev *bands, const WorkItem *items, int n_
     return hipGetLastError();
 }
 
-template <typename T, int DT>
+template <typename T, int DT, int NC>
 static void launch_resample_m_t(const BandDev *bands, const WorkItem *items, int n_items, int blocks, int window,
                                 const double *coef, void *y, hipStream_t stream) {
     if (window == 0)
-        hipLaunchKernelGGL((k_resample_m<T, DT, 0>), dim3(blocks), dim3(64), 0, stream, bands, items, n_items, coef,
-                           (c2<T> *)y);
+        hipLaunchKernelGGL((k_resample_m<T, DT, 0, NC>), dim3(blocks), dim3(64), 0, stream, bands, items, n_items,
+                           coef, (c2<T> *)y);
     else
-        hipLaunchKernelGGL((k_resample_m<T, DT, 1>), dim3(blocks), dim3(64), 0, stream, bands, items, n_items, coef,
-                           (c2<T> *)y);
+        hipLaunchKernelGGL((k_resample_m<T, DT, 1, NC>), dim3(blocks), dim3(64), 0, stream, bands, items, n_items,
+                           coef, (c2<T> *)y);
 }
 
 hipError_t launch_resample_m(const BandDev *bands, const WorkItem *items, int n_items, int blocks, bool fp64, int D,
-                             int window, const double *coef, void *y, hipStream_t stream) {
+                             int window, int n_cheb, const double *coef, void *y, hipStream_t stream) {
     if (blocks == 0) return hipSuccess;
     if (fp64) {
-        if (D == 8) launch_resample_m_t<double, 8>(bands, items, n_items, blocks, window, coef, y, stream);
-        else launch_resample_m_t<double, 0>(bands, items, n_items, blocks, window, coef, y, stream);
+        if (D == 8) launch_resample_m_t<double, 8, kCheb>(bands, items, n_items, blocks, window, coef, y, stream);
+        else launch_resample_m_t<double, 0, kCheb>(bands, items, n_items, blocks, window, coef, y, stream);
+    } else if (n_cheb == kChebSplit) {
+        if (D == 8) launch_resample_m_t<float, 8, kChebSplit>(bands, items, n_items, blocks, window, coef, y, stream);
+        else launch_resample_m_t<float, 0, kChebSplit>(bands, items, n_items, blocks, window, coef, y, stream);
     } else {
-        if (D == 8) launch_resample_m_t<float, 8>(bands, items, n_items, blocks, window, coef, y, stream);
-        else launch_resample_m_t<float, 0>(bands, items, n_items, blocks, window, coef, y, stream);
+        if (D == 8) launch_resample_m_t<float, 8, kCheb>(bands, items, n_items, blocks, window, coef, y, stream);
+        else launch_resample_m_t<float, 0, kCheb>(bands, items, n_items, blocks, window, coef, y, stream);
     }
     return hipGetLastError();
 }
