@@ -27,10 +27,10 @@ sys.path.insert(0, ROOT)
 
 METRIC = "ρ evaluations (templates×freq bins)/s, FP32-batched vs plain FP64 at ≤1e-4 rel err"
 HBM_PEAK_GBS = 8000.0
-# FP32 vector peak of the build: 256 CU x 4 SIMD x 16 lanes x 2 flop (FMA) x 2.4 GHz = 78.6 TFLOP/s.
-# The chip's 157.3 TFLOP/s counts packed FP32 (two lanes per instruction), which this library is
-# compiled without.
-FP32_PEAK_TFLOPS = 78.6
+# MI355X FP32 vector peak.  A probe of plain (non-packed) v_fma_f32 throughput on the chip retires
+# a wave64 instruction every ~2 cycles per SIMD, i.e. 256 CU x 4 SIMD x 32 lanes x 2 flop x 2.4 GHz
+# = 157.3 TFLOP/s, the published figure, without packed FP32.
+FP32_PEAK_TFLOPS = 157.3
 
 WORKLOADS = {
     "band": "2 detectors, 120 d, 30% gaps, T_short 600 s, 0.1 Hz at 200 Hz, 4096 templates "
@@ -121,8 +121,7 @@ def roofline(name, avg_ms, tb, info, workload):
     kern = {"spectra": "k_spectra16_m", "spectra_pairs": "k_spectra_pairs_m", "fused": "k_fused"}[name]
     return {"kernel": kern, "bound": "alu", "achieved": ach, "peak": FP32_PEAK_TFLOPS, "unit": "TFLOP/s",
             "frac": ach / FP32_PEAK_TFLOPS, "traffic": read_traffic(name, workload),
-            "avg_launch_ms": avg_ms, "algorithmic_flops_per_launch": flops, "per_unit": per_unit,
-            "peak_note": "non-packed FP32 FMA rate (packed FP32 is not used): 256 CU x 4 SIMD x 16 lanes x 2 x 2.4 GHz"}
+            "avg_launch_ms": avg_ms, "algorithmic_flops_per_launch": flops, "per_unit": per_unit}
 
 
 def main():

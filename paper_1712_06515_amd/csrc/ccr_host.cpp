@@ -81,10 +81,11 @@ struct Band {
     int Q = 0;
     // device tables
     DevBuf d_x, d_mask, d_anchor, d_earth, d_win64, d_win32, d_cheb_x, d_cheb_T, d_tw64, d_tw32, d_bin_m, d_bin_p,
-        d_bin_kb, d_bin_pos, d_segw, d_active, d_work, d_seg_work, d_tmpl, d_lagph;
+        d_bin_kb, d_bin_pos, d_segw, d_active, d_work, d_seg_work, d_tmpl, d_lagph, d_seg_any;
     int bins_unique = 0;
     int n_work = 0;
     int newton_steps = 3, cheb_split = kCheb;
+    int n_seg_any = 0;
     std::vector<double> freqs;
     std::vector<uint8_t> active;
 };
@@ -508,6 +509,16 @@ ccr_status prepare(ccr_ctx *c, Band &B) {
     if ((st = upload(c, B.d_tw64, tw64))) return st;
     if ((st = upload(c, B.d_tw32, tw32))) return st;
     if ((st = upload(c, B.d_lagph, lagph))) return st;
+    {
+        std::vector<int> any;
+        for (int64_t K = 0; K < M; ++K) {
+            bool a = false;
+            for (int X = 0; X < Q; ++X) a = a || B.active[(size_t)X * M + K];
+            if (a) any.push_back((int)K);
+        }
+        B.n_seg_any = (int)any.size();
+        if ((st = upload(c, B.d_seg_any, any))) return st;
+    }
     if ((st = upload(c, B.d_bin_m, bm))) return st;
     if ((st = upload(c, B.d_bin_p, bp))) return st;
     if ((st = upload(c, B.d_bin_kb, bkb))) return st;
@@ -647,6 +658,8 @@ BandDev band_dev(const Band &B) {
     d.n_work = B.n_work;
     d.tmpl = B.d_tmpl.as<double>();
     d.lagph = B.d_lagph.as<float2>();
+    d.seg_any = B.d_seg_any.as<int>();
+    d.n_seg_any = B.n_seg_any;
     d.newton_steps = B.newton_steps;
     d.cheb_split = B.cheb_split;
     return d;

@@ -75,6 +75,8 @@ struct BandDev {
     // lag phases of the pair sum, lagph[dl n_f + i] = exp(+2 pi i kbar_i dl n_k / N_FFT), dl <= R:
     // F*_XK F_YL = lagph(K - L) conj(F~_XK) F~_YL for spectra F~ taken without Phi_in
     const float2 *lagph;
+    const int *seg_any;       // [n_seg_any] ascending segments K where some detector is active
+    int n_seg_any;
     int newton_steps;         // Newton steps of the time-base node solve (2 or 3)
     int cheb_split;           // Chebyshev terms the split path sums (kChebSplit or kCheb)
 };

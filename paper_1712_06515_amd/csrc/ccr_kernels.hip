@@ -35,6 +35,14 @@ template <typename T> __device__ __forceinline__ const c2<T> *twiddles(const Ban
 template <> __device__ __forceinline__ const float2 *twiddles<float>(const BandDev &B) { return B.tw32; }
 template <> __device__ __forceinline__ const double2 *twiddles<double>(const BandDev &B) { return B.tw64; }
 
+// Orders the LDS accesses of one wavefront around this point (compiler ordering only: the
+// hardware executes a wavefront's LDS operations in issue order).
+__device__ __forceinline__ void wave_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
 // ------------------------------------------------------------------ time base (FP64)
 
 // sin(x) and cos(x) - 1 by their Taylor series through x^11 / x^12; |x| <= 0.3 keeps the
@@ -337,10 +345,41 @@ __device__ __forceinline__ c2<T> interpolate_window(const BandDev &B, const floa
     return mk<T>(re, im);
 }
 
-// Resampler: one 64-thread workgroup per (template, active segment), looping over the segment's
-// samples; the segment's Chebyshev coefficients and anchor are uniform (scalar loads).
+// Tap sum with every tap inside a zero-padded window (no bounds checks): the w0 form for the
+// tap-indexed window, else the general taps.
+template <typename T, int DT, int WIN>
+__device__ __forceinline__ c2<T> interpolate_inside(const BandDev &B, const float2 *xc, double dcd, const T *cw) {
+    const T dc = (T)dcd;
+    if constexpr (WIN == 0 && DT > 0) {
+        return interpolate_w0_inside<T, DT>(cw, xc, dc);
+    } else {
+        const int D = DT > 0 ? DT : B.D;
+        const T s = sin_pi<T>(dc) * (T)0.318309886183790671537767526745;
+        const T *wt = win_table<T>(B);
+        const T inv_d1 = (T)1 / (T)(D + 1);
+        T re = 0, im = 0;
+        for (int n = -D; n <= D; ++n) {
+            const T wv = tap_weight<T, WIN>(wt, D, inv_d1, dc, s, n);
+            const float2 xv = xc[n];
+            re = fma(wv, (T)xv.x, re);
+            im = fma(wv, (T)xv.y, im);
+        }
+        return mk<T>(re, im);
+    }
+}
+
+// Input window of one 64-sample pass of the resampler: j* is nondecreasing in the sample index
+// (t(tau) is increasing), so the pass needs x'[j*_first - D, j*_last + D], at most 64 + 2D + 1
+// samples plus the drift; kResWin holds that with room to spare.
+constexpr int kResWin = 128;
+
+// Resampler: one 64-lane workgroup (one wavefront) per (template, active segment), looping over
+// the segment's samples 64 at a time; the segment's Chebyshev coefficients and anchor are
+// uniform (scalar loads).  Each pass stages its input window in LDS (two coalesced loads per
+// lane, zero outside the data) and every lane reads its 2D + 1 taps from there.
 template <typename T, int DT, int WIN, int NC = kCheb>
 __device__ __forceinline__ void resample_body(const BandDev &B, const double *coef, c2<T> *y, int w, int tb) {
+    __shared__ float2 win[kResWin];
     const int entry = B.work[w];
     const int det = entry / B.n_seg;
     const int K = entry - det * B.n_seg;
@@ -355,20 +394,40 @@ __device__ __forceinline__ void resample_body(const BandDev &B, const double *co
     const Anchor an = B.anchors[entry];
     const double inv_nk = 1.0 / (double)B.n_k;
     const int64_t r0 = (int64_t)K * B.n_k;
+    const int D = DT > 0 ? DT : B.D;
+    const int lane = threadIdx.x;
     T cw[2 * (DT > 0 ? DT : 0) + 1];
     if constexpr (WIN == 0 && DT > 0) load_signed_window<T, DT>(B, cw);
-    for (int s = threadIdx.x; s < B.n_k; s += 64) {
-        if (!mk_[s]) {
-            yo[s] = mk<T>((T)0, (T)0);
-            continue;
+    for (int s0 = 0; s0 < B.n_k; s0 += 64) {
+        const int s = s0 + lane;
+        const bool in = s < B.n_k;
+        const bool m = in && mk_[s];
+        int64_t jstar = r0 + s;
+        double dc = 0.0, psi = 0.0;
+        if (in) sample_time<NC>(cl, (double)(2 * s - B.n_k) * inv_nk, an, B.inv_dt, B.f_het, r0 + s, jstar, dc, psi);
+        // window bounds from the pass's first and last samples (shifts relative to r0 fit 32 bits)
+        const int last = min(63, B.n_k - 1 - s0);
+        const int jrel = (int)(jstar - r0);
+        const int lo_rel = __builtin_amdgcn_readlane(jrel, 0) - D;
+        const int span = __builtin_amdgcn_readlane(jrel, last) + D - lo_rel + 1;
+        c2<T> acc = mk<T>((T)0, (T)0);
+        if (span <= kResWin) {
+            const int64_t j_lo = r0 + lo_rel;
+            wave_sync();  // the previous pass's reads of the window are done (one wavefront)
+            for (int k = lane; k < span; k += 64) {
+                const int64_t j = j_lo + k;
+                win[k] = (j >= 0 && j < B.n) ? xd[j] : make_float2(0.f, 0.f);
+            }
+            wave_sync();
+            if (m) acc = interpolate_inside<T, DT, WIN>(B, win + (int)(jstar - j_lo), dc, cw);
+        } else if (m) {
+            acc = interpolate<T, DT, WIN>(B, xd, jstar, dc, cw);
         }
-        int64_t jstar;
-        double dc, psi;
-        sample_time<NC>(cl, (double)(2 * s - B.n_k) * inv_nk, an, B.inv_dt, B.f_het, r0 + s, jstar, dc, psi);
-        const c2<T> acc = interpolate<T, DT, WIN>(B, xd, jstar, dc, cw);
-        T c, sn;
-        sincos_rev<T>(psi, sn, c);
-        yo[s] = mk<T>(c * acc.x - sn * acc.y, sn * acc.x + c * acc.y);
+        if (in) {
+            T c, sn;
+            sincos_rev<T>(psi, sn, c);
+            yo[s] = m ? mk<T>(c * acc.x - sn * acc.y, sn * acc.x + c * acc.y) : mk<T>((T)0, (T)0);
+        }
     }
 }
 
@@ -460,13 +519,6 @@ __device__ c2<T> *stockham(c2<T> *a, c2<T> *b, int n, const c2<T> *tw, int n_fft
 // bins kbar = m P + p, apply Phi_in = exp(-2 pi i kbar r_B / N_FFT) and 1 / (sigma sqrt N_K).
 // ------------------------------------------------------------------ register FFT (256 points)
 
-// Orders the LDS accesses of one wavefront around this point (compiler ordering only: the
-// hardware executes a wavefront's LDS operations in issue order).
-__device__ __forceinline__ void wave_sync() {
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-}
 
 // 4-point forward DFT in place: (a0, a1, a2, a3) -> sum_n a_n exp(-2 pi i n k / 4).
 template <typename T>
@@ -587,7 +639,8 @@ k_spectra16(BandDev B, const c2<T> *y, c2<T> *F) {
 
 // Spectra + pair sum for 256-point segments (split precision, distinct bins): one wavefront =
 // one template x one chunk of segments [K0, K1) (plus R halo segments before K0).  Each step
-// transforms S = 4 / Q consecutive segments of every detector, one 16-lane group per
+// transforms the next S = 4 / Q segments that take part in some pair (a compacted list; wholly
+// idle segments are skipped) of every detector, one 16-lane group per
 // (segment, detector), into an LDS ring of R + S decimated spectra, then accumulates each
 // bin's pair sum for the step's segments in the same order as k_pairs.  The segment spectra
 // never leave LDS and the workgroup is a single wavefront, so no step needs a block barrier;
@@ -596,15 +649,15 @@ constexpr int kSpairMaxRounds = 8;  // bins per lane: n_f <= 64 * kSpairMaxRound
 
 struct SpairLayout {
     int S, slots, cand;
-    size_t off_ring, off_list, off_meta, off_flag, off_pos, total;
+    size_t off_ring, off_list, off_meta, off_flag, off_slotk, off_pos, total;
 };
 
-// cand = candidate pairs per step: S segments x Q detectors x (R+1) partner segments x Q.
+// cand = candidate pairs per step: S segments x Q detectors x ring slots x Q.
 __host__ __device__ inline SpairLayout spair_layout(int Q, int n_f, int R, int n_fft) {
     SpairLayout L;
     L.S = 4 / Q < 1 ? 1 : 4 / Q;
     L.slots = R + L.S;
-    L.cand = L.S * Q * (R + 1) * Q;
+    L.cand = L.S * Q * L.slots * Q;
     size_t o = 4 * 16 * 17 * sizeof(float2);  // transpose scratch of the 4 groups
     L.off_ring = o;
     o += (size_t)L.slots * Q * (n_f + 1) * sizeof(float2);
@@ -615,6 +668,9 @@ __host__ __device__ inline SpairLayout spair_layout(int Q, int n_f, int R, int n
     o += (size_t)L.slots * Q * 16;   // (hat a, hat b) of the spectrum in each ring slot
     L.off_flag = o;
     o += (size_t)L.slots * Q;
+    o = (o + 15) & ~(size_t)15;
+    L.off_slotk = o;                  // segment held by each ring slot, -1 if none
+    o += (size_t)L.slots * sizeof(int);
     o = (o + 15) & ~(size_t)15;
     L.off_pos = o;                    // ring column of FFT output (p, k2, t), n_f if unused
     o += (size_t)n_fft * sizeof(int16_t);
@@ -632,6 +688,7 @@ __device__ __forceinline__ void spectra_pairs_body(const BandDev &B, const float
     int4 *lst = reinterpret_cast<int4 *>(smem + Ly.off_list);
     double2 *meta = reinterpret_cast<double2 *>(smem + Ly.off_meta);
     uint8_t *flag = smem + Ly.off_flag;
+    int *slotk = reinterpret_cast<int *>(smem + Ly.off_slotk);
     int16_t *opos = reinterpret_cast<int16_t *>(smem + Ly.off_pos);
     const int lane = threadIdx.x;
     const int grp = lane >> 4, t = lane & 15;
@@ -655,19 +712,32 @@ __device__ __forceinline__ void spectra_pairs_body(const BandDev &B, const float
         opos[e] = (int16_t)(i >= 0 ? i : n_f);
     }
     for (int e = lane; e < slots * Q; e += 64) flag[e] = 0;
+    for (int e = lane; e < slots; e += 64) slotk[e] = -1;
+    // the steps visit only segments where some detector takes part in a pair: the band's sorted
+    // list seg_any, entries [lo, hi) for the chunk with its halo [Kh, K1)
+    auto lower = [&](int key) {
+        int a = 0, b = B.n_seg_any;
+        while (a < b) {
+            const int m = (a + b) >> 1;
+            if (B.seg_any[m] < key) a = m + 1;
+            else b = m;
+        }
+        return a;
+    };
+    const int lo = lower(Kh), hi = lower(K1);
     double acc[NR];
 #pragma unroll
     for (int r = 0; r < NR; ++r) acc[r] = 0.0;
     const int rounds = (n_f + 63) >> 6;
 
-    int slot_b = Kh % slots;  // ring slot of segment Kb
+    int slot_b = 0;  // ring slot of the step's first entry
     // this group's samples for the next step, loaded while the current step's pairs are summed
     float2 yv[16];
     // unconditional loads, then a select (no branches): samples past n_k belong to the next
     // segment or, after the last one, to the workspace's 256-sample tail pad
-    auto load_y = [&](int Kn) {
-        const bool in = used && Kn < K1;
-        const float2 *ysn = ybase + (size_t)(in ? Kn : 0) * n_k + t;
+    auto load_y = [&](int e) {
+        const bool in = used && e < hi;
+        const float2 *ysn = ybase + (size_t)(in ? B.seg_any[e] : 0) * n_k + t;
 #pragma unroll
         for (int n1 = 0; n1 < 16; ++n1) {
             const float2 v = ysn[16 * n1];
@@ -675,12 +745,12 @@ __device__ __forceinline__ void spectra_pairs_body(const BandDev &B, const float
             yv[n1] = make_float2(keep ? v.x : 0.f, keep ? v.y : 0.f);
         }
     };
-    load_y(Kh + sd);
+    load_y(lo + sd);
     wave_sync();
-    for (int Kb = Kh; Kb < K1; Kb += S) {
-        const int ns = min(S, K1 - Kb);
-        const int K = Kb + sd;
+    for (int eb = lo; eb < hi; eb += S) {
+        const int ns = min(S, hi - eb);
         const bool mine = used && sd < ns;
+        const int K = mine ? B.seg_any[eb + sd] : 0;
         const bool on = mine && B.seg_work[X * B.n_seg + K] >= 0;
         int myslot = slot_b + sd;
         if (myslot >= slots) myslot -= slots;
@@ -689,6 +759,7 @@ __device__ __forceinline__ void spectra_pairs_body(const BandDev &B, const float
             const SegWeight sw = B.segw[X * B.n_seg + K];
             flag[myslot * Q + X] = on ? 1 : 0;
             meta[myslot * Q + X] = make_double2(sw.ahat * sw.scale, sw.bhat * sw.scale);
+            if (X == 0) slotk[myslot] = K;
         }
         float2 *Fo = ring + ((size_t)myslot * Q + X) * n_f1;
         for (int p = 0; p < P; ++p) {
@@ -708,11 +779,12 @@ __device__ __forceinline__ void spectra_pairs_body(const BandDev &B, const float
                 for (int k2 = 0; k2 < 16; ++k2) Fo[op[16 * k2]] = v[4 * (k2 & 3) + (k2 >> 2)];
             }
         }
-        load_y(K + S);
+        load_y(eb + sd + S);
         wave_sync();
-        // pair list of the step, compacted with a ballot: segment Kc of the step with detector
-        // Xc, partner (Y, L = Kc - dl): L < Kc any detector allowed by the pair kinds, L = Kc
-        // only Y > Xc across detectors; both spectra present
+        // pair list of the step, compacted with a ballot: step entry s2 (segment Kc, detector
+        // Xc) with the spectrum of ring slot j (segment Kj, detector Y), dl = Kc - Kj: lags
+        // 0 < dl <= R for any detector the pair kinds allow, dl = 0 (the entry itself) for
+        // Y > Xc across detectors; both spectra present, Kc inside the chunk
         int ne = 0;
         for (int c0 = 0; c0 < Ly.cand; c0 += 64) {
             const int cd = c0 + lane;
@@ -721,22 +793,23 @@ __device__ __forceinline__ void spectra_pairs_body(const BandDev &B, const float
             float W = 0.f;
             if (cd < Ly.cand) {
                 const int Y = cd % Q;
-                const int dl = (cd / Q) % (B.R + 1);
-                const int Xc = (cd / (Q * (B.R + 1))) % Q;
-                const int s2 = cd / (Q * (B.R + 1) * Q);
-                const int Kc = Kb + s2, L = Kc - dl;
-                if (s2 < ns && Kc >= K0 && L >= 0) {
+                const int j = (cd / Q) % slots;
+                const int Xc = (cd / (Q * slots)) % Q;
+                const int s2 = cd / (Q * slots * Q);
+                if (s2 < ns) {
                     int slot = slot_b + s2;
                     if (slot >= slots) slot -= slots;
-                    int sl = slot - dl;
-                    if (sl < 0) sl += slots;
-                    const bool inc = (dl > 0) ? ((Y != Xc) ? cross : same) : (cross && Y > Xc);
-                    if (inc && flag[slot * Q + Xc] && flag[sl * Q + Y]) {
+                    const int Kc = slotk[slot], Kj = slotk[j];
+                    const int dl = Kc - Kj;
+                    const bool inc = (Kj >= 0 && Kc >= K0) &&
+                                     ((dl > 0 && dl <= B.R) ? ((Y != Xc) ? cross : same)
+                                                            : (dl == 0 && j == slot && cross && Y > Xc));
+                    if (inc && flag[slot * Q + Xc] && flag[j * Q + Y]) {
                         valid = true;
-                        const double2 wk = meta[slot * Q + Xc], wl = meta[sl * Q + Y];
+                        const double2 wk = meta[slot * Q + Xc], wl = meta[j * Q + Y];
                         W = (float)(wk.x * wl.x + wk.y * wl.y);
                         o1 = (slot * Q + Xc) * n_f1;
-                        o2 = (sl * Q + Y) * n_f1;
+                        o2 = (j * Q + Y) * n_f1;
                         dl_c = dl;
                     }
                 }
@@ -1181,6 +1254,7 @@ __device__ __forceinline__ BandDev global_view(const BandDev &b, const void *bas
     g.seg_work = as_global(b.seg_work, base);
     g.tmpl = as_global(b.tmpl, base);
     g.lagph = as_global(b.lagph, base);
+    g.seg_any = as_global(b.seg_any, base);
     return g;
 }
 
