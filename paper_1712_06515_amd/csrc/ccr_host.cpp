@@ -905,6 +905,7 @@ ccr_status build_plan(ccr_ctx *c, bool fp64, int n_bands, const int *band_ids, v
             q.coef = coef1 * nb;
             q.lds = v.sp ? spectra_pairs_lds(bd) : 0;
             for (int st = 0; st < kStages; ++st) q.blk[st] = per_t[st] * nb;
+            q.blk[kStResample] = per_t[kStResample] * ((nb + kResTemplates - 1) / kResTemplates);
             pend.push_back(q);
         }
     }

@@ -106,6 +106,7 @@ constexpr int kTbEntries = 16;       // time base: work entries per workgroup (x
 constexpr int kSpec16Groups = 8;     // 256-point register FFT: segments per 128-thread workgroup
 constexpr int kPairsThreads = 128;   // pair sum: bins per workgroup
 constexpr int kFinishThreads = 256;  // finish: bins per workgroup
+constexpr int kResTemplates = 4;     // resampling: templates per workgroup
 
 // Launchers (ccr_kernels.hip).  All queue work on `stream` and return the launch status.
 // Chebyshev coefficients of the time base, coef[n_tmpl][n_work][kCheb].

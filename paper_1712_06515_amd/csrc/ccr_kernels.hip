@@ -373,24 +373,21 @@ __device__ __forceinline__ c2<T> interpolate_inside(const BandDev &B, const floa
 // samples plus the drift; kResWin holds that with room to spare.
 constexpr int kResWin = 128;
 
-// Resampler: one 64-lane workgroup (one wavefront) per (template, active segment), looping over
-// the segment's samples 64 at a time; the segment's Chebyshev coefficients and anchor are
-// uniform (scalar loads).  Each pass stages its input window in LDS (two coalesced loads per
-// lane, zero outside the data) and every lane reads its 2D + 1 taps from there.
+// Resampler: one 64-lane workgroup (one wavefront) per (active segment, templates [t0, t1)),
+// looping over the segment's samples 64 at a time for each template; the segment's anchor and
+// window coefficients are loaded once, each template's Chebyshev coefficients are uniform
+// (scalar loads).  Each pass stages its input window in LDS (two coalesced loads per lane,
+// zero outside the data) and every lane reads its 2D + 1 taps from there.
 template <typename T, int DT, int WIN, int NC = kCheb>
-__device__ __forceinline__ void resample_body(const BandDev &B, const double *coef, c2<T> *y, int w, int tb) {
+__device__ __forceinline__ void resample_body(const BandDev &B, const double *coef, c2<T> *y, int w, int t0,
+                                              int t1) {
     __shared__ float2 win[kResWin];
     const int entry = B.work[w];
     const int det = entry / B.n_seg;
     const int K = entry - det * B.n_seg;
     const int64_t nr = (int64_t)B.n_seg * B.n_k;
-    c2<T> *yo = y + ((size_t)tb * B.Q + det) * nr + (size_t)K * B.n_k;
     const uint8_t *mk_ = B.mask + (size_t)det * nr + (size_t)K * B.n_k;
     const float2 *xd = B.x + (size_t)det * B.n;
-    const double *cf = coef + ((size_t)tb * B.n_work + w) * kCheb;
-    double cl[kCheb];
-#pragma unroll
-    for (int k = 0; k < kCheb; ++k) cl[k] = cf[k];
     const Anchor an = B.anchors[entry];
     const double inv_nk = 1.0 / (double)B.n_k;
     const int64_t r0 = (int64_t)K * B.n_k;
@@ -398,6 +395,12 @@ __device__ __forceinline__ void resample_body(const BandDev &B, const double *co
     const int lane = threadIdx.x;
     T cw[2 * (DT > 0 ? DT : 0) + 1];
     if constexpr (WIN == 0 && DT > 0) load_signed_window<T, DT>(B, cw);
+    for (int tb = t0; tb < t1; ++tb) {
+    c2<T> *yo = y + ((size_t)tb * B.Q + det) * nr + (size_t)K * B.n_k;
+    const double *cf = coef + ((size_t)tb * B.n_work + w) * kCheb;
+    double cl[kCheb];
+#pragma unroll
+    for (int k = 0; k < kCheb; ++k) cl[k] = cf[k];
     for (int s0 = 0; s0 < B.n_k; s0 += 64) {
         const int s = s0 + lane;
         const bool in = s < B.n_k;
@@ -429,11 +432,12 @@ __device__ __forceinline__ void resample_body(const BandDev &B, const double *co
             yo[s] = m ? mk<T>(c * acc.x - sn * acc.y, sn * acc.x + c * acc.y) : mk<T>((T)0, (T)0);
         }
     }
+    }
 }
 
 template <typename T, int DT, int WIN>
 __global__ void __launch_bounds__(64) k_resample(BandDev B, const double *coef, c2<T> *y) {
-    resample_body<T, DT, WIN>(B, coef, y, blockIdx.x, blockIdx.y);
+    resample_body<T, DT, WIN>(B, coef, y, blockIdx.x, blockIdx.y, blockIdx.y + 1);
 }
 
 // Time base samples of one detector's segments [k0, k0 + n) for one template (stage output).
@@ -1284,7 +1288,8 @@ k_resample_m(const BandDev *__restrict__ bands, const WorkItem *__restrict__ ite
     const WorkItem &it = items[find_item(items, n_items, kStResample, blockIdx.x)];
     const BandDev B = global_view(bands[it.band], bands);
     const int l = blockIdx.x - it.first[kStResample], gx = it.gx[kStResample];
-    resample_body<T, DT, WIN, NC>(B, coef + it.coef_off, y + it.y_off, l % gx, l / gx);
+    const int t0 = (l / gx) * kResTemplates;
+    resample_body<T, DT, WIN, NC>(B, coef + it.coef_off, y + it.y_off, l % gx, t0, min(it.n_tmpl, t0 + kResTemplates));
 }
 
 template <int NR>
