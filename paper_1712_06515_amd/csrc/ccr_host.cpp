@@ -80,7 +80,7 @@ struct Band {
     Plan plan;
     int Q = 0;
     // device tables
-    DevBuf d_x, d_mask, d_anchor, d_earth, d_win64, d_win32, d_cheb_x, d_cheb_T, d_tw64, d_tw32, d_bin_m, d_bin_p,
+    DevBuf d_x, d_mask, d_anchor, d_earth, d_win64, d_win32, d_cheb_x, d_mono, d_tw64, d_tw32, d_bin_m, d_bin_p,
         d_bin_kb, d_bin_pos, d_segw, d_active, d_work, d_seg_work, d_tmpl, d_lagph, d_seg_any;
     int bins_unique = 0;
     int n_work = 0;
@@ -487,12 +487,32 @@ ccr_status prepare(ccr_ctx *c, Band &B) {
         B.prepared = true;
         return CCR_OK;
     }
-    // Chebyshev nodes and the cosine matrix of the coefficient transform
-    std::vector<double> cx(kCheb), cT(kCheb * kCheb);
-    for (int j = 0; j < kCheb; ++j) {
-        cx[j] = (double)cosl(kPiL * ((long double)j + 0.5L) / kCheb);
-        for (int k = 0; k < kCheb; ++k)
-            cT[k * kCheb + j] = (double)cosl(kPiL * (long double)k * ((long double)j + 0.5L) / kCheb);
+    // Chebyshev nodes x_j of an N-node rule (N = kCheb, then N = kChebSplit) and the maps from
+    // node values to the monomial coefficients of the interpolant: Chebyshev coefficients
+    // c_k = (2 / N) sum_j eta_j T_k(x_j) (c_0 halved), then the monomial coefficients of each
+    // T_k (T_{k+1} = 2 x T_k - T_{k-1}); long double, rows and columns beyond N zero
+    std::vector<double> cx(kCheb + kChebSplit), mono(2 * kCheb * kCheb, 0.0);
+    {
+        long double Tm[kCheb][kCheb] = {};  // Tm[k][m]: coefficient of x^m in T_k
+        Tm[0][0] = 1.0L;
+        Tm[1][1] = 1.0L;
+        for (int k = 1; k + 1 < kCheb; ++k)
+            for (int m = 0; m < kCheb; ++m)
+                Tm[k + 1][m] = (m > 0 ? 2.0L * Tm[k][m - 1] : 0.0L) - Tm[k - 1][m];
+        for (int v = 0; v < 2; ++v) {
+            const int N = v == 0 ? kCheb : kChebSplit;
+            for (int j = 0; j < N; ++j) cx[(v ? kCheb : 0) + j] = (double)cosl(kPiL * ((long double)j + 0.5L) / N);
+            for (int m = 0; m < N; ++m)
+                for (int j = 0; j < N; ++j) {
+                    long double a = 0.0L;
+                    for (int k = 0; k < N; ++k) {
+                        const long double ck = (k == 0 ? 1.0L : 2.0L) / N *
+                                               cosl(kPiL * (long double)k * ((long double)j + 0.5L) / N);
+                        a += Tm[k][m] * ck;
+                    }
+                    mono[((size_t)v * kCheb + m) * kCheb + j] = (double)a;
+                }
+        }
     }
     // device upload
     std::vector<float2> xs((size_t)Q * n);
@@ -505,7 +525,7 @@ ccr_status prepare(ccr_ctx *c, Band &B) {
     if ((st = upload(c, B.d_win64, w64))) return st;
     if ((st = upload(c, B.d_win32, w32))) return st;
     if ((st = upload(c, B.d_cheb_x, cx))) return st;
-    if ((st = upload(c, B.d_cheb_T, cT))) return st;
+    if ((st = upload(c, B.d_mono, mono))) return st;
     if ((st = upload(c, B.d_tw64, tw64))) return st;
     if ((st = upload(c, B.d_tw32, tw32))) return st;
     if ((st = upload(c, B.d_lagph, lagph))) return st;
@@ -560,8 +580,9 @@ ccr_status prepare_templates(ccr_ctx *c, Band &B) {
     // e0 = de + a_p Omega (a_p + de) (de: Earth-delay change over the segment), and each step
     // maps e -> K e^2 with K = G''/(2 G'); two steps suffice when K^3 e0^4 < 1e-20 s.
     // Chebyshev: the series of A sin(omega u + phi) on [-h, h] has coefficients 2A J_k(omega h)
-    // <= 2A (omega h / 2)^k / k!; the split path drops terms 7..9 when their sum stays below
-    // 1e-9 cycles of the top frequency and 1e-9 samples.
+    // <= 2A (omega h / 2)^k / k!; the split path interpolates at 7 nodes (error at most twice the
+    // tail from k = 7) when twice the tail stays below 1e-9 cycles of the top frequency and 1e-9
+    // samples.
     {
         double Aw = 0.0, Aw2 = 0.0;
         std::vector<std::pair<double, double>> comps;  // (amplitude, angular rate) of the Earth terms
@@ -597,7 +618,7 @@ ccr_status prepare_templates(ccr_ctx *c, Band &B) {
         }
         const double f_top = B.p.f_min + B.p.f_band;
         B.newton_steps = worst_e2 < 1e-20 ? 2 : 3;
-        B.cheb_split = (worst_tail * f_top < 1e-9 && worst_tail / (double)dt < 1e-9) ? kChebSplit : kCheb;
+        B.cheb_split = (2.0 * worst_tail * f_top < 1e-9 && 2.0 * worst_tail / (double)dt < 1e-9) ? kChebSplit : kCheb;
     }
     B.tmpl.assign((size_t)T * kTmplStride, 0.0);
     for (int64_t t = 0; t < T; ++t) {
@@ -643,7 +664,7 @@ BandDev band_dev(const Band &B) {
     d.win64 = B.d_win64.as<double>();
     d.win32 = B.d_win32.as<float>();
     d.cheb_x = B.d_cheb_x.as<double>();
-    d.cheb_T = B.d_cheb_T.as<double>();
+    d.mono = B.d_mono.as<double>();
     d.tw64 = B.d_tw64.as<double2>();
     d.tw32 = B.d_tw32.as<float2>();
     d.bin_m = B.d_bin_m.as<int>();
@@ -779,10 +800,11 @@ ccr_status compute_fused(ccr_ctx *c, Band &B, const BandDev &bd, bool fp64, int 
 struct Variant {
     bool sp = false;     // spectra + pair sum in one kernel
     bool reg16 = false;  // otherwise: 256-point register FFT (else the LDS Stockham FFT on n_s points)
+    bool z4 = false;     // spectra + pair sum: N_K <= 192 (4 of the 16 FFT input rows are zero)
     int DT = 0, window = 0, n_s = 0, nr = 0, n_cheb = kCheb;
     bool operator==(const Variant &o) const {
-        return sp == o.sp && reg16 == o.reg16 && DT == o.DT && window == o.window && n_s == o.n_s && nr == o.nr &&
-               n_cheb == o.n_cheb;
+        return sp == o.sp && reg16 == o.reg16 && z4 == o.z4 && DT == o.DT && window == o.window && n_s == o.n_s &&
+               nr == o.nr && n_cheb == o.n_cheb;
     }
 };
 
@@ -816,6 +838,7 @@ Variant variant_of(const BandDev &bd, bool fp64) {
     v.n_cheb = fp64 ? kCheb : bd.cheb_split;
     if (v.sp) {
         v.nr = spectra_pairs_rounds(bd);
+        v.z4 = bd.n_k <= 192;
     } else {
         v.reg16 = !fp64 && bd.n_s == 256 && bd.bins_unique;
         if (!v.reg16) v.n_s = bd.n_s;
@@ -880,7 +903,7 @@ ccr_status build_plan(ccr_ctx *c, bool fp64, int n_bands, const int *band_ids, v
         proto.n_chunks = nch;
         proto.factor = pl.norm > 0.0 ? std::sqrt(2.0) / pl.norm : 0.0;
         proto.out_fp64 = out_fp64 ? 1 : 0;
-        proto.gx[kStTimebase] = (B.n_work + kTbEntries - 1) / kTbEntries;
+        proto.gx[kStTimebase] = (B.n_work + tb_entries(v.n_cheb) - 1) / tb_entries(v.n_cheb);
         proto.gx[kStResample] = B.n_work;
         proto.gx[kStSpectra] = v.sp ? nch : (v.reg16 ? (B.n_work + kSpec16Groups - 1) / kSpec16Groups : B.n_work);
         proto.gx[kStPairs] = v.sp ? 0 : (int)((pl.n_f + kPairsThreads - 1) / kPairsThreads);
@@ -986,7 +1009,7 @@ ccr_status run_rounds(ccr_ctx *c, const CallPlan &cp, size_t r0, size_t r1, bool
         const WorkItem *di = ditems + r.i0;
         {
             LaunchTimer lt(c, 5, s, timing);
-            HIP_OK(c, launch_timebase_m(db, di, r.n, (int)r.blocks[kStTimebase], coef, s));
+            HIP_OK(c, launch_timebase_m(db, di, r.n, (int)r.blocks[kStTimebase], r.v.n_cheb, coef, s));
         }
         {
             LaunchTimer lt(c, 0, s, timing);
@@ -995,7 +1018,7 @@ ccr_status run_rounds(ccr_ctx *c, const CallPlan &cp, size_t r0, size_t r1, bool
         }
         if (r.v.sp) {
             LaunchTimer lt(c, 6, s, timing);
-            HIP_OK(c, launch_spectra_pairs_m(db, di, r.n, (int)r.blocks[kStSpectra], r.v.nr, r.lds, c->ws_y.p, part, s));
+            HIP_OK(c, launch_spectra_pairs_m(db, di, r.n, (int)r.blocks[kStSpectra], r.v.nr, r.v.z4, r.lds, c->ws_y.p, part, s));
         } else {
             {
                 LaunchTimer lt(c, 1, s, timing);

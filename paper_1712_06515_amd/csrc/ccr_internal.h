@@ -34,8 +34,8 @@ struct SegWeight {
 // of segment K's mid-time as c0 + K c1 in double-double: c0h, c0l, c1h, c1l.
 constexpr int kTmplStride = 6;
 
-// Chebyshev nodes per segment for the time base; the split path may sum only the first
-// kChebSplit coefficients when the host's bound on the rest allows; detector limit.
+// Chebyshev nodes per segment for the time base; the split path may use kChebSplit nodes
+// (degree 6) when the host's bound on the Chebyshev tail allows; detector limit.
 constexpr int kCheb = 10;
 constexpr int kChebSplit = 7;
 #define CCR_MAX_DET_K 8
@@ -57,8 +57,9 @@ struct BandDev {
     const EarthConst *earth;  // [Q]
     const double *win64;      // [2D+1] tap window (window == 0)
     const float *win32;
-    const double *cheb_x;     // [kCheb] cos(pi (j + 1/2) / kCheb)
-    const double *cheb_T;     // [kCheb][kCheb] cos(pi k (j + 1/2) / kCheb)
+    const double *cheb_x;     // [kCheb] cos(pi (j + 1/2) / kCheb), then [kChebSplit] likewise
+    const double *mono;       // [2][kCheb][kCheb] node values -> monomial coefficients of the
+                              // interpolant through kCheb (0) or kChebSplit (1) Chebyshev nodes
     const double2 *tw64;      // [n_fft] exp(-2 pi i j / n_fft)
     const float2 *tw32;
     const int *bin_m;         // [n_f] FFT output index within residue class
@@ -78,7 +79,7 @@ struct BandDev {
     const int *seg_any;       // [n_seg_any] ascending segments K where some detector is active
     int n_seg_any;
     int newton_steps;         // Newton steps of the time-base node solve (2 or 3)
-    int cheb_split;           // Chebyshev terms the split path sums (kChebSplit or kCheb)
+    int cheb_split;           // Chebyshev terms the split path keeps (kChebSplit or kCheb)
 };
 
 // One work item of a batched launch: a run of consecutive templates of one band.  A batched
@@ -102,14 +103,15 @@ struct WorkItem {
 };
 
 // Block geometry shared by the host planner and the kernels.
-constexpr int kTbEntries = 16;       // time base: work entries per workgroup (x kCheb threads)
+// time base: work entries per workgroup for NN nodes (x NN threads: whole wavefronts)
+constexpr int tb_entries(int nn) { return nn == kCheb ? 32 : 64; }
 constexpr int kSpec16Groups = 8;     // 256-point register FFT: segments per 128-thread workgroup
 constexpr int kPairsThreads = 128;   // pair sum: bins per workgroup
 constexpr int kFinishThreads = 256;  // finish: bins per workgroup
 constexpr int kResTemplates = 4;     // resampling: templates per workgroup
 
 // Launchers (ccr_kernels.hip).  All queue work on `stream` and return the launch status.
-// Chebyshev coefficients of the time base, coef[n_tmpl][n_work][kCheb].
+// Monomial coefficients of the time base (interpolant through Chebyshev nodes), coef[n_tmpl][n_work][kCheb].
 hipError_t launch_timebase(const BandDev &B, const double *d_tmpl, int n_tmpl, double *coef,
                            hipStream_t stream);
 hipError_t launch_resample(const BandDev &B, const double *coef, int n_tmpl, bool fp64, void *y,
@@ -133,12 +135,13 @@ hipError_t launch_finish(const BandDev &B, int n_tmpl, const double *part, int n
 size_t spectra_pairs_lds(const BandDev &B);
 int spectra_pairs_rounds(const BandDev &B);  // bins per lane of the spectra+pairs kernel (3 or 8)
 int spectra_threads(int n_s);               // threads of the LDS Stockham FFT workgroup
-hipError_t launch_timebase_m(const BandDev *bands, const WorkItem *items, int n_items, int blocks, double *coef,
+hipError_t launch_timebase_m(const BandDev *bands, const WorkItem *items, int n_items, int blocks, int n_cheb, double *coef,
                              hipStream_t stream);
 hipError_t launch_resample_m(const BandDev *bands, const WorkItem *items, int n_items, int blocks, bool fp64, int D,
                              int window, int n_cheb, const double *coef, void *y, hipStream_t stream);
+// z4: N_K <= 192, so the last 4 of the 16 input rows of each 256-point FFT are zero padding.
 hipError_t launch_spectra_pairs_m(const BandDev *bands, const WorkItem *items, int n_items, int blocks, int rounds,
-                                  size_t lds, const void *y, double *part, hipStream_t stream);
+                                  bool z4, size_t lds, const void *y, double *part, hipStream_t stream);
 // reg16: the 256-point register FFT (split precision, distinct bins); else the LDS Stockham FFT
 // with `threads` threads and 2 n_s complex values of LDS.
 hipError_t launch_spectra_m(const BandDev *bands, const WorkItem *items, int n_items, int blocks, bool fp64,

@@ -103,52 +103,60 @@ __device__ __forceinline__ double node_eta(double u, double a_p, double Om, doub
     return eta;
 }
 
-// eta(u) over a segment, u in [-h, h] with h = N_K dt / 2, as a Chebyshev series of degree
-// kCheb - 1: node values at u_j = h cos(pi (j + 1/2) / kCheb), coefficients
-// c_k = (2 / kCheb) sum_j eta_j cos(pi k (j + 1/2) / kCheb), c_0 stored halved.  eta is an
-// entire function whose k-th coefficient is bounded by a_p (Omega h / 2)^k / k!, so degree 9
-// keeps the truncation below 1e-16 s for segments up to ~6000 s.
-// Threads 0..kCheb-1 of `lanes` compute the nodes of one (detector, segment).
-__device__ __forceinline__ double cheb_coef(const double *eta, const double *T, int k) {
+// eta(u) over a segment, u in [-h, h] with h = N_K dt / 2: the degree kCheb - 1 polynomial
+// through the values at the Chebyshev nodes u_j = h cos(pi (j + 1/2) / kCheb), stored by its
+// monomial coefficients in x = u / h: eta = sum_m p_m x^m.  eta is an entire function whose k-th
+// Chebyshev coefficient is bounded by a_p (Omega h / 2)^k / k!, so degree 9 keeps the
+// truncation below 1e-16 s for segments up to ~6000 s.  The host's table maps node values to
+// p_m (row m of `V`); it is applied to differences from the first node, which are small, so
+// the large entries of the monomial transform do not amplify the rounding of eta itself.
+// Thread k of an entry computes p_k from its NN node values (table rows and columns < NN).
+template <int NN>
+__device__ __forceinline__ double mono_coef(const double *eta, const double *V, int k) {
+    const double e0 = eta[0];
     double c = 0.0;
 #pragma unroll
-    for (int j = 0; j < kCheb; ++j) c = fma(eta[j], T[k * kCheb + j], c);
-    c *= 2.0 / kCheb;
-    return k == 0 ? 0.5 * c : c;
+    for (int j = 1; j < NN; ++j) c = fma(eta[j] - e0, V[k * kCheb + j], c);
+    return k == 0 ? e0 + c : c;
 }
 
-// Per sample: eta by Clenshaw at x = u / h, then the interpolation centre j* = r +
+// Per sample: eta by Horner at x = u / h, then the interpolation centre j* = r +
 // round-half-up(Delta / dt), the offset delta_c = Delta / dt - round(.) in [-1/2, 1/2) and the
 // heterodyne phase frac(f_h Delta) = frac(psi_a + f_h eta), cycles.
-// NC <= kCheb leading coefficients are summed (the split path drops a tail the host bounds).
+// NC must be at least the number of nonzero coefficients the time base wrote.
+template <int NC = kCheb>
+__device__ __forceinline__ double eta_at(const double *coef, double x) {
+    double eta = coef[NC - 1];
+#pragma unroll
+    for (int k = NC - 2; k >= 0; --k) eta = fma(eta, x, coef[k]);
+    return eta;
+}
+
 template <int NC = kCheb>
 __device__ __forceinline__ void sample_time(const double *coef, double x, const Anchor &an, double inv_dt,
                                             double f_het, int64_t r, int64_t &jstar, double &dc, double &psi) {
-    double b1 = 0.0, b2 = 0.0;
-    const double x2 = 2.0 * x;
-#pragma unroll
-    for (int k = NC - 1; k >= 1; --k) {
-        const double b0 = fma(x2, b1, coef[k] - b2);
-        b2 = b1;
-        b1 = b0;
-    }
-    const double eta = fma(x, b1, coef[0] - b2);
+    const double eta = eta_at<NC>(coef, x);
     const double q = (eta - an.D_a) * inv_dt;
     const double k = floor(q + 0.5);
-    jstar = r + (int64_t)(int)k;  // |delay| / dt < 2^31 (the host bounds dt and the delay)
+    jstar = r + (int64_t)(int)k;  // |delay| / dt < 2^30 (the host bounds dt and the delay)
     dc = q - k;
     const double ps = fma(f_het, eta, an.psi_a);
     psi = ps - floor(ps);
 }
 
 // Time base kernel: one thread per (template, active segment entry, Chebyshev node).  Writes the
-// kCheb coefficients of eta(u) for every (template, entry): coef[tb][entry][k].  16 entries x
-// kCheb nodes per workgroup; node values meet in LDS for the coefficient transform.
+// monomial coefficients of eta(u) for every (template, entry): coef[tb][entry][k], k < NN.
+// NN = kCheb nodes (degree 9) for the FP64 path; NN = kChebSplit nodes (degree 6) when the
+// split path keeps only kChebSplit terms (the host's bound covers the interpolation error, at
+// most twice the dropped Chebyshev tail).  tb_entries(NN) entries x NN nodes per workgroup
+// (whole wavefronts); node values meet in LDS for the coefficient transform.
+template <int NN>
 __device__ __forceinline__ void timebase_body(const BandDev &B, const double *tmpl, double *coef, int bx, int tb) {
-    __shared__ double sh_eta[kTbEntries * kCheb];
-    const int le = threadIdx.x / kCheb;           // entry within the workgroup
-    const int j = threadIdx.x - le * kCheb;       // node (and later coefficient) index
-    const int w = bx * kTbEntries + le;           // entry in the work list
+    constexpr int E = tb_entries(NN);
+    __shared__ double sh_eta[E * NN];
+    const int le = threadIdx.x / NN;              // entry within the workgroup
+    const int j = threadIdx.x - le * NN;          // node (and later coefficient) index
+    const int w = bx * E + le;                    // entry in the work list
     const bool on = w < B.n_work;
     if (on) {
         const int entry = B.work[w];
@@ -158,15 +166,17 @@ __device__ __forceinline__ void timebase_body(const BandDev &B, const double *tm
         double sb, cb;
         binary_anchor(tp, K, sb, cb);
         const double h = 0.5 * (double)B.n_k * B.dt;
-        sh_eta[threadIdx.x] = node_eta(h * B.cheb_x[j], tp[0], tp[1], sb, cb, B.earth[det], B.anchors[entry],
+        const double *xn = B.cheb_x + (NN == kCheb ? 0 : kCheb);
+        sh_eta[threadIdx.x] = node_eta(h * xn[j], tp[0], tp[1], sb, cb, B.earth[det], B.anchors[entry],
                                        B.newton_steps);
     }
     __syncthreads();
-    if (on) coef[((size_t)tb * B.n_work + w) * kCheb + j] = cheb_coef(sh_eta + le * kCheb, B.cheb_T, j);
+    const double *V = B.mono + (NN == kCheb ? 0 : kCheb * kCheb);
+    if (on) coef[((size_t)tb * B.n_work + w) * kCheb + j] = mono_coef<NN>(sh_eta + le * NN, V, j);
 }
 
-__global__ void __launch_bounds__(kTbEntries * kCheb) k_timebase(BandDev B, const double *tmpl, double *coef) {
-    timebase_body(B, tmpl, coef, blockIdx.x, blockIdx.y);
+__global__ void __launch_bounds__(tb_entries(kCheb) * kCheb) k_timebase(BandDev B, const double *tmpl, double *coef) {
+    timebase_body<kCheb>(B, tmpl, coef, blockIdx.x, blockIdx.y);
 }
 
 // ------------------------------------------------------------------ resampling
@@ -372,6 +382,7 @@ __device__ __forceinline__ c2<T> interpolate_inside(const BandDev &B, const floa
 // (t(tau) is increasing), so the pass needs x'[j*_first - D, j*_last + D], at most 64 + 2D + 1
 // samples plus the drift; kResWin holds that with room to spare.
 constexpr int kResWin = 128;
+static_assert(kResWin == 128, "the interior window fill loads 2 x 64 entries");
 
 // Resampler: one 64-lane workgroup (one wavefront) per (active segment, templates [t0, t1)),
 // looping over the segment's samples 64 at a time for each template; the segment's anchor and
@@ -398,9 +409,9 @@ __device__ __forceinline__ void resample_body(const BandDev &B, const double *co
     for (int tb = t0; tb < t1; ++tb) {
     c2<T> *yo = y + ((size_t)tb * B.Q + det) * nr + (size_t)K * B.n_k;
     const double *cf = coef + ((size_t)tb * B.n_work + w) * kCheb;
-    double cl[kCheb];
+    double cl[NC];
 #pragma unroll
-    for (int k = 0; k < kCheb; ++k) cl[k] = cf[k];
+    for (int k = 0; k < NC; ++k) cl[k] = cf[k];
     for (int s0 = 0; s0 < B.n_k; s0 += 64) {
         const int s = s0 + lane;
         const bool in = s < B.n_k;
@@ -417,9 +428,16 @@ __device__ __forceinline__ void resample_body(const BandDev &B, const double *co
         if (span <= kResWin) {
             const int64_t j_lo = r0 + lo_rel;
             wave_sync();  // the previous pass's reads of the window are done (one wavefront)
-            for (int k = lane; k < span; k += 64) {
-                const int64_t j = j_lo + k;
-                win[k] = (j >= 0 && j < B.n) ? xd[j] : make_float2(0.f, 0.f);
+            if (j_lo >= 0 && j_lo + kResWin <= B.n) {
+                // interior (uniform branch): the whole LDS window, no bounds checks
+                const float2 *xw = xd + j_lo;
+                win[lane] = xw[lane];
+                win[lane + 64] = xw[lane + 64];
+            } else {
+                for (int k = lane; k < span; k += 64) {
+                    const int64_t j = j_lo + k;
+                    win[k] = (j >= 0 && j < B.n) ? xd[j] : make_float2(0.f, 0.f);
+                }
             }
             wave_sync();
             if (m) acc = interpolate_inside<T, DT, WIN>(B, win + (int)(jstar - j_lo), dc, cw);
@@ -452,17 +470,11 @@ __global__ void __launch_bounds__(64) k_time_samples(BandDev B, const double *co
     const double inv_nk = 1.0 / (double)B.n_k;
     for (int s = threadIdx.x; s < B.n_k; s += 64) {
         const double x = (double)(2 * s - B.n_k) * inv_nk;
-        double b1 = 0.0, b2 = 0.0;
-        for (int k = kCheb - 1; k >= 1; --k) {
-            const double b0 = fma(2.0 * x, b1, cf[k] - b2);
-            b2 = b1;
-            b1 = b0;
-        }
         int64_t jstar;
         double dc, ps;
         sample_time(cf, x, an, B.inv_dt, B.f_het, (int64_t)K * B.n_k + s, jstar, dc, ps);
         const size_t o = (size_t)blockIdx.x * B.n_k + s;
-        eta[o] = fma(x, b1, cf[0] - b2);
+        eta[o] = eta_at(cf, x);
         psi[o] = ps;
     }
 }
@@ -535,13 +547,28 @@ __device__ __forceinline__ void dft4(c2<T> &a0, c2<T> &a1, c2<T> &a2, c2<T> &a3)
     a3 = csub<T>(t1, t3);
 }
 
-// 16-point forward DFT in registers, n = 4a + b, k = c + 4d: 4-point DFTs over a, twiddles
-// W16^(b c), 4-point DFTs over b.  On return A[k] is held in v[4 (k % 4) + k / 4].
+// 4-point DFT whose last input is zero.
 template <typename T>
+__device__ __forceinline__ void dft4_z(c2<T> &a0, c2<T> &a1, c2<T> &a2, c2<T> &a3) {
+    const c2<T> t0 = cadd<T>(a0, a2), t1 = csub<T>(a0, a2);
+    const c2<T> t3 = cmul_mi<T>(a1);
+    a0 = cadd<T>(t0, a1);
+    a2 = csub<T>(t0, a1);
+    a3 = csub<T>(t1, t3);
+    a1 = cadd<T>(t1, t3);
+}
+
+// 16-point forward DFT in registers, n = 4a + b, k = c + 4d: 4-point DFTs over a, twiddles
+// W16^(b c), 4-point DFTs over b.  On return A[k] is held in v[4 (k % 4) + k / 4].  Z4: the
+// inputs v[12..15] are zero (their values are not read).
+template <typename T, bool Z4 = false>
 __device__ __forceinline__ void dft16(c2<T> *v) {
     const T c1 = (T)0.92387953251128675613, s1 = (T)0.38268343236508977173, h = (T)0.70710678118654752440;
 #pragma unroll
-    for (int b = 0; b < 4; ++b) dft4<T>(v[b], v[4 + b], v[8 + b], v[12 + b]);
+    for (int b = 0; b < 4; ++b) {
+        if constexpr (Z4) dft4_z<T>(v[b], v[4 + b], v[8 + b], v[12 + b]);
+        else dft4<T>(v[b], v[4 + b], v[8 + b], v[12 + b]);
+    }
     // v[4c + b] *= W16^(b c)
     v[5] = cmul<T>(v[5], mk<T>(c1, -s1));    // b1 c1: W^1
     v[6] = cmul<T>(v[6], mk<T>(h, -h));      // b2 c1: W^2
@@ -565,21 +592,28 @@ __device__ __forceinline__ void dft16(c2<T> *v) {
 // execute in issue order); every lane of the wave calls it.
 // `pre` (applied when `has_pre`) multiplies every stage-1 output of the lane: the per-lane part
 // of a residue-class input twiddle, folded into the W256 twiddles.
+// Stage 1 of the 256-point FFT below: 16-point DFTs over n1, then the twiddles (and `pre`).
+template <typename T, bool Z4 = false>
+__device__ __forceinline__ void fft256_stage1(c2<T> *v, int t, const c2<T> *tw, int tw_stride, bool has_pre,
+                                              c2<T> pre) {
+    dft16<T, Z4>(v);
+    // pre * W256^(t k1) by recurrence from W256^t (FP32 rounding grows to ~1e-6 by k1 = 15)
+    const c2<T> w1 = tw[t * tw_stride];
+    c2<T> wk = has_pre ? cmul<T>(pre, w1) : w1;
+    if (has_pre) v[0] = cmul<T>(v[0], pre);
+#pragma unroll
+    for (int k1 = 1; k1 < 16; ++k1) {
+        const int pos = 4 * (k1 & 3) + (k1 >> 2);
+        v[pos] = cmul<T>(v[pos], wk);
+        wk = cmul<T>(wk, w1);
+    }
+}
+
 template <typename T>
 __device__ __forceinline__ void fft256_lanes(c2<T> *v, int t, c2<T> *sc, const c2<T> *tw, int tw_stride,
                                              bool on, bool has_pre = false, c2<T> pre = c2<T>{}) {
     if (on) {
-        dft16<T>(v);
-        // pre * W256^(t k1) by recurrence from W256^t (FP32 rounding grows to ~1e-6 by k1 = 15)
-        const c2<T> w1 = tw[t * tw_stride];
-        c2<T> wk = has_pre ? cmul<T>(pre, w1) : w1;
-        if (has_pre) v[0] = cmul<T>(v[0], pre);
-#pragma unroll
-        for (int k1 = 1; k1 < 16; ++k1) {
-            const int pos = 4 * (k1 & 3) + (k1 >> 2);
-            v[pos] = cmul<T>(v[pos], wk);
-            wk = cmul<T>(wk, w1);
-        }
+        fft256_stage1<T>(v, t, tw, tw_stride, has_pre, pre);
 #pragma unroll
         for (int k1 = 0; k1 < 16; ++k1) sc[k1 * 17 + t] = v[4 * (k1 & 3) + (k1 >> 2)];
     }
@@ -588,6 +622,36 @@ __device__ __forceinline__ void fft256_lanes(c2<T> *v, int t, c2<T> *sc, const c
 #pragma unroll
         for (int n2 = 0; n2 < 16; ++n2) v[n2] = sc[t * 17 + n2];
         dft16<T>(v);
+    }
+    wave_sync();
+}
+
+// The same FFT with half the scratch: the transpose moves the real parts, then the imaginary
+// parts, through a 16 x 17 float array.  A lane has written all its real parts before it
+// overwrites them with the transposed ones, so no extra registers are needed.
+template <bool Z4>
+__device__ __forceinline__ void fft256_lanes_half(float2 *v, int t, float *sc, const float2 *tw, int tw_stride,
+                                                  bool on, bool has_pre, float2 pre) {
+    if (on) {
+        fft256_stage1<float, Z4>(v, t, tw, tw_stride, has_pre, pre);
+#pragma unroll
+        for (int k1 = 0; k1 < 16; ++k1) sc[k1 * 17 + t] = v[4 * (k1 & 3) + (k1 >> 2)].x;
+    }
+    wave_sync();
+    if (on) {
+#pragma unroll
+        for (int n2 = 0; n2 < 16; ++n2) v[n2].x = sc[t * 17 + n2];
+    }
+    wave_sync();  // every lane's reads of the real parts precede the writes below
+    if (on) {
+#pragma unroll
+        for (int k1 = 0; k1 < 16; ++k1) sc[k1 * 17 + t] = v[4 * (k1 & 3) + (k1 >> 2)].y;
+    }
+    wave_sync();
+    if (on) {
+#pragma unroll
+        for (int n2 = 0; n2 < 16; ++n2) v[n2].y = sc[t * 17 + n2];
+        dft16<float>(v);
     }
     wave_sync();
 }
@@ -662,7 +726,7 @@ __host__ __device__ inline SpairLayout spair_layout(int Q, int n_f, int R, int n
     L.S = 4 / Q < 1 ? 1 : 4 / Q;
     L.slots = R + L.S;
     L.cand = L.S * Q * L.slots * Q;
-    size_t o = 4 * 16 * 17 * sizeof(float2);  // transpose scratch of the 4 groups
+    size_t o = 4 * 16 * 17 * sizeof(float);  // transpose scratch of the 4 groups (one component at a time)
     L.off_ring = o;
     o += (size_t)L.slots * Q * (n_f + 1) * sizeof(float2);
     o = (o + 15) & ~(size_t)15;
@@ -682,7 +746,7 @@ __host__ __device__ inline SpairLayout spair_layout(int Q, int n_f, int R, int n
     return L;
 }
 
-template <int NR>
+template <int NR, bool Z4>
 __device__ __forceinline__ void spectra_pairs_body(const BandDev &B, const float2 *y, double *part, int k_chunk,
                                                    int n_chunks, int c, int tb) {
     extern __shared__ __align__(16) unsigned char smem[];
@@ -703,7 +767,7 @@ __device__ __forceinline__ void spectra_pairs_body(const BandDev &B, const float
     const int64_t nr = (int64_t)B.n_seg * n_k;
     const float2 *tw = B.tw32;
     const bool cross = (B.pairs & 1) != 0, same = (B.pairs & 2) != 0;
-    float2 *sc = reinterpret_cast<float2 *>(smem) + grp * 16 * 17;
+    float *sc = reinterpret_cast<float *>(smem) + grp * 16 * 17;
     const int sd = grp / Q, X = grp - sd * Q;  // this group's (segment in step, detector)
     const bool used = sd < S;                  // Q = 3: the fourth group idles
     const int n_f1 = n_f + 1;                  // ring rows hold a dummy entry for unused outputs
@@ -743,7 +807,7 @@ __device__ __forceinline__ void spectra_pairs_body(const BandDev &B, const float
         const bool in = used && e < hi;
         const float2 *ysn = ybase + (size_t)(in ? B.seg_any[e] : 0) * n_k + t;
 #pragma unroll
-        for (int n1 = 0; n1 < 16; ++n1) {
+        for (int n1 = 0; n1 < (Z4 ? 12 : 16); ++n1) {
             const float2 v = ysn[16 * n1];
             const bool keep = in && 16 * n1 + t < n_k;
             yv[n1] = make_float2(keep ? v.x : 0.f, keep ? v.y : 0.f);
@@ -773,8 +837,8 @@ __device__ __forceinline__ void spectra_pairs_body(const BandDev &B, const float
             float2 v[16];
             const int tstride = 16 * p;
 #pragma unroll
-            for (int n1 = 0; n1 < 16; ++n1) v[n1] = p ? cmul<float>(yv[n1], tw[tstride * n1]) : yv[n1];
-            fft256_lanes<float>(v, t, sc, tw, B.n_fft >> 8, on, p != 0, tw[p * t]);
+            for (int n1 = 0; n1 < (Z4 ? 12 : 16); ++n1) v[n1] = p ? cmul<float>(yv[n1], tw[tstride * n1]) : yv[n1];
+            fft256_lanes_half<Z4>(v, t, sc, tw, B.n_fft >> 8, on, p != 0, tw[p * t]);
             if (on) {
                 // the spectrum without Phi_in and normalisation: both enter the pair sum (the
                 // normalisation through the weights, Phi_in as the lag phase of each pair)
@@ -1245,7 +1309,7 @@ __device__ __forceinline__ BandDev global_view(const BandDev &b, const void *bas
     g.win64 = as_global(b.win64, base);
     g.win32 = as_global(b.win32, base);
     g.cheb_x = as_global(b.cheb_x, base);
-    g.cheb_T = as_global(b.cheb_T, base);
+    g.mono = as_global(b.mono, base);
     g.tw64 = as_global(b.tw64, base);
     g.tw32 = as_global(b.tw32, base);
     g.bin_m = as_global(b.bin_m, base);
@@ -1273,12 +1337,14 @@ __device__ __forceinline__ int find_item(const WorkItem *__restrict__ items, int
     return lo;
 }
 
-__global__ void __launch_bounds__(kTbEntries * kCheb)
-k_timebase_m(const BandDev *__restrict__ bands, const WorkItem *__restrict__ items, int n_items, double *__restrict__ coef) {
+template <int NN>
+__global__ void __launch_bounds__(tb_entries(NN) * NN)
+k_timebase_m(const BandDev *__restrict__ bands, const WorkItem *__restrict__ items, int n_items,
+             double *__restrict__ coef) {
     const WorkItem &it = items[find_item(items, n_items, kStTimebase, blockIdx.x)];
     const BandDev B = global_view(bands[it.band], bands);
     const int l = blockIdx.x - it.first[kStTimebase], gx = it.gx[kStTimebase];
-    timebase_body(B, B.tmpl + (size_t)it.tmpl_off * kTmplStride, coef + it.coef_off, l % gx, l / gx);
+    timebase_body<NN>(B, B.tmpl + (size_t)it.tmpl_off * kTmplStride, coef + it.coef_off, l % gx, l / gx);
 }
 
 template <typename T, int DT, int WIN, int NC>
@@ -1292,14 +1358,14 @@ k_resample_m(const BandDev *__restrict__ bands, const WorkItem *__restrict__ ite
     resample_body<T, DT, WIN, NC>(B, coef + it.coef_off, y + it.y_off, l % gx, t0, min(it.n_tmpl, t0 + kResTemplates));
 }
 
-template <int NR>
+template <int NR, bool Z4>
 __global__ void __launch_bounds__(64)
 k_spectra_pairs_m(const BandDev *__restrict__ bands, const WorkItem *__restrict__ items, int n_items,
                   const float2 *__restrict__ y, double *__restrict__ part) {
     const WorkItem &it = items[find_item(items, n_items, kStSpectra, blockIdx.x)];
     const BandDev B = global_view(bands[it.band], bands);
     const int l = blockIdx.x - it.first[kStSpectra], gx = it.gx[kStSpectra];
-    spectra_pairs_body<NR>(B, y + it.y_off, part + it.part_off, it.k_chunk, it.n_chunks, l % gx, l / gx);
+    spectra_pairs_body<NR, Z4>(B, y + it.y_off, part + it.part_off, it.k_chunk, it.n_chunks, l % gx, l / gx);
 }
 
 template <typename T>
@@ -1349,7 +1415,8 @@ k_finish_m(const BandDev *__restrict__ bands, const WorkItem *__restrict__ items
 hipError_t launch_timebase(const BandDev &B, const double *d_tmpl, int n_tmpl, double *coef,
                            hipStream_t stream) {
     if (B.n_work == 0 || n_tmpl == 0) return hipSuccess;
-    dim3 grid((B.n_work + kTbEntries - 1) / kTbEntries, n_tmpl), block(kTbEntries * kCheb);
+    constexpr int E = tb_entries(kCheb);
+    dim3 grid((B.n_work + E - 1) / E, n_tmpl), block(E * kCheb);
     hipLaunchKernelGGL(k_timebase, grid, block, 0, stream, B, d_tmpl, coef);
     return hipGetLastError();
 }
@@ -1467,10 +1534,15 @@ int spectra_pairs_rounds(const BandDev &B) { return B.n_f <= 64 * 3 ? 3 : kSpair
 
 int spectra_threads(int n_s) { return n_s / 4 >= 256 ? 256 : (n_s / 4 < 64 ? 64 : n_s / 4); }
 
-hipError_t launch_timebase_m(const BandDev *bands, const WorkItem *items, int n_items, int blocks, double *coef,
-                             hipStream_t stream) {
+hipError_t launch_timebase_m(const BandDev *bands, const WorkItem *items, int n_items, int blocks, int n_cheb,
+                             double *coef, hipStream_t stream) {
     if (blocks == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_timebase_m, dim3(blocks), dim3(kTbEntries * kCheb), 0, stream, bands, items, n_items, coef);
+    if (n_cheb == kCheb)
+        hipLaunchKernelGGL(k_timebase_m<kCheb>, dim3(blocks), dim3(tb_entries(kCheb) * kCheb), 0, stream, bands,
+                           items, n_items, coef);
+    else
+        hipLaunchKernelGGL(k_timebase_m<kChebSplit>, dim3(blocks), dim3(tb_entries(kChebSplit) * kChebSplit), 0,
+                           stream, bands, items, n_items, coef);
     return hipGetLastError();
 }
 
@@ -1501,15 +1573,22 @@ hipError_t launch_resample_m(const BandDev *bands, const WorkItem *items, int n_
     return hipGetLastError();
 }
 
-hipError_t launch_spectra_pairs_m(const BandDev *bands, const WorkItem *items, int n_items, int blocks, int rounds,
-                                  size_t lds, const void *y, double *part, hipStream_t stream) {
-    if (blocks == 0) return hipSuccess;
-    if (rounds == 3)
-        hipLaunchKernelGGL(k_spectra_pairs_m<3>, dim3(blocks), dim3(64), lds, stream, bands, items, n_items,
+template <int NR>
+static void launch_spectra_pairs_m_t(const BandDev *bands, const WorkItem *items, int n_items, int blocks, bool z4,
+                                     size_t lds, const void *y, double *part, hipStream_t stream) {
+    if (z4)
+        hipLaunchKernelGGL((k_spectra_pairs_m<NR, true>), dim3(blocks), dim3(64), lds, stream, bands, items, n_items,
                            (const float2 *)y, part);
     else
-        hipLaunchKernelGGL(k_spectra_pairs_m<kSpairMaxRounds>, dim3(blocks), dim3(64), lds, stream, bands, items,
+        hipLaunchKernelGGL((k_spectra_pairs_m<NR, false>), dim3(blocks), dim3(64), lds, stream, bands, items,
                            n_items, (const float2 *)y, part);
+}
+
+hipError_t launch_spectra_pairs_m(const BandDev *bands, const WorkItem *items, int n_items, int blocks, int rounds,
+                                  bool z4, size_t lds, const void *y, double *part, hipStream_t stream) {
+    if (blocks == 0) return hipSuccess;
+    if (rounds == 3) launch_spectra_pairs_m_t<3>(bands, items, n_items, blocks, z4, lds, y, part, stream);
+    else launch_spectra_pairs_m_t<kSpairMaxRounds>(bands, items, n_items, blocks, z4, lds, y, part, stream);
     return hipGetLastError();
 }
 

@@ -262,7 +262,7 @@ def test_time_base_parity(ccr, large_workload):
     oracle's long-double Newton solve of the full time map.  The delay of sample r is returned
     as a small eta and the anchor offset D_a (|D_a| <= 500 s, stored in FP64: half an ulp is
     2.8e-14 s); the phase is carried without that rounding.  Bars from the FP64 arithmetic:
-    |eta| <= a_p + A_o w_o T_short / 2 ~ 2.1 s, so the ten-term Chebyshev evaluation rounds to
+    |eta| <= a_p + A_o w_o T_short / 2 ~ 2.1 s, so evaluating the degree-9 interpolant rounds to
     ~10 eps |eta| ~ 2.3e-15 s, i.e. 1e-12 cycles at 400 Hz; the delay adds the D_a rounding."""
     ds = large_workload
     o = oracle.Oracle(ds)
