@@ -104,13 +104,17 @@ def roofline(name, avg_ms, tb, info, workload):
     ns = 1 << (int(info["n_k"]) - 1).bit_length()
     P = info["n_fft"] // ns
     if name == "resample":
-        # one complex64 sample written and one input sample read per resampled sample
-        byts = n_active * info["n_k"] * tb * 16.0
+        # one complex64 sample written per resampled sample; the input sample is read once per
+        # tile of T_b templates (the templates one workgroup resamples from one staged input
+        # window)
+        T_b = info["resample_templates"]
+        byts = n_active * info["n_k"] * tb * (8.0 + 8.0 / T_b)
         ach = byts / (avg_ms * 1e-3) / 1e9
         return {"kernel": "k_resample_m", "bound": "hbm", "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": ach / HBM_PEAK_GBS, "traffic": read_traffic("resample", workload),
                 "avg_launch_ms": avg_ms, "algorithmic_bytes_per_launch": byts,
-                "per_unit": "16 B per resampled sample (8 B written, 8 B input)"}
+                "per_unit": f"{8.0 + 8.0 / T_b:g} B per resampled sample (8 B written, 8 B input "
+                            f"per tile of {T_b} templates)"}
     flops = n_active * tb * P * (5.0 * ns * np.log2(ns) + 6.0 * ns)
     per_unit = f"P (5 n_s log2 n_s + 6 n_s) FP32 flop per (template, detector, segment), n_s={ns}, P={P}"
     if name in ("spectra_pairs", "fused"):
@@ -165,6 +169,7 @@ def main():
     ctx.set_option("fused", args.fused)
     bid = ctx.load(ds)
     info = ctx.band_info(bid)
+    info["resample_templates"] = ctx.get_option("resample_templates")
     n_t, n_f = info["n_templates"], info["n_f"]
     out = torch.empty((n_t, n_f), dtype=torch.float32, device="cuda")
     stream = torch.cuda.current_stream()

@@ -159,8 +159,9 @@ const char *ccr_last_error(const ccr_ctx *ctx);
 ccr_status ccr_set_option(ccr_ctx *ctx, const char *name, int64_t value);
 
 /* Read an option set with ccr_set_option, or "tuned_k_chunk" / "tuned_template_batch": the
- * launch shape the autotuner chose last (0 before any tuning).  CCR_EUNSUP for an unknown
- * name. */
+ * launch shape the autotuner chose last (0 before any tuning), or "resample_templates": the
+ * templates one resampling workgroup handles from one staged input window (a constant of the
+ * build).  CCR_EUNSUP for an unknown name. */
 ccr_status ccr_get_option(ccr_ctx *ctx, const char *name, int64_t *value);
 
 /* Add a band; returns its id and the part of the plan known before data (n_k, dt, f_het,

@@ -1285,6 +1285,7 @@ ccr_status ccr_get_option(ccr_ctx *c, const char *name, int64_t *value) {
     else if (k == "items_per_launch") *value = c->opt_items_per_launch;
     else if (k == "tuned_k_chunk") *value = c->last_tuned_k_chunk;
     else if (k == "tuned_template_batch") *value = c->last_tuned_template_batch;
+    else if (k == "resample_templates") *value = kResTemplates;
     else return fail(c, CCR_EUNSUP, "unknown option '%s'", name);
     return CCR_OK;
 }

@@ -154,6 +154,18 @@ template <int NN>
 __device__ __forceinline__ void timebase_body(const BandDev &B, const double *tmpl, double *coef, int bx, int tb) {
     constexpr int E = tb_entries(NN);
     __shared__ double sh_eta[E * NN];
+    __shared__ double2 sh_bin[E];
+    const double *tp = tmpl + (size_t)kTmplStride * tb;
+    // the binary phase at each entry's anchor, once per entry (threads 0 .. E - 1)
+    if (threadIdx.x < E) {
+        const int w0 = bx * E + (int)threadIdx.x;
+        if (w0 < B.n_work) {
+            double sb, cb;
+            binary_anchor(tp, B.work[w0] % B.n_seg, sb, cb);
+            sh_bin[threadIdx.x] = make_double2(sb, cb);
+        }
+    }
+    __syncthreads();
     const int le = threadIdx.x / NN;              // entry within the workgroup
     const int j = threadIdx.x - le * NN;          // node (and later coefficient) index
     const int w = bx * E + le;                    // entry in the work list
@@ -161,10 +173,8 @@ __device__ __forceinline__ void timebase_body(const BandDev &B, const double *tm
     if (on) {
         const int entry = B.work[w];
         const int det = entry / B.n_seg;
-        const int K = entry - det * B.n_seg;
-        const double *tp = tmpl + (size_t)kTmplStride * tb;
-        double sb, cb;
-        binary_anchor(tp, K, sb, cb);
+        const double2 bn = sh_bin[le];
+        const double sb = bn.x, cb = bn.y;
         const double h = 0.5 * (double)B.n_k * B.dt;
         const double *xn = B.cheb_x + (NN == kCheb ? 0 : kCheb);
         sh_eta[threadIdx.x] = node_eta(h * xn[j], tp[0], tp[1], sb, cb, B.earth[det], B.anchors[entry],
