@@ -81,7 +81,7 @@ struct Band {
     int Q = 0;
     // device tables
     DevBuf d_x, d_mask, d_anchor, d_earth, d_win64, d_win32, d_cheb_x, d_mono, d_tw64, d_tw32, d_bin_m, d_bin_p,
-        d_bin_kb, d_bin_pos, d_segw, d_active, d_work, d_seg_work, d_tmpl, d_lagph, d_seg_any;
+        d_bin_kb, d_bin_pos, d_segw, d_active, d_work, d_seg_work, d_tmpl, d_lagph, d_seg_any, d_col_bin, d_bin_col, d_zero256;
     int bins_unique = 0;
     int n_work = 0;
     int newton_steps = 3, cheb_split = kCheb;
@@ -463,14 +463,23 @@ ccr_status prepare(ccr_ctx *c, Band &B) {
         tw64[j] = make_double2((double)cosl(a), (double)sinl(a));
         tw32[j] = make_float2((float)cosl(a), (float)sinl(a));
     }
-    // lag phases of the pair sum (spectra taken without Phi_in)
+    // ring columns of the spectra + pair-sum kernel: bins ordered by (residue class, index in
+    // the class), so the 16 lanes of an FFT group, which hold consecutive outputs of one class,
+    // write consecutive columns
+    std::vector<int> col_bin(pl.n_f), bin_col(pl.n_f);
+    for (int64_t i = 0; i < pl.n_f; ++i) col_bin[i] = (int)i;
+    std::stable_sort(col_bin.begin(), col_bin.end(),
+                     [&](int a, int b) { return bp[a] != bp[b] ? bp[a] < bp[b] : bm[a] < bm[b]; });
+    for (int64_t cc = 0; cc < pl.n_f; ++cc) bin_col[col_bin[cc]] = (int)cc;
+    // lag phases of the pair sum (spectra taken without Phi_in), in ring-column order
     const int64_t Rl = B.p.max_lag;
     std::vector<float2> lagph((size_t)(Rl + 1) * pl.n_f);
     for (int64_t dl = 0; dl <= Rl; ++dl)
-        for (int64_t i = 0; i < pl.n_f; ++i) {
+        for (int64_t cc = 0; cc < pl.n_f; ++cc) {
+            const int64_t i = col_bin[cc];
             const int64_t e = (int64_t)(((__int128)bkb[i] * dl * pl.n_k) % pl.n_fft);
             const long double a = 2.0L * kPiL * (long double)e / (long double)pl.n_fft;
-            lagph[(size_t)(dl * pl.n_f + i)] = make_float2((float)cosl(a), (float)sinl(a));
+            lagph[(size_t)(dl * pl.n_f + cc)] = make_float2((float)cosl(a), (float)sinl(a));
         }
     const int D = B.p.dirichlet_D;
     std::vector<double> w64(2 * D + 1);
@@ -529,6 +538,9 @@ ccr_status prepare(ccr_ctx *c, Band &B) {
     if ((st = upload(c, B.d_tw64, tw64))) return st;
     if ((st = upload(c, B.d_tw32, tw32))) return st;
     if ((st = upload(c, B.d_lagph, lagph))) return st;
+    if ((st = upload(c, B.d_col_bin, col_bin))) return st;
+    if ((st = upload(c, B.d_bin_col, bin_col))) return st;
+    if ((st = upload(c, B.d_zero256, std::vector<float2>(256, make_float2(0.f, 0.f))))) return st;
     {
         std::vector<int> any;
         for (int64_t K = 0; K < M; ++K) {
@@ -679,6 +691,9 @@ BandDev band_dev(const Band &B) {
     d.n_work = B.n_work;
     d.tmpl = B.d_tmpl.as<double>();
     d.lagph = B.d_lagph.as<float2>();
+    d.col_bin = B.d_col_bin.as<int>();
+    d.bin_col = B.d_bin_col.as<int>();
+    d.zero256 = B.d_zero256.as<float2>();
     d.seg_any = B.d_seg_any.as<int>();
     d.n_seg_any = B.n_seg_any;
     d.newton_steps = B.newton_steps;

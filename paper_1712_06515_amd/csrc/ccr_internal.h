@@ -73,9 +73,13 @@ struct BandDev {
     const int *seg_work;      // [Q][n_seg] position of (det, K) in `work`, -1 if inactive
     int n_work;
     const double *tmpl;       // [n_templates][kTmplStride] template table
-    // lag phases of the pair sum, lagph[dl n_f + i] = exp(+2 pi i kbar_i dl n_k / N_FFT), dl <= R:
-    // F*_XK F_YL = lagph(K - L) conj(F~_XK) F~_YL for spectra F~ taken without Phi_in
+    // lag phases of the pair sum, lagph[dl n_f + c] = exp(+2 pi i kbar dl n_k / N_FFT) for the
+    // bin of ring column c, dl <= R: F*_XK F_YL = lagph(K - L) conj(F~_XK) F~_YL for spectra F~
+    // taken without Phi_in
     const float2 *lagph;
+    const int *col_bin;       // [n_f] spectra + pair-sum ring: bin of column c (bins ordered by
+    const int *bin_col;       // [n_f] residue class, then index in the class); column of bin i
+    const float2 *zero256;    // [256] zero samples (input of FFT groups without a segment)
     const int *seg_any;       // [n_seg_any] ascending segments K where some detector is active
     int n_seg_any;
     int newton_steps;         // Newton steps of the time-base node solve (2 or 3)

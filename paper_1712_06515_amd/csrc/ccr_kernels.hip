@@ -787,7 +787,7 @@ __device__ __forceinline__ void spectra_pairs_body(const BandDev &B, const float
     for (int e = lane; e < B.n_fft; e += 64) {
         const int tt = e & 15, k2 = (e >> 4) & 15, pp = e >> 8;
         const int i = B.bin_pos[(tt + 16 * k2) * P + pp];
-        opos[e] = (int16_t)(i >= 0 ? i : n_f);
+        opos[e] = (int16_t)(i >= 0 ? B.bin_col[i] : n_f);
     }
     for (int e = lane; e < slots * Q; e += 64) flag[e] = 0;
     for (int e = lane; e < slots; e += 64) slotk[e] = -1;
@@ -811,15 +811,20 @@ __device__ __forceinline__ void spectra_pairs_body(const BandDev &B, const float
     int slot_b = 0;  // ring slot of the step's first entry
     // this group's samples for the next step, loaded while the current step's pairs are summed
     float2 yv[16];
-    // unconditional loads, then a select (no branches): samples past n_k belong to the next
-    // segment or, after the last one, to the workspace's 256-sample tail pad
+    // unconditional loads (no branches); a group without a segment reads the band's 256 zero
+    // samples.  N_K > 128, so rows 16 n1 + t < 128 are always data; of the next 4 rows (the
+    // last 4 of the 12 nonzero ones when Z4) a lane keeps the samples below N_K: samples past
+    // N_K belong to the next segment or, after the last one, to the workspace's tail pad
     auto load_y = [&](int e) {
         const bool in = used && e < hi;
-        const float2 *ysn = ybase + (size_t)(in ? B.seg_any[e] : 0) * n_k + t;
+        const float2 *ysn = (in ? ybase + (size_t)B.seg_any[e] * n_k : B.zero256) + t;
+        constexpr int kFull = Z4 ? 8 : 12, kRows = Z4 ? 12 : 16;
 #pragma unroll
-        for (int n1 = 0; n1 < (Z4 ? 12 : 16); ++n1) {
+        for (int n1 = 0; n1 < kFull; ++n1) yv[n1] = ysn[16 * n1];
+#pragma unroll
+        for (int n1 = kFull; n1 < kRows; ++n1) {
             const float2 v = ysn[16 * n1];
-            const bool keep = in && 16 * n1 + t < n_k;
+            const bool keep = 16 * n1 + t < n_k;
             yv[n1] = make_float2(keep ? v.x : 0.f, keep ? v.y : 0.f);
         }
     };
@@ -936,7 +941,7 @@ __device__ __forceinline__ void spectra_pairs_body(const BandDev &B, const float
 #pragma unroll
     for (int r = 0; r < NR; ++r) {
         const int i = 64 * r + lane;
-        if (r < rounds && i < n_f) part[((size_t)tb * n_chunks + c) * n_f + i] = acc[r];
+        if (r < rounds && i < n_f) part[((size_t)tb * n_chunks + c) * n_f + B.col_bin[i]] = acc[r];
     }
 }
 
@@ -1333,6 +1338,9 @@ __device__ __forceinline__ BandDev global_view(const BandDev &b, const void *bas
     g.tmpl = as_global(b.tmpl, base);
     g.lagph = as_global(b.lagph, base);
     g.seg_any = as_global(b.seg_any, base);
+    g.col_bin = as_global(b.col_bin, base);
+    g.zero256 = as_global(b.zero256, base);
+    g.bin_col = as_global(b.bin_col, base);
     return g;
 }
 
@@ -1363,9 +1371,13 @@ k_resample_m(const BandDev *__restrict__ bands, const WorkItem *__restrict__ ite
              const double *__restrict__ coef, c2<T> *__restrict__ y) {
     const WorkItem &it = items[find_item(items, n_items, kStResample, blockIdx.x)];
     const BandDev B = global_view(bands[it.band], bands);
-    const int l = blockIdx.x - it.first[kStResample], gx = it.gx[kStResample];
-    const int t0 = (l / gx) * kResTemplates;
-    resample_body<T, DT, WIN, NC>(B, coef + it.coef_off, y + it.y_off, l % gx, t0, min(it.n_tmpl, t0 + kResTemplates));
+    // consecutive workgroups take the template tiles of one segment entry, so that they run
+    // together and read the segment's input (and mask) through L2 instead of once per tile
+    const int l = blockIdx.x - it.first[kStResample];
+    const int tiles = (it.n_tmpl + kResTemplates - 1) / kResTemplates;
+    const int t0 = (l % tiles) * kResTemplates;
+    resample_body<T, DT, WIN, NC>(B, coef + it.coef_off, y + it.y_off, l / tiles, t0,
+                                  min(it.n_tmpl, t0 + kResTemplates));
 }
 
 template <int NR, bool Z4>
