@@ -496,11 +496,11 @@ ccr_status prepare(ccr_ctx *c, Band &B) {
         B.prepared = true;
         return CCR_OK;
     }
-    // Chebyshev nodes x_j of an N-node rule (N = kCheb, then N = kChebSplit) and the maps from
+    // Chebyshev nodes x_j of an N-node rule (N = kCheb, kChebSplit, kChebSplitMin) and the maps from
     // node values to the monomial coefficients of the interpolant: Chebyshev coefficients
     // c_k = (2 / N) sum_j eta_j T_k(x_j) (c_0 halved), then the monomial coefficients of each
     // T_k (T_{k+1} = 2 x T_k - T_{k-1}); long double, rows and columns beyond N zero
-    std::vector<double> cx(kCheb + kChebSplit), mono(2 * kCheb * kCheb, 0.0);
+    std::vector<double> cx(kCheb + kChebSplit + kChebSplitMin), mono(3 * kCheb * kCheb, 0.0);
     {
         long double Tm[kCheb][kCheb] = {};  // Tm[k][m]: coefficient of x^m in T_k
         Tm[0][0] = 1.0L;
@@ -508,9 +508,9 @@ ccr_status prepare(ccr_ctx *c, Band &B) {
         for (int k = 1; k + 1 < kCheb; ++k)
             for (int m = 0; m < kCheb; ++m)
                 Tm[k + 1][m] = (m > 0 ? 2.0L * Tm[k][m - 1] : 0.0L) - Tm[k - 1][m];
-        for (int v = 0; v < 2; ++v) {
-            const int N = v == 0 ? kCheb : kChebSplit;
-            for (int j = 0; j < N; ++j) cx[(v ? kCheb : 0) + j] = (double)cosl(kPiL * ((long double)j + 0.5L) / N);
+        for (int N : {kCheb, kChebSplit, kChebSplitMin}) {
+            const int v = cheb_rule(N);
+            for (int j = 0; j < N; ++j) cx[cheb_x_off(N) + j] = (double)cosl(kPiL * ((long double)j + 0.5L) / N);
             for (int m = 0; m < N; ++m)
                 for (int j = 0; j < N; ++j) {
                     long double a = 0.0L;
@@ -592,9 +592,9 @@ ccr_status prepare_templates(ccr_ctx *c, Band &B) {
     // e0 = de + a_p Omega (a_p + de) (de: Earth-delay change over the segment), and each step
     // maps e -> K e^2 with K = G''/(2 G'); two steps suffice when K^3 e0^4 < 1e-20 s.
     // Chebyshev: the series of A sin(omega u + phi) on [-h, h] has coefficients 2A J_k(omega h)
-    // <= 2A (omega h / 2)^k / k!; the split path interpolates at 7 nodes (error at most twice the
-    // tail from k = 7) when twice the tail stays below 1e-9 cycles of the top frequency and 1e-9
-    // samples.
+    // <= 2A (omega h / 2)^k / k!; the split path interpolates at 6 or else 7 nodes (error at most
+    // twice the tail from k = 6 or 7) when twice the tail stays below 1e-9 cycles of the top
+    // frequency and 1e-9 samples.
     {
         double Aw = 0.0, Aw2 = 0.0;
         std::vector<std::pair<double, double>> comps;  // (amplitude, angular rate) of the Earth terms
@@ -606,7 +606,7 @@ ccr_status prepare_templates(ccr_ctx *c, Band &B) {
             comps.push_back({(double)m.A_d, (double)m.w_d});
         }
         const double h = 0.5 * (double)tseg;
-        double worst_e2 = 0.0, worst_tail = 0.0;
+        double worst_e2 = 0.0, worst_tail = 0.0, worst_tail6 = 0.0;
         for (int64_t t = 0; t < T; ++t) {
             const double ap = B.tmpl_raw[3 * t], Om = 2.0 * kPi / B.tmpl_raw[3 * t + 2];
             const double X = h + ap + 1.0;
@@ -615,7 +615,7 @@ ccr_status prepare_templates(ccr_ctx *c, Band &B) {
             const double K = (1.1 * ap * Om * Om + 1.1 * Aw2) / (2.0 * (1.0 - ap * Om) * (1.0 - Aw));
             const double e1 = K * e0 * e0, e2 = K * e1 * e1;
             worst_e2 = std::max(worst_e2, e2);
-            double tail = 0.0;
+            double tail = 0.0, tail6 = 0.0;
             std::vector<std::pair<double, double>> all = comps;
             all.push_back({ap, Om});
             for (const auto &cw : all) {
@@ -624,13 +624,16 @@ ccr_status prepare_templates(ccr_ctx *c, Band &B) {
                 for (int k = 1; k <= 20; ++k) {
                     term *= z / k;
                     if (k >= kChebSplit) tail += term;
+                    if (k >= kChebSplitMin) tail6 += term;
                 }
             }
             worst_tail = std::max(worst_tail, tail);
+            worst_tail6 = std::max(worst_tail6, tail6);
         }
         const double f_top = B.p.f_min + B.p.f_band;
         B.newton_steps = worst_e2 < 1e-20 ? 2 : 3;
-        B.cheb_split = (2.0 * worst_tail * f_top < 1e-9 && 2.0 * worst_tail / (double)dt < 1e-9) ? kChebSplit : kCheb;
+        auto fits = [&](double tl) { return 2.0 * tl * f_top < 1e-9 && 2.0 * tl / (double)dt < 1e-9; };
+        B.cheb_split = fits(worst_tail6) ? kChebSplitMin : (fits(worst_tail) ? kChebSplit : kCheb);
     }
     B.tmpl.assign((size_t)T * kTmplStride, 0.0);
     for (int64_t t = 0; t < T; ++t) {

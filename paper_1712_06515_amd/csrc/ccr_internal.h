@@ -34,10 +34,15 @@ struct SegWeight {
 // of segment K's mid-time as c0 + K c1 in double-double: c0h, c0l, c1h, c1l.
 constexpr int kTmplStride = 6;
 
-// Chebyshev nodes per segment for the time base; the split path may use kChebSplit nodes
-// (degree 6) when the host's bound on the Chebyshev tail allows; detector limit.
+// Chebyshev nodes per segment for the time base; the split path may use kChebSplit or
+// kChebSplitMin nodes (degree 6 or 5) when the host's bound on the Chebyshev tail allows;
+// detector limit.
 constexpr int kCheb = 10;
 constexpr int kChebSplit = 7;
+constexpr int kChebSplitMin = 6;
+// node rules: index of the table of an NN-node rule, and offset of its nodes in cheb_x
+constexpr int cheb_rule(int nn) { return nn == kCheb ? 0 : (nn == kChebSplit ? 1 : 2); }
+constexpr int cheb_x_off(int nn) { return nn == kCheb ? 0 : (nn == kChebSplit ? kCheb : kCheb + kChebSplit); }
 #define CCR_MAX_DET_K 8
 
 // Everything a kernel needs about a band (device pointers + scalars).
@@ -57,9 +62,9 @@ struct BandDev {
     const EarthConst *earth;  // [Q]
     const double *win64;      // [2D+1] tap window (window == 0)
     const float *win32;
-    const double *cheb_x;     // [kCheb] cos(pi (j + 1/2) / kCheb), then [kChebSplit] likewise
-    const double *mono;       // [2][kCheb][kCheb] node values -> monomial coefficients of the
-                              // interpolant through kCheb (0) or kChebSplit (1) Chebyshev nodes
+    const double *cheb_x;     // nodes cos(pi (j + 1/2) / N) for N = kCheb, kChebSplit, kChebSplitMin
+    const double *mono;       // [3][kCheb][kCheb] node values -> monomial coefficients of the
+                              // interpolant through the N Chebyshev nodes (rule cheb_rule(N))
     const double2 *tw64;      // [n_fft] exp(-2 pi i j / n_fft)
     const float2 *tw32;
     const int *bin_m;         // [n_f] FFT output index within residue class
@@ -83,7 +88,7 @@ struct BandDev {
     const int *seg_any;       // [n_seg_any] ascending segments K where some detector is active
     int n_seg_any;
     int newton_steps;         // Newton steps of the time-base node solve (2 or 3)
-    int cheb_split;           // Chebyshev terms the split path keeps (kChebSplit or kCheb)
+    int cheb_split;           // time-base nodes of the split path (kChebSplitMin, kChebSplit or kCheb)
 };
 
 // One work item of a batched launch: a run of consecutive templates of one band.  A batched

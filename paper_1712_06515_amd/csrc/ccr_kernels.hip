@@ -146,8 +146,8 @@ __device__ __forceinline__ void sample_time(const double *coef, double x, const 
 
 // Time base kernel: one thread per (template, active segment entry, Chebyshev node).  Writes the
 // monomial coefficients of eta(u) for every (template, entry): coef[tb][entry][k], k < NN.
-// NN = kCheb nodes (degree 9) for the FP64 path; NN = kChebSplit nodes (degree 6) when the
-// split path keeps only kChebSplit terms (the host's bound covers the interpolation error, at
+// NN = kCheb nodes (degree 9) for the FP64 path; NN = kChebSplit or kChebSplitMin nodes
+// (degree 6 or 5) on the split path when the host's bound covers the interpolation error (at
 // most twice the dropped Chebyshev tail).  tb_entries(NN) entries x NN nodes per workgroup
 // (whole wavefronts); node values meet in LDS for the coefficient transform.
 template <int NN>
@@ -176,12 +176,12 @@ __device__ __forceinline__ void timebase_body(const BandDev &B, const double *tm
         const double2 bn = sh_bin[le];
         const double sb = bn.x, cb = bn.y;
         const double h = 0.5 * (double)B.n_k * B.dt;
-        const double *xn = B.cheb_x + (NN == kCheb ? 0 : kCheb);
+        const double *xn = B.cheb_x + cheb_x_off(NN);
         sh_eta[threadIdx.x] = node_eta(h * xn[j], tp[0], tp[1], sb, cb, B.earth[det], B.anchors[entry],
                                        B.newton_steps);
     }
     __syncthreads();
-    const double *V = B.mono + (NN == kCheb ? 0 : kCheb * kCheb);
+    const double *V = B.mono + cheb_rule(NN) * kCheb * kCheb;
     if (on) coef[((size_t)tb * B.n_work + w) * kCheb + j] = mono_coef<NN>(sh_eta + le * NN, V, j);
 }
 
@@ -1562,9 +1562,12 @@ hipError_t launch_timebase_m(const BandDev *bands, const WorkItem *items, int n_
     if (n_cheb == kCheb)
         hipLaunchKernelGGL(k_timebase_m<kCheb>, dim3(blocks), dim3(tb_entries(kCheb) * kCheb), 0, stream, bands,
                            items, n_items, coef);
-    else
+    else if (n_cheb == kChebSplit)
         hipLaunchKernelGGL(k_timebase_m<kChebSplit>, dim3(blocks), dim3(tb_entries(kChebSplit) * kChebSplit), 0,
                            stream, bands, items, n_items, coef);
+    else
+        hipLaunchKernelGGL(k_timebase_m<kChebSplitMin>, dim3(blocks),
+                           dim3(tb_entries(kChebSplitMin) * kChebSplitMin), 0, stream, bands, items, n_items, coef);
     return hipGetLastError();
 }
 
@@ -1588,6 +1591,10 @@ hipError_t launch_resample_m(const BandDev *bands, const WorkItem *items, int n_
     } else if (n_cheb == kChebSplit) {
         if (D == 8) launch_resample_m_t<float, 8, kChebSplit>(bands, items, n_items, blocks, window, coef, y, stream);
         else launch_resample_m_t<float, 0, kChebSplit>(bands, items, n_items, blocks, window, coef, y, stream);
+    } else if (n_cheb == kChebSplitMin) {
+        if (D == 8)
+            launch_resample_m_t<float, 8, kChebSplitMin>(bands, items, n_items, blocks, window, coef, y, stream);
+        else launch_resample_m_t<float, 0, kChebSplitMin>(bands, items, n_items, blocks, window, coef, y, stream);
     } else {
         if (D == 8) launch_resample_m_t<float, 8, kCheb>(bands, items, n_items, blocks, window, coef, y, stream);
         else launch_resample_m_t<float, 0, kCheb>(bands, items, n_items, blocks, window, coef, y, stream);

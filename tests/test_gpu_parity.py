@@ -264,11 +264,26 @@ def test_time_base_parity(ccr, large_workload):
     2.8e-14 s); the phase is carried without that rounding.  Bars from the FP64 arithmetic:
     |eta| <= a_p + A_o w_o T_short / 2 ~ 2.1 s, so evaluating the degree-9 interpolant rounds to
     ~10 eps |eta| ~ 2.3e-15 s, i.e. 1e-12 cycles at 400 Hz; the delay adds the D_a rounding."""
-    ds = large_workload
+    worst_d, worst_p = _time_base_errors(ccr, large_workload, [7, 50000, 100199])
+    print(f"time base: delay {worst_d:.2e} s, phase {worst_p:.2e} cycles")
+    assert worst_d < 5e-14
+    assert worst_p < 2e-12
+
+
+def test_time_base_parity_band(ccr, band_workload):
+    """The same check on the realistic band (120 days, 30 % gaps, T_short 600 s, 200 Hz), at the
+    corners of its template grid."""
+    worst_d, worst_p = _time_base_errors(ccr, band_workload, [0, 63, 4032, 4095])
+    print(f"time base (band): delay {worst_d:.2e} s, phase {worst_p:.2e} cycles")
+    assert worst_d < 5e-14
+    assert worst_p < 2e-12
+
+
+def _time_base_errors(ccr, ds, picks):
     o = oracle.Oracle(ds)
     LD = np.longdouble
     n_k, M = ds.n_k, ds.n_seg
-    tm = ds.templates[[7, 50000, 100199]]
+    tm = ds.templates[picks]
     worst_d = worst_p = 0.0
     with ccr.Context(ds.sky, device=0) as ctx:
         bid = ctx.load(ds, templates=tm)
@@ -283,9 +298,7 @@ def test_time_base_parity(ccr, large_workload):
                         pref = LD(ds.f_het) * dref
                         dp = float(LD(psi[0, s]) - (pref - np.floor(pref)))
                         worst_p = max(worst_p, abs(dp - round(dp)))
-    print(f"time base: delay {worst_d:.2e} s, phase {worst_p:.2e} cycles")
-    assert worst_d < 5e-14
-    assert worst_p < 2e-12
+    return worst_d, worst_p
 
 
 @pytest.fixture(scope="module")
