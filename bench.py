@@ -140,6 +140,7 @@ def main():
     ap.add_argument("--profile-steps", type=int, default=0)
     ap.add_argument("--copy-calibration", action="store_true")
     ap.add_argument("--fused", type=int, default=0, help="1: fused kernel, 0: staged kernels (default)")
+    ap.add_argument("--workspace-mb", type=int, default=0, help="workspace budget (0: the library default)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: this build has no multi-GPU path "
@@ -167,6 +168,8 @@ def main():
           f"({time.perf_counter() - t_gen:.1f} s)", file=sys.stderr, flush=True)
     ctx = Context(ds.sky, device=0)
     ctx.set_option("fused", args.fused)
+    if args.workspace_mb:
+        ctx.set_option("workspace_mb", args.workspace_mb)
     bid = ctx.load(ds)
     info = ctx.band_info(bid)
     info["resample_templates"] = ctx.get_option("resample_templates")

@@ -140,7 +140,10 @@ const char *ccr_last_error(const ccr_ctx *ctx);
 /* Set an option (value >= 0).  Names:
  *   "template_batch"  templates per work item (one band's share of a launch), 0 = as many as
  *                     the workspace budget holds;
- *   "workspace_mb"    device workspace budget in MiB (resampled series, spectra, partials);
+ *   "workspace_mb"    device workspace budget in MiB (resampled series, spectra, partials),
+ *                     at least 64; 0 (the default) = 3/4 of the device memory that is free,
+ *                     plus what the context's workspace already holds, at the context's first
+ *                     compute call (fixed from then on; fewer, larger launch rounds);
  *   "k_chunk"         segments per pair-sum chunk, 0 = min(M, 256) or the tuned value;
  *   "fused"           1: fused resample + FFT + pair kernel where a band fits it, 0: staged;
  *   "items_per_launch" work items per launch, 0 = as many as the workspace holds (1 with

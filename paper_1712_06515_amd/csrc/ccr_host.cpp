@@ -99,7 +99,8 @@ struct ccr_ctx {
     std::string err;
     hipStream_t stream = nullptr;
     int64_t opt_template_batch = 0;
-    int64_t opt_workspace_mb = 16384;
+    int64_t opt_workspace_mb = 0;   // 0: automatic (see auto_budget)
+    size_t auto_budget = 0;         // automatic workspace budget, fixed at the first compute call
     int64_t opt_k_chunk = 0;
     int64_t opt_fused = 0;
     int64_t opt_timing = 0;
@@ -880,7 +881,14 @@ ccr_status build_plan(ccr_ctx *c, bool fp64, int n_bands, const int *band_ids, v
                       int out_on_device, int out_fp64, const BatchParams &bp, CallPlan &cp) {
     const size_t cs = fp64 ? 16 : 8;
     const size_t osz = out_fp64 ? sizeof(double) : sizeof(float);
-    const size_t budget = (size_t)c->opt_workspace_mb << 20;
+    if (c->opt_workspace_mb == 0 && c->auto_budget == 0) {
+        // 3/4 of the free device memory plus the workspace the context already holds
+        size_t fr = 0, tot = 0;
+        HIP_OK(c, hipMemGetInfo(&fr, &tot));
+        const size_t held = c->ws_y.bytes + c->ws_F.bytes + c->ws_part.bytes + c->ws_coef.bytes;
+        c->auto_budget = std::max<size_t>((fr + held) / 4 * 3, (size_t)64 << 20);
+    }
+    const size_t budget = c->opt_workspace_mb > 0 ? (size_t)c->opt_workspace_mb << 20 : c->auto_budget;
     cp = CallPlan();
     cp.out_off.assign((size_t)n_bands, 0);
     for (int bi = 0; bi < n_bands; ++bi) {
@@ -1277,7 +1285,7 @@ ccr_status ccr_set_option(ccr_ctx *c, const char *name, int64_t value) {
     std::string k(name);
     if (value < 0) return fail(c, CCR_EINVAL, "negative option value");
     if (k == "template_batch") c->opt_template_batch = value;
-    else if (k == "workspace_mb") c->opt_workspace_mb = std::max<int64_t>(value, 64);
+    else if (k == "workspace_mb") c->opt_workspace_mb = value == 0 ? 0 : std::max<int64_t>(value, 64);
     else if (k == "k_chunk") c->opt_k_chunk = value;
     else if (k == "fused") c->opt_fused = value;
     else if (k == "timing") c->opt_timing = value;

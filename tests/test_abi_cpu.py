@@ -75,6 +75,29 @@ def test_host_only_context_rejects_device_work(lib):
     assert e.value.status == ccr.EDEVICE
 
 
+def test_options_round_trip(lib):
+    """Option values as documented in include/ccr.h: the workspace budget defaults to 0
+    (automatic), explicit budgets are at least 64 MiB; read-only launch constants; unknown
+    names and negative values are rejected."""
+    ds = synth.make_dataset(small_config(n_seg=4), signal=False)
+    ctx = _host_ctx(ds)
+    assert ctx.get_option("workspace_mb") == 0
+    ctx.set_option("workspace_mb", 10)
+    assert ctx.get_option("workspace_mb") == 64
+    ctx.set_option("workspace_mb", 4096)
+    assert ctx.get_option("workspace_mb") == 4096
+    ctx.set_option("workspace_mb", 0)
+    assert ctx.get_option("workspace_mb") == 0
+    assert ctx.get_option("resample_templates") == 4
+    assert ctx.get_option("tuned_k_chunk") == 0
+    with pytest.raises(ccr.CcrError) as e:
+        ctx.get_option("no_such_option")
+    assert e.value.status == ccr.EUNSUP
+    with pytest.raises(ccr.CcrError) as e:
+        ctx.set_option("k_chunk", -1)
+    assert e.value.status == ccr.EINVAL
+
+
 def test_validation_errors(lib):
     ds = synth.make_dataset(small_config(n_seg=4), signal=False)
     ctx = _host_ctx(ds)
