@@ -85,6 +85,7 @@ struct Band {
     int bins_unique = 0;
     int n_work = 0;
     int newton_steps = 3, cheb_split = kCheb;
+    bool short_series = false;  // node solve with the x^7 / x^8 small-angle series
     int n_seg_any = 0;
     std::vector<double> freqs;
     std::vector<uint8_t> active;
@@ -631,6 +632,19 @@ ccr_status prepare_templates(ccr_ctx *c, Band &B) {
             worst_tail = std::max(worst_tail, tail);
             worst_tail6 = std::max(worst_tail6, tail6);
         }
+        // short small-angle series (through x^7 / x^8) in the node solve when the dropped terms,
+        // amplitude x |angle|^9 / 9! summed over the binary and Earth terms, stay below 1e-16 s
+        // for every template (angles bounded as in the validity check above)
+        double worst_series = 0.0;
+        {
+            double earth = 0.0;
+            for (const auto &cw : comps) earth += cw.first * std::pow(cw.second * (ld + 4.0), 9) / 362880.0;
+            for (int64_t t = 0; t < T; ++t) {
+                const double ap = B.tmpl_raw[3 * t], Om = 2.0 * kPi / B.tmpl_raw[3 * t + 2];
+                worst_series = std::max(worst_series, ap * std::pow(Om * (ld + 2.0 * ap + 2.0), 9) / 362880.0 + earth);
+            }
+        }
+        B.short_series = worst_series < 1e-16;
         const double f_top = B.p.f_min + B.p.f_band;
         B.newton_steps = worst_e2 < 1e-20 ? 2 : 3;
         auto fits = [&](double tl) { return 2.0 * tl * f_top < 1e-9 && 2.0 * tl / (double)dt < 1e-9; };
@@ -820,9 +834,10 @@ struct Variant {
     bool sp = false;     // spectra + pair sum in one kernel
     bool reg16 = false;  // otherwise: 256-point register FFT (else the LDS Stockham FFT on n_s points)
     bool z4 = false;     // spectra + pair sum: N_K <= 192 (4 of the 16 FFT input rows are zero)
+    bool ss = false;     // time base with the short small-angle series
     int DT = 0, window = 0, n_s = 0, nr = 0, n_cheb = kCheb;
     bool operator==(const Variant &o) const {
-        return sp == o.sp && reg16 == o.reg16 && z4 == o.z4 && DT == o.DT && window == o.window && n_s == o.n_s &&
+        return sp == o.sp && reg16 == o.reg16 && z4 == o.z4 && ss == o.ss && DT == o.DT && window == o.window && n_s == o.n_s &&
                nr == o.nr && n_cheb == o.n_cheb;
     }
 };
@@ -849,8 +864,9 @@ struct BatchParams {
     int64_t template_batch = 0, k_chunk = 0;
 };
 
-Variant variant_of(const BandDev &bd, bool fp64) {
+Variant variant_of(const BandDev &bd, bool fp64, bool short_series) {
     Variant v;
+    v.ss = short_series;
     v.sp = spectra_pairs_ok(bd, fp64, kMaxLds);
     v.DT = bd.D == 8 ? 8 : 0;
     v.window = bd.window;
@@ -913,7 +929,7 @@ ccr_status build_plan(ccr_ctx *c, bool fp64, int n_bands, const int *band_ids, v
         const Plan &pl = B.plan;
         const BandDev bd = band_dev(B);
         cp.bands.push_back(bd);
-        const Variant v = variant_of(bd, fp64);
+        const Variant v = variant_of(bd, fp64, B.short_series);
         if (std::find(variants.begin(), variants.end(), v) == variants.end()) variants.push_back(v);
         int64_t kc = bp.k_chunk > 0 ? bp.k_chunk : std::min<int64_t>(pl.n_seg, 256);
         kc = std::max<int64_t>(1, std::min<int64_t>(kc, pl.n_seg));
@@ -1035,7 +1051,7 @@ ccr_status run_rounds(ccr_ctx *c, const CallPlan &cp, size_t r0, size_t r1, bool
         const WorkItem *di = ditems + r.i0;
         {
             LaunchTimer lt(c, 5, s, timing);
-            HIP_OK(c, launch_timebase_m(db, di, r.n, (int)r.blocks[kStTimebase], r.v.n_cheb, coef, s));
+            HIP_OK(c, launch_timebase_m(db, di, r.n, (int)r.blocks[kStTimebase], r.v.n_cheb, r.v.ss, coef, s));
         }
         {
             LaunchTimer lt(c, 0, s, timing);

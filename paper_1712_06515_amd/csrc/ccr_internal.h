@@ -144,7 +144,9 @@ hipError_t launch_finish(const BandDev &B, int n_tmpl, const double *part, int n
 size_t spectra_pairs_lds(const BandDev &B);
 int spectra_pairs_rounds(const BandDev &B);  // bins per lane of the spectra+pairs kernel (3 or 8)
 int spectra_threads(int n_s);               // threads of the LDS Stockham FFT workgroup
-hipError_t launch_timebase_m(const BandDev *bands, const WorkItem *items, int n_items, int blocks, int n_cheb, double *coef,
+// short_series: the node solve's small-angle series end at x^7 / x^8 (a band's host bound).
+hipError_t launch_timebase_m(const BandDev *bands, const WorkItem *items, int n_items, int blocks, int n_cheb,
+                             bool short_series, double *coef,
                              hipStream_t stream);
 hipError_t launch_resample_m(const BandDev *bands, const WorkItem *items, int n_items, int blocks, bool fp64, int D,
                              int window, int n_cheb, const double *coef, void *y, hipStream_t stream);

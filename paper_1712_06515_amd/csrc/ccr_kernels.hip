@@ -45,14 +45,21 @@ __device__ __forceinline__ void wave_sync() {
 
 // ------------------------------------------------------------------ time base (FP64)
 
-// sin(x) and cos(x) - 1 by their Taylor series through x^11 / x^12; |x| <= 0.3 keeps the
-// truncation below 3e-17 relative.
+// sin(x) and cos(x) - 1 by their Taylor series: through x^11 / x^12 (|x| <= 0.3 keeps the
+// truncation below 3e-17 relative), or with SHORT through x^7 / x^8, which a band uses when the
+// host's bound on the dropped terms, amplitude x |x|^9 / 9! over its templates, is below 1e-16 s.
+template <bool SHORT>
 __device__ __forceinline__ void sincos_small(double x, double &s, double &cm1) {
     const double x2 = x * x;
-    s = x * (1.0 - x2 * (1.0 / 6.0) * (1.0 - x2 * (1.0 / 20.0) * (1.0 - x2 * (1.0 / 42.0) *
-             (1.0 - x2 * (1.0 / 72.0) * (1.0 - x2 * (1.0 / 110.0))))));
-    cm1 = -x2 * 0.5 * (1.0 - x2 * (1.0 / 12.0) * (1.0 - x2 * (1.0 / 30.0) * (1.0 - x2 * (1.0 / 56.0) *
-             (1.0 - x2 * (1.0 / 90.0) * (1.0 - x2 * (1.0 / 132.0))))));
+    if constexpr (SHORT) {
+        s = x * (1.0 - x2 * (1.0 / 6.0) * (1.0 - x2 * (1.0 / 20.0) * (1.0 - x2 * (1.0 / 42.0))));
+        cm1 = -x2 * 0.5 * (1.0 - x2 * (1.0 / 12.0) * (1.0 - x2 * (1.0 / 30.0) * (1.0 - x2 * (1.0 / 56.0))));
+    } else {
+        s = x * (1.0 - x2 * (1.0 / 6.0) * (1.0 - x2 * (1.0 / 20.0) * (1.0 - x2 * (1.0 / 42.0) *
+                 (1.0 - x2 * (1.0 / 72.0) * (1.0 - x2 * (1.0 / 110.0))))));
+        cm1 = -x2 * 0.5 * (1.0 - x2 * (1.0 / 12.0) * (1.0 - x2 * (1.0 / 30.0) * (1.0 - x2 * (1.0 / 56.0) *
+                 (1.0 - x2 * (1.0 / 90.0) * (1.0 - x2 * (1.0 / 132.0))))));
+    }
 }
 
 // Binary orbital phase (cycles in [0,1)) of segment K's mid-time: frac(c0 + K c1), both in
@@ -76,10 +83,11 @@ __device__ __forceinline__ void binary_anchor(const double *tp, int K, double &s
 // de(x) = r(t_a + x).n - r(t_a).n, theta_b the binary phase at tau_a; Delta = eta - D_a.
 // Three Newton steps from eta_0 = a_p sin(theta_b + Omega u) (quadratic convergence from an
 // initial error below 0.1 s leaves < 1e-25 s).
+template <bool SHORT>
 __device__ __forceinline__ double node_eta(double u, double a_p, double Om, double sb, double cb,
                                            const EarthConst &ec, const Anchor &an, int steps) {
     double s, cm;
-    sincos_small(Om * u, s, cm);
+    sincos_small<SHORT>(Om * u, s, cm);
     double eta = a_p * (fma(sb, cm, sb) + cb * s);
     // Newton from the binary-only value; `steps` (2 or 3) comes from the host's convergence bound
 #pragma unroll
@@ -87,13 +95,13 @@ __device__ __forceinline__ double node_eta(double u, double a_p, double Om, doub
         if (it >= steps) break;
         const double x = u + eta;
         double so, co, sd, cd;
-        sincos_small(ec.w_o * x, so, co);
-        sincos_small(ec.w_d * x, sd, cd);
+        sincos_small<SHORT>(ec.w_o * x, so, co);
+        sincos_small<SHORT>(ec.w_d * x, sd, cd);
         const double de = ec.A_o * (an.c_o * co - an.s_o * so) + ec.A_d * (an.c_d * cd - an.s_d * sd) + an.rho_a;
         const double dep = -ec.A_o * ec.w_o * (an.c_o * so + fma(an.s_o, co, an.s_o)) -
                            ec.A_d * ec.w_d * (an.c_d * sd + fma(an.s_d, cd, an.s_d));
         double sbn, cbn;
-        sincos_small(Om * (x + de), sbn, cbn);
+        sincos_small<SHORT>(Om * (x + de), sbn, cbn);
         const double sinb = fma(sb, cbn, sb) + cb * sbn;
         const double cosb = fma(cb, cbn, cb) - sb * sbn;
         const double G = eta + de - a_p * sinb;
@@ -150,8 +158,9 @@ __device__ __forceinline__ void sample_time(const double *coef, double x, const 
 // (degree 6 or 5) on the split path when the host's bound covers the interpolation error (at
 // most twice the dropped Chebyshev tail).  tb_entries(NN) entries x NN nodes per workgroup
 // (whole wavefronts); node values meet in LDS for the coefficient transform.
-template <int NN>
+template <int NN, bool SHORT>
 __device__ __forceinline__ void timebase_body(const BandDev &B, const double *tmpl, double *coef, int bx, int tb) {
+    static_assert(NN == kCheb || NN == kChebSplit || NN == kChebSplitMin, "node rule");
     constexpr int E = tb_entries(NN);
     __shared__ double sh_eta[E * NN];
     __shared__ double2 sh_bin[E];
@@ -177,7 +186,7 @@ __device__ __forceinline__ void timebase_body(const BandDev &B, const double *tm
         const double sb = bn.x, cb = bn.y;
         const double h = 0.5 * (double)B.n_k * B.dt;
         const double *xn = B.cheb_x + cheb_x_off(NN);
-        sh_eta[threadIdx.x] = node_eta(h * xn[j], tp[0], tp[1], sb, cb, B.earth[det], B.anchors[entry],
+        sh_eta[threadIdx.x] = node_eta<SHORT>(h * xn[j], tp[0], tp[1], sb, cb, B.earth[det], B.anchors[entry],
                                        B.newton_steps);
     }
     __syncthreads();
@@ -186,7 +195,7 @@ __device__ __forceinline__ void timebase_body(const BandDev &B, const double *tm
 }
 
 __global__ void __launch_bounds__(tb_entries(kCheb) * kCheb) k_timebase(BandDev B, const double *tmpl, double *coef) {
-    timebase_body<kCheb>(B, tmpl, coef, blockIdx.x, blockIdx.y);
+    timebase_body<kCheb, false>(B, tmpl, coef, blockIdx.x, blockIdx.y);
 }
 
 // ------------------------------------------------------------------ resampling
@@ -396,7 +405,7 @@ static_assert(kResWin == 128, "the interior window fill loads 2 x 64 entries");
 
 // Resampler: one 64-lane workgroup (one wavefront) per (active segment, templates [t0, t1)),
 // looping over the segment's samples 64 at a time for each template; the segment's anchor and
-// window coefficients are loaded once, each template's Chebyshev coefficients are uniform
+// window coefficients are loaded once, each template's time-base coefficients are uniform
 // (scalar loads).  Each pass stages its input window in LDS (two coalesced loads per lane,
 // zero outside the data) and every lane reads its 2D + 1 taps from there.
 template <typename T, int DT, int WIN, int NC = kCheb>
@@ -1355,14 +1364,14 @@ __device__ __forceinline__ int find_item(const WorkItem *__restrict__ items, int
     return lo;
 }
 
-template <int NN>
+template <int NN, bool SHORT>
 __global__ void __launch_bounds__(tb_entries(NN) * NN)
 k_timebase_m(const BandDev *__restrict__ bands, const WorkItem *__restrict__ items, int n_items,
              double *__restrict__ coef) {
     const WorkItem &it = items[find_item(items, n_items, kStTimebase, blockIdx.x)];
     const BandDev B = global_view(bands[it.band], bands);
     const int l = blockIdx.x - it.first[kStTimebase], gx = it.gx[kStTimebase];
-    timebase_body<NN>(B, B.tmpl + (size_t)it.tmpl_off * kTmplStride, coef + it.coef_off, l % gx, l / gx);
+    timebase_body<NN, SHORT>(B, B.tmpl + (size_t)it.tmpl_off * kTmplStride, coef + it.coef_off, l % gx, l / gx);
 }
 
 template <typename T, int DT, int WIN, int NC>
@@ -1556,18 +1565,23 @@ int spectra_pairs_rounds(const BandDev &B) { return B.n_f <= 64 * 3 ? 3 : kSpair
 
 int spectra_threads(int n_s) { return n_s / 4 >= 256 ? 256 : (n_s / 4 < 64 ? 64 : n_s / 4); }
 
-hipError_t launch_timebase_m(const BandDev *bands, const WorkItem *items, int n_items, int blocks, int n_cheb,
-                             double *coef, hipStream_t stream) {
-    if (blocks == 0) return hipSuccess;
-    if (n_cheb == kCheb)
-        hipLaunchKernelGGL(k_timebase_m<kCheb>, dim3(blocks), dim3(tb_entries(kCheb) * kCheb), 0, stream, bands,
-                           items, n_items, coef);
-    else if (n_cheb == kChebSplit)
-        hipLaunchKernelGGL(k_timebase_m<kChebSplit>, dim3(blocks), dim3(tb_entries(kChebSplit) * kChebSplit), 0,
-                           stream, bands, items, n_items, coef);
+template <int NN>
+static void launch_timebase_m_t(const BandDev *bands, const WorkItem *items, int n_items, int blocks, bool short_series,
+                                double *coef, hipStream_t stream) {
+    if (short_series)
+        hipLaunchKernelGGL((k_timebase_m<NN, true>), dim3(blocks), dim3(tb_entries(NN) * NN), 0, stream, bands, items,
+                           n_items, coef);
     else
-        hipLaunchKernelGGL(k_timebase_m<kChebSplitMin>, dim3(blocks),
-                           dim3(tb_entries(kChebSplitMin) * kChebSplitMin), 0, stream, bands, items, n_items, coef);
+        hipLaunchKernelGGL((k_timebase_m<NN, false>), dim3(blocks), dim3(tb_entries(NN) * NN), 0, stream, bands, items,
+                           n_items, coef);
+}
+
+hipError_t launch_timebase_m(const BandDev *bands, const WorkItem *items, int n_items, int blocks, int n_cheb,
+                             bool short_series, double *coef, hipStream_t stream) {
+    if (blocks == 0) return hipSuccess;
+    if (n_cheb == kCheb) launch_timebase_m_t<kCheb>(bands, items, n_items, blocks, short_series, coef, stream);
+    else if (n_cheb == kChebSplit) launch_timebase_m_t<kChebSplit>(bands, items, n_items, blocks, short_series, coef, stream);
+    else launch_timebase_m_t<kChebSplitMin>(bands, items, n_items, blocks, short_series, coef, stream);
     return hipGetLastError();
 }
 
