@@ -736,7 +736,7 @@ constexpr int kSpairMaxRounds = 8;  // bins per lane: n_f <= 64 * kSpairMaxRound
 
 struct SpairLayout {
     int S, slots, cand;
-    size_t off_ring, off_list, off_meta, off_flag, off_slotk, off_pos, total;
+    size_t off_ring, off_list, off_meta, off_flag, off_slotk, off_pos, off_dec, total;
 };
 
 // cand = candidate pairs per step: S segments x Q detectors x ring slots x Q.
@@ -761,8 +761,18 @@ __host__ __device__ inline SpairLayout spair_layout(int Q, int n_f, int R, int n
     o = (o + 15) & ~(size_t)15;
     L.off_pos = o;                    // ring column of FFT output (p, k2, t), n_f if unused
     o += (size_t)n_fft * sizeof(int16_t);
+    o = (o + 15) & ~(size_t)15;
+    L.off_dec = o;                    // decoded pair candidates (cand_decode)
+    o += (size_t)L.cand * sizeof(unsigned);
     L.total = (o + 15) & ~(size_t)15;
     return L;
+}
+
+// Pair candidate cd of a step = (s2, Xc, j, Y) in mixed radix (S, Q, slots, Q), packed one
+// byte each (Y lowest); Q <= 4 and slots < 256.
+__device__ __forceinline__ unsigned cand_decode(int cd, int Q, int slots) {
+    const int Y = cd % Q, j = (cd / Q) % slots, Xc = (cd / (Q * slots)) % Q, s2 = cd / (Q * slots * Q);
+    return (unsigned)Y | ((unsigned)j << 8) | ((unsigned)Xc << 16) | ((unsigned)s2 << 24);
 }
 
 template <int NR, bool Z4>
@@ -777,6 +787,7 @@ __device__ __forceinline__ void spectra_pairs_body(const BandDev &B, const float
     uint8_t *flag = smem + Ly.off_flag;
     int *slotk = reinterpret_cast<int *>(smem + Ly.off_slotk);
     int16_t *opos = reinterpret_cast<int16_t *>(smem + Ly.off_pos);
+    unsigned *ldec = reinterpret_cast<unsigned *>(smem + Ly.off_dec);
     const int lane = threadIdx.x;
     const int grp = lane >> 4, t = lane & 15;
     const int K0 = c * k_chunk;
@@ -800,6 +811,7 @@ __device__ __forceinline__ void spectra_pairs_body(const BandDev &B, const float
     }
     for (int e = lane; e < slots * Q; e += 64) flag[e] = 0;
     for (int e = lane; e < slots; e += 64) slotk[e] = -1;
+    for (int e = lane; e < Ly.cand; e += 64) ldec[e] = cand_decode(e, Q, slots);
     // the steps visit only segments where some detector takes part in a pair: the band's sorted
     // list seg_any, entries [lo, hi) for the chunk with its halo [Kh, K1)
     auto lower = [&](int key) {
@@ -884,10 +896,10 @@ __device__ __forceinline__ void spectra_pairs_body(const BandDev &B, const float
             int o1 = 0, o2 = 0, dl_c = 0;
             float W = 0.f;
             if (cd < Ly.cand) {
-                const int Y = cd % Q;
-                const int j = (cd / Q) % slots;
-                const int Xc = (cd / (Q * slots)) % Q;
-                const int s2 = cd / (Q * slots * Q);
+                // candidate index -> (s2, Xc, j, Y), decoded once per workgroup into LDS
+                const unsigned dec = ldec[cd];
+                const int Y = (int)(dec & 255u), j = (int)((dec >> 8) & 255u);
+                const int Xc = (int)((dec >> 16) & 255u), s2 = (int)(dec >> 24);
                 if (s2 < ns) {
                     int slot = slot_b + s2;
                     if (slot >= slots) slot -= slots;
@@ -1492,8 +1504,9 @@ hipError_t launch_spectra(const BandDev &B, int n_tmpl, bool fp64, const void *y
 }
 
 bool spectra_pairs_ok(const BandDev &B, bool fp64, size_t limit) {
-    return !fp64 && B.n_s == 256 && B.bins_unique && B.Q <= 4 && B.n_f <= 64 * kSpairMaxRounds &&
-           spair_layout(B.Q, B.n_f, B.R, B.n_fft).total <= limit;
+    const SpairLayout L = spair_layout(B.Q, B.n_f, B.R, B.n_fft);
+    return !fp64 && B.n_s == 256 && B.bins_unique && B.Q <= 4 && B.n_f <= 64 * kSpairMaxRounds && L.slots < 256 &&
+           L.total <= limit;
 }
 
 
