@@ -82,6 +82,8 @@ def test_resampled_series_parity(ccr):
                 y64 = ctx.resample_series(bid, t, X, prec=ccr.PREC_FP64)
                 y32 = ctx.resample_series(bid, t, X, prec=ccr.PREC_SPLIT)
                 scale = np.abs(y_ref).max()
+                print(f"resampled series t={t} X={X}: fp64 {np.abs(y64 - y_ref).max() / scale:.2e}, "
+                      f"split {np.abs(y32 - y_ref).max() / scale:.2e} of the peak")
                 assert np.abs(y64 - y_ref).max() < 1e-12 * scale
                 assert np.abs(y32 - y_ref).max() < 2e-6 * scale
                 assert np.all((y64 == 0) >= (m == 0))
