@@ -217,6 +217,18 @@ def test_band_workload_sampled(ccr, band_workload):
     assert 0.8 < np.median(np.abs(r64)) / 0.6745 < 1.25
 
 
+def test_workspace_rounds(ccr, band_workload):
+    """The workspace budget only changes how templates are packed into launch rounds: 40
+    templates of the band in one round (default budget) and in 40 (64 MiB, less than one
+    template's FP64 series) give bitwise-equal FP64 rho and split rho within rounding."""
+    ds = band_workload
+    tm = ds.templates[:40]
+    a64, a32 = run_both(ccr, ds, tm)
+    b64, b32 = run_both(ccr, ds, tm, workspace_mb=64)
+    assert np.array_equal(a64, b64)
+    assert np.max(np.abs(a32 - b32)) <= 1e-6 * max(1.0, np.abs(a32).max())
+
+
 @pytest.fixture(scope="module")
 def large_workload():
     return synth.make_dataset(synth.config("large"))
