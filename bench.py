@@ -141,6 +141,8 @@ def main():
     ap.add_argument("--copy-calibration", action="store_true")
     ap.add_argument("--fused", type=int, default=0, help="1: fused kernel, 0: staged kernels (default)")
     ap.add_argument("--workspace-mb", type=int, default=0, help="workspace budget (0: the library default)")
+    ap.add_argument("--max-templates", type=int, default=0,
+                    help="time only the first N templates of the workload (0: all; the rate is per rho evaluation)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: this build has no multi-GPU path "
@@ -164,6 +166,8 @@ def main():
 
     t_gen = time.perf_counter()
     ds = synth.make_dataset(synth.config(args.workload))
+    if args.max_templates and args.max_templates < len(ds.templates):
+        ds.templates = ds.templates[:args.max_templates]
     print(f"[bench] dataset {args.workload}: {ds.n_det} det x {ds.n} samples, {len(ds.templates)} templates "
           f"({time.perf_counter() - t_gen:.1f} s)", file=sys.stderr, flush=True)
     ctx = Context(ds.sky, device=0)

@@ -81,7 +81,8 @@ struct Band {
     int Q = 0;
     // device tables
     DevBuf d_x, d_mask, d_anchor, d_earth, d_win64, d_win32, d_cheb_x, d_mono, d_tw64, d_tw32, d_bin_m, d_bin_p,
-        d_bin_kb, d_bin_pos, d_segw, d_active, d_work, d_seg_work, d_tmpl, d_lagph, d_seg_any, d_col_bin, d_bin_col, d_zero256;
+        d_bin_kb, d_bin_pos, d_segw, d_active, d_work, d_seg_work, d_tmpl, d_lagph, d_seg_any, d_col_bin, d_bin_col, d_zero256,
+        d_class_start;
     int bins_unique = 0;
     int n_work = 0;
     int newton_steps = 3, cheb_split = kCheb;
@@ -473,6 +474,10 @@ ccr_status prepare(ccr_ctx *c, Band &B) {
     std::stable_sort(col_bin.begin(), col_bin.end(),
                      [&](int a, int b) { return bp[a] != bp[b] ? bp[a] < bp[b] : bm[a] < bm[b]; });
     for (int64_t cc = 0; cc < pl.n_f; ++cc) bin_col[col_bin[cc]] = (int)cc;
+    // the same order groups the bins by residue class: class p is [class_start[p], class_start[p + 1])
+    std::vector<int> class_start((size_t)pl.P + 1, 0);
+    for (int64_t cc = 0; cc < pl.n_f; ++cc) ++class_start[(size_t)bp[col_bin[cc]] + 1];
+    for (int64_t q = 0; q < pl.P; ++q) class_start[(size_t)q + 1] += class_start[(size_t)q];
     // lag phases of the pair sum (spectra taken without Phi_in), in ring-column order
     const int64_t Rl = B.p.max_lag;
     std::vector<float2> lagph((size_t)(Rl + 1) * pl.n_f);
@@ -542,6 +547,7 @@ ccr_status prepare(ccr_ctx *c, Band &B) {
     if ((st = upload(c, B.d_lagph, lagph))) return st;
     if ((st = upload(c, B.d_col_bin, col_bin))) return st;
     if ((st = upload(c, B.d_bin_col, bin_col))) return st;
+    if ((st = upload(c, B.d_class_start, class_start))) return st;
     if ((st = upload(c, B.d_zero256, std::vector<float2>(256, make_float2(0.f, 0.f))))) return st;
     {
         std::vector<int> any;
@@ -711,6 +717,7 @@ BandDev band_dev(const Band &B) {
     d.lagph = B.d_lagph.as<float2>();
     d.col_bin = B.d_col_bin.as<int>();
     d.bin_col = B.d_bin_col.as<int>();
+    d.class_start = B.d_class_start.as<int>();
     d.zero256 = B.d_zero256.as<float2>();
     d.seg_any = B.d_seg_any.as<int>();
     d.n_seg_any = B.n_seg_any;

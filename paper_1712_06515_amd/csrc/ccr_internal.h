@@ -84,6 +84,8 @@ struct BandDev {
     const float2 *lagph;
     const int *col_bin;       // [n_f] spectra + pair-sum ring: bin of column c (bins ordered by
     const int *bin_col;       // [n_f] residue class, then index in the class); column of bin i
+    const int *class_start;   // [P + 1] the bins of residue class p are col_bin[class_start[p] ..
+                              // class_start[p + 1])
     const float2 *zero256;    // [256] zero samples (input of FFT groups without a segment)
     const int *seg_any;       // [n_seg_any] ascending segments K where some detector is active
     int n_seg_any;

@@ -995,8 +995,9 @@ __device__ __forceinline__ void spectra_body(const BandDev &B, const c2<T> *y, c
         }
         __syncthreads();
         const c2<T> *res = stockham<T>(buf0, buf1, B.n_s, tw, B.n_fft, threadIdx.x, blockDim.x);
-        for (int i = threadIdx.x; i < B.n_f; i += blockDim.x) {
-            if (B.bin_p[i] != p) continue;
+        // the output bins of class p only
+        for (int c = B.class_start[p] + (int)threadIdx.x; c < B.class_start[p + 1]; c += blockDim.x) {
+            const int i = B.col_bin[c];
             const int ph = mod_fft(B, (int64_t)B.bin_kb[i] * rb_mod);
             Fo[i] = cscale<T>(cmul<T>(res[B.bin_m[i]], tw[ph]), scale);
         }
@@ -1014,7 +1015,10 @@ __global__ void __launch_bounds__(256) k_spectra(BandDev B, const c2<T> *y, c2<T
 // Partial rho of one (template, bin, chunk of segments): for each segment K and detector X,
 // conj(F_XK) times the weighted sum of its partners (Y, L) that precede it -- L in
 // [K - R, K - 1] (other detectors if cross pairs, the same detector if same pairs) and
-// L = K with Y > X (cross pairs) -- so each unordered pair of the set enters once.
+// L = K with Y > X (cross pairs) -- so each unordered pair of the set enters once.  The sums
+// over L in [K - R, K - 1] are kept per detector as sliding windows (add segment K - 1, drop
+// K - R - 1), so each spectrum is read twice instead of (R + 1) Q times; inactive segments
+// (whose spectra are not computed) never enter.
 template <typename T>
 __device__ __forceinline__ void pairs_body(const BandDev &B, const c2<T> *F, double *part, int k_chunk, int n_chunks,
                                            int bx, int c, int tb) {
@@ -1022,23 +1026,53 @@ __device__ __forceinline__ void pairs_body(const BandDev &B, const c2<T> *F, dou
     if (i >= B.n_f) return;
     const bool cross = (B.pairs & 1) != 0, same = (B.pairs & 2) != 0;
     const c2<T> *Ft = F + (size_t)tb * B.Q * B.n_seg * B.n_f;
+    const int Q = B.Q, R = B.R;
     const int K0 = c * k_chunk;
     const int K1 = min(B.n_seg, K0 + k_chunk);
+    // wa[Y], wb[Y]: sum over L in [K - R, K - 1] of hat a_YL F_YL and hat b_YL F_YL
+    c2<T> wa[CCR_MAX_DET_K], wb[CCR_MAX_DET_K];
+#pragma unroll
+    for (int Y = 0; Y < CCR_MAX_DET_K; ++Y) wa[Y] = wb[Y] = mk<T>((T)0, (T)0);
+    auto add = [&](int Y, int L, T sign) {
+        const int el = Y * B.n_seg + L;
+        if (!B.active[el]) return;
+        const c2<T> g = Ft[(size_t)el * B.n_f + i];
+        const T a = sign * (T)B.segw[el].ahat, b = sign * (T)B.segw[el].bhat;
+        wa[Y] = mk<T>(fma(a, g.x, wa[Y].x), fma(a, g.y, wa[Y].y));
+        wb[Y] = mk<T>(fma(b, g.x, wb[Y].x), fma(b, g.y, wb[Y].y));
+    };
+    for (int L = max(0, K0 - R); L < K0; ++L)
+#pragma unroll
+        for (int Y = 0; Y < CCR_MAX_DET_K; ++Y)
+            if (Y < Q) add(Y, L, (T)1);
     double acc = 0.0;
     for (int K = K0; K < K1; ++K) {
-        for (int X = 0; X < B.Q; ++X) {
+        if (R > 0 && K > K0) {
+            // slide: segment K - 1 enters, K - 1 - R leaves
+#pragma unroll
+            for (int Y = 0; Y < CCR_MAX_DET_K; ++Y) {
+                if (Y >= Q) continue;
+                add(Y, K - 1, (T)1);
+                if (K - 1 - R >= 0) add(Y, K - 1 - R, (T)-1);
+            }
+        }
+        for (int X = 0; X < Q; ++X) {
             const int ek = X * B.n_seg + K;
             if (!B.active[ek]) continue;
             c2<T> ga = mk<T>((T)0, (T)0), gb = mk<T>((T)0, (T)0);
-            for (int L = max(0, K - B.R); L <= K; ++L) {
-                for (int Y = 0; Y < B.Q; ++Y) {
-                    const bool inc = (L < K) ? ((Y != X) ? cross : same) : (cross && Y > X);
-                    const int el = Y * B.n_seg + L;
-                    if (!inc || !B.active[el]) continue;
+#pragma unroll
+            for (int Y = 0; Y < CCR_MAX_DET_K; ++Y) {
+                if (Y >= Q) continue;
+                if (R > 0 && ((Y != X) ? cross : same)) {
+                    ga = mk<T>(ga.x + wa[Y].x, ga.y + wa[Y].y);
+                    gb = mk<T>(gb.x + wb[Y].x, gb.y + wb[Y].y);
+                }
+                const int el = Y * B.n_seg + K;
+                if (cross && Y > X && B.active[el]) {
                     const c2<T> g = Ft[(size_t)el * B.n_f + i];
-                    const T wa = (T)B.segw[el].ahat, wb = (T)B.segw[el].bhat;
-                    ga.x += wa * g.x; ga.y += wa * g.y;
-                    gb.x += wb * g.x; gb.y += wb * g.y;
+                    const T wa_ = (T)B.segw[el].ahat, wb_ = (T)B.segw[el].bhat;
+                    ga = mk<T>(fma(wa_, g.x, ga.x), fma(wa_, g.y, ga.y));
+                    gb = mk<T>(fma(wb_, g.x, gb.x), fma(wb_, g.y, gb.y));
                 }
             }
             const c2<T> f = Ft[(size_t)ek * B.n_f + i];
@@ -1253,8 +1287,8 @@ __global__ void __launch_bounds__(256) k_fused(BandDev B, const double *coef, co
                 const int rb_mod = mod_fft(B, (int64_t)K * n_k);
                 const T scale = (T)B.segw[X * B.n_seg + K].scale;
                 c2<T> *Fo = ring + ((size_t)(K % slots) * Q + X) * n_f;
-                for (int i = g0; i < n_f; i += per) {
-                    if (B.bin_p[i] != p) continue;
+                for (int c = B.class_start[p] + g0; c < B.class_start[p + 1]; c += per) {
+                    const int i = B.col_bin[c];
                     const int ph = mod_fft(B, (int64_t)B.bin_kb[i] * rb_mod);
                     Fo[i] = cscale<T>(cmul<T>(res[B.bin_m[i]], tw[ph]), scale);
                 }
@@ -1360,6 +1394,7 @@ __device__ __forceinline__ BandDev global_view(const BandDev &b, const void *bas
     g.lagph = as_global(b.lagph, base);
     g.seg_any = as_global(b.seg_any, base);
     g.col_bin = as_global(b.col_bin, base);
+    g.class_start = as_global(b.class_start, base);
     g.zero256 = as_global(b.zero256, base);
     g.bin_col = as_global(b.bin_col, base);
     return g;
