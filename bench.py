@@ -103,6 +103,18 @@ def roofline(name, avg_ms, tb, info, workload):
     n_active = info["n_active"]
     ns = 1 << (int(info["n_k"]) - 1).bit_length()
     P = info["n_fft"] // ns
+    if name == "resample" and info.get("farrow_used"):
+        # Farrow form: one complex64 sample written per resampled sample, plus the band's
+        # table (kFarDeg + 1 complex64 planes per input sample and detector) read once
+        planes = info["farrow_degree"] + 1
+        table = info["n_det"] * planes * 8.0 * info["n_seg"] * info["n_k"]
+        byts = n_active * info["n_k"] * tb * 8.0 + table
+        ach = byts / (avg_ms * 1e-3) / 1e9
+        return {"kernel": "k_resample_far_m", "bound": "hbm", "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": ach / HBM_PEAK_GBS, "traffic": read_traffic("resample", workload),
+                "avg_launch_ms": avg_ms, "algorithmic_bytes_per_launch": byts,
+                "per_unit": f"8 B written per resampled sample + the Farrow table ({planes} x 8 B per input "
+                            f"sample and detector) read once per launch"}
     if name == "resample":
         # one complex64 sample written per resampled sample; the input sample is read once per
         # tile of T_b templates (the templates one workgroup resamples from one staged input
@@ -141,6 +153,8 @@ def main():
     ap.add_argument("--copy-calibration", action="store_true")
     ap.add_argument("--fused", type=int, default=0, help="1: fused kernel, 0: staged kernels (default)")
     ap.add_argument("--workspace-mb", type=int, default=0, help="workspace budget (0: the library default)")
+    ap.add_argument("--farrow", type=int, default=None,
+                    help="split-precision resampler: 1 Farrow form (library default), 0 direct tap sum")
     ap.add_argument("--max-templates", type=int, default=0,
                     help="time only the first N templates of the workload (0: all; the rate is per rho evaluation)")
     args = ap.parse_args()
@@ -176,7 +190,10 @@ def main():
         ctx.set_option("workspace_mb", args.workspace_mb)
     bid = ctx.load(ds)
     info = ctx.band_info(bid)
+    if args.farrow is not None:
+        ctx.set_option("farrow", args.farrow)
     info["resample_templates"] = ctx.get_option("resample_templates")
+    info["farrow_used"] = bool(ctx.get_option("farrow")) and info["farrow_degree"] > 0
     n_t, n_f = info["n_templates"], info["n_f"]
     out = torch.empty((n_t, n_f), dtype=torch.float32, device="cuda")
     stream = torch.cuda.current_stream()

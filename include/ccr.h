@@ -48,7 +48,7 @@
 extern "C" {
 #endif
 
-#define CCR_ABI_VERSION 1
+#define CCR_ABI_VERSION 2
 #define CCR_MAX_DET 8
 #define CCR_PAIRS_CROSS 1 /* pairs across detectors, |K - L| <= R        */
 #define CCR_PAIRS_SAME 2  /* pairs within a detector, 0 < L - K <= R     */
@@ -124,6 +124,13 @@ typedef struct {
     int64_t n_active;     /* (detector, segment) entries that take part in a pair and are computed */
     double dt, f_het, df_load, t_coh, dlambda_f, t_fft, nu_r;
     double norm;          /* N of App. A (0 when no pair carries weight) */
+    /* Split-precision resampling in Farrow form (Sec. III.B interpolation, evaluated as one
+     * polynomial in the offset per sample): polynomial degree of the tap weights, 0 when the
+     * band has no Farrow table (the fit's error bound is too large, or no device memory for
+     * it: the direct 2D + 1-tap form runs instead); farrow_err = max over offsets of
+     * sum_n |fitted - exact tap weight| (relative to the input amplitude). */
+    int64_t farrow_degree;
+    double farrow_err;
 } ccr_band_info;
 
 int ccr_abi_version(void);
@@ -155,7 +162,10 @@ const char *ccr_last_error(const ccr_ctx *ctx);
  *                     applies to device outputs only;
  *   "autotune"        1: on the first call for a given band list and precision, time the
  *                     first launch round for k_chunk = 32 ... 1024 and keep the fastest
- *                     (an explicit "k_chunk" disables tuning).
+ *                     (an explicit "k_chunk" disables tuning);
+ *   "farrow"          1 (default): split-precision resampling in Farrow form where the band
+ *                     has the table (see ccr_band_info.farrow_degree), 0: the direct
+ *                     2D + 1-tap form.  FP64 always uses the direct form.
  * All bands of a compute call run in shared launches: one launch per stage covers the work
  * items of many bands (grouped by kernel variant, packed to the workspace budget).
  * Returns CCR_EUNSUP for an unknown name. */
@@ -164,7 +174,8 @@ ccr_status ccr_set_option(ccr_ctx *ctx, const char *name, int64_t value);
 /* Read an option set with ccr_set_option, or "tuned_k_chunk" / "tuned_template_batch": the
  * launch shape the autotuner chose last (0 before any tuning), or "resample_templates": the
  * templates one resampling workgroup handles from one staged input window (a constant of the
- * build).  CCR_EUNSUP for an unknown name. */
+ * build), "farrow_templates" / "farrow_degree": the same for the Farrow-form kernel and its
+ * polynomial degree.  CCR_EUNSUP for an unknown name. */
 ccr_status ccr_get_option(ccr_ctx *ctx, const char *name, int64_t *value);
 
 /* Add a band; returns its id and the part of the plan known before data (n_k, dt, f_het,

@@ -48,7 +48,8 @@ class BandInfo(ctypes.Structure):
                 ("n_det", ctypes.c_int64), ("n_templates", ctypes.c_int64), ("n_active", ctypes.c_int64),
                 ("dt", ctypes.c_double), ("f_het", ctypes.c_double), ("df_load", ctypes.c_double),
                 ("t_coh", ctypes.c_double), ("dlambda_f", ctypes.c_double), ("t_fft", ctypes.c_double),
-                ("nu_r", ctypes.c_double), ("norm", ctypes.c_double)]
+                ("nu_r", ctypes.c_double), ("norm", ctypes.c_double), ("farrow_degree", ctypes.c_int64),
+                ("farrow_err", ctypes.c_double)]
 
     def as_dict(self):
         return {f[0]: getattr(self, f[0]) for f in self._fields_}

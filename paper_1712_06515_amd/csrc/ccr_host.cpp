@@ -82,7 +82,9 @@ struct Band {
     // device tables
     DevBuf d_x, d_mask, d_anchor, d_earth, d_win64, d_win32, d_cheb_x, d_mono, d_tw64, d_tw32, d_bin_m, d_bin_p,
         d_bin_kb, d_bin_pos, d_segw, d_active, d_work, d_seg_work, d_tmpl, d_lagph, d_seg_any, d_col_bin, d_bin_col, d_zero256,
-        d_class_start;
+        d_class_start, d_farrow, d_farrow_A;
+    int64_t far_len = 0;  // plane length of the Farrow table, 0 when the band has none
+    double far_err = 0;   // bound of the fitted tap weights' error, sum over taps
     int bins_unique = 0;
     int n_work = 0;
     int newton_steps = 3, cheb_split = kCheb;
@@ -108,6 +110,7 @@ struct ccr_ctx {
     int64_t opt_timing = 0;
     DevBuf ws_y, ws_F, ws_part, ws_out, ws_coef;
     int64_t opt_graph = 0, opt_autotune = 0, opt_items_per_launch = 0;
+    int64_t opt_farrow = 1;  // split-precision resampling in Farrow form where a band has the table
     // bumped whenever device memory a captured launch sequence refers to may have moved
     uint64_t gen = 1;
     // device copies of the band and work-item tables of the last eager call, their pinned
@@ -339,6 +342,77 @@ ccr_status check_ready(ccr_ctx *c, Band &B) {
     return CCR_OK;
 }
 
+// Farrow form of the resampler's tap weights (split precision): c_n(dc) = w sinc(dc - n) on
+// dc in [-1/2, 1/2] is fitted as [n == 0] + sum_{k=1..kFarDeg} A[k - 1][n + D] dc^k by least
+// squares on 64 Chebyshev points (modified Gram-Schmidt, twice, in long double), with the
+// constant term exact so that an on-grid sample stays the input sample.  Returns the largest
+// sum_n |fit - c_n| over a grid of 4001 offsets (infinity if the window's centre weight is not 1).
+double farrow_fit(int D, int window, const std::vector<double> &w64, std::vector<double> &A) {
+    constexpr int NP = 64, NK = kFarDeg;
+    const int NT = 2 * D + 1;
+    auto tap = [&](long double dc, int n) -> long double {
+        const long double d = dc - (long double)n;
+        const long double sc = d == 0.0L ? 1.0L : sinl(kPiL * d) / (kPiL * d);
+        const long double w =
+            window == 0 ? (long double)w64[n + D] : 0.54L + 0.46L * cosl(kPiL * d / (long double)(D + 1));
+        return w * sc;
+    };
+    const long double w0 = window == 0 ? (long double)w64[D] : 1.0L;
+    if (fabsl(w0 - 1.0L) > 1e-15L) return INFINITY;
+    long double x[NP], Qm[NK][NP], Rm[NK][NK] = {};
+    for (int i = 0; i < NP; ++i) x[i] = 0.5L * cosl(kPiL * ((long double)i + 0.5L) / NP);
+    for (int k = 0; k < NK; ++k) {
+        for (int i = 0; i < NP; ++i) Qm[k][i] = powl(x[i], k + 1);
+        for (int pass = 0; pass < 2; ++pass)
+            for (int q = 0; q < k; ++q) {
+                long double d = 0.0L;
+                for (int i = 0; i < NP; ++i) d += Qm[q][i] * Qm[k][i];
+                Rm[q][k] += d;
+                for (int i = 0; i < NP; ++i) Qm[k][i] -= d * Qm[q][i];
+            }
+        long double nn = 0.0L;
+        for (int i = 0; i < NP; ++i) nn += Qm[k][i] * Qm[k][i];
+        nn = sqrtl(nn);
+        Rm[k][k] = nn;
+        for (int i = 0; i < NP; ++i) Qm[k][i] /= nn;
+    }
+    A.assign((size_t)NK * NT, 0.0);
+    std::vector<long double> Al((size_t)NK * NT);
+    for (int n = -D; n <= D; ++n) {
+        long double b[NP], qb[NK], a[NK];
+        for (int i = 0; i < NP; ++i) b[i] = tap(x[i], n) - (n == 0 ? 1.0L : 0.0L);
+        for (int k = 0; k < NK; ++k) {
+            qb[k] = 0.0L;
+            for (int i = 0; i < NP; ++i) qb[k] += Qm[k][i] * b[i];
+        }
+        for (int k = NK - 1; k >= 0; --k) {
+            long double v = qb[k];
+            for (int q = k + 1; q < NK; ++q) v -= Rm[k][q] * a[q];
+            a[k] = v / Rm[k][k];
+        }
+        for (int k = 0; k < NK; ++k) {
+            Al[(size_t)k * NT + n + D] = a[k];
+            A[(size_t)k * NT + n + D] = (double)a[k];
+        }
+    }
+    long double worst = 0.0L;
+    for (int g = 0; g <= 4000; ++g) {
+        const long double dc = -0.5L + (long double)g / 4000.0L;
+        long double e = 0.0L;
+        for (int n = -D; n <= D; ++n) {
+            long double v = 0.0L;
+            for (int k = NK - 1; k >= 0; --k) v = (v + (long double)A[(size_t)k * NT + n + D]) * dc;
+            e += fabsl(v + (n == 0 ? 1.0L : 0.0L) - tap(dc, n));
+        }
+        worst = std::max(worst, e);
+    }
+    return (double)worst;
+}
+
+// Largest fit error accepted for the Farrow form (sum over the taps, relative to the input
+// amplitude): below the split path's FP32 rounding of the tap sum.
+constexpr double kFarTol = 2e-7;
+
 ccr_status prepare(ccr_ctx *c, Band &B) {
     if (B.prepared) return CCR_OK;
     ccr_status st = check_ready(c, B);
@@ -499,6 +573,9 @@ ccr_status prepare(ccr_ctx *c, Band &B) {
     B.n_work = (int)work.size();
     B.active = std::move(active);
     B.plan = pl;
+    B.far_len = 0;
+    std::vector<double> farA;
+    B.far_err = farrow_fit(D, B.p.window, w64, farA);
     if (c->device < 0) {  // host-only context: planning and validation without device tables
         B.prepared = true;
         return CCR_OK;
@@ -568,6 +645,22 @@ ccr_status prepare(ccr_ctx *c, Band &B) {
     if ((st = upload(c, B.d_active, B.active))) return st;
     if ((st = upload(c, B.d_work, work))) return st;
     if ((st = upload(c, B.d_seg_work, seg_work))) return st;
+    // Farrow table of the split-precision resampler (kept out when the fit is not accurate
+    // enough or the table does not fit in device memory)
+    {
+        const int64_t L = (n + 2 * D + 255) / 256 * 256;
+        if (B.far_err <= kFarTol) {
+            if ((st = upload(c, B.d_farrow_A, farA))) return st;
+            if (B.d_farrow.ensure((size_t)Q * (kFarDeg + 1) * L * sizeof(float2)) == hipSuccess) {
+                HIP_OK(c, launch_farrow_table(B.d_x.as<float2>(), n, Q, D, B.d_farrow_A.as<double>(), L,
+                                              B.d_farrow.as<float2>(), nullptr));
+                HIP_OK(c, hipStreamSynchronize(nullptr));
+                B.far_len = L;
+            } else {
+                (void)hipGetLastError();
+            }
+        }
+    }
     B.prepared = true;
     return CCR_OK;
 }
@@ -723,6 +816,8 @@ BandDev band_dev(const Band &B) {
     d.n_seg_any = B.n_seg_any;
     d.newton_steps = B.newton_steps;
     d.cheb_split = B.cheb_split;
+    d.farrow = B.far_len > 0 ? B.d_farrow.as<float2>() : nullptr;
+    d.far_len = B.far_len;
     return d;
 }
 
@@ -842,10 +937,11 @@ struct Variant {
     bool reg16 = false;  // otherwise: 256-point register FFT (else the LDS Stockham FFT on n_s points)
     bool z4 = false;     // spectra + pair sum: N_K <= 192 (4 of the 16 FFT input rows are zero)
     bool ss = false;     // time base with the short small-angle series
+    bool far = false;    // split-precision resampling in Farrow form
     int DT = 0, window = 0, n_s = 0, nr = 0, n_cheb = kCheb;
     bool operator==(const Variant &o) const {
-        return sp == o.sp && reg16 == o.reg16 && z4 == o.z4 && ss == o.ss && DT == o.DT && window == o.window && n_s == o.n_s &&
-               nr == o.nr && n_cheb == o.n_cheb;
+        return sp == o.sp && reg16 == o.reg16 && z4 == o.z4 && ss == o.ss && far == o.far && DT == o.DT &&
+               window == o.window && n_s == o.n_s && nr == o.nr && n_cheb == o.n_cheb;
     }
 };
 
@@ -871,9 +967,10 @@ struct BatchParams {
     int64_t template_batch = 0, k_chunk = 0;
 };
 
-Variant variant_of(const BandDev &bd, bool fp64, bool short_series) {
+Variant variant_of(const BandDev &bd, bool fp64, bool short_series, bool farrow) {
     Variant v;
     v.ss = short_series;
+    v.far = farrow && !fp64 && bd.farrow != nullptr;
     v.sp = spectra_pairs_ok(bd, fp64, kMaxLds);
     v.DT = bd.D == 8 ? 8 : 0;
     v.window = bd.window;
@@ -889,6 +986,17 @@ Variant variant_of(const BandDev &bd, bool fp64, bool short_series) {
 }
 
 constexpr int64_t kMaxBlocks = ((int64_t)1 << 31) - 1;
+
+// Largest grid of a stage's kernel: at most 2^31 - 1 workgroups and 2^32 - 1 work-items.
+int64_t stage_max_blocks(const Variant &v, int st) {
+    int threads = 64;
+    if (st == kStTimebase) threads = tb_entries(v.n_cheb) * v.n_cheb;
+    else if (st == kStResample) threads = v.far ? 256 : 64;
+    else if (st == kStSpectra) threads = v.sp ? 64 : (v.reg16 ? 128 : spectra_threads(v.n_s));
+    else if (st == kStPairs) threads = kPairsThreads;
+    else if (st == kStFinish) threads = kFinishThreads;
+    return std::min<int64_t>(kMaxBlocks, (((int64_t)1 << 32) - 1) / threads);
+}
 
 // Grow a workspace buffer; device work that may still use the old allocation is finished
 // first, and captured launch sequences that refer to it are invalidated.
@@ -936,7 +1044,8 @@ ccr_status build_plan(ccr_ctx *c, bool fp64, int n_bands, const int *band_ids, v
         const Plan &pl = B.plan;
         const BandDev bd = band_dev(B);
         cp.bands.push_back(bd);
-        const Variant v = variant_of(bd, fp64, B.short_series);
+        const Variant v = variant_of(bd, fp64, B.short_series, c->opt_farrow != 0);
+        const int res_t = v.far ? kFarTemplates : kResTemplates;  // templates per resampler workgroup
         if (std::find(variants.begin(), variants.end(), v) == variants.end()) variants.push_back(v);
         int64_t kc = bp.k_chunk > 0 ? bp.k_chunk : std::min<int64_t>(pl.n_seg, 256);
         kc = std::max<int64_t>(1, std::min<int64_t>(kc, pl.n_seg));
@@ -960,7 +1069,10 @@ ccr_status build_plan(ccr_ctx *c, bool fp64, int n_bands, const int *band_ids, v
         const int64_t per_t[kStages] = {proto.gx[0], proto.gx[1], proto.gx[2], (int64_t)proto.gx[3] * nch, proto.gx[4]};
         int64_t tb = bp.template_batch > 0 ? bp.template_batch : c->opt_template_batch;
         if (tb <= 0) tb = (int64_t)std::max<size_t>(1, budget / std::max<size_t>(y1 + F1 + part1 + coef1, 1));
-        for (int st = 0; st < kStages; ++st) tb = std::min<int64_t>(tb, kMaxBlocks / std::max<int64_t>(per_t[st], 1));
+        for (int st = 0; st < kStages; ++st) {
+            const int64_t mb = stage_max_blocks(v, st) / std::max<int64_t>(per_t[st], 1);
+            tb = std::min<int64_t>(tb, st == kStResample ? mb * res_t : mb);
+        }
         tb = std::max<int64_t>(1, std::min<int64_t>(tb, B.n_tmpl));
         char *dst = out_on_device ? static_cast<char *>(rho_out[bi]) : c->ws_out.as<char>() + cp.out_off[bi];
         for (int64_t t = 0; t < B.n_tmpl; t += tb) {
@@ -977,7 +1089,7 @@ ccr_status build_plan(ccr_ctx *c, bool fp64, int n_bands, const int *band_ids, v
             q.coef = coef1 * nb;
             q.lds = v.sp ? spectra_pairs_lds(bd) : 0;
             for (int st = 0; st < kStages; ++st) q.blk[st] = per_t[st] * nb;
-            q.blk[kStResample] = per_t[kStResample] * ((nb + kResTemplates - 1) / kResTemplates);
+            q.blk[kStResample] = per_t[kStResample] * ((nb + res_t - 1) / res_t);
             pend.push_back(q);
         }
     }
@@ -997,7 +1109,7 @@ ccr_status build_plan(ccr_ctx *c, bool fp64, int n_bands, const int *band_ids, v
         for (const Pending &q : pend) {
             if (!(q.v == v)) continue;
             bool full = r.y_bytes + r.F_bytes + r.part_bytes + r.coef_bytes + q.y + q.F + q.part + q.coef > budget;
-            for (int st = 0; st < kStages; ++st) full = full || r.blocks[st] + q.blk[st] > kMaxBlocks;
+            for (int st = 0; st < kStages; ++st) full = full || r.blocks[st] + q.blk[st] > stage_max_blocks(v, st);
             if (c->opt_items_per_launch > 0 && r.n >= c->opt_items_per_launch) full = true;
             if (r.n > 0 && full) {
                 close();
@@ -1028,12 +1140,29 @@ ccr_status build_plan(ccr_ctx *c, bool fp64, int n_bands, const int *band_ids, v
 }
 
 ccr_status ensure_workspace(ccr_ctx *c, const CallPlan &cp) {
-    ccr_status st;
     // 256 samples of tail pad: the spectra kernels read whole 256-sample rows of the last segment
-    if ((st = grow(c, c->ws_y, cp.y_bytes + 256 * sizeof(double2)))) return st;
-    if ((st = grow(c, c->ws_F, std::max<size_t>(cp.F_bytes, 16)))) return st;
-    if ((st = grow(c, c->ws_part, std::max<size_t>(cp.part_bytes, 16)))) return st;
-    return grow(c, c->ws_coef, std::max<size_t>(cp.coef_bytes, 16));
+    DevBuf *buf[4] = {&c->ws_y, &c->ws_F, &c->ws_part, &c->ws_coef};
+    const size_t need[4] = {cp.y_bytes + 256 * sizeof(double2), std::max<size_t>(cp.F_bytes, 16),
+                            std::max<size_t>(cp.part_bytes, 16), std::max<size_t>(cp.coef_bytes, 16)};
+    // Buffers that grow are re-allocated; the others are kept.  When what is kept plus what
+    // grows exceeds the budget (a call of another precision or band mix, whose split between
+    // the buffers differs), every buffer is released first and allocated at its exact size,
+    // so the workspace never holds more than the budget.
+    size_t keep = 0, add = 0;
+    for (int i = 0; i < 4; ++i) {
+        if (need[i] > buf[i]->bytes || !buf[i]->p) add += need[i];
+        else keep += buf[i]->bytes;
+    }
+    const size_t budget = c->opt_workspace_mb > 0 ? (size_t)c->opt_workspace_mb << 20 : c->auto_budget;
+    if (add > 0 && keep + add > budget + (256 << 10)) {
+        HIP_OK(c, hipDeviceSynchronize());
+        for (DevBuf *b : buf) b->release();
+        c->gen++;
+    }
+    ccr_status st;
+    for (int i = 0; i < 4; ++i)
+        if ((st = grow(c, *buf[i], need[i]))) return st;
+    return CCR_OK;
 }
 
 // Bytes of the device table (band descriptors, then work items, 256-byte aligned).
@@ -1063,7 +1192,7 @@ ccr_status run_rounds(ccr_ctx *c, const CallPlan &cp, size_t r0, size_t r1, bool
         {
             LaunchTimer lt(c, 0, s, timing);
             HIP_OK(c, launch_resample_m(db, di, r.n, (int)r.blocks[kStResample], fp64, r.v.DT, r.v.window,
-                                        r.v.n_cheb, coef, c->ws_y.p, s));
+                                        r.v.n_cheb, r.v.far, coef, c->ws_y.p, s));
         }
         if (r.v.sp) {
             LaunchTimer lt(c, 6, s, timing);
@@ -1315,8 +1444,10 @@ ccr_status ccr_set_option(ccr_ctx *c, const char *name, int64_t value) {
     else if (k == "graph") c->opt_graph = value;
     else if (k == "autotune") c->opt_autotune = value;
     else if (k == "items_per_launch") c->opt_items_per_launch = value;
+    else if (k == "farrow") c->opt_farrow = value ? 1 : 0;
     else return fail(c, CCR_EUNSUP, "unknown option '%s'", name);
-    if (k == "template_batch" || k == "workspace_mb" || k == "k_chunk" || k == "items_per_launch") c->gen++;
+    if (k == "template_batch" || k == "workspace_mb" || k == "k_chunk" || k == "items_per_launch" || k == "farrow")
+        c->gen++;
     return CCR_OK;
 }
 
@@ -1335,6 +1466,9 @@ ccr_status ccr_get_option(ccr_ctx *c, const char *name, int64_t *value) {
     else if (k == "tuned_k_chunk") *value = c->last_tuned_k_chunk;
     else if (k == "tuned_template_batch") *value = c->last_tuned_template_batch;
     else if (k == "resample_templates") *value = kResTemplates;
+    else if (k == "farrow") *value = c->opt_farrow;
+    else if (k == "farrow_templates") *value = kFarTemplates;
+    else if (k == "farrow_degree") *value = kFarDeg;
     else return fail(c, CCR_EUNSUP, "unknown option '%s'", name);
     return CCR_OK;
 }
@@ -1507,6 +1641,8 @@ ccr_status ccr_get_band_info(ccr_ctx *c, int band_id, ccr_band_info *info, doubl
     info->t_fft = pl.t_fft;
     info->nu_r = pl.nu_r;
     info->norm = pl.norm;
+    info->farrow_degree = B->far_len > 0 ? kFarDeg : 0;
+    info->farrow_err = B->far_err;
     if (bin_freqs) std::memcpy(bin_freqs, B->freqs.data(), sizeof(double) * (size_t)pl.n_f);
     return CCR_OK;
 }
@@ -1598,7 +1734,8 @@ ccr_status ccr_resample_series(ccr_ctx *c, ccr_precision prec, int band_id, int6
     HIP_OK(c, cf.ensure((size_t)std::max(B->n_work, 1) * kCheb * sizeof(double)));
     hipStream_t s = c->stream;
     HIP_OK(c, launch_zero(y.p, bytes, s));
-    const BandDev bd = band_dev(*B);
+    BandDev bd = band_dev(*B);
+    if (!c->opt_farrow) bd.farrow = nullptr;
     HIP_OK(c, launch_timebase(bd, B->d_tmpl.as<double>() + (size_t)template_index * kTmplStride, 1, cf.as<double>(), s));
     HIP_OK(c, launch_resample(bd, cf.as<double>(), 1, fp64, y.p, s));
     const size_t per = (size_t)pl.n_seg * pl.n_k * cs;
@@ -1667,7 +1804,8 @@ ccr_status ccr_segment_spectra(ccr_ctx *c, ccr_precision prec, int band_id, int6
     hipStream_t s = c->stream;
     HIP_OK(c, launch_zero(y.p, ybytes, s));
     HIP_OK(c, launch_zero(F.p, fbytes, s));
-    const BandDev bd = band_dev(*B);
+    BandDev bd = band_dev(*B);
+    if (!c->opt_farrow) bd.farrow = nullptr;
     HIP_OK(c, launch_timebase(bd, B->d_tmpl.as<double>() + (size_t)template_index * kTmplStride, 1, cf.as<double>(), s));
     HIP_OK(c, launch_resample(bd, cf.as<double>(), 1, fp64, y.p, s));
     HIP_OK(c, launch_spectra(bd, 1, fp64, y.p, F.p, s));

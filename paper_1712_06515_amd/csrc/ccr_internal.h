@@ -91,6 +91,11 @@ struct BandDev {
     int n_seg_any;
     int newton_steps;         // Newton steps of the time-base node solve (2 or 3)
     int cheb_split;           // time-base nodes of the split path (kChebSplitMin, kChebSplit or kCheb)
+    // Farrow table of the split-precision resampler, [Q][kFarDeg + 1][far_len] complex64:
+    // plane k at index j + D holds F_k(j) = sum_n A_kn x'_{j+n} (F_0 = x'), zero beyond
+    // j + D >= n + 2D; null when the band has none
+    const float2 *farrow;
+    int64_t far_len;
 };
 
 // One work item of a batched launch: a run of consecutive templates of one band.  A batched
@@ -120,6 +125,15 @@ constexpr int kSpec16Groups = 8;     // 256-point register FFT: segments per 128
 constexpr int kPairsThreads = 128;   // pair sum: bins per workgroup
 constexpr int kFinishThreads = 256;  // finish: bins per workgroup
 constexpr int kResTemplates = 4;     // resampling: templates per workgroup
+// Farrow-form resampling (split precision): tap weights as polynomials of degree kFarDeg in the
+// offset; a 256-thread workgroup (kFarWaves wavefronts, kFarPerWave templates each) stages the
+// table planes of chunks of kFarChunk samples of one segment in LDS (kFarCap entries a plane)
+constexpr int kFarDeg = 9;
+constexpr int kFarWaves = 4;
+constexpr int kFarPerWave = 8;
+constexpr int kFarTemplates = kFarWaves * kFarPerWave;
+constexpr int kFarChunk = 192;
+constexpr int kFarCap = 224;
 
 // Launchers (ccr_kernels.hip).  All queue work on `stream` and return the launch status.
 // Monomial coefficients of the time base (interpolant through Chebyshev nodes), coef[n_tmpl][n_work][kCheb].
@@ -150,8 +164,14 @@ int spectra_threads(int n_s);               // threads of the LDS Stockham FFT w
 hipError_t launch_timebase_m(const BandDev *bands, const WorkItem *items, int n_items, int blocks, int n_cheb,
                              bool short_series, double *coef,
                              hipStream_t stream);
+// farrow: the split-precision Farrow-form kernel (bands with a table; kFarTemplates templates a
+// workgroup); else one wavefront per kResTemplates templates.
 hipError_t launch_resample_m(const BandDev *bands, const WorkItem *items, int n_items, int blocks, bool fp64, int D,
-                             int window, int n_cheb, const double *coef, void *y, hipStream_t stream);
+                             int window, int n_cheb, bool farrow, const double *coef, void *y, hipStream_t stream);
+// The Farrow table of a band (BandDev::farrow) from its input series x [Q][n] and the fitted
+// coefficients A [kFarDeg][2D + 1] (row k - 1 for the power dc^k).
+hipError_t launch_farrow_table(const float2 *x, int64_t n, int Q, int D, const double *A, int64_t far_len,
+                               float2 *tab, hipStream_t stream);
 // z4: N_K <= 192, so the last 4 of the 16 input rows of each 256-point FFT are zero padding.
 hipError_t launch_spectra_pairs_m(const BandDev *bands, const WorkItem *items, int n_items, int blocks, int rounds,
                                   bool z4, size_t lds, const void *y, double *part, hipStream_t stream);

@@ -10,6 +10,8 @@
 //   k_finish    sum of chunk partials and the sqrt(2) / N factor.
 #include <hip/hip_runtime.h>
 
+#include <climits>
+
 #include "ccr_internal.h"
 
 namespace ccr {
@@ -475,6 +477,184 @@ __device__ __forceinline__ void resample_body(const BandDev &B, const double *co
 template <typename T, int DT, int WIN>
 __global__ void __launch_bounds__(64) k_resample(BandDev B, const double *coef, c2<T> *y) {
     resample_body<T, DT, WIN>(B, coef, y, blockIdx.x, blockIdx.y, blockIdx.y + 1);
+}
+
+// ------------------------------------------------------------------ Farrow-form resampling
+// Split precision.  The weight of tap n as a function of the offset, c_n(dc) = w sinc(dc - n)
+// on dc in [-1/2, 1/2], is replaced by a polynomial [n == 0] + sum_{k=1..kFarDeg} A_kn dc^k
+// (least-squares fit by the host, which bounds sum_n |error| and keeps the direct kernel for a
+// window whose bound is too large); then the interpolated value is a polynomial in dc,
+// sum_n c_n(dc) x'_{j*+n} = sum_k F_k(j*) dc^k with F_k(j) = sum_n A_kn x'_{j+n} and F_0 = x'
+// (the Farrow structure of fractional-delay filters).  F depends on the input series only, so it
+// is tabulated once per band and detector; per sample the resampler evaluates one complex
+// polynomial of degree kFarDeg instead of 2D + 1 reciprocals and products.  An on-grid sample
+// (dc = 0) is x'_{j*} exactly, as in the direct form.
+
+// F_k(j) for every detector and j + D in [0, far_len): FP64 sums, stored complex64.
+__global__ void __launch_bounds__(256) k_farrow_table(const float2 *__restrict__ x, int64_t n, int D,
+                                                      const double *__restrict__ A, int64_t far_len,
+                                                      float2 *__restrict__ tab) {
+    const int64_t jj = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (jj >= far_len) return;
+    const int det = blockIdx.y;
+    const float2 *xd = x + (size_t)det * n;
+    float2 *td = tab + (size_t)det * (kFarDeg + 1) * far_len;
+    const int64_t j = jj - D;
+    double re[kFarDeg], im[kFarDeg];
+#pragma unroll
+    for (int k = 0; k < kFarDeg; ++k) re[k] = im[k] = 0.0;
+    for (int m = -D; m <= D; ++m) {
+        const int64_t jm = j + m;
+        if (jm < 0 || jm >= n) continue;
+        const float2 xv = xd[jm];
+        const double *a = A + (m + D);
+#pragma unroll
+        for (int k = 0; k < kFarDeg; ++k) {
+            re[k] = fma(a[k * (2 * D + 1)], (double)xv.x, re[k]);
+            im[k] = fma(a[k * (2 * D + 1)], (double)xv.y, im[k]);
+        }
+    }
+    td[jj] = (j >= 0 && j < n) ? xd[j] : make_float2(0.f, 0.f);
+#pragma unroll
+    for (int k = 0; k < kFarDeg; ++k) td[(size_t)(k + 1) * far_len + jj] = make_float2((float)re[k], (float)im[k]);
+}
+
+// sum_k F_k dc^k by Horner; F_k at p[k * stride].
+template <typename P>
+__device__ __forceinline__ float2 farrow_eval(const P *p, int64_t stride, float dc) {
+    float2 f[kFarDeg + 1];
+#pragma unroll
+    for (int k = 0; k <= kFarDeg; ++k) f[k] = p[k * stride];
+    float re = f[kFarDeg].x, im = f[kFarDeg].y;
+#pragma unroll
+    for (int k = kFarDeg - 1; k >= 0; --k) {
+        re = fmaf(re, dc, f[k].x);
+        im = fmaf(im, dc, f[k].y);
+    }
+    return make_float2(re, im);
+}
+
+// One 256-thread workgroup per (active segment entry, templates [t0, t1)), t1 - t0 <=
+// kFarTemplates; wavefront v takes templates t0 + v kFarPerWave + i.  Per chunk of kFarChunk
+// samples the workgroup finds the range of j* over its templates (j* is nondecreasing in the
+// sample index, so the chunk's first and last samples bound it), stages that range of every
+// table plane in LDS with coalesced loads, and each lane then reads its sample's kFarDeg + 1
+// coefficients from LDS (consecutive lanes, consecutive entries).  A range wider than kFarCap
+// (not met for physical delays) reads the table in global memory instead.
+template <int NC>
+__device__ __forceinline__ void resample_far_body(const BandDev &B, const double *coef, float2 *y, int w, int t0,
+                                                  int t1) {
+    __shared__ float2 sf[(kFarDeg + 1) * kFarCap];
+    __shared__ int s_lo[kFarWaves], s_hi[kFarWaves];
+    const int entry = B.work[w];
+    const int det = entry / B.n_seg;
+    const int K = entry - det * B.n_seg;
+    const int64_t nr = (int64_t)B.n_seg * B.n_k;
+    const uint8_t *mk_ = B.mask + (size_t)det * nr + (size_t)K * B.n_k;
+    const float2 *tab = B.farrow + (size_t)det * (kFarDeg + 1) * B.far_len;
+    const Anchor an = B.anchors[entry];
+    const double inv_nk = 1.0 / (double)B.n_k;
+    const int64_t r0 = (int64_t)K * B.n_k;
+    // wave-uniform (readfirstlane), so that a template's time-base coefficients are scalar
+    // loads: a vector load's wait would also wait for the previous pass's stores
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
+    const int tw0 = t0 + wave * kFarPerWave;
+    for (int c0 = 0; c0 < B.n_k; c0 += kFarChunk) {
+        const int c1 = min(B.n_k, c0 + kFarChunk);
+        {
+            // lanes i < kFarPerWave: j* - r0 at sample c0 of template tw0 + i; lanes 32 + i: at c1 - 1
+            const int i = lane & 31, tb = tw0 + i;
+            int jr = 0;
+            if (i < kFarPerWave && tb < t1) {
+                const double *cf = coef + ((size_t)tb * B.n_work + w) * kCheb;
+                double cl[NC];
+#pragma unroll
+                for (int k = 0; k < NC; ++k) cl[k] = cf[k];
+                const int s = lane < 32 ? c0 : c1 - 1;
+                int64_t js;
+                double dc, psi;
+                sample_time<NC>(cl, (double)(2 * s - B.n_k) * inv_nk, an, B.inv_dt, B.f_het, r0 + s, js, dc, psi);
+                jr = (int)(js - r0);
+            }
+            int lo = INT_MAX, hi = INT_MIN;
+#pragma unroll
+            for (int q = 0; q < kFarPerWave; ++q) {
+                if (tw0 + q < t1) {
+                    lo = min(lo, __builtin_amdgcn_readlane(jr, q));
+                    hi = max(hi, __builtin_amdgcn_readlane(jr, 32 + q));
+                }
+            }
+            if (lane == 0) {
+                s_lo[wave] = lo;
+                s_hi[wave] = hi;
+            }
+        }
+        __syncthreads();
+        int jlo = s_lo[0], jhi = s_hi[0];  // wavefront 0 holds template t0 < t1
+#pragma unroll
+        for (int q = 1; q < kFarWaves; ++q) {
+            jlo = min(jlo, s_lo[q]);
+            jhi = max(jhi, s_hi[q]);
+        }
+        const int span = jhi - jlo + 1;
+        const bool staged = span <= kFarCap;
+        if (staged) {
+            const int64_t jb = r0 + jlo + B.D;  // table index of j* = r0 + jlo
+            for (int i = threadIdx.x; i < span; i += 256) {
+                const int64_t jj = jb + i;
+                const bool ok = jj >= 0 && jj < B.far_len;
+#pragma unroll
+                for (int k = 0; k <= kFarDeg; ++k)
+                    sf[k * kFarCap + i] = ok ? tab[(size_t)k * B.far_len + jj] : make_float2(0.f, 0.f);
+            }
+        }
+        // gap mask of the chunk's samples, shared by the templates: bit p = sample c0 + 64 p + lane
+        static_assert(kFarChunk <= 64 * 32, "mask bits");
+        uint32_t mbits = 0;
+        for (int p = 0; c0 + 64 * p < c1; ++p) {
+            const int s = c0 + 64 * p + lane;
+            if (s < c1 && mk_[s]) mbits |= 1u << p;
+        }
+        __syncthreads();
+        for (int i = 0; i < kFarPerWave; ++i) {
+            const int tb = tw0 + i;
+            if (tb >= t1) break;
+            float2 *yo = y + ((size_t)tb * B.Q + det) * nr + r0;
+            const double *cf = coef + ((size_t)tb * B.n_work + w) * kCheb;
+            double cl[NC];
+#pragma unroll
+            for (int k = 0; k < NC; ++k) cl[k] = cf[k];
+            for (int s0 = c0, p = 0; s0 < c1; s0 += 64, ++p) {
+                const int s = s0 + lane;
+                if (s >= c1) continue;
+                float2 v = make_float2(0.f, 0.f);
+                if ((mbits >> p) & 1u) {
+                    int64_t js;
+                    double dcd, psi;
+                    sample_time<NC>(cl, (double)(2 * s - B.n_k) * inv_nk, an, B.inv_dt, B.f_het, r0 + s, js, dcd, psi);
+                    const float dc = (float)dcd;
+                    const int jr = (int)(js - r0) - jlo;
+                    float2 a;
+                    if (staged && jr >= 0 && jr < span) {
+                        a = farrow_eval(sf + jr, kFarCap, dc);
+                    } else {
+                        const int64_t jj = js + B.D;
+                        a = (jj >= 0 && jj < B.far_len) ? farrow_eval(tab + jj, B.far_len, dc) : make_float2(0.f, 0.f);
+                    }
+                    float c, sn;
+                    sincos_rev<float>(psi, sn, c);
+                    v = make_float2(c * a.x - sn * a.y, sn * a.x + c * a.y);
+                }
+                yo[s] = v;
+            }
+        }
+        __syncthreads();  // the next chunk restages sf
+    }
+}
+
+__global__ void __launch_bounds__(256) k_resample_far(BandDev B, const double *coef, float2 *y, int n_tmpl) {
+    const int t0 = blockIdx.y * kFarTemplates;
+    resample_far_body<kCheb>(B, coef, y, blockIdx.x, t0, min(n_tmpl, t0 + kFarTemplates));
 }
 
 // Time base samples of one detector's segments [k0, k0 + n) for one template (stage output).
@@ -1397,6 +1577,7 @@ __device__ __forceinline__ BandDev global_view(const BandDev &b, const void *bas
     g.class_start = as_global(b.class_start, base);
     g.zero256 = as_global(b.zero256, base);
     g.bin_col = as_global(b.bin_col, base);
+    g.farrow = as_global(b.farrow, base);
     return g;
 }
 
@@ -1434,6 +1615,19 @@ k_resample_m(const BandDev *__restrict__ bands, const WorkItem *__restrict__ ite
     const int t0 = (l % tiles) * kResTemplates;
     resample_body<T, DT, WIN, NC>(B, coef + it.coef_off, y + it.y_off, l / tiles, t0,
                                   min(it.n_tmpl, t0 + kResTemplates));
+}
+
+template <int NC>
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8)))
+k_resample_far_m(const BandDev *__restrict__ bands, const WorkItem *__restrict__ items, int n_items,
+                 const double *__restrict__ coef, float2 *__restrict__ y) {
+    const WorkItem &it = items[find_item(items, n_items, kStResample, blockIdx.x)];
+    const BandDev B = global_view(bands[it.band], bands);
+    // a segment's template tiles are consecutive workgroups (its table slice stays in L2)
+    const int l = blockIdx.x - it.first[kStResample];
+    const int tiles = (it.n_tmpl + kFarTemplates - 1) / kFarTemplates;
+    const int t0 = (l % tiles) * kFarTemplates;
+    resample_far_body<NC>(B, coef + it.coef_off, y + it.y_off, l / tiles, t0, min(it.n_tmpl, t0 + kFarTemplates));
 }
 
 template <int NR, bool Z4>
@@ -1511,13 +1705,24 @@ static void launch_resample_t(const BandDev &B, const double *coef, int n_tmpl, 
 hipError_t launch_resample(const BandDev &B, const double *coef, int n_tmpl, bool fp64, void *y,
                            hipStream_t stream) {
     if (B.n_work == 0 || n_tmpl == 0) return hipSuccess;
-    if (fp64) {
+    if (!fp64 && B.farrow) {
+        dim3 grid((unsigned)B.n_work, (n_tmpl + kFarTemplates - 1) / kFarTemplates);
+        hipLaunchKernelGGL(k_resample_far, grid, dim3(256), 0, stream, B, coef, (float2 *)y, n_tmpl);
+    } else if (fp64) {
         if (B.D == 8) launch_resample_t<double, 8>(B, coef, n_tmpl, y, stream);
         else launch_resample_t<double, 0>(B, coef, n_tmpl, y, stream);
     } else {
         if (B.D == 8) launch_resample_t<float, 8>(B, coef, n_tmpl, y, stream);
         else launch_resample_t<float, 0>(B, coef, n_tmpl, y, stream);
     }
+    return hipGetLastError();
+}
+
+hipError_t launch_farrow_table(const float2 *x, int64_t n, int Q, int D, const double *A, int64_t far_len,
+                               float2 *tab, hipStream_t stream) {
+    if (Q == 0 || far_len == 0) return hipSuccess;
+    dim3 grid((unsigned)((far_len + 255) / 256), Q);
+    hipLaunchKernelGGL(k_farrow_table, grid, dim3(256), 0, stream, x, n, D, A, far_len, tab);
     return hipGetLastError();
 }
 
@@ -1645,9 +1850,19 @@ static void launch_resample_m_t(const BandDev *bands, const WorkItem *items, int
 }
 
 hipError_t launch_resample_m(const BandDev *bands, const WorkItem *items, int n_items, int blocks, bool fp64, int D,
-                             int window, int n_cheb, const double *coef, void *y, hipStream_t stream) {
+                             int window, int n_cheb, bool farrow, const double *coef, void *y, hipStream_t stream) {
     if (blocks == 0) return hipSuccess;
-    if (fp64) {
+    if (farrow && !fp64) {
+        if (n_cheb == kChebSplitMin)
+            hipLaunchKernelGGL(k_resample_far_m<kChebSplitMin>, dim3(blocks), dim3(256), 0, stream, bands, items,
+                               n_items, coef, (float2 *)y);
+        else if (n_cheb == kChebSplit)
+            hipLaunchKernelGGL(k_resample_far_m<kChebSplit>, dim3(blocks), dim3(256), 0, stream, bands, items,
+                               n_items, coef, (float2 *)y);
+        else
+            hipLaunchKernelGGL(k_resample_far_m<kCheb>, dim3(blocks), dim3(256), 0, stream, bands, items, n_items,
+                               coef, (float2 *)y);
+    } else if (fp64) {
         if (D == 8) launch_resample_m_t<double, 8, kCheb>(bands, items, n_items, blocks, window, coef, y, stream);
         else launch_resample_m_t<double, 0, kCheb>(bands, items, n_items, blocks, window, coef, y, stream);
     } else if (n_cheb == kChebSplit) {

@@ -38,7 +38,7 @@ def test_exports_every_declared_symbol(lib):
     for n in names:
         assert hasattr(lib, n), n
     assert set(names) == set(ccr.SIGNATURES), set(names) ^ set(ccr.SIGNATURES)
-    assert lib.ccr_abi_version() == 1
+    assert lib.ccr_abi_version() == 2
 
 
 def test_struct_layouts_match_header(lib):
@@ -46,7 +46,7 @@ def test_struct_layouts_match_header(lib):
     assert ctypes.sizeof(ccr.Sky) == 9 * 8
     assert ctypes.sizeof(ccr.Site) == 16
     assert ctypes.sizeof(ccr.Band) == 3 * 8 + 4 * 4 + 8 + 8 + 8 + 8  # int32 pairs padded to 8
-    assert ctypes.sizeof(ccr.BandInfo) == 9 * 8 + 8 * 8
+    assert ctypes.sizeof(ccr.BandInfo) == 10 * 8 + 9 * 8
 
 
 def test_null_and_bad_arguments(lib):
@@ -89,6 +89,11 @@ def test_options_round_trip(lib):
     ctx.set_option("workspace_mb", 0)
     assert ctx.get_option("workspace_mb") == 0
     assert ctx.get_option("resample_templates") == 4
+    assert ctx.get_option("farrow") == 1
+    ctx.set_option("farrow", 0)
+    assert ctx.get_option("farrow") == 0
+    assert ctx.get_option("farrow_templates") == 8
+    assert ctx.get_option("farrow_degree") == 9
     assert ctx.get_option("tuned_k_chunk") == 0
     with pytest.raises(ccr.CcrError) as e:
         ctx.get_option("no_such_option")
@@ -192,3 +197,34 @@ def test_plan_of_named_workloads(lib):
         assert info["n_k"] == synth.samples_per_segment(band)
         assert abs(info["df_load"] - synth.load_bandwidth(band["f_min"], band["f_band"], band["t_short"],
                                                           band["a_p_max"])) < 1e-12
+
+
+@pytest.mark.parametrize("window", [0, 1])
+@pytest.mark.parametrize("D", [4, 8, 16])
+def test_farrow_fit_error(lib, D, window):
+    """The host's Farrow fit of the tap weights (degree 9 in the offset, constant term exact):
+    its reported bound, max over offsets of sum_n |fit - w sinc(dc - n)|, is below the 2e-7
+    the library accepts, for the Hamming window indexed by tap (0) and at the offset (1).  The
+    bound is checked against an independent fit (numpy least squares on the same basis) that
+    must reach the same error to within a factor 2, so neither a loose nor a wrong bound passes."""
+    import numpy as np
+    ds = synth.make_dataset(small_config(n_seg=4, dirichlet_D=D, window=window), signal=False)
+    ctx = _host_ctx(ds)
+    info = ctx.band_info(ctx.load(ds))
+    assert info["farrow_degree"] == 0  # host-only context: no device table
+    err = info["farrow_err"]
+    n = np.arange(-D, D + 1)
+
+    def taps(dc):
+        d = dc[:, None] - n[None, :]
+        w = (0.54 - 0.46 * np.cos(np.pi * (n + D) / D)) if window == 0 else 0.54 + 0.46 * np.cos(np.pi * d / (D + 1))
+        return w * np.sinc(d)
+
+    xs = 0.5 * np.cos(np.pi * (np.arange(64) + 0.5) / 64)
+    V = np.vander(xs, 9, increasing=True) * xs[:, None]
+    c0 = (n == 0).astype(float)
+    A = np.linalg.lstsq(V, taps(xs) - c0[None, :], rcond=None)[0]
+    xt = np.linspace(-0.5, 0.5, 4001)
+    ref = np.abs(c0[None, :] + xt[:, None] * (np.vander(xt, 9, increasing=True) @ A) - taps(xt)).sum(1).max()
+    assert err < 2e-7
+    assert 0.5 * ref < err < 2.0 * ref

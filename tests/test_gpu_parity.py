@@ -70,19 +70,39 @@ def test_rho_small_cases(ccr, case, fused):
     assert e32 < TOL32
 
 
-def test_resampled_series_parity(ccr):
-    cfg = small_config(n_seg=12, gap_fraction=0.2, max_lag=1)
+@pytest.mark.parametrize("case", sorted(SMALL_CASES))
+def test_rho_small_cases_direct_taps(ccr, case):
+    # the split path with the direct 2D + 1-tap resampler instead of the Farrow form
+    kw = SMALL_CASES[case]
+    cfg = small_config(**kw, injections=[dict(f0=50.21, a_p=1.25, t_asc_off=0.0, period=68023.7, h0=0.35,
+                                              cosi=0.5, psi=0.3, phi0=1.0)])
+    ds = synth.make_dataset(cfg, sigma_wander=0.2)
+    tm = ds.templates
+    ref = oracle.Oracle(ds).rho(tm)
+    _, r32 = run_both(ccr, ds, tm, farrow=0, k_chunk=5)
+    e32 = rho_err(r32, ref)
+    print(f"{case} direct taps: split {e32:.2e}")
+    assert e32 < TOL32
+
+
+@pytest.mark.parametrize("farrow", [1, 0])
+@pytest.mark.parametrize("window", [0, 1])
+def test_resampled_series_parity(ccr, farrow, window):
+    # farrow 1: split precision in Farrow form (the default), 0: the direct tap sum
+    cfg = small_config(n_seg=12, gap_fraction=0.2, max_lag=1, window=window)
     ds = synth.make_dataset(cfg)
     o = oracle.Oracle(ds)
     with ccr.Context(ds.sky, device=0) as ctx:
+        ctx.set_option("farrow", farrow)
         bid = ctx.load(ds)
+        assert ctx.band_info(bid)["farrow_degree"] == 9
         for t in (0, 3, 5):
             for X in range(2):
                 y_ref, js, off, m = o.resample(X, ds.templates[t])
                 y64 = ctx.resample_series(bid, t, X, prec=ccr.PREC_FP64)
                 y32 = ctx.resample_series(bid, t, X, prec=ccr.PREC_SPLIT)
                 scale = np.abs(y_ref).max()
-                print(f"resampled series t={t} X={X}: fp64 {np.abs(y64 - y_ref).max() / scale:.2e}, "
+                print(f"resampled series farrow={farrow} window={window} t={t} X={X}: fp64 {np.abs(y64 - y_ref).max() / scale:.2e}, "
                       f"split {np.abs(y32 - y_ref).max() / scale:.2e} of the peak")
                 assert np.abs(y64 - y_ref).max() < 1e-12 * scale
                 assert np.abs(y32 - y_ref).max() < 2e-6 * scale
