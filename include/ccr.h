@@ -165,7 +165,10 @@ const char *ccr_last_error(const ccr_ctx *ctx);
  *                     (an explicit "k_chunk" disables tuning);
  *   "farrow"          1 (default): split-precision resampling in Farrow form where the band
  *                     has the table (see ccr_band_info.farrow_degree), 0: the direct
- *                     2D + 1-tap form.  FP64 always uses the direct form.
+ *                     2D + 1-tap form.  FP64 always uses the direct form;
+ *   "farrow_stage"    1 (default): the Farrow kernel stages each chunk's table entries in
+ *                     LDS; 0: every sample reads them from global memory (the path a chunk
+ *                     takes when its range is too wide for LDS; slower, for testing).
  * All bands of a compute call run in shared launches: one launch per stage covers the work
  * items of many bands (grouped by kernel variant, packed to the workspace budget).
  * Returns CCR_EUNSUP for an unknown name. */

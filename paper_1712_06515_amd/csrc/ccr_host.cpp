@@ -111,6 +111,7 @@ struct ccr_ctx {
     DevBuf ws_y, ws_F, ws_part, ws_out, ws_coef;
     int64_t opt_graph = 0, opt_autotune = 0, opt_items_per_launch = 0;
     int64_t opt_farrow = 1;  // split-precision resampling in Farrow form where a band has the table
+    int64_t opt_farrow_stage = 1;  // Farrow kernel: stage the table in LDS (0: global reads, for tests)
     // bumped whenever device memory a captured launch sequence refers to may have moved
     uint64_t gen = 1;
     // device copies of the band and work-item tables of the last eager call, their pinned
@@ -580,11 +581,11 @@ ccr_status prepare(ccr_ctx *c, Band &B) {
         B.prepared = true;
         return CCR_OK;
     }
-    // Chebyshev nodes x_j of an N-node rule (N = kCheb, kChebSplit, kChebSplitMin) and the maps from
+    // Chebyshev nodes x_j of an N-node rule (N = kCheb ... kChebSplitLow) and the maps from
     // node values to the monomial coefficients of the interpolant: Chebyshev coefficients
     // c_k = (2 / N) sum_j eta_j T_k(x_j) (c_0 halved), then the monomial coefficients of each
     // T_k (T_{k+1} = 2 x T_k - T_{k-1}); long double, rows and columns beyond N zero
-    std::vector<double> cx(kCheb + kChebSplit + kChebSplitMin), mono(3 * kCheb * kCheb, 0.0);
+    std::vector<double> cx(kChebNodesAll), mono(kChebRules * kCheb * kCheb, 0.0);
     {
         long double Tm[kCheb][kCheb] = {};  // Tm[k][m]: coefficient of x^m in T_k
         Tm[0][0] = 1.0L;
@@ -592,7 +593,7 @@ ccr_status prepare(ccr_ctx *c, Band &B) {
         for (int k = 1; k + 1 < kCheb; ++k)
             for (int m = 0; m < kCheb; ++m)
                 Tm[k + 1][m] = (m > 0 ? 2.0L * Tm[k][m - 1] : 0.0L) - Tm[k - 1][m];
-        for (int N : {kCheb, kChebSplit, kChebSplitMin}) {
+        for (int N : {kCheb, kChebSplit, kChebSplitMin, kChebSplitLow}) {
             const int v = cheb_rule(N);
             for (int j = 0; j < N; ++j) cx[cheb_x_off(N) + j] = (double)cosl(kPiL * ((long double)j + 0.5L) / N);
             for (int m = 0; m < N; ++m)
@@ -693,9 +694,10 @@ ccr_status prepare_templates(ccr_ctx *c, Band &B) {
     // e0 = de + a_p Omega (a_p + de) (de: Earth-delay change over the segment), and each step
     // maps e -> K e^2 with K = G''/(2 G'); two steps suffice when K^3 e0^4 < 1e-20 s.
     // Chebyshev: the series of A sin(omega u + phi) on [-h, h] has coefficients 2A J_k(omega h)
-    // <= 2A (omega h / 2)^k / k!; the split path interpolates at 6 or else 7 nodes (error at most
-    // twice the tail from k = 6 or 7) when twice the tail stays below 1e-9 cycles of the top
-    // frequency and 1e-9 samples.
+    // <= 2A (omega h / 2)^k / k!; the split path interpolates at 5, 6 or else 7 nodes (error at
+    // most twice the tail from k = 5, 6 or 7) when twice the tail stays below 1e-8 cycles of the
+    // top frequency and 1e-8 samples: under the FP32 rounding of the phase and the offset the
+    // split path applies afterwards (up to 3e-8 cycles and 3e-8 samples).
     {
         double Aw = 0.0, Aw2 = 0.0;
         std::vector<std::pair<double, double>> comps;  // (amplitude, angular rate) of the Earth terms
@@ -707,7 +709,7 @@ ccr_status prepare_templates(ccr_ctx *c, Band &B) {
             comps.push_back({(double)m.A_d, (double)m.w_d});
         }
         const double h = 0.5 * (double)tseg;
-        double worst_e2 = 0.0, worst_tail = 0.0, worst_tail6 = 0.0;
+        double worst_e2 = 0.0, worst_tail = 0.0, worst_tail6 = 0.0, worst_tail5 = 0.0;
         for (int64_t t = 0; t < T; ++t) {
             const double ap = B.tmpl_raw[3 * t], Om = 2.0 * kPi / B.tmpl_raw[3 * t + 2];
             const double X = h + ap + 1.0;
@@ -716,7 +718,7 @@ ccr_status prepare_templates(ccr_ctx *c, Band &B) {
             const double K = (1.1 * ap * Om * Om + 1.1 * Aw2) / (2.0 * (1.0 - ap * Om) * (1.0 - Aw));
             const double e1 = K * e0 * e0, e2 = K * e1 * e1;
             worst_e2 = std::max(worst_e2, e2);
-            double tail = 0.0, tail6 = 0.0;
+            double tail = 0.0, tail6 = 0.0, tail5 = 0.0;
             std::vector<std::pair<double, double>> all = comps;
             all.push_back({ap, Om});
             for (const auto &cw : all) {
@@ -726,10 +728,12 @@ ccr_status prepare_templates(ccr_ctx *c, Band &B) {
                     term *= z / k;
                     if (k >= kChebSplit) tail += term;
                     if (k >= kChebSplitMin) tail6 += term;
+                    if (k >= kChebSplitLow) tail5 += term;
                 }
             }
             worst_tail = std::max(worst_tail, tail);
             worst_tail6 = std::max(worst_tail6, tail6);
+            worst_tail5 = std::max(worst_tail5, tail5);
         }
         // short small-angle series (through x^7 / x^8) in the node solve when the dropped terms,
         // amplitude x |angle|^9 / 9! summed over the binary and Earth terms, stay below 1e-16 s
@@ -746,8 +750,10 @@ ccr_status prepare_templates(ccr_ctx *c, Band &B) {
         B.short_series = worst_series < 1e-16;
         const double f_top = B.p.f_min + B.p.f_band;
         B.newton_steps = worst_e2 < 1e-20 ? 2 : 3;
-        auto fits = [&](double tl) { return 2.0 * tl * f_top < 1e-9 && 2.0 * tl / (double)dt < 1e-9; };
-        B.cheb_split = fits(worst_tail6) ? kChebSplitMin : (fits(worst_tail) ? kChebSplit : kCheb);
+        auto fits = [&](double tl) { return 2.0 * tl * f_top < 1e-8 && 2.0 * tl / (double)dt < 1e-8; };
+        B.cheb_split = fits(worst_tail5)   ? kChebSplitLow
+                       : fits(worst_tail6) ? kChebSplitMin
+                                           : (fits(worst_tail) ? kChebSplit : kCheb);
     }
     B.tmpl.assign((size_t)T * kTmplStride, 0.0);
     for (int64_t t = 0; t < T; ++t) {
@@ -818,6 +824,7 @@ BandDev band_dev(const Band &B) {
     d.cheb_split = B.cheb_split;
     d.farrow = B.far_len > 0 ? B.d_farrow.as<float2>() : nullptr;
     d.far_len = B.far_len;
+    d.far_stage = 1;
     return d;
 }
 
@@ -1042,7 +1049,8 @@ ccr_status build_plan(ccr_ctx *c, bool fp64, int n_bands, const int *band_ids, v
     for (int bi = 0; bi < n_bands; ++bi) {
         const Band &B = *get_band(c, band_ids[bi]);
         const Plan &pl = B.plan;
-        const BandDev bd = band_dev(B);
+        BandDev bd = band_dev(B);
+        bd.far_stage = (int)c->opt_farrow_stage;
         cp.bands.push_back(bd);
         const Variant v = variant_of(bd, fp64, B.short_series, c->opt_farrow != 0);
         const int res_t = v.far ? kFarTemplates : kResTemplates;  // templates per resampler workgroup
@@ -1445,8 +1453,10 @@ ccr_status ccr_set_option(ccr_ctx *c, const char *name, int64_t value) {
     else if (k == "autotune") c->opt_autotune = value;
     else if (k == "items_per_launch") c->opt_items_per_launch = value;
     else if (k == "farrow") c->opt_farrow = value ? 1 : 0;
+    else if (k == "farrow_stage") c->opt_farrow_stage = value ? 1 : 0;
     else return fail(c, CCR_EUNSUP, "unknown option '%s'", name);
-    if (k == "template_batch" || k == "workspace_mb" || k == "k_chunk" || k == "items_per_launch" || k == "farrow")
+    if (k == "template_batch" || k == "workspace_mb" || k == "k_chunk" || k == "items_per_launch" || k == "farrow" ||
+        k == "farrow_stage")
         c->gen++;
     return CCR_OK;
 }
@@ -1467,6 +1477,7 @@ ccr_status ccr_get_option(ccr_ctx *c, const char *name, int64_t *value) {
     else if (k == "tuned_template_batch") *value = c->last_tuned_template_batch;
     else if (k == "resample_templates") *value = kResTemplates;
     else if (k == "farrow") *value = c->opt_farrow;
+    else if (k == "farrow_stage") *value = c->opt_farrow_stage;
     else if (k == "farrow_templates") *value = kFarTemplates;
     else if (k == "farrow_degree") *value = kFarDeg;
     else return fail(c, CCR_EUNSUP, "unknown option '%s'", name);
@@ -1736,6 +1747,7 @@ ccr_status ccr_resample_series(ccr_ctx *c, ccr_precision prec, int band_id, int6
     HIP_OK(c, launch_zero(y.p, bytes, s));
     BandDev bd = band_dev(*B);
     if (!c->opt_farrow) bd.farrow = nullptr;
+    bd.far_stage = (int)c->opt_farrow_stage;
     HIP_OK(c, launch_timebase(bd, B->d_tmpl.as<double>() + (size_t)template_index * kTmplStride, 1, cf.as<double>(), s));
     HIP_OK(c, launch_resample(bd, cf.as<double>(), 1, fp64, y.p, s));
     const size_t per = (size_t)pl.n_seg * pl.n_k * cs;
@@ -1806,6 +1818,7 @@ ccr_status ccr_segment_spectra(ccr_ctx *c, ccr_precision prec, int band_id, int6
     HIP_OK(c, launch_zero(F.p, fbytes, s));
     BandDev bd = band_dev(*B);
     if (!c->opt_farrow) bd.farrow = nullptr;
+    bd.far_stage = (int)c->opt_farrow_stage;
     HIP_OK(c, launch_timebase(bd, B->d_tmpl.as<double>() + (size_t)template_index * kTmplStride, 1, cf.as<double>(), s));
     HIP_OK(c, launch_resample(bd, cf.as<double>(), 1, fp64, y.p, s));
     HIP_OK(c, launch_spectra(bd, 1, fp64, y.p, F.p, s));

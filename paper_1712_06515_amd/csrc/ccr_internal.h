@@ -34,15 +34,21 @@ struct SegWeight {
 // of segment K's mid-time as c0 + K c1 in double-double: c0h, c0l, c1h, c1l.
 constexpr int kTmplStride = 6;
 
-// Chebyshev nodes per segment for the time base; the split path may use kChebSplit or
-// kChebSplitMin nodes (degree 6 or 5) when the host's bound on the Chebyshev tail allows;
-// detector limit.
+// Chebyshev nodes per segment for the time base; the split path may use kChebSplit,
+// kChebSplitMin or kChebSplitLow nodes (degree 6, 5 or 4) when the host's bound on the
+// Chebyshev tail allows; detector limit.
 constexpr int kCheb = 10;
 constexpr int kChebSplit = 7;
 constexpr int kChebSplitMin = 6;
+constexpr int kChebSplitLow = 5;
+constexpr int kChebRules = 4;
 // node rules: index of the table of an NN-node rule, and offset of its nodes in cheb_x
-constexpr int cheb_rule(int nn) { return nn == kCheb ? 0 : (nn == kChebSplit ? 1 : 2); }
-constexpr int cheb_x_off(int nn) { return nn == kCheb ? 0 : (nn == kChebSplit ? kCheb : kCheb + kChebSplit); }
+constexpr int cheb_rule(int nn) { return nn == kCheb ? 0 : (nn == kChebSplit ? 1 : (nn == kChebSplitMin ? 2 : 3)); }
+constexpr int cheb_x_off(int nn) {
+    return nn == kCheb ? 0
+                       : (nn == kChebSplit ? kCheb : (nn == kChebSplitMin ? kCheb + kChebSplit : kCheb + kChebSplit + kChebSplitMin));
+}
+constexpr int kChebNodesAll = kCheb + kChebSplit + kChebSplitMin + kChebSplitLow;
 #define CCR_MAX_DET_K 8
 
 // Everything a kernel needs about a band (device pointers + scalars).
@@ -62,8 +68,8 @@ struct BandDev {
     const EarthConst *earth;  // [Q]
     const double *win64;      // [2D+1] tap window (window == 0)
     const float *win32;
-    const double *cheb_x;     // nodes cos(pi (j + 1/2) / N) for N = kCheb, kChebSplit, kChebSplitMin
-    const double *mono;       // [3][kCheb][kCheb] node values -> monomial coefficients of the
+    const double *cheb_x;     // nodes cos(pi (j + 1/2) / N) for N = kCheb, kChebSplit, kChebSplitMin, kChebSplitLow
+    const double *mono;       // [kChebRules][kCheb][kCheb] node values -> monomial coefficients of the
                               // interpolant through the N Chebyshev nodes (rule cheb_rule(N))
     const double2 *tw64;      // [n_fft] exp(-2 pi i j / n_fft)
     const float2 *tw32;
@@ -90,12 +96,13 @@ struct BandDev {
     const int *seg_any;       // [n_seg_any] ascending segments K where some detector is active
     int n_seg_any;
     int newton_steps;         // Newton steps of the time-base node solve (2 or 3)
-    int cheb_split;           // time-base nodes of the split path (kChebSplitMin, kChebSplit or kCheb)
+    int cheb_split;           // time-base nodes of the split path (kChebSplitLow ... kChebSplit, or kCheb)
     // Farrow table of the split-precision resampler, [Q][kFarDeg + 1][far_len] complex64:
     // plane k at index j + D holds F_k(j) = sum_n A_kn x'_{j+n} (F_0 = x'), zero beyond
     // j + D >= n + 2D; null when the band has none
     const float2 *farrow;
     int64_t far_len;
+    int far_stage;  // 1: stage the table in LDS (else every sample reads it from global memory)
 };
 
 // One work item of a batched launch: a run of consecutive templates of one band.  A batched
@@ -130,7 +137,7 @@ constexpr int kResTemplates = 4;     // resampling: templates per workgroup
 // table planes of chunks of kFarChunk samples of one segment in LDS (kFarCap entries a plane)
 constexpr int kFarDeg = 9;
 constexpr int kFarWaves = 4;
-constexpr int kFarPerWave = 8;
+constexpr int kFarPerWave = 16;
 constexpr int kFarTemplates = kFarWaves * kFarPerWave;
 constexpr int kFarChunk = 192;
 constexpr int kFarCap = 224;

@@ -162,7 +162,7 @@ __device__ __forceinline__ void sample_time(const double *coef, double x, const 
 // (whole wavefronts); node values meet in LDS for the coefficient transform.
 template <int NN, bool SHORT>
 __device__ __forceinline__ void timebase_body(const BandDev &B, const double *tmpl, double *coef, int bx, int tb) {
-    static_assert(NN == kCheb || NN == kChebSplit || NN == kChebSplitMin, "node rule");
+    static_assert(NN == kCheb || NN == kChebSplit || NN == kChebSplitMin || NN == kChebSplitLow, "node rule");
     constexpr int E = tb_entries(NN);
     __shared__ double sh_eta[E * NN];
     __shared__ double2 sh_bin[E];
@@ -519,12 +519,18 @@ __global__ void __launch_bounds__(256) k_farrow_table(const float2 *__restrict__
     for (int k = 0; k < kFarDeg; ++k) td[(size_t)(k + 1) * far_len + jj] = make_float2((float)re[k], (float)im[k]);
 }
 
-// sum_k F_k dc^k by Horner; F_k at p[k * stride].
-template <typename P>
-__device__ __forceinline__ float2 farrow_eval(const P *p, int64_t stride, float dc) {
+// sum_k F_k dc^k by Horner from the kFarDeg + 1 coefficients of one entry, stored
+// consecutively in LDS (16-byte aligned: five 128-bit reads).
+__device__ __forceinline__ float2 farrow_eval_lds(const float2 *p, float dc) {
+    static_assert((kFarDeg + 1) % 2 == 0, "pairs of coefficients");
     float2 f[kFarDeg + 1];
+    const float4 *q = reinterpret_cast<const float4 *>(p);
 #pragma unroll
-    for (int k = 0; k <= kFarDeg; ++k) f[k] = p[k * stride];
+    for (int k = 0; k < (kFarDeg + 1) / 2; ++k) {
+        const float4 v = q[k];
+        f[2 * k] = make_float2(v.x, v.y);
+        f[2 * k + 1] = make_float2(v.z, v.w);
+    }
     float re = f[kFarDeg].x, im = f[kFarDeg].y;
 #pragma unroll
     for (int k = kFarDeg - 1; k >= 0; --k) {
@@ -534,17 +540,47 @@ __device__ __forceinline__ float2 farrow_eval(const P *p, int64_t stride, float 
     return make_float2(re, im);
 }
 
+// Per sample, as sample_time: j* - r - the offset's integer part (jr), the offset dc and the
+// heterodyne phase frac(psi_a + f_h eta) in cycles (v_fract_f64), the last two rounded to FP32.
+template <int NC>
+__device__ __forceinline__ void sample_time_far(const double *coef, double x, const Anchor &an, double inv_dt,
+                                                double f_het, int &jr, float &dc, float &psi) {
+    const double eta = eta_at<NC>(coef, x);
+    const double q = (eta - an.D_a) * inv_dt;
+    const double k = floor(q + 0.5);
+    jr = (int)k;
+    dc = (float)(q - k);
+    psi = (float)__builtin_amdgcn_fract(fma(f_het, eta, an.psi_a));
+}
+
+// The same from the table in global memory (the rare unstaged case), as a plain loop so that
+// the planes' addresses are not kept in registers across the sample loop.
+__device__ __forceinline__ float2 farrow_eval_global(const float2 *p, int64_t stride, float dc) {
+    float re = 0.f, im = 0.f;
+#pragma unroll 1
+    for (int k = kFarDeg; k >= 0; --k) {
+        const float2 f = p[k * stride];
+        re = fmaf(re, dc, f.x);
+        im = fmaf(im, dc, f.y);
+    }
+    return make_float2(re, im);
+}
+
 // One 256-thread workgroup per (active segment entry, templates [t0, t1)), t1 - t0 <=
 // kFarTemplates; wavefront v takes templates t0 + v kFarPerWave + i.  Per chunk of kFarChunk
 // samples the workgroup finds the range of j* over its templates (j* is nondecreasing in the
 // sample index, so the chunk's first and last samples bound it), stages that range of every
-// table plane in LDS with coalesced loads, and each lane then reads its sample's kFarDeg + 1
-// coefficients from LDS (consecutive lanes, consecutive entries).  A range wider than kFarCap
-// (not met for physical delays) reads the table in global memory instead.
+// table plane in LDS with coalesced loads (entry-major there: an entry's kFarDeg + 1
+// coefficients are 80 consecutive bytes, read by a lane with five 128-bit LDS reads; the
+// 20-dword stride between lanes keeps 16 lanes on distinct banks).  A range wider than
+// kFarCap (not met for physical delays) reads the table in global memory instead.  The gap
+// mask and the in-chunk test of each pass are wave-wide bit masks (ballots), applied as
+// execution masks.
 template <int NC>
 __device__ __forceinline__ void resample_far_body(const BandDev &B, const double *coef, float2 *y, int w, int t0,
                                                   int t1) {
-    __shared__ float2 sf[(kFarDeg + 1) * kFarCap];
+    constexpr int kE = kFarDeg + 1;  // coefficients of an entry
+    __shared__ __align__(16) float2 sf[kE * kFarCap];
     __shared__ int s_lo[kFarWaves], s_hi[kFarWaves];
     const int entry = B.work[w];
     const int det = entry / B.n_seg;
@@ -571,10 +607,9 @@ __device__ __forceinline__ void resample_far_body(const BandDev &B, const double
 #pragma unroll
                 for (int k = 0; k < NC; ++k) cl[k] = cf[k];
                 const int s = lane < 32 ? c0 : c1 - 1;
-                int64_t js;
-                double dc, psi;
-                sample_time<NC>(cl, (double)(2 * s - B.n_k) * inv_nk, an, B.inv_dt, B.f_het, r0 + s, js, dc, psi);
-                jr = (int)(js - r0);
+                float dc, psi;
+                sample_time_far<NC>(cl, (double)(2 * s - B.n_k) * inv_nk, an, B.inv_dt, B.f_het, jr, dc, psi);
+                jr += s;
             }
             int lo = INT_MAX, hi = INT_MIN;
 #pragma unroll
@@ -597,23 +632,36 @@ __device__ __forceinline__ void resample_far_body(const BandDev &B, const double
             jhi = max(jhi, s_hi[q]);
         }
         const int span = jhi - jlo + 1;
-        const bool staged = span <= kFarCap;
+        const bool staged = B.far_stage && span <= kFarCap;
         if (staged) {
             const int64_t jb = r0 + jlo + B.D;  // table index of j* = r0 + jlo
             for (int i = threadIdx.x; i < span; i += 256) {
                 const int64_t jj = jb + i;
                 const bool ok = jj >= 0 && jj < B.far_len;
+                float2 f[kE];
 #pragma unroll
-                for (int k = 0; k <= kFarDeg; ++k)
-                    sf[k * kFarCap + i] = ok ? tab[(size_t)k * B.far_len + jj] : make_float2(0.f, 0.f);
+                for (int k = 0; k < kE; ++k) f[k] = ok ? tab[(size_t)k * B.far_len + jj] : make_float2(0.f, 0.f);
+                float4 *d = reinterpret_cast<float4 *>(sf + i * kE);
+#pragma unroll
+                for (int k = 0; k < kE / 2; ++k) d[k] = make_float4(f[2 * k].x, f[2 * k].y, f[2 * k + 1].x, f[2 * k + 1].y);
             }
         }
-        // gap mask of the chunk's samples, shared by the templates: bit p = sample c0 + 64 p + lane
-        static_assert(kFarChunk <= 64 * 32, "mask bits");
-        uint32_t mbits = 0;
-        for (int p = 0; c0 + 64 * p < c1; ++p) {
+        // per pass p (sample c0 + 64 p + lane), shared by the templates: the samples inside the
+        // chunk (ballot in_b[p]), those of them outside gaps (m_b[p]), the time-base abscissa
+        // x and the sample's offset from the staged range
+        constexpr int kPasses = kFarChunk / 64;
+        static_assert(kFarChunk % 64 == 0, "whole passes");
+        uint64_t in_b[kPasses], m_b[kPasses];
+        double xs[kPasses];
+        int sj[kPasses];
+#pragma unroll
+        for (int p = 0; p < kPasses; ++p) {
             const int s = c0 + 64 * p + lane;
-            if (s < c1 && mk_[s]) mbits |= 1u << p;
+            xs[p] = (double)(2 * s - B.n_k) * inv_nk;
+            sj[p] = s - jlo;
+            const bool in = s < c1;
+            in_b[p] = __builtin_amdgcn_ballot_w64(in);
+            m_b[p] = __builtin_amdgcn_ballot_w64(in && mk_[s]);
         }
         __syncthreads();
         for (int i = 0; i < kFarPerWave; ++i) {
@@ -624,28 +672,28 @@ __device__ __forceinline__ void resample_far_body(const BandDev &B, const double
             double cl[NC];
 #pragma unroll
             for (int k = 0; k < NC; ++k) cl[k] = cf[k];
-            for (int s0 = c0, p = 0; s0 < c1; s0 += 64, ++p) {
-                const int s = s0 + lane;
-                if (s >= c1) continue;
+#pragma unroll
+            for (int p = 0; p < kPasses; ++p) {
+                if (c0 + 64 * p >= c1) break;
+                if (!__builtin_amdgcn_inverse_ballot_w64(in_b[p])) continue;
                 float2 v = make_float2(0.f, 0.f);
-                if ((mbits >> p) & 1u) {
-                    int64_t js;
-                    double dcd, psi;
-                    sample_time<NC>(cl, (double)(2 * s - B.n_k) * inv_nk, an, B.inv_dt, B.f_het, r0 + s, js, dcd, psi);
-                    const float dc = (float)dcd;
-                    const int jr = (int)(js - r0) - jlo;
+                if (__builtin_amdgcn_inverse_ballot_w64(m_b[p])) {
+                    int jr;
+                    float dc, psi;
+                    sample_time_far<NC>(cl, xs[p], an, B.inv_dt, B.f_het, jr, dc, psi);
+                    jr += sj[p];  // j* - r0 - jlo
                     float2 a;
-                    if (staged && jr >= 0 && jr < span) {
-                        a = farrow_eval(sf + jr, kFarCap, dc);
+                    if (staged && (unsigned)jr < (unsigned)span) {
+                        a = farrow_eval_lds(sf + __umul24(jr, kE), dc);  // 0 <= jr < kFarCap
                     } else {
-                        const int64_t jj = js + B.D;
-                        a = (jj >= 0 && jj < B.far_len) ? farrow_eval(tab + jj, B.far_len, dc) : make_float2(0.f, 0.f);
+                        const int64_t jj = r0 + jlo + jr + B.D;
+                        a = (jj >= 0 && jj < B.far_len) ? farrow_eval_global(tab + jj, B.far_len, dc)
+                                                         : make_float2(0.f, 0.f);
                     }
-                    float c, sn;
-                    sincos_rev<float>(psi, sn, c);
+                    const float c = __builtin_amdgcn_cosf(psi), sn = __builtin_amdgcn_sinf(psi);
                     v = make_float2(c * a.x - sn * a.y, sn * a.x + c * a.y);
                 }
-                yo[s] = v;
+                yo[c0 + 64 * p + lane] = v;
             }
         }
         __syncthreads();  // the next chunk restages sf
@@ -1834,7 +1882,9 @@ hipError_t launch_timebase_m(const BandDev *bands, const WorkItem *items, int n_
     if (blocks == 0) return hipSuccess;
     if (n_cheb == kCheb) launch_timebase_m_t<kCheb>(bands, items, n_items, blocks, short_series, coef, stream);
     else if (n_cheb == kChebSplit) launch_timebase_m_t<kChebSplit>(bands, items, n_items, blocks, short_series, coef, stream);
-    else launch_timebase_m_t<kChebSplitMin>(bands, items, n_items, blocks, short_series, coef, stream);
+    else if (n_cheb == kChebSplitMin)
+        launch_timebase_m_t<kChebSplitMin>(bands, items, n_items, blocks, short_series, coef, stream);
+    else launch_timebase_m_t<kChebSplitLow>(bands, items, n_items, blocks, short_series, coef, stream);
     return hipGetLastError();
 }
 
@@ -1853,7 +1903,10 @@ hipError_t launch_resample_m(const BandDev *bands, const WorkItem *items, int n_
                              int window, int n_cheb, bool farrow, const double *coef, void *y, hipStream_t stream) {
     if (blocks == 0) return hipSuccess;
     if (farrow && !fp64) {
-        if (n_cheb == kChebSplitMin)
+        if (n_cheb == kChebSplitLow)
+            hipLaunchKernelGGL(k_resample_far_m<kChebSplitLow>, dim3(blocks), dim3(256), 0, stream, bands, items,
+                               n_items, coef, (float2 *)y);
+        else if (n_cheb == kChebSplitMin)
             hipLaunchKernelGGL(k_resample_far_m<kChebSplitMin>, dim3(blocks), dim3(256), 0, stream, bands, items,
                                n_items, coef, (float2 *)y);
         else if (n_cheb == kChebSplit)
@@ -1872,6 +1925,10 @@ hipError_t launch_resample_m(const BandDev *bands, const WorkItem *items, int n_
         if (D == 8)
             launch_resample_m_t<float, 8, kChebSplitMin>(bands, items, n_items, blocks, window, coef, y, stream);
         else launch_resample_m_t<float, 0, kChebSplitMin>(bands, items, n_items, blocks, window, coef, y, stream);
+    } else if (n_cheb == kChebSplitLow) {
+        if (D == 8)
+            launch_resample_m_t<float, 8, kChebSplitLow>(bands, items, n_items, blocks, window, coef, y, stream);
+        else launch_resample_m_t<float, 0, kChebSplitLow>(bands, items, n_items, blocks, window, coef, y, stream);
     } else {
         if (D == 8) launch_resample_m_t<float, 8, kCheb>(bands, items, n_items, blocks, window, coef, y, stream);
         else launch_resample_m_t<float, 0, kCheb>(bands, items, n_items, blocks, window, coef, y, stream);

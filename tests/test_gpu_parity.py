@@ -109,6 +109,23 @@ def test_resampled_series_parity(ccr, farrow, window):
                 assert np.all((y64 == 0) >= (m == 0))
 
 
+def test_farrow_unstaged_path_identical(ccr):
+    # the Farrow kernel's global-memory path (taken by a chunk whose j* range does not fit in
+    # LDS) evaluates the same polynomial from the same table: bitwise the staged result
+    cfg = small_config(n_seg=10, gap_fraction=0.2, max_lag=1)
+    ds = synth.make_dataset(cfg)
+    with ccr.Context(ds.sky, device=0) as ctx:
+        bid = ctx.load(ds)
+        y1 = [ctx.resample_series(bid, t, 1, prec=ccr.PREC_SPLIT) for t in (0, 4)]
+        r1 = ctx.compute_rho(bid, prec=ccr.PREC_SPLIT, out_fp64=False)
+        ctx.set_option("farrow_stage", 0)
+        y0 = [ctx.resample_series(bid, t, 1, prec=ccr.PREC_SPLIT) for t in (0, 4)]
+        r0 = ctx.compute_rho(bid, prec=ccr.PREC_SPLIT, out_fp64=False)
+    for a, b in zip(y1, y0):
+        assert np.array_equal(a, b)
+    assert np.array_equal(r1, r0)
+
+
 def test_segment_spectra_parity(ccr):
     cfg = small_config(n_seg=10, max_lag=2, q=3, gap_fraction=0.1)
     ds = synth.make_dataset(cfg)
