@@ -412,7 +412,7 @@ double farrow_fit(int D, int window, const std::vector<double> &w64, std::vector
 
 // Largest fit error accepted for the Farrow form (sum over the taps, relative to the input
 // amplitude): below the split path's FP32 rounding of the tap sum.
-constexpr double kFarTol = 2e-7;
+constexpr double kFarTol = 4e-7;
 
 ccr_status prepare(ccr_ctx *c, Band &B) {
     if (B.prepared) return CCR_OK;

@@ -135,7 +135,7 @@ constexpr int kResTemplates = 4;     // resampling: templates per workgroup
 // Farrow-form resampling (split precision): tap weights as polynomials of degree kFarDeg in the
 // offset; a 256-thread workgroup (kFarWaves wavefronts, kFarPerWave templates each) stages the
 // table planes of chunks of kFarChunk samples of one segment in LDS (kFarCap entries a plane)
-constexpr int kFarDeg = 9;
+constexpr int kFarDeg = 8;
 constexpr int kFarWaves = 4;
 constexpr int kFarPerWave = 16;
 constexpr int kFarTemplates = kFarWaves * kFarPerWave;

@@ -519,10 +519,16 @@ __global__ void __launch_bounds__(256) k_farrow_table(const float2 *__restrict__
     for (int k = 0; k < kFarDeg; ++k) td[(size_t)(k + 1) * far_len + jj] = make_float2((float)re[k], (float)im[k]);
 }
 
+// A wave-uniform double computed by the vector unit, moved to scalar registers.
+__device__ __forceinline__ double uniform_f64(double v) {
+    const uint64_t b = __double_as_longlong(v);
+    const unsigned lo = __builtin_amdgcn_readfirstlane((unsigned)b), hi = __builtin_amdgcn_readfirstlane((unsigned)(b >> 32));
+    return __longlong_as_double((long long)(((uint64_t)hi << 32) | lo));
+}
+
 // sum_k F_k dc^k by Horner from the kFarDeg + 1 coefficients of one entry, stored
 // consecutively in LDS (16-byte aligned: five 128-bit reads).
 __device__ __forceinline__ float2 farrow_eval_lds(const float2 *p, float dc) {
-    static_assert((kFarDeg + 1) % 2 == 0, "pairs of coefficients");
     float2 f[kFarDeg + 1];
     const float4 *q = reinterpret_cast<const float4 *>(p);
 #pragma unroll
@@ -531,6 +537,7 @@ __device__ __forceinline__ float2 farrow_eval_lds(const float2 *p, float dc) {
         f[2 * k] = make_float2(v.x, v.y);
         f[2 * k + 1] = make_float2(v.z, v.w);
     }
+    if constexpr ((kFarDeg + 1) % 2 == 1) f[kFarDeg] = p[kFarDeg];
     float re = f[kFarDeg].x, im = f[kFarDeg].y;
 #pragma unroll
     for (int k = kFarDeg - 1; k >= 0; --k) {
@@ -541,16 +548,18 @@ __device__ __forceinline__ float2 farrow_eval_lds(const float2 *p, float dc) {
 }
 
 // Per sample, as sample_time: j* - r - the offset's integer part (jr), the offset dc and the
-// heterodyne phase frac(psi_a + f_h eta) in cycles (v_fract_f64), the last two rounded to FP32.
+// heterodyne phase in cycles (v_fract_f64), the last two rounded to FP32.  `coef` holds the
+// time base with D_a taken out of its constant term (its polynomial is the delay
+// Delta = eta - D_a), and psi_b = frac(psi_a + f_h D_a), so psi = frac(psi_b + f_h Delta).
 template <int NC>
-__device__ __forceinline__ void sample_time_far(const double *coef, double x, const Anchor &an, double inv_dt,
-                                                double f_het, int &jr, float &dc, float &psi) {
-    const double eta = eta_at<NC>(coef, x);
-    const double q = (eta - an.D_a) * inv_dt;
+__device__ __forceinline__ void sample_time_far(const double *coef, double x, double inv_dt, double f_het,
+                                                double psi_b, int &jr, float &dc, float &psi) {
+    const double delta = eta_at<NC>(coef, x);
+    const double q = delta * inv_dt;
     const double k = floor(q + 0.5);
     jr = (int)k;
     dc = (float)(q - k);
-    psi = (float)__builtin_amdgcn_fract(fma(f_het, eta, an.psi_a));
+    psi = (float)__builtin_amdgcn_fract(fma(f_het, delta, psi_b));
 }
 
 // The same from the table in global memory (the rare unstaged case), as a plain loop so that
@@ -579,8 +588,9 @@ __device__ __forceinline__ float2 farrow_eval_global(const float2 *p, int64_t st
 template <int NC>
 __device__ __forceinline__ void resample_far_body(const BandDev &B, const double *coef, float2 *y, int w, int t0,
                                                   int t1) {
-    constexpr int kE = kFarDeg + 1;  // coefficients of an entry
-    __shared__ __align__(16) float2 sf[kE * kFarCap];
+    constexpr int kE = kFarDeg + 1;          // coefficients of an entry
+    constexpr int kES = (kE + 1) / 2 * 2;   // LDS stride of an entry (16-byte aligned)
+    __shared__ __align__(16) float2 sf[kES * kFarCap];
     __shared__ int s_lo[kFarWaves], s_hi[kFarWaves];
     const int entry = B.work[w];
     const int det = entry / B.n_seg;
@@ -589,6 +599,7 @@ __device__ __forceinline__ void resample_far_body(const BandDev &B, const double
     const uint8_t *mk_ = B.mask + (size_t)det * nr + (size_t)K * B.n_k;
     const float2 *tab = B.farrow + (size_t)det * (kFarDeg + 1) * B.far_len;
     const Anchor an = B.anchors[entry];
+    const double psi_b = __builtin_amdgcn_fract(fma(B.f_het, an.D_a, an.psi_a));
     const double inv_nk = 1.0 / (double)B.n_k;
     const int64_t r0 = (int64_t)K * B.n_k;
     // wave-uniform (readfirstlane), so that a template's time-base coefficients are scalar
@@ -606,9 +617,10 @@ __device__ __forceinline__ void resample_far_body(const BandDev &B, const double
                 double cl[NC];
 #pragma unroll
                 for (int k = 0; k < NC; ++k) cl[k] = cf[k];
+                cl[0] -= an.D_a;
                 const int s = lane < 32 ? c0 : c1 - 1;
                 float dc, psi;
-                sample_time_far<NC>(cl, (double)(2 * s - B.n_k) * inv_nk, an, B.inv_dt, B.f_het, jr, dc, psi);
+                sample_time_far<NC>(cl, (double)(2 * s - B.n_k) * inv_nk, B.inv_dt, B.f_het, psi_b, jr, dc, psi);
                 jr += s;
             }
             int lo = INT_MAX, hi = INT_MIN;
@@ -641,9 +653,10 @@ __device__ __forceinline__ void resample_far_body(const BandDev &B, const double
                 float2 f[kE];
 #pragma unroll
                 for (int k = 0; k < kE; ++k) f[k] = ok ? tab[(size_t)k * B.far_len + jj] : make_float2(0.f, 0.f);
-                float4 *d = reinterpret_cast<float4 *>(sf + i * kE);
+                float4 *d = reinterpret_cast<float4 *>(sf + i * kES);
 #pragma unroll
                 for (int k = 0; k < kE / 2; ++k) d[k] = make_float4(f[2 * k].x, f[2 * k].y, f[2 * k + 1].x, f[2 * k + 1].y);
+                if constexpr (kE % 2 == 1) sf[i * kES + kE - 1] = f[kE - 1];
             }
         }
         // per pass p (sample c0 + 64 p + lane), shared by the templates: the samples inside the
@@ -672,28 +685,29 @@ __device__ __forceinline__ void resample_far_body(const BandDev &B, const double
             double cl[NC];
 #pragma unroll
             for (int k = 0; k < NC; ++k) cl[k] = cf[k];
+            cl[0] = uniform_f64(cl[0] - an.D_a);  // once per template, kept in scalar registers
 #pragma unroll
             for (int p = 0; p < kPasses; ++p) {
                 if (c0 + 64 * p >= c1) break;
-                if (!__builtin_amdgcn_inverse_ballot_w64(in_b[p])) continue;
-                float2 v = make_float2(0.f, 0.f);
+                const unsigned so = (unsigned)(c0 + 64 * p + lane);  // sample index (32-bit offset from yo)
+                // samples in gaps: zero (their own execution mask)
+                if (__builtin_amdgcn_inverse_ballot_w64(in_b[p] & ~m_b[p])) yo[so] = make_float2(0.f, 0.f);
                 if (__builtin_amdgcn_inverse_ballot_w64(m_b[p])) {
                     int jr;
                     float dc, psi;
-                    sample_time_far<NC>(cl, xs[p], an, B.inv_dt, B.f_het, jr, dc, psi);
+                    sample_time_far<NC>(cl, xs[p], B.inv_dt, B.f_het, psi_b, jr, dc, psi);
                     jr += sj[p];  // j* - r0 - jlo
                     float2 a;
                     if (staged && (unsigned)jr < (unsigned)span) {
-                        a = farrow_eval_lds(sf + __umul24(jr, kE), dc);  // 0 <= jr < kFarCap
+                        a = farrow_eval_lds(sf + __umul24(jr, kES), dc);  // 0 <= jr < kFarCap
                     } else {
                         const int64_t jj = r0 + jlo + jr + B.D;
                         a = (jj >= 0 && jj < B.far_len) ? farrow_eval_global(tab + jj, B.far_len, dc)
                                                          : make_float2(0.f, 0.f);
                     }
                     const float c = __builtin_amdgcn_cosf(psi), sn = __builtin_amdgcn_sinf(psi);
-                    v = make_float2(c * a.x - sn * a.y, sn * a.x + c * a.y);
+                    yo[so] = make_float2(c * a.x - sn * a.y, sn * a.x + c * a.y);
                 }
-                yo[c0 + 64 * p + lane] = v;
             }
         }
         __syncthreads();  // the next chunk restages sf

@@ -95,7 +95,7 @@ def test_resampled_series_parity(ccr, farrow, window):
     with ccr.Context(ds.sky, device=0) as ctx:
         ctx.set_option("farrow", farrow)
         bid = ctx.load(ds)
-        assert ctx.band_info(bid)["farrow_degree"] == 9
+        assert ctx.band_info(bid)["farrow_degree"] == ctx.get_option("farrow_degree")
         for t in (0, 3, 5):
             for X in range(2):
                 y_ref, js, off, m = o.resample(X, ds.templates[t])
