@@ -124,7 +124,8 @@ typedef struct {
     int64_t n_active;     /* (detector, segment) entries that take part in a pair and are computed */
     double dt, f_het, df_load, t_coh, dlambda_f, t_fft, nu_r;
     double norm;          /* N of App. A (0 when no pair carries weight) */
-    /* Split-precision resampling in Farrow form (Sec. III.B interpolation, evaluated as one
+    /* Split-precision resampling in Farrow form (Sec. III.A interpolation, eq.
+     * shannon-interp-formula, evaluated as one
      * polynomial in the offset per sample): polynomial degree of the tap weights, 0 when the
      * band has no Farrow table (the fit's error bound is too large, or no device memory for
      * it: the direct 2D + 1-tap form runs instead); farrow_err = max over offsets of
