@@ -41,9 +41,16 @@ WORKLOADS = {
 
 
 def kernel_source_hash():
+    """Hash of the kernel sources with comments and blank lines removed (a comment edit does
+    not change the kernels the counters were taken on)."""
     h = hashlib.sha256()
     for f in ("ccr_kernels.hip", "ccr_internal.h"):
-        h.update(open(os.path.join(ROOT, "paper_1712_06515_amd", "csrc", f), "rb").read())
+        text = open(os.path.join(ROOT, "paper_1712_06515_amd", "csrc", f)).read()
+        text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+        for line in text.splitlines():
+            line = line.split("//", 1)[0].rstrip()
+            if line:
+                h.update(line.encode() + b"\n")
     return h.hexdigest()[:16]
 
 

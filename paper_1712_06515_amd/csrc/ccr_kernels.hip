@@ -579,9 +579,9 @@ __device__ __forceinline__ float2 farrow_eval_global(const float2 *p, int64_t st
 // kFarTemplates; wavefront v takes templates t0 + v kFarPerWave + i.  Per chunk of kFarChunk
 // samples the workgroup finds the range of j* over its templates (j* is nondecreasing in the
 // sample index, so the chunk's first and last samples bound it), stages that range of every
-// table plane in LDS with coalesced loads (entry-major there: an entry's kFarDeg + 1
-// coefficients are 80 consecutive bytes, read by a lane with five 128-bit LDS reads; the
-// 20-dword stride between lanes keeps 16 lanes on distinct banks).  A range wider than
+// table plane in LDS with coalesced loads (entry-major there: an entry's kFarDeg + 1 = 9
+// coefficients occupy 80 bytes, read by a lane with four 128-bit and one 64-bit LDS reads;
+// the 20-dword stride between lanes keeps 16 lanes on distinct banks).  A range wider than
 // kFarCap (not met for physical delays) reads the table in global memory instead.  The gap
 // mask and the in-chunk test of each pass are wave-wide bit masks (ballots), applied as
 // execution masks.
