@@ -1212,7 +1212,8 @@ __device__ __forceinline__ void spectra_pairs_body(const BandDev &B, const float
 // The fused kernel keeps the activity bits of a step (S segments x Q detectors) in 64 bits.
 __host__ __device__ inline bool Q_ok(const BandDev &B) { return B.Q >= 1 && B.Q * 4 <= 64; }
 
-template <typename T>
+// PER: samples per thread, n_s / blockDim.x (at most 4 below n_s = 2048, else 8).
+template <typename T, int PER>
 __device__ __forceinline__ void spectra_body(const BandDev &B, const c2<T> *y, c2<T> *F, int w, int tb) {
     extern __shared__ __align__(16) unsigned char smem[];
     c2<T> *buf0 = reinterpret_cast<c2<T> *>(smem);
@@ -1226,17 +1227,38 @@ __device__ __forceinline__ void spectra_body(const BandDev &B, const c2<T> *y, c
     const int rb_mod = mod_fft(B, (int64_t)K * B.n_k);
     const T scale = (T)B.segw[entry].scale;
     c2<T> *Fo = F + (((size_t)tb * B.Q + det) * B.n_seg + K) * B.n_f;
+    // The FFT's stage twiddles are all n_s-th roots of unity: a copy of those n_s entries of
+    // the N_FFT-entry table in LDS (when it fits beside the two work buffers) replaces the
+    // strided gathers from global memory.
+    const bool ltw = 3 * (size_t)B.n_s * sizeof(c2<T>) <= 65536;
+    c2<T> *twl = buf1 + B.n_s;
+    if (ltw) {
+        const int st = B.n_fft / B.n_s;
+        for (int j = threadIdx.x; j < B.n_s; j += blockDim.x) twl[j] = tw[j * st];
+    }
+    // input twiddles W^(p s) (W = exp(-2 pi i / N_FFT)) of this thread's samples
+    // s = threadIdx.x + r blockDim.x, advanced from class to class by W^s and refreshed from the
+    // table every 8 classes (bounding the product's rounding growth)
+    constexpr int kPer = PER;
+    c2<T> ts[kPer], ws[kPer];
+#pragma unroll
+    for (int r = 0; r < kPer; ++r) {
+        const int s = threadIdx.x + r * blockDim.x;
+        ws[r] = s < B.n_s ? tw[s] : mk<T>((T)1, (T)0);
+        ts[r] = mk<T>((T)1, (T)0);
+    }
     for (int p = 0; p < B.P; ++p) {
-        for (int s = threadIdx.x; s < B.n_s; s += blockDim.x) {
-            c2<T> v = mk<T>((T)0, (T)0);
-            if (s < B.n_k) {
-                v = ys[s];
-                if (p) v = cmul<T>(v, tw[p * s]);
+#pragma unroll
+        for (int r = 0; r < kPer; ++r) {
+            const int s = threadIdx.x + r * blockDim.x;
+            if (s < B.n_s) {
+                if (p > 0) ts[r] = (p & 7) == 0 ? tw[mod_fft(B, (int64_t)p * s)] : cmul<T>(ts[r], ws[r]);
+                buf0[s] = s < B.n_k ? (p ? cmul<T>(ys[s], ts[r]) : ys[s]) : mk<T>((T)0, (T)0);
             }
-            buf0[s] = v;
         }
         __syncthreads();
-        const c2<T> *res = stockham<T>(buf0, buf1, B.n_s, tw, B.n_fft, threadIdx.x, blockDim.x);
+        const c2<T> *res = ltw ? stockham<T>(buf0, buf1, B.n_s, twl, B.n_s, threadIdx.x, blockDim.x)
+                               : stockham<T>(buf0, buf1, B.n_s, tw, B.n_fft, threadIdx.x, blockDim.x);
         // the output bins of class p only
         for (int c = B.class_start[p] + (int)threadIdx.x; c < B.class_start[p + 1]; c += blockDim.x) {
             const int i = B.col_bin[c];
@@ -1247,9 +1269,9 @@ __device__ __forceinline__ void spectra_body(const BandDev &B, const c2<T> *y, c
     }
 }
 
-template <typename T>
+template <typename T, int PER>
 __global__ void __launch_bounds__(256) k_spectra(BandDev B, const c2<T> *y, c2<T> *F) {
-    spectra_body<T>(B, y, F, blockIdx.x, blockIdx.y);
+    spectra_body<T, PER>(B, y, F, blockIdx.x, blockIdx.y);
 }
 
 // ------------------------------------------------------------------ pair sum
@@ -1712,14 +1734,14 @@ k_spectra16_m(const BandDev *__restrict__ bands, const WorkItem *__restrict__ it
     spectra16_body<T>(B, y + it.y_off, F + it.F_off, l % gx, l / gx);
 }
 
-template <typename T>
+template <typename T, int PER>
 __global__ void __launch_bounds__(256)
 k_spectra_m(const BandDev *__restrict__ bands, const WorkItem *__restrict__ items, int n_items,
             const c2<T> *__restrict__ y, c2<T> *__restrict__ F) {
     const WorkItem &it = items[find_item(items, n_items, kStSpectra, blockIdx.x)];
     const BandDev B = global_view(bands[it.band], bands);
     const int l = blockIdx.x - it.first[kStSpectra], gx = it.gx[kStSpectra];
-    spectra_body<T>(B, y + it.y_off, F + it.F_off, l % gx, l / gx);
+    spectra_body<T, PER>(B, y + it.y_off, F + it.F_off, l % gx, l / gx);
 }
 
 template <typename T>
@@ -1797,11 +1819,17 @@ hipError_t launch_spectra(const BandDev &B, int n_tmpl, bool fp64, const void *y
         return hipGetLastError();
     }
     dim3 grid(B.n_work, n_tmpl), block(spectra_threads(B.n_s));
-    const size_t lds = 2 * (size_t)B.n_s * (fp64 ? sizeof(double2) : sizeof(float2));
-    if (fp64)
-        hipLaunchKernelGGL(k_spectra<double>, grid, block, lds, stream, B, (const double2 *)y, (double2 *)F);
+    const size_t cs = fp64 ? sizeof(double2) : sizeof(float2);
+    const size_t lds = (3 * (size_t)B.n_s * cs <= 65536 ? 3 : 2) * (size_t)B.n_s * cs;  // + stage twiddles
+    const bool p8 = B.n_s > 4 * spectra_threads(B.n_s);
+    if (fp64 && p8)
+        hipLaunchKernelGGL((k_spectra<double, 8>), grid, block, lds, stream, B, (const double2 *)y, (double2 *)F);
+    else if (fp64)
+        hipLaunchKernelGGL((k_spectra<double, 4>), grid, block, lds, stream, B, (const double2 *)y, (double2 *)F);
+    else if (p8)
+        hipLaunchKernelGGL((k_spectra<float, 8>), grid, block, lds, stream, B, (const float2 *)y, (float2 *)F);
     else
-        hipLaunchKernelGGL(k_spectra<float>, grid, block, lds, stream, B, (const float2 *)y, (float2 *)F);
+        hipLaunchKernelGGL((k_spectra<float, 4>), grid, block, lds, stream, B, (const float2 *)y, (float2 *)F);
     return hipGetLastError();
 }
 
@@ -1977,12 +2005,20 @@ hipError_t launch_spectra_m(const BandDev *bands, const WorkItem *items, int n_i
                            n_items, (const float2 *)y, (float2 *)F);
         return hipGetLastError();
     }
-    const size_t lds = 2 * (size_t)n_s * (fp64 ? sizeof(double2) : sizeof(float2));
-    if (fp64)
-        hipLaunchKernelGGL(k_spectra_m<double>, dim3(blocks), dim3(threads), lds, stream, bands, items, n_items,
+    const size_t cs = fp64 ? sizeof(double2) : sizeof(float2);
+    const size_t lds = (3 * (size_t)n_s * cs <= 65536 ? 3 : 2) * (size_t)n_s * cs;  // + stage twiddles
+    const bool p8 = n_s > 4 * threads;
+    if (fp64 && p8)
+        hipLaunchKernelGGL((k_spectra_m<double, 8>), dim3(blocks), dim3(threads), lds, stream, bands, items, n_items,
                            (const double2 *)y, (double2 *)F);
+    else if (fp64)
+        hipLaunchKernelGGL((k_spectra_m<double, 4>), dim3(blocks), dim3(threads), lds, stream, bands, items, n_items,
+                           (const double2 *)y, (double2 *)F);
+    else if (p8)
+        hipLaunchKernelGGL((k_spectra_m<float, 8>), dim3(blocks), dim3(threads), lds, stream, bands, items, n_items,
+                           (const float2 *)y, (float2 *)F);
     else
-        hipLaunchKernelGGL(k_spectra_m<float>, dim3(blocks), dim3(threads), lds, stream, bands, items, n_items,
+        hipLaunchKernelGGL((k_spectra_m<float, 4>), dim3(blocks), dim3(threads), lds, stream, bands, items, n_items,
                            (const float2 *)y, (float2 *)F);
     return hipGetLastError();
 }
