@@ -166,8 +166,9 @@ def main():
                     help="time only the first N templates of the workload (0: all; the rate is per rho evaluation)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py measures one GPU: this build has no multi-GPU path "
-              "(templates shard across GPUs with no exchange; see DESIGN.md)", file=sys.stderr)
+        print("bench.py measures one GPU: the library has no multi-GPU path (orbital templates are "
+              "independent, so they would shard across GPUs with no exchange but a final gather)",
+              file=sys.stderr)
         sys.exit(2)
 
     import numpy as np
