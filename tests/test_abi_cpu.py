@@ -231,3 +231,14 @@ def test_farrow_fit_error(lib, D, window):
     ref = np.abs(c0[None, :] + xt[:, None] * (np.vander(xt, deg, increasing=True) @ A) - taps(xt)).sum(1).max()
     assert err < 4e-7
     assert 0.5 * ref < err < 2.0 * ref
+
+
+def test_farrow_fit_rejected_for_long_windows(lib):
+    """Windows of 2D + 1 = 49 taps: the degree-8 fit's bound exceeds the 4e-7 the library
+    accepts, so such a band keeps the direct tap sum on the split path."""
+    ds = synth.make_dataset(small_config(n_seg=4, dirichlet_D=24), signal=False)
+    ctx = _host_ctx(ds)
+    info = ctx.band_info(ctx.load(ds))
+    if ctx.get_option("farrow_degree") == 8:
+        assert info["farrow_err"] > 4e-7
+    assert info["farrow_degree"] == 0

@@ -109,6 +109,24 @@ def test_resampled_series_parity(ccr, farrow, window):
                 assert np.all((y64 == 0) >= (m == 0))
 
 
+def test_split_without_farrow_table(ccr):
+    # D = 24: the degree-8 fit's bound (5.2e-7) exceeds the library's 4e-7, so the band gets no
+    # Farrow table and the split path resamples with the direct tap sum
+    cfg = small_config(n_seg=8, dirichlet_D=24, max_lag=1)
+    ds = synth.make_dataset(cfg)
+    ref = oracle.Oracle(ds).rho(ds.templates)
+    with ccr.Context(ds.sky, device=0) as ctx:
+        bid = ctx.load(ds)
+        info = ctx.band_info(bid)
+        r64 = ctx.compute_rho(bid, prec=ccr.PREC_FP64)
+        r32 = ctx.compute_rho(bid, prec=ccr.PREC_SPLIT, out_fp64=False)
+    e64, e32 = rho_err(r64, ref), rho_err(r32, ref)
+    print(f"D=24 (no Farrow table, bound {info['farrow_err']:.2e}): fp64 {e64:.2e} split {e32:.2e}")
+    assert info["farrow_degree"] == 0 and info["farrow_err"] > 4e-7
+    assert e64 < TOL64
+    assert e32 < TOL32
+
+
 def test_farrow_unstaged_path_identical(ccr):
     # the Farrow kernel's global-memory path (taken by a chunk whose j* range does not fit in
     # LDS) evaluates the same polynomial from the same table: bitwise the staged result
