@@ -141,7 +141,8 @@ def roofline(name, avg_ms, tb, info, workload):
         flops += 8.0 * info["n_pairs"] * info["n_f"] * tb
         per_unit += " + 8 flop per (template, pair, bin)"
     ach = flops / (avg_ms * 1e-3) / 1e12
-    kern = {"spectra": "k_spectra16_m", "spectra_pairs": "k_spectra_pairs_m", "fused": "k_fused"}[name]
+    kern = {"spectra": "k_spectra16_m" if ns == 256 else "k_spectra_m", "spectra_pairs": "k_spectra_pairs_m",
+            "fused": "k_fused"}[name]
     return {"kernel": kern, "bound": "alu", "achieved": ach, "peak": FP32_PEAK_TFLOPS, "unit": "TFLOP/s",
             "frac": ach / FP32_PEAK_TFLOPS, "traffic": read_traffic(name, workload),
             "avg_launch_ms": avg_ms, "algorithmic_flops_per_launch": flops, "per_unit": per_unit}

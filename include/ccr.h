@@ -20,7 +20,7 @@
  *                     (eq. resampled-time-series-q-eq);
  *   3. spectra        zero-padded FFT of each T_short segment, decimated bins
  *                     kbar = k_lo + floor(nu_R i), phase referenced to the
- *                     series origin (Phi_in, Sec. III.B.3-4);
+ *                     series origin (Phi_in, Sec. III.B.4-5);
  *   4. pair sum       rho_i = sqrt(2) Re sum_{pairs} W_KL conj(F_K) F_L / N with
  *                     W_KL = hat a_K hat a_L + hat b_K hat b_L (eq.
  *                     geometric-filter) over the pair set of Sec. III.B.1 and
@@ -67,8 +67,9 @@ typedef enum {
 
 typedef enum {
     CCR_PREC_FP64 = 0,  /* time base, interpolation, FFT and pair sum in FP64 */
-    CCR_PREC_SPLIT = 1  /* FP64 time base and phases; FP32 interpolation, FFT and pair products
-                           (pair sums accumulated in FP64) */
+    CCR_PREC_SPLIT = 1  /* FP64 time base and phases; FP32 interpolation, FFT and pair products.
+                           Pair products of one pass of a pair-sum kernel (the segments of one
+                           step, a few at a time) are summed in FP32, the passes in FP64 */
 } ccr_precision;
 
 /* Source direction and the analytic Earth model of the detector position r(t):
@@ -201,15 +202,21 @@ ccr_status ccr_set_data(ccr_ctx *ctx, int band_id, int det, const ccr_site *site
 ccr_status ccr_set_weights(ccr_ctx *ctx, int band_id, int det, int64_t n_seg, const double *a,
                            const double *b, const double *noise_var);
 
-/* Orbital templates of a band: n triples (a_p [s], T_asc [s after epoch], P [s]).
- * a_p >= 0, P > 0, all finite. */
+/* Orbital templates of a band (the Doppler parameters lambda of Sec. II.A.2, circular orbit,
+ * eq. tau-equation): n triples (a_p [s], T_asc [s after epoch], P [s]).  a_p >= 0, P > 0, all
+ * finite; otherwise CCR_EINVAL and the band keeps its previous templates.  Replaces the band's
+ * template list (copied). */
 ccr_status ccr_set_templates(ccr_ctx *ctx, int band_id, int64_t n, const double *a_p,
                              const double *t_asc, const double *period);
 
-/* Full plan of a band; bin_freqs (n_f doubles, may be NULL) receives f_het + kbar_i / T_FFT. */
+/* Full plan of a band (Sec. III.B.1-2: M, T_coh, delta lambda_f, N_FFT by eq. n-fft-final,
+ * nu_R; App. B eq. delta-f-load; the normalisation N of App. A); bin_freqs (n_f doubles, may be
+ * NULL) receives the output frequencies f_het + kbar_i / T_FFT, kbar_i = k_lo + floor(nu_R i)
+ * (Sec. III.B.2, bin-centred frequencies).  CCR_ESTATE before every detector has data. */
 ccr_status ccr_get_band_info(ccr_ctx *ctx, int band_id, ccr_band_info *info, double *bin_freqs);
 
-/* rho for every template and bin of each listed band.  rho_out[b] points to
+/* rho of eq. final-formatted-rho (Sec. III.B.6) for every template and bin of each listed band:
+ * steps 1-4 above on the device, in the precision `prec`.  rho_out[b] points to
  * n_templates * n_f values (row-major, template-major) of double (out_fp64 = 1) or float,
  * in device memory (out_on_device = 1, must stay valid until ccr_sync) or host memory
  * (written before the call returns).  hip_stream: a hipStream_t, or NULL for the context's

@@ -12,9 +12,9 @@
  *   time base Sec. II.A.2 (eqs. t-ssb-equation, tau-equation, circular R/c), Sec. III.A.2
  *   interp    Sec. III.A.1 (eq. shannon-interp-formula), Sec. III.A.2 (eqs. delta-q-eq,
  *             q-prime-eq, resampled-time-series-q-eq)
- *   spectra   Sec. III.B.3-4 (zero-padded DFT of each T_short segment with Phi_in)
+ *   spectra   Sec. III.B.5 (zero-padded DFT of each T_short segment) with Phi_in of Sec. III.B.4
  *   pairs     Sec. III.B.1 (pair selection {L|K})
- *   rho       Sec. III.B.5 (eq. final-formatted-rho) with App. A normalisation
+ *   rho       Sec. III.B.6 (eq. final-formatted-rho) with App. A normalisation
  *
  * Precision: long double (x87, 64-bit mantissa) for the time base and all
  * phases, double for interpolation, the direct DFT and the pair sum.  Nothing
@@ -355,7 +355,7 @@ static int64_t bin_mod(const cco_plan *pl, int64_t i) {
     return k < 0 ? k + pl->n_fft : k;
 }
 
-/* Tier R spectra (Sec. III.B.3-4): zero-padded DFT of segment K starting at
+/* Tier R spectra (Sec. III.B.4-5): zero-padded DFT of segment K starting at
  * r_B = K N_K, referenced to the series origin (Phi_in folded into the kernel):
  *   F_XK(i) = (sigma_XK sqrt(N_K))^-1 sum_{s<N_K} y_{r_B+s} exp(-2 pi i kbar_i (r_B + s) / N_FFT),
  * the phase index (kbar (r_B + s)) mod N_FFT kept as an exact integer. */
@@ -389,7 +389,7 @@ static void spectra_from_series(const cco_problem *p, const cco_plan *pl, int de
     for (int64_t K = 0; K < pl->n_seg; ++K) spectra_segment(p, pl, det, K, y + 2 * K * pl->n_k, tw, bins, nb, F);
 }
 
-/* Tier D spectra (App. A, eq. from-here-resamp; Sec. III.B.5 frame invariance):
+/* Tier D spectra (App. A, eq. from-here-resamp; Sec. III.B.6 frame invariance):
  * no interpolation; each raw detector sample j is demodulated with the exact
  * phase model and assigned to the segment holding its source time:
  *   F^D_XK(i) = (sigma sqrt(N_K))^-1 sum_{j: tau(t_j) in K} valid_j x'_j
@@ -476,7 +476,7 @@ int64_t cco_pair_count(const cco_problem *p) {
     return c;
 }
 
-/* Normalisation (Sec. III.B.5 and App. A): N^2 = sum_P A_XK A_YL + 2 C_XK C_YL + B_XK B_YL
+/* Normalisation (Sec. III.B.6 and App. A): N^2 = sum_P A_XK A_YL + 2 C_XK C_YL + B_XK B_YL
  * with hat a = a / sigma, A = hat a^2 phi, B = hat b^2 phi, C = hat a hat b phi, where phi is
  * the valid fraction of the segment (gaps carry zero weight).  This gives Var rho = 1 for
  * unit-variance segment spectra. */

@@ -882,6 +882,8 @@ void collect_times(ccr_ctx *c) {
 
 constexpr size_t kMaxLds = 65536;
 
+ccr_status grow(ccr_ctx *c, DevBuf &b, size_t bytes);
+
 // Fused path: one launch per template batch computes partial rho per (template, segment chunk)
 // with every intermediate in LDS, then the chunk partials are summed in order.
 ccr_status compute_fused(ccr_ctx *c, Band &B, const BandDev &bd, bool fp64, int S, void *rho_out,
@@ -896,13 +898,15 @@ ccr_status compute_fused(ccr_ctx *c, Band &B, const BandDev &bd, bool fp64, int 
         tb = std::max<int64_t>(1, ((int64_t)2 << 30) / per);
     }
     tb = std::max<int64_t>(1, std::min<int64_t>({tb, (int64_t)65535, B.n_tmpl}));
-    HIP_OK(c, c->ws_part.ensure((size_t)tb * nch * pl.n_f * sizeof(double)));
-    HIP_OK(c, c->ws_coef.ensure((size_t)tb * std::max(B.n_work, 1) * kCheb * sizeof(double)));
+    // workspace growth through grow(): finishes queued work and invalidates captured graphs
+    ccr_status st = grow(c, c->ws_part, (size_t)tb * nch * pl.n_f * sizeof(double));
+    if (!st) st = grow(c, c->ws_coef, (size_t)tb * std::max(B.n_work, 1) * kCheb * sizeof(double));
+    if (st) return st;
     const size_t osz = out_fp64 ? sizeof(double) : sizeof(float);
     const size_t out_bytes = (size_t)B.n_tmpl * pl.n_f * osz;
     void *dst = rho_out;
     if (!out_on_device) {
-        HIP_OK(c, c->ws_out.ensure(out_bytes));
+        if ((st = grow(c, c->ws_out, out_bytes))) return st;
         dst = c->ws_out.p;
     }
     const double factor = pl.norm > 0.0 ? std::sqrt(2.0) / pl.norm : 0.0;
@@ -1456,7 +1460,7 @@ ccr_status ccr_set_option(ccr_ctx *c, const char *name, int64_t value) {
     else if (k == "farrow_stage") c->opt_farrow_stage = value ? 1 : 0;
     else return fail(c, CCR_EUNSUP, "unknown option '%s'", name);
     if (k == "template_batch" || k == "workspace_mb" || k == "k_chunk" || k == "items_per_launch" || k == "farrow" ||
-        k == "farrow_stage")
+        k == "farrow_stage" || k == "fused")
         c->gen++;
     return CCR_OK;
 }

@@ -68,6 +68,26 @@ def test_plan_invariants(name):
     assert f[-1] <= band["f_min"] + band["f_band"] + 1.0 / pl.t_fft
 
 
+@pytest.mark.parametrize("name", ["tiny", "band", "large"])
+def test_plan_matches_hand_derived_values(name):
+    """App. B eq. delta-f-load (with eqs. f-drift-eq, delta-f-obs) and Sec. III.B.2 eq.
+    n-fft-final worked by hand (tests/golden/paper_values.json, derivation written out there):
+    a dropped (1 + 4/(2D+1)) factor, 16/T_sft term or Doppler wing moves df_load, N_K, N_FFT or N_f."""
+    g = GOLD["plan_derived"][name]
+    cfg = synth.config(name)
+    band = cfg["band"]
+    nk = synth.samples_per_segment(band)
+    dt = band["t_short"] / nk
+    ds = Dataset(sky=synth.default_sky(), band=band, sites=[synth.SITES["H"], synth.SITES["L"]],
+                 dt=dt, t0=0.0, n=nk * 4, n_k=nk, n_seg=4, f_het=band["f_min"] + band["f_band"] / 2,
+                 x=np.zeros((2, nk * 4), np.complex64), valid=np.ones((2, nk * 4), np.uint8),
+                 a=np.ones((2, 4)), b=np.ones((2, 4)), noise_var=np.ones((2, 4)),
+                 templates=np.zeros((1, 3)))
+    pl = oracle.Oracle(ds).plan()
+    assert abs(pl.df_load - g["df_load"]) < 5e-5
+    assert (pl.n_k, pl.n_fft, pl.n_f) == (g["n_k"], g["n_fft"], g["n_f"])
+
+
 def test_pair_counts_and_asymptotic_total():
     """Sec. III.B.1: 2R+1 cross partners and R same-detector partners per interior K; the total
     approaches N_det^2 T_max T_obs / T_short^2 (Sec. III.B) for large R."""
@@ -150,7 +170,7 @@ def test_pure_binary_delay_fixed_point():
 # ----------------------------------------------------------- interpolation
 
 def test_zero_delay_resampling_is_identity():
-    """Sec. III.B.5: with zero Roemer delay no resampling is needed; on-grid sinc returns the sample."""
+    """Sec. III.B.6: with zero Roemer delay no resampling is needed; on-grid sinc returns the sample."""
     ds = synth.make_dataset(small_config(n_seg=6, gap_fraction=0.0), sky=NO_EARTH)
     o = oracle.Oracle(ds)
     y, js, off, m = o.resample(0, np.array([0.0, 0.0, 68023.7]))
@@ -200,7 +220,40 @@ def test_sinc_interpolation_converges_with_D(window):
         sel = slice(200, len(y) - 200)
         errs.append(np.abs(y[sel] - exact[sel]).max())
     assert errs[0] > errs[1] > errs[2] > errs[3]
-    assert errs[1] < (2e-2 if window == 0 else 5e-3)
+    # D = 8 budget at this offset (0.37 samples) and tone (0.19 cycles/sample), as measured:
+    # 4.29e-3 (window indexed by tap) and 2.45e-3 (window at the offset).  Two-sided, so that a
+    # Hann window (5.6e-3 / 1.9e-4) or a Hamming indexed over 2D + 1 (2.2e-2) fails.
+    lo, hi = (3.9e-3, 4.7e-3) if window == 0 else (2.2e-3, 2.7e-3)
+    assert lo < errs[1] < hi, errs[1]
+
+
+@pytest.mark.parametrize("window", [0, 1])
+def test_tap_weights_are_hamming_times_sinc(window):
+    """Sec. III.A.1 (eq. shannon-interp-formula, Hamming window of length 2D + 1): the resampled
+    impulse response is w sinc(d) tap by tap, checked against numpy's Hamming window and sinc.
+    Window 0 is indexed by tap n, w_n = np.hamming(2D + 1)[n + D]; window 1 is evaluated at the
+    continuous offset d = delta_c - n, w(d) = 0.54 + 0.46 cos(pi d / (D + 1)), which at the
+    half-integer offsets used here is np.hamming(4D + 5)[2d + 2D + 2]."""
+    D = 8
+    delay = 2.37 if window == 0 else 2.5
+    ds = _pole_dataset(delay, D=D, window=window, n_seg=6)
+    j0 = ds.n // 2
+    ds.x = np.zeros_like(ds.x)
+    ds.x[:, j0] = 1.0
+    o = oracle.Oracle(ds)
+    y, js, off, m = o.resample(0, np.array([0.0, 0.0, 68023.7]))
+    phase = np.exp(2j * np.pi * ds.f_het * (-ds.sky["re_s"]))
+    hit = np.nonzero(np.abs(js - j0) <= D)[0]
+    assert len(hit) == 2 * D + 1
+    for r in hit:
+        n = j0 - js[r]
+        d = off[r] - n
+        if window == 0:
+            w = np.hamming(2 * D + 1)[n + D]
+        else:
+            assert abs(abs(off[r]) - 0.5) < 1e-9
+            w = np.hamming(4 * D + 5)[int(round(2 * d)) + 2 * D + 2]
+        assert abs(y[r] / phase - w * np.sinc(d)) < 1e-9, (r, n, d)
 
 
 # ------------------------------------------------------------- DFT, phases
@@ -218,7 +271,7 @@ def _tone_dataset(kappa_bins, n_seg=5, sigma=1.3, t_short=120.0):
 
 @pytest.mark.parametrize("kappa", [0.0, 0.25, -0.4, 0.5])
 def test_segment_dft_is_geometric_series(kappa):
-    """Zero-padded DFT of a tone at bin offset kappa (Sec. III.B.3-4): per segment
+    """Zero-padded DFT of a tone at bin offset kappa (Sec. III.B.5): per segment
     sum_s exp(2 pi i kappa (r_B + s)/N_FFT) = exp(2 pi i kappa r_B/N) e^{i pi kappa (N_K-1)/N} sin(pi kappa N_K/N)/sin(pi kappa/N)."""
     ds, pl, i0, kb = _tone_dataset(kappa)
     o = oracle.Oracle(ds)
@@ -236,7 +289,7 @@ def test_segment_dft_is_geometric_series(kappa):
 
 
 def test_span_dft_equals_sum_of_phased_segments():
-    """Sec. III.B.4: one DFT over an L-span equals the sum of per-segment DFTs once Phi_in is
+    """Sec. III.B.4-5: one DFT over an L-span equals the sum of per-segment DFTs once Phi_in is
     applied (linearity); reference DFT computed by numpy from the resampled series."""
     ds = synth.make_dataset(small_config(n_seg=8, sigma=[1.0, 1.0]))
     o = oracle.Oracle(ds)
@@ -256,7 +309,7 @@ def test_span_dft_equals_sum_of_phased_segments():
 
 
 def test_zero_delay_tiers_agree():
-    """Sec. III.B.5: with zero Roemer delay the resampled rho exactly equals the detector-frame rho."""
+    """Sec. III.B.6: with zero Roemer delay the resampled rho exactly equals the detector-frame rho."""
     ds = synth.make_dataset(small_config(n_seg=10, gap_fraction=0.2, max_lag=2), sky=NO_EARTH)
     o = oracle.Oracle(ds)
     tm = np.array([[0.0, 0.0, 68023.7]])
