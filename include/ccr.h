@@ -232,7 +232,8 @@ ccr_status ccr_sync(ccr_ctx *ctx);
  * since the last ccr_reset_kernel_times (HIP events recorded on the launch stream around each
  * launch).  kernel: 0 resampling, 1 segment spectra, 2 pair sum, 3 final scaling,
  * 4 fused resampling + spectra + pair sum, 5 FP64 time base (per-segment interpolating polynomial),
- * 6 spectra + pair sum in one kernel (split precision, 256-point segments).
+ * 6 spectra + pair sum in one kernel (split precision, 256-point segments), 7 the same for
+ * 1024-point segments.
  * Waits for the recorded launches to finish. */
 ccr_status ccr_kernel_time(ccr_ctx *ctx, int kernel, double *ms, int64_t *launches);
 ccr_status ccr_reset_kernel_times(ccr_ctx *ctx);

@@ -211,7 +211,7 @@ class Context:
     def sync(self):
         self._check(self.L.ccr_sync(self.h))
 
-    KERNELS = ("resample", "spectra", "pairs", "finish", "fused", "timebase", "spectra_pairs")
+    KERNELS = ("resample", "spectra", "pairs", "finish", "fused", "timebase", "spectra_pairs", "spectra_wide")
 
     def kernel_times(self, reset=False):
         """{kernel: (total_ms, launches)} recorded while option "timing" is 1."""

@@ -82,7 +82,8 @@ struct Band {
     // device tables
     DevBuf d_x, d_mask, d_anchor, d_earth, d_win64, d_win32, d_cheb_x, d_mono, d_tw64, d_tw32, d_bin_m, d_bin_p,
         d_bin_kb, d_bin_pos, d_segw, d_active, d_work, d_seg_work, d_tmpl, d_lagph, d_seg_any, d_col_bin, d_bin_col, d_zero256,
-        d_class_start, d_farrow, d_farrow_A;
+        d_class_start, d_farrow, d_farrow_A, d_cls_m0;
+    int wide_jmax = 0, wide_ncol = 0;  // 1024-point spectra + pair-sum kernel (see BandDev)
     int64_t far_len = 0;  // plane length of the Farrow table, 0 when the band has none
     double far_err = 0;   // bound of the fitted tap weights' error, sum over taps
     int bins_unique = 0;
@@ -134,8 +135,8 @@ struct ccr_ctx {
         hipEvent_t a, b;
     };
     std::vector<Timed> timed;
-    double kt_ms[7] = {0, 0, 0, 0, 0, 0, 0};
-    int64_t kt_n[7] = {0, 0, 0, 0, 0, 0, 0};
+    double kt_ms[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+    int64_t kt_n[8] = {0, 0, 0, 0, 0, 0, 0, 0};
 };
 
 // A compute call captured as a HIP graph: replayed while the call's arguments and the
@@ -553,6 +554,30 @@ ccr_status prepare(ccr_ctx *c, Band &B) {
     std::vector<int> class_start((size_t)pl.P + 1, 0);
     for (int64_t cc = 0; cc < pl.n_f; ++cc) ++class_start[(size_t)bp[col_bin[cc]] + 1];
     for (int64_t q = 0; q < pl.P; ++q) class_start[(size_t)q + 1] += class_start[(size_t)q];
+    // 1024-point kernel: the bins of class p, at FFT outputs m (ascending in column order), span
+    // a circular range of the n_s outputs; m0 = the output after the range's largest gap, so the
+    // class occupies m0 .. m0 + span - 1 (mod n_s)
+    std::vector<int> cls_m0((size_t)pl.P, 0);
+    int wide_jmax = 0, wide_ncol = 0;
+    for (int64_t q = 0; q < pl.P; ++q) {
+        const int a = class_start[(size_t)q], b = class_start[(size_t)q + 1];
+        wide_ncol = std::max(wide_ncol, b - a);
+        if (b == a) continue;
+        int best_gap = -1, m0 = bm[col_bin[a]];
+        for (int cc = a; cc < b; ++cc) {
+            const int m = bm[col_bin[cc]];
+            const int prev = bm[col_bin[cc == a ? b - 1 : cc - 1]];
+            const int gap = (int)((m - prev + pl.n_s) % pl.n_s);
+            if (gap > best_gap) {
+                best_gap = gap;
+                m0 = m;
+            }
+        }
+        int span = 0;
+        for (int cc = a; cc < b; ++cc) span = std::max(span, (int)((bm[col_bin[cc]] - m0 + pl.n_s) % pl.n_s) + 1);
+        cls_m0[(size_t)q] = m0;
+        wide_jmax = std::max(wide_jmax, (span + 63) / 64);
+    }
     // lag phases of the pair sum (spectra taken without Phi_in), in ring-column order
     const int64_t Rl = B.p.max_lag;
     std::vector<float2> lagph((size_t)(Rl + 1) * pl.n_f);
@@ -626,6 +651,9 @@ ccr_status prepare(ccr_ctx *c, Band &B) {
     if ((st = upload(c, B.d_col_bin, col_bin))) return st;
     if ((st = upload(c, B.d_bin_col, bin_col))) return st;
     if ((st = upload(c, B.d_class_start, class_start))) return st;
+    if ((st = upload(c, B.d_cls_m0, cls_m0))) return st;
+    B.wide_jmax = wide_jmax;
+    B.wide_ncol = wide_ncol;
     if ((st = upload(c, B.d_zero256, std::vector<float2>(256, make_float2(0.f, 0.f))))) return st;
     {
         std::vector<int> any;
@@ -825,6 +853,9 @@ BandDev band_dev(const Band &B) {
     d.farrow = B.far_len > 0 ? B.d_farrow.as<float2>() : nullptr;
     d.far_len = B.far_len;
     d.far_stage = 1;
+    d.cls_m0 = B.d_cls_m0.as<int>();
+    d.wide_jmax = B.wide_jmax;
+    d.wide_ncol = B.wide_ncol;
     return d;
 }
 
@@ -949,10 +980,13 @@ struct Variant {
     bool z4 = false;     // spectra + pair sum: N_K <= 192 (4 of the 16 FFT input rows are zero)
     bool ss = false;     // time base with the short small-angle series
     bool far = false;    // split-precision resampling in Farrow form
+    bool wide = false;   // spectra + pair sum in one kernel, 1024-point segments
     int DT = 0, window = 0, n_s = 0, nr = 0, n_cheb = kCheb;
+    int wcols = 0, wqm = 0;  // wide: bins of a class per lane, detector bound (2 or 4)
     bool operator==(const Variant &o) const {
-        return sp == o.sp && reg16 == o.reg16 && z4 == o.z4 && ss == o.ss && far == o.far && DT == o.DT &&
-               window == o.window && n_s == o.n_s && nr == o.nr && n_cheb == o.n_cheb;
+        return sp == o.sp && reg16 == o.reg16 && z4 == o.z4 && ss == o.ss && far == o.far && wide == o.wide &&
+               DT == o.DT && window == o.window && n_s == o.n_s && nr == o.nr && n_cheb == o.n_cheb &&
+               wcols == o.wcols && wqm == o.wqm;
     }
 };
 
@@ -983,10 +1017,14 @@ Variant variant_of(const BandDev &bd, bool fp64, bool short_series, bool farrow)
     v.ss = short_series;
     v.far = farrow && !fp64 && bd.farrow != nullptr;
     v.sp = spectra_pairs_ok(bd, fp64, kMaxLds);
+    v.wide = !v.sp && spectra_wide_ok(bd, fp64, kMaxLds);
     v.DT = bd.D == 8 ? 8 : 0;
     v.window = bd.window;
     v.n_cheb = fp64 ? kCheb : bd.cheb_split;
-    if (v.sp) {
+    if (v.wide) {
+        v.wcols = spectra_wide_cols(bd);
+        v.wqm = bd.Q <= 2 ? 2 : 4;
+    } else if (v.sp) {
         v.nr = spectra_pairs_rounds(bd);
         v.z4 = bd.n_k <= 192;
     } else {
@@ -1003,7 +1041,7 @@ int64_t stage_max_blocks(const Variant &v, int st) {
     int threads = 64;
     if (st == kStTimebase) threads = tb_entries(v.n_cheb) * v.n_cheb;
     else if (st == kStResample) threads = v.far ? 256 : 64;
-    else if (st == kStSpectra) threads = v.sp ? 64 : (v.reg16 ? 128 : spectra_threads(v.n_s));
+    else if (st == kStSpectra) threads = (v.sp || v.wide) ? 64 : (v.reg16 ? 128 : spectra_threads(v.n_s));
     else if (st == kStPairs) threads = kPairsThreads;
     else if (st == kStFinish) threads = kFinishThreads;
     return std::min<int64_t>(kMaxBlocks, (((int64_t)1 << 32) - 1) / threads);
@@ -1019,18 +1057,21 @@ ccr_status grow(ccr_ctx *c, DevBuf &b, size_t bytes) {
     return CCR_OK;
 }
 
+// budget_override > 0: pack rounds to that many workspace bytes instead of the context's budget.
 ccr_status build_plan(ccr_ctx *c, bool fp64, int n_bands, const int *band_ids, void *const *rho_out,
-                      int out_on_device, int out_fp64, const BatchParams &bp, CallPlan &cp) {
+                      int out_on_device, int out_fp64, const BatchParams &bp, CallPlan &cp, size_t budget_override = 0) {
     const size_t cs = fp64 ? 16 : 8;
     const size_t osz = out_fp64 ? sizeof(double) : sizeof(float);
-    if (c->opt_workspace_mb == 0 && c->auto_budget == 0) {
+    if (budget_override == 0 && c->opt_workspace_mb == 0 && c->auto_budget == 0) {
         // 3/4 of the free device memory plus the workspace the context already holds
         size_t fr = 0, tot = 0;
         HIP_OK(c, hipMemGetInfo(&fr, &tot));
         const size_t held = c->ws_y.bytes + c->ws_F.bytes + c->ws_part.bytes + c->ws_coef.bytes;
         c->auto_budget = std::max<size_t>((fr + held) / 4 * 3, (size_t)64 << 20);
     }
-    const size_t budget = c->opt_workspace_mb > 0 ? (size_t)c->opt_workspace_mb << 20 : c->auto_budget;
+    const size_t budget = budget_override > 0          ? budget_override
+                          : c->opt_workspace_mb > 0 ? (size_t)c->opt_workspace_mb << 20
+                                                    : c->auto_budget;
     cp = CallPlan();
     cp.out_off.assign((size_t)n_bands, 0);
     for (int bi = 0; bi < n_bands; ++bi) {
@@ -1063,7 +1104,7 @@ ccr_status build_plan(ccr_ctx *c, bool fp64, int n_bands, const int *band_ids, v
         kc = std::max<int64_t>(1, std::min<int64_t>(kc, pl.n_seg));
         const int nch = (int)((pl.n_seg + kc - 1) / kc);
         const size_t y1 = (size_t)B.Q * pl.n_seg * pl.n_k * cs;
-        const size_t F1 = v.sp ? 0 : (size_t)B.Q * pl.n_seg * pl.n_f * cs;
+        const size_t F1 = (v.sp || v.wide) ? 0 : (size_t)B.Q * pl.n_seg * pl.n_f * cs;
         const size_t part1 = (size_t)nch * pl.n_f * sizeof(double);
         const size_t coef1 = (size_t)std::max(B.n_work, 1) * kCheb * sizeof(double);
         WorkItem proto;
@@ -1075,8 +1116,10 @@ ccr_status build_plan(ccr_ctx *c, bool fp64, int n_bands, const int *band_ids, v
         proto.out_fp64 = out_fp64 ? 1 : 0;
         proto.gx[kStTimebase] = (B.n_work + tb_entries(v.n_cheb) - 1) / tb_entries(v.n_cheb);
         proto.gx[kStResample] = B.n_work;
-        proto.gx[kStSpectra] = v.sp ? nch : (v.reg16 ? (B.n_work + kSpec16Groups - 1) / kSpec16Groups : B.n_work);
-        proto.gx[kStPairs] = v.sp ? 0 : (int)((pl.n_f + kPairsThreads - 1) / kPairsThreads);
+        proto.gx[kStSpectra] = v.wide ? nch * (int)pl.P
+                               : v.sp ? nch
+                                      : (v.reg16 ? (B.n_work + kSpec16Groups - 1) / kSpec16Groups : B.n_work);
+        proto.gx[kStPairs] = (v.sp || v.wide) ? 0 : (int)((pl.n_f + kPairsThreads - 1) / kPairsThreads);
         proto.gx[kStFinish] = (int)((pl.n_f + kFinishThreads - 1) / kFinishThreads);
         const int64_t per_t[kStages] = {proto.gx[0], proto.gx[1], proto.gx[2], (int64_t)proto.gx[3] * nch, proto.gx[4]};
         int64_t tb = bp.template_batch > 0 ? bp.template_batch : c->opt_template_batch;
@@ -1099,7 +1142,7 @@ ccr_status build_plan(ccr_ctx *c, bool fp64, int n_bands, const int *band_ids, v
             q.F = F1 * nb;
             q.part = part1 * nb;
             q.coef = coef1 * nb;
-            q.lds = v.sp ? spectra_pairs_lds(bd) : 0;
+            q.lds = v.sp ? spectra_pairs_lds(bd) : (v.wide ? spectra_wide_lds(bd) : 0);
             for (int st = 0; st < kStages; ++st) q.blk[st] = per_t[st] * nb;
             q.blk[kStResample] = per_t[kStResample] * ((nb + res_t - 1) / res_t);
             pend.push_back(q);
@@ -1188,12 +1231,29 @@ void fill_tables(const CallPlan &cp, void *dst, size_t items_off) {
     std::memcpy(static_cast<char *>(dst) + items_off, cp.items.data(), cp.items.size() * sizeof(WorkItem));
 }
 
+// Device workspace of a launch sequence: time-base coefficients, resampled series, segment
+// spectra (general path) and chunk partials.
+struct Workspace {
+    double *coef = nullptr;
+    void *y = nullptr, *F = nullptr;
+    double *part = nullptr;
+};
+
+Workspace ctx_workspace(ccr_ctx *c) {
+    Workspace w;
+    w.coef = c->ws_coef.as<double>();
+    w.y = c->ws_y.p;
+    w.F = c->ws_F.p;
+    w.part = c->ws_part.as<double>();
+    return w;
+}
+
 // Queue the rounds [r0, r1) of a plan on `s` (tables already on the device).
 ccr_status run_rounds(ccr_ctx *c, const CallPlan &cp, size_t r0, size_t r1, bool fp64, const void *d_tables,
-                      size_t items_off, hipStream_t s, bool timing) {
+                      size_t items_off, hipStream_t s, bool timing, const Workspace &ws) {
     const BandDev *db = static_cast<const BandDev *>(d_tables);
     const WorkItem *ditems = reinterpret_cast<const WorkItem *>(static_cast<const char *>(d_tables) + items_off);
-    double *coef = c->ws_coef.as<double>(), *part = c->ws_part.as<double>();
+    double *coef = ws.coef, *part = ws.part;
     for (size_t ri = r0; ri < r1; ++ri) {
         const Round &r = cp.rounds[ri];
         const WorkItem *di = ditems + r.i0;
@@ -1204,20 +1264,24 @@ ccr_status run_rounds(ccr_ctx *c, const CallPlan &cp, size_t r0, size_t r1, bool
         {
             LaunchTimer lt(c, 0, s, timing);
             HIP_OK(c, launch_resample_m(db, di, r.n, (int)r.blocks[kStResample], fp64, r.v.DT, r.v.window,
-                                        r.v.n_cheb, r.v.far, coef, c->ws_y.p, s));
+                                        r.v.n_cheb, r.v.far, coef, ws.y, s));
         }
         if (r.v.sp) {
             LaunchTimer lt(c, 6, s, timing);
-            HIP_OK(c, launch_spectra_pairs_m(db, di, r.n, (int)r.blocks[kStSpectra], r.v.nr, r.v.z4, r.lds, c->ws_y.p, part, s));
+            HIP_OK(c, launch_spectra_pairs_m(db, di, r.n, (int)r.blocks[kStSpectra], r.v.nr, r.v.z4, r.lds, ws.y, part, s));
+        } else if (r.v.wide) {
+            LaunchTimer lt(c, 7, s, timing);
+            HIP_OK(c, launch_spectra_wide_m(db, di, r.n, (int)r.blocks[kStSpectra], r.v.wcols, r.v.wqm, r.lds, ws.y,
+                                            part, s));
         } else {
             {
                 LaunchTimer lt(c, 1, s, timing);
                 HIP_OK(c, launch_spectra_m(db, di, r.n, (int)r.blocks[kStSpectra], fp64, r.v.reg16,
-                                           spectra_threads(r.v.n_s), r.v.n_s, c->ws_y.p, c->ws_F.p, s));
+                                           spectra_threads(r.v.n_s), r.v.n_s, ws.y, ws.F, s));
             }
             {
                 LaunchTimer lt(c, 2, s, timing);
-                HIP_OK(c, launch_pairs_m(db, di, r.n, (int)r.blocks[kStPairs], fp64, c->ws_F.p, part, s));
+                HIP_OK(c, launch_pairs_m(db, di, r.n, (int)r.blocks[kStPairs], fp64, ws.F, part, s));
             }
         }
         {
@@ -1285,7 +1349,8 @@ ccr_status choose_params(ccr_ctx *c, ccr_precision prec, int n_bands, const int 
         // one untimed pass of the round, then the timed one
         for (int rep = 0; rep < 2 && !st; ++rep) {
             if (rep == 1 && hipEventRecord(e0, s) != hipSuccess) st = fail(c, CCR_EDEVICE, "event record failed");
-            if (!st) st = run_rounds(c, cp, 0, std::min<size_t>(1, cp.rounds.size()), fp64, c->d_tables.p, items_off, s, false);
+            if (!st) st = run_rounds(c, cp, 0, std::min<size_t>(1, cp.rounds.size()), fp64, c->d_tables.p, items_off, s, false,
+                                     ctx_workspace(c));
         }
         if (st) break;
         HIP_OK(c, hipEventRecord(e1, s));
@@ -1346,7 +1411,7 @@ ccr_status compute_batched(ccr_ctx *c, ccr_precision prec, int n_bands, const in
         HIP_OK(c, hipMalloc(&g->tables, bytes));
         HIP_OK(c, hipMemcpy(g->tables, host.data(), bytes, hipMemcpyHostToDevice));
         HIP_OK(c, hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal));
-        st = run_rounds(c, cp, 0, cp.rounds.size(), fp64, g->tables, items_off, c->stream, false);
+        st = run_rounds(c, cp, 0, cp.rounds.size(), fp64, g->tables, items_off, c->stream, false, ctx_workspace(c));
         hipGraph_t gr = nullptr;
         const hipError_t ec = hipStreamEndCapture(c->stream, &gr);
         if (st) {
@@ -1368,7 +1433,8 @@ ccr_status compute_batched(ccr_ctx *c, ccr_precision prec, int n_bands, const in
     }
     size_t items_off = 0;
     if ((st = upload_tables(c, cp, s, &items_off))) return st;
-    if ((st = run_rounds(c, cp, 0, cp.rounds.size(), fp64, c->d_tables.p, items_off, s, true))) return st;
+    if ((st = run_rounds(c, cp, 0, cp.rounds.size(), fp64, c->d_tables.p, items_off, s, true, ctx_workspace(c))))
+        return st;
     if (!out_on_device) {
         for (int bi = 0; bi < n_bands; ++bi) {
             const Band &B = *get_band(c, band_ids[bi]);
@@ -1702,7 +1768,7 @@ ccr_status ccr_compute_rho(ccr_ctx *c, ccr_precision prec, int n_bands, const in
 
 ccr_status ccr_kernel_time(ccr_ctx *c, int kernel, double *ms, int64_t *launches) {
     if (!c || !ms || !launches) return CCR_EINVAL;
-    if (kernel < 0 || kernel > 6) return fail(c, CCR_EINVAL, "kernel id %d out of range", kernel);
+    if (kernel < 0 || kernel > 7) return fail(c, CCR_EINVAL, "kernel id %d out of range", kernel);
     collect_times(c);
     *ms = c->kt_ms[kernel];
     *launches = c->kt_n[kernel];
@@ -1712,7 +1778,7 @@ ccr_status ccr_kernel_time(ccr_ctx *c, int kernel, double *ms, int64_t *launches
 ccr_status ccr_reset_kernel_times(ccr_ctx *c) {
     if (!c) return CCR_EINVAL;
     collect_times(c);
-    for (int k = 0; k < 7; ++k) {
+    for (int k = 0; k < 8; ++k) {
         c->kt_ms[k] = 0.0;
         c->kt_n[k] = 0;
     }

@@ -103,6 +103,11 @@ struct BandDev {
     const float2 *farrow;
     int64_t far_len;
     int far_stage;  // 1: stage the table in LDS (else every sample reads it from global memory)
+    // 1024-point spectra + pair-sum kernel: per residue class p the first FFT output index m0 of
+    // its bins in circular order (the class's bins occupy m0 .. m0 + span - 1 mod n_s); the
+    // widest span in units of 64 outputs, and the largest class (bins)
+    const int *cls_m0;
+    int wide_jmax, wide_ncol;
 };
 
 // One work item of a batched launch: a run of consecutive templates of one band.  A batched
@@ -179,6 +184,15 @@ hipError_t launch_resample_m(const BandDev *bands, const WorkItem *items, int n_
 // coefficients A [kFarDeg][2D + 1] (row k - 1 for the power dc^k).
 hipError_t launch_farrow_table(const float2 *x, int64_t n, int Q, int D, const double *A, int64_t far_len,
                                float2 *tab, hipStream_t stream);
+// Split-precision spectra + pair sum for 1024-point segments (N_FFT a power of two, distinct
+// bins, at most 4 detectors, classes of at most 512 bins, LDS within `limit`); its LDS bytes,
+// and the bins of a class per lane it is instantiated for (2, 4 or 8).
+bool spectra_wide_ok(const BandDev &B, bool fp64, size_t limit);
+size_t spectra_wide_lds(const BandDev &B);
+int spectra_wide_cols(const BandDev &B);
+// cols: spectra_wide_cols of the round's bands; qm: their largest detector count.
+hipError_t launch_spectra_wide_m(const BandDev *bands, const WorkItem *items, int n_items, int blocks, int cols,
+                                 int qm, size_t lds, const void *y, double *part, hipStream_t stream);
 // z4: N_K <= 192, so the last 4 of the 16 input rows of each 256-point FFT are zero padding.
 hipError_t launch_spectra_pairs_m(const BandDev *bands, const WorkItem *items, int n_items, int blocks, int rounds,
                                   bool z4, size_t lds, const void *y, double *part, hipStream_t stream);

@@ -1209,6 +1209,285 @@ __device__ __forceinline__ void spectra_pairs_body(const BandDev &B, const float
 }
 
 
+// ------------------------------------------------------------------ spectra + pair sum, 1024-point segments
+
+// 1024-point forward FFT held by one wavefront: on entry lane l holds x[l + 64 r] in v[r]
+// (r < 16), on return X[l + 64 J] in v[J].  Three self-sorting (Stockham) passes of radix 16,
+// 16 and 4 run in registers; between passes the values go through `fx` (1024 complex, index i
+// stored at i + i / 16 so that the strided accesses of a pass spread over the LDS banks).
+// w2[r - 1] = W256^(r (l % 16)) (r = 1..15) and w3[q][r - 1] = W1024^(r (l + 64 q)) (q < 4,
+// r = 1..3) are the pass twiddles of this lane, W_n = exp(-2 pi i / n).  Single wavefront:
+// the hardware runs its LDS operations in issue order, wave_sync() keeps the compiler's order.
+__device__ __forceinline__ void fft1024_wave(float2 *v, float2 *fx, const float2 *w2, const float2 (*w3)[3],
+                                             int lane) {
+    // pass 1 (radix 16 over r, no twiddles): output k of butterfly j = l goes to 16 l + k
+    dft16<float>(v);
+#pragma unroll
+    for (int k = 0; k < 16; ++k) fx[17 * lane + k] = v[4 * (k & 3) + (k >> 2)];
+    wave_sync();
+    // pass 2 (sub-transforms of 16): butterfly j = l reads a[l + 64 r], twiddles W256^(r k) with
+    // k = l % 16, writes output k2 to 256 (l / 16) + k + 16 k2
+    const int g = lane >> 4, k = lane & 15;
+#pragma unroll
+    for (int r = 0; r < 16; ++r) v[r] = fx[lane + g + 68 * r];
+#pragma unroll
+    for (int r = 1; r < 16; ++r) v[r] = cmul<float>(v[r], w2[r - 1]);
+    dft16<float>(v);
+    wave_sync();
+#pragma unroll
+    for (int k2 = 0; k2 < 16; ++k2) fx[272 * g + k + 17 * k2] = v[4 * (k2 & 3) + (k2 >> 2)];
+    wave_sync();
+    // pass 3 (sub-transforms of 256): butterflies j = l + 64 q read a[j + 256 r], twiddles
+    // W1024^(r j), write output r to j + 256 r = l + 64 (q + 4 r)
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        float2 u0 = fx[lane + g + 68 * q], u1 = fx[lane + g + 68 * q + 272], u2 = fx[lane + g + 68 * q + 544],
+               u3 = fx[lane + g + 68 * q + 816];
+        u1 = cmul<float>(u1, w3[q][0]);
+        u2 = cmul<float>(u2, w3[q][1]);
+        u3 = cmul<float>(u3, w3[q][2]);
+        dft4<float>(u0, u1, u2, u3);
+        v[q] = u0;
+        v[q + 4] = u1;
+        v[q + 8] = u2;
+        v[q + 12] = u3;
+    }
+    wave_sync();
+}
+
+// LDS of the 1024-point spectra + pair-sum kernel (bytes).
+struct SpwLayout {
+    int slots, ncol1;
+    size_t off_fx, off_ring, off_pos, off_meta, off_slotk, total;
+};
+
+__host__ __device__ inline SpwLayout spw_layout(int Q, int R, int ncol, int jmax) {
+    SpwLayout L;
+    L.slots = R + 1;
+    L.ncol1 = ncol + 1;  // the last column of a ring row takes FFT outputs that are not output bins
+    size_t o = 0;
+    L.off_fx = o;
+    o += (1024 + 64) * sizeof(float2);
+    L.off_ring = o;
+    o += (size_t)L.slots * Q * L.ncol1 * sizeof(float2);
+    L.off_pos = o;
+    o += (size_t)jmax * 64 * sizeof(int16_t);
+    o = (o + 15) & ~(size_t)15;
+    L.off_meta = o;
+    o += (size_t)L.slots * Q * sizeof(float2);
+    L.off_slotk = o;
+    o += (size_t)L.slots * sizeof(int);
+    L.total = (o + 15) & ~(size_t)15;
+    return L;
+}
+
+// Spectra + pair sum for 1024-point segments (split precision, N_FFT a power of two, distinct
+// bins): one wavefront per (template, residue class p of the output bins, chunk [K0, K1) of
+// segments plus R halo segments before it).
+//   Spectra: for each segment K that some detector takes part in (the compacted list
+//   seg_any) and each detector with data there, the zero-padded segment is multiplied by
+//   W_N^(q s), q = p + P m0 (class p, its bins rotated so that the class's output indices
+//   m0 .. m0 + span - 1 land on FFT outputs 0 .. span - 1), transformed by fft1024_wave, and its
+//   class-p bins are written to a ring of R + 1 spectra in LDS.
+//   Pair sum: lane l owns the class's bins (columns) l, l + 64, ...  Each spectrum is rotated by
+//   Phi_in = exp(-2 pi i (kbar r_B mod N) / N) (eq. after phi-out-eq: absolute phase reference,
+//   so a pair's lag phase is the product of its two rotations), then the pairs whose later
+//   member is segment K enter: against the window sums G^a_Y, G^b_Y = sum over the last R
+//   segments L of hat a_YL F_YL, hat b_YL F_YL (cross pairs: Y != X; same-detector pairs:
+//   Y = X) and, across detectors, the same-time partners Y > X.  Each unordered pair of the pair
+//   set therefore enters once.  The window sums are kept in registers: a spectrum is added after
+//   its own step and subtracted when its segment falls R segments behind the next one.  Pair
+//   products of a step are summed in FP32, steps in FP64; one partial per (template, chunk, bin).
+// U: bins of a class per lane (class size <= 64 U); QM: detector bound of the register arrays.
+template <int U, int QM>
+__device__ __forceinline__ void spectra_wide_body(const BandDev &B, const float2 *__restrict__ y, double *part,
+                                                  int k_chunk, int n_chunks, int c, int p, int tb) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    const int Q = B.Q, n_k = B.n_k, R = B.R, N = B.n_fft, mask = B.nfft_mask;
+    const SpwLayout Ly = spw_layout(Q, R, B.wide_ncol, B.wide_jmax);
+    float2 *fx = reinterpret_cast<float2 *>(smem + Ly.off_fx);
+    float2 *ring = reinterpret_cast<float2 *>(smem + Ly.off_ring);
+    int16_t *opos = reinterpret_cast<int16_t *>(smem + Ly.off_pos);
+    float2 *meta = reinterpret_cast<float2 *>(smem + Ly.off_meta);
+    int *slotk = reinterpret_cast<int *>(smem + Ly.off_slotk);
+    const int lane = threadIdx.x;
+    const int slots = Ly.slots, ncol1 = Ly.ncol1, jmax = B.wide_jmax;
+    const bool cross = (B.pairs & 1) != 0, same = (B.pairs & 2) != 0;
+    const float2 *tw = B.tw32;
+    const int cs = B.class_start[p], n_p = B.class_start[p + 1] - cs;
+    const int m0 = B.cls_m0[p];
+
+    // FFT output m' = l + 64 J (J < jmax) of the rotated class: its ring column, or the spare one
+    for (int e = lane; e < jmax * 64; e += 64) opos[e] = (int16_t)(ncol1 - 1);
+    wave_sync();
+    for (int col = lane; col < n_p; col += 64) {
+        const int mm = (B.bin_m[B.col_bin[cs + col]] - m0) & 1023;
+        opos[mm] = (int16_t)col;
+    }
+    for (int e = lane; e < slots * Q * ncol1; e += 64) ring[e] = make_float2(0.f, 0.f);
+    // this lane's bins: kbar mod N (for Phi_in) and bin index
+    int kbc[U], binc[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+        const int col = lane + 64 * u;
+        binc[u] = col < n_p ? B.col_bin[cs + col] : -1;
+        kbc[u] = col < n_p ? B.bin_kb[binc[u]] : 0;
+    }
+    // pass twiddles and the class's input twiddles W_N^(q s), s = l + 64 r (N is a power of two)
+    const int st256 = N >> 8, st1024 = N >> 10;
+    float2 w2[15], w3[4][3], win[16];
+#pragma unroll
+    for (int r = 1; r < 16; ++r) w2[r - 1] = tw[(r * (lane & 15) * st256) & mask];
+#pragma unroll
+    for (int q = 0; q < 4; ++q)
+#pragma unroll
+        for (int r = 1; r < 4; ++r) w3[q][r - 1] = tw[(r * (lane + 64 * q) * st1024) & mask];
+    const int qrot = (p + B.P * m0) & mask;
+#pragma unroll
+    for (int r = 0; r < 16; ++r) win[r] = tw[(int)(((unsigned)qrot * (unsigned)(lane + 64 * r)) & (unsigned)mask)];
+
+    const int K0 = c * k_chunk;
+    const int K1 = min(B.n_seg, K0 + k_chunk);
+    const int Kh = max(0, K0 - R);
+    auto lower = [&](int key) {
+        int a = 0, b = B.n_seg_any;
+        while (a < b) {
+            const int m = (a + b) >> 1;
+            if (B.seg_any[m] < key) a = m + 1;
+            else b = m;
+        }
+        return a;
+    };
+    const int lo = lower(Kh), hi = lower(K1);
+    const int64_t nr = (int64_t)B.n_seg * n_k;
+
+    float2 Ga[QM][U], Gb[QM][U];
+    double acc[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+        acc[u] = 0.0;
+#pragma unroll
+        for (int X = 0; X < QM; ++X) Ga[X][u] = Gb[X][u] = make_float2(0.f, 0.f);
+    }
+    int head = 0, tail = 0, count = 0;
+    wave_sync();
+    for (int e = lo; e < hi; ++e) {
+        const int K = B.seg_any[e];
+        float wa[QM], wb[QM];
+#pragma unroll
+        for (int X = 0; X < QM; ++X) {
+            wa[X] = wb[X] = 0.f;
+            if (X >= Q) continue;
+            const int ew = X * B.n_seg + K;
+            if (B.seg_work[ew] < 0) continue;  // no data of detector X in segment K
+            const SegWeight sw = B.segw[ew];
+            wa[X] = (float)(sw.ahat * sw.scale);
+            wb[X] = (float)(sw.bhat * sw.scale);
+            const float2 *ys = y + ((size_t)tb * Q + X) * nr + (size_t)K * n_k;
+            float2 v[16];
+#pragma unroll
+            for (int r = 0; r < 16; ++r) {
+                const int sidx = lane + 64 * r;
+                const float2 xv = sidx < n_k ? ys[sidx] : make_float2(0.f, 0.f);
+                v[r] = cmul<float>(xv, win[r]);
+            }
+            fft1024_wave(v, fx, w2, w3, lane);
+            float2 *row = ring + ((size_t)head * Q + X) * ncol1;
+#pragma unroll
+            for (int J = 0; J < 16; ++J)
+                if (J < jmax) row[opos[lane + 64 * J]] = v[J];
+        }
+        if (lane == 0) {
+            slotk[head] = K;
+#pragma unroll
+            for (int X = 0; X < QM; ++X)
+                if (X < Q) meta[head * Q + X] = make_float2(wa[X], wb[X]);
+        }
+        wave_sync();
+        // Phi_in and the pairs whose later member is segment K
+        const unsigned rB = (unsigned)(((int64_t)K * n_k) & mask);
+        const bool count_it = K >= K0;
+        const float invN = 1.0f / (float)N;
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int col = lane + 64 * u;
+            if (U > 1 && 64 * u >= n_p) break;  // uniform: no lane has a bin in this round
+            const int cc = col < n_p ? col : ncol1 - 1;
+            const float ph = -(float)(((unsigned)kbc[u] * rB) & (unsigned)mask) * invN;  // revolutions
+            const float cph = __builtin_amdgcn_cosf(ph), sph = __builtin_amdgcn_sinf(ph);
+            float2 f[QM];
+#pragma unroll
+            for (int X = 0; X < QM; ++X) {
+                if (X >= Q) continue;
+                float2 *slotp = ring + ((size_t)head * Q + X) * ncol1 + cc;
+                const float2 g = *slotp;
+                f[X] = make_float2(g.x * cph - g.y * sph, g.x * sph + g.y * cph);
+                *slotp = f[X];
+            }
+            if (count_it) {
+                float st = 0.f;
+#pragma unroll
+                for (int X = 0; X < QM; ++X) {
+                    if (X >= Q || (wa[X] == 0.f && wb[X] == 0.f)) continue;
+                    float2 ha = make_float2(0.f, 0.f), hb = make_float2(0.f, 0.f);
+#pragma unroll
+                    for (int Y = 0; Y < QM; ++Y) {
+                        if (Y >= Q) continue;
+                        if ((Y != X) ? cross : same) {
+                            ha.x += Ga[Y][u].x; ha.y += Ga[Y][u].y;
+                            hb.x += Gb[Y][u].x; hb.y += Gb[Y][u].y;
+                        }
+                        if (cross && Y > X) {
+                            ha.x = fmaf(wa[Y], f[Y].x, ha.x); ha.y = fmaf(wa[Y], f[Y].y, ha.y);
+                            hb.x = fmaf(wb[Y], f[Y].x, hb.x); hb.y = fmaf(wb[Y], f[Y].y, hb.y);
+                        }
+                    }
+                    st = fmaf(wa[X], f[X].x * ha.x + f[X].y * ha.y, st);
+                    st = fmaf(wb[X], f[X].x * hb.x + f[X].y * hb.y, st);
+                }
+                acc[u] += (double)st;
+            }
+#pragma unroll
+            for (int X = 0; X < QM; ++X) {
+                if (X >= Q) continue;
+                Ga[X][u].x = fmaf(wa[X], f[X].x, Ga[X][u].x); Ga[X][u].y = fmaf(wa[X], f[X].y, Ga[X][u].y);
+                Gb[X][u].x = fmaf(wb[X], f[X].x, Gb[X][u].x); Gb[X][u].y = fmaf(wb[X], f[X].y, Gb[X][u].y);
+            }
+        }
+        head = head + 1 == slots ? 0 : head + 1;
+        ++count;
+        // spectra whose segment is more than R behind the next step's leave the window sums
+        if (e + 1 < hi) {
+            const int Kn = B.seg_any[e + 1];
+            while (count > 0) {
+                const int Kt = __builtin_amdgcn_readfirstlane(slotk[tail]);
+                if (Kt >= Kn - R) break;
+#pragma unroll
+                for (int X = 0; X < QM; ++X) {
+                    if (X >= Q) continue;
+                    const float2 wt = meta[tail * Q + X];
+                    if (wt.x == 0.f && wt.y == 0.f) continue;
+                    const float2 *rowt = ring + ((size_t)tail * Q + X) * ncol1;
+#pragma unroll
+                    for (int u = 0; u < U; ++u) {
+                        if (U > 1 && 64 * u >= n_p) break;
+                        const int col = lane + 64 * u;
+                        const float2 g = rowt[col < n_p ? col : ncol1 - 1];
+                        Ga[X][u].x = fmaf(-wt.x, g.x, Ga[X][u].x); Ga[X][u].y = fmaf(-wt.x, g.y, Ga[X][u].y);
+                        Gb[X][u].x = fmaf(-wt.y, g.x, Gb[X][u].x); Gb[X][u].y = fmaf(-wt.y, g.y, Gb[X][u].y);
+                    }
+                }
+                tail = tail + 1 == slots ? 0 : tail + 1;
+                --count;
+            }
+        }
+        wave_sync();
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u)
+        if (binc[u] >= 0) part[((size_t)tb * n_chunks + c) * B.n_f + binc[u]] = acc[u];
+}
+
 // The fused kernel keeps the activity bits of a step (S segments x Q detectors) in 64 bits.
 __host__ __device__ inline bool Q_ok(const BandDev &B) { return B.Q >= 1 && B.Q * 4 <= 64; }
 
@@ -1662,6 +1941,7 @@ __device__ __forceinline__ BandDev global_view(const BandDev &b, const void *bas
     g.zero256 = as_global(b.zero256, base);
     g.bin_col = as_global(b.bin_col, base);
     g.farrow = as_global(b.farrow, base);
+    g.cls_m0 = as_global(b.cls_m0, base);
     return g;
 }
 
@@ -1722,6 +2002,32 @@ k_spectra_pairs_m(const BandDev *__restrict__ bands, const WorkItem *__restrict_
     const BandDev B = global_view(bands[it.band], bands);
     const int l = blockIdx.x - it.first[kStSpectra], gx = it.gx[kStSpectra];
     spectra_pairs_body<NR, Z4>(B, y + it.y_off, part + it.part_off, it.k_chunk, it.n_chunks, l % gx, l / gx);
+}
+
+// Blocks of an item: n_tmpl x n_chunks groups of P workgroups (one per residue class).  The
+// dispatcher hands workgroups to the 8 XCDs in turn, so block l runs on XCD l mod 8: the P class
+// workgroups of one (template, chunk) group are given indices with equal l mod 8, which puts
+// them on one XCD, where they read the group's resampled series through that XCD's L2.
+template <int U, int QM>
+__global__ void __launch_bounds__(64)
+k_spectra_wide_m(const BandDev *__restrict__ bands, const WorkItem *__restrict__ items, int n_items,
+                 const float2 *__restrict__ y, double *__restrict__ part) {
+    const WorkItem &it = items[find_item(items, n_items, kStSpectra, blockIdx.x)];
+    const BandDev B = global_view(bands[it.band], bands);
+    const int l = blockIdx.x - it.first[kStSpectra];
+    const int P = B.P, G = it.n_tmpl * it.n_chunks;
+    const int full = (G >> 3) * 8 * P;
+    int g, p;
+    if (l < full) {
+        const int r = l >> 3;
+        p = r % P;
+        g = (r / P) * 8 + (l & 7);
+    } else {
+        g = (G >> 3) * 8 + (l - full) / P;
+        p = (l - full) % P;
+    }
+    spectra_wide_body<U, QM>(B, y + it.y_off, part + it.part_off, it.k_chunk, it.n_chunks, g % it.n_chunks, p,
+                             g / it.n_chunks);
 }
 
 template <typename T>
@@ -1904,6 +2210,16 @@ hipError_t launch_zero(void *p, size_t bytes, hipStream_t stream) {
 
 size_t spectra_pairs_lds(const BandDev &B) { return spair_layout(B.Q, B.n_f, B.R, B.n_fft).total; }
 
+size_t spectra_wide_lds(const BandDev &B) { return spw_layout(B.Q, B.R, B.wide_ncol, B.wide_jmax).total; }
+
+int spectra_wide_cols(const BandDev &B) { return B.wide_ncol <= 128 ? 2 : (B.wide_ncol <= 256 ? 4 : 8); }
+
+bool spectra_wide_ok(const BandDev &B, bool fp64, size_t limit) {
+    return !fp64 && B.n_s == 1024 && B.nfft_mask != 0 && B.bins_unique && B.Q >= 1 && B.Q <= 4 &&
+           B.wide_ncol <= 512 && B.wide_jmax >= 1 && B.wide_jmax <= 16 && B.cls_m0 != nullptr &&
+           spectra_wide_lds(B) <= limit;
+}
+
 int spectra_pairs_rounds(const BandDev &B) { return B.n_f <= 64 * 3 ? 3 : kSpairMaxRounds; }
 
 int spectra_threads(int n_s) { return n_s / 4 >= 256 ? 256 : (n_s / 4 < 64 ? 64 : n_s / 4); }
@@ -1994,6 +2310,26 @@ hipError_t launch_spectra_pairs_m(const BandDev *bands, const WorkItem *items, i
     if (blocks == 0) return hipSuccess;
     if (rounds == 3) launch_spectra_pairs_m_t<3>(bands, items, n_items, blocks, z4, lds, y, part, stream);
     else launch_spectra_pairs_m_t<kSpairMaxRounds>(bands, items, n_items, blocks, z4, lds, y, part, stream);
+    return hipGetLastError();
+}
+
+template <int U>
+static void launch_spectra_wide_u(const BandDev *bands, const WorkItem *items, int n_items, int blocks, int qm,
+                                  size_t lds, const void *y, double *part, hipStream_t stream) {
+    if (qm <= 2)
+        hipLaunchKernelGGL((k_spectra_wide_m<U, 2>), dim3(blocks), dim3(64), lds, stream, bands, items, n_items,
+                           (const float2 *)y, part);
+    else
+        hipLaunchKernelGGL((k_spectra_wide_m<U, 4>), dim3(blocks), dim3(64), lds, stream, bands, items, n_items,
+                           (const float2 *)y, part);
+}
+
+hipError_t launch_spectra_wide_m(const BandDev *bands, const WorkItem *items, int n_items, int blocks, int cols,
+                                 int qm, size_t lds, const void *y, double *part, hipStream_t stream) {
+    if (blocks == 0) return hipSuccess;
+    if (cols <= 2) launch_spectra_wide_u<2>(bands, items, n_items, blocks, qm, lds, y, part, stream);
+    else if (cols <= 4) launch_spectra_wide_u<4>(bands, items, n_items, blocks, qm, lds, y, part, stream);
+    else launch_spectra_wide_u<8>(bands, items, n_items, blocks, qm, lds, y, part, stream);
     return hipGetLastError();
 }
 

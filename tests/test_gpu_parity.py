@@ -216,6 +216,50 @@ def test_spectra_pairs_256_lagged(ccr, case):
     assert e64 < TOL64 and e32 < TOL32
 
 
+WIDE_1024 = {
+    # (detectors, max lag, pair kinds, chunk length): N_K = 731 (2000 s at 0.366 Hz), n_s = 1024
+    "q1_lag3_same": (1, 3, 2, 7),
+    "q2_lag4_both": (2, 4, 3, 7),
+    "q2_lag0_cross": (2, 0, 1, 256),
+    "q3_lag2_both": (3, 2, 3, 5),
+    "q4_lag1_both": (4, 1, 3, 256),
+}
+
+
+@pytest.mark.parametrize("case", sorted(WIDE_1024))
+def test_spectra_wide_1024(ccr, case):
+    """The 1024-point spectra + pair-sum kernel (segment spectra of one residue class in
+    registers and an LDS ring, window sums of the last R segments, Phi_in as an absolute
+    rotation): 1-4 detectors, lags 0-4, 30 % gaps (runs of empty segments longer than R),
+    chunks of 5-7 segments with their halo, classes of 86-155 bins.  FP64 (general path) and
+    split against the oracle (Sec. III.B.1 pairs, eq. final-formatted-rho)."""
+    q, R, pairs, kc = WIDE_1024[case]
+    cfg = small_config(q=q, n_seg=30, t_short=2000.0, f_min=400.0, f_band=0.06, max_lag=R, pairs=pairs,
+                       a_p_max=2.0, gap_fraction=0.3,
+                       templates=dict(a_p=(1.0, 2.0, 2), t_asc=(-200.0, 200.0, 2), period=[68023.70]),
+                       injections=[dict(f0=400.029, a_p=1.3, t_asc_off=0.0, period=68023.7, h0=0.2,
+                                        cosi=0.7, psi=0.4, phi0=2.0)])
+    ds = synth.make_dataset(cfg, sigma_wander=0.2)
+    ref = oracle.Oracle(ds).rho(ds.templates)
+    with ccr.Context(ds.sky, device=0) as ctx:
+        ctx.set_option("timing", 1)
+        ctx.set_option("k_chunk", kc)
+        bid = ctx.load(ds)
+        info = ctx.band_info(bid)
+        assert 512 < info["n_k"] <= 1024
+        r64 = ctx.compute_rho(bid, prec=ccr.PREC_FP64)
+        ctx.kernel_times(reset=True)
+        r32 = ctx.compute_rho(bid, prec=ccr.PREC_SPLIT, out_fp64=False)
+        kt = ctx.kernel_times(reset=True)
+        ctx.set_option("template_batch", 1)
+        r32b = ctx.compute_rho(bid, prec=ccr.PREC_SPLIT, out_fp64=False)
+    assert kt["spectra_wide"][1] > 0, kt  # the split call ran the 1024-point kernel
+    e64, e32 = rho_err(r64, ref), rho_err(r32, ref)
+    print(f"1024-point {case}: fp64 {e64:.2e} split {e32:.2e} max|rho| {np.abs(ref).max():.2f}")
+    assert e64 < TOL64 and e32 < TOL32
+    assert np.array_equal(r32, r32b)  # one template per launch: same kernel arithmetic
+
+
 def test_tiny_workload_full(ccr):
     """2 detectors, 2 days, T_short 360 s, 0.25 Hz at 100 Hz, 64 templates, same-time pairs."""
     ds = synth.make_dataset(synth.config("tiny"))
