@@ -109,7 +109,8 @@ struct ccr_ctx {
     int64_t opt_k_chunk = 0;
     int64_t opt_fused = 0;
     int64_t opt_timing = 0;
-    DevBuf ws_y, ws_F, ws_part, ws_out, ws_coef;
+    DevBuf ws_arena;                // workspace of the batched path: one arena, laid out per launch round
+    DevBuf ws_part, ws_out, ws_coef;  // fused path: chunk partials, time-base coefficients; host outputs
     int64_t opt_graph = 0, opt_autotune = 0, opt_items_per_launch = 0;
     int64_t opt_farrow = 1;  // split-precision resampling in Farrow form where a band has the table
     int64_t opt_farrow_stage = 1;  // Farrow kernel: stage the table in LDS (0: global reads, for tests)
@@ -990,19 +991,30 @@ struct Variant {
     }
 };
 
+// Workspace of one launch round, laid out in the arena: time-base coefficients, resampled series
+// (with a tail pad of 256 complex FP64 samples: the spectra kernels read whole 256-sample rows
+// of the last segment), segment spectra (general path), chunk partials; 256-byte aligned.
+constexpr size_t kArenaAlign = 256;
+constexpr size_t kYTailPad = 256 * sizeof(double2);
+inline size_t arena_al(size_t v) { return (v + kArenaAlign - 1) & ~(kArenaAlign - 1); }
+inline size_t arena_bytes_of(size_t coef, size_t y, size_t F, size_t part) {
+    return arena_al(coef) + arena_al(y + kYTailPad) + arena_al(F) + arena_al(part);
+}
+
 struct Round {
     int i0 = 0, n = 0;  // items [i0, i0 + n) of the call's item table
     Variant v;
     size_t lds = 0;     // dynamic LDS of the spectra + pair-sum kernel
     int64_t blocks[kStages] = {0, 0, 0, 0, 0};
     size_t y_bytes = 0, F_bytes = 0, part_bytes = 0, coef_bytes = 0;
+    size_t arena() const { return arena_bytes_of(coef_bytes, y_bytes, F_bytes, part_bytes); }
 };
 
 struct CallPlan {
     std::vector<BandDev> bands;  // by position in the call
     std::vector<WorkItem> items;
     std::vector<Round> rounds;
-    size_t y_bytes = 0, F_bytes = 0, part_bytes = 0, coef_bytes = 0;  // largest round
+    size_t arena_bytes = 0;       // largest round's workspace (rounds run in turn and share the arena)
     std::vector<size_t> out_off;  // host outputs: byte offset of each band's rho in ws_out
     size_t out_bytes = 0;
 };
@@ -1066,7 +1078,7 @@ ccr_status build_plan(ccr_ctx *c, bool fp64, int n_bands, const int *band_ids, v
         // 3/4 of the free device memory plus the workspace the context already holds
         size_t fr = 0, tot = 0;
         HIP_OK(c, hipMemGetInfo(&fr, &tot));
-        const size_t held = c->ws_y.bytes + c->ws_F.bytes + c->ws_part.bytes + c->ws_coef.bytes;
+        const size_t held = c->ws_arena.bytes + c->ws_part.bytes + c->ws_coef.bytes;
         c->auto_budget = std::max<size_t>((fr + held) / 4 * 3, (size_t)64 << 20);
     }
     const size_t budget = budget_override > 0          ? budget_override
@@ -1154,16 +1166,13 @@ ccr_status build_plan(ccr_ctx *c, bool fp64, int n_bands, const int *band_ids, v
         auto close = [&]() {
             if (r.n == 0) return;
             cp.rounds.push_back(r);
-            cp.y_bytes = std::max(cp.y_bytes, r.y_bytes);
-            cp.F_bytes = std::max(cp.F_bytes, r.F_bytes);
-            cp.part_bytes = std::max(cp.part_bytes, r.part_bytes);
-            cp.coef_bytes = std::max(cp.coef_bytes, r.coef_bytes);
+            cp.arena_bytes = std::max(cp.arena_bytes, r.arena());
         };
         r.v = v;
         r.i0 = (int)cp.items.size();
         for (const Pending &q : pend) {
             if (!(q.v == v)) continue;
-            bool full = r.y_bytes + r.F_bytes + r.part_bytes + r.coef_bytes + q.y + q.F + q.part + q.coef > budget;
+            bool full = arena_bytes_of(r.coef_bytes + q.coef, r.y_bytes + q.y, r.F_bytes + q.F, r.part_bytes + q.part) > budget;
             for (int st = 0; st < kStages; ++st) full = full || r.blocks[st] + q.blk[st] > stage_max_blocks(v, st);
             if (c->opt_items_per_launch > 0 && r.n >= c->opt_items_per_launch) full = true;
             if (r.n > 0 && full) {
@@ -1194,30 +1203,22 @@ ccr_status build_plan(ccr_ctx *c, bool fp64, int n_bands, const int *band_ids, v
     return CCR_OK;
 }
 
+// The arena holds the largest round of the plan (each round fits the budget on its own); the
+// fused path's buffers are released when the arena has to grow, so the two never add up.
 ccr_status ensure_workspace(ccr_ctx *c, const CallPlan &cp) {
-    // 256 samples of tail pad: the spectra kernels read whole 256-sample rows of the last segment
-    DevBuf *buf[4] = {&c->ws_y, &c->ws_F, &c->ws_part, &c->ws_coef};
-    const size_t need[4] = {cp.y_bytes + 256 * sizeof(double2), std::max<size_t>(cp.F_bytes, 16),
-                            std::max<size_t>(cp.part_bytes, 16), std::max<size_t>(cp.coef_bytes, 16)};
-    // Buffers that grow are re-allocated; the others are kept.  When what is kept plus what
-    // grows exceeds the budget (a call of another precision or band mix, whose split between
-    // the buffers differs), every buffer is released first and allocated at its exact size,
-    // so the workspace never holds more than the budget.
-    size_t keep = 0, add = 0;
-    for (int i = 0; i < 4; ++i) {
-        if (need[i] > buf[i]->bytes || !buf[i]->p) add += need[i];
-        else keep += buf[i]->bytes;
-    }
-    const size_t budget = c->opt_workspace_mb > 0 ? (size_t)c->opt_workspace_mb << 20 : c->auto_budget;
-    if (add > 0 && keep + add > budget + (256 << 10)) {
+    if (cp.arena_bytes > c->ws_arena.bytes && (c->ws_part.p || c->ws_coef.p)) {
         HIP_OK(c, hipDeviceSynchronize());
-        for (DevBuf *b : buf) b->release();
+        c->ws_part.release();
+        c->ws_coef.release();
         c->gen++;
     }
-    ccr_status st;
-    for (int i = 0; i < 4; ++i)
-        if ((st = grow(c, *buf[i], need[i]))) return st;
-    return CCR_OK;
+    if (cp.arena_bytes > c->ws_arena.bytes && c->ws_arena.p) {
+        // free the old arena before allocating the larger one
+        HIP_OK(c, hipDeviceSynchronize());
+        c->ws_arena.release();
+        c->gen++;
+    }
+    return grow(c, c->ws_arena, std::max<size_t>(cp.arena_bytes, kArenaAlign));
 }
 
 // Bytes of the device table (band descriptors, then work items, 256-byte aligned).
@@ -1239,23 +1240,30 @@ struct Workspace {
     double *part = nullptr;
 };
 
-Workspace ctx_workspace(ccr_ctx *c) {
+// A round's buffers in the arena (layout of arena_bytes_of).
+Workspace round_workspace(void *arena, const Round &r) {
+    char *a = static_cast<char *>(arena);
     Workspace w;
-    w.coef = c->ws_coef.as<double>();
-    w.y = c->ws_y.p;
-    w.F = c->ws_F.p;
-    w.part = c->ws_part.as<double>();
+    w.coef = reinterpret_cast<double *>(a);
+    a += arena_al(r.coef_bytes);
+    w.y = a;
+    a += arena_al(r.y_bytes + kYTailPad);
+    w.F = a;
+    a += arena_al(r.F_bytes);
+    w.part = reinterpret_cast<double *>(a);
     return w;
 }
 
-// Queue the rounds [r0, r1) of a plan on `s` (tables already on the device).
+// Queue the rounds [r0, r1) of a plan on `s` (tables already on the device; each round's
+// workspace at the start of `arena`).
 ccr_status run_rounds(ccr_ctx *c, const CallPlan &cp, size_t r0, size_t r1, bool fp64, const void *d_tables,
-                      size_t items_off, hipStream_t s, bool timing, const Workspace &ws) {
+                      size_t items_off, hipStream_t s, bool timing, void *arena) {
     const BandDev *db = static_cast<const BandDev *>(d_tables);
     const WorkItem *ditems = reinterpret_cast<const WorkItem *>(static_cast<const char *>(d_tables) + items_off);
-    double *coef = ws.coef, *part = ws.part;
     for (size_t ri = r0; ri < r1; ++ri) {
         const Round &r = cp.rounds[ri];
+        const Workspace ws = round_workspace(arena, r);
+        double *coef = ws.coef, *part = ws.part;
         const WorkItem *di = ditems + r.i0;
         {
             LaunchTimer lt(c, 5, s, timing);
@@ -1350,7 +1358,7 @@ ccr_status choose_params(ccr_ctx *c, ccr_precision prec, int n_bands, const int 
         for (int rep = 0; rep < 2 && !st; ++rep) {
             if (rep == 1 && hipEventRecord(e0, s) != hipSuccess) st = fail(c, CCR_EDEVICE, "event record failed");
             if (!st) st = run_rounds(c, cp, 0, std::min<size_t>(1, cp.rounds.size()), fp64, c->d_tables.p, items_off, s, false,
-                                     ctx_workspace(c));
+                                     c->ws_arena.p);
         }
         if (st) break;
         HIP_OK(c, hipEventRecord(e1, s));
@@ -1411,7 +1419,7 @@ ccr_status compute_batched(ccr_ctx *c, ccr_precision prec, int n_bands, const in
         HIP_OK(c, hipMalloc(&g->tables, bytes));
         HIP_OK(c, hipMemcpy(g->tables, host.data(), bytes, hipMemcpyHostToDevice));
         HIP_OK(c, hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal));
-        st = run_rounds(c, cp, 0, cp.rounds.size(), fp64, g->tables, items_off, c->stream, false, ctx_workspace(c));
+        st = run_rounds(c, cp, 0, cp.rounds.size(), fp64, g->tables, items_off, c->stream, false, c->ws_arena.p);
         hipGraph_t gr = nullptr;
         const hipError_t ec = hipStreamEndCapture(c->stream, &gr);
         if (st) {
@@ -1433,7 +1441,7 @@ ccr_status compute_batched(ccr_ctx *c, ccr_precision prec, int n_bands, const in
     }
     size_t items_off = 0;
     if ((st = upload_tables(c, cp, s, &items_off))) return st;
-    if ((st = run_rounds(c, cp, 0, cp.rounds.size(), fp64, c->d_tables.p, items_off, s, true, ctx_workspace(c))))
+    if ((st = run_rounds(c, cp, 0, cp.rounds.size(), fp64, c->d_tables.p, items_off, s, true, c->ws_arena.p)))
         return st;
     if (!out_on_device) {
         for (int bi = 0; bi < n_bands; ++bi) {
@@ -1494,8 +1502,7 @@ void ccr_destroy(ccr_ctx *c) {
     (void)hipDeviceSynchronize();
     collect_times(c);
     c->bands.clear();
-    c->ws_y.release();
-    c->ws_F.release();
+    c->ws_arena.release();
     c->ws_part.release();
     c->ws_out.release();
     c->ws_coef.release();
