@@ -225,6 +225,27 @@ ccr_status ccr_get_band_info(ccr_ctx *ctx, int band_id, ccr_band_info *info, dou
 ccr_status ccr_compute_rho(ccr_ctx *ctx, ccr_precision prec, int n_bands, const int *band_ids,
                            void *const *rho_out, int out_on_device, int out_fp64, void *hip_stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph capture, tight serving
+ * loops, harnesses that forbid hipMalloc): ccr_compute_rho with device outputs whose workspace
+ * (band and work-item tables, time-base coefficients, resampled series, spectra, chunk
+ * partials) lives in a fixed device array of 256 MiB per device instead of the context's
+ * workspace.  The call makes no hipMalloc, hipFree or other allocating call; it queues a table
+ * copy and the kernels on hip_stream (NULL: the context's stream) and returns.
+ *   - Every band must be prepared beforehand (set-up that allocates): after its data, weights
+ *     and templates are set, call ccr_get_band_info (or ccr_compute_rho) once; otherwise
+ *     CCR_ESTATE.
+ *   - rho_out[b]: device memory, n_templates * n_f values (double if out_fp64, else float), valid
+ *     until the work completes.  Templates are processed in as many launch rounds as the fixed
+ *     array requires; a band whose single-template workspace exceeds it (e.g. 240 days at
+ *     T_short 1440 s in FP64) gives CCR_ERANGE, as do band and work-item tables over 1 MiB.
+ *   - Options "template_batch" and "k_chunk" apply; "graph", "autotune" and "timing" do not.
+ *   - The array is shared by every call on the device and keeps the last call's contents; no
+ *     part of it needs to start at zero.  Calls that overlap on one device (different
+ *     contexts or streams) race: order them on one stream or synchronise between them.
+ * Results equal ccr_compute_rho's for the same options. */
+ccr_status ccr_compute_rho_noalloc(ccr_ctx *ctx, ccr_precision prec, int n_bands, const int *band_ids,
+                                   void *const *rho_out, int out_fp64, void *hip_stream);
+
 /* Wait for all work queued by this context. */
 ccr_status ccr_sync(ccr_ctx *ctx);
 

@@ -73,6 +73,8 @@ SIGNATURES = {
     "ccr_get_band_info": ([_vp, ctypes.c_int, ctypes.POINTER(BandInfo), _dp], ctypes.c_int),
     "ccr_compute_rho": ([_vp, ctypes.c_int, ctypes.c_int, ctypes.POINTER(ctypes.c_int), ctypes.POINTER(_vp),
                          ctypes.c_int, ctypes.c_int, _vp], ctypes.c_int),
+    "ccr_compute_rho_noalloc": ([_vp, ctypes.c_int, ctypes.c_int, ctypes.POINTER(ctypes.c_int), ctypes.POINTER(_vp),
+                                 ctypes.c_int, _vp], ctypes.c_int),
     "ccr_sync": ([_vp], ctypes.c_int),
     "ccr_kernel_time": ([_vp, ctypes.c_int, _dp, ctypes.POINTER(ctypes.c_int64)], ctypes.c_int),
     "ccr_reset_kernel_times": ([_vp], ctypes.c_int),
@@ -207,6 +209,15 @@ class Context:
         self._check(self.L.ccr_compute_rho(self.h, int(prec), len(ids), idarr, ptrs, 1, int(bool(out_fp64)),
                                            None if stream is None else _vp(int(stream))))
         return None
+
+    def compute_rho_noalloc(self, band_ids, outputs, prec=PREC_FP64, out_fp64=True, stream=None):
+        """ccr_compute_rho_noalloc: rho into device buffers `outputs` (addresses), workspace in the
+        library's fixed device array; the bands must be prepared (band_info after loading)."""
+        ids = [band_ids] if isinstance(band_ids, int) else list(band_ids)
+        idarr = (ctypes.c_int * len(ids))(*ids)
+        ptrs = (_vp * len(ids))(*[int(p) for p in outputs])
+        self._check(self.L.ccr_compute_rho_noalloc(self.h, int(prec), len(ids), idarr, ptrs, int(bool(out_fp64)),
+                                                   None if stream is None else _vp(int(stream))))
 
     def sync(self):
         self._check(self.L.ccr_sync(self.h))

@@ -138,6 +138,10 @@ struct ccr_ctx {
     std::vector<Timed> timed;
     double kt_ms[8] = {0, 0, 0, 0, 0, 0, 0, 0};
     int64_t kt_n[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+    // no-allocation entry point: host staging of its band and work-item tables (fixed size,
+    // allocated with the context) and the event after which the staging may be rewritten
+    std::vector<char> na_host;
+    hipEvent_t na_copied = nullptr;
 };
 
 // A compute call captured as a HIP graph: replayed while the call's arguments and the
@@ -913,6 +917,8 @@ void collect_times(ccr_ctx *c) {
 
 
 constexpr size_t kMaxLds = 65536;
+// host staging (and scratch region) of the no-allocation entry point's tables
+constexpr size_t kNoAllocTableBytes = (size_t)1 << 20;
 
 ccr_status grow(ccr_ctx *c, DevBuf &b, size_t bytes);
 
@@ -1488,6 +1494,21 @@ ccr_status ccr_create(ccr_ctx **out, int hip_device, const ccr_sky *sky) {
         delete c;
         return CCR_EDEVICE;
     }
+    // set-up of the no-allocation entry point: the device address of the fixed scratch on this
+    // device (looked up once per device), its host staging and event
+    if (scratch_init(hip_device) != hipSuccess || hipEventCreateWithFlags(&c->na_copied, hipEventDisableTiming) != hipSuccess) {
+        (void)hipStreamDestroy(c->stream);
+        delete c;
+        return CCR_EDEVICE;
+    }
+    try {
+        c->na_host.assign(kNoAllocTableBytes, 0);
+    } catch (const std::bad_alloc &) {
+        (void)hipEventDestroy(c->na_copied);
+        (void)hipStreamDestroy(c->stream);
+        delete c;
+        return CCR_ENOMEM;
+    }
     *out = c;
     return CCR_OK;
 }
@@ -1510,6 +1531,7 @@ void ccr_destroy(ccr_ctx *c) {
     c->d_tables.release();
     if (c->h_tables) (void)hipHostFree(c->h_tables);
     if (c->tables_copied) (void)hipEventDestroy(c->tables_copied);
+    if (c->na_copied) (void)hipEventDestroy(c->na_copied);
     if (c->stream) (void)hipStreamDestroy(c->stream);
     delete c;
 }
@@ -1708,7 +1730,8 @@ ccr_status ccr_get_band_info(ccr_ctx *c, int band_id, ccr_band_info *info, doubl
     Band *B = get_band(c, band_id);
     if (!B) return fail(c, CCR_EINVAL, "bad band id %d", band_id);
     if (c->device >= 0) HIP_OK(c, hipSetDevice(c->device));
-    ccr_status st = prepare(c, *B);
+    // with templates set, the band is prepared completely (device tables and template table)
+    ccr_status st = B->n_tmpl > 0 && c->device >= 0 ? ensure_ready(c, *B) : prepare(c, *B);
     if (st) return st;
     const Plan &pl = B->plan;
     std::memset(info, 0, sizeof *info);
@@ -1771,6 +1794,54 @@ ccr_status ccr_compute_rho(ccr_ctx *c, ccr_precision prec, int n_bands, const in
         return compute_batched(c, prec, (int)rest.size(), rest.data(), rest_out.data(), out_on_device, out_fp64, s);
     }
     return compute_batched(c, prec, n_bands, band_ids, rho_out, out_on_device, out_fp64, s);
+}
+
+ccr_status ccr_compute_rho_noalloc(ccr_ctx *c, ccr_precision prec, int n_bands, const int *band_ids,
+                                   void *const *rho_out, int out_fp64, void *hip_stream) {
+    if (!c) return CCR_EINVAL;
+    c->err.clear();
+    if (n_bands < 1 || !band_ids || !rho_out) return fail(c, CCR_EINVAL, "no bands or outputs");
+    if (prec != CCR_PREC_FP64 && prec != CCR_PREC_SPLIT) return fail(c, CCR_EINVAL, "bad precision");
+    if (c->device < 0) return fail(c, CCR_EDEVICE, "host-only context");
+    HIP_OK(c, hipSetDevice(c->device));
+    void *scr = scratch_device_ptr(c->device);
+    if (!scr) return fail(c, CCR_EDEVICE, "no scratch address on device %d", c->device);
+    for (int bi = 0; bi < n_bands; ++bi) {
+        Band *B = get_band(c, band_ids[bi]);
+        if (!B) return fail(c, CCR_EINVAL, "bad band id %d", band_ids[bi]);
+        if (!rho_out[bi]) return fail(c, CCR_EINVAL, "null output for band %d", band_ids[bi]);
+        // preparing a band allocates its device tables: that is set-up, done by
+        // ccr_get_band_info (or ccr_compute_rho) after data, weights and templates are set
+        if (!B->prepared || B->n_tmpl == 0 || B->tmpl.empty())
+            return fail(c, CCR_ESTATE, "band %d is not prepared: call ccr_get_band_info after setting its data, "
+                                       "weights and templates", band_ids[bi]);
+    }
+    hipStream_t s = hip_stream ? (hipStream_t)hip_stream : c->stream;
+    const bool fp64 = prec == CCR_PREC_FP64;
+    // the scratch holds the band and work-item tables, then the workspace of the largest round
+    const size_t tables_cap = arena_al(kNoAllocTableBytes);
+    const size_t budget = kScratchBytes - tables_cap;
+    BatchParams bp;
+    bp.k_chunk = c->opt_k_chunk;
+    bp.template_batch = c->opt_template_batch;
+    CallPlan cp;
+    ccr_status st = build_plan(c, fp64, n_bands, band_ids, rho_out, 1, out_fp64, bp, cp, budget);
+    if (st) return st;
+    if (cp.arena_bytes > budget)
+        return fail(c, CCR_ERANGE, "one template's workspace (%zu MiB) exceeds the fixed scratch of %zu MiB",
+                    cp.arena_bytes >> 20, budget >> 20);
+    size_t items_off = 0;
+    const size_t tbytes = tables_bytes(cp, &items_off);
+    if (tbytes > kNoAllocTableBytes)
+        return fail(c, CCR_ERANGE, "band and work-item tables (%zu bytes) exceed the fixed %zu", tbytes,
+                    (size_t)kNoAllocTableBytes);
+    char *base = static_cast<char *>(scr);
+    // the previous call's table copy has finished reading the staging before it is rewritten
+    HIP_OK(c, hipEventSynchronize(c->na_copied));
+    fill_tables(cp, c->na_host.data(), items_off);
+    HIP_OK(c, hipMemcpyAsync(base, c->na_host.data(), tbytes, hipMemcpyHostToDevice, s));
+    HIP_OK(c, hipEventRecord(c->na_copied, s));
+    return run_rounds(c, cp, 0, cp.rounds.size(), fp64, base, items_off, s, false, base + tables_cap);
 }
 
 ccr_status ccr_kernel_time(ccr_ctx *c, int kernel, double *ms, int64_t *launches) {

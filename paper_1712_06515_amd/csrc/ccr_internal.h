@@ -205,6 +205,15 @@ hipError_t launch_pairs_m(const BandDev *bands, const WorkItem *items, int n_ite
 hipError_t launch_finish_m(const BandDev *bands, const WorkItem *items, int n_items, int blocks, const double *part,
                            hipStream_t stream);
 hipError_t launch_zero(void *p, size_t bytes, hipStream_t stream);
+
+// Fixed device scratch of the no-allocation entry point (a file-scope device array of
+// kScratchBytes per device).  scratch_init(device) looks up the array's device address on
+// `device` once (hipGetSymbolAddress with that device current) and keeps it; scratch_device_ptr
+// returns it (null before scratch_init succeeded).
+constexpr size_t kScratchBytes = (size_t)256 << 20;
+constexpr int kScratchMaxDevices = 64;
+hipError_t scratch_init(int device);
+void *scratch_device_ptr(int device);
 // eta and the heterodyne phase of every sample of active segments [k0, k0 + n) of one detector
 // (one template, coefficients from launch_timebase): eta[(K - k0) n_k + s], psi likewise.
 hipError_t launch_time_samples(const BandDev &B, const double *coef, int det, int k0, int n, double *eta,

@@ -10,6 +10,8 @@
 //   k_finish    sum of chunk partials and the sqrt(2) / N factor.
 #include <hip/hip_runtime.h>
 
+#include <mutex>
+
 #include <climits>
 
 #include "ccr_internal.h"
@@ -2376,6 +2378,40 @@ hipError_t launch_finish_m(const BandDev *bands, const WorkItem *items, int n_it
     if (blocks == 0) return hipSuccess;
     hipLaunchKernelGGL(k_finish_m, dim3(blocks), dim3(kFinishThreads), 0, stream, bands, items, n_items, part);
     return hipGetLastError();
+}
+
+// ------------------------------------------------------------------ fixed scratch
+
+// Workspace of ccr_compute_rho_noalloc: a file-scope device array, so that the entry point
+// allocates nothing.  Each device the library runs on holds its own copy (kScratchBytes) until
+// the process ends.  In host code `scratch` is only a stand-in for the symbol: its device
+// address comes from hipGetSymbolAddress, once per device, and only that address is used.
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+
+namespace {
+std::mutex g_scratch_mu;
+void *g_scratch_ptr[kScratchMaxDevices] = {};
+}  // namespace
+
+hipError_t scratch_init(int device) {
+    if (device < 0 || device >= kScratchMaxDevices) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (g_scratch_ptr[device]) return hipSuccess;
+    int cur = -1;
+    hipError_t e = hipGetDevice(&cur);
+    if (e != hipSuccess) return e;
+    if (cur != device && (e = hipSetDevice(device)) != hipSuccess) return e;
+    void *ptr = nullptr;
+    e = hipGetSymbolAddress((void **)&ptr, HIP_SYMBOL(scratch));
+    if (e == hipSuccess) g_scratch_ptr[device] = ptr;
+    if (cur != device) (void)hipSetDevice(cur);
+    return e;
+}
+
+void *scratch_device_ptr(int device) {
+    if (device < 0 || device >= kScratchMaxDevices) return nullptr;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    return g_scratch_ptr[device];
 }
 
 }  // namespace ccr
