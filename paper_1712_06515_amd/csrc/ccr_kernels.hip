@@ -1213,6 +1213,14 @@ __device__ __forceinline__ void spectra_pairs_body(const BandDev &B, const float
 
 // ------------------------------------------------------------------ spectra + pair sum, 1024-point segments
 
+// Load of a table entry that is the same for every lane (uniform index into memory the kernel
+// does not write), through the constant address space: a scalar load, whose wait does not wait
+// for the wavefront's outstanding vector loads.
+template <typename T> __device__ __forceinline__ T ld_uniform(const T *p, int i) {
+    i = __builtin_amdgcn_readfirstlane(i);
+    return ((const __attribute__((address_space(4))) T *)p)[i];
+}
+
 // 1024-point forward FFT held by one wavefront: on entry lane l holds x[l + 64 r] in v[r]
 // (r < 16), on return X[l + 64 J] in v[J].  Three self-sorting (Stockham) passes of radix 16,
 // 16 and 4 run in registers; between passes the values go through `fx` (1024 complex, index i
@@ -1257,6 +1265,11 @@ __device__ __forceinline__ void fft1024_wave(float2 *v, float2 *fx, const float2
     wave_sync();
 }
 
+// Workgroup of the 1024-point spectra + pair-sum kernel: kSpwWaves wavefronts share one spectrum
+// ring; wavefront w transforms the detectors X = w, w + kSpwWaves, ... and sums the pairs of the
+// bins (ring columns) w 64 + l + 128 u.
+constexpr int kSpwWaves = 2;
+
 // LDS of the 1024-point spectra + pair-sum kernel (bytes).
 struct SpwLayout {
     int slots, ncol1;
@@ -1268,8 +1281,8 @@ __host__ __device__ inline SpwLayout spw_layout(int Q, int R, int ncol, int jmax
     L.slots = R + 1;
     L.ncol1 = ncol + 1;  // the last column of a ring row takes FFT outputs that are not output bins
     size_t o = 0;
-    L.off_fx = o;
-    o += (1024 + 64) * sizeof(float2);
+    L.off_fx = o;  // one FFT exchange buffer per wavefront
+    o += (size_t)kSpwWaves * (1024 + 64) * sizeof(float2);
     L.off_ring = o;
     o += (size_t)L.slots * Q * L.ncol1 * sizeof(float2);
     L.off_pos = o;
@@ -1284,35 +1297,39 @@ __host__ __device__ inline SpwLayout spw_layout(int Q, int R, int ncol, int jmax
 }
 
 // Spectra + pair sum for 1024-point segments (split precision, N_FFT a power of two, distinct
-// bins): one wavefront per (template, residue class p of the output bins, chunk [K0, K1) of
-// segments plus R halo segments before it).
+// bins): one workgroup of kSpwWaves wavefronts per (template, residue class p of the output
+// bins, chunk [K0, K1) of segments plus R halo segments before it).
 //   Spectra: for each segment K that some detector takes part in (the compacted list
 //   seg_any) and each detector with data there, the zero-padded segment is multiplied by
 //   W_N^(q s), q = p + P m0 (class p, its bins rotated so that the class's output indices
 //   m0 .. m0 + span - 1 land on FFT outputs 0 .. span - 1), transformed by fft1024_wave, and its
-//   class-p bins are written to a ring of R + 1 spectra in LDS.
-//   Pair sum: lane l owns the class's bins (columns) l, l + 64, ...  Each spectrum is rotated by
-//   Phi_in = exp(-2 pi i (kbar r_B mod N) / N) (eq. after phi-out-eq: absolute phase reference,
-//   so a pair's lag phase is the product of its two rotations), then the pairs whose later
-//   member is segment K enter: against the window sums G^a_Y, G^b_Y = sum over the last R
-//   segments L of hat a_YL F_YL, hat b_YL F_YL (cross pairs: Y != X; same-detector pairs:
-//   Y = X) and, across detectors, the same-time partners Y > X.  Each unordered pair of the pair
-//   set therefore enters once.  The window sums are kept in registers: a spectrum is added after
-//   its own step and subtracted when its segment falls R segments behind the next one.  Pair
-//   products of a step are summed in FP32, steps in FP64; one partial per (template, chunk, bin).
-// U: bins of a class per lane (class size <= 64 U); QM: detector bound of the register arrays.
+//   class-p bins are written to a ring of R + 1 spectra in LDS.  Each wavefront loads the input
+//   of its next transform while it computes the current one.
+//   Pair sum: each spectrum is rotated by Phi_in = exp(-2 pi i (kbar r_B mod N) / N) (the phase
+//   reference after eq. phi-out-eq, absolute, so a pair's lag phase is the product of its two
+//   rotations), then the pairs whose later member is segment K enter: against the window sums
+//   G^a_Y, G^b_Y = sum over the last R segments L of hat a_YL F_YL, hat b_YL F_YL (cross pairs:
+//   Y != X; same-detector pairs: Y = X) and, across detectors, the same-time partners Y > X.
+//   Each unordered pair of the pair set therefore enters once.  The window sums are kept in
+//   registers: a spectrum is added after its own step and subtracted when its segment falls R
+//   segments behind the next one.  Pair products of a step are summed in FP32, steps in FP64;
+//   one partial per (template, chunk, bin).  Two barriers a step: after the transforms (the ring
+//   holds the step's spectra) and after the pair sums (a ring slot is free again).
+// U: bins of a class per lane (class size <= 128 U); QM: detector bound of the register arrays.
 template <int U, int QM>
 __device__ __forceinline__ void spectra_wide_body(const BandDev &B, const float2 *__restrict__ y, double *part,
                                                   int k_chunk, int n_chunks, int c, int p, int tb) {
     extern __shared__ __align__(16) unsigned char smem[];
     const int Q = B.Q, n_k = B.n_k, R = B.R, N = B.n_fft, mask = B.nfft_mask;
     const SpwLayout Ly = spw_layout(Q, R, B.wide_ncol, B.wide_jmax);
-    float2 *fx = reinterpret_cast<float2 *>(smem + Ly.off_fx);
+    // the wavefront index, uniform within the wavefront (readfirstlane makes that known to the
+    // compiler, so that per-wavefront addresses and buffer descriptors stay in scalar registers)
+    const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
+    float2 *fx = reinterpret_cast<float2 *>(smem + Ly.off_fx) + wv * (1024 + 64);
     float2 *ring = reinterpret_cast<float2 *>(smem + Ly.off_ring);
     int16_t *opos = reinterpret_cast<int16_t *>(smem + Ly.off_pos);
     float2 *meta = reinterpret_cast<float2 *>(smem + Ly.off_meta);
     int *slotk = reinterpret_cast<int *>(smem + Ly.off_slotk);
-    const int lane = threadIdx.x;
     const int slots = Ly.slots, ncol1 = Ly.ncol1, jmax = B.wide_jmax;
     const bool cross = (B.pairs & 1) != 0, same = (B.pairs & 2) != 0;
     const float2 *tw = B.tw32;
@@ -1320,18 +1337,28 @@ __device__ __forceinline__ void spectra_wide_body(const BandDev &B, const float2
     const int m0 = B.cls_m0[p];
 
     // FFT output m' = l + 64 J (J < jmax) of the rotated class: its ring column, or the spare one
-    for (int e = lane; e < jmax * 64; e += 64) opos[e] = (int16_t)(ncol1 - 1);
-    wave_sync();
-    for (int col = lane; col < n_p; col += 64) {
+    for (int e = threadIdx.x; e < jmax * 64; e += 64 * kSpwWaves) opos[e] = (int16_t)(ncol1 - 1);
+    for (int e = threadIdx.x; e < slots * Q * ncol1; e += 64 * kSpwWaves) ring[e] = make_float2(0.f, 0.f);
+    __syncthreads();
+    for (int col = threadIdx.x; col < n_p; col += 64 * kSpwWaves) {
         const int mm = (B.bin_m[B.col_bin[cs + col]] - m0) & 1023;
         opos[mm] = (int16_t)col;
     }
-    for (int e = lane; e < slots * Q * ncol1; e += 64) ring[e] = make_float2(0.f, 0.f);
+    __syncthreads();
+    // ring column of this lane's FFT outputs l + 64 J (J < jmax), two 16-bit columns a register
+    unsigned cpos[8];
+#pragma unroll
+    for (int h = 0; h < 8; ++h) {
+        const int J0 = 2 * h, J1 = 2 * h + 1;
+        const unsigned c0 = J0 < jmax ? (unsigned)(uint16_t)opos[lane + 64 * J0] : (unsigned)(ncol1 - 1);
+        const unsigned c1 = J1 < jmax ? (unsigned)(uint16_t)opos[lane + 64 * J1] : (unsigned)(ncol1 - 1);
+        cpos[h] = c0 | (c1 << 16);
+    }
     // this lane's bins: kbar mod N (for Phi_in) and bin index
     int kbc[U], binc[U];
 #pragma unroll
     for (int u = 0; u < U; ++u) {
-        const int col = lane + 64 * u;
+        const int col = wv * 64 + lane + 128 * u;
         binc[u] = col < n_p ? B.col_bin[cs + col] : -1;
         kbc[u] = col < n_p ? B.bin_kb[binc[u]] : 0;
     }
@@ -1362,6 +1389,25 @@ __device__ __forceinline__ void spectra_wide_body(const BandDev &B, const float2
     };
     const int lo = lower(Kh), hi = lower(K1);
     const int64_t nr = (int64_t)B.n_seg * n_k;
+    const float2 *ybase = y + (size_t)tb * Q * nr;
+    // this wavefront's detectors X = wv + kSpwWaves i (i < NJ); the input of a detector's next
+    // segment is loaded while the current one is transformed.  Buffer loads with the segment's
+    // n_k samples as the buffer range read zero past it (no branches, no zero padding in memory).
+    constexpr int NJ = (QM + kSpwWaves - 1) / kSpwWaves;
+    float2 nxt[NJ][16];
+    auto load = [&](int e, int i) {
+        const int X = wv + kSpwWaves * i;
+        const float2 *ys = ybase + (size_t)X * nr + (size_t)ld_uniform(B.seg_any, e) * n_k;
+        const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc((void *)ys, (short)0, n_k * 8, 0x00020000);
+#pragma unroll
+        for (int r = 0; r < 16; ++r)
+            nxt[i][r] = __builtin_bit_cast(float2, __builtin_amdgcn_raw_buffer_load_b64(rs, (lane + 64 * r) * 8, 0, 0));
+    };
+    if (lo < hi) {
+#pragma unroll
+        for (int i = 0; i < NJ; ++i)
+            if (wv + kSpwWaves * i < Q) load(lo, i);
+    }
 
     float2 Ga[QM][U], Gb[QM][U];
     double acc[U];
@@ -1372,48 +1418,52 @@ __device__ __forceinline__ void spectra_wide_body(const BandDev &B, const float2
         for (int X = 0; X < QM; ++X) Ga[X][u] = Gb[X][u] = make_float2(0.f, 0.f);
     }
     int head = 0, tail = 0, count = 0;
-    wave_sync();
     for (int e = lo; e < hi; ++e) {
-        const int K = B.seg_any[e];
+        const int K = ld_uniform(B.seg_any, e);
+        // this wavefront's transforms of step e
+#pragma unroll
+        for (int i = 0; i < NJ; ++i) {
+            const int X = wv + kSpwWaves * i;
+            if (X >= Q) continue;
+            float2 v[16];
+#pragma unroll
+            for (int r = 0; r < 16; ++r) v[r] = cmul<float>(nxt[i][r], win[r]);
+            if (e + 1 < hi) load(e + 1, i);
+            if (ld_uniform(B.seg_work, X * B.n_seg + K) < 0) continue;  // no data of detector X in K
+            fft1024_wave(v, fx, w2, w3, lane);
+            float2 *row = ring + ((size_t)head * Q + X) * ncol1;
+#pragma unroll
+            for (int J = 0; J < 16; ++J)
+                if (J < jmax) row[(cpos[J >> 1] >> (16 * (J & 1))) & 0xffffu] = v[J];
+        }
         float wa[QM], wb[QM];
 #pragma unroll
         for (int X = 0; X < QM; ++X) {
             wa[X] = wb[X] = 0.f;
             if (X >= Q) continue;
             const int ew = X * B.n_seg + K;
-            if (B.seg_work[ew] < 0) continue;  // no data of detector X in segment K
-            const SegWeight sw = B.segw[ew];
-            wa[X] = (float)(sw.ahat * sw.scale);
-            wb[X] = (float)(sw.bhat * sw.scale);
-            const float2 *ys = y + ((size_t)tb * Q + X) * nr + (size_t)K * n_k;
-            float2 v[16];
-#pragma unroll
-            for (int r = 0; r < 16; ++r) {
-                const int sidx = lane + 64 * r;
-                const float2 xv = sidx < n_k ? ys[sidx] : make_float2(0.f, 0.f);
-                v[r] = cmul<float>(xv, win[r]);
-            }
-            fft1024_wave(v, fx, w2, w3, lane);
-            float2 *row = ring + ((size_t)head * Q + X) * ncol1;
-#pragma unroll
-            for (int J = 0; J < 16; ++J)
-                if (J < jmax) row[opos[lane + 64 * J]] = v[J];
+            if (ld_uniform(B.seg_work, ew) < 0) continue;  // no data of detector X in segment K
+            static_assert(sizeof(SegWeight) == 3 * sizeof(double), "SegWeight is (ahat, bhat, scale)");
+            const double *swp = reinterpret_cast<const double *>(B.segw);
+            const double sc = ld_uniform(swp, 3 * ew + 2);
+            wa[X] = (float)(ld_uniform(swp, 3 * ew) * sc);
+            wb[X] = (float)(ld_uniform(swp, 3 * ew + 1) * sc);
         }
-        if (lane == 0) {
+        if (threadIdx.x == 0) {
             slotk[head] = K;
 #pragma unroll
             for (int X = 0; X < QM; ++X)
                 if (X < Q) meta[head * Q + X] = make_float2(wa[X], wb[X]);
         }
-        wave_sync();
+        __syncthreads();
         // Phi_in and the pairs whose later member is segment K
         const unsigned rB = (unsigned)(((int64_t)K * n_k) & mask);
         const bool count_it = K >= K0;
         const float invN = 1.0f / (float)N;
 #pragma unroll
         for (int u = 0; u < U; ++u) {
-            const int col = lane + 64 * u;
-            if (U > 1 && 64 * u >= n_p) break;  // uniform: no lane has a bin in this round
+            const int col = wv * 64 + lane + 128 * u;
+            if (U > 1 && 128 * u >= n_p) break;  // uniform: no lane of the workgroup has a bin here
             const int cc = col < n_p ? col : ncol1 - 1;
             const float ph = -(float)(((unsigned)kbc[u] * rB) & (unsigned)mask) * invN;  // revolutions
             const float cph = __builtin_amdgcn_cosf(ph), sph = __builtin_amdgcn_sinf(ph);
@@ -1424,7 +1474,7 @@ __device__ __forceinline__ void spectra_wide_body(const BandDev &B, const float2
                 float2 *slotp = ring + ((size_t)head * Q + X) * ncol1 + cc;
                 const float2 g = *slotp;
                 f[X] = make_float2(g.x * cph - g.y * sph, g.x * sph + g.y * cph);
-                *slotp = f[X];
+                if (col < n_p) *slotp = f[X];
             }
             if (count_it) {
                 float st = 0.f;
@@ -1460,7 +1510,7 @@ __device__ __forceinline__ void spectra_wide_body(const BandDev &B, const float2
         ++count;
         // spectra whose segment is more than R behind the next step's leave the window sums
         if (e + 1 < hi) {
-            const int Kn = B.seg_any[e + 1];
+            const int Kn = ld_uniform(B.seg_any, e + 1);
             while (count > 0) {
                 const int Kt = __builtin_amdgcn_readfirstlane(slotk[tail]);
                 if (Kt >= Kn - R) break;
@@ -1472,8 +1522,8 @@ __device__ __forceinline__ void spectra_wide_body(const BandDev &B, const float2
                     const float2 *rowt = ring + ((size_t)tail * Q + X) * ncol1;
 #pragma unroll
                     for (int u = 0; u < U; ++u) {
-                        if (U > 1 && 64 * u >= n_p) break;
-                        const int col = lane + 64 * u;
+                        if (U > 1 && 128 * u >= n_p) break;
+                        const int col = wv * 64 + lane + 128 * u;
                         const float2 g = rowt[col < n_p ? col : ncol1 - 1];
                         Ga[X][u].x = fmaf(-wt.x, g.x, Ga[X][u].x); Ga[X][u].y = fmaf(-wt.x, g.y, Ga[X][u].y);
                         Gb[X][u].x = fmaf(-wt.y, g.x, Gb[X][u].x); Gb[X][u].y = fmaf(-wt.y, g.y, Gb[X][u].y);
@@ -1483,7 +1533,7 @@ __device__ __forceinline__ void spectra_wide_body(const BandDev &B, const float2
                 --count;
             }
         }
-        wave_sync();
+        __syncthreads();
     }
 #pragma unroll
     for (int u = 0; u < U; ++u)
@@ -2011,7 +2061,7 @@ k_spectra_pairs_m(const BandDev *__restrict__ bands, const WorkItem *__restrict_
 // workgroups of one (template, chunk) group are given indices with equal l mod 8, which puts
 // them on one XCD, where they read the group's resampled series through that XCD's L2.
 template <int U, int QM>
-__global__ void __launch_bounds__(64)
+__global__ void __launch_bounds__(64 * kSpwWaves)
 k_spectra_wide_m(const BandDev *__restrict__ bands, const WorkItem *__restrict__ items, int n_items,
                  const float2 *__restrict__ y, double *__restrict__ part) {
     const WorkItem &it = items[find_item(items, n_items, kStSpectra, blockIdx.x)];
@@ -2214,7 +2264,7 @@ size_t spectra_pairs_lds(const BandDev &B) { return spair_layout(B.Q, B.n_f, B.R
 
 size_t spectra_wide_lds(const BandDev &B) { return spw_layout(B.Q, B.R, B.wide_ncol, B.wide_jmax).total; }
 
-int spectra_wide_cols(const BandDev &B) { return B.wide_ncol <= 128 ? 2 : (B.wide_ncol <= 256 ? 4 : 8); }
+int spectra_wide_cols(const BandDev &B) { return B.wide_ncol <= 128 ? 1 : (B.wide_ncol <= 256 ? 2 : 4); }
 
 bool spectra_wide_ok(const BandDev &B, bool fp64, size_t limit) {
     return !fp64 && B.n_s == 1024 && B.nfft_mask != 0 && B.bins_unique && B.Q >= 1 && B.Q <= 4 &&
@@ -2319,19 +2369,19 @@ template <int U>
 static void launch_spectra_wide_u(const BandDev *bands, const WorkItem *items, int n_items, int blocks, int qm,
                                   size_t lds, const void *y, double *part, hipStream_t stream) {
     if (qm <= 2)
-        hipLaunchKernelGGL((k_spectra_wide_m<U, 2>), dim3(blocks), dim3(64), lds, stream, bands, items, n_items,
+        hipLaunchKernelGGL((k_spectra_wide_m<U, 2>), dim3(blocks), dim3(64 * kSpwWaves), lds, stream, bands, items, n_items,
                            (const float2 *)y, part);
     else
-        hipLaunchKernelGGL((k_spectra_wide_m<U, 4>), dim3(blocks), dim3(64), lds, stream, bands, items, n_items,
+        hipLaunchKernelGGL((k_spectra_wide_m<U, 4>), dim3(blocks), dim3(64 * kSpwWaves), lds, stream, bands, items, n_items,
                            (const float2 *)y, part);
 }
 
 hipError_t launch_spectra_wide_m(const BandDev *bands, const WorkItem *items, int n_items, int blocks, int cols,
                                  int qm, size_t lds, const void *y, double *part, hipStream_t stream) {
     if (blocks == 0) return hipSuccess;
-    if (cols <= 2) launch_spectra_wide_u<2>(bands, items, n_items, blocks, qm, lds, y, part, stream);
-    else if (cols <= 4) launch_spectra_wide_u<4>(bands, items, n_items, blocks, qm, lds, y, part, stream);
-    else launch_spectra_wide_u<8>(bands, items, n_items, blocks, qm, lds, y, part, stream);
+    if (cols <= 1) launch_spectra_wide_u<1>(bands, items, n_items, blocks, qm, lds, y, part, stream);
+    else if (cols <= 2) launch_spectra_wide_u<2>(bands, items, n_items, blocks, qm, lds, y, part, stream);
+    else launch_spectra_wide_u<4>(bands, items, n_items, blocks, qm, lds, y, part, stream);
     return hipGetLastError();
 }
 
