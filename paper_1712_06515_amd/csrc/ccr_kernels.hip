@@ -1428,7 +1428,7 @@ __device__ __forceinline__ void spectra_wide_body(const BandDev &B, const float2
             float2 v[16];
 #pragma unroll
             for (int r = 0; r < 16; ++r) v[r] = cmul<float>(nxt[i][r], win[r]);
-            if (e + 1 < hi) load(e + 1, i);
+            load(min(e + 1, hi - 1), i);  // unconditional (the last step reloads its own segment)
             if (ld_uniform(B.seg_work, X * B.n_seg + K) < 0) continue;  // no data of detector X in K
             fft1024_wave(v, fx, w2, w3, lane);
             float2 *row = ring + ((size_t)head * Q + X) * ncol1;
@@ -1446,8 +1446,11 @@ __device__ __forceinline__ void spectra_wide_body(const BandDev &B, const float2
             static_assert(sizeof(SegWeight) == 3 * sizeof(double), "SegWeight is (ahat, bhat, scale)");
             const double *swp = reinterpret_cast<const double *>(B.segw);
             const double sc = ld_uniform(swp, 3 * ew + 2);
-            wa[X] = (float)(ld_uniform(swp, 3 * ew) * sc);
-            wb[X] = (float)(ld_uniform(swp, 3 * ew + 1) * sc);
+            // products formed in vector registers: readfirstlane keeps them uniform (scalar)
+            wa[X] = __builtin_bit_cast(float, __builtin_amdgcn_readfirstlane(
+                                                  __builtin_bit_cast(int, (float)(ld_uniform(swp, 3 * ew) * sc))));
+            wb[X] = __builtin_bit_cast(float, __builtin_amdgcn_readfirstlane(
+                                                  __builtin_bit_cast(int, (float)(ld_uniform(swp, 3 * ew + 1) * sc))));
         }
         if (threadIdx.x == 0) {
             slotk[head] = K;
@@ -1517,7 +1520,10 @@ __device__ __forceinline__ void spectra_wide_body(const BandDev &B, const float2
 #pragma unroll
                 for (int X = 0; X < QM; ++X) {
                     if (X >= Q) continue;
-                    const float2 wt = meta[tail * Q + X];
+                    const float2 wt0 = meta[tail * Q + X];
+                    const float2 wt = make_float2(
+                        __builtin_bit_cast(float, __builtin_amdgcn_readfirstlane(__builtin_bit_cast(int, wt0.x))),
+                        __builtin_bit_cast(float, __builtin_amdgcn_readfirstlane(__builtin_bit_cast(int, wt0.y))));
                     if (wt.x == 0.f && wt.y == 0.f) continue;
                     const float2 *rowt = ring + ((size_t)tail * Q + X) * ncol1;
 #pragma unroll
