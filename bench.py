@@ -1,14 +1,16 @@
 """Throughput of the resampled cross-correlation hot path on one MI355X.
 
-One step = one ccr_compute_rho over every orbital template and output bin of the workload
-(time base, resampling, segment FFTs, pair sum), inputs resident in HBM, output on device.
+One step = one ccr_compute_rho over every orbital template of the step and every output bin
+(time base, resampling, segment FFTs, pair sums, normalisation), inputs resident in HBM, output
+on device, split precision (FP64 time base and phases; FP32 interpolation, FFT and pair
+products), the call captured as a HIP graph and its launch shapes autotuned on first use.
 
-Workload "band" (default): 2 detectors, 120 days with 30 % seeded gaps, T_short = 600 s,
-0.1 Hz band at 200 Hz, 4096 orbital templates (64 a_p in [1, 2] lt-s x 64 T_asc over
-+-1000 s), lag-0 cross-detector pairs, Gaussian noise + 10 injections.  The value is
-rho evaluations (templates x bins) per second of the split-precision path (FP64 time base and
-phases, FP32 interpolation / FFT / pair products); the plain FP64 path (one template per
-launch sequence) is timed beside it on a bounded template subset.
+Workload "large" (default): 2 detectors, 240 days, no gaps, T_short = 1440 s, lags up to
+4 segments, 0.25 Hz band at 400 Hz (N_K 870, N_FFT 32768, 7413 bins), Gaussian noise + 100
+injections; its grid has 100 200 templates (200 a_p x 167 T_asc x 3 P), of which a step takes
+the first 1002 (one GPU's share of a 100-GPU template split; the rate is per rho evaluation).
+The plain FP64 path (one template per launch sequence, no graph) is timed beside it, and the
+realistic 120-day band and the 64-band batching workload are timed as extra lines.
 
 Prints one JSON line.  Also: --profile-steps N runs N untimed steps only (for rocprofv3),
 --copy-calibration runs a 1 GiB device copy (for scaling HBM counters).
@@ -27,16 +29,18 @@ sys.path.insert(0, ROOT)
 
 METRIC = "ρ evaluations (templates×freq bins)/s, FP32-batched vs plain FP64 at ≤1e-4 rel err"
 HBM_PEAK_GBS = 8000.0
-# MI355X FP32 vector peak.  A probe of plain (non-packed) v_fma_f32 throughput on the chip retires
-# a wave64 instruction every ~2 cycles per SIMD, i.e. 256 CU x 4 SIMD x 32 lanes x 2 flop x 2.4 GHz
-# = 157.3 TFLOP/s, the published figure, without packed FP32.
+# MI355X FP32 vector peak (published).  It counts packed FP32 (two lanes of arithmetic per
+# instruction); this build compiles without packed FP32, so its kernels can reach at most half.
 FP32_PEAK_TFLOPS = 157.3
 
 WORKLOADS = {
+    "large": "2 detectors, 240 d, no gaps, T_short 1440 s, lags up to 4, 0.25 Hz at 400 Hz (7413 bins), "
+             "noise + 100 injections; grid of 100200 templates (200 a_p x 167 T_asc x 3 P), first {n} per step",
     "band": "2 detectors, 120 d, 30% gaps, T_short 600 s, 0.1 Hz at 200 Hz, 4096 templates "
             "(64 a_p x 64 T_asc), lag 0 cross-detector pairs, noise + 10 injections",
     "tiny": "2 detectors, 2 d, T_short 360 s, 0.25 Hz at 100 Hz, 64 templates, same-time pairs",
-    "large": "2 detectors, 240 d, T_short 1440 s, lag 4, 0.25 Hz at 400 Hz, 100200 templates",
+    "multiband": "3 detectors (100/120/80 d of 120 d, 15% gaps), 64 bands of 0.05-0.2 Hz between 50 and "
+                 "400 Hz, T_short 1400-240 s, lag 1, 1024 templates per band, one call",
 }
 
 
@@ -73,12 +77,12 @@ def read_traffic(kernel, workload):
         return None
 
 
-def cpu_baseline(ds, seg_fraction=0.25):
+def cpu_baseline(ds, n_templates, seg_fraction):
     """The oracle timed on the host's cores over a bounded sample of the workload: as many
-    templates as the oracle has threads (one template per thread), each over the first
-    `seg_fraction` of the segments (same band, detectors, sampling, gaps and weights).  The
-    oracle's cost is linear in the number of segments, so the rate is scaled to full-length
-    templates: value = templates x bins / (wall x M / M_sample)."""
+    templates as the oracle has threads (one template per thread, drawn from the step's
+    templates), every bin, over the first `seg_fraction` of the segments (same band, detectors,
+    sampling, gaps and weights).  The oracle's cost is linear in the number of segments, so the
+    rate is scaled to full-length templates: value = templates x bins / (wall x M / M_sample)."""
     import copy
 
     import numpy as np
@@ -93,15 +97,15 @@ def cpu_baseline(ds, seg_fraction=0.25):
     o = oracle.Oracle(sub)
     n_f = o.plan().n_f
     rng = np.random.default_rng(5)
-    n = min(len(ds.templates), max(1, nthreads))
-    idx = rng.choice(len(ds.templates), size=n, replace=False)
+    n = min(n_templates, max(1, nthreads))
+    idx = rng.choice(n_templates, size=n, replace=False)
     t0 = time.perf_counter()
     o.rho(ds.templates[idx])
     dt = time.perf_counter() - t0
     scale = ds.n_seg / m_sub
     return {"value": n * n_f / (dt * scale), "unit": "rho-evals/s", "cores": int(n), "kind": "oracle",
-            "sample": f"{n} random templates x all {n_f} bins over the first {m_sub} of {ds.n_seg} segments "
-                      f"({dt:.1f} s wall on {n} threads), rate scaled by {scale:.2f} to full-length templates"}
+            "sample": f"{n} random templates of the step x all {n_f} bins over the first {m_sub} of {ds.n_seg} "
+                      f"segments ({dt:.1f} s wall on {n} threads), rate scaled by {scale:.1f} to full-length templates"}
 
 
 def roofline(name, avg_ms, tb, info, workload):
@@ -123,9 +127,8 @@ def roofline(name, avg_ms, tb, info, workload):
                 "per_unit": f"8 B written per resampled sample + the Farrow table ({planes} x 8 B per input "
                             f"sample and detector) read once per launch"}
     if name == "resample":
-        # one complex64 sample written per resampled sample; the input sample is read once per
-        # tile of T_b templates (the templates one workgroup resamples from one staged input
-        # window)
+        # one complex sample written per resampled sample; the input sample is read once per
+        # tile of T_b templates
         T_b = info["resample_templates"]
         byts = n_active * info["n_k"] * tb * (8.0 + 8.0 / T_b)
         ach = byts / (avg_ms * 1e-3) / 1e9
@@ -137,39 +140,97 @@ def roofline(name, avg_ms, tb, info, workload):
     flops = n_active * tb * P * (5.0 * ns * np.log2(ns) + 6.0 * ns)
     per_unit = f"P (5 n_s log2 n_s + 6 n_s) FP32 flop per (template, detector, segment), n_s={ns}, P={P}"
     if name in ("spectra_pairs", "fused"):
-        # the pair sum runs in the same kernel: 8 flop per (template, pair, bin)
-        flops += 8.0 * info["n_pairs"] * info["n_f"] * tb
-        per_unit += " + 8 flop per (template, pair, bin)"
+        # the direct pair sum runs in the same kernel: 8 flop per (template, pair, bin) over the
+        # pairs whose two spectra are present
+        flops += 8.0 * info["n_pairs_present"] * info["n_f"] * tb
+        per_unit += " + 8 flop per (template, pair with both spectra present, bin)"
+    if name == "spectra_wide":
+        per_unit += " (segment FFTs only: the pair sums, done as window sums, are not counted)"
     ach = flops / (avg_ms * 1e-3) / 1e12
     kern = {"spectra": "k_spectra16_m" if ns == 256 else "k_spectra_m", "spectra_pairs": "k_spectra_pairs_m",
-            "fused": "k_fused"}[name]
+            "fused": "k_fused", "spectra_wide": "k_spectra_wide_m"}[name]
     return {"kernel": kern, "bound": "alu", "achieved": ach, "peak": FP32_PEAK_TFLOPS, "unit": "TFLOP/s",
             "frac": ach / FP32_PEAK_TFLOPS, "traffic": read_traffic(name, workload),
             "avg_launch_ms": avg_ms, "algorithmic_flops_per_launch": flops, "per_unit": per_unit}
 
 
+def pairs_present(ds, R, pairs):
+    """Pairs of the pair set (Sec. III.B.1) whose two segment spectra exist, approximately: both
+    segments hold valid input samples of their detector (the library marks a segment active from
+    its source samples mapped through the Earth delay, which can differ at gap edges by a
+    segment).  Exact for workloads without gaps."""
+    import numpy as np
+    Q, M = ds.n_det, ds.n_seg
+    act = ds.valid[:, :M * ds.n_k].reshape(Q, M, ds.n_k).any(axis=2)
+    n = 0
+    for X in range(Q):
+        for Y in range(Q):
+            for dl in range(-R, R + 1):
+                if not (((pairs & 1) and X < Y) or ((pairs & 2) and X == Y and dl > 0)):
+                    continue
+                a = act[X, max(0, -dl):M - max(0, dl)]
+                b = act[Y, max(0, dl):M - max(0, -dl)]
+                n += int(np.sum(a & b))
+    return n
+
+
+def golden_error(ds, rho, n_templates):
+    """max |rho - rho_oracle| / max(|rho_oracle|, 1) of the timed output against the oracle's
+    stored values (tests/golden, written by a script that calls only the oracle) for the sampled
+    templates that lie in the step."""
+    import numpy as np
+    path = os.path.join(ROOT, "tests", "golden", "oracle_values.json")
+    if not os.path.exists(path):
+        return None
+    meta = json.load(open(path)).get("large")
+    if meta is None:
+        return None
+    ref = np.load(os.path.join(ROOT, "tests", "golden", "oracle_large.npy"))
+    lo, hi = meta["bins"]
+    rows = [(j, t) for j, t in enumerate(meta["templates"]) if t < n_templates]
+    if not rows:
+        return None
+    err = max(float(np.max(np.abs(rho[t, lo:hi] - ref[j]) / np.maximum(np.abs(ref[j]), 1.0))) for j, t in rows)
+    return {"max_rel_err": err, "templates": len(rows), "bins": hi - lo,
+            "against": "oracle (tests/golden/oracle_large.npy)"}
+
+
+def time_steps(step, steps, warmup):
+    import torch
+    for _ in range(warmup):
+        step()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        step()
+    torch.cuda.synchronize()
+    return (time.perf_counter() - t0) / steps
+
+
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=5)
-    ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="band", choices=sorted(WORKLOADS))
-    ap.add_argument("--fp64-templates", type=int, default=256,
-                    help="templates timed on the plain FP64 path")
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--workload", default="large", choices=["large", "band", "tiny"])
+    ap.add_argument("--templates", type=int, default=1002,
+                    help="templates per step (first N of the grid; 0: all)")
+    ap.add_argument("--fp64-templates", type=int, default=32, help="templates timed on the plain FP64 path")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-extra", action="store_true", help="skip the extra workload lines")
     ap.add_argument("--profile-steps", type=int, default=0)
     ap.add_argument("--copy-calibration", action="store_true")
-    ap.add_argument("--fused", type=int, default=0, help="1: fused kernel, 0: staged kernels (default)")
-    ap.add_argument("--workspace-mb", type=int, default=0, help="workspace budget (0: the library default)")
-    ap.add_argument("--farrow", type=int, default=None,
-                    help="split-precision resampler: 1 Farrow form (library default), 0 direct tap sum")
-    ap.add_argument("--max-templates", type=int, default=0,
-                    help="time only the first N templates of the workload (0: all; the rate is per rho evaluation)")
+    ap.add_argument("--graph", type=int, default=1)
+    ap.add_argument("--autotune", type=int, default=1)
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py measures one GPU: the library has no multi-GPU path (orbital templates are "
-              "independent, so they would shard across GPUs with no exchange but a final gather)",
-              file=sys.stderr)
+        print("bench.py measures one GPU. Templates (and bands) are independent, so N GPUs would each "
+              "take 1/N of the template list with the band data replicated, and exchange nothing but an "
+              "optional final gather of candidates; that path is not built.", file=sys.stderr)
         sys.exit(2)
 
     import numpy as np
@@ -188,87 +249,80 @@ def main():
     from paper_1712_06515_amd import Context, PREC_FP64, PREC_SPLIT
 
     t_gen = time.perf_counter()
-    ds = synth.make_dataset(synth.config(args.workload))
-    if args.max_templates and args.max_templates < len(ds.templates):
-        ds.templates = ds.templates[:args.max_templates]
-    print(f"[bench] dataset {args.workload}: {ds.n_det} det x {ds.n} samples, {len(ds.templates)} templates "
-          f"({time.perf_counter() - t_gen:.1f} s)", file=sys.stderr, flush=True)
+    cfg = synth.config(args.workload)
+    ds = synth.make_dataset(cfg)
+    n_grid = len(ds.templates)
+    if args.templates and args.templates < n_grid:
+        ds.templates = ds.templates[:args.templates]
+    log(f"dataset {args.workload}: {ds.n_det} det x {ds.n} samples, {len(ds.templates)} of {n_grid} templates "
+        f"({time.perf_counter() - t_gen:.1f} s)")
     ctx = Context(ds.sky, device=0)
-    ctx.set_option("fused", args.fused)
-    if args.workspace_mb:
-        ctx.set_option("workspace_mb", args.workspace_mb)
     bid = ctx.load(ds)
     info = ctx.band_info(bid)
-    if args.farrow is not None:
-        ctx.set_option("farrow", args.farrow)
     info["resample_templates"] = ctx.get_option("resample_templates")
     info["farrow_used"] = bool(ctx.get_option("farrow")) and info["farrow_degree"] > 0
+    info["n_pairs_present"] = pairs_present(ds, cfg["band"]["max_lag"], cfg["band"].get("pairs", 3))
     n_t, n_f = info["n_templates"], info["n_f"]
     out = torch.empty((n_t, n_f), dtype=torch.float32, device="cuda")
     stream = torch.cuda.current_stream()
 
-    def step(prec=PREC_SPLIT, band=bid, o=out):
-        ctx.compute_rho(band, prec=prec, out_fp64=False, outputs=[o.data_ptr()], stream=stream.cuda_stream)
+    def step():
+        ctx.compute_rho(bid, prec=PREC_SPLIT, out_fp64=False, outputs=[out.data_ptr()], stream=stream.cuda_stream)
 
     if args.profile_steps:
         for i in range(args.profile_steps):
             step()
             torch.cuda.synchronize()
-            print(f"[bench] profile step {i} done", file=sys.stderr, flush=True)
+            log(f"profile step {i} done")
         return
 
-    for _ in range(args.warmup):
-        step()
-    torch.cuda.synchronize()
-    print("[bench] warm-up done", file=sys.stderr, flush=True)
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
-        step()
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
-    ms_per_step = 1e3 * wall / args.steps
-    value = n_t * n_f / (wall / args.steps)
-    print(f"[bench] split path {ms_per_step:.2f} ms/step", file=sys.stderr, flush=True)
+    # the timed path: graph capture + autotuned launch shapes (tuning and capture happen in the
+    # warm-up); at least one warm-up step so that neither is timed
+    ctx.set_option("autotune", args.autotune)
+    ctx.set_option("graph", args.graph)
+    sec = time_steps(step, args.steps, max(1, args.warmup))
+    ms_per_step = 1e3 * sec
+    value = n_t * n_f / sec
+    log(f"split path {ms_per_step:.2f} ms/step ({value:.3e} rho/s)")
+    rho = out.cpu().numpy()
+    err = golden_error(ds, rho, n_t) if args.workload == "large" else None
+    tuned = {"k_chunk": ctx.get_option("tuned_k_chunk"), "template_batch": ctx.get_option("tuned_template_batch")}
 
-    # per-kernel device time (events on the launch stream), separate pass
+    # per-kernel device time (HIP events on the launch stream), separate eager pass with the
+    # same launches (graph replays are not timed per kernel)
+    ctx.set_option("graph", 0)
     ctx.set_option("timing", 1)
     ctx.kernel_times(reset=True)
-    for _ in range(args.steps):
+    k_steps = min(args.steps, 3)
+    for _ in range(k_steps):
         step()
     kt = ctx.kernel_times(reset=True)
     ctx.set_option("timing", 0)
 
-    # plain FP64 path: one template per launch sequence, on a bounded subset
+    # plain FP64 path: one template per launch sequence, no graph, on a bounded subset
     nsub = min(args.fp64_templates, n_t)
     ctx2 = Context(ds.sky, device=0)
     ctx2.set_option("template_batch", 1)
     ctx2.set_option("items_per_launch", 1)
-    ctx2.set_option("fused", 0)
     bid2 = ctx2.load(ds, templates=ds.templates[:nsub])
     out2 = torch.empty((nsub, n_f), dtype=torch.float64, device="cuda")
 
     def step64():
         ctx2.compute_rho(bid2, prec=PREC_FP64, out_fp64=True, outputs=[out2.data_ptr()], stream=stream.cuda_stream)
 
-    step64()
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    step64()
-    torch.cuda.synchronize()
-    w64 = time.perf_counter() - t0
-    value64 = nsub * n_f / w64
-    print(f"[bench] fp64 plain {1e3 * w64:.1f} ms for {nsub} templates", file=sys.stderr, flush=True)
+    s64 = time_steps(step64, 3, 1)
+    value64 = nsub * n_f / s64
+    log(f"fp64 plain {1e3 * s64:.1f} ms for {nsub} templates ({value64:.3e} rho/s)")
+    ctx2.close()
 
-    # roofline of the dominant kernel (device time per launch from HIP events on the launch
-    # stream; algorithmic work per launch = per-unit figure x units per launch); the other
-    # hot kernel's roofline is reported beside it
     rooflines = {}
     for kname, (ms_tot, nl) in kt.items():
-        if nl == 0 or kname not in ("resample", "spectra", "spectra_pairs", "fused"):
+        if nl == 0 or kname not in ("resample", "spectra", "spectra_pairs", "fused", "spectra_wide"):
             continue
-        rooflines[kname] = roofline(kname, ms_tot / nl, n_t / max(1, nl // args.steps), info, args.workload)
+        rooflines[kname] = roofline(kname, ms_tot / nl, n_t / max(1, nl // k_steps), info, args.workload)
     name = max((k for k in rooflines), key=lambda k: kt[k][0])
     roof = rooflines.pop(name)
+    workload = WORKLOADS[args.workload].format(n=n_t)
     result = {
         "metric": METRIC,
         "value": value,
@@ -281,18 +335,64 @@ def main():
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "f32 (f64 time base and phases)",
-        "data": "synthetic",
-        "config": {"workload": f"{args.workload}: {WORKLOADS[args.workload]}", "templates": n_t, "bins": n_f,
-                   "n_k": info["n_k"], "n_seg": info["n_seg"], "n_fft": info["n_fft"]},
+        "data": "synthetic (seeded noise, injections, gaps; analytic Earth model)",
+        "config": {"workload": f"{args.workload}: {workload}", "templates": n_t, "bins": n_f,
+                   "n_k": info["n_k"], "n_seg": info["n_seg"], "n_fft": info["n_fft"], "max_lag": cfg["band"]["max_lag"],
+                   "graph": args.graph, "autotune": args.autotune, "tuned": tuned},
+        "rho_error": err,
         "fp64_plain": {"value": value64, "unit": "rho-evals/s", "templates_timed": nsub,
                        "speedup_split_batched_over_fp64_plain": value / value64},
-        "kernels_ms_per_step": {k: v[0] / args.steps for k, v in kt.items()},
+        "kernels_ms_per_step": {k: v[0] / k_steps for k, v in kt.items() if v[1]},
         "roofline": roof,
         "roofline_other_kernels": rooflines,
     }
+    ctx.close()
+
+    if not args.no_extra and args.workload == "large":
+        result["extra"] = extra_lines(args)
     if not args.no_cpu_baseline:
-        result["cpu_baseline"] = cpu_baseline(ds)
+        frac = {"large": 1.0 / 24.0, "band": 0.25, "tiny": 1.0}[args.workload]
+        result["cpu_baseline"] = cpu_baseline(ds, n_t, frac)
     print(json.dumps(result))
+
+
+def extra_lines(args):
+    """The realistic band (120 days, 4096 templates, split) and the batching workload (64 bands
+    x 1024 templates in one call), both with graph capture and autotuning: rho-evals/s."""
+    import torch
+    import synth
+    from paper_1712_06515_amd import Context, PREC_SPLIT
+    out = {}
+    t0 = time.perf_counter()
+    ds = synth.make_dataset(synth.config("band"))
+    with Context(ds.sky, device=0) as ctx:
+        bid = ctx.load(ds)
+        info = ctx.band_info(bid)
+        o = torch.empty((info["n_templates"], info["n_f"]), dtype=torch.float32, device="cuda")
+        ctx.set_option("autotune", 1)
+        ctx.set_option("graph", 1)
+        sec = time_steps(lambda: ctx.compute_rho(bid, prec=PREC_SPLIT, out_fp64=False, outputs=[o.data_ptr()]),
+                         10, 2)
+        out["band"] = {"workload": WORKLOADS["band"], "value": info["n_templates"] * info["n_f"] / sec,
+                       "unit": "rho-evals/s", "ms_per_step": 1e3 * sec}
+    log(f"extra band: {out['band']['ms_per_step']:.1f} ms/step ({time.perf_counter() - t0:.0f} s)")
+    t0 = time.perf_counter()
+    dss = synth.make_multiband(synth.config("multiband"))
+    log(f"multiband data ({time.perf_counter() - t0:.0f} s)")
+    with Context(dss[0].sky, device=0) as ctx:
+        ids = [ctx.load(d) for d in dss]
+        infos = [ctx.band_info(b) for b in ids]
+        outs = [torch.empty((i["n_templates"], i["n_f"]), dtype=torch.float32, device="cuda") for i in infos]
+        ctx.set_option("autotune", 1)
+        ctx.set_option("graph", 1)
+        sec = time_steps(lambda: ctx.compute_rho(ids, prec=PREC_SPLIT, out_fp64=False,
+                                                 outputs=[x.data_ptr() for x in outs]), 3, 1)
+        n_eval = sum(i["n_templates"] * i["n_f"] for i in infos)
+        out["multiband"] = {"workload": WORKLOADS["multiband"], "value": n_eval / sec, "unit": "rho-evals/s",
+                            "ms_per_step": 1e3 * sec, "bands": len(ids), "rho_evals_per_step": n_eval,
+                            "tuned_k_chunk": ctx.get_option("tuned_k_chunk")}
+    log(f"extra multiband: {out['multiband']['ms_per_step']:.1f} ms/step")
+    return out
 
 
 if __name__ == "__main__":
