@@ -41,7 +41,7 @@ class Band(ctypes.Structure):
     _fields_ = [("f_min", ctypes.c_double), ("f_band", ctypes.c_double), ("t_short", ctypes.c_double),
                 ("max_lag", ctypes.c_int), ("dirichlet_D", ctypes.c_int), ("window", ctypes.c_int),
                 ("n_fft_override", ctypes.c_int), ("mu_f", ctypes.c_double), ("pairs", ctypes.c_int),
-                ("a_p_max", ctypes.c_double), ("orbit_period", ctypes.c_double)]
+                ("a_p_max", ctypes.c_double), ("orbit_period", ctypes.c_double), ("weight", ctypes.c_int)]
 
 
 class Plan(ctypes.Structure):
@@ -62,7 +62,9 @@ class Problem(ctypes.Structure):
                 ("f_het", ctypes.c_double),
                 ("x", ctypes.c_void_p * MAX_DET), ("valid", ctypes.c_void_p * MAX_DET),
                 ("a", ctypes.c_void_p * MAX_DET), ("b", ctypes.c_void_p * MAX_DET),
-                ("noise_var", ctypes.c_void_p * MAX_DET)]
+                ("noise_var", ctypes.c_void_p * MAX_DET),
+                ("ar", ctypes.c_void_p * MAX_DET), ("br", ctypes.c_void_p * MAX_DET),
+                ("ecc", ctypes.c_int)]
 
 
 def lib():
@@ -91,6 +93,8 @@ def lib():
         L.cco_pair_count.restype = ctypes.c_int64
         L.cco_rho.argtypes = [P, dp, ctypes.c_int64, ctypes.c_int, i64p, ctypes.c_int64, dp]
         L.cco_num_threads.restype = ctypes.c_int
+        L.cco_kepler.argtypes = [ctypes.c_double, ctypes.c_double]
+        L.cco_kepler.restype = ctypes.c_double
         _lib = L
     return _lib
 
@@ -112,7 +116,9 @@ class Oracle:
     """Wraps one problem (data, weights, band) for repeated oracle calls.
 
     ``ds`` is a ``synth.Dataset``-like object with fields sky, band, sites, dt,
-    t0, n, f_het, x, valid, a, b, noise_var.  Arrays are kept alive here."""
+    t0, n, f_het, x, valid, a, b, noise_var, and optionally ar, br (per-sample antenna
+    functions on the source lattice, [n_det][n_seg * n_k]) and ecc (templates of 5 values:
+    a_p, T_p, omega, e, P).  Arrays are kept alive here."""
 
     def __init__(self, ds):
         self._keep = []
@@ -124,7 +130,7 @@ class Oracle:
         p.band = Band(b["f_min"], b["f_band"], b["t_short"], int(b["max_lag"]), int(b.get("dirichlet_D", 8)),
                       int(b.get("window", 0)), int(b.get("n_fft_override", 0)), float(b.get("mu_f", 0.1)),
                       int(b.get("pairs", 3)), float(b.get("a_p_max", 0.0)),
-                      float(b.get("orbit_period", 68023.70)))
+                      float(b.get("orbit_period", 68023.70)), int(b.get("weight", 0)))
         q = ds.x.shape[0]
         p.n_det = q
         for X in range(q):
@@ -141,6 +147,15 @@ class Oracle:
             p.a[X] = aa.ctypes.data
             p.b[X] = bb.ctypes.data
             p.noise_var[X] = nv.ctypes.data
+            ar = getattr(ds, "ar", None)
+            br = getattr(ds, "br", None)
+            if ar is not None and br is not None:
+                arr = np.ascontiguousarray(ar[X], dtype=np.float64)
+                brr = np.ascontiguousarray(br[X], dtype=np.float64)
+                self._keep += [arr, brr]
+                p.ar[X] = arr.ctypes.data
+                p.br[X] = brr.ctypes.data
+        p.ecc = 1 if getattr(ds, "ecc", False) else 0
         p.t0 = ds.t0
         p.dt = ds.dt
         p.n = ds.x.shape[1]
@@ -223,3 +238,8 @@ class Oracle:
 
 def num_threads():
     return lib().cco_num_threads()
+
+
+def kepler(M, e):
+    """Eccentric anomaly E with E - e sin E = M (the oracle's long-double Newton solve)."""
+    return lib().cco_kepler(float(M), float(e))

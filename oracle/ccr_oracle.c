@@ -9,11 +9,14 @@
  * accelerate cross-correlation searches for continuous gravitational waves
  * from binary systems"):
  *   plan      Sec. III.B.2 (eqs. n-fft-final, delta lambda_f), App. B (eq. delta-f-load)
- *   time base Sec. II.A.2 (eqs. t-ssb-equation, tau-equation, circular R/c), Sec. III.A.2
+ *   time base Sec. II.A.2 (eqs. t-ssb-equation, tau-equation; circular R/c, or the eccentric
+ *             orbit of eqs. solve-for-E and Kepler-equation), Sec. III.A.2
  *   interp    Sec. III.A.1 (eq. shannon-interp-formula), Sec. III.A.2 (eqs. delta-q-eq,
  *             q-prime-eq, resampled-time-series-q-eq)
  *   spectra   Sec. III.B.5 (zero-padded DFT of each T_short segment) with Phi_in of Sec. III.B.4
- *   pairs     Sec. III.B.1 (pair selection {L|K})
+ *   pairs     Sec. III.B.1 (pair selection {L|K}); all pairs with auto-correlations, App. A.1-A.2
+ *   weights   eq. geometric-filter (Gamma^ave) or Gamma^circ (Sec. II.B); per-segment a_K, b_K
+ *             or per-sample a_r, b_r (Sec. III.B.3, eq. norm-a-eq)
  *   rho       Sec. III.B.6 (eq. final-formatted-rho) with App. A normalisation
  *
  * Precision: long double (x87, 64-bit mantissa) for the time base and all
@@ -60,7 +63,8 @@ int cco_plan_band(const cco_problem *p, cco_plan *o) {
     const cco_band *b = &p->band;
     if (!(b->t_short > 0.0) || !(b->f_band > 0.0) || b->dirichlet_D < 1 || b->max_lag < 0 ||
         !(p->dt > 0.0) || !(b->mu_f > 0.0) || !(b->orbit_period > 0.0) || b->a_p_max < 0.0 ||
-        p->n_det < 1 || p->n_det > CCO_MAX_DET || (b->pairs & 3) == 0)
+        p->n_det < 1 || p->n_det > CCO_MAX_DET || (b->pairs & 7) == 0 || ((b->pairs & 4) && (b->pairs & 3)) ||
+        b->weight < 0 || b->weight > 1)
         return CCO_EINVAL;
     const double pi = 3.14159265358979323846;
     double f_top = b->f_min + b->f_band;
@@ -153,36 +157,95 @@ double cco_earth_delay(const cco_problem *p, int det, double t) {
     return (double)e;
 }
 
-/* Forward map tau(t) - t = r.n - a_p sin(Omega (t_SSB - T_asc)), circular orbit,
- * orbital phase taken at the SSB time (eqs. t-ssb-equation, tau-equation). */
-static long double forward_offset_l(const cco_problem *p, int det, long double ap, long double tasc,
-                                    long double period, long double t) {
-    long double e;
-    earth_delay_l(p, det, t, &e, NULL);
-    long double om = 2.0L * PI_L / period;
-    return e - ap * sinl(om * (t + e - tasc));
+/* Binary orbit of a template.  Circular (Sec. II.A.2, the circular-case R/c):
+ *   R/c = a_p sin(Omega (t_SSB - T_asc)),  template (a_p, T_asc, P);
+ * eccentric (eqs. solve-for-E, Kepler-equation), the anomaly taken at t_SSB as the circular
+ * case takes its phase (tau ~ t, Sec. II.A.2):
+ *   Omega (t_SSB - T_p) = E - e sin E,
+ *   R/c = a_p [sin(omega) (cos E - e) + cos(omega) sqrt(1 - e^2) sin E],  template
+ *   (a_p, T_p, omega, e, P).  With e = 0 this is the circular orbit with T_asc = T_p - omega/Omega. */
+typedef struct {
+    int ecc;
+    long double ap, tref, om, w, e;  /* tref: T_asc (circular) or T_p; om = 2 pi / P; w = omega */
+} orbit;
+
+static orbit orbit_of(const cco_problem *p, const double *t) {
+    orbit o;
+    o.ecc = p->ecc;
+    o.ap = t[0];
+    o.tref = t[1];
+    if (p->ecc) {
+        o.w = t[2];
+        o.e = t[3];
+        o.om = 2.0L * PI_L / t[4];
+    } else {
+        o.w = 0.0L;
+        o.e = 0.0L;
+        o.om = 2.0L * PI_L / t[2];
+    }
+    return o;
 }
 
-double cco_forward_offset(const cco_problem *p, int det, const double tmpl[3], double t) {
-    return (double)forward_offset_l(p, det, tmpl[0], tmpl[1], tmpl[2], t);
+/* Kepler's equation E - e sin E = M by Newton's method in long double from E = M + e sin M,
+ * iterated until the step is below 1e-19 rad and then once more (0 <= e < 1). */
+static long double kepler_l(long double M, long double e) {
+    long double E = M + e * sinl(M);
+    int extra = 0;
+    for (int it = 0; it < 100; ++it) {
+        long double step = (E - e * sinl(E) - M) / (1.0L - e * cosl(E));
+        E -= step;
+        if (fabsl(step) < 1e-19L && ++extra >= 1) break;
+    }
+    return E;
+}
+
+double cco_kepler(double M, double e) { return (double)kepler_l(M, e); }
+
+/* Binary Roemer delay R/c at SSB time ts and its derivative d(R/c)/d ts. */
+static void binary_delay_l(const orbit *o, long double ts, long double *R, long double *Rd) {
+    if (!o->ecc) {
+        long double th = o->om * (ts - o->tref);
+        *R = o->ap * sinl(th);
+        if (Rd) *Rd = o->ap * o->om * cosl(th);
+        return;
+    }
+    long double M = o->om * (ts - o->tref);
+    M -= 2.0L * PI_L * floorl(M / (2.0L * PI_L));
+    long double E = kepler_l(M, o->e);
+    long double sE = sinl(E), cE = cosl(E), sw = sinl(o->w), cw = cosl(o->w);
+    long double q = sqrtl(1.0L - o->e * o->e);
+    *R = o->ap * (sw * (cE - o->e) + cw * q * sE);
+    if (Rd) *Rd = o->ap * (-sw * sE + cw * q * cE) * o->om / (1.0L - o->e * cE);
+}
+
+/* Forward map tau(t) - t = r.n - R(t_SSB)/c, t_SSB = t + r.n (eqs. t-ssb-equation,
+ * tau-equation). */
+static long double forward_offset_l(const cco_problem *p, int det, const orbit *o, long double t) {
+    long double e, R;
+    earth_delay_l(p, det, t, &e, NULL);
+    binary_delay_l(o, t + e, &R, NULL);
+    return e - R;
+}
+
+double cco_forward_offset(const cco_problem *p, int det, const double *tmpl, double t) {
+    const orbit o = orbit_of(p, tmpl);
+    return (double)forward_offset_l(p, det, &o, t);
 }
 
 /* Inverse map (Sec. III.A.2, t(tau) as the functional inverse of tau(t)): the
  * delay Delta = t - tau of source time tau solves
- *   G(Delta) = Delta + e(tau + Delta) - a_p sin(Omega (tau + Delta + e(tau + Delta) - T_asc)) = 0
+ *   G(Delta) = Delta + e(tau + Delta) - R(tau + Delta + e(tau + Delta))/c = 0
  * by Newton iteration in long double, started from guess, iterated until the
  * step is below 1e-15 s and then twice more. */
-static long double solve_delay(const cco_problem *p, int det, long double ap, long double tasc,
-                               long double period, long double tau, long double guess) {
-    long double om = 2.0L * PI_L / period;
+static long double solve_delay(const cco_problem *p, int det, const orbit *o, long double tau, long double guess) {
     long double D = guess;
     int extra = 0;
     for (int it = 0; it < 100; ++it) {
-        long double t = tau + D, e, ed;
+        long double t = tau + D, e, ed, R, Rd;
         earth_delay_l(p, det, t, &e, &ed);
-        long double th = om * (t + e - tasc);
-        long double G = D + e - ap * sinl(th);
-        long double Gp = 1.0L + ed - ap * om * cosl(th) * (1.0L + ed);
+        binary_delay_l(o, t + e, &R, &Rd);
+        long double G = D + e - R;
+        long double Gp = 1.0L + ed - Rd * (1.0L + ed);
         long double step = G / Gp;
         D -= step;
         if (fabsl(step) < 1e-15L) {
@@ -192,18 +255,19 @@ static long double solve_delay(const cco_problem *p, int det, long double ap, lo
     return D;
 }
 
-static long double crude_guess(const cco_problem *p, int det, long double ap, long double tasc,
-                               long double period, long double tau) {
-    long double e;
+static long double crude_guess(const cco_problem *p, int det, const orbit *o, long double tau) {
+    long double e, R;
     earth_delay_l(p, det, tau, &e, NULL);
-    return -e + ap * sinl(2.0L * PI_L / period * (tau - tasc));
+    binary_delay_l(o, tau, &R, NULL);
+    return -e + R;
 }
 
-int cco_delay(const cco_problem *p, int det, const double tmpl[3], int64_t r, double *hi, double *lo) {
+int cco_delay(const cco_problem *p, int det, const double *tmpl, int64_t r, double *hi, double *lo) {
     if (det < 0 || det >= p->n_det) return CCO_EINVAL;
+    const orbit o = orbit_of(p, tmpl);
     long double tau = (long double)p->t0 + (long double)r * (long double)p->dt;
-    long double g = crude_guess(p, det, tmpl[0], tmpl[1], tmpl[2], tau);
-    long double D = solve_delay(p, det, tmpl[0], tmpl[1], tmpl[2], tau, g);
+    long double g = crude_guess(p, det, &o, tau);
+    long double D = solve_delay(p, det, &o, tau, g);
     *hi = (double)D;
     *lo = (double)(D - (long double)*hi);
     return CCO_OK;
@@ -214,10 +278,14 @@ int cco_delay(const cco_problem *p, int det, const double tmpl[3], int64_t r, do
  * and the normalisation do not depend on the template. */
 static void earth_only_mask_segment(const cco_problem *p, const cco_plan *pl, int det, int64_t K, uint8_t *m) {
     long double guess = 0.0L;
+    orbit none;
+    none.ecc = 0;
+    none.ap = none.tref = none.w = none.e = 0.0L;
+    none.om = 2.0L * PI_L;
     for (int64_t r = K * pl->n_k; r < (K + 1) * pl->n_k; ++r) {
         long double tau = (long double)p->t0 + (long double)r * (long double)p->dt;
-        if (r == K * pl->n_k) guess = crude_guess(p, det, 0.0L, 0.0L, 1.0L, tau);
-        long double D = solve_delay(p, det, 0.0L, 0.0L, 1.0L, tau, guess);
+        if (r == K * pl->n_k) guess = crude_guess(p, det, &none, tau);
+        long double D = solve_delay(p, det, &none, tau, guess);
         guess = D;
         int64_t j = r + (int64_t)floorl(D / (long double)p->dt + 0.5L);
         uint8_t v = 0;
@@ -278,16 +346,17 @@ static long double sinc_l(long double d) {
  * delay by the Newton solve (started from crude_guess at the segment's first sample, then
  * from the previous sample's delay), windowed sinc over the valid input samples, heterodyne
  * correction, gap mask. */
-static void resample_segment(const cco_problem *p, const cco_plan *pl, int det, const double tmpl[3],
+static void resample_segment(const cco_problem *p, const cco_plan *pl, int det, const double *tmpl,
                              const uint8_t *mask, int64_t K, double *ys, int64_t *jstar, double *offset) {
     int D = p->band.dirichlet_D, win = p->band.window;
+    const orbit o = orbit_of(p, tmpl);
     const float *x = p->x[det];
     const uint8_t *val = p->valid[det];
     long double guess = 0.0L;
     for (int64_t r = K * pl->n_k; r < (K + 1) * pl->n_k; ++r) {
         long double tau = (long double)p->t0 + (long double)r * (long double)p->dt;
-        if (r == K * pl->n_k) guess = crude_guess(p, det, tmpl[0], tmpl[1], tmpl[2], tau);
-        long double Dl = solve_delay(p, det, tmpl[0], tmpl[1], tmpl[2], tau, guess);
+        if (r == K * pl->n_k) guess = crude_guess(p, det, &o, tau);
+        long double Dl = solve_delay(p, det, &o, tau, guess);
         guess = Dl;
         long double q = Dl / (long double)p->dt;
         int64_t k = (int64_t)floorl(q + 0.5L);
@@ -314,14 +383,14 @@ static void resample_segment(const cco_problem *p, const cco_plan *pl, int det, 
     }
 }
 
-static int resample_det(const cco_problem *p, const cco_plan *pl, int det, const double tmpl[3],
+static int resample_det(const cco_problem *p, const cco_plan *pl, int det, const double *tmpl,
                         const uint8_t *mask, double *y, int64_t *jstar, double *offset) {
     for (int64_t K = 0; K < pl->n_seg; ++K)
         resample_segment(p, pl, det, tmpl, mask, K, y + 2 * K * pl->n_k, jstar, offset);
     return CCO_OK;
 }
 
-int cco_resample(const cco_problem *p, int det, const double tmpl[3], double *y,
+int cco_resample(const cco_problem *p, int det, const double *tmpl, double *y,
                  int64_t *jstar, double *offset, uint8_t *mask_out) {
     cco_plan pl;
     int st = validate(p, &pl);
@@ -394,14 +463,15 @@ static void spectra_from_series(const cco_problem *p, const cco_plan *pl, int de
  * phase model and assigned to the segment holding its source time:
  *   F^D_XK(i) = (sigma sqrt(N_K))^-1 sum_{j: tau(t_j) in K} valid_j x'_j
  *               exp(-2 pi i [nu_i (tau(t_j) - t0) - f_h Delta_j]),  nu_i = kbar_i / T_FFT. */
-static void spectra_direct(const cco_problem *p, const cco_plan *pl, int det, const double tmpl[3],
+static void spectra_direct(const cco_problem *p, const cco_plan *pl, int det, const double *tmpl,
                            const int64_t *bins, int64_t nb, double *F) {
     int64_t nk = pl->n_k, nfft = pl->n_fft;
+    const orbit o = orbit_of(p, tmpl);
     memset(F + 2 * det * pl->n_seg * nb, 0, sizeof(double) * 2 * (size_t)(pl->n_seg * nb));
     for (int64_t j = 0; j < p->n; ++j) {
         if (p->valid[det] && !p->valid[det][j]) continue;
         long double t = (long double)p->t0 + (long double)j * (long double)p->dt;
-        long double off = forward_offset_l(p, det, tmpl[0], tmpl[1], tmpl[2], t); /* tau - t */
+        long double off = forward_offset_l(p, det, &o, t);                          /* tau - t */
         long double u = (long double)j + off / (long double)p->dt;                /* (tau - t0)/dt */
         int64_t K = (int64_t)floorl(u / (long double)nk);
         if (K < 0 || K >= pl->n_seg) continue;
@@ -423,7 +493,7 @@ static void spectra_direct(const cco_problem *p, const cco_plan *pl, int det, co
     }
 }
 
-int cco_spectra(const cco_problem *p, const double tmpl[3], int tier, const int64_t *bins,
+int cco_spectra(const cco_problem *p, const double *tmpl, int tier, const int64_t *bins,
                 int64_t n_bins, double *F) {
     cco_plan pl;
     int st = validate(p, &pl);
@@ -456,11 +526,21 @@ int cco_spectra(const cco_problem *p, const double tmpl[3], int tier, const int6
 
 /* Pair set P (Sec. III.B.1): cross-detector pairs X < Y with |K - L| <= R, and
  * same-detector pairs with K < L <= K + R (no auto-correlation); each unordered
- * pair once. */
+ * pair once.  CCO_PAIRS_ALL: every ordered pair (X K, Y L), auto-correlations included and
+ * any lag (App. A.1: all pairs P, the sum expanding into |F_a|^2 + |F_b|^2). */
 static int pair_in_set(int pairs, int R, int X, int64_t K, int Y, int64_t L) {
+    if (pairs & CCO_PAIRS_ALL) return 1;
     if ((pairs & CCO_PAIRS_CROSS) && X < Y && llabs(K - L) <= R) return 1;
     if ((pairs & CCO_PAIRS_SAME) && X == Y && L > K && L <= K + R) return 1;
     return 0;
+}
+
+/* Range of partner segments L of segment K that the pair loops visit. */
+static int64_t lag_lo(const cco_problem *p, int64_t K) {
+    return (p->band.pairs & CCO_PAIRS_ALL) ? 0 : K - p->band.max_lag;
+}
+static int64_t lag_hi(const cco_problem *p, const cco_plan *pl, int64_t K) {
+    return (p->band.pairs & CCO_PAIRS_ALL) ? pl->n_seg - 1 : K + p->band.max_lag;
 }
 
 int64_t cco_pair_count(const cco_problem *p) {
@@ -471,7 +551,7 @@ int64_t cco_pair_count(const cco_problem *p) {
     for (int X = 0; X < p->n_det; ++X)
         for (int64_t K = 0; K < pl.n_seg; ++K)
             for (int Y = 0; Y < p->n_det; ++Y)
-                for (int64_t L = K - R; L <= K + R; ++L)
+                for (int64_t L = lag_lo(p, K); L <= lag_hi(p, &pl, K); ++L)
                     if (L >= 0 && L < pl.n_seg && pair_in_set(p->band.pairs, R, X, K, Y, L)) ++c;
     return c;
 }
@@ -486,7 +566,7 @@ static double norm_from_phi(const cco_problem *p, const cco_plan *pl, const doub
     for (int X = 0; X < p->n_det; ++X)
         for (int64_t K = 0; K < pl->n_seg; ++K)
             for (int Y = 0; Y < p->n_det; ++Y)
-                for (int64_t L = K - R; L <= K + R; ++L) {
+                for (int64_t L = lag_lo(p, K); L <= lag_hi(p, pl, K); ++L) {
                     if (L < 0 || L >= pl->n_seg || !pair_in_set(p->band.pairs, R, X, K, Y, L)) continue;
                     double sK = sqrt(p->noise_var[X][K]), sL = sqrt(p->noise_var[Y][L]);
                     double aK = p->a[X][K] / sK, bK = p->b[X][K] / sK;
@@ -499,9 +579,145 @@ static double norm_from_phi(const cco_problem *p, const cco_plan *pl, const doub
     return (double)sqrtl(acc);
 }
 
+/* ------------------------------------------------- weighted spectra streams */
+
+/* Per-sample antenna weighting (Sec. III.B.3, eq. norm-a-eq): the resampled series is
+ * multiplied by hat a_r = a(tau_r) / sigma_XK and by hat b_r before the DFT, giving two
+ * spectra per segment,
+ *   F^a_XK(i) = (sigma_XK sqrt(N_K))^-1 sum_s hat a_{r_B+s} y_{r_B+s} exp(-2 pi i kbar (r_B+s)/N_FFT),
+ * and F^b likewise.  With per-segment weights the streams are F^a = hat a_K F, F^b = hat b_K F.
+ * The pair sum and its normalisation then take one form for both (App. A.1,
+ * eq. well-formatted-rho, and its Gamma^circ counterpart):
+ *   Gamma^ave:  rho = sqrt2 Re sum_P [conj(F^a_K) F^a_L + conj(F^b_K) F^b_L] / N,
+ *               N^2 = sum_P A_K A_L + 2 C_K C_L + B_K B_L;
+ *   Gamma^circ: rho = sqrt2 sum_P Im[conj(F^b_K) F^a_L - conj(F^a_K) F^b_L] / N,
+ *               N^2 = sum_P A_K B_L + B_K A_L - 2 C_K C_L,
+ * with A_K = E|F^a_K|^2 = mean over the segment of m_r hat a_r^2, B_K, C_K = mean of
+ * m_r hat a_r hat b_r likewise (per-segment: hat a^2 phi, ...), so that Var rho = 1 in Gaussian
+ * noise.  The Gamma^circ term pairs (hat b_K hat a_L - hat a_K hat b_L) with the imaginary part
+ * of conj(F_K) F_L, whose mean for a circularly polarised signal (cos iota = 1) is
+ * proportional to that weight: the sign makes its expectation positive for cos iota > 0 with the
+ * signal convention x' = (F+ A+ - i Fx Ax) exp(i Phi) / 2. */
+static int per_sample(const cco_problem *p) {
+    for (int X = 0; X < p->n_det; ++X)
+        if (!p->ar[X] || !p->br[X]) return 0;
+    return 1;
+}
+
+/* A_XK, B_XK, C_XK (3 * n_det * n_seg doubles) from the gap masks. */
+static void stream_moments(const cco_problem *p, const cco_plan *pl, const uint8_t *masks, double *abc) {
+    int64_t nr = pl->n_seg * pl->n_k;
+    for (int X = 0; X < p->n_det; ++X)
+        for (int64_t K = 0; K < pl->n_seg; ++K) {
+            double sig = sqrt(p->noise_var[X][K]);
+            double A = 0.0, B = 0.0, C = 0.0;
+            for (int64_t s = 0; s < pl->n_k; ++s) {
+                int64_t r = K * pl->n_k + s;
+                if (!masks[X * nr + r]) continue;
+                double ar = per_sample(p) ? p->ar[X][r] / sig : p->a[X][K] / sig;
+                double br = per_sample(p) ? p->br[X][r] / sig : p->b[X][K] / sig;
+                A += ar * ar;
+                B += br * br;
+                C += ar * br;
+            }
+            double *o = abc + 3 * (X * pl->n_seg + K);
+            o[0] = A / (double)pl->n_k;
+            o[1] = B / (double)pl->n_k;
+            o[2] = C / (double)pl->n_k;
+        }
+}
+
+static double stream_norm(const cco_problem *p, const cco_plan *pl, const double *abc) {
+    int R = p->band.max_lag;
+    long double acc = 0.0L;
+    for (int X = 0; X < p->n_det; ++X)
+        for (int64_t K = 0; K < pl->n_seg; ++K)
+            for (int Y = 0; Y < p->n_det; ++Y)
+                for (int64_t L = lag_lo(p, K); L <= lag_hi(p, pl, K); ++L) {
+                    if (L < 0 || L >= pl->n_seg || !pair_in_set(p->band.pairs, R, X, K, Y, L)) continue;
+                    const double *k = abc + 3 * (X * pl->n_seg + K), *l = abc + 3 * (Y * pl->n_seg + L);
+                    if (p->band.weight == 0)
+                        acc += (long double)k[0] * l[0] + 2.0L * k[2] * l[2] + (long double)k[1] * l[1];
+                    else
+                        acc += (long double)k[0] * l[1] + (long double)k[1] * l[0] - 2.0L * k[2] * l[2];
+                }
+    return (double)sqrtl(acc);
+}
+
+/* Streams of segment K from its resampled samples: Fa, Fb (2 * nb doubles each). */
+static void streams_segment(const cco_problem *p, const cco_plan *pl, int det, int64_t K, const double *ys,
+                            const double *tw, const int64_t *bins, int64_t nb, double *Fa, double *Fb) {
+    int64_t nk = pl->n_k, nfft = pl->n_fft, rb = K * nk;
+    double sig = sqrt(p->noise_var[det][K]);
+    double scale = 1.0 / (sig * sqrt((double)nk));
+    int ps = per_sample(p);
+    for (int64_t ii = 0; ii < nb; ++ii) {
+        int64_t kb = bin_mod(pl, bins ? bins[ii] : ii);
+        int64_t idx = (kb * rb) % nfft;
+        double ra = 0.0, ia = 0.0, rbb = 0.0, ib = 0.0;
+        for (int64_t s = 0; s < nk; ++s) {
+            const double *yy = ys + 2 * s;
+            double wa = ps ? p->ar[det][rb + s] / sig : p->a[det][K] / sig;
+            double wb = ps ? p->br[det][rb + s] / sig : p->b[det][K] / sig;
+            double c = tw[2 * idx], sn = tw[2 * idx + 1];
+            double tr = yy[0] * c - yy[1] * sn, ti = yy[0] * sn + yy[1] * c;
+            ra += wa * tr;
+            ia += wa * ti;
+            rbb += wb * tr;
+            ib += wb * ti;
+            idx += kb;
+            if (idx >= nfft) idx -= nfft;
+        }
+        double *oa = Fa + 2 * ((det * pl->n_seg + K) * nb + ii), *ob = Fb + 2 * ((det * pl->n_seg + K) * nb + ii);
+        oa[0] = ra * scale;
+        oa[1] = ia * scale;
+        ob[0] = rbb * scale;
+        ob[1] = ib * scale;
+    }
+}
+
+static void rho_from_streams(const cco_problem *p, const cco_plan *pl, const double *Fa, const double *Fb,
+                             int64_t nb, double N, double *rho) {
+    int R = p->band.max_lag;
+    for (int64_t ii = 0; ii < nb; ++ii) {
+        double acc = 0.0;
+        for (int X = 0; X < p->n_det; ++X)
+            for (int64_t K = 0; K < pl->n_seg; ++K)
+                for (int Y = 0; Y < p->n_det; ++Y)
+                    for (int64_t L = lag_lo(p, K); L <= lag_hi(p, pl, K); ++L) {
+                        if (L < 0 || L >= pl->n_seg || !pair_in_set(p->band.pairs, R, X, K, Y, L)) continue;
+                        const double *ak = Fa + 2 * ((X * pl->n_seg + K) * nb + ii);
+                        const double *bk = Fb + 2 * ((X * pl->n_seg + K) * nb + ii);
+                        const double *al = Fa + 2 * ((Y * pl->n_seg + L) * nb + ii);
+                        const double *bl = Fb + 2 * ((Y * pl->n_seg + L) * nb + ii);
+                        if (p->band.weight == 0)  /* Re conj(a_K) a_L + Re conj(b_K) b_L */
+                            acc += ak[0] * al[0] + ak[1] * al[1] + bk[0] * bl[0] + bk[1] * bl[1];
+                        else                      /* Im conj(b_K) a_L - Im conj(a_K) b_L */
+                            acc += (bk[0] * al[1] - bk[1] * al[0]) - (ak[0] * bl[1] - ak[1] * bl[0]);
+                    }
+        rho[ii] = (N > 0.0) ? sqrt(2.0) * acc / N : 0.0;
+    }
+}
+
+static double stream_norm_of(const cco_problem *p, const cco_plan *pl) {
+    int64_t nr = pl->n_seg * pl->n_k;
+    uint8_t *masks = (uint8_t *)malloc((size_t)(p->n_det * nr));
+    double *abc = (double *)malloc(sizeof(double) * 3 * (size_t)(p->n_det * pl->n_seg));
+    if (!masks || !abc) {
+        free(masks); free(abc);
+        return -1.0;
+    }
+    for (int X = 0; X < p->n_det; ++X) earth_only_mask(p, pl, X, masks + X * nr);
+    stream_moments(p, pl, masks, abc);
+    double N = stream_norm(p, pl, abc);
+    free(masks); free(abc);
+    return N;
+}
+
 double cco_norm(const cco_problem *p) {
     cco_plan pl;
     if (validate(p, &pl)) return -1.0;
+    if (per_sample(p) || p->band.weight != 0) return stream_norm_of(p, &pl);
     double *phi = (double *)malloc(sizeof(double) * (size_t)(p->n_det * pl.n_seg));
     if (!phi) return -1.0;
     cco_valid_fraction(p, phi);
@@ -521,7 +737,7 @@ static void rho_from_spectra(const cco_problem *p, const cco_plan *pl, const dou
         for (int X = 0; X < p->n_det; ++X)
             for (int64_t K = 0; K < pl->n_seg; ++K)
                 for (int Y = 0; Y < p->n_det; ++Y)
-                    for (int64_t L = K - R; L <= K + R; ++L) {
+                    for (int64_t L = lag_lo(p, K); L <= lag_hi(p, pl, K); ++L) {
                         if (L < 0 || L >= pl->n_seg || !pair_in_set(p->band.pairs, R, X, K, Y, L)) continue;
                         double sK = sqrt(p->noise_var[X][K]), sL = sqrt(p->noise_var[Y][L]);
                         double W = (p->a[X][K] / sK) * (p->a[Y][L] / sL) + (p->b[X][K] / sK) * (p->b[Y][L] / sL);
@@ -533,6 +749,48 @@ static void rho_from_spectra(const cco_problem *p, const cco_plan *pl, const dou
     }
 }
 
+/* rho through the weighted streams (per-sample antenna functions or the Gamma^circ weight),
+ * tier R only. */
+static int rho_streams(const cco_problem *p, const cco_plan *pl, const double *tmpl, int64_t n_tmpl,
+                       const int64_t *bins, int64_t nb, double *rho) {
+    int64_t nr = pl->n_seg * pl->n_k;
+    int Q = p->n_det;
+    int stride = p->ecc ? 5 : 3;
+    uint8_t *masks = (uint8_t *)malloc((size_t)(Q * nr));
+    double *abc = (double *)malloc(sizeof(double) * 3 * (size_t)(Q * pl->n_seg));
+    double *tw = twiddles(pl->n_fft);
+    size_t fsz = (size_t)(Q * pl->n_seg * nb) * 2;
+    double *Fa = (double *)malloc(sizeof(double) * fsz), *Fb = (double *)malloc(sizeof(double) * fsz);
+    int nth = cco_num_threads();
+    double *y = (double *)malloc(sizeof(double) * 2 * (size_t)pl->n_k * (size_t)nth);
+    if (!masks || !abc || !tw || !Fa || !Fb || !y) {
+        free(masks); free(abc); free(tw); free(Fa); free(Fb); free(y);
+        return CCO_ENOMEM;
+    }
+#pragma omp parallel for schedule(dynamic, 64)
+    for (int64_t w = 0; w < Q * pl->n_seg; ++w)
+        earth_only_mask_segment(p, pl, (int)(w / pl->n_seg), w % pl->n_seg, masks + (w / pl->n_seg) * nr);
+    stream_moments(p, pl, masks, abc);
+    double N = stream_norm(p, pl, abc);
+    for (int64_t t = 0; t < n_tmpl; ++t) {
+#pragma omp parallel for schedule(dynamic, 16)
+        for (int64_t w = 0; w < Q * pl->n_seg; ++w) {
+            int X = (int)(w / pl->n_seg);
+            int64_t K = w % pl->n_seg;
+#ifdef _OPENMP
+            double *yt = y + 2 * (size_t)pl->n_k * (size_t)omp_get_thread_num();
+#else
+            double *yt = y;
+#endif
+            resample_segment(p, pl, X, tmpl + stride * t, masks + X * nr, K, yt, NULL, NULL);
+            streams_segment(p, pl, X, K, yt, tw, bins, nb, Fa, Fb);
+        }
+        rho_from_streams(p, pl, Fa, Fb, nb, N, rho + t * nb);
+    }
+    free(masks); free(abc); free(tw); free(Fa); free(Fb); free(y);
+    return CCO_OK;
+}
+
 int cco_rho(const cco_problem *p, const double *tmpl, int64_t n_tmpl, int tier,
             const int64_t *bins, int64_t n_bins, double *rho) {
     cco_plan pl;
@@ -541,8 +799,13 @@ int cco_rho(const cco_problem *p, const double *tmpl, int64_t n_tmpl, int tier,
     int64_t nb = bins ? n_bins : pl.n_f;
     for (int64_t ii = 0; ii < nb; ++ii)
         if (bins && (bins[ii] < 0 || bins[ii] >= pl.n_f)) return CCO_EINVAL;
+    if (per_sample(p) || p->band.weight != 0) {
+        if (tier != 0) return CCO_EINVAL;
+        return rho_streams(p, &pl, tmpl, n_tmpl, bins, nb, rho);
+    }
     int64_t nr = pl.n_seg * pl.n_k;
     int Q = p->n_det;
+    const int stride = p->ecc ? 5 : 3;
     uint8_t *masks = (uint8_t *)malloc((size_t)(Q * nr));
     double *phi = (double *)malloc(sizeof(double) * (size_t)(Q * pl.n_seg));
     double *tw = twiddles(pl.n_fft);
@@ -586,13 +849,13 @@ int cco_rho(const cco_problem *p, const double *tmpl, int64_t n_tmpl, int tier,
 #else
                 double *yt = y;
 #endif
-                resample_segment(p, &pl, X, tmpl + 3 * (g + tl), masks + X * nr, K, yt, NULL, NULL);
+                resample_segment(p, &pl, X, tmpl + stride * (g + tl), masks + X * nr, K, yt, NULL, NULL);
                 spectra_segment(p, &pl, X, K, yt, tw, bins, nb, F + fsz * (size_t)tl);
             }
         } else {
 #pragma omp parallel for schedule(dynamic, 1)
             for (int64_t w = 0; w < gn * Q; ++w)
-                spectra_direct(p, &pl, (int)(w % Q), tmpl + 3 * (g + w / Q), bins, nb, F + fsz * (size_t)(w / Q));
+                spectra_direct(p, &pl, (int)(w % Q), tmpl + stride * (g + w / Q), bins, nb, F + fsz * (size_t)(w / Q));
         }
 #pragma omp parallel for schedule(dynamic, 1)
         for (int64_t tl = 0; tl < gn; ++tl) rho_from_spectra(p, &pl, F + fsz * (size_t)tl, nb, N, rho + (g + tl) * nb);

@@ -22,6 +22,8 @@ extern "C" {
 #define CCO_MAX_DET 8
 #define CCO_PAIRS_CROSS 1
 #define CCO_PAIRS_SAME 2
+#define CCO_PAIRS_ALL 4   /* every ordered pair of segments of every detector, auto-correlations
+                             included, any lag (App. A.1-A.2: the F-statistic limit) */
 
 enum { CCO_OK = 0, CCO_EINVAL = -1, CCO_ENOMEM = -2, CCO_ERANGE = -5 };
 
@@ -40,9 +42,10 @@ typedef struct {
     int window;           /* 0: Hamming indexed by tap; 1: Hamming at the continuous offset */
     int n_fft_override;   /* 0: eq. n-fft-final; else N_FFT (multiple of the pow2 >= N_K) */
     double mu_f;          /* frequency mismatch */
-    int pairs;            /* CCO_PAIRS_CROSS | CCO_PAIRS_SAME */
+    int pairs;            /* CCO_PAIRS_CROSS | CCO_PAIRS_SAME, or CCO_PAIRS_ALL */
     double a_p_max;       /* largest a_p (sizes the Doppler wings) */
     double orbit_period;  /* P used for the wing width */
+    int weight;           /* 0: Gamma^ave (eq. geometric-filter); 1: Gamma^circ (Sec. II.B) */
 } cco_band;
 
 typedef struct {
@@ -61,6 +64,12 @@ typedef struct {
     const float *x[CCO_MAX_DET];            /* interleaved complex, n each */
     const uint8_t *valid[CCO_MAX_DET];      /* n each, or NULL = all valid */
     const double *a[CCO_MAX_DET], *b[CCO_MAX_DET], *noise_var[CCO_MAX_DET];  /* n_seg each */
+    /* per-sample antenna functions a(tau_r), b(tau_r) on the source lattice (n_seg * n_k each,
+       Sec. III.B.3 eq. norm-a-eq), or NULL: per-segment a, b above */
+    const double *ar[CCO_MAX_DET], *br[CCO_MAX_DET];
+    /* 0: templates (a_p, T_asc, P), circular orbit; 1: templates (a_p, T_p, omega, e, P),
+       eccentric orbit (Sec. II.A.2 eqs. solve-for-E, Kepler-equation) */
+    int ecc;
 } cco_problem;
 
 int cco_plan_band(const cco_problem *p, cco_plan *out);
@@ -69,28 +78,31 @@ int64_t cco_bin_index(const cco_plan *pl, int64_t i);
 
 /* Earth Roemer delay r(t).n for detector det at time t. */
 double cco_earth_delay(const cco_problem *p, int det, double t);
-/* Forward map: tau(t) - t for the template (a_p, T_asc, P) (eqs. t-ssb-equation, tau-equation). */
-double cco_forward_offset(const cco_problem *p, int det, const double tmpl[3], double t);
+/* Forward map: tau(t) - t for one template (eqs. t-ssb-equation, tau-equation); a template
+   is 3 doubles (a_p, T_asc, P) or, with ecc, 5 (a_p, T_p, omega, e, P). */
+double cco_forward_offset(const cco_problem *p, int det, const double *tmpl, double t);
+/* Eccentric anomaly E of mean anomaly M: E - e sin E = M (eq. solve-for-E). */
+double cco_kepler(double M, double e);
 /* Delay Delta_r = t_r - tau_r of source sample r (inverse map, long double Newton).
    Writes Delta as hi + lo doubles. */
-int cco_delay(const cco_problem *p, int det, const double tmpl[3], int64_t r, double *hi, double *lo);
+int cco_delay(const cco_problem *p, int det, const double *tmpl, int64_t r, double *hi, double *lo);
 
 /* Resampled series of one detector for one template: y (2 * n_seg * n_k doubles,
    interleaved), optional jstar / offset / mask per sample (may be NULL). */
-int cco_resample(const cco_problem *p, int det, const double tmpl[3], double *y,
+int cco_resample(const cco_problem *p, int det, const double *tmpl, double *y,
                  int64_t *jstar, double *offset, uint8_t *mask);
 /* Segment valid fractions phi[det][K] (n_det * n_seg). */
 int cco_valid_fraction(const cco_problem *p, double *phi);
 /* Per-segment spectra F[det][K][i] (2 * n_det * n_seg * n_bins doubles), tier 0 = resampled
    (method steps), tier 1 = direct detector-frame demodulation with no interpolation.
    bins: indices into 0..n_f-1, or NULL for all. */
-int cco_spectra(const cco_problem *p, const double tmpl[3], int tier, const int64_t *bins,
+int cco_spectra(const cco_problem *p, const double *tmpl, int tier, const int64_t *bins,
                 int64_t n_bins, double *F);
 /* Normalisation sqrt(sum_P A A + 2 C C + B B). */
 double cco_norm(const cco_problem *p);
 /* Number of pairs in P. */
 int64_t cco_pair_count(const cco_problem *p);
-/* rho[t][i] for n_tmpl templates (rows a_p, T_asc, P), OpenMP over templates. */
+/* rho[t][i] for n_tmpl templates (rows of 3 or, with ecc, 5), OpenMP over templates. */
 int cco_rho(const cco_problem *p, const double *tmpl, int64_t n_tmpl, int tier,
             const int64_t *bins, int64_t n_bins, double *rho);
 int cco_num_threads(void);

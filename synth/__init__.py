@@ -22,7 +22,7 @@ configuration.
 """
 
 from .model import (  # noqa: F401
-    SPEED_OF_LIGHT, default_sky, site, SITES, earth_roemer, forward_delay,
+    SPEED_OF_LIGHT, default_sky, site, SITES, earth_roemer, forward_delay, forward_delay_ecc, kepler_E,
     antenna_ab, load_bandwidth, samples_per_segment,
 )
 from .configs import CONFIGS, config  # noqa: F401

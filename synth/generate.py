@@ -7,7 +7,8 @@ from dataclasses import dataclass, field
 
 import numpy as np
 
-from .model import SITES, antenna_ab, default_sky, earth_roemer, forward_delay, samples_per_segment
+from .model import (SITES, antenna_ab, default_sky, earth_roemer, forward_delay, forward_delay_ecc,
+                    samples_per_segment)
 
 
 @dataclass
@@ -26,9 +27,12 @@ class Dataset:
     a: np.ndarray          # (Q, M) float64, a(t) at segment mid-times
     b: np.ndarray          # (Q, M)
     noise_var: np.ndarray  # (Q, M) noise variance E|x'|^2 per sample
-    templates: np.ndarray  # (T, 3) columns a_p, T_asc, P
+    templates: np.ndarray  # (T, 3) columns a_p, T_asc, P; eccentric: (T, 5) a_p, T_p, omega, e, P
     injections: list = field(default_factory=list)
     name: str = ""
+    ar: np.ndarray = None  # (Q, M N_K) a(tau_r) on the source lattice (per-sample weighting), or None
+    br: np.ndarray = None
+    ecc: bool = False      # templates are eccentric orbits
 
     @property
     def n_det(self):
@@ -102,7 +106,7 @@ def _random_injections(rng, count, band, tspec, t_asc0, period):
 
 
 def make_dataset(cfg, seed=None, signal=True, noise=True, sky=None, antenna_piecewise=False,
-                 sigma_wander=0.0, chunk=1 << 20, workers=None):
+                 sigma_wander=0.0, chunk=1 << 20, workers=None, per_sample_antenna=False):
     """Build a dataset from a workload dict (see ``configs.CONFIGS``).
 
     ``sky`` overrides Earth-model/sky fields (e.g. ``au_s=0`` to switch off the
@@ -110,7 +114,9 @@ def make_dataset(cfg, seed=None, signal=True, noise=True, sky=None, antenna_piec
     at the mid-segment values over each segment (closed-form tests).
     ``sigma_wander`` makes the noise level vary slowly from segment to segment.
     ``workers`` threads synthesise the injected signals chunk by chunk (default: CPU count,
-    at most 16); the result does not depend on it.
+    at most 16); the result does not depend on it.  ``per_sample_antenna`` also stores a(tau_r),
+    b(tau_r) on the source lattice (ds.ar, ds.br).  An injection with keys ``ecc``, ``w`` and
+    ``t_p_off`` follows an eccentric orbit (periapse time t_asc0 + t_p_off).
     """
     if workers is None:
         workers = min(16, os.cpu_count() or 1)
@@ -191,7 +197,11 @@ def make_dataset(cfg, seed=None, signal=True, noise=True, sky=None, antenna_piec
                 at, bt = antenna_ab(tj, s, skyd)
             ej = earth_roemer(tj, s, skyd)
             for inj in injections:
-                d = forward_delay(tj, s, skyd, inj["a_p"], inj["t_asc"], inj["period"], e=ej)
+                if "ecc" in inj:
+                    d = forward_delay_ecc(tj, s, skyd, inj["a_p"], t_asc0 + inj["t_p_off"], inj["w"], inj["ecc"],
+                                          inj["period"], e=ej)
+                else:
+                    d = forward_delay(tj, s, skyd, inj["a_p"], inj["t_asc"], inj["period"], e=ej)
                 if antenna_piecewise:
                     # hold a, b at the value of the source-frame segment the sample lands in
                     kidx = np.clip(np.floor((tj + d - t0) / t_short).astype(np.int64), 0, n_seg - 1)
@@ -216,9 +226,15 @@ def make_dataset(cfg, seed=None, signal=True, noise=True, sky=None, antenna_piec
         x[X] = xs_all.astype(np.complex64)
 
     templates = template_grid(cfg["templates"], t_asc0)
+    ar = br = None
+    if per_sample_antenna:
+        tau = t0 + np.arange(n_seg * n_k) * dt
+        ab = [antenna_ab(tau, s_, skyd) for s_ in sites]
+        ar = np.stack([v[0] for v in ab])
+        br = np.stack([v[1] for v in ab])
     return Dataset(sky=skyd, band=band, sites=sites, dt=dt, t0=t0, n=n, n_k=n_k, n_seg=n_seg,
                    f_het=f_het, x=x, valid=valid, a=a, b=b, noise_var=noise_var,
-                   templates=templates, injections=injections, name=cfg.get("name", ""))
+                   templates=templates, injections=injections, name=cfg.get("name", ""), ar=ar, br=br)
 
 
 def multiband_bands(spec):

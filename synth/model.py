@@ -101,6 +101,30 @@ def forward_delay(t, s, sky, a_p, t_asc, period, e=None):
     return t_ssb_minus_t - a_p * np.sin(ang)
 
 
+def kepler_E(M, ecc, iters=40):
+    """Eccentric anomaly for mean anomaly M (array) and eccentricity ecc: E - ecc sin E = M,
+    Newton iterations from E = M + ecc sin M (vectorised, float64)."""
+    M = np.asarray(M, dtype=np.float64)
+    E = M + ecc * np.sin(M)
+    for _ in range(iters):
+        E = E - (E - ecc * np.sin(E) - M) / (1.0 - ecc * np.cos(E))
+    return E
+
+
+def forward_delay_ecc(t, s, sky, a_p, t_p, omega_p, ecc, period, e=None):
+    """tau(t) - t for an eccentric binary orbit (forward map, explicit): t_SSB = t + r.n,
+    mean anomaly Omega (t_SSB - T_p) = E - ecc sin E, R/c = a_p [sin w (cos E - ecc) +
+    cos w sqrt(1 - ecc^2) sin E] (eqs. solve-for-E, Kepler-equation), tau = t_SSB - R/c."""
+    if e is None:
+        e = earth_roemer(t, s, sky)
+    omega = 2.0 * math.pi / period
+    M = omega * (np.asarray(t, dtype=np.float64) - t_p) + omega * e
+    M = np.mod(M, 2.0 * math.pi)
+    E = kepler_E(M, ecc)
+    R = a_p * (math.sin(omega_p) * (np.cos(E) - ecc) + math.cos(omega_p) * math.sqrt(1.0 - ecc * ecc) * np.sin(E))
+    return e - R
+
+
 def antenna_ab(t, s, sky):
     """Beam-pattern functions a(t) = F+(psi=0), b(t) = Fx(psi=0).
 

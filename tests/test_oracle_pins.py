@@ -373,6 +373,22 @@ def test_matched_signal_closed_form_amplitude():
     assert r.argmax() == i0
 
 
+def _edge_phi(ds):
+    """Valid fraction per segment: source samples whose Earth-only arrival lies outside the data
+    carry no weight; the Earth-only inverse t + r.n = tau is solved here by fixed point."""
+    nr = ds.n_seg * ds.n_k
+    tau = ds.t0 + np.arange(nr) * ds.dt
+    phi = np.zeros((ds.n_det, ds.n_seg))
+    for X in range(ds.n_det):
+        t = tau.copy()
+        for _ in range(8):
+            t = tau - synth.earth_roemer(t, ds.sites[X], ds.sky)
+        j = np.arange(nr) + np.floor((t - tau) / ds.dt + 0.5).astype(np.int64)
+        inside = ((j >= 0) & (j < ds.n)).astype(float)
+        phi[X] = inside.reshape(ds.n_seg, ds.n_k).mean(axis=1)
+    return phi
+
+
 def test_matched_signal_with_delays_and_peak_location():
     """With Earth and binary Roemer delays the matched template still recovers the closed-form
     amplitude within the interpolation budget (Sec. III.A.1) and peaks at the injected bin and
@@ -392,18 +408,7 @@ def test_matched_signal_with_delays_and_peak_location():
     good = np.array([[1.6, t_asc, 68023.7]])
     off = np.array([[1.6, t_asc + 900.0, 68023.7], [1.1, t_asc, 68023.7]])
     r = o.rho(np.vstack([good, off]))
-    # valid fraction per segment: source samples whose Earth-only arrival lies outside the data
-    # carry no weight; the Earth-only inverse t + r.n = tau is solved here by fixed point.
-    nr = ds.n_seg * ds.n_k
-    tau = ds.t0 + np.arange(nr) * ds.dt
-    phi = np.zeros((2, ds.n_seg))
-    for X in range(2):
-        t = tau.copy()
-        for _ in range(8):
-            t = tau - synth.earth_roemer(t, ds.sites[X], ds.sky)
-        j = np.arange(nr) + np.floor((t - tau) / ds.dt + 0.5).astype(np.int64)
-        inside = ((j >= 0) & (j < ds.n)).astype(float)
-        phi[X] = inside.reshape(ds.n_seg, ds.n_k).mean(axis=1)
+    phi = _edge_phi(ds)
     assert phi.min() < 1.0          # the data edges do cut the first or last segments
     pred = math.sqrt(2) / 4 * pl.n_k * 0.3 ** 2 * math.sqrt(_w2(ds, 1, pairs=1, phi=phi))
     assert r[0].argmax() == i0
@@ -452,3 +457,249 @@ def test_demod_two_bin_value_quadrature():
     from scipy.integrate import quad
     v = 2 * quad(lambda k: np.sinc(k) ** 2, 0, GOLD["xi2_demod_m2"]["m"] / 2)[0]
     assert round(v, 3) == GOLD["xi2_demod_m2"]["value"]
+
+
+# --------------------------------------------- all pairs (the F-statistic limit)
+
+def _circ_weights(ds, M):
+    """a_K = cos(theta_K), b_K = sin(theta_K), theta_K = 2 pi K / M (M a multiple of 4): the sums
+    of a^2 and b^2 over segments are equal and the sum of a b vanishes (A = B, C = 0)."""
+    th = 2.0 * math.pi * np.arange(M) / M
+    for X in range(ds.n_det):
+        ds.a[X] = np.cos(th + 0.3 * X)
+        ds.b[X] = np.sin(th + 0.3 * X)
+
+
+def test_all_pairs_noise_is_chi2_4():
+    """App. A.2: with every pair, auto-correlations included, rho = sqrt2 (|F_a|^2 + |F_b|^2) /
+    sqrt(A^2 + 2 C^2 + B^2); in Gaussian noise with A = B and C = 0, 2 rho is the F-statistic's
+    chi-squared variable with 4 degrees of freedom (mean 4, variance 8), checked over 300 seeds
+    with a Kolmogorov-Smirnov test against scipy's distribution."""
+    from scipy import stats
+    vals = []
+    for seed in range(300):
+        cfg = small_config(n_seg=12, max_lag=1, pairs=4, seed=500 + seed, sigma=[1.0, 1.0])
+        ds = synth.make_dataset(cfg, signal=False, sky=NO_EARTH)
+        _circ_weights(ds, 12)
+        o = oracle.Oracle(ds)
+        r = o.rho(np.array([[0.0, 0.0, 68023.7]]), bins=np.arange(2, o.plan().n_f, 11))
+        vals.append(2.0 * r[0])
+    v = np.concatenate(vals)
+    n = len(v)
+    assert abs(v.mean() - 4.0) < 5.0 * math.sqrt(8.0 / n)
+    assert abs(v.var() - 8.0) < 5.0 * math.sqrt(np.var((v - 4.0) ** 2) / n)
+    assert stats.kstest(v, stats.chi2(4).cdf).pvalue > 1e-3
+
+
+def _matched_zero_delay(cfg, cosi, psi=0.7, per_sample=False, piecewise=True, i0=31):
+    ds0 = synth.make_dataset(cfg, signal=False, sky=NO_EARTH)
+    o0 = oracle.Oracle(ds0)
+    pl = o0.plan()
+    f0 = ds0.f_het + o0.bins()[i0] / pl.t_fft
+    cfg = dict(cfg, injections=[dict(f0=f0, a_p=0.0, t_asc_off=0.0, period=68023.7, h0=0.3, cosi=cosi, psi=psi,
+                                     phi0=1.1)])
+    ds = synth.make_dataset(cfg, noise=False, sky=NO_EARTH, antenna_piecewise=piecewise, sigma_wander=0.2,
+                            per_sample_antenna=per_sample)
+    return ds, pl, i0
+
+
+def test_all_pairs_matched_signal_closed_form():
+    """All pairs, noiseless circularly polarised matched signal, zero delay, antennas constant
+    per segment: F_K = sqrt(N_K) h0 (a_K - i b_K) e^{i theta} / (2 sigma_K), so |F_a|^2 + |F_b|^2 =
+    N_K h0^2 [(sum A)^2 + 2 (sum C)^2 + (sum B)^2] / 4 and rho = (sqrt2/4) N_K h0^2
+    sqrt((sum A)^2 + 2 (sum C)^2 + (sum B)^2) with A = hat a^2, B = hat b^2, C = hat a hat b."""
+    cfg = small_config(n_seg=16, max_lag=1, pairs=4, sigma=[1.0, 1.4])
+    ds, pl, i0 = _matched_zero_delay(cfg, cosi=1.0)
+    r = oracle.Oracle(ds).rho(np.array([[0.0, 0.0, 68023.7]]))[0]
+    sig = np.sqrt(ds.noise_var)
+    A = np.sum((ds.a / sig) ** 2)
+    B = np.sum((ds.b / sig) ** 2)
+    C = np.sum(ds.a * ds.b / sig ** 2)
+    pred = math.sqrt(2) / 4 * pl.n_k * 0.3 ** 2 * math.sqrt(A * A + 2 * C * C + B * B)
+    assert abs(r[i0] / pred - 1.0) < 1e-6
+    assert r.argmax() == i0
+
+
+# ------------------------------------------------------------ Gamma^circ
+
+def _circ_w2(ds, R, pairs=3):
+    Q, M = ds.a.shape
+    s = 0.0
+    for X in range(Q):
+        for K in range(M):
+            for Y in range(Q):
+                for L in range(max(0, K - R), min(M, K + R + 1)):
+                    if not (((pairs & 1) and X < Y) or ((pairs & 2) and X == Y and L > K)):
+                        continue
+                    sK, sL = math.sqrt(ds.noise_var[X, K]), math.sqrt(ds.noise_var[Y, L])
+                    G = ds.a[X, K] / sK * ds.b[Y, L] / sL - ds.b[X, K] / sK * ds.a[Y, L] / sL
+                    s += G * G
+    return s
+
+
+@pytest.mark.parametrize("cosi", [1.0, -1.0, 0.0])
+def test_circ_weight_matched_signal_closed_form(cosi):
+    """Sec. II.B Gamma^circ = hat a_K hat b_L - hat b_K hat a_L: for a matched circularly polarised
+    signal (zero delay, antennas constant per segment) conj(F_K) F_L = N_K h0^2 [(hat a_K hat a_L +
+    hat b_K hat b_L) + i (hat b_K hat a_L - hat a_K hat b_L)] / 4, so rho_circ = +-(sqrt2/4) N_K h0^2
+    sqrt(sum_P Gamma^circ^2) for cos iota = +-1, and 0 for a linearly polarised one."""
+    cfg = small_config(n_seg=16, max_lag=2, pairs=3, sigma=[1.0, 1.4])
+    cfg["band"]["weight"] = 1
+    ds, pl, i0 = _matched_zero_delay(cfg, cosi=cosi)
+    ds.band = dict(ds.band, weight=1)
+    r = oracle.Oracle(ds).rho(np.array([[0.0, 0.0, 68023.7]]))[0]
+    pred = math.sqrt(2) / 4 * pl.n_k * 0.3 ** 2 * math.sqrt(_circ_w2(ds, 2))
+    if cosi == 0.0:
+        assert abs(r[i0]) < 1e-9 * pred
+    else:
+        assert abs(r[i0] / (cosi * pred) - 1.0) < 1e-6
+
+
+@pytest.mark.parametrize("mode", ["circ", "per_sample"])
+def test_weighted_streams_unit_variance_in_noise(mode):
+    """Normalisation of the weighted streams (Gamma^circ: N^2 = sum_P A_K B_L + B_K A_L - 2 C_K C_L;
+    per-sample antenna functions: A_K the segment mean of m_r hat a_r^2, ...): E rho = 0 and
+    Var rho = 1 in Gaussian noise with gaps, uneven noise, R = 2, both pair kinds."""
+    vals = []
+    for seed in range(200):
+        cfg = small_config(n_seg=12, max_lag=2, gap_fraction=0.15, seed=900 + seed, sigma=[1.0, 1.7])
+        if mode == "circ":
+            cfg["band"]["weight"] = 1
+        ds = synth.make_dataset(cfg, signal=False, sky=NO_EARTH, sigma_wander=0.3,
+                                per_sample_antenna=(mode == "per_sample"))
+        if mode == "per_sample":  # a fast-varying weighting, so that per-sample weights matter
+            r_idx = np.arange(ds.ar.shape[1])
+            ds.ar = ds.ar * (1.0 + 0.5 * np.cos(2 * np.pi * r_idx / 97.0))
+            ds.br = ds.br * (1.0 + 0.5 * np.sin(2 * np.pi * r_idx / 61.0))
+        o = oracle.Oracle(ds)
+        r = o.rho(np.array([[0.0, 0.0, 68023.7]]), bins=np.arange(2, o.plan().n_f, 9))
+        vals.append(r[0])
+    v = np.concatenate(vals)
+    n = len(v)
+    assert abs(v.mean()) < 5.0 / math.sqrt(n)
+    assert abs(v.var() - 1.0) < 5.0 * math.sqrt(2.0 / n)
+
+
+# ---------------------------------------------- per-sample antenna weighting
+
+def test_per_sample_antenna_constant_per_segment_reduces():
+    """Sec. III.B.3: per-sample a_r, b_r that are constant over each segment give the per-segment
+    statistic (F^a = hat a_K F, F^b = hat b_K F) to rounding."""
+    cfg = small_config(n_seg=10, max_lag=2, gap_fraction=0.2,
+                       injections=[dict(f0=50.21, a_p=1.25, t_asc_off=0.0, period=68023.7, h0=0.35, cosi=0.5,
+                                        psi=0.3, phi0=1.0)])
+    ds = synth.make_dataset(cfg, sigma_wander=0.2)
+    ref = oracle.Oracle(ds).rho(ds.templates[:3])
+    ds.ar = np.repeat(ds.a, ds.n_k, axis=1)
+    ds.br = np.repeat(ds.b, ds.n_k, axis=1)
+    got = oracle.Oracle(ds).rho(ds.templates[:3])
+    assert np.max(np.abs(got - ref)) < 1e-11 * max(1.0, np.abs(ref).max())
+
+
+def test_per_sample_antenna_matched_signal_closed_form():
+    """Per-sample weighting with the true a(t), b(t) (eq. norm-a-eq) for a matched circularly
+    polarised signal with continuously varying antenna response, zero delay:
+    F^a_K = sqrt(N_K) h0 (A_K - i C_K) e^{i theta} / 2, F^b_K = sqrt(N_K) h0 (C_K - i B_K) e^{i theta} / 2
+    with segment means A_K = <hat a^2>, B_K = <hat b^2>, C_K = <hat a hat b> (computed here from the
+    antenna model), so rho = (sqrt2/4) N_K h0^2 sqrt(sum_P A_K A_L + 2 C_K C_L + B_K B_L)."""
+    cfg = small_config(n_seg=16, max_lag=2, pairs=3, sigma=[1.0, 1.4], t_short=2400.0)
+    ds, pl, i0 = _matched_zero_delay(cfg, cosi=1.0, per_sample=True, piecewise=False, i0=20)
+    r = oracle.Oracle(ds).rho(np.array([[0.0, 0.0, 68023.7]]))[0]
+    Q, M, nk = ds.n_det, ds.n_seg, ds.n_k
+    sig = np.sqrt(ds.noise_var)[:, :, None]
+    ar = ds.ar.reshape(Q, M, nk) / sig
+    br = ds.br.reshape(Q, M, nk) / sig
+    A, B, C = (ar * ar).mean(axis=2), (br * br).mean(axis=2), (ar * br).mean(axis=2)
+    s = 0.0
+    for X in range(Q):
+        for K in range(M):
+            for Y in range(Q):
+                for L in range(max(0, K - 2), min(M, K + 3)):
+                    if (X < Y) or (X == Y and L > K):
+                        s += A[X, K] * A[Y, L] + 2 * C[X, K] * C[Y, L] + B[X, K] * B[Y, L]
+    pred = math.sqrt(2) / 4 * pl.n_k * 0.3 ** 2 * math.sqrt(s)
+    assert abs(r[i0] / pred - 1.0) < 1e-6
+    # per-segment weights (antenna at the mid-time) recover less of this signal
+    ds_seg = synth.make_dataset(cfg, noise=False, sky=NO_EARTH, sigma_wander=0.2)
+    ds_seg.x = ds.x
+    r_seg = oracle.Oracle(ds_seg).rho(np.array([[0.0, 0.0, 68023.7]]))[0]
+    assert r_seg[i0] < r[i0]
+
+
+# ------------------------------------------------------- eccentric orbits
+
+def test_kepler_against_bracketing_root_finder():
+    """eq. solve-for-E: the oracle's E solves E - e sin E = M, compared with scipy's brentq on a
+    grid of mean anomalies and eccentricities."""
+    from scipy.optimize import brentq
+    for e in (0.0, 0.05, 0.3, 0.7, 0.95):
+        for M in np.linspace(0.0, 2 * math.pi, 37):
+            ref = brentq(lambda E: E - e * math.sin(E) - M, M - 1.0 - e, M + 1.0 + e, xtol=1e-15, rtol=1e-15)
+            assert abs(oracle.kepler(M, e) - ref) < 1e-13
+
+
+def _ecc_dataset(**kw):
+    ds = synth.make_dataset(small_config(n_seg=6, t_short=600.0, **kw), signal=False)
+    ds.ecc = True
+    return ds
+
+
+def test_eccentric_zero_e_is_circular():
+    """eq. Kepler-equation with e = 0: R/c = a_p sin(Omega (t - T_p) + omega), the circular orbit
+    with T_asc = T_p - omega / Omega; delays of both template forms agree."""
+    ds = _ecc_dataset()
+    oe = oracle.Oracle(ds)
+    ds.ecc = False
+    oc = oracle.Oracle(ds)
+    P, w, tp = 68023.7, 1.1, 7000.0
+    for r in (0, 517, 2 * ds.n_k + 3, ds.n_seg * ds.n_k - 1):
+        for X in range(2):
+            he, le = oe.delay(X, np.array([1.4, tp, w, 0.0, P]), r)
+            hc, lc = oc.delay(X, np.array([1.4, tp - w * P / (2 * math.pi), P]), r)
+            assert abs((he - hc) + (le - lc)) < 1e-12
+
+
+def test_eccentric_inverse_map_round_trip_against_independent_forward_model():
+    """The inverse map t(tau) with an eccentric binary (e = 0.3 and 0.6) against an independent
+    numpy forward model (synth.forward_delay_ecc, its own vectorised Kepler solve)."""
+    ds = _ecc_dataset()
+    o = oracle.Oracle(ds)
+    rng = np.random.default_rng(8)
+    for e in (0.3, 0.6):
+        for det in range(2):
+            for _ in range(5):
+                tm = np.array([rng.uniform(1.0, 2.0), rng.uniform(0, 7e4), rng.uniform(0, 2 * math.pi), e, 68023.7])
+                r = int(rng.integers(0, ds.n_k * ds.n_seg))
+                hi, lo = o.delay(det, tm, r)
+                tau = ds.t0 + r * ds.dt
+                t = tau + hi + lo
+                off = synth.forward_delay_ecc(np.array([t]), ds.sites[det], ds.sky, tm[0], tm[1], tm[2], tm[3],
+                                              tm[4])[0]
+                assert abs(t + off - tau) < 2e-9
+                assert abs(o.forward_offset(det, tm, t)[0] + hi + lo) < 1e-12
+
+
+def test_eccentric_matched_template_recovers_injection():
+    """An eccentric (e = 0.4) injection is recovered by its own eccentric template at the injected
+    bin within the interpolation budget of the closed-form amplitude, while the circular template
+    with the same a_p and ascending node loses most of it (Sec. II.A.2: resampling handles
+    elliptical orbits)."""
+    cfg = small_config(n_seg=60, t_short=240.0, max_lag=1, pairs=1, sigma=[1.0, 1.0], f_min=100.0, f_band=0.3,
+                       a_p_max=2.0)
+    ds0 = synth.make_dataset(cfg, signal=False)
+    o0 = oracle.Oracle(ds0)
+    pl = o0.plan()
+    i0 = 40
+    f0 = ds0.f_het + o0.bins()[i0] / pl.t_fft
+    w, e, tpo, ap = 0.8, 0.4, 300.0, 1.6
+    cfg["injections"] = [dict(f0=f0, a_p=ap, t_asc_off=0.0, period=68023.7, h0=0.3, cosi=1.0, psi=0.2, phi0=0.3,
+                              ecc=e, w=w, t_p_off=tpo)]
+    ds = synth.make_dataset(cfg, noise=False, antenna_piecewise=True)
+    ds.ecc = True
+    tp = cfg["t_asc0"] + tpo
+    r = oracle.Oracle(ds).rho(np.array([[ap, tp, w, e, 68023.7], [ap, tp - w * 68023.7 / (2 * math.pi), 0.0, 0.0,
+                                                                    68023.7]]))
+    pred = math.sqrt(2) / 4 * pl.n_k * 0.3 ** 2 * math.sqrt(_w2(ds, 1, pairs=1, phi=_edge_phi(ds)))
+    assert r[0].argmax() == i0
+    assert abs(r[0, i0] / pred - 1.0) < 0.03
+    assert r[1].max() < 0.5 * r[0, i0]
