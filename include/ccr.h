@@ -48,10 +48,16 @@
 extern "C" {
 #endif
 
-#define CCR_ABI_VERSION 2
+#define CCR_ABI_VERSION 3
 #define CCR_MAX_DET 8
 #define CCR_PAIRS_CROSS 1 /* pairs across detectors, |K - L| <= R        */
 #define CCR_PAIRS_SAME 2  /* pairs within a detector, 0 < L - K <= R     */
+#define CCR_PAIRS_ALL 4   /* every ordered pair of segments of every detector, auto-correlations
+                             included, any lag: rho = sqrt2 (|F_a|^2 + |F_b|^2) / N, the
+                             F-statistic limit (App. A.1-A.2); not combined with the two above */
+#define CCR_WEIGHT_AVE 0  /* pair weight Gamma^ave (eq. geometric-filter)                     */
+#define CCR_WEIGHT_CIRC 1 /* pair weight Gamma^circ = hat a_K hat b_L - hat b_K hat a_L (Sec.
+                             II.B), on the imaginary part of conj(F_K) F_L              */
 
 typedef struct ccr_ctx ccr_ctx;
 
@@ -101,15 +107,20 @@ typedef struct {
  *   n_fft_override 0: N_FFT from eq. n-fft-final; otherwise N_FFT (a multiple of the power of
  *                  two holding N_K)
  *   mu_f           frequency mismatch (delta lambda_f = sqrt(6 mu_f / pi) / T_coh)
- *   pairs          CCR_PAIRS_CROSS | CCR_PAIRS_SAME
+ *   pairs          CCR_PAIRS_CROSS | CCR_PAIRS_SAME, or CCR_PAIRS_ALL (max_lag then only sets
+ *                  T_coh, hence the frequency resolution)
  *   a_p_max, orbit_period  size the Doppler wings of the load bandwidth (App. B,
- *                  eq. delta-f-load with eqs. f-drift-eq, delta-f-obs, v/c = 1e-4). */
+ *                  eq. delta-f-load with eqs. f-drift-eq, delta-f-obs, v/c = 1e-4)
+ *   weight         CCR_WEIGHT_AVE or CCR_WEIGHT_CIRC.  Gamma^circ:
+ *                  rho = sqrt2 sum_P (hat b_K hat a_L - hat a_K hat b_L) Im(conj(F_K) F_L) / N with
+ *                  N^2 = sum_P A_K B_L + B_K A_L - 2 C_K C_L (positive mean for cos iota > 0). */
 typedef struct {
     double f_min, f_band, t_short;
     int32_t max_lag, dirichlet_D, window, n_fft_override;
     double mu_f;
     int32_t pairs;
     double a_p_max, orbit_period;
+    int32_t weight;
 } ccr_band;
 
 /* Plan of a band.  Fields after n_k / dt are valid once every detector has data. */
@@ -201,6 +212,18 @@ ccr_status ccr_set_data(ccr_ctx *ctx, int band_id, int det, const ccr_site *site
  * segment (> 0).  hat a = a / sigma (Sec. II.B, eq. geometric-filter). */
 ccr_status ccr_set_weights(ccr_ctx *ctx, int band_id, int det, int64_t n_seg, const double *a,
                            const double *b, const double *noise_var);
+
+/* Per-sample antenna functions of detector `det` (Sec. III.B.3, eq. norm-a-eq): a[r], b[r] =
+ * a(tau_r), b(tau_r) on the source lattice tau_r = t0 + r dt, r < n; n must be at least the
+ * band's n_seg * n_k (checked when the band is prepared; CCR_EINVAL).  Once every detector of
+ * the band has them, the resampled series is weighted sample by sample before the FFT, giving
+ * two spectra per segment, F^a_K = FFT(hat a_r y_r) and F^b_K = FFT(hat b_r y_r) (hat a_r =
+ * a_r / sigma_K), and rho = sqrt2 Re sum_P [conj(F^a_K) F^a_L + conj(F^b_K) F^b_L] / N with
+ * N^2 = sum_P A_K A_L + 2 C_K C_L + B_K B_L, A_K the segment mean of m_r hat a_r^2 (m_r the gap
+ * mask), B_K, C_K likewise (Gamma^circ: sqrt2 sum_P Im[conj(F^b_K) F^a_L - conj(F^a_K) F^b_L] / N).
+ * The per-segment a_K, b_K of ccr_set_weights are then not used (their noise_var is).  Copied;
+ * n = 0 (or null arrays) removes them.  NaN/Inf give CCR_EINVAL. */
+ccr_status ccr_set_antenna(ccr_ctx *ctx, int band_id, int det, int64_t n, const double *a, const double *b);
 
 /* Orbital templates of a band (the Doppler parameters lambda of Sec. II.A.2, circular orbit,
  * eq. tau-equation): n triples (a_p [s], T_asc [s after epoch], P [s]).  a_p >= 0, P > 0, all

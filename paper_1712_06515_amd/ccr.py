@@ -14,7 +14,8 @@ LIB_PATH = os.path.join(_PKG, "libccr.so")
 
 OK, EINVAL, ENOMEM, EDEVICE, ESTATE, ERANGE, EUNSUP = 0, -1, -2, -3, -4, -5, -6
 PREC_FP64, PREC_SPLIT = 0, 1
-PAIRS_CROSS, PAIRS_SAME = 1, 2
+PAIRS_CROSS, PAIRS_SAME, PAIRS_ALL = 1, 2, 4
+WEIGHT_AVE, WEIGHT_CIRC = 0, 1
 MAX_DET = 8
 _STATUS = {0: "OK", -1: "EINVAL", -2: "ENOMEM", -3: "EDEVICE", -4: "ESTATE", -5: "ERANGE", -6: "EUNSUP"}
 
@@ -39,7 +40,7 @@ class Band(ctypes.Structure):
     _fields_ = [("f_min", ctypes.c_double), ("f_band", ctypes.c_double), ("t_short", ctypes.c_double),
                 ("max_lag", ctypes.c_int32), ("dirichlet_D", ctypes.c_int32), ("window", ctypes.c_int32),
                 ("n_fft_override", ctypes.c_int32), ("mu_f", ctypes.c_double), ("pairs", ctypes.c_int32),
-                ("a_p_max", ctypes.c_double), ("orbit_period", ctypes.c_double)]
+                ("a_p_max", ctypes.c_double), ("orbit_period", ctypes.c_double), ("weight", ctypes.c_int32)]
 
 
 class BandInfo(ctypes.Structure):
@@ -69,6 +70,7 @@ SIGNATURES = {
     "ccr_set_data": ([_vp, ctypes.c_int, ctypes.c_int, ctypes.POINTER(Site), ctypes.c_double, ctypes.c_double,
                       ctypes.c_int64, ctypes.c_double, _vp, _vp], ctypes.c_int),
     "ccr_set_weights": ([_vp, ctypes.c_int, ctypes.c_int, ctypes.c_int64, _dp, _dp, _dp], ctypes.c_int),
+    "ccr_set_antenna": ([_vp, ctypes.c_int, ctypes.c_int, ctypes.c_int64, _dp, _dp], ctypes.c_int),
     "ccr_set_templates": ([_vp, ctypes.c_int, ctypes.c_int64, _dp, _dp, _dp], ctypes.c_int),
     "ccr_get_band_info": ([_vp, ctypes.c_int, ctypes.POINTER(BandInfo), _dp], ctypes.c_int),
     "ccr_compute_rho": ([_vp, ctypes.c_int, ctypes.c_int, ctypes.POINTER(ctypes.c_int), ctypes.POINTER(_vp),
@@ -156,7 +158,8 @@ class Context:
         b = Band(float(band["f_min"]), float(band["f_band"]), float(band["t_short"]), int(band["max_lag"]),
                  int(band.get("dirichlet_D", 8)), int(band.get("window", 0)), int(band.get("n_fft_override", 0)),
                  float(band.get("mu_f", 0.1)), int(band.get("pairs", PAIRS_CROSS | PAIRS_SAME)),
-                 float(band.get("a_p_max", 0.0)), float(band.get("orbit_period", 68023.70)))
+                 float(band.get("a_p_max", 0.0)), float(band.get("orbit_period", 68023.70)),
+                 int(band.get("weight", WEIGHT_AVE)))
         bid = ctypes.c_int()
         info = BandInfo()
         self._check(self.L.ccr_add_band(self.h, ctypes.byref(b), ctypes.byref(bid), ctypes.byref(info)))
@@ -174,6 +177,17 @@ class Context:
         a_, b_, n_ = _arr(a, np.float64), _arr(b, np.float64), _arr(noise_var, np.float64)
         self._check(self.L.ccr_set_weights(self.h, band_id, det, a_.shape[0],
                                            a_.ctypes.data_as(_dp), b_.ctypes.data_as(_dp), n_.ctypes.data_as(_dp)))
+
+    def set_antenna(self, band_id, det, a, b):
+        """Per-sample antenna functions on the source lattice; a = None removes them."""
+        if a is None:
+            self._check(self.L.ccr_set_antenna(self.h, band_id, det, 0, None, None))
+            return
+        a_, b_ = _arr(a, np.float64), _arr(b, np.float64)
+        if a_.shape != b_.shape or a_.ndim != 1:
+            raise ValueError("a and b must be 1-d arrays of one length")
+        self._check(self.L.ccr_set_antenna(self.h, band_id, det, a_.shape[0], a_.ctypes.data_as(_dp),
+                                           b_.ctypes.data_as(_dp)))
 
     def set_templates(self, band_id, templates):
         t = _arr(np.atleast_2d(templates), np.float64)
@@ -270,5 +284,7 @@ class Context:
             self.set_data(bid, X, ds.sites[X], ds.t0, ds.dt, ds.x[X], ds.f_het,
                           None if ds.valid is None else ds.valid[X])
             self.set_weights(bid, X, ds.a[X], ds.b[X], ds.noise_var[X])
+            if getattr(ds, "ar", None) is not None:
+                self.set_antenna(bid, X, ds.ar[X], ds.br[X])
         self.set_templates(bid, ds.templates if templates is None else templates)
         return bid

@@ -61,6 +61,7 @@ struct DetData {
     std::vector<float> x;        // interleaved, zero where invalid
     std::vector<uint8_t> valid;  // empty = all valid
     std::vector<double> a, b, nv;
+    std::vector<double> ar, br;  // per-sample antenna functions on the source lattice, or empty
 };
 
 struct Plan {
@@ -82,7 +83,8 @@ struct Band {
     // device tables
     DevBuf d_x, d_mask, d_anchor, d_earth, d_win64, d_win32, d_cheb_x, d_mono, d_tw64, d_tw32, d_bin_m, d_bin_p,
         d_bin_kb, d_bin_pos, d_segw, d_active, d_work, d_seg_work, d_tmpl, d_lagph, d_seg_any, d_col_bin, d_bin_col, d_zero256,
-        d_class_start, d_farrow, d_farrow_A, d_cls_m0;
+        d_class_start, d_farrow, d_farrow_A, d_cls_m0, d_pw;
+    bool per_sample = false;  // every detector has per-sample antenna functions (two spectra streams)
     int wide_jmax = 0, wide_ncol = 0;  // 1024-point spectra + pair-sum kernel (see BandDev)
     int64_t far_len = 0;  // plane length of the Farrow table, 0 when the band has none
     double far_err = 0;   // bound of the fitted tap weights' error, sum over taps
@@ -436,6 +438,17 @@ ccr_status prepare(ccr_ctx *c, Band &B) {
         if ((int64_t)B.det[X].a.size() != M)
             return fail(c, CCR_EINVAL, "detector %d weights hold %zu segments, plan has %lld", X,
                         B.det[X].a.size(), (long long)M);
+    int n_ps = 0;
+    for (int X = 0; X < Q; ++X) {
+        if (B.det[X].ar.empty()) continue;
+        ++n_ps;
+        if ((int64_t)B.det[X].ar.size() < nr)
+            return fail(c, CCR_EINVAL, "detector %d antenna functions hold %zu samples, the segments need %lld", X,
+                        B.det[X].ar.size(), (long long)nr);
+    }
+    if (n_ps != 0 && n_ps != Q)
+        return fail(c, CCR_EINVAL, "per-sample antenna functions set for %d of %d detectors", n_ps, Q);
+    const bool per_sample = n_ps == Q;
     const double dt = pl.dt, t0 = B.det[0].t0;
     // Earth constants and per-segment anchors
     std::vector<EarthConst> earth(Q);
@@ -491,29 +504,75 @@ ccr_status prepare(ccr_ctx *c, Band &B) {
             const double sg = std::sqrt(B.det[X].nv[K]);
             segw[X * M + K] = SegWeight{B.det[X].a[K] / sg, B.det[X].b[K] / sg, 1.0 / (sg * std::sqrt((double)nk))};
         }
+    // stream moments A_XK = E|F^a_XK|^2, B_XK, C_XK (Sec. III.B.3 eq. norm-a-eq with App. A): the
+    // segment mean of m_r hat a_r^2, m_r hat b_r^2, m_r hat a_r hat b_r (m the gap mask, hat a =
+    // a / sigma_XK); with per-segment weights hat a_XK^2 phi_XK, ...
+    std::vector<double> mom((size_t)3 * Q * M);
+    parallel_for((int64_t)Q * M, [&](int64_t e) {
+        const int X = (int)(e / M);
+        const int64_t K = e % M;
+        const SegWeight &w = segw[e];
+        double A = w.ahat * w.ahat * phi[e], Bm = w.bhat * w.bhat * phi[e], C = w.ahat * w.bhat * phi[e];
+        if (per_sample) {
+            const double isg = 1.0 / std::sqrt(B.det[X].nv[K]);
+            A = Bm = C = 0.0;
+            for (int64_t s = 0; s < nk; ++s) {
+                const int64_t r = K * nk + s;
+                if (!mask[(size_t)X * nr + r]) continue;
+                const double ar = B.det[X].ar[r] * isg, br = B.det[X].br[r] * isg;
+                A += ar * ar;
+                Bm += br * br;
+                C += ar * br;
+            }
+            A /= (double)nk;
+            Bm /= (double)nk;
+            C /= (double)nk;
+        }
+        mom[3 * e] = A;
+        mom[3 * e + 1] = Bm;
+        mom[3 * e + 2] = C;
+    });
+    // pair set, normalisation N^2 = sum_P A_K A_L + 2 C_K C_L + B_K B_L (Gamma^ave) or
+    // sum_P A_K B_L + B_K A_L - 2 C_K C_L (Gamma^circ), and the segments that take part
     const int R = B.p.max_lag;
     const bool cross = B.p.pairs & CCR_PAIRS_CROSS, same = B.p.pairs & CCR_PAIRS_SAME;
+    const bool allp = B.p.pairs == CCR_PAIRS_ALL, circ = B.p.weight == CCR_WEIGHT_CIRC;
     std::vector<uint8_t> active((size_t)Q * M, 0);
     long double nacc = 0.0L;
     int64_t npairs = 0;
-    for (int X = 0; X < Q; ++X)
-        for (int64_t K = 0; K < M; ++K)
-            for (int Y = 0; Y < Q; ++Y)
-                for (int64_t L = std::max<int64_t>(0, K - R); L <= std::min<int64_t>(M - 1, K + R); ++L) {
-                    bool in = (cross && X < Y) || (same && X == Y && L > K);
-                    if (!in) continue;
-                    ++npairs;
-                    const SegWeight &wk = segw[X * M + K], &wl = segw[Y * M + L];
-                    const double fk = phi[X * M + K], fl = phi[Y * M + L];
-                    if (fk > 0.0 && fl > 0.0) {
-                        active[X * M + K] = 1;
-                        active[Y * M + L] = 1;
+    auto pair_norm = [&](size_t k, size_t l) -> long double {
+        const double *a = &mom[3 * k], *b = &mom[3 * l];
+        return circ ? (long double)a[0] * b[1] + (long double)a[1] * b[0] - 2.0L * a[2] * b[2]
+                    : (long double)a[0] * b[0] + 2.0L * a[2] * b[2] + (long double)a[1] * b[1];
+    };
+    if (allp) {
+        // every ordered pair: the double sum factorises into sums over segments
+        long double sa = 0.0L, sb = 0.0L, sc = 0.0L;
+        for (int64_t e = 0; e < (int64_t)Q * M; ++e) {
+            sa += mom[3 * e];
+            sb += mom[3 * e + 1];
+            sc += mom[3 * e + 2];
+            active[e] = phi[e] > 0.0 ? 1 : 0;
+        }
+        nacc = circ ? 2.0L * sa * sb - 2.0L * sc * sc : sa * sa + 2.0L * sc * sc + sb * sb;
+        npairs = (int64_t)Q * M * Q * M;
+    } else {
+        for (int X = 0; X < Q; ++X)
+            for (int64_t K = 0; K < M; ++K)
+                for (int Y = 0; Y < Q; ++Y)
+                    for (int64_t L = std::max<int64_t>(0, K - R); L <= std::min<int64_t>(M - 1, K + R); ++L) {
+                        bool in = (cross && X < Y) || (same && X == Y && L > K);
+                        if (!in) continue;
+                        ++npairs;
+                        const double fk = phi[X * M + K], fl = phi[Y * M + L];
+                        if (fk > 0.0 && fl > 0.0) {
+                            active[X * M + K] = 1;
+                            active[Y * M + L] = 1;
+                        }
+                        nacc += pair_norm((size_t)(X * M + K), (size_t)(Y * M + L));
                     }
-                    const double AK = wk.ahat * wk.ahat * fk, BK = wk.bhat * wk.bhat * fk, CK = wk.ahat * wk.bhat * fk;
-                    const double AL = wl.ahat * wl.ahat * fl, BL = wl.bhat * wl.bhat * fl, CL = wl.ahat * wl.bhat * fl;
-                    nacc += (long double)AK * AL + 2.0L * CK * CL + (long double)BK * BL;
-                }
-    pl.norm = (double)sqrtl(nacc);
+    }
+    pl.norm = nacc > 0.0L ? (double)sqrtl(nacc) : 0.0;
     pl.n_pairs = npairs;
     std::vector<int> work, seg_work((size_t)Q * M, -1);
     for (int X = 0; X < Q; ++X)
@@ -676,6 +735,24 @@ ccr_status prepare(ccr_ctx *c, Band &B) {
     if ((st = upload(c, B.d_bin_pos, bpos))) return st;
     B.bins_unique = unique;
     if ((st = upload(c, B.d_segw, segw))) return st;
+    // per-sample stream weights (a_r, b_r) / (sigma_XK^2 sqrt(N_K)): hat a_r times the spectra's
+    // 1 / (sigma sqrt N_K)
+    B.per_sample = per_sample;
+    if (per_sample) {
+        std::vector<double2> pw((size_t)Q * nr);
+        parallel_for((int64_t)Q * M, [&](int64_t e) {
+            const int X = (int)(e / M);
+            const int64_t K = e % M;
+            const double f = 1.0 / (B.det[X].nv[K] * std::sqrt((double)nk));
+            for (int64_t s = 0; s < nk; ++s) {
+                const int64_t r = K * nk + s;
+                pw[(size_t)X * nr + r] = make_double2(B.det[X].ar[r] * f, B.det[X].br[r] * f);
+            }
+        });
+        if ((st = upload(c, B.d_pw, pw))) return st;
+    } else {
+        B.d_pw.release();
+    }
     if ((st = upload(c, B.d_active, B.active))) return st;
     if ((st = upload(c, B.d_work, work))) return st;
     if ((st = upload(c, B.d_seg_work, seg_work))) return st;
@@ -861,6 +938,9 @@ BandDev band_dev(const Band &B) {
     d.cls_m0 = B.d_cls_m0.as<int>();
     d.wide_jmax = B.wide_jmax;
     d.wide_ncol = B.wide_ncol;
+    d.weight = B.p.weight;
+    d.allp = B.p.pairs == CCR_PAIRS_ALL ? 1 : 0;
+    d.pw = B.per_sample ? B.d_pw.as<double2>() : nullptr;
     return d;
 }
 
@@ -1034,8 +1114,11 @@ Variant variant_of(const BandDev &bd, bool fp64, bool short_series, bool farrow)
     Variant v;
     v.ss = short_series;
     v.far = farrow && !fp64 && bd.farrow != nullptr;
-    v.sp = spectra_pairs_ok(bd, fp64, kMaxLds);
-    v.wide = !v.sp && spectra_wide_ok(bd, fp64, kMaxLds);
+    // the spectra + pair-sum kernels take the Gamma^ave weight over lagged pairs with per-segment
+    // weights; the other forms run on the general path
+    const bool plain = bd.weight == CCR_WEIGHT_AVE && !bd.allp && bd.pw == nullptr;
+    v.sp = plain && spectra_pairs_ok(bd, fp64, kMaxLds);
+    v.wide = plain && !v.sp && spectra_wide_ok(bd, fp64, kMaxLds);
     v.DT = bd.D == 8 ? 8 : 0;
     v.window = bd.window;
     v.n_cheb = fp64 ? kCheb : bd.cheb_split;
@@ -1046,7 +1129,7 @@ Variant variant_of(const BandDev &bd, bool fp64, bool short_series, bool farrow)
         v.nr = spectra_pairs_rounds(bd);
         v.z4 = bd.n_k <= 192;
     } else {
-        v.reg16 = !fp64 && bd.n_s == 256 && bd.bins_unique;
+        v.reg16 = !fp64 && bd.n_s == 256 && bd.bins_unique && bd.pw == nullptr;
         if (!v.reg16) v.n_s = bd.n_s;
     }
     return v;
@@ -1122,8 +1205,10 @@ ccr_status build_plan(ccr_ctx *c, bool fp64, int n_bands, const int *band_ids, v
         kc = std::max<int64_t>(1, std::min<int64_t>(kc, pl.n_seg));
         const int nch = (int)((pl.n_seg + kc - 1) / kc);
         const size_t y1 = (size_t)B.Q * pl.n_seg * pl.n_k * cs;
-        const size_t F1 = (v.sp || v.wide) ? 0 : (size_t)B.Q * pl.n_seg * pl.n_f * cs;
-        const size_t part1 = (size_t)nch * pl.n_f * sizeof(double);
+        // two spectra streams per segment with per-sample weights; four partials per bin (the
+        // stream sums) for every ordered pair
+        const size_t F1 = (v.sp || v.wide) ? 0 : (size_t)B.Q * pl.n_seg * pl.n_f * cs * (bd.pw ? 2 : 1);
+        const size_t part1 = (size_t)nch * pl.n_f * sizeof(double) * (bd.allp ? 4 : 1);
         const size_t coef1 = (size_t)std::max(B.n_work, 1) * kCheb * sizeof(double);
         WorkItem proto;
         std::memset(&proto, 0, sizeof proto);
@@ -1595,7 +1680,9 @@ ccr_status ccr_add_band(ccr_ctx *c, const ccr_band *band, int *band_id, ccr_band
     if (b.dirichlet_D < 1 || b.dirichlet_D > 64) return fail(c, CCR_ERANGE, "dirichlet_D must be 1..64");
     if (b.max_lag < 0 || b.max_lag > 1024) return fail(c, CCR_ERANGE, "max_lag must be 0..1024");
     if (b.window != 0 && b.window != 1) return fail(c, CCR_EINVAL, "window must be 0 or 1");
-    if ((b.pairs & 3) == 0 || (b.pairs & ~3)) return fail(c, CCR_EINVAL, "pairs must be a nonzero mask of CROSS|SAME");
+    if (b.pairs != CCR_PAIRS_ALL && ((b.pairs & 3) == 0 || (b.pairs & ~3)))
+        return fail(c, CCR_EINVAL, "pairs must be a nonzero mask of CROSS|SAME, or ALL");
+    if (b.weight != CCR_WEIGHT_AVE && b.weight != CCR_WEIGHT_CIRC) return fail(c, CCR_EINVAL, "weight must be AVE or CIRC");
     if (b.n_fft_override < 0) return fail(c, CCR_EINVAL, "negative n_fft_override");
     try {
         auto B = std::make_unique<Band>();
@@ -1698,6 +1785,32 @@ ccr_status ccr_set_weights(ccr_ctx *c, int band_id, int det, int64_t n_seg, cons
     return CCR_OK;
 }
 
+ccr_status ccr_set_antenna(ccr_ctx *c, int band_id, int det, int64_t n, const double *a, const double *b) {
+    if (!c) return CCR_EINVAL;
+    c->err.clear();
+    Band *B = get_band(c, band_id);
+    if (!B) return fail(c, CCR_EINVAL, "bad band id %d", band_id);
+    if (det < 0 || det >= CCR_MAX_DET) return fail(c, CCR_EINVAL, "detector index %d out of range", det);
+    if (n < 0) return fail(c, CCR_EINVAL, "negative sample count");
+    try {
+        DetData &d = B->det[det];
+        if (n == 0 || !a || !b) {
+            d.ar.clear();
+            d.br.clear();
+        } else {
+            if (n > (int64_t)1 << 34) return fail(c, CCR_ERANGE, "series too long");
+            if (!finite_all(a, n) || !finite_all(b, n)) return fail(c, CCR_EINVAL, "non-finite antenna function");
+            d.ar.assign(a, a + n);
+            d.br.assign(b, b + n);
+        }
+    } catch (const std::bad_alloc &) {
+        return fail(c, CCR_ENOMEM, "out of host memory");
+    }
+    B->prepared = false;
+    B->tmpl.clear();
+    return CCR_OK;
+}
+
 ccr_status ccr_set_templates(ccr_ctx *c, int band_id, int64_t n, const double *a_p, const double *t_asc,
                              const double *period) {
     if (!c) return CCR_EINVAL;
@@ -1782,7 +1895,8 @@ ccr_status ccr_compute_rho(ccr_ctx *c, ccr_precision prec, int n_bands, const in
         for (int bi = 0; bi < n_bands; ++bi) {
             Band &B = *get_band(c, band_ids[bi]);
             const BandDev bd = band_dev(B);
-            const int S = fused_steps(bd, fp64, kMaxLds);
+            const bool plain = bd.weight == CCR_WEIGHT_AVE && !bd.allp && bd.pw == nullptr;
+            const int S = plain ? fused_steps(bd, fp64, kMaxLds) : 0;
             if (S > 0) {
                 if ((st = compute_fused(c, B, bd, fp64, S, rho_out[bi], out_on_device, out_fp64, s))) return st;
             } else {
@@ -1969,6 +2083,7 @@ ccr_status ccr_segment_spectra(ccr_ctx *c, ccr_precision prec, int band_id, int6
     bd.far_stage = (int)c->opt_farrow_stage;
     HIP_OK(c, launch_timebase(bd, B->d_tmpl.as<double>() + (size_t)template_index * kTmplStride, 1, cf.as<double>(), s));
     HIP_OK(c, launch_resample(bd, cf.as<double>(), 1, fp64, y.p, s));
+    bd.pw = nullptr;  // the unweighted spectra F
     HIP_OK(c, launch_spectra(bd, 1, fp64, y.p, F.p, s));
     HIP_OK(c, hipMemcpyAsync(f_out, F.p, fbytes, hipMemcpyDeviceToHost, s));
     HIP_OK(c, hipStreamSynchronize(s));

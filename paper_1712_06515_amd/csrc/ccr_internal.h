@@ -108,6 +108,12 @@ struct BandDev {
     // widest span in units of 64 outputs, and the largest class (bins)
     const int *cls_m0;
     int wide_jmax, wide_ncol;
+    // pair weight (0 Gamma^ave, 1 Gamma^circ) and pair set (allp: every ordered pair, autos
+    // included: the partials are the chunk sums of the two streams, 4 values a bin)
+    int weight, allp;
+    // per-sample antenna weights [Q][n_seg * n_k]: (a_r, b_r) / (sigma_K^2 sqrt(N_K)), or null
+    // (per-segment weights: the two streams are hat a_K F and hat b_K F)
+    const double2 *pw;
 };
 
 // One work item of a batched launch: a run of consecutive templates of one band.  A batched

@@ -1550,8 +1550,12 @@ __device__ __forceinline__ void spectra_wide_body(const BandDev &B, const float2
 __host__ __device__ inline bool Q_ok(const BandDev &B) { return B.Q >= 1 && B.Q * 4 <= 64; }
 
 // PER: samples per thread, n_s / blockDim.x (at most 4 below n_s = 2048, else 8).
+// With per-sample antenna weights (B.pw) the segment gives two spectra, of hat a_r y_r and of
+// hat b_r y_r (the table's weights carry 1 / (sigma sqrt N_K)); the second is written `plane`
+// entries after the first.
 template <typename T, int PER>
-__device__ __forceinline__ void spectra_body(const BandDev &B, const c2<T> *y, c2<T> *F, int w, int tb) {
+__device__ __forceinline__ void spectra_body(const BandDev &B, const c2<T> *y, c2<T> *F, int w, int tb,
+                                             size_t plane) {
     extern __shared__ __align__(16) unsigned char smem[];
     c2<T> *buf0 = reinterpret_cast<c2<T> *>(smem);
     c2<T> *buf1 = buf0 + B.n_s;
@@ -1562,8 +1566,9 @@ __device__ __forceinline__ void spectra_body(const BandDev &B, const c2<T> *y, c
     const c2<T> *ys = y + ((size_t)tb * B.Q + det) * nr + (size_t)K * B.n_k;
     const c2<T> *tw = twiddles<T>(B);
     const int rb_mod = mod_fft(B, (int64_t)K * B.n_k);
-    const T scale = (T)B.segw[entry].scale;
-    c2<T> *Fo = F + (((size_t)tb * B.Q + det) * B.n_seg + K) * B.n_f;
+    const bool two = B.pw != nullptr;
+    const T scale = two ? (T)1 : (T)B.segw[entry].scale;
+    const double2 *pws = two ? B.pw + (size_t)det * nr + (size_t)K * B.n_k : nullptr;
     // The FFT's stage twiddles are all n_s-th roots of unity: a copy of those n_s entries of
     // the N_FFT-entry table in LDS (when it fits beside the two work buffers) replaces the
     // strided gathers from global memory.
@@ -1577,70 +1582,139 @@ __device__ __forceinline__ void spectra_body(const BandDev &B, const c2<T> *y, c
     // s = threadIdx.x + r blockDim.x, advanced from class to class by W^s and refreshed from the
     // table every 8 classes (bounding the product's rounding growth)
     constexpr int kPer = PER;
-    c2<T> ts[kPer], ws[kPer];
+    c2<T> ts[kPer], ws[kPer], yv[kPer];
 #pragma unroll
     for (int r = 0; r < kPer; ++r) {
         const int s = threadIdx.x + r * blockDim.x;
         ws[r] = s < B.n_s ? tw[s] : mk<T>((T)1, (T)0);
-        ts[r] = mk<T>((T)1, (T)0);
     }
-    for (int p = 0; p < B.P; ++p) {
+    for (int st = 0; st < (two ? 2 : 1); ++st) {
+        c2<T> *Fo = F + (size_t)st * plane + (((size_t)tb * B.Q + det) * B.n_seg + K) * B.n_f;
 #pragma unroll
         for (int r = 0; r < kPer; ++r) {
             const int s = threadIdx.x + r * blockDim.x;
-            if (s < B.n_s) {
-                if (p > 0) ts[r] = (p & 7) == 0 ? tw[mod_fft(B, (int64_t)p * s)] : cmul<T>(ts[r], ws[r]);
-                buf0[s] = s < B.n_k ? (p ? cmul<T>(ys[s], ts[r]) : ys[s]) : mk<T>((T)0, (T)0);
+            ts[r] = mk<T>((T)1, (T)0);
+            yv[r] = mk<T>((T)0, (T)0);
+            if (s < B.n_k) {
+                yv[r] = ys[s];
+                if (two) {
+                    const double2 wv = pws[s];
+                    yv[r] = cscale<T>(yv[r], (T)(st ? wv.y : wv.x));
+                }
             }
         }
-        __syncthreads();
-        const c2<T> *res = ltw ? stockham<T>(buf0, buf1, B.n_s, twl, B.n_s, threadIdx.x, blockDim.x)
-                               : stockham<T>(buf0, buf1, B.n_s, tw, B.n_fft, threadIdx.x, blockDim.x);
-        // the output bins of class p only
-        for (int c = B.class_start[p] + (int)threadIdx.x; c < B.class_start[p + 1]; c += blockDim.x) {
-            const int i = B.col_bin[c];
-            const int ph = mod_fft(B, (int64_t)B.bin_kb[i] * rb_mod);
-            Fo[i] = cscale<T>(cmul<T>(res[B.bin_m[i]], tw[ph]), scale);
+        for (int p = 0; p < B.P; ++p) {
+#pragma unroll
+            for (int r = 0; r < kPer; ++r) {
+                const int s = threadIdx.x + r * blockDim.x;
+                if (s < B.n_s) {
+                    if (p > 0) ts[r] = (p & 7) == 0 ? tw[mod_fft(B, (int64_t)p * s)] : cmul<T>(ts[r], ws[r]);
+                    buf0[s] = p ? cmul<T>(yv[r], ts[r]) : yv[r];
+                }
+            }
+            __syncthreads();
+            const c2<T> *res = ltw ? stockham<T>(buf0, buf1, B.n_s, twl, B.n_s, threadIdx.x, blockDim.x)
+                                   : stockham<T>(buf0, buf1, B.n_s, tw, B.n_fft, threadIdx.x, blockDim.x);
+            // the output bins of class p only
+            for (int c = B.class_start[p] + (int)threadIdx.x; c < B.class_start[p + 1]; c += blockDim.x) {
+                const int i = B.col_bin[c];
+                const int ph = mod_fft(B, (int64_t)B.bin_kb[i] * rb_mod);
+                Fo[i] = cscale<T>(cmul<T>(res[B.bin_m[i]], tw[ph]), scale);
+            }
+            __syncthreads();
         }
-        __syncthreads();
     }
 }
 
 template <typename T, int PER>
-__global__ void __launch_bounds__(256) k_spectra(BandDev B, const c2<T> *y, c2<T> *F) {
-    spectra_body<T, PER>(B, y, F, blockIdx.x, blockIdx.y);
+__global__ void __launch_bounds__(256) k_spectra(BandDev B, const c2<T> *y, c2<T> *F, size_t plane) {
+    spectra_body<T, PER>(B, y, F, blockIdx.x, blockIdx.y, plane);
 }
 
 // ------------------------------------------------------------------ pair sum
 
+// Pair sums in stream form: segment (X, K) contributes the two streams F^a_XK and F^b_XK at
+// bin i -- hat a_XK F_XK and hat b_XK F_XK with per-segment weights, or the two spectra of the
+// weighted series (B.pw, stored `plane` entries apart).  A pair (K, L) adds
+//   Gamma^ave:  Re[conj(F^a_K) F^a_L + conj(F^b_K) F^b_L]
+//   Gamma^circ: Im[conj(F^b_K) F^a_L - conj(F^a_K) F^b_L]
+// (with per-segment weights (hat a_K hat a_L + hat b_K hat b_L) Re[conj(F_K) F_L] and
+// (hat b_K hat a_L - hat a_K hat b_L) Im[conj(F_K) F_L]); both are symmetric in K and L.
+template <typename T> struct Streams {
+    const c2<T> *F;  // this template's spectra
+    size_t plane;    // offset of the b-stream, two-stream form only
+    bool two;
+    __device__ __forceinline__ void at(const BandDev &B, int el, int i, c2<T> &fa, c2<T> &fb) const {
+        const c2<T> g = F[(size_t)el * B.n_f + i];
+        if (two) {
+            fa = g;
+            fb = F[plane + (size_t)el * B.n_f + i];
+        } else {
+            const T a = (T)B.segw[el].ahat, b = (T)B.segw[el].bhat;
+            fa = cscale<T>(g, a);
+            fb = cscale<T>(g, b);
+        }
+    }
+};
+
 // Partial rho of one (template, bin, chunk of segments): for each segment K and detector X,
-// conj(F_XK) times the weighted sum of its partners (Y, L) that precede it -- L in
-// [K - R, K - 1] (other detectors if cross pairs, the same detector if same pairs) and
-// L = K with Y > X (cross pairs) -- so each unordered pair of the set enters once.  The sums
-// over L in [K - R, K - 1] are kept per detector as sliding windows (add segment K - 1, drop
-// K - R - 1), so each spectrum is read twice instead of (R + 1) Q times; inactive segments
-// (whose spectra are not computed) never enter.
+// segment (X, K) against the sum of its partners (Y, L) that precede it -- L in [K - R, K - 1]
+// (other detectors if cross pairs, the same detector if same pairs) and L = K with Y > X (cross
+// pairs) -- so each unordered pair of the set enters once.  The partner sums over
+// L in [K - R, K - 1] are kept per detector as sliding windows of the two streams (add segment
+// K - 1, drop K - R - 1), so each spectrum is read twice instead of (R + 1) Q times; inactive
+// segments (whose spectra are not computed) never enter.
 template <typename T>
 __device__ __forceinline__ void pairs_body(const BandDev &B, const c2<T> *F, double *part, int k_chunk, int n_chunks,
-                                           int bx, int c, int tb) {
+                                           int bx, int c, int tb, size_t plane) {
     const int i = bx * blockDim.x + threadIdx.x;
     if (i >= B.n_f) return;
     const bool cross = (B.pairs & 1) != 0, same = (B.pairs & 2) != 0;
-    const c2<T> *Ft = F + (size_t)tb * B.Q * B.n_seg * B.n_f;
+    const bool circ = B.weight != 0, two = B.pw != nullptr;
+    const Streams<T> S{F + (size_t)tb * B.Q * B.n_seg * B.n_f, plane, two};
     const int Q = B.Q, R = B.R;
     const int K0 = c * k_chunk;
     const int K1 = min(B.n_seg, K0 + k_chunk);
-    // wa[Y], wb[Y]: sum over L in [K - R, K - 1] of hat a_YL F_YL and hat b_YL F_YL
+    if (B.allp) {
+        // every ordered pair, autos included: the pair sum is a function of the stream sums
+        // G^a = sum_XK F^a_XK and G^b (combined by the finishing kernel); this chunk's share
+        double ga_x = 0.0, ga_y = 0.0, gb_x = 0.0, gb_y = 0.0;
+        for (int K = K0; K < K1; ++K)
+            for (int X = 0; X < Q; ++X) {
+                const int ek = X * B.n_seg + K;
+                if (!B.active[ek]) continue;
+                c2<T> fa, fb;
+                S.at(B, ek, i, fa, fb);
+                ga_x += (double)fa.x;
+                ga_y += (double)fa.y;
+                gb_x += (double)fb.x;
+                gb_y += (double)fb.y;
+            }
+        double *o = part + (((size_t)tb * n_chunks + c) * B.n_f + i) * 4;
+        o[0] = ga_x;
+        o[1] = ga_y;
+        o[2] = gb_x;
+        o[3] = gb_y;
+        return;
+    }
+    // wa[Y], wb[Y]: sum over L in [K - R, K - 1] of F^a_YL and F^b_YL
     c2<T> wa[CCR_MAX_DET_K], wb[CCR_MAX_DET_K];
 #pragma unroll
     for (int Y = 0; Y < CCR_MAX_DET_K; ++Y) wa[Y] = wb[Y] = mk<T>((T)0, (T)0);
     auto add = [&](int Y, int L, T sign) {
         const int el = Y * B.n_seg + L;
         if (!B.active[el]) return;
-        const c2<T> g = Ft[(size_t)el * B.n_f + i];
-        const T a = sign * (T)B.segw[el].ahat, b = sign * (T)B.segw[el].bhat;
-        wa[Y] = mk<T>(fma(a, g.x, wa[Y].x), fma(a, g.y, wa[Y].y));
-        wb[Y] = mk<T>(fma(b, g.x, wb[Y].x), fma(b, g.y, wb[Y].y));
+        if (two) {
+            c2<T> fa, fb;
+            S.at(B, el, i, fa, fb);
+            wa[Y] = mk<T>(fma(sign, fa.x, wa[Y].x), fma(sign, fa.y, wa[Y].y));
+            wb[Y] = mk<T>(fma(sign, fb.x, wb[Y].x), fma(sign, fb.y, wb[Y].y));
+        } else {
+            const c2<T> g = S.F[(size_t)el * B.n_f + i];
+            const T a = sign * (T)B.segw[el].ahat, b = sign * (T)B.segw[el].bhat;
+            wa[Y] = mk<T>(fma(a, g.x, wa[Y].x), fma(a, g.y, wa[Y].y));
+            wb[Y] = mk<T>(fma(b, g.x, wb[Y].x), fma(b, g.y, wb[Y].y));
+        }
     };
     for (int L = max(0, K0 - R); L < K0; ++L)
 #pragma unroll
@@ -1670,16 +1744,38 @@ __device__ __forceinline__ void pairs_body(const BandDev &B, const c2<T> *F, dou
                 }
                 const int el = Y * B.n_seg + K;
                 if (cross && Y > X && B.active[el]) {
-                    const c2<T> g = Ft[(size_t)el * B.n_f + i];
-                    const T wa_ = (T)B.segw[el].ahat, wb_ = (T)B.segw[el].bhat;
-                    ga = mk<T>(fma(wa_, g.x, ga.x), fma(wa_, g.y, ga.y));
-                    gb = mk<T>(fma(wb_, g.x, gb.x), fma(wb_, g.y, gb.y));
+                    if (two) {
+                        c2<T> fa, fb;
+                        S.at(B, el, i, fa, fb);
+                        ga = cadd<T>(ga, fa);
+                        gb = cadd<T>(gb, fb);
+                    } else {
+                        const c2<T> g = S.F[(size_t)el * B.n_f + i];
+                        const T wa_ = (T)B.segw[el].ahat, wb_ = (T)B.segw[el].bhat;
+                        ga = mk<T>(fma(wa_, g.x, ga.x), fma(wa_, g.y, ga.y));
+                        gb = mk<T>(fma(wb_, g.x, gb.x), fma(wb_, g.y, gb.y));
+                    }
                 }
             }
-            const c2<T> f = Ft[(size_t)ek * B.n_f + i];
-            const T aK = (T)B.segw[ek].ahat, bK = (T)B.segw[ek].bhat;
-            const T hx = aK * ga.x + bK * gb.x, hy = aK * ga.y + bK * gb.y;
-            acc += (double)(f.x * hx + f.y * hy);
+            if (two) {
+                c2<T> fa, fb;
+                S.at(B, ek, i, fa, fb);
+                if (circ)
+                    acc += (double)((fb.x * ga.y - fb.y * ga.x) - (fa.x * gb.y - fa.y * gb.x));
+                else
+                    acc += (double)(fa.x * ga.x + fa.y * ga.y + fb.x * gb.x + fb.y * gb.y);
+            } else {
+                const c2<T> f = S.F[(size_t)ek * B.n_f + i];
+                const T aK = (T)B.segw[ek].ahat, bK = (T)B.segw[ek].bhat;
+                if (circ) {
+                    // Im[conj(F_K) (hat b_K G^a - hat a_K G^b)]
+                    const T hx = bK * ga.x - aK * gb.x, hy = bK * ga.y - aK * gb.y;
+                    acc += (double)(f.x * hy - f.y * hx);
+                } else {
+                    const T hx = aK * ga.x + bK * gb.x, hy = aK * ga.y + bK * gb.y;
+                    acc += (double)(f.x * hx + f.y * hy);
+                }
+            }
         }
     }
     part[((size_t)tb * n_chunks + c) * B.n_f + i] = acc;
@@ -1932,12 +2028,23 @@ __global__ void __launch_bounds__(256) k_fused(BandDev B, const double *coef, co
     for (int i = tid; i < n_f; i += nth) part[((size_t)tb * n_chunks + c) * n_f + i] = acc[i];
 }
 
+// allp = 0: rho = factor x the sum of the chunk partials.  allp = 1 (every ordered pair): the
+// partials are chunk sums of the streams (G^a, G^b, 4 doubles); rho = factor x
+// (|G^a|^2 + |G^b|^2) for Gamma^ave, factor x 2 Im[conj(G^b) G^a] for Gamma^circ.
 __device__ __forceinline__ void finish_body(int n_f, int n_tmpl, const double *part, int n_chunks, double factor,
-                                            void *out, int out_fp64, int bx, int t) {
+                                            void *out, int out_fp64, int bx, int t, int allp = 0, int circ = 0) {
     const int i = bx * blockDim.x + threadIdx.x;
     if (i >= n_f || t >= n_tmpl) return;
     double s = 0.0;
-    for (int c = 0; c < n_chunks; ++c) s += part[((size_t)t * n_chunks + c) * n_f + i];
+    if (allp) {
+        double g[4] = {0.0, 0.0, 0.0, 0.0};
+        for (int c = 0; c < n_chunks; ++c)
+#pragma unroll
+            for (int j = 0; j < 4; ++j) g[j] += part[(((size_t)t * n_chunks + c) * n_f + i) * 4 + j];
+        s = circ ? 2.0 * (g[2] * g[1] - g[3] * g[0]) : g[0] * g[0] + g[1] * g[1] + g[2] * g[2] + g[3] * g[3];
+    } else {
+        for (int c = 0; c < n_chunks; ++c) s += part[((size_t)t * n_chunks + c) * n_f + i];
+    }
     s *= factor;
     if (out_fp64)
         static_cast<double *>(out)[(size_t)t * n_f + i] = s;
@@ -2000,6 +2107,7 @@ __device__ __forceinline__ BandDev global_view(const BandDev &b, const void *bas
     g.bin_col = as_global(b.bin_col, base);
     g.farrow = as_global(b.farrow, base);
     g.cls_m0 = as_global(b.cls_m0, base);
+    if (b.pw) g.pw = as_global(b.pw, base);
     return g;
 }
 
@@ -2105,7 +2213,8 @@ k_spectra_m(const BandDev *__restrict__ bands, const WorkItem *__restrict__ item
     const WorkItem &it = items[find_item(items, n_items, kStSpectra, blockIdx.x)];
     const BandDev B = global_view(bands[it.band], bands);
     const int l = blockIdx.x - it.first[kStSpectra], gx = it.gx[kStSpectra];
-    spectra_body<T, PER>(B, y + it.y_off, F + it.F_off, l % gx, l / gx);
+    const size_t plane = (size_t)it.n_tmpl * B.Q * B.n_seg * B.n_f;
+    spectra_body<T, PER>(B, y + it.y_off, F + it.F_off, l % gx, l / gx, plane);
 }
 
 template <typename T>
@@ -2116,8 +2225,9 @@ k_pairs_m(const BandDev *__restrict__ bands, const WorkItem *__restrict__ items,
     const BandDev B = global_view(bands[it.band], bands);
     const int l = blockIdx.x - it.first[kStPairs], gx = it.gx[kStPairs];
     const int bx = l % gx, rest = l / gx;
+    const size_t plane = (size_t)it.n_tmpl * B.Q * B.n_seg * B.n_f;
     pairs_body<T>(B, F + it.F_off, part + it.part_off, it.k_chunk, it.n_chunks, bx, rest % it.n_chunks,
-                  rest / it.n_chunks);
+                  rest / it.n_chunks, plane);
 }
 
 __global__ void __launch_bounds__(kFinishThreads)
@@ -2127,7 +2237,7 @@ k_finish_m(const BandDev *__restrict__ bands, const WorkItem *__restrict__ items
     const BandDev B = global_view(bands[it.band], bands);
     const int l = blockIdx.x - it.first[kStFinish], gx = it.gx[kStFinish];
     finish_body(B.n_f, it.n_tmpl, part + it.part_off, it.n_chunks, it.factor, as_global(it.out, (const gchar *)part),
-                it.out_fp64, l % gx, l / gx);
+                it.out_fp64, l % gx, l / gx, B.allp, B.weight);
 }
 
 }  // namespace
@@ -2177,23 +2287,24 @@ hipError_t launch_farrow_table(const float2 *x, int64_t n, int Q, int D, const d
 hipError_t launch_spectra(const BandDev &B, int n_tmpl, bool fp64, const void *y, void *F,
                           hipStream_t stream) {
     if (B.n_work == 0 || n_tmpl == 0) return hipSuccess;
-    if (!fp64 && B.n_s == 256 && B.bins_unique) {
+    if (!fp64 && B.n_s == 256 && B.bins_unique && !B.pw) {
         dim3 grid((B.n_work + 7) / 8, n_tmpl), block(128);
         hipLaunchKernelGGL(k_spectra16<float>, grid, block, 0, stream, B, (const float2 *)y, (float2 *)F);
         return hipGetLastError();
     }
     dim3 grid(B.n_work, n_tmpl), block(spectra_threads(B.n_s));
+    const size_t plane = (size_t)n_tmpl * B.Q * B.n_seg * B.n_f;
     const size_t cs = fp64 ? sizeof(double2) : sizeof(float2);
     const size_t lds = (3 * (size_t)B.n_s * cs <= 65536 ? 3 : 2) * (size_t)B.n_s * cs;  // + stage twiddles
     const bool p8 = B.n_s > 4 * spectra_threads(B.n_s);
     if (fp64 && p8)
-        hipLaunchKernelGGL((k_spectra<double, 8>), grid, block, lds, stream, B, (const double2 *)y, (double2 *)F);
+        hipLaunchKernelGGL((k_spectra<double, 8>), grid, block, lds, stream, B, (const double2 *)y, (double2 *)F, plane);
     else if (fp64)
-        hipLaunchKernelGGL((k_spectra<double, 4>), grid, block, lds, stream, B, (const double2 *)y, (double2 *)F);
+        hipLaunchKernelGGL((k_spectra<double, 4>), grid, block, lds, stream, B, (const double2 *)y, (double2 *)F, plane);
     else if (p8)
-        hipLaunchKernelGGL((k_spectra<float, 8>), grid, block, lds, stream, B, (const float2 *)y, (float2 *)F);
+        hipLaunchKernelGGL((k_spectra<float, 8>), grid, block, lds, stream, B, (const float2 *)y, (float2 *)F, plane);
     else
-        hipLaunchKernelGGL((k_spectra<float, 4>), grid, block, lds, stream, B, (const float2 *)y, (float2 *)F);
+        hipLaunchKernelGGL((k_spectra<float, 4>), grid, block, lds, stream, B, (const float2 *)y, (float2 *)F, plane);
     return hipGetLastError();
 }
 

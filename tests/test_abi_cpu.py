@@ -38,14 +38,15 @@ def test_exports_every_declared_symbol(lib):
     for n in names:
         assert hasattr(lib, n), n
     assert set(names) == set(ccr.SIGNATURES), set(names) ^ set(ccr.SIGNATURES)
-    assert lib.ccr_abi_version() == 2
+    assert lib.ccr_abi_version() == 3
 
 
 def test_struct_layouts_match_header(lib):
     # sizes implied by the header field lists
     assert ctypes.sizeof(ccr.Sky) == 9 * 8
     assert ctypes.sizeof(ccr.Site) == 16
-    assert ctypes.sizeof(ccr.Band) == 3 * 8 + 4 * 4 + 8 + 8 + 8 + 8  # int32 pairs padded to 8
+    assert ctypes.sizeof(ccr.Band) == 3 * 8 + 4 * 4 + 8 + 8 + 8 + 8 + 8  # int32 pairs, weight padded to 8
+    assert ccr.Band.weight.offset == 72
     assert ctypes.sizeof(ccr.BandInfo) == 10 * 8 + 9 * 8
 
 
@@ -160,6 +161,35 @@ def test_validation_errors(lib):
         ctx.set_data(bid4, X, ds.sites[X], 0.0, ds.dt, ds.x[X], ds.f_het)
         ctx.set_weights(bid4, X, ds.a[X], ds.b[X], ds.noise_var[X])
     assert err(ctx.band_info, bid4) == ccr.EINVAL
+    # pair set ALL is not combined with CROSS / SAME; weight is AVE or CIRC
+    assert err(ctx.add_band, dict(ds.band, pairs=ccr.PAIRS_ALL | ccr.PAIRS_CROSS)) == ccr.EINVAL
+    assert err(ctx.add_band, dict(ds.band, pairs=8)) == ccr.EINVAL
+    assert err(ctx.add_band, dict(ds.band, weight=2)) == ccr.EINVAL
+
+
+def test_antenna_validation(lib):
+    ds = synth.make_dataset(small_config(n_seg=4), signal=False, per_sample_antenna=True)
+    ctx = _host_ctx(ds)
+    bid = ctx.load(ds)
+    ctx.band_info(bid)
+
+    def err(fn, *a, **k):
+        with pytest.raises(ccr.CcrError) as e:
+            fn(*a, **k)
+        return e.value.status
+
+    bad = ds.ar[0].copy()
+    bad[3] = np.nan
+    assert err(ctx.set_antenna, bid, 0, bad, ds.br[0]) == ccr.EINVAL
+    assert err(ctx.set_antenna, bid, 9, ds.ar[0], ds.br[0]) == ccr.EINVAL
+    # too short for the band's segments: caught when the band is planned
+    ctx.set_antenna(bid, 0, ds.ar[0][:-1], ds.br[0][:-1])
+    assert err(ctx.band_info, bid) == ccr.EINVAL
+    # set for one detector only
+    ctx.set_antenna(bid, 0, None, None)
+    assert err(ctx.band_info, bid) == ccr.EINVAL
+    ctx.set_antenna(bid, 1, None, None)
+    ctx.band_info(bid)  # per-segment weights again
 
 
 @pytest.mark.parametrize("kw", [
@@ -168,11 +198,22 @@ def test_validation_errors(lib):
     dict(max_lag=3, pairs=1, q=3, n_seg=20, gap_fraction=0.1),
     dict(max_lag=1, pairs=2, n_seg=12, mu_f=0.3),
     dict(n_fft_override=3 * 128, max_lag=1),
+    dict(max_lag=2, gap_fraction=0.25, n_seg=24, weight=1),
+    dict(max_lag=1, pairs=4, n_seg=12, gap_fraction=0.2),
+    dict(max_lag=1, pairs=4, q=3, n_seg=10, weight=1),
+    dict(max_lag=2, n_seg=14, gap_fraction=0.2, per_sample=True),
+    dict(max_lag=1, pairs=1, n_seg=10, per_sample=True, weight=1),
+    dict(max_lag=1, pairs=4, n_seg=10, per_sample=True, gap_fraction=0.1),
 ])
 def test_plan_and_normalisation_match_oracle(lib, kw):
     """Band plan integers are bit-identical to the oracle's; the normalisation (weights, gap
-    mask fractions, pair set) agrees to rounding."""
-    ds = synth.make_dataset(small_config(**kw), sigma_wander=0.2)
+    mask fractions, pair set, Gamma^ave or Gamma^circ, per-segment or per-sample antenna
+    functions) agrees to rounding."""
+    kw = dict(kw)
+    weight, per_sample = kw.pop("weight", 0), kw.pop("per_sample", False)
+    cfg = small_config(**kw)
+    cfg["band"]["weight"] = weight
+    ds = synth.make_dataset(cfg, sigma_wander=0.2, per_sample_antenna=per_sample)
     ctx = _host_ctx(ds)
     bid = ctx.load(ds)
     info, freqs = ctx.band_info(bid, freqs=True)

@@ -260,6 +260,86 @@ def test_spectra_wide_1024(ccr, case):
     assert np.array_equal(r32, r32b)  # one template per launch: same kernel arithmetic
 
 
+WEIGHTED = {
+    # (pair set, weight, per-sample antenna functions, detectors, max lag, gap fraction, shape)
+    "circ_lag2_both": (3, 1, False, 2, 2, 0.25, "small"),
+    "circ_q3_cross": (1, 1, False, 3, 1, 0.1, "small"),
+    "all_ave": (4, 0, False, 2, 1, 0.2, "small"),
+    "all_circ_q3": (4, 1, False, 3, 1, 0.1, "small"),
+    "ps_ave_lag2": (3, 0, True, 2, 2, 0.2, "small"),
+    "ps_circ_cross": (1, 1, True, 2, 1, 0.1, "small"),
+    "ps_all_ave": (4, 0, True, 2, 1, 0.2, "small"),
+    "ps_all_circ_q3": (4, 1, True, 3, 0, 0.0, "small"),
+    "circ_256_lag3": (3, 1, False, 2, 3, 0.2, "256"),
+    "ps_ave_256_lag2": (3, 0, True, 2, 2, 0.2, "256"),
+    "circ_1024_lag2": (3, 1, False, 2, 2, 0.3, "1024"),
+    "ps_all_1024": (4, 0, True, 2, 1, 0.3, "1024"),
+}
+
+
+def weighted_dataset(pairs, weight, per_sample, q, R, gaps, shape):
+    inj = dict(a_p=1.3, t_asc_off=0.0, period=68023.7, h0=0.3, cosi=0.8, psi=0.4, phi0=2.0)
+    if shape == "small":
+        cfg = small_config(q=q, n_seg=18, max_lag=R, pairs=pairs, gap_fraction=gaps,
+                           injections=[dict(inj, f0=50.21, a_p=1.25)])
+    else:
+        t_short, n_seg = (400.0, 23) if shape == "256" else (2000.0, 30)
+        cfg = small_config(q=q, n_seg=n_seg, t_short=t_short, f_min=400.0, f_band=0.06, max_lag=R, pairs=pairs,
+                           a_p_max=2.0, gap_fraction=gaps,
+                           templates=dict(a_p=(1.0, 2.0, 2), t_asc=(-200.0, 200.0, 2), period=[68023.70]),
+                           injections=[dict(inj, f0=400.031)])
+    cfg["band"]["weight"] = weight
+    return synth.make_dataset(cfg, sigma_wander=0.2, per_sample_antenna=per_sample)
+
+
+@pytest.mark.parametrize("case", sorted(WEIGHTED))
+def test_weighted_pair_sums(ccr, case):
+    """The Gamma^circ weight (Sec. II.B), every ordered pair with auto-correlations (App.
+    A.1-A.2) and per-sample antenna functions (Sec. III.B.3, eq. norm-a-eq: two spectra streams
+    per segment), alone and combined, on 128-, 256- and 1024-point segments with gaps, against
+    the oracle's stream form; FP64 and split, chunks of 5 segments with their halo, the fused
+    option set (these forms take the general path whatever the option)."""
+    pairs, weight, per_sample, q, R, gaps, shape = WEIGHTED[case]
+    ds = weighted_dataset(pairs, weight, per_sample, q, R, gaps, shape)
+    o = oracle.Oracle(ds)
+    ref = o.rho(ds.templates)
+    with ccr.Context(ds.sky, device=0) as ctx:
+        ctx.set_option("timing", 1)
+        ctx.set_option("k_chunk", 5)
+        ctx.set_option("fused", 1)
+        bid = ctx.load(ds)
+        info = ctx.band_info(bid)
+        assert abs(info["norm"] / o.norm() - 1.0) < 1e-12
+        r64 = ctx.compute_rho(bid, prec=ccr.PREC_FP64)
+        r32 = ctx.compute_rho(bid, prec=ccr.PREC_SPLIT, out_fp64=False)
+        kt = ctx.kernel_times(reset=True)
+        ctx.set_option("template_batch", 1)
+        r64b = ctx.compute_rho(bid, prec=ccr.PREC_FP64)
+    assert kt["pairs"][1] > 0 and kt["spectra_pairs"][1] == 0 and kt["spectra_wide"][1] == 0, kt
+    e64, e32 = rho_err(r64, ref), rho_err(r32, ref)
+    print(f"weighted {case}: fp64 {e64:.2e} split {e32:.2e} max|rho| {np.abs(ref).max():.2f}")
+    assert e64 < TOL64 and e32 < TOL32
+    assert np.array_equal(r64, r64b)  # one template per launch: same arithmetic
+
+
+def test_weighted_forms_reduce(ccr):
+    """Per-sample antenna functions that are constant over each segment give the per-segment
+    result (one spectrum stream scaled, against two weighted streams), for Gamma^ave and
+    Gamma^circ; the FP64 results agree to rounding."""
+    for weight in (0, 1):
+        ds = weighted_dataset(3, weight, False, 2, 2, 0.2, "small")
+        with ccr.Context(ds.sky, device=0) as ctx:
+            bid = ctx.load(ds)
+            r_seg = ctx.compute_rho(bid, prec=ccr.PREC_FP64)
+            n_k = ctx.band_info(bid)["n_k"]
+            for X in range(2):
+                ctx.set_antenna(bid, X, np.repeat(ds.a[X], n_k), np.repeat(ds.b[X], n_k))
+            r_ps = ctx.compute_rho(bid, prec=ccr.PREC_FP64)
+        err = np.max(np.abs(r_ps - r_seg)) / max(1.0, np.abs(r_seg).max())
+        print(f"constant per-sample weights, weight {weight}: {err:.2e}")
+        assert err < 1e-12
+
+
 def test_tiny_workload_full(ccr):
     """2 detectors, 2 days, T_short 360 s, 0.25 Hz at 100 Hz, 64 templates, same-time pairs."""
     ds = synth.make_dataset(synth.config("tiny"))
