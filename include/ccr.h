@@ -232,6 +232,19 @@ ccr_status ccr_set_antenna(ccr_ctx *ctx, int band_id, int det, int64_t n, const 
 ccr_status ccr_set_templates(ccr_ctx *ctx, int band_id, int64_t n, const double *a_p,
                              const double *t_asc, const double *period);
 
+
+/* Eccentric orbital templates (Sec. II.A.2, eqs. solve-for-E and Kepler-equation): the binary
+ * delay is R/c = a_p [sin omega (cos E - e) + cos omega sqrt(1 - e^2) sin E] with
+ * E - e sin E = Omega (t_SSB - T_p), Omega = 2 pi / P, the anomaly taken at the SSB time of the
+ * detector sample as the circular orbit takes its phase; with e = 0 this is the circular orbit
+ * with T_asc = T_p - omega / Omega.  Arrays of n: a_p (s, >= 0), t_p (periapse time, s after
+ * the epoch), omega (argument of periapse, rad), e (0 <= e <= 0.95, else CCR_EINVAL), period
+ * (s, > 0).  Replaces the band's templates (as ccr_set_templates).  When the band is prepared
+ * a template whose Kepler solve or time-base interpolation the library cannot bound over a
+ * segment (e too large for the segment length) gives CCR_ERANGE. */
+ccr_status ccr_set_templates_ecc(ccr_ctx *ctx, int band_id, int64_t n, const double *a_p, const double *t_p,
+                                 const double *omega, const double *e, const double *period);
+
 /* Full plan of a band (Sec. III.B.1-2: M, T_coh, delta lambda_f, N_FFT by eq. n-fft-final,
  * nu_R; App. B eq. delta-f-load; the normalisation N of App. A); bin_freqs (n_f doubles, may be
  * NULL) receives the output frequencies f_het + kbar_i / T_FFT, kbar_i = k_lo + floor(nu_R i)

@@ -72,6 +72,7 @@ SIGNATURES = {
     "ccr_set_weights": ([_vp, ctypes.c_int, ctypes.c_int, ctypes.c_int64, _dp, _dp, _dp], ctypes.c_int),
     "ccr_set_antenna": ([_vp, ctypes.c_int, ctypes.c_int, ctypes.c_int64, _dp, _dp], ctypes.c_int),
     "ccr_set_templates": ([_vp, ctypes.c_int, ctypes.c_int64, _dp, _dp, _dp], ctypes.c_int),
+    "ccr_set_templates_ecc": ([_vp, ctypes.c_int, ctypes.c_int64, _dp, _dp, _dp, _dp, _dp], ctypes.c_int),
     "ccr_get_band_info": ([_vp, ctypes.c_int, ctypes.POINTER(BandInfo), _dp], ctypes.c_int),
     "ccr_compute_rho": ([_vp, ctypes.c_int, ctypes.c_int, ctypes.POINTER(ctypes.c_int), ctypes.POINTER(_vp),
                          ctypes.c_int, ctypes.c_int, _vp], ctypes.c_int),
@@ -190,10 +191,16 @@ class Context:
                                            b_.ctypes.data_as(_dp)))
 
     def set_templates(self, band_id, templates):
+        """Rows (a_p, T_asc, P) of circular orbits or (a_p, T_p, omega, e, P) of eccentric ones."""
         t = _arr(np.atleast_2d(templates), np.float64)
-        ap, ta, pp = _arr(t[:, 0], np.float64), _arr(t[:, 1], np.float64), _arr(t[:, 2], np.float64)
-        self._check(self.L.ccr_set_templates(self.h, band_id, t.shape[0], ap.ctypes.data_as(_dp),
-                                             ta.ctypes.data_as(_dp), pp.ctypes.data_as(_dp)))
+        cols = [_arr(t[:, k], np.float64) for k in range(t.shape[1])]
+        if t.shape[1] == 3:
+            self._check(self.L.ccr_set_templates(self.h, band_id, t.shape[0], *(c.ctypes.data_as(_dp) for c in cols)))
+        elif t.shape[1] == 5:
+            self._check(self.L.ccr_set_templates_ecc(self.h, band_id, t.shape[0],
+                                                     *(c.ctypes.data_as(_dp) for c in cols)))
+        else:
+            raise ValueError("templates need 3 (circular) or 5 (eccentric) columns")
         self.n_templates[band_id] = t.shape[0]
 
     def band_info(self, band_id, freqs=False):

@@ -22,6 +22,7 @@ using namespace ccr;
 namespace {
 
 constexpr double kPi = 3.14159265358979323846;
+constexpr int kRawStride = 5;
 constexpr long double kPiL = 3.141592653589793238462643383279502884L;
 
 // ------------------------------------------------------------------ device buffers
@@ -75,7 +76,8 @@ struct Band {
     int64_t n_k_min = 0;
     DetData det[CCR_MAX_DET];
     std::vector<double> tmpl;  // kTmplStride per template
-    std::vector<double> tmpl_raw;
+    std::vector<double> tmpl_raw;  // kRawStride per template: a_p, T_asc or T_p, P, e, omega
+    bool ecc = false;               // eccentric templates (set by ccr_set_templates_ecc)
     int64_t n_tmpl = 0;
     bool prepared = false;
     Plan plan;
@@ -776,6 +778,46 @@ ccr_status prepare(ccr_ctx *c, Band &B) {
     return CCR_OK;
 }
 
+// Amplitudes of the harmonics of an eccentric orbit's delay R/c (eqs. solve-for-E,
+// Kepler-equation) in the mean anomaly: with cos E = -e/2 + sum_k (2/k) J'_k(ke) cos kM and
+// sin E = sum_k (2/(ke)) J_k(ke) sin kM, harmonic k of
+// a_p [sin w (cos E - e) + cos w sqrt(1 - e^2) sin E] has amplitude
+// a_p sqrt((sin w (2/k) J'_k(ke))^2 + (cos w sqrt(1 - e^2) (2/(ke)) J_k(ke))^2).  Harmonics are
+// listed until they fall below 1e-24 a_p (at most 4000).
+std::vector<double> orbit_harmonics(double ap, double e, double w) {
+    std::vector<double> A;
+    if (e == 0.0) {
+        A.push_back(ap);
+        return A;
+    }
+    const double sw = std::sin(w), cw = std::cos(w), q = std::sqrt(1.0 - e * e);
+    for (int k = 1; k <= 4000; ++k) {
+        const double x = k * e;
+        const double jk = std::cyl_bessel_j((double)k, x);
+        const double jd = 0.5 * (std::cyl_bessel_j((double)(k - 1), x) - std::cyl_bessel_j((double)(k + 1), x));
+        const double a = sw * 2.0 / k * jd, b = cw * q * 2.0 / x * jk;
+        const double amp = ap * std::sqrt(a * a + b * b);
+        A.push_back(amp);
+        if (k > 4 && amp < 1e-24 * ap) break;
+    }
+    return A;
+}
+
+// Bound on the Chebyshev coefficients from degree n on of A sin(omega u + phi) over [-h, h]:
+// 2 A sum_{m >= n} z^m / m!, z = omega h / 2 (the coefficients are 2 A J_m(omega h)).
+double cheb_tail(double A, double omega, double h, int n) {
+    const double z = 0.5 * omega * h;
+    if (z > 40.0) return HUGE_VAL;
+    double term = 2.0 * A, sum = 0.0;
+    for (int m = 1; m < n; ++m) term *= z / m;
+    for (int m = n; m < n + 400; ++m) {
+        if (m > 0) term *= z / m;
+        sum += term;
+        if (m > z && term < 1e-40 * (sum + 1e-300)) break;
+    }
+    return sum;
+}
+
 ccr_status prepare_templates(ccr_ctx *c, Band &B) {
     const Plan &pl = B.plan;
     if (c->device >= 0) HIP_OK(c, hipDeviceSynchronize());
@@ -784,16 +826,31 @@ ccr_status prepare_templates(ccr_ctx *c, Band &B) {
     const long double t0 = B.det[0].t0, dt = pl.dt;
     const long double tseg = (long double)pl.n_k * dt;
     const long double tau_a0 = t0 + 0.5L * tseg;
-    // Series validity of the in-kernel small-angle expansions (|angle| <= 0.3).
+    auto raw = [&](int64_t t, int k) { return B.tmpl_raw[(size_t)t * kRawStride + k]; };
+    // Series validity of the in-kernel small-angle expansions (|angle| <= 0.3); for an eccentric
+    // orbit the same bound keeps the mean-anomaly offsets of the Kepler solve small.
     const double ld = 0.5 * (double)tseg + 1.0;
     for (int64_t t = 0; t < T; ++t) {
-        const double ap = B.tmpl_raw[3 * t], P = B.tmpl_raw[3 * t + 2];
+        const double ap = raw(t, 0), P = raw(t, 2), e = raw(t, 3);
+        const double apm = ap * (1.0 + e);  // largest |R/c|
         const double Om = 2.0 * kPi / P;
-        if (Om * (ld + 2.0 * ap + 2.0) > 0.3)
+        if (Om * (ld + 2.0 * apm + 2.0) > 0.3)
             return fail(c, CCR_ERANGE, "template %lld: orbit too short for the segment length", (long long)t);
         // the kernels hold the sample shift of a delay (Earth + binary) in 32 bits
-        if ((c->sky.au_s + c->sky.re_s + ap + 1.0) / (double)dt > (double)(1 << 30))
+        if ((c->sky.au_s + c->sky.re_s + apm + 1.0) / (double)dt > (double)(1 << 30))
             return fail(c, CCR_ERANGE, "template %lld: delay too long for the sampling interval", (long long)t);
+        if (B.ecc && e > 0.0) {
+            // six Newton steps of the anchor-relative Kepler solve: from d0 = dM / (1 - e cos E_a)
+            // the error is at most Kc d0^2, Kc = e / (2 (1 - e)) bounding f'' / (2 f'), and each
+            // step maps err -> Kc err^2
+            const double d0 = Om * (ld + 2.0 * apm + 2.0) / (1.0 - e);
+            const double Kc = e / (2.0 * (1.0 - e));
+            double err = Kc * d0 * d0;
+            for (int it = 0; it < 6; ++it) err = Kc * err * err;
+            if (!(err < 1e-17))
+                return fail(c, CCR_ERANGE, "template %lld: Kepler solve does not converge over a segment (e = %.3g)",
+                            (long long)t, e);
+        }
     }
     {
         EarthModel m = earth_model(c->sky, B.det[0].site);
@@ -801,13 +858,18 @@ ccr_status prepare_templates(ccr_ctx *c, Band &B) {
     }
     // Newton steps of the node solve and Chebyshev terms of the split path, from bounds over the
     // templates and detectors.  Newton: the binary-only start is off by at most
-    // e0 = de + a_p Omega (a_p + de) (de: Earth-delay change over the segment), and each step
-    // maps e -> K e^2 with K = G''/(2 G'); two steps suffice when K^3 e0^4 < 1e-20 s.
+    // e0 = de + a_p Omega_1 (a_p (1 + e) + de) (de: Earth-delay change over the segment; Omega_1 =
+    // Omega / (1 - e) bounds the rate of R/c / a_p), and each step maps e -> K e^2 with
+    // K = G''/(2 G'), G'' bounded with a_p Omega^2 / (1 - e)^3; two steps suffice when
+    // K^3 e0^4 < 1e-20 s.
     // Chebyshev: the series of A sin(omega u + phi) on [-h, h] has coefficients 2A J_k(omega h)
-    // <= 2A (omega h / 2)^k / k!; the split path interpolates at 5, 6 or else 7 nodes (error at
-    // most twice the tail from k = 5, 6 or 7) when twice the tail stays below 1e-8 cycles of the
-    // top frequency and 1e-8 samples: under the FP32 rounding of the phase and the offset the
-    // split path applies afterwards (up to 3e-8 cycles and 3e-8 samples).
+    // <= 2A (omega h / 2)^k / k!, summed over the Earth terms and the orbit's harmonics (one for
+    // a circular orbit).  The FP64 path's 10 nodes must leave twice the tail from k = 10 below
+    // 1e-12 cycles of the top frequency and 1e-12 samples (else the template is rejected); the
+    // split path interpolates at 5, 6 or else 7 nodes (error at most twice the tail from k = 5,
+    // 6 or 7) when twice the tail stays below 1e-8 cycles and 1e-8 samples: under the FP32
+    // rounding of the phase and the offset the split path applies afterwards (up to 3e-8 cycles
+    // and 3e-8 samples).
     {
         double Aw = 0.0, Aw2 = 0.0;
         std::vector<std::pair<double, double>> comps;  // (amplitude, angular rate) of the Earth terms
@@ -819,46 +881,65 @@ ccr_status prepare_templates(ccr_ctx *c, Band &B) {
             comps.push_back({(double)m.A_d, (double)m.w_d});
         }
         const double h = 0.5 * (double)tseg;
+        const double f_top = B.p.f_min + B.p.f_band;
         double worst_e2 = 0.0, worst_tail = 0.0, worst_tail6 = 0.0, worst_tail5 = 0.0;
+        std::vector<std::pair<std::pair<double, double>, std::vector<double>>> harm;  // (e, omega) -> harmonics / a_p
         for (int64_t t = 0; t < T; ++t) {
-            const double ap = B.tmpl_raw[3 * t], Om = 2.0 * kPi / B.tmpl_raw[3 * t + 2];
-            const double X = h + ap + 1.0;
+            const double ap = raw(t, 0), Om = 2.0 * kPi / raw(t, 2), e = raw(t, 3);
+            const double Om1 = Om / (1.0 - e), Om2 = Om * Om / ((1.0 - e) * (1.0 - e) * (1.0 - e));
+            const double X = h + ap * (1.0 + e) + 1.0;
             const double de = 1.01 * Aw * X + 1e-9;
-            const double e0 = de + ap * Om * (ap + de);
-            const double K = (1.1 * ap * Om * Om + 1.1 * Aw2) / (2.0 * (1.0 - ap * Om) * (1.0 - Aw));
+            const double e0 = de + ap * Om1 * (ap * (1.0 + e) + de);
+            const double K = (1.1 * ap * Om2 + 1.1 * Aw2) / (2.0 * (1.0 - ap * Om1) * (1.0 - Aw));
             const double e1 = K * e0 * e0, e2 = K * e1 * e1;
             worst_e2 = std::max(worst_e2, e2);
-            double tail = 0.0, tail6 = 0.0, tail5 = 0.0;
             std::vector<std::pair<double, double>> all = comps;
-            all.push_back({ap, Om});
-            for (const auto &cw : all) {
-                const double z = 0.5 * cw.second * 1.01 * h;
-                double term = 2.0 * cw.first;
-                for (int k = 1; k <= 20; ++k) {
-                    term *= z / k;
-                    if (k >= kChebSplit) tail += term;
-                    if (k >= kChebSplitMin) tail6 += term;
-                    if (k >= kChebSplitLow) tail5 += term;
+            if (B.ecc) {
+                const std::pair<double, double> key{e, raw(t, 4)};
+                size_t hi = 0;
+                while (hi < harm.size() && harm[hi].first != key) ++hi;
+                if (hi == harm.size()) {
+                    if (harm.size() >= 64) harm.erase(harm.begin());
+                    harm.push_back({key, orbit_harmonics(1.0, e, key.second)});
+                    hi = harm.size() - 1;
                 }
+                const std::vector<double> &hk = harm[hi].second;
+                for (size_t k = 0; k < hk.size(); ++k) all.push_back({ap * hk[k], (double)(k + 1) * Om});
+            } else {
+                all.push_back({ap, Om});
             }
+            double tail = 0.0, tail6 = 0.0, tail5 = 0.0, tail10 = 0.0;
+            for (const auto &cw : all) {
+                const double hh = 1.01 * h;
+                tail += cheb_tail(cw.first, cw.second, hh, kChebSplit);
+                tail6 += cheb_tail(cw.first, cw.second, hh, kChebSplitMin);
+                tail5 += cheb_tail(cw.first, cw.second, hh, kChebSplitLow);
+                tail10 += cheb_tail(cw.first, cw.second, hh, kCheb);
+            }
+            if (!(2.0 * tail10 * f_top < 1e-12 && 2.0 * tail10 / (double)dt < 1e-12))
+                return fail(c, CCR_ERANGE,
+                            "template %lld: the time base's interpolation error bound (%.3g s) is too large for the "
+                            "segment length (orbit too eccentric or too short)",
+                            (long long)t, 2.0 * tail10);
             worst_tail = std::max(worst_tail, tail);
             worst_tail6 = std::max(worst_tail6, tail6);
             worst_tail5 = std::max(worst_tail5, tail5);
         }
         // short small-angle series (through x^7 / x^8) in the node solve when the dropped terms,
         // amplitude x |angle|^9 / 9! summed over the binary and Earth terms, stay below 1e-16 s
-        // for every template (angles bounded as in the validity check above)
+        // for every template (angles bounded as in the validity check above); an eccentric
+        // orbit's delay is evaluated with full-range sin / cos, so only the Earth terms count
         double worst_series = 0.0;
         {
             double earth = 0.0;
             for (const auto &cw : comps) earth += cw.first * std::pow(cw.second * (ld + 4.0), 9) / 362880.0;
-            for (int64_t t = 0; t < T; ++t) {
-                const double ap = B.tmpl_raw[3 * t], Om = 2.0 * kPi / B.tmpl_raw[3 * t + 2];
+            worst_series = earth;
+            for (int64_t t = 0; t < T && !B.ecc; ++t) {
+                const double ap = raw(t, 0), Om = 2.0 * kPi / raw(t, 2);
                 worst_series = std::max(worst_series, ap * std::pow(Om * (ld + 2.0 * ap + 2.0), 9) / 362880.0 + earth);
             }
         }
         B.short_series = worst_series < 1e-16;
-        const double f_top = B.p.f_min + B.p.f_band;
         B.newton_steps = worst_e2 < 1e-20 ? 2 : 3;
         auto fits = [&](double tl) { return 2.0 * tl * f_top < 1e-8 && 2.0 * tl / (double)dt < 1e-8; };
         B.cheb_split = fits(worst_tail5)   ? kChebSplitLow
@@ -867,8 +948,8 @@ ccr_status prepare_templates(ccr_ctx *c, Band &B) {
     }
     B.tmpl.assign((size_t)T * kTmplStride, 0.0);
     for (int64_t t = 0; t < T; ++t) {
-        const long double ap = B.tmpl_raw[3 * t], tasc = B.tmpl_raw[3 * t + 1], P = B.tmpl_raw[3 * t + 2];
-        long double c0 = (tau_a0 - tasc) / P;
+        const long double ap = raw(t, 0), tref = raw(t, 1), P = raw(t, 2);
+        long double c0 = (tau_a0 - tref) / P;
         c0 -= floorl(c0);
         long double c1 = tseg / P;
         double *o = &B.tmpl[(size_t)t * kTmplStride];
@@ -878,6 +959,11 @@ ccr_status prepare_templates(ccr_ctx *c, Band &B) {
         o[3] = (double)(c0 - (long double)o[2]);
         o[4] = (double)c1;
         o[5] = (double)(c1 - (long double)o[4]);
+        const long double e = raw(t, 3), w = raw(t, 4);
+        o[6] = (double)e;
+        o[7] = (double)sinl(w);
+        o[8] = (double)cosl(w);
+        o[9] = (double)sqrtl(1.0L - e * e);
     }
     if (c->device < 0) return CCR_OK;
     return upload(c, B.d_tmpl, B.tmpl);
@@ -931,6 +1017,7 @@ BandDev band_dev(const Band &B) {
     d.seg_any = B.d_seg_any.as<int>();
     d.n_seg_any = B.n_seg_any;
     d.newton_steps = B.newton_steps;
+    d.ecc = B.ecc ? 1 : 0;
     d.cheb_split = B.cheb_split;
     d.farrow = B.far_len > 0 ? B.d_farrow.as<float2>() : nullptr;
     d.far_len = B.far_len;
@@ -1823,13 +1910,47 @@ ccr_status ccr_set_templates(ccr_ctx *c, int band_id, int64_t n, const double *a
     for (int64_t i = 0; i < n; ++i)
         if (a_p[i] < 0 || !(period[i] > 0)) return fail(c, CCR_EINVAL, "template %lld: a_p < 0 or P <= 0", (long long)i);
     try {
-        B->tmpl_raw.resize((size_t)n * 3);
+        B->tmpl_raw.assign((size_t)n * kRawStride, 0.0);
         for (int64_t i = 0; i < n; ++i) {
-            B->tmpl_raw[3 * i] = a_p[i];
-            B->tmpl_raw[3 * i + 1] = t_asc[i];
-            B->tmpl_raw[3 * i + 2] = period[i];
+            B->tmpl_raw[kRawStride * i] = a_p[i];
+            B->tmpl_raw[kRawStride * i + 1] = t_asc[i];
+            B->tmpl_raw[kRawStride * i + 2] = period[i];
         }
         B->n_tmpl = n;
+        B->ecc = false;
+        B->tmpl.clear();
+    } catch (const std::bad_alloc &) {
+        return fail(c, CCR_ENOMEM, "out of host memory");
+    }
+    return CCR_OK;
+}
+
+ccr_status ccr_set_templates_ecc(ccr_ctx *c, int band_id, int64_t n, const double *a_p, const double *t_p,
+                                 const double *omega, const double *e, const double *period) {
+    if (!c) return CCR_EINVAL;
+    c->err.clear();
+    Band *B = get_band(c, band_id);
+    if (!B) return fail(c, CCR_EINVAL, "bad band id %d", band_id);
+    if (n < 1 || !a_p || !t_p || !omega || !e || !period) return fail(c, CCR_EINVAL, "null or empty template arrays");
+    if (!finite_all(a_p, n) || !finite_all(t_p, n) || !finite_all(omega, n) || !finite_all(e, n) ||
+        !finite_all(period, n))
+        return fail(c, CCR_EINVAL, "non-finite template parameter");
+    for (int64_t i = 0; i < n; ++i) {
+        if (a_p[i] < 0 || !(period[i] > 0)) return fail(c, CCR_EINVAL, "template %lld: a_p < 0 or P <= 0", (long long)i);
+        if (e[i] < 0 || e[i] > 0.95) return fail(c, CCR_EINVAL, "template %lld: e outside [0, 0.95]", (long long)i);
+    }
+    try {
+        B->tmpl_raw.assign((size_t)n * kRawStride, 0.0);
+        for (int64_t i = 0; i < n; ++i) {
+            double *r = &B->tmpl_raw[kRawStride * i];
+            r[0] = a_p[i];
+            r[1] = t_p[i];
+            r[2] = period[i];
+            r[3] = e[i];
+            r[4] = omega[i];
+        }
+        B->n_tmpl = n;
+        B->ecc = true;
         B->tmpl.clear();
     } catch (const std::bad_alloc &) {
         return fail(c, CCR_ENOMEM, "out of host memory");
@@ -1843,8 +1964,9 @@ ccr_status ccr_get_band_info(ccr_ctx *c, int band_id, ccr_band_info *info, doubl
     Band *B = get_band(c, band_id);
     if (!B) return fail(c, CCR_EINVAL, "bad band id %d", band_id);
     if (c->device >= 0) HIP_OK(c, hipSetDevice(c->device));
-    // with templates set, the band is prepared completely (device tables and template table)
-    ccr_status st = B->n_tmpl > 0 && c->device >= 0 ? ensure_ready(c, *B) : prepare(c, *B);
+    // with templates set, the band is prepared completely (device tables and template table;
+    // a host-only context checks the templates without building device tables)
+    ccr_status st = B->n_tmpl > 0 ? ensure_ready(c, *B) : prepare(c, *B);
     if (st) return st;
     const Plan &pl = B->plan;
     std::memset(info, 0, sizeof *info);

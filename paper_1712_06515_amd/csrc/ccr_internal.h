@@ -30,9 +30,11 @@ struct SegWeight {
     double ahat, bhat, scale;
 };
 
-// Per template, six doubles: a_p, Omega = 2 pi / P, and the binary orbital phase (cycles)
-// of segment K's mid-time as c0 + K c1 in double-double: c0h, c0l, c1h, c1l.
-constexpr int kTmplStride = 6;
+// Per template, ten doubles: a_p, Omega = 2 pi / P, and the binary orbital phase (cycles)
+// of segment K's mid-time as c0 + K c1 in double-double: c0h, c0l, c1h, c1l -- for a circular
+// orbit measured from T_asc, for an eccentric one the mean anomaly measured from T_p -- then
+// (eccentric orbits) e, sin omega, cos omega, sqrt(1 - e^2).
+constexpr int kTmplStride = 10;
 
 // Chebyshev nodes per segment for the time base; the split path may use kChebSplit,
 // kChebSplitMin or kChebSplitLow nodes (degree 6, 5 or 4) when the host's bound on the
@@ -96,6 +98,7 @@ struct BandDev {
     const int *seg_any;       // [n_seg_any] ascending segments K where some detector is active
     int n_seg_any;
     int newton_steps;         // Newton steps of the time-base node solve (2 or 3)
+    int ecc;                  // templates are eccentric orbits (Kepler solve in the time base)
     int cheb_split;           // time-base nodes of the split path (kChebSplitLow ... kChebSplit, or kCheb)
     // Farrow table of the split-precision resampler, [Q][kFarDeg + 1][far_len] complex64:
     // plane k at index j + D holds F_k(j) = sum_n A_kn x'_{j+n} (F_0 = x'), zero beyond

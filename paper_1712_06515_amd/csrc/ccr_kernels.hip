@@ -115,6 +115,95 @@ __device__ __forceinline__ double node_eta(double u, double a_p, double Om, doub
     return eta;
 }
 
+// ---- eccentric orbits (Sec. II.A.2, eqs. solve-for-E and Kepler-equation): the binary delay is
+// R/c = a_p [sin w (cos E - e) + cos w sqrt(1 - e^2) sin E] with E - e sin E = M, the mean
+// anomaly M = Omega (t_SSB - T_p).
+
+// E at segment K's anchor: the mean anomaly M_a = 2 pi frac(c0 + K c1) (as binary_anchor), then
+// Newton's method on Kepler's equation from E = M + e sin M until the step is below 1e-15 rad
+// (at most 50 steps; the host admits e <= 0.95).  Returns (sin E_a, cos E_a).
+__device__ __forceinline__ void kepler_anchor(const double *tp, int K, double &sE, double &cE) {
+#pragma clang fp contract(off)
+    const double kd = (double)K;
+    const double A = kd * tp[4];
+    const double eA = fma(kd, tp[4], -A);
+    const double fA = A - floor(A);
+    double ph = fA + (eA + (kd * tp[5] + (tp[2] + tp[3])));
+    ph -= floor(ph);
+    const double e = tp[6];
+    double sM, cM;
+    sincospi(2.0 * ph, &sM, &cM);
+    const double M = 2.0 * M_PI * ph;
+    double E = M + e * sM;
+    for (int it = 0; it < 50; ++it) {
+        double s, c;
+        sincos(E, &s, &c);
+        const double step = (E - e * s - M) / (1.0 - e * c);
+        E -= step;
+        if (fabs(step) < 1e-15) break;
+    }
+    sincos(E, &sE, &cE);
+}
+
+// sin E, cos E at mean anomaly M_a + dM from (sin, cos) of E_a: E = E_a + d solves
+// d - e [sin E_a (cos d - 1) + cos E_a sin d] = dM; six Newton steps from d = dM / (1 - e cos E_a)
+// (the host bounds |dM| and e so that they converge to rounding).  (cos d - 1, sin d) from the
+// half angle, so both stay accurate for small d.
+__device__ __forceinline__ void kepler_offset(double dM, double e, double sEa, double cEa, double &sE, double &cE) {
+    double d = dM / (1.0 - e * cEa);
+    double sd = 0.0, cm = 0.0;
+#pragma unroll
+    for (int it = 0; it < 7; ++it) {
+        double sh, ch;
+        sincos(0.5 * d, &sh, &ch);
+        sd = 2.0 * sh * ch;
+        cm = -2.0 * sh * sh;
+        if (it == 6) break;
+        const double f = d - e * (sEa * cm + cEa * sd) - dM;
+        const double fp = 1.0 - e * (cEa * (1.0 + cm) - sEa * sd);
+        d -= f / fp;
+    }
+    sE = fma(sEa, cm, sEa) + cEa * sd;
+    cE = fma(cEa, cm, cEa) - sEa * sd;
+}
+
+// Binary delay R/c and d(R/c)/dt_SSB at (sin E, cos E).
+__device__ __forceinline__ void ecc_delay(const double *tp, double sE, double cE, double &R, double &Rd) {
+    const double ap = tp[0], Om = tp[1], e = tp[6], sw = tp[7], cw = tp[8], q = tp[9];
+    R = ap * (sw * (cE - e) + cw * q * sE);
+    Rd = ap * Om * (cw * q * cE - sw * sE) / (1.0 - e * cE);
+}
+
+// node_eta for an eccentric orbit: the same equation with the Kepler delay,
+//   G(eta) = eta + rho_a + de(u + eta) - R(M_a + Omega (u + eta + rho_a + de))/c = 0,
+// Newton from the binary-only value R(M_a + Omega u).
+template <bool SHORT>
+__device__ __forceinline__ double node_eta_ecc(double u, const double *tp, double sEa, double cEa,
+                                               const EarthConst &ec, const Anchor &an, int steps) {
+    const double Om = tp[1], e = tp[6];
+    double sE, cE, R, Rd;
+    kepler_offset(Om * u, e, sEa, cEa, sE, cE);
+    ecc_delay(tp, sE, cE, R, Rd);
+    double eta = R;
+#pragma unroll
+    for (int it = 0; it < 3; ++it) {
+        if (it >= steps) break;
+        const double x = u + eta;
+        double so, co, sd, cd;
+        sincos_small<SHORT>(ec.w_o * x, so, co);
+        sincos_small<SHORT>(ec.w_d * x, sd, cd);
+        const double de = ec.A_o * (an.c_o * co - an.s_o * so) + ec.A_d * (an.c_d * cd - an.s_d * sd) + an.rho_a;
+        const double dep = -ec.A_o * ec.w_o * (an.c_o * so + fma(an.s_o, co, an.s_o)) -
+                           ec.A_d * ec.w_d * (an.c_d * sd + fma(an.s_d, cd, an.s_d));
+        kepler_offset(Om * (x + de), e, sEa, cEa, sE, cE);
+        ecc_delay(tp, sE, cE, R, Rd);
+        const double G = eta + de - R;
+        const double Gp = (1.0 + dep) * (1.0 - Rd);
+        eta -= G / Gp;
+    }
+    return eta;
+}
+
 // eta(u) over a segment, u in [-h, h] with h = N_K dt / 2: the degree kCheb - 1 polynomial
 // through the values at the Chebyshev nodes u_j = h cos(pi (j + 1/2) / kCheb), stored by its
 // monomial coefficients in x = u / h: eta = sum_m p_m x^m.  eta is an entire function whose k-th
@@ -169,12 +258,15 @@ __device__ __forceinline__ void timebase_body(const BandDev &B, const double *tm
     __shared__ double sh_eta[E * NN];
     __shared__ double2 sh_bin[E];
     const double *tp = tmpl + (size_t)kTmplStride * tb;
-    // the binary phase at each entry's anchor, once per entry (threads 0 .. E - 1)
+    // the binary phase (eccentric: E) at each entry's anchor, once per entry (threads 0 .. E - 1)
     if (threadIdx.x < E) {
         const int w0 = bx * E + (int)threadIdx.x;
         if (w0 < B.n_work) {
             double sb, cb;
-            binary_anchor(tp, B.work[w0] % B.n_seg, sb, cb);
+            if (B.ecc)
+                kepler_anchor(tp, B.work[w0] % B.n_seg, sb, cb);
+            else
+                binary_anchor(tp, B.work[w0] % B.n_seg, sb, cb);
             sh_bin[threadIdx.x] = make_double2(sb, cb);
         }
     }
@@ -190,8 +282,10 @@ __device__ __forceinline__ void timebase_body(const BandDev &B, const double *tm
         const double sb = bn.x, cb = bn.y;
         const double h = 0.5 * (double)B.n_k * B.dt;
         const double *xn = B.cheb_x + cheb_x_off(NN);
-        sh_eta[threadIdx.x] = node_eta<SHORT>(h * xn[j], tp[0], tp[1], sb, cb, B.earth[det], B.anchors[entry],
-                                       B.newton_steps);
+        sh_eta[threadIdx.x] = B.ecc ? node_eta_ecc<SHORT>(h * xn[j], tp, sb, cb, B.earth[det], B.anchors[entry],
+                                                          B.newton_steps)
+                                    : node_eta<SHORT>(h * xn[j], tp[0], tp[1], sb, cb, B.earth[det],
+                                                      B.anchors[entry], B.newton_steps);
     }
     __syncthreads();
     const double *V = B.mono + cheb_rule(NN) * kCheb * kCheb;

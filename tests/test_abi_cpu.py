@@ -283,3 +283,31 @@ def test_farrow_fit_rejected_for_long_windows(lib):
     if ctx.get_option("farrow_degree") == 8:
         assert info["farrow_err"] > 4e-7
     assert info["farrow_degree"] == 0
+
+
+def test_eccentric_template_validation(lib):
+    """Eccentric templates (a_p, T_p, omega, e, P): e outside [0, 0.95] or a non-finite value is
+    rejected when set; an orbit whose time-base interpolation over a segment the library cannot
+    bound (e = 0.9 with 1800 s segments) is rejected when the band is prepared, while moderate
+    eccentricities pass."""
+    ds = synth.make_dataset(small_config(n_seg=4, t_short=1800.0), signal=False)
+    ctx = _host_ctx(ds)
+    bid = ctx.load(ds)
+
+    def err(fn, *a, **k):
+        with pytest.raises(ccr.CcrError) as e:
+            fn(*a, **k)
+        return e.value.status
+
+    P = 68023.7
+    assert err(ctx.set_templates, bid, np.array([[1.0, 0.0, 0.3, 0.96, P]])) == ccr.EINVAL
+    assert err(ctx.set_templates, bid, np.array([[1.0, 0.0, 0.3, -0.1, P]])) == ccr.EINVAL
+    assert err(ctx.set_templates, bid, np.array([[1.0, np.nan, 0.3, 0.1, P]])) == ccr.EINVAL
+    with pytest.raises(ValueError):
+        ctx.set_templates(bid, np.zeros((2, 4)))
+    ctx.set_templates(bid, np.array([[1.5, 100.0, 0.3, 0.3, P], [1.0, 0.0, 2.0, 0.0, P]]))
+    assert ctx.band_info(bid)["n_templates"] == 2
+    ctx.set_templates(bid, np.array([[1.5, 100.0, 0.3, 0.9, P]]))
+    assert err(ctx.band_info, bid) == ccr.ERANGE
+    ctx.set_templates(bid, np.array([[1.5, 100.0, P]]))
+    assert ctx.band_info(bid)["n_templates"] == 1

@@ -680,3 +680,77 @@ def test_autotune_picks_chunk(ccr):
         again = ctx.compute_rho(bid, prec=ccr.PREC_FP64)
         assert np.array_equal(again, tuned)
         assert ctx.get_option("tuned_k_chunk") == kc
+
+
+# ------------------------------------------------------- eccentric orbits
+
+def _ecc_grid(t_p0):
+    # eccentricities 0 ... 0.5, two arguments of periapse, two periapse times
+    rows = []
+    for e in (0.0, 0.1, 0.3, 0.5):
+        for w in (0.8, 2.5):
+            for dtp in (0.0, 900.0):
+                rows.append([1.6, t_p0 + dtp, w, e, 68023.7])
+    return np.array(rows)
+
+
+def _ecc_dataset(q=2, R=1, pairs=3, gaps=0.2, n_seg=24, t_short=240.0):
+    cfg = small_config(q=q, n_seg=n_seg, t_short=t_short, max_lag=R, pairs=pairs, gap_fraction=gaps,
+                       f_min=100.0, f_band=0.3, a_p_max=2.0)
+    cfg["injections"] = [dict(f0=100.13, a_p=1.6, t_asc_off=0.0, period=68023.7, h0=1.0, cosi=0.6, psi=0.2,
+                              phi0=0.3, ecc=0.3, w=0.8, t_p_off=300.0)]
+    ds = synth.make_dataset(cfg, sigma_wander=0.2)
+    ds.templates = _ecc_grid(cfg["t_asc0"] + 300.0)
+    ds.ecc = True
+    return ds
+
+
+ECC_CASES = {
+    # (detectors, max lag, pair kinds, gap fraction, segments, T_short)
+    "q2_lag1_both": (2, 1, 3, 0.2, 24, 240.0),
+    "q3_lag2_cross": (3, 2, 1, 0.1, 18, 240.0),
+    "q2_lag0_wide": (2, 0, 1, 0.2, 14, 600.0),
+}
+
+
+@pytest.mark.parametrize("case", sorted(ECC_CASES))
+def test_eccentric_templates(ccr, case):
+    """Eccentric orbital templates (Sec. II.A.2, eqs. solve-for-E and Kepler-equation; e up to
+    0.5, two arguments of periapse, two periapse times) with an eccentric injection: the
+    library's anchor-relative Kepler solve in the time base against the oracle's long-double
+    solve of the full map, rho element by element, FP64 and split."""
+    q, R, pairs, gaps, n_seg, ts = ECC_CASES[case]
+    ds = _ecc_dataset(q, R, pairs, gaps, n_seg, ts)
+    ref = oracle.Oracle(ds).rho(ds.templates)
+    r64, r32 = run_both(ccr, ds, ds.templates, k_chunk=5)
+    e64, e32 = rho_err(r64, ref), rho_err(r32, ref)
+    print(f"eccentric {case}: fp64 {e64:.2e} split {e32:.2e} max|rho| {np.abs(ref).max():.2f} at template "
+          f"{np.unravel_index(ref.argmax(), ref.shape)[0]}")
+    assert e64 < TOL64 and e32 < TOL32
+
+
+def test_eccentric_time_base(ccr):
+    """The eccentric time base alone (e = 0.3 and 0.5): delay and heterodyne phase of samples of
+    first, middle and last segments against the oracle's long-double Newton solve (bars as for
+    the circular time base)."""
+    ds = _ecc_dataset(n_seg=30, t_short=600.0, gaps=0.0)  # every segment computed
+    ds.templates = ds.templates[[4, 5, 12, 15]]
+    worst_d, worst_p = _time_base_errors(ccr, ds, [0, 1, 2, 3])
+    print(f"eccentric time base: delay {worst_d:.2e} s, phase {worst_p:.2e} cycles")
+    assert worst_d < 5e-14
+    assert worst_p < 2e-12
+
+
+def test_eccentric_zero_e_matches_circular(ccr):
+    """e = 0 through the eccentric path equals the circular template with T_asc = T_p - omega /
+    Omega (eq. Kepler-equation at e = 0) to rounding."""
+    ds = _ecc_dataset(n_seg=16)
+    P, w, tp = 68023.7, 0.8, ds.templates[0, 1]
+    tm_e = np.array([[1.6, tp, w, 0.0, P], [1.2, tp + 500.0, 2.0, 0.0, P]])
+    tm_c = np.array([[1.6, tp - w * P / (2 * math.pi), P], [1.2, tp + 500.0 - 2.0 * P / (2 * math.pi), P]])
+    re64, re32 = run_both(ccr, ds, tm_e)
+    rc64, rc32 = run_both(ccr, ds, tm_c)
+    scale = max(1.0, np.abs(rc64).max())
+    print(f"e = 0 vs circular: fp64 {np.abs(re64 - rc64).max() / scale:.2e} split {np.abs(re32 - rc32).max() / scale:.2e}")
+    assert np.abs(re64 - rc64).max() < 1e-11 * scale
+    assert np.abs(re32 - rc32).max() < 2e-5 * scale
