@@ -282,6 +282,28 @@ ccr_status ccr_compute_rho(ccr_ctx *ctx, ccr_precision prec, int n_bands, const 
 ccr_status ccr_compute_rho_noalloc(ccr_ctx *ctx, ccr_precision prec, int n_bands, const int *band_ids,
                                    void *const *rho_out, int out_fp64, void *hip_stream);
 
+/* The heterodyned, downsampled series of one detector from its short Fourier transforms (App. B,
+ * downsampling and heterodyning), computed on the context's device: the input of ccr_set_data.
+ *   n_sft, t_sft, t0   SFT K covers [t0 + K t_sft, t0 + (K + 1) t_sft) (seconds after the epoch)
+ *   n_bins, k_first    bins held per SFT, frequencies k / t_sft for k = k_first .. k_first + n_bins - 1
+ *   z                  n_sft x n_bins complex bins (interleaved float32, host), the transform
+ *                      z_k = dt sum_j x_j exp(-2 pi i j k / N) of the SFT's N samples x_j
+ *   sft_valid          n_sft flags (host) or NULL: a missing SFT (0) gives zeros
+ *   f_het              heterodyne frequency (the band's f_min + f_band / 2)
+ *   n_out              N' samples per SFT (1 .. 4096; at least t_sft x the band's load bandwidth)
+ *   x_out, valid_out   n_sft x n_out complex (interleaved float32, host) and 0/1 bytes (or NULL)
+ * Output sample j of SFT K, at t = t0 + K t_sft + j t_sft / N', is
+ *   exp(-2 pi i f_het t_K) sum_{k} z_{K,k} exp(2 pi i (k - f_het t_sft) j / N') / t_sft,
+ * the sum over the N' bins k_h - h .. k_h - h + N' - 1 around the nearest bin k_h to f_het
+ * (h = floor(N'/2)), t_K = t0 + K t_sft: the band's inverse transform (eq. freq-shifted-eq),
+ * stitched across SFTs by the phase of eq. long-time-series-het-corrected and heterodyned by
+ * f_het itself (the remainder of f_het off the bin grid is applied, not dropped).  With
+ * t_sft = the band's T_short and N' its N_K, the series has the band's lattice (dt = T_short /
+ * N_K).  CCR_ERANGE when the SFTs do not hold the N' bins; CCR_EINVAL for NaN/Inf. */
+ccr_status ccr_sft_series(ccr_ctx *ctx, int64_t n_sft, double t_sft, double t0, int64_t n_bins, int64_t k_first,
+                          const float *z, const uint8_t *sft_valid, double f_het, int64_t n_out, float *x_out,
+                          uint8_t *valid_out);
+
 /* Wait for all work queued by this context. */
 ccr_status ccr_sync(ccr_ctx *ctx);
 
@@ -290,7 +312,7 @@ ccr_status ccr_sync(ccr_ctx *ctx);
  * launch).  kernel: 0 resampling, 1 segment spectra, 2 pair sum, 3 final scaling,
  * 4 fused resampling + spectra + pair sum, 5 FP64 time base (per-segment interpolating polynomial),
  * 6 spectra + pair sum in one kernel (split precision, 256-point segments), 7 the same for
- * 1024-point segments.
+ * 1024-point segments, 8 the SFT front end (ccr_sft_series).
  * Waits for the recorded launches to finish. */
 ccr_status ccr_kernel_time(ccr_ctx *ctx, int kernel, double *ms, int64_t *launches);
 ccr_status ccr_reset_kernel_times(ccr_ctx *ctx);

@@ -95,6 +95,8 @@ def lib():
         L.cco_num_threads.restype = ctypes.c_int
         L.cco_kepler.argtypes = [ctypes.c_double, ctypes.c_double]
         L.cco_kepler.restype = ctypes.c_double
+        L.cco_sft_series.argtypes = [ctypes.c_int64, ctypes.c_double, ctypes.c_double, ctypes.c_int64, ctypes.c_int64,
+                                     dp, ctypes.c_void_p, ctypes.c_double, ctypes.c_int64, dp]
         _lib = L
     return _lib
 
@@ -243,3 +245,17 @@ def num_threads():
 def kepler(M, e):
     """Eccentric anomaly E with E - e sin E = M (the oracle's long-double Newton solve)."""
     return lib().cco_kepler(float(M), float(e))
+
+
+def sft_series(z, t_sft, t0, k_first, f_het, n_out, sft_valid=None):
+    """Heterodyned, downsampled series (n_sft * n_out complex128) from SFT bins z (n_sft x n_bins
+    complex, first bin k_first) by the steps of App. B."""
+    zz = np.ascontiguousarray(np.asarray(z, dtype=np.complex128))
+    n_sft, n_bins = zz.shape
+    zv = zz.view(np.float64).reshape(-1)
+    out = np.zeros(2 * n_sft * n_out)
+    vv = None if sft_valid is None else np.ascontiguousarray(sft_valid, dtype=np.uint8)
+    _check(lib().cco_sft_series(n_sft, float(t_sft), float(t0), n_bins, int(k_first), _dp(zv),
+                                None if vv is None else vv.ctypes.data, float(f_het), int(n_out), _dp(out)),
+           "sft_series")
+    return out.view(np.complex128)

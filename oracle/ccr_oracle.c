@@ -865,3 +865,67 @@ int cco_rho(const cco_problem *p, const double *tmpl, int64_t n_tmpl, int tier,
     free(masks); free(phi); free(tw);
     return fail ? CCO_ENOMEM : CCO_OK;
 }
+
+/* ------------------------------------------------- SFT front end */
+
+/* Heterodyned, downsampled series from short Fourier transforms (App. B, Downsampling and
+ * heterodyning).  SFT K holds bins z_{K,k}, k = k_first .. k_first + n_bins - 1 (frequency
+ * k / T_sft), of the data starting at t0 + K T_sft; its inverse transform is
+ * x_K(t0 + K T_sft + j dt) = sum_k z_{K,k} exp(2 pi i j k dt / T_sft) / T_sft (eq. inverse-fft-eq).
+ * Steps in the appendix's order:
+ *   - heterodyne bin k_h, the nearest bin to f_h, with bar f_h = k_h / T_sft and remainder
+ *     f_r = f_h - bar f_h;
+ *   - the band of N' = n_out bins k_h - h .. k_h - h + N' - 1 (h = floor(N'/2); the appendix's
+ *     k_a .. k_b with k_b - k_a = N'), re-indexed m = l + h with l = k - k_h;
+ *   - per SFT, x_{K,s}(j') = e^{-2 pi i j' h / N'} sum_m e^{2 pi i j' m / N'} z_{K,(m + k_h - h)} / T_sft
+ *     at the downsampled samples j' = 0 .. N' - 1 (dt' = T_sft / N'); the leading factor is the
+ *     appendix's (-1)^{-j'} for even N', written for any N';
+ *   - the phase that stitches the SFTs: x^h(t) = e^{-2 pi i f_h (t_K - T_sft/2)} x_{K,s}(j') with
+ *     t_K - T_sft/2 = t0 + K T_sft (eq. long-time-series-het-corrected);
+ *   - and, where the appendix sets bar f_h ~ f_h (eq. heterodyne-shift-approx), the remainder
+ *     kept exactly: a factor e^{-2 pi i f_r j' dt'}, so that the series is heterodyned by f_h
+ *     itself (the resampler's correction e^{2 pi i f_h Delta} assumes that).
+ * Missing SFTs (sft_valid[K] == 0) give zeros.  x: 2 * n_sft * n_out doubles (interleaved). */
+int cco_sft_series(int64_t n_sft, double t_sft, double t0, int64_t n_bins, int64_t k_first, const double *z,
+                   const uint8_t *sft_valid, double f_het, int64_t n_out, double *x) {
+    if (n_sft < 1 || n_bins < 1 || n_out < 1 || !(t_sft > 0) || !z || !x) return CCO_EINVAL;
+    long double ts = t_sft, fh = f_het;
+    int64_t kh = (int64_t)llroundl(fh * ts);
+    long double fr = fh - (long double)kh / ts;
+    int64_t h = n_out / 2;
+    if (kh - h < k_first || kh - h + n_out > k_first + n_bins) return CCO_ERANGE;
+    long double dtp = ts / (long double)n_out;
+#pragma omp parallel for schedule(static)
+    for (int64_t K = 0; K < n_sft; ++K) {
+        double *xo = x + 2 * K * n_out;
+        if (sft_valid && !sft_valid[K]) {
+            for (int64_t j = 0; j < 2 * n_out; ++j) xo[j] = 0.0;
+            continue;
+        }
+        /* stitching phase of this SFT, cycles */
+        long double tk = (long double)t0 + (long double)K * ts;
+        long double ph = fh * tk;
+        ph -= floorl(ph);
+        long double cs = cosl(-2.0L * PI_L * ph), sn = sinl(-2.0L * PI_L * ph);
+        const double *zk = z + 2 * (K * n_bins + (kh - h - k_first));
+        for (int64_t j = 0; j < n_out; ++j) {
+            long double re = 0.0L, im = 0.0L;
+            for (int64_t m = 0; m < n_out; ++m) {
+                long double a = 2.0L * PI_L * (long double)((j * m) % n_out) / (long double)n_out;
+                long double c = cosl(a), s = sinl(a);
+                re += (long double)zk[2 * m] * c - (long double)zk[2 * m + 1] * s;
+                im += (long double)zk[2 * m] * s + (long double)zk[2 * m + 1] * c;
+            }
+            /* x_{K,s}: shift factor and 1 / T_sft */
+            long double as = -2.0L * PI_L * (long double)((j * h) % n_out) / (long double)n_out;
+            long double xr = (re * cosl(as) - im * sinl(as)) / ts;
+            long double xi = (re * sinl(as) + im * cosl(as)) / ts;
+            /* remainder f_r and stitching phase */
+            long double ar = -2.0L * PI_L * fr * (long double)j * dtp;
+            long double c2 = cosl(ar) * cs - sinl(ar) * sn, s2 = cosl(ar) * sn + sinl(ar) * cs;
+            xo[2 * j] = (double)(xr * c2 - xi * s2);
+            xo[2 * j + 1] = (double)(xr * s2 + xi * c2);
+        }
+    }
+    return CCO_OK;
+}

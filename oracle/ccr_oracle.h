@@ -106,6 +106,12 @@ int64_t cco_pair_count(const cco_problem *p);
 int cco_rho(const cco_problem *p, const double *tmpl, int64_t n_tmpl, int tier,
             const int64_t *bins, int64_t n_bins, double *rho);
 int cco_num_threads(void);
+/* Heterodyned, downsampled series from SFT bins (App. B): z holds n_sft x n_bins complex bins
+   (interleaved doubles) starting at bin k_first (frequency k_first / t_sft); SFT K starts at
+   t0 + K t_sft; output x (2 * n_sft * n_out doubles) at t0 + K t_sft + j t_sft / n_out.  ERANGE when
+   the n_out bins around f_het are not all held. */
+int cco_sft_series(int64_t n_sft, double t_sft, double t0, int64_t n_bins, int64_t k_first, const double *z,
+                   const uint8_t *sft_valid, double f_het, int64_t n_out, double *x);
 
 #ifdef __cplusplus
 }

@@ -78,6 +78,8 @@ SIGNATURES = {
                          ctypes.c_int, ctypes.c_int, _vp], ctypes.c_int),
     "ccr_compute_rho_noalloc": ([_vp, ctypes.c_int, ctypes.c_int, ctypes.POINTER(ctypes.c_int), ctypes.POINTER(_vp),
                                  ctypes.c_int, _vp], ctypes.c_int),
+    "ccr_sft_series": ([_vp, ctypes.c_int64, ctypes.c_double, ctypes.c_double, ctypes.c_int64, ctypes.c_int64, _vp,
+                        _vp, ctypes.c_double, ctypes.c_int64, _vp, _vp], ctypes.c_int),
     "ccr_sync": ([_vp], ctypes.c_int),
     "ccr_kernel_time": ([_vp, ctypes.c_int, _dp, ctypes.POINTER(ctypes.c_int64)], ctypes.c_int),
     "ccr_reset_kernel_times": ([_vp], ctypes.c_int),
@@ -243,7 +245,8 @@ class Context:
     def sync(self):
         self._check(self.L.ccr_sync(self.h))
 
-    KERNELS = ("resample", "spectra", "pairs", "finish", "fused", "timebase", "spectra_pairs", "spectra_wide")
+    KERNELS = ("resample", "spectra", "pairs", "finish", "fused", "timebase", "spectra_pairs", "spectra_wide",
+               "sft_series")
 
     def kernel_times(self, reset=False):
         """{kernel: (total_ms, launches)} recorded while option "timing" is 1."""
@@ -275,6 +278,19 @@ class Context:
         self._check(self.L.ccr_time_base(self.h, band_id, int(template_index), int(det), int(k0), int(n),
                                          eta.ctypes.data_as(_dp), anc.ctypes.data_as(_dp), psi.ctypes.data_as(_dp)))
         return eta, anc, psi
+
+    def sft_series(self, z, t_sft, t0, k_first, f_het, n_out, sft_valid=None):
+        """ccr_sft_series: (x complex64 [n_sft * n_out], valid uint8 [n_sft * n_out]) from SFT bins z
+        (n_sft x n_bins complex, first bin k_first)."""
+        zz = _arr(np.atleast_2d(z), np.complex64)
+        n_sft, n_bins = zz.shape
+        vs = None if sft_valid is None else _arr(sft_valid, np.uint8)
+        x = np.zeros(n_sft * int(n_out), dtype=np.complex64)
+        v = np.zeros(n_sft * int(n_out), dtype=np.uint8)
+        self._check(self.L.ccr_sft_series(self.h, n_sft, float(t_sft), float(t0), n_bins, int(k_first), zz.ctypes.data,
+                                          None if vs is None else vs.ctypes.data, float(f_het), int(n_out),
+                                          x.ctypes.data, v.ctypes.data))
+        return x, v
 
     def segment_spectra(self, band_id, template_index, prec=PREC_FP64):
         info = self.band_info(band_id)

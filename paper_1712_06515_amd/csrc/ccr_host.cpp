@@ -140,8 +140,8 @@ struct ccr_ctx {
         hipEvent_t a, b;
     };
     std::vector<Timed> timed;
-    double kt_ms[8] = {0, 0, 0, 0, 0, 0, 0, 0};
-    int64_t kt_n[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+    double kt_ms[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
+    int64_t kt_n[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
     // no-allocation entry point: host staging of its band and work-item tables (fixed size,
     // allocated with the context) and the event after which the staging may be rewritten
     std::vector<char> na_host;
@@ -2082,7 +2082,7 @@ ccr_status ccr_compute_rho_noalloc(ccr_ctx *c, ccr_precision prec, int n_bands, 
 
 ccr_status ccr_kernel_time(ccr_ctx *c, int kernel, double *ms, int64_t *launches) {
     if (!c || !ms || !launches) return CCR_EINVAL;
-    if (kernel < 0 || kernel > 7) return fail(c, CCR_EINVAL, "kernel id %d out of range", kernel);
+    if (kernel < 0 || kernel > 8) return fail(c, CCR_EINVAL, "kernel id %d out of range", kernel);
     collect_times(c);
     *ms = c->kt_ms[kernel];
     *launches = c->kt_n[kernel];
@@ -2092,7 +2092,7 @@ ccr_status ccr_kernel_time(ccr_ctx *c, int kernel, double *ms, int64_t *launches
 ccr_status ccr_reset_kernel_times(ccr_ctx *c) {
     if (!c) return CCR_EINVAL;
     collect_times(c);
-    for (int k = 0; k < 8; ++k) {
+    for (int k = 0; k < 9; ++k) {
         c->kt_ms[k] = 0.0;
         c->kt_n[k] = 0;
     }
@@ -2104,6 +2104,69 @@ ccr_status ccr_sync(ccr_ctx *c) {
     if (c->device < 0) return CCR_OK;
     HIP_OK(c, hipSetDevice(c->device));
     HIP_OK(c, hipDeviceSynchronize());
+    return CCR_OK;
+}
+
+ccr_status ccr_sft_series(ccr_ctx *c, int64_t n_sft, double t_sft, double t0, int64_t n_bins, int64_t k_first,
+                          const float *z, const uint8_t *sft_valid, double f_het, int64_t n_out, float *x_out,
+                          uint8_t *valid_out) {
+    if (!c) return CCR_EINVAL;
+    c->err.clear();
+    if (!z || !x_out) return fail(c, CCR_EINVAL, "null input or output");
+    if (n_sft < 1 || n_bins < 1 || n_out < 1) return fail(c, CCR_EINVAL, "empty SFT set");
+    if (!std::isfinite(t_sft) || !std::isfinite(t0) || !std::isfinite(f_het) || !(t_sft > 0) || !(f_het > 0))
+        return fail(c, CCR_EINVAL, "t_sft, t0 or f_het not finite and positive");
+    if (n_out > kSftMaxOut) return fail(c, CCR_ERANGE, "n_out %lld above %d", (long long)n_out, kSftMaxOut);
+    if (n_sft > (int64_t)1 << 31 || n_sft * n_out > (int64_t)1 << 34)
+        return fail(c, CCR_ERANGE, "too many SFTs for one call");
+    if (c->device < 0) return fail(c, CCR_EDEVICE, "host-only context");
+    // heterodyne bin, the band of n_out bins around it and the remainder of f_h off the bin grid
+    const long double ts = t_sft, fh = f_het;
+    const int64_t kh = (int64_t)llroundl(fh * ts);
+    const long double nu = fh * ts - (long double)kh;
+    const int64_t h = n_out / 2;
+    const int64_t off = kh - h - k_first;
+    if (off < 0 || off + n_out > n_bins)
+        return fail(c, CCR_ERANGE, "the SFTs hold bins %lld..%lld, the band needs %lld..%lld", (long long)k_first,
+                    (long long)(k_first + n_bins - 1), (long long)(kh - h), (long long)(kh - h + n_out - 1));
+    for (int64_t i = 0; i < 2 * n_sft * n_bins; ++i)
+        if (!std::isfinite(z[i])) return fail(c, CCR_EINVAL, "non-finite SFT bin at %lld", (long long)(i / 2));
+    HIP_OK(c, hipSetDevice(c->device));
+    std::vector<double2> roots((size_t)n_out), ej((size_t)n_out), sk((size_t)n_sft);
+    for (int64_t m = 0; m < n_out; ++m) {
+        const long double a = 2.0L * kPiL * (long double)m / (long double)n_out;
+        roots[(size_t)m] = make_double2((double)cosl(a), (double)sinl(a));
+        const long double b = -2.0L * kPiL * nu * (long double)m / (long double)n_out;
+        ej[(size_t)m] = make_double2((double)(cosl(b) / ts), (double)(sinl(b) / ts));
+    }
+    for (int64_t K = 0; K < n_sft; ++K) {
+        long double ph = fh * ((long double)t0 + (long double)K * ts);
+        ph -= floorl(ph);
+        const long double a = -2.0L * kPiL * ph;
+        sk[(size_t)K] = make_double2((double)cosl(a), (double)sinl(a));
+    }
+    DevBuf dz, dx, dr, de, ds, dv;
+    const size_t zb = (size_t)n_sft * n_bins * sizeof(float2), xb = (size_t)n_sft * n_out * sizeof(float2);
+    HIP_OK(c, dz.ensure(zb));
+    HIP_OK(c, dx.ensure(xb));
+    ccr_status st;
+    if ((st = upload(c, dr, roots)) || (st = upload(c, de, ej)) || (st = upload(c, ds, sk))) return st;
+    if (sft_valid) {
+        if ((st = upload(c, dv, std::vector<uint8_t>(sft_valid, sft_valid + n_sft)))) return st;
+    }
+    hipStream_t s = c->stream;
+    HIP_OK(c, hipMemcpyAsync(dz.p, z, zb, hipMemcpyHostToDevice, s));
+    {
+        LaunchTimer lt(c, 8, s);
+        HIP_OK(c, launch_sft_series(dz.as<float2>(), n_sft, n_bins, off, (int)n_out, (int)h, dr.as<double2>(),
+                                    de.as<double2>(), ds.as<double2>(), sft_valid ? dv.as<uint8_t>() : nullptr,
+                                    dx.as<float2>(), s));
+    }
+    HIP_OK(c, hipMemcpyAsync(x_out, dx.p, xb, hipMemcpyDeviceToHost, s));
+    HIP_OK(c, hipStreamSynchronize(s));
+    if (valid_out)
+        for (int64_t K = 0; K < n_sft; ++K)
+            std::memset(valid_out + K * n_out, sft_valid ? (sft_valid[K] ? 1 : 0) : 1, (size_t)n_out);
     return CCR_OK;
 }
 

@@ -214,6 +214,13 @@ hipError_t launch_pairs_m(const BandDev *bands, const WorkItem *items, int n_ite
 hipError_t launch_finish_m(const BandDev *bands, const WorkItem *items, int n_items, int blocks, const double *part,
                            hipStream_t stream);
 hipError_t launch_zero(void *p, size_t bytes, hipStream_t stream);
+// SFT front end: the heterodyned series of n_sft SFTs (complex64 bins, n_bins per SFT; the band of
+// n_out bins starts `off` bins in), roots[m] = exp(2 pi i m / n_out), ej[j] (remainder phase and
+// 1 / T_sft), sk[K] (stitching phase), present[K] (null: all); x: n_sft x n_out complex64.
+constexpr int kSftMaxOut = 4096;
+hipError_t launch_sft_series(const float2 *z, int64_t n_sft, int64_t n_bins, int64_t off, int n_out, int h,
+                             const double2 *roots, const double2 *ej, const double2 *sk, const uint8_t *present,
+                             float2 *x, hipStream_t stream);
 
 // Fixed device scratch of the no-allocation entry point (a file-scope device array of
 // kScratchBytes per device).  scratch_init(device) looks up the array's device address on

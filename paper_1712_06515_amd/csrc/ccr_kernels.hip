@@ -2641,6 +2641,74 @@ hipError_t launch_finish_m(const BandDev *bands, const WorkItem *items, int n_it
     return hipGetLastError();
 }
 
+// ------------------------------------------------------------------ SFT front end
+// Heterodyned, downsampled series from SFT bins (App. B): for SFT K and output sample j
+// (dt' = T_sft / N'),
+//   x(K, j) = S_K E_j sum_{l=-h}^{N'-1-h} z_{K, k_h + l} exp(2 pi i l j / N'),
+// the inverse transform of the N' bins around the heterodyne bin k_h (h = floor(N'/2)), with
+// E_j = exp(-2 pi i nu_r j / N') / T_sft the remainder nu_r = f_h T_sft - k_h of the heterodyne
+// frequency off the bin grid, and S_K = exp(-2 pi i f_h t_K) the phase that makes consecutive
+// SFTs continue one another (t_K the SFT's start).  One 256-thread workgroup per SFT: the SFT's
+// bins (FP32 as given) and, for N' <= kSftTwLds, the N' roots of unity (FP64) sit in LDS; each
+// thread sums outputs j, j + 256, ... in FP64 with the root index (l j) mod N' stepped exactly in
+// integers.  Output complex64.
+namespace {
+constexpr int kSftThreads = 256;
+constexpr int kSftTwLds = 2048;
+
+__global__ void __launch_bounds__(kSftThreads)
+k_sft_series(const float2 *__restrict__ z, int64_t n_bins, int64_t off, int n_out, int h,
+             const double2 *__restrict__ roots, const double2 *__restrict__ ej, const double2 *__restrict__ sk,
+             const uint8_t *__restrict__ present, float2 *__restrict__ x) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    double2 *tw = reinterpret_cast<double2 *>(smem);
+    const bool lds_tw = n_out <= kSftTwLds;
+    float2 *zb = reinterpret_cast<float2 *>(smem + (lds_tw ? (size_t)n_out * sizeof(double2) : 0));
+    const int K = blockIdx.x;
+    float2 *xo = x + (size_t)K * n_out;
+    if (present && !present[K]) {
+        for (int j = threadIdx.x; j < n_out; j += kSftThreads) xo[j] = make_float2(0.f, 0.f);
+        return;
+    }
+    const float2 *zk = z + (size_t)K * n_bins + off;
+    for (int m = threadIdx.x; m < n_out; m += kSftThreads) {
+        zb[m] = zk[m];
+        if (lds_tw) tw[m] = roots[m];
+    }
+    __syncthreads();
+    const double2 *T = lds_tw ? tw : roots;
+    const double2 s = sk[K];
+    for (int j = threadIdx.x; j < n_out; j += kSftThreads) {
+        // index of l = -h: (-h j) mod N'
+        int idx = (int)((int64_t)(n_out - h) * j % n_out);
+        double re = 0.0, im = 0.0;
+        for (int m = 0; m < n_out; ++m) {
+            const float2 v = zb[m];
+            const double2 w = T[idx];
+            re = fma((double)v.x, w.x, fma(-(double)v.y, w.y, re));
+            im = fma((double)v.x, w.y, fma((double)v.y, w.x, im));
+            idx += j;
+            if (idx >= n_out) idx -= n_out;
+        }
+        const double2 e = ej[j];
+        const double er = re * e.x - im * e.y, ei = re * e.y + im * e.x;
+        xo[j] = make_float2((float)(er * s.x - ei * s.y), (float)(er * s.y + ei * s.x));
+    }
+}
+
+}  // namespace
+
+hipError_t launch_sft_series(const float2 *z, int64_t n_sft, int64_t n_bins, int64_t off, int n_out, int h,
+                             const double2 *roots, const double2 *ej, const double2 *sk, const uint8_t *present,
+                             float2 *x, hipStream_t stream) {
+    if (n_sft == 0) return hipSuccess;
+    if (n_out < 1 || n_out > kSftMaxOut) return hipErrorInvalidValue;
+    const size_t lds = (size_t)n_out * sizeof(float2) + (n_out <= kSftTwLds ? (size_t)n_out * sizeof(double2) : 0);
+    hipLaunchKernelGGL(k_sft_series, dim3((unsigned)n_sft), dim3(kSftThreads), lds, stream, z, n_bins, off, n_out, h,
+                       roots, ej, sk, present, x);
+    return hipGetLastError();
+}
+
 // ------------------------------------------------------------------ fixed scratch
 
 // Workspace of ccr_compute_rho_noalloc: a file-scope device array, so that the entry point

@@ -13,7 +13,9 @@ interpolation, no DFT, no pair sum).  What it does:
 * circular complex Gaussian noise, exponential-length data gaps and uneven
   detector coverage (Sec. III.B: gaps are zero-filled);
 * per-segment antenna values a_K, b_K (mid-segment) and noise variances;
-* orbital template grids.
+* orbital template grids;
+* short Fourier transforms of sampled real sinusoids plus white noise, in closed form (the input
+  of the SFT front end, App. B).
 
 The sample interval of the heterodyned series comes from the load bandwidth of
 App. B (eq. delta-f-load), rounded so that T_short holds an integer number of
@@ -27,3 +29,4 @@ from .model import (  # noqa: F401
 )
 from .configs import CONFIGS, config  # noqa: F401
 from .generate import Dataset, make_dataset, make_multiband, multiband_bands, template_grid  # noqa: F401
+from .sft import make_sfts  # noqa: F401

@@ -754,3 +754,90 @@ def test_eccentric_zero_e_matches_circular(ccr):
     print(f"e = 0 vs circular: fp64 {np.abs(re64 - rc64).max() / scale:.2e} split {np.abs(re32 - rc32).max() / scale:.2e}")
     assert np.abs(re64 - rc64).max() < 1e-11 * scale
     assert np.abs(re32 - rc32).max() < 2e-5 * scale
+
+
+# ------------------------------------------------------- SFT front end (App. B)
+
+SFT_CASES = {
+    # (N' samples per SFT, SFTs, f_het, SFT length)
+    "n64_on_grid": (64, 16, 200.0, 240.0),
+    "n63_odd": (63, 16, 200.013, 240.0),
+    "n153_band1": (153, 12, 100.0, 360.0),
+    "n179_prime": (179, 12, 199.9871, 600.0),
+    "n870_large": (870, 6, 400.0, 1440.0),
+    "n2048_lds_table": (2048, 4, 300.0021, 1800.0),
+    "n3001_global_table": (3001, 3, 250.0003, 1800.0),
+}
+
+
+@pytest.mark.parametrize("case", sorted(SFT_CASES))
+def test_sft_series_parity(ccr, case):
+    """The SFT front end (App. B: band selection around k_h, inverse transform of the band, the
+    remainder of f_h off the bin grid, the stitching phase across SFTs) against the oracle's
+    long-double steps, element by element: white noise, two tones (one on a bin centre), a
+    missing SFT; even, odd and prime N', twiddles from LDS and from global memory.  Bar: 2e-6 of
+    the largest |x| (complex64 output of an FP64 sum)."""
+    n_out, n_sft, f_het, t_sft = SFT_CASES[case]
+    kh = int(round(f_het * t_sft))
+    k_first = kh - n_out // 2 - 11
+    n_bins = n_out + 23
+    lines = [(f_het + 3.0 / t_sft, 2.0, 0.3), (f_het - 0.2 * n_out / t_sft + 0.37 / t_sft, 1.0, 1.1)]
+    z, valid = synth.make_sfts(n_sft, t_sft, 1.0 / 4096.0, k_first, n_bins, t0=1234.0 * t_sft, lines=lines,
+                               sigma=0.3, seed=n_out)
+    valid[1] = 0
+    z[1] = 0
+    ref = oracle.sft_series(z, t_sft, 1234.0 * t_sft, k_first, f_het, n_out, sft_valid=valid)
+    with ccr.Context(synth.default_sky(), device=0) as ctx:
+        x, v = ctx.sft_series(z, t_sft, 1234.0 * t_sft, k_first, f_het, n_out, sft_valid=valid)
+    err = np.abs(x - ref).max() / np.abs(ref).max()
+    print(f"SFT front end {case}: {err:.2e} of the peak")
+    assert err < 2e-6
+    assert np.array_equal(v, np.repeat(valid, n_out))
+    assert np.all(x[n_out:2 * n_out] == 0)
+
+
+def test_sft_series_errors(ccr):
+    """Bins not held, too many output samples and NaN bins are rejected before any launch."""
+    z, _ = synth.make_sfts(2, 240.0, 1.0 / 1024.0, 47900, 200, sigma=1.0)
+    with ccr.Context(synth.default_sky(), device=0) as ctx:
+        with pytest.raises(ccr.CcrError) as e:
+            ctx.sft_series(z, 240.0, 0.0, 47900, 200.0, 256)
+        assert e.value.status == ccr.ERANGE
+        with pytest.raises(ccr.CcrError) as e:
+            ctx.sft_series(z, 240.0, 0.0, 47900, 200.0, 5000)
+        assert e.value.status == ccr.ERANGE
+        zb = z.copy()
+        zb[1, 3] = np.nan
+        with pytest.raises(ccr.CcrError) as e:
+            ctx.sft_series(zb, 240.0, 0.0, 47900, 200.0, 64)
+        assert e.value.status == ccr.EINVAL
+
+
+def test_sft_front_end_feeds_rho(ccr):
+    """SFTs -> heterodyned series on the GPU -> rho on the GPU, against SFTs -> the oracle's series
+    -> the oracle's rho: a bin-centred tone in noise, 2 detectors with their own SFTs (one SFT
+    missing), T_sft = T_short and N' = N_K so the series falls on the band's lattice.  The two
+    series differ by the complex64 rounding of the front end's output, so rho agrees to 1e-5."""
+    cfg = small_config(n_seg=16, t_short=240.0, f_min=100.0, f_band=0.2, max_lag=1, gap_fraction=0.0)
+    ds = synth.make_dataset(cfg, signal=False)
+    n_k, t_sft = ds.n_k, cfg["band"]["t_short"]
+    kh = int(round(ds.f_het * t_sft))
+    k_first = kh - n_k // 2 - 4
+    valid_sft = np.ones(ds.n_seg, dtype=np.uint8)
+    valid_sft[5] = 0
+    ref_ds = synth.make_dataset(cfg, signal=False)
+    with ccr.Context(ds.sky, device=0) as ctx:
+        for X in range(2):
+            z, _ = synth.make_sfts(ds.n_seg, t_sft, 1.0 / 2048.0, k_first, n_k + 8, t0=ds.t0,
+                                   lines=[((kh + 9) / t_sft, 2.0, 0.3 + X)], sigma=0.02, seed=10 + X)
+            z[5] = 0
+            x, v = ctx.sft_series(z, t_sft, ds.t0, k_first, ds.f_het, n_k, sft_valid=valid_sft)
+            ds.x[X], ds.valid[X] = x, v
+            xr = oracle.sft_series(z, t_sft, ds.t0, k_first, ds.f_het, n_k, sft_valid=valid_sft)
+            ref_ds.x[X], ref_ds.valid[X] = xr.astype(np.complex64), np.repeat(valid_sft, n_k)
+        bid = ctx.load(ds)
+        r = ctx.compute_rho(bid, prec=ccr.PREC_FP64)
+    ref = oracle.Oracle(ref_ds).rho(ref_ds.templates)
+    err = rho_err(r, ref)
+    print(f"SFT -> series -> rho: {err:.2e}, max rho {ref.max():.2f}")
+    assert err < 1e-5 and ref.max() > 5

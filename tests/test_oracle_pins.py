@@ -703,3 +703,55 @@ def test_eccentric_matched_template_recovers_injection():
     assert r[0].argmax() == i0
     assert abs(r[0, i0] / pred - 1.0) < 0.03
     assert r[1].max() < 0.5 * r[0, i0]
+
+
+# ------------------------------------------------------- SFT front end (App. B)
+
+def _tone_series(f0, amp, ph, f_het, t):
+    return 0.5 * amp * np.exp(1j * (2 * np.pi * np.mod((f0 - f_het) * t, 1.0) + ph))
+
+
+@pytest.mark.parametrize("n_out,f_het", [(64, 200.0), (63, 200.013), (153, 199.9871), (179, 200.0049)])
+def test_sft_front_end_bin_centred_tone(n_out, f_het):
+    """App. B: a real sinusoid on a bin centre inside the band becomes exactly the heterodyned
+    complex tone (A/2) exp(i (2 pi (f0 - f_h) t + phi)) at every downsampled sample of every SFT.
+    This fixes the inverse transform and its index shift (even and odd N'), the stitching phase
+    exp(-2 pi i f_h (t_K - T_sft/2)) across SFTs and the remainder f_r = f_h - k_h / T_sft (f_h off
+    the bin grid)."""
+    t_sft, dt, t0 = 240.0, 1.0 / 1024.0, 7200.0
+    k0 = int(round(200.0 * t_sft)) + 5
+    f0 = k0 / t_sft
+    kh = int(round(f_het * t_sft))
+    k_first = kh - n_out // 2 - 7
+    z, valid = synth.make_sfts(9, t_sft, dt, k_first, n_out + 14, t0=t0, lines=[(f0, 1.3, 0.4)])
+    x = oracle.sft_series(z, t_sft, t0, k_first, f_het, n_out)
+    t = t0 + np.arange(9 * n_out) * (t_sft / n_out)
+    ref = _tone_series(f0, 1.3, 0.4, f_het, t)
+    assert np.abs(x - ref).max() < 1e-11
+
+
+def test_sft_front_end_off_bin_tone_and_gaps():
+    """An off-bin tone (frequency between bins, mid-band) is reproduced to the band's truncation
+    of its Dirichlet leakage, which shrinks as the band widens; a missing SFT gives zeros there
+    and leaves its neighbours unchanged; bins not held give ERANGE."""
+    t_sft, dt, t0, f_het = 240.0, 1.0 / 1024.0, 0.0, 100.0
+    f0 = 100.0 + 0.37 / t_sft
+    errs = []
+    for n_out in (64, 256, 1024):
+        kh = int(round(f_het * t_sft))
+        k_first = kh - n_out // 2
+        z, _ = synth.make_sfts(3, t_sft, dt, k_first, n_out, t0=t0, lines=[(f0, 1.0, 0.0)])
+        x = oracle.sft_series(z, t_sft, t0, k_first, f_het, n_out)
+        t = t0 + np.arange(3 * n_out) * (t_sft / n_out)
+        # away from the SFT edges (the truncated leakage is largest at the edges)
+        inner = np.concatenate([np.arange(K * n_out + n_out // 4, K * n_out + 3 * n_out // 4) for K in range(3)])
+        errs.append(np.abs(x - _tone_series(f0, 1.0, 0.0, f_het, t))[inner].max())
+    assert errs[0] > errs[1] > errs[2] and errs[2] < 0.02
+    z, valid = synth.make_sfts(5, t_sft, dt, 24000 - 40, 80, lines=[(100.1, 1.0, 0.0)], sigma=0.5, seed=3)
+    v = np.array([1, 1, 0, 1, 1], dtype=np.uint8)
+    x_all = oracle.sft_series(z, t_sft, 0.0, 24000 - 40, f_het, 64)
+    x_gap = oracle.sft_series(z, t_sft, 0.0, 24000 - 40, f_het, 64, sft_valid=v)
+    assert np.all(x_gap[128:192] == 0)
+    assert np.array_equal(x_gap[:128], x_all[:128]) and np.array_equal(x_gap[192:], x_all[192:])
+    with pytest.raises(RuntimeError):
+        oracle.sft_series(z, t_sft, 0.0, 24000 - 40, f_het, 96)
