@@ -30,8 +30,8 @@ def test_terms_from_plan():
 def test_fit_recovers_known_constants():
     """Run times made from known constants (the paper's low-N_FFT Table II values) with 2 % noise
     over the sweep's plans: the fit returns the constants within their reported uncertainty (3
-    sigma) and 10 %, and the relative rms residual near the noise level; a side of the N_FFT split
-    with too few rows is left unfitted."""
+    sigma) and 10 %, and the relative rms residual near the noise level; a kernel path with too
+    few rows is left unfitted."""
     rng = np.random.default_rng(3)
     tau = np.array([1.01e-7, 1.62e-7, 5.27e-10])
     rows = []
@@ -42,14 +42,14 @@ def test_fit_recovers_known_constants():
                     n_fft=ns * int(rng.choice([1, 2, 4, 8, 16])))
         x = tmod.features(info, 256, c["D"])
         rows.append(dict(features=list(x), seconds=float(x @ tau) * (1 + 0.02 * rng.standard_normal()),
-                         n_fft=info["n_fft"]))
+                         path="general" if len(rows) % 8 else "fused1024"))
     m = tmod.fit(rows)
-    assert m["high"] is None
-    low = m["low"]
+    assert m["fused256"] is None and m["fused1024"] is not None
+    low = m["general"]
     for i, n in enumerate(tmod.NAMES):
         assert abs(low["tau"][n] - tau[i]) < max(3 * low["sigma"][n], 1e-12)
         assert abs(low["tau"][n] / tau[i] - 1) < 0.1
     assert 0.01 < low["rel_rms"] < 0.03
     info = dict(n_det=2, n_seg=100, n_f=300, n_k=200, n_fft=1024)
-    assert tmod.predict(m, info, 5, 8) == pytest.approx(float(tmod.features(info, 5, 8) @
+    assert tmod.predict(m, info, 5, 8, "general") == pytest.approx(float(tmod.features(info, 5, 8) @
                                                                np.array([low["tau"][n] for n in tmod.NAMES])))
