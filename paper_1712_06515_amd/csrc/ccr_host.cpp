@@ -1155,12 +1155,13 @@ struct Variant {
     bool ss = false;     // time base with the short small-angle series
     bool far = false;    // split-precision resampling in Farrow form
     bool wide = false;   // spectra + pair sum in one kernel, 1024-point segments
+    bool wallp = false;  // wide: every ordered pair (stream-sum partials)
     int DT = 0, window = 0, n_s = 0, nr = 0, n_cheb = kCheb;
     int wcols = 0, wqm = 0;  // wide: bins of a class per lane, detector bound (2 or 4)
     bool operator==(const Variant &o) const {
         return sp == o.sp && reg16 == o.reg16 && z4 == o.z4 && ss == o.ss && far == o.far && wide == o.wide &&
                DT == o.DT && window == o.window && n_s == o.n_s && nr == o.nr && n_cheb == o.n_cheb &&
-               wcols == o.wcols && wqm == o.wqm;
+               wcols == o.wcols && wqm == o.wqm && wallp == o.wallp;
     }
 };
 
@@ -1203,9 +1204,13 @@ Variant variant_of(const BandDev &bd, bool fp64, bool short_series, bool farrow)
     v.far = farrow && !fp64 && bd.farrow != nullptr;
     // the spectra + pair-sum kernels take the Gamma^ave weight over lagged pairs with per-segment
     // weights; the other forms run on the general path
+    // the 256-point spectra + pair-sum kernel takes the Gamma^ave weight over lagged pairs with
+    // per-segment weights, the 1024-point one either weight and every ordered pair as well; the
+    // other forms (per-sample antenna functions: two spectra streams) run on the general path
     const bool plain = bd.weight == CCR_WEIGHT_AVE && !bd.allp && bd.pw == nullptr;
     v.sp = plain && spectra_pairs_ok(bd, fp64, kMaxLds);
-    v.wide = plain && !v.sp && spectra_wide_ok(bd, fp64, kMaxLds);
+    v.wide = !v.sp && bd.pw == nullptr && spectra_wide_ok(bd, fp64, kMaxLds);
+    v.wallp = v.wide && bd.allp;
     v.DT = bd.D == 8 ? 8 : 0;
     v.window = bd.window;
     v.n_cheb = fp64 ? kCheb : bd.cheb_split;
@@ -1457,8 +1462,8 @@ ccr_status run_rounds(ccr_ctx *c, const CallPlan &cp, size_t r0, size_t r1, bool
             HIP_OK(c, launch_spectra_pairs_m(db, di, r.n, (int)r.blocks[kStSpectra], r.v.nr, r.v.z4, r.lds, ws.y, part, s));
         } else if (r.v.wide) {
             LaunchTimer lt(c, 7, s, timing);
-            HIP_OK(c, launch_spectra_wide_m(db, di, r.n, (int)r.blocks[kStSpectra], r.v.wcols, r.v.wqm, r.lds, ws.y,
-                                            part, s));
+            HIP_OK(c, launch_spectra_wide_m(db, di, r.n, (int)r.blocks[kStSpectra], r.v.wcols, r.v.wqm, r.v.wallp,
+                                            r.lds, ws.y, part, s));
         } else {
             {
                 LaunchTimer lt(c, 1, s, timing);

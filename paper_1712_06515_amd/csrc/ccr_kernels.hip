@@ -1409,8 +1409,12 @@ __host__ __device__ inline SpwLayout spw_layout(int Q, int R, int ncol, int jmax
 //   segments behind the next one.  Pair products of a step are summed in FP32, steps in FP64;
 //   one partial per (template, chunk, bin).  Two barriers a step: after the transforms (the ring
 //   holds the step's spectra) and after the pair sums (a ring slot is free again).
+//   Gamma^circ (B.weight): the pair term is (hat b_K hat a_L - hat a_K hat b_L) Im[conj(F_K) F_L],
+//   from the same window sums.  ALLP (every ordered pair, autos included): no windows; the
+//   partials are the chunk's stream sums G^a = sum hat a_XK F_XK and G^b (4 doubles a bin), which
+//   the finishing kernel combines.
 // U: bins of a class per lane (class size <= 128 U); QM: detector bound of the register arrays.
-template <int U, int QM>
+template <int U, int QM, bool ALLP>
 __device__ __forceinline__ void spectra_wide_body(const BandDev &B, const float2 *__restrict__ y, double *part,
                                                   int k_chunk, int n_chunks, int c, int p, int tb) {
     extern __shared__ __align__(16) unsigned char smem[];
@@ -1425,7 +1429,7 @@ __device__ __forceinline__ void spectra_wide_body(const BandDev &B, const float2
     float2 *meta = reinterpret_cast<float2 *>(smem + Ly.off_meta);
     int *slotk = reinterpret_cast<int *>(smem + Ly.off_slotk);
     const int slots = Ly.slots, ncol1 = Ly.ncol1, jmax = B.wide_jmax;
-    const bool cross = (B.pairs & 1) != 0, same = (B.pairs & 2) != 0;
+    const bool cross = (B.pairs & 1) != 0, same = (B.pairs & 2) != 0, circ = B.weight != 0;
     const float2 *tw = B.tw32;
     const int cs = B.class_start[p], n_p = B.class_start[p + 1] - cs;
     const int m0 = B.cls_m0[p];
@@ -1471,7 +1475,7 @@ __device__ __forceinline__ void spectra_wide_body(const BandDev &B, const float2
 
     const int K0 = c * k_chunk;
     const int K1 = min(B.n_seg, K0 + k_chunk);
-    const int Kh = max(0, K0 - R);
+    const int Kh = ALLP ? K0 : max(0, K0 - R);  // every ordered pair: no halo
     auto lower = [&](int key) {
         int a = 0, b = B.n_seg_any;
         while (a < b) {
@@ -1505,9 +1509,11 @@ __device__ __forceinline__ void spectra_wide_body(const BandDev &B, const float2
 
     float2 Ga[QM][U], Gb[QM][U];
     double acc[U];
+    double2 sa[ALLP ? U : 1], sb[ALLP ? U : 1];  // all pairs: the chunk's stream sums
 #pragma unroll
     for (int u = 0; u < U; ++u) {
         acc[u] = 0.0;
+        if constexpr (ALLP) sa[u] = sb[u] = make_double2(0.0, 0.0);
 #pragma unroll
         for (int X = 0; X < QM; ++X) Ga[X][u] = Gb[X][u] = make_float2(0.f, 0.f);
     }
@@ -1573,6 +1579,19 @@ __device__ __forceinline__ void spectra_wide_body(const BandDev &B, const float2
                 f[X] = make_float2(g.x * cph - g.y * sph, g.x * sph + g.y * cph);
                 if (col < n_p) *slotp = f[X];
             }
+            if constexpr (ALLP) {
+                // this step's share of G^a and G^b: FP32 over the detectors, FP64 over steps
+                float2 ta = make_float2(0.f, 0.f), tb2 = make_float2(0.f, 0.f);
+#pragma unroll
+                for (int X = 0; X < QM; ++X) {
+                    if (X >= Q) continue;
+                    ta.x = fmaf(wa[X], f[X].x, ta.x); ta.y = fmaf(wa[X], f[X].y, ta.y);
+                    tb2.x = fmaf(wb[X], f[X].x, tb2.x); tb2.y = fmaf(wb[X], f[X].y, tb2.y);
+                }
+                sa[u].x += (double)ta.x; sa[u].y += (double)ta.y;
+                sb[u].x += (double)tb2.x; sb[u].y += (double)tb2.y;
+                continue;
+            }
             if (count_it) {
                 float st = 0.f;
 #pragma unroll
@@ -1591,8 +1610,14 @@ __device__ __forceinline__ void spectra_wide_body(const BandDev &B, const float2
                             hb.x = fmaf(wb[Y], f[Y].x, hb.x); hb.y = fmaf(wb[Y], f[Y].y, hb.y);
                         }
                     }
-                    st = fmaf(wa[X], f[X].x * ha.x + f[X].y * ha.y, st);
-                    st = fmaf(wb[X], f[X].x * hb.x + f[X].y * hb.y, st);
+                    if (circ) {
+                        // hat b_K Im[conj(F_K) G^a] - hat a_K Im[conj(F_K) G^b]
+                        st = fmaf(wb[X], f[X].x * ha.y - f[X].y * ha.x, st);
+                        st = fmaf(-wa[X], f[X].x * hb.y - f[X].y * hb.x, st);
+                    } else {
+                        st = fmaf(wa[X], f[X].x * ha.x + f[X].y * ha.y, st);
+                        st = fmaf(wb[X], f[X].x * hb.x + f[X].y * hb.y, st);
+                    }
                 }
                 acc[u] += (double)st;
             }
@@ -1606,7 +1631,10 @@ __device__ __forceinline__ void spectra_wide_body(const BandDev &B, const float2
         head = head + 1 == slots ? 0 : head + 1;
         ++count;
         // spectra whose segment is more than R behind the next step's leave the window sums
-        if (e + 1 < hi) {
+        if (ALLP) {
+            tail = head;
+            count = 0;
+        } else if (e + 1 < hi) {
             const int Kn = ld_uniform(B.seg_any, e + 1);
             while (count > 0) {
                 const int Kt = __builtin_amdgcn_readfirstlane(slotk[tail]);
@@ -1636,8 +1664,18 @@ __device__ __forceinline__ void spectra_wide_body(const BandDev &B, const float2
         __syncthreads();
     }
 #pragma unroll
-    for (int u = 0; u < U; ++u)
-        if (binc[u] >= 0) part[((size_t)tb * n_chunks + c) * B.n_f + binc[u]] = acc[u];
+    for (int u = 0; u < U; ++u) {
+        if (binc[u] < 0) continue;
+        if constexpr (ALLP) {
+            double *o = part + (((size_t)tb * n_chunks + c) * B.n_f + binc[u]) * 4;
+            o[0] = sa[u].x;
+            o[1] = sa[u].y;
+            o[2] = sb[u].x;
+            o[3] = sb[u].y;
+        } else {
+            part[((size_t)tb * n_chunks + c) * B.n_f + binc[u]] = acc[u];
+        }
+    }
 }
 
 // The fused kernel keeps the activity bits of a step (S segments x Q detectors) in 64 bits.
@@ -2268,7 +2306,7 @@ k_spectra_pairs_m(const BandDev *__restrict__ bands, const WorkItem *__restrict_
 // dispatcher hands workgroups to the 8 XCDs in turn, so block l runs on XCD l mod 8: the P class
 // workgroups of one (template, chunk) group are given indices with equal l mod 8, which puts
 // them on one XCD, where they read the group's resampled series through that XCD's L2.
-template <int U, int QM>
+template <int U, int QM, bool ALLP>
 __global__ void __launch_bounds__(64 * kSpwWaves)
 k_spectra_wide_m(const BandDev *__restrict__ bands, const WorkItem *__restrict__ items, int n_items,
                  const float2 *__restrict__ y, double *__restrict__ part) {
@@ -2286,8 +2324,8 @@ k_spectra_wide_m(const BandDev *__restrict__ bands, const WorkItem *__restrict__
         g = (G >> 3) * 8 + (l - full) / P;
         p = (l - full) % P;
     }
-    spectra_wide_body<U, QM>(B, y + it.y_off, part + it.part_off, it.k_chunk, it.n_chunks, g % it.n_chunks, p,
-                             g / it.n_chunks);
+    spectra_wide_body<U, QM, ALLP>(B, y + it.y_off, part + it.part_off, it.k_chunk, it.n_chunks, g % it.n_chunks, p,
+                                   g / it.n_chunks);
 }
 
 template <typename T>
@@ -2576,23 +2614,30 @@ hipError_t launch_spectra_pairs_m(const BandDev *bands, const WorkItem *items, i
     return hipGetLastError();
 }
 
-template <int U>
-static void launch_spectra_wide_u(const BandDev *bands, const WorkItem *items, int n_items, int blocks, int qm,
-                                  size_t lds, const void *y, double *part, hipStream_t stream) {
-    if (qm <= 2)
-        hipLaunchKernelGGL((k_spectra_wide_m<U, 2>), dim3(blocks), dim3(64 * kSpwWaves), lds, stream, bands, items, n_items,
-                           (const float2 *)y, part);
-    else
-        hipLaunchKernelGGL((k_spectra_wide_m<U, 4>), dim3(blocks), dim3(64 * kSpwWaves), lds, stream, bands, items, n_items,
-                           (const float2 *)y, part);
+template <bool ALLP>
+static void launch_spectra_wide_u(const BandDev *bands, const WorkItem *items, int n_items, int blocks, int cols,
+                                  int qm, size_t lds, const void *y, double *part, hipStream_t stream) {
+#define CCR_WIDE(U_, QM_)                                                                                       \
+    hipLaunchKernelGGL((k_spectra_wide_m<U_, QM_, ALLP>), dim3(blocks), dim3(64 * kSpwWaves), lds, stream, bands, \
+                       items, n_items, (const float2 *)y, part)
+    if (cols <= 1) {
+        if (qm <= 2) CCR_WIDE(1, 2);
+        else CCR_WIDE(1, 4);
+    } else if (cols <= 2) {
+        if (qm <= 2) CCR_WIDE(2, 2);
+        else CCR_WIDE(2, 4);
+    } else {
+        if (qm <= 2) CCR_WIDE(4, 2);
+        else CCR_WIDE(4, 4);
+    }
+#undef CCR_WIDE
 }
 
 hipError_t launch_spectra_wide_m(const BandDev *bands, const WorkItem *items, int n_items, int blocks, int cols,
-                                 int qm, size_t lds, const void *y, double *part, hipStream_t stream) {
+                                 int qm, bool allp, size_t lds, const void *y, double *part, hipStream_t stream) {
     if (blocks == 0) return hipSuccess;
-    if (cols <= 1) launch_spectra_wide_u<1>(bands, items, n_items, blocks, qm, lds, y, part, stream);
-    else if (cols <= 2) launch_spectra_wide_u<2>(bands, items, n_items, blocks, qm, lds, y, part, stream);
-    else launch_spectra_wide_u<4>(bands, items, n_items, blocks, qm, lds, y, part, stream);
+    if (allp) launch_spectra_wide_u<true>(bands, items, n_items, blocks, cols, qm, lds, y, part, stream);
+    else launch_spectra_wide_u<false>(bands, items, n_items, blocks, cols, qm, lds, y, part, stream);
     return hipGetLastError();
 }
 

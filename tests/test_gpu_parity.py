@@ -273,6 +273,9 @@ WEIGHTED = {
     "circ_256_lag3": (3, 1, False, 2, 3, 0.2, "256"),
     "ps_ave_256_lag2": (3, 0, True, 2, 2, 0.2, "256"),
     "circ_1024_lag2": (3, 1, False, 2, 2, 0.3, "1024"),
+    "circ_1024_q3_both": (3, 1, False, 3, 2, 0.3, "1024"),
+    "all_1024_lag1": (4, 0, False, 2, 1, 0.3, "1024"),
+    "all_circ_1024_q3": (4, 1, False, 3, 2, 0.3, "1024"),
     "ps_all_1024": (4, 0, True, 2, 1, 0.3, "1024"),
 }
 
@@ -298,7 +301,8 @@ def test_weighted_pair_sums(ccr, case):
     A.1-A.2) and per-sample antenna functions (Sec. III.B.3, eq. norm-a-eq: two spectra streams
     per segment), alone and combined, on 128-, 256- and 1024-point segments with gaps, against
     the oracle's stream form; FP64 and split, chunks of 5 segments with their halo, the fused
-    option set (these forms take the general path whatever the option)."""
+    option set.  The split path runs the 1024-point spectra + pair-sum kernel for both weights
+    and all pairs with per-segment weights, the general kernels otherwise."""
     pairs, weight, per_sample, q, R, gaps, shape = WEIGHTED[case]
     ds = weighted_dataset(pairs, weight, per_sample, q, R, gaps, shape)
     o = oracle.Oracle(ds)
@@ -311,15 +315,20 @@ def test_weighted_pair_sums(ccr, case):
         info = ctx.band_info(bid)
         assert abs(info["norm"] / o.norm() - 1.0) < 1e-12
         r64 = ctx.compute_rho(bid, prec=ccr.PREC_FP64)
+        ctx.kernel_times(reset=True)
         r32 = ctx.compute_rho(bid, prec=ccr.PREC_SPLIT, out_fp64=False)
         kt = ctx.kernel_times(reset=True)
         ctx.set_option("template_batch", 1)
         r64b = ctx.compute_rho(bid, prec=ccr.PREC_FP64)
-    assert kt["pairs"][1] > 0 and kt["spectra_pairs"][1] == 0 and kt["spectra_wide"][1] == 0, kt
+        r32b = ctx.compute_rho(bid, prec=ccr.PREC_SPLIT, out_fp64=False)
+    wide = shape == "1024" and not per_sample
+    assert kt["spectra_pairs"][1] == 0, kt
+    assert (kt["spectra_wide"][1] > 0) == wide and (kt["pairs"][1] > 0) != wide, kt
     e64, e32 = rho_err(r64, ref), rho_err(r32, ref)
     print(f"weighted {case}: fp64 {e64:.2e} split {e32:.2e} max|rho| {np.abs(ref).max():.2f}")
     assert e64 < TOL64 and e32 < TOL32
     assert np.array_equal(r64, r64b)  # one template per launch: same arithmetic
+    assert np.array_equal(r32, r32b)
 
 
 def test_weighted_forms_reduce(ccr):
