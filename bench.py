@@ -108,8 +108,9 @@ def cpu_baseline(ds, n_templates, seg_fraction):
                       f"segments ({dt:.1f} s wall on {n} threads), rate scaled by {scale:.1f} to full-length templates"}
 
 
-def roofline(name, avg_ms, tb, info, workload):
-    """Roofline entry of one kernel: `tb` templates per launch, `avg_ms` mean launch time."""
+def roofline(name, avg_ms, tb, info, workload, streams=1):
+    """Roofline entry of one kernel: `tb` templates per launch, `avg_ms` mean launch time;
+    `streams` spectra per segment (2 with per-sample antenna functions)."""
     import numpy as np
     n_active = info["n_active"]
     ns = 1 << (int(info["n_k"]) - 1).bit_length()
@@ -137,8 +138,10 @@ def roofline(name, avg_ms, tb, info, workload):
                 "avg_launch_ms": avg_ms, "algorithmic_bytes_per_launch": byts,
                 "per_unit": f"{8.0 + 8.0 / T_b:g} B per resampled sample (8 B written, 8 B input "
                             f"per tile of {T_b} templates)"}
-    flops = n_active * tb * P * (5.0 * ns * np.log2(ns) + 6.0 * ns)
+    flops = streams * n_active * tb * P * (5.0 * ns * np.log2(ns) + 6.0 * ns)
     per_unit = f"P (5 n_s log2 n_s + 6 n_s) FP32 flop per (template, detector, segment), n_s={ns}, P={P}"
+    if streams != 1:
+        per_unit += f", x{streams} spectra per segment"
     if name in ("spectra_pairs", "fused"):
         # the direct pair sum runs in the same kernel: 8 flop per (template, pair, bin) over the
         # pairs whose two spectra are present
@@ -224,6 +227,8 @@ def main():
     ap.add_argument("--no-extra", action="store_true", help="skip the extra workload lines")
     ap.add_argument("--profile-steps", type=int, default=0)
     ap.add_argument("--copy-calibration", action="store_true")
+    ap.add_argument("--form-templates", type=int, default=256,
+                    help="templates per step of the weighting / pair-set / orbit / front-end lines")
     ap.add_argument("--graph", type=int, default=1)
     ap.add_argument("--autotune", type=int, default=1)
     args = ap.parse_args()
@@ -349,11 +354,110 @@ def main():
     ctx.close()
 
     if not args.no_extra and args.workload == "large":
+        result["forms"] = form_lines(args, ds, info)
         result["extra"] = extra_lines(args)
     if not args.no_cpu_baseline:
         frac = {"large": 1.0 / 24.0, "band": 0.25, "tiny": 1.0}[args.workload]
         result["cpu_baseline"] = cpu_baseline(ds, n_t, frac)
     print(json.dumps(result))
+
+
+def form_lines(args, ds, info0):
+    """The same 240-day band with the other forms of the statistic, each timed on the split path
+    (graph capture, no autotuning) over the first --form-templates templates: the Gamma^circ
+    weight (Sec. II.B), every ordered pair with auto-correlations (App. A.1-A.2), per-sample
+    antenna functions (Sec. III.B.3, two spectra streams), eccentric orbits (e = 0.1, Sec. II.A.2);
+    and the SFT front end (App. B) for the band's 2 x 14400 SFTs of 1440 s.  rho-evals/s, with the
+    roofline of the form's dominant kernel."""
+    import copy
+
+    import numpy as np
+    import torch
+    import synth
+    from paper_1712_06515_amd import Context, PREC_SPLIT
+    n = min(args.form_templates, len(ds.templates))
+    out = {}
+
+    def run(name, dsf, tm, streams=1):
+        t0 = time.perf_counter()
+        with Context(dsf.sky, device=0) as ctx:
+            bid = ctx.load(dsf, templates=tm)
+            inf = ctx.band_info(bid)
+            inf["resample_templates"] = ctx.get_option("resample_templates")
+            inf["farrow_used"] = bool(ctx.get_option("farrow")) and inf["farrow_degree"] > 0
+            inf["n_pairs_present"] = info0["n_pairs_present"]
+            o = torch.empty((len(tm), inf["n_f"]), dtype=torch.float32, device="cuda")
+
+            def step():
+                ctx.compute_rho(bid, prec=PREC_SPLIT, out_fp64=False, outputs=[o.data_ptr()])
+
+            ctx.set_option("graph", 1)
+            sec = time_steps(step, 3, 1)
+            ctx.set_option("graph", 0)
+            ctx.set_option("timing", 1)
+            ctx.kernel_times(reset=True)
+            step()
+            kt = ctx.kernel_times(reset=True)
+        dom = max((k for k in kt if kt[k][1]), key=lambda k: kt[k][0])
+        line = {"value": len(tm) * inf["n_f"] / sec, "unit": "rho-evals/s", "ms_per_step": 1e3 * sec,
+                "templates": len(tm), "kernels_ms_per_step": {k: v[0] for k, v in kt.items() if v[1]},
+                "dominant_kernel": dom}
+        if dom in ("resample", "spectra", "spectra_pairs", "fused", "spectra_wide"):
+            line["roofline"] = roofline(dom, kt[dom][0] / kt[dom][1], len(tm) / kt[dom][1], inf, "large_" + name,
+                                        streams=streams)
+        out[name] = line
+        log(f"form {name}: {line['ms_per_step']:.1f} ms/step, dominant {dom} ({time.perf_counter() - t0:.0f} s)")
+
+    tm = ds.templates[:n]
+    d = copy.copy(ds)
+    d.band = dict(ds.band, weight=1)
+    run("gamma_circ", d, tm)
+    d = copy.copy(ds)
+    d.band = dict(ds.band, pairs=4)
+    run("all_pairs_with_autos", d, tm)
+    d = copy.copy(ds)
+    tau = ds.t0 + np.arange(ds.n_seg * ds.n_k) * ds.dt
+    ab = [synth.antenna_ab(tau, s_, ds.sky) for s_ in ds.sites]
+    d.ar = np.stack([v[0] for v in ab])
+    d.br = np.stack([v[1] for v in ab])
+    del ab, tau
+    run("per_sample_antenna", d, tm, streams=2)
+    d.ar = d.br = None
+    d = copy.copy(ds)
+    d.ecc = True
+    tme = np.stack([tm[:, 0], tm[:, 1], np.full(n, 0.7), np.full(n, 0.1), tm[:, 2]], axis=1)
+    run("eccentric_e0.1", d, tme)
+
+    # SFT front end: one detector's SFTs at a time (the call takes host bins and returns host samples)
+    t_sft, n_out = ds.band["t_short"], ds.n_k
+    kh = int(round(ds.f_het * t_sft))
+    k_first = kh - n_out // 2 - 16
+    z, valid = synth.make_sfts(ds.n_seg, t_sft, 1.0 / 4096.0, k_first, n_out + 32, t0=ds.t0,
+                               lines=[(ds.f_het + 0.01, 1.0, 0.2)], sigma=1.0, seed=9)
+    with Context(ds.sky, device=0) as ctx:
+        ctx.set_option("timing", 1)
+        walls = []
+        for _ in range(3):
+            ctx.kernel_times(reset=True)
+            t0 = time.perf_counter()
+            for X in range(ds.n_det):
+                ctx.sft_series(z, t_sft, ds.t0, k_first, ds.f_het, n_out, sft_valid=valid)
+            walls.append(time.perf_counter() - t0)
+            kt = ctx.kernel_times(reset=True)
+    wall = min(walls)
+    k_ms = kt["sft_series"][0] / kt["sft_series"][1]
+    flops = ds.n_seg * float(n_out) ** 2 * 8.0
+    samples = ds.n_det * ds.n_seg * n_out
+    out["sft_front_end"] = {
+        "value": samples / wall, "unit": "series-samples/s (host bins in, host samples out)",
+        "ms_per_band": 1e3 * wall, "sfts": ds.n_det * ds.n_seg, "n_out": n_out,
+        "kernel_ms_per_detector": k_ms,
+        "roofline": {"kernel": "k_sft_series", "bound": "alu", "achieved": flops / (k_ms * 1e-3) / 1e12,
+                     "peak": 78.6, "unit": "TFLOP/s", "frac": flops / (k_ms * 1e-3) / 1e12 / 78.6, "traffic": None,
+                     "avg_launch_ms": k_ms, "algorithmic_flops_per_launch": flops,
+                     "per_unit": "8 FP64 flop per (SFT, output sample, band bin): the direct inverse transform"}}
+    log(f"form sft_front_end: {1e3 * wall:.1f} ms for {ds.n_det} detectors, kernel {k_ms:.2f} ms per detector")
+    return out
 
 
 def extra_lines(args):
