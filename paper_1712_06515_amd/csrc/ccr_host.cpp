@@ -1156,12 +1156,13 @@ struct Variant {
     bool far = false;    // split-precision resampling in Farrow form
     bool wide = false;   // spectra + pair sum in one kernel, 1024-point segments
     bool wallp = false;  // wide: every ordered pair (stream-sum partials)
+    int wns = 0;         // wide: segment FFT length (256, 512 or 1024)
     int DT = 0, window = 0, n_s = 0, nr = 0, n_cheb = kCheb;
     int wcols = 0, wqm = 0;  // wide: bins of a class per lane, detector bound (2 or 4)
     bool operator==(const Variant &o) const {
         return sp == o.sp && reg16 == o.reg16 && z4 == o.z4 && ss == o.ss && far == o.far && wide == o.wide &&
                DT == o.DT && window == o.window && n_s == o.n_s && nr == o.nr && n_cheb == o.n_cheb &&
-               wcols == o.wcols && wqm == o.wqm && wallp == o.wallp;
+               wcols == o.wcols && wqm == o.wqm && wallp == o.wallp && wns == o.wns;
     }
 };
 
@@ -1215,6 +1216,7 @@ Variant variant_of(const BandDev &bd, bool fp64, bool short_series, bool farrow)
     v.window = bd.window;
     v.n_cheb = fp64 ? kCheb : bd.cheb_split;
     if (v.wide) {
+        v.wns = bd.n_s;
         v.wcols = spectra_wide_cols(bd);
         v.wqm = bd.Q <= 2 ? 2 : 4;
     } else if (v.sp) {
@@ -1462,8 +1464,8 @@ ccr_status run_rounds(ccr_ctx *c, const CallPlan &cp, size_t r0, size_t r1, bool
             HIP_OK(c, launch_spectra_pairs_m(db, di, r.n, (int)r.blocks[kStSpectra], r.v.nr, r.v.z4, r.lds, ws.y, part, s));
         } else if (r.v.wide) {
             LaunchTimer lt(c, 7, s, timing);
-            HIP_OK(c, launch_spectra_wide_m(db, di, r.n, (int)r.blocks[kStSpectra], r.v.wcols, r.v.wqm, r.v.wallp,
-                                            r.lds, ws.y, part, s));
+            HIP_OK(c, launch_spectra_wide_m(db, di, r.n, (int)r.blocks[kStSpectra], r.v.wns, r.v.wcols, r.v.wqm,
+                                            r.v.wallp, r.lds, ws.y, part, s));
         } else {
             {
                 LaunchTimer lt(c, 1, s, timing);

@@ -200,8 +200,9 @@ bool spectra_wide_ok(const BandDev &B, bool fp64, size_t limit);
 size_t spectra_wide_lds(const BandDev &B);
 int spectra_wide_cols(const BandDev &B);
 // cols: spectra_wide_cols of the round's bands; qm: their largest detector count.
-hipError_t launch_spectra_wide_m(const BandDev *bands, const WorkItem *items, int n_items, int blocks, int cols,
-                                 int qm, bool allp, size_t lds, const void *y, double *part, hipStream_t stream);
+hipError_t launch_spectra_wide_m(const BandDev *bands, const WorkItem *items, int n_items, int blocks, int ns,
+                                 int cols, int qm, bool allp, size_t lds, const void *y, double *part,
+                                 hipStream_t stream);
 // z4: N_K <= 192, so the last 4 of the 16 input rows of each 256-point FFT are zero padding.
 hipError_t launch_spectra_pairs_m(const BandDev *bands, const WorkItem *items, int n_items, int blocks, int rounds,
                                   bool z4, size_t lds, const void *y, double *part, hipStream_t stream);

@@ -1359,24 +1359,165 @@ __device__ __forceinline__ void fft1024_wave(float2 *v, float2 *fx, const float2
     wave_sync();
 }
 
-// Workgroup of the 1024-point spectra + pair-sum kernel: kSpwWaves wavefronts share one spectrum
-// ring; wavefront w transforms the detectors X = w, w + kSpwWaves, ... and sums the pairs of the
-// bins (ring columns) w 64 + l + 128 u.
+// 8-point forward DFT in place, natural order: 4-point DFTs of the even and odd inputs, then
+// X[k] = E[k] + W8^k O[k], X[k + 4] = E[k] - W8^k O[k].
+template <typename T>
+__device__ __forceinline__ void dft8(c2<T> *v) {
+    const T h = (T)0.70710678118654752440;
+    c2<T> e0 = v[0], e1 = v[2], e2 = v[4], e3 = v[6], o0 = v[1], o1 = v[3], o2 = v[5], o3 = v[7];
+    dft4<T>(e0, e1, e2, e3);
+    dft4<T>(o0, o1, o2, o3);
+    o1 = cmul<T>(o1, mk<T>(h, -h));
+    o2 = cmul_mi<T>(o2);
+    o3 = cmul<T>(o3, mk<T>(-h, -h));
+    v[0] = cadd<T>(e0, o0);
+    v[4] = csub<T>(e0, o0);
+    v[1] = cadd<T>(e1, o1);
+    v[5] = csub<T>(e1, o1);
+    v[2] = cadd<T>(e2, o2);
+    v[6] = csub<T>(e2, o2);
+    v[3] = cadd<T>(e3, o3);
+    v[7] = csub<T>(e3, o3);
+}
+
+// Pass twiddles of the one-wavefront FFTs (this lane's), W_n = exp(-2 pi i / n), from the
+// N-entry table `tw` of W_N (N = N_FFT, a power of two, at least the FFT length):
+//   1024 points (radix 16, 16, 4): w2[r - 1] = W256^(r (l % 16)), w3[q][r - 1] = W1024^(r (l + 64 q));
+//   512 points (radix 8, 8, 8):    a[r - 1] = W64^(r (l % 8)), b[r - 1] = W512^(r l);
+//   256 points (radix 4, 4, 4, 4): a[r - 1] = W16^(r (l % 4)), b[r - 1] = W64^(r (l % 16)),
+//                                  c[r - 1] = W256^(r l).
+template <int NS> struct WaveTw;
+template <> struct WaveTw<1024> {
+    float2 w2[15], w3[4][3];
+    __device__ __forceinline__ void load(const float2 *tw, int N, int mask, int lane) {
+#pragma unroll
+        for (int r = 1; r < 16; ++r) w2[r - 1] = tw[(r * (lane & 15) * (N >> 8)) & mask];
+#pragma unroll
+        for (int q = 0; q < 4; ++q)
+#pragma unroll
+            for (int r = 1; r < 4; ++r) w3[q][r - 1] = tw[(r * (lane + 64 * q) * (N >> 10)) & mask];
+    }
+};
+template <> struct WaveTw<512> {
+    float2 a[7], b[7];
+    __device__ __forceinline__ void load(const float2 *tw, int N, int mask, int lane) {
+#pragma unroll
+        for (int r = 1; r < 8; ++r) {
+            a[r - 1] = tw[(r * (lane & 7) * (N >> 6)) & mask];
+            b[r - 1] = tw[(r * lane * (N >> 9)) & mask];
+        }
+    }
+};
+template <> struct WaveTw<256> {
+    float2 a[3], b[3], c[3];
+    __device__ __forceinline__ void load(const float2 *tw, int N, int mask, int lane) {
+#pragma unroll
+        for (int r = 1; r < 4; ++r) {
+            a[r - 1] = tw[(r * (lane & 3) * (N >> 4)) & mask];
+            b[r - 1] = tw[(r * (lane & 15) * (N >> 6)) & mask];
+            c[r - 1] = tw[(r * lane * (N >> 8)) & mask];
+        }
+    }
+};
+
+// NS-point forward FFT held by one wavefront (V = NS / 64 values a lane): on entry lane l holds
+// x[l + 64 r] in v[r], on return X[l + 64 J] in v[J].  Self-sorting (Stockham) passes; a pass
+// of radix V with stride Ns has butterfly j = l read a[l + 64 r], twiddle input r by
+// W_(V Ns)^(r (l % Ns)) and write output r to (l / Ns) V Ns + l % Ns + r Ns; the last pass
+// (Ns = 64) writes X[l + 64 r] straight to v[r].  Between passes the values go through `fx`,
+// index i stored at i + i / V (the padding spreads the strided accesses over the LDS banks).
+// 1024 points use fft1024_wave (radix 16, 16, 4).  Single wavefront: wave_sync() orders the
+// LDS accesses for the compiler, the hardware runs them in issue order.
+template <int NS>
+__device__ __forceinline__ void fft_wave(float2 *v, float2 *fx, const WaveTw<NS> &t, int lane);
+
+template <>
+__device__ __forceinline__ void fft_wave<1024>(float2 *v, float2 *fx, const WaveTw<1024> &t, int lane) {
+    fft1024_wave(v, fx, t.w2, t.w3, lane);
+}
+
+template <>
+__device__ __forceinline__ void fft_wave<512>(float2 *v, float2 *fx, const WaveTw<512> &t, int lane) {
+    const int g = lane >> 3, k = lane & 7;
+    // pass 1 (Ns = 1): output r of butterfly l to 8 l + r
+    dft8<float>(v);
+#pragma unroll
+    for (int r = 0; r < 8; ++r) fx[9 * lane + r] = v[r];
+    wave_sync();
+    // pass 2 (Ns = 8): output r to 64 (l / 8) + l % 8 + 8 r
+#pragma unroll
+    for (int r = 0; r < 8; ++r) v[r] = fx[lane + g + 72 * r];
+#pragma unroll
+    for (int r = 1; r < 8; ++r) v[r] = cmul<float>(v[r], t.a[r - 1]);
+    dft8<float>(v);
+    wave_sync();
+#pragma unroll
+    for (int r = 0; r < 8; ++r) fx[72 * g + k + 9 * r] = v[r];
+    wave_sync();
+    // pass 3 (Ns = 64)
+#pragma unroll
+    for (int r = 0; r < 8; ++r) v[r] = fx[lane + g + 72 * r];
+#pragma unroll
+    for (int r = 1; r < 8; ++r) v[r] = cmul<float>(v[r], t.b[r - 1]);
+    dft8<float>(v);
+    wave_sync();
+}
+
+template <>
+__device__ __forceinline__ void fft_wave<256>(float2 *v, float2 *fx, const WaveTw<256> &t, int lane) {
+    const int g4 = lane >> 2, k4 = lane & 3, g16 = lane >> 4, k16 = lane & 15;
+    // pass 1 (Ns = 1): output r of butterfly l to 4 l + r
+    dft4<float>(v[0], v[1], v[2], v[3]);
+#pragma unroll
+    for (int r = 0; r < 4; ++r) fx[5 * lane + r] = v[r];
+    wave_sync();
+    // pass 2 (Ns = 4): output r to 16 (l / 4) + l % 4 + 4 r
+#pragma unroll
+    for (int r = 0; r < 4; ++r) v[r] = fx[lane + g4 + 80 * r];
+#pragma unroll
+    for (int r = 1; r < 4; ++r) v[r] = cmul<float>(v[r], t.a[r - 1]);
+    dft4<float>(v[0], v[1], v[2], v[3]);
+    wave_sync();
+#pragma unroll
+    for (int r = 0; r < 4; ++r) fx[20 * g4 + k4 + 5 * r] = v[r];
+    wave_sync();
+    // pass 3 (Ns = 16): output r to 64 (l / 16) + l % 16 + 16 r
+#pragma unroll
+    for (int r = 0; r < 4; ++r) v[r] = fx[lane + g4 + 80 * r];
+#pragma unroll
+    for (int r = 1; r < 4; ++r) v[r] = cmul<float>(v[r], t.b[r - 1]);
+    dft4<float>(v[0], v[1], v[2], v[3]);
+    wave_sync();
+#pragma unroll
+    for (int r = 0; r < 4; ++r) fx[80 * g16 + k16 + (k16 >> 2) + 20 * r] = v[r];
+    wave_sync();
+    // pass 4 (Ns = 64)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) v[r] = fx[lane + g4 + 80 * r];
+#pragma unroll
+    for (int r = 1; r < 4; ++r) v[r] = cmul<float>(v[r], t.c[r - 1]);
+    dft4<float>(v[0], v[1], v[2], v[3]);
+    wave_sync();
+}
+
+// Workgroup of the spectra + pair-sum kernel for 256- to 1024-point segments: kSpwWaves
+// wavefronts share one spectrum ring; wavefront w transforms the detectors X = w, w + kSpwWaves,
+// ... and sums the pairs of the bins (ring columns) w 64 + l + 128 u.
 constexpr int kSpwWaves = 2;
 
-// LDS of the 1024-point spectra + pair-sum kernel (bytes).
+// LDS of the spectra + pair-sum kernel for ns-point segments (bytes).
 struct SpwLayout {
     int slots, ncol1;
     size_t off_fx, off_ring, off_pos, off_meta, off_slotk, total;
 };
 
-__host__ __device__ inline SpwLayout spw_layout(int Q, int R, int ncol, int jmax) {
+__host__ __device__ inline SpwLayout spw_layout(int Q, int R, int ncol, int jmax, int ns) {
     SpwLayout L;
     L.slots = R + 1;
     L.ncol1 = ncol + 1;  // the last column of a ring row takes FFT outputs that are not output bins
     size_t o = 0;
-    L.off_fx = o;  // one FFT exchange buffer per wavefront
-    o += (size_t)kSpwWaves * (1024 + 64) * sizeof(float2);
+    L.off_fx = o;  // one FFT exchange buffer per wavefront (ns values, padded)
+    o += (size_t)kSpwWaves * (ns + 64) * sizeof(float2);
     L.off_ring = o;
     o += (size_t)L.slots * Q * L.ncol1 * sizeof(float2);
     L.off_pos = o;
@@ -1390,13 +1531,13 @@ __host__ __device__ inline SpwLayout spw_layout(int Q, int R, int ncol, int jmax
     return L;
 }
 
-// Spectra + pair sum for 1024-point segments (split precision, N_FFT a power of two, distinct
-// bins): one workgroup of kSpwWaves wavefronts per (template, residue class p of the output
-// bins, chunk [K0, K1) of segments plus R halo segments before it).
+// Spectra + pair sum for NS-point segments, NS = 256, 512 or 1024 (split precision, N_FFT a power
+// of two, distinct bins): one workgroup of kSpwWaves wavefronts per (template, residue class p of
+// the output bins, chunk [K0, K1) of segments plus R halo segments before it).
 //   Spectra: for each segment K that some detector takes part in (the compacted list
 //   seg_any) and each detector with data there, the zero-padded segment is multiplied by
 //   W_N^(q s), q = p + P m0 (class p, its bins rotated so that the class's output indices
-//   m0 .. m0 + span - 1 land on FFT outputs 0 .. span - 1), transformed by fft1024_wave, and its
+//   m0 .. m0 + span - 1 land on FFT outputs 0 .. span - 1), transformed by fft_wave<NS>, and its
 //   class-p bins are written to a ring of R + 1 spectra in LDS.  Each wavefront loads the input
 //   of its next transform while it computes the current one.
 //   Pair sum: each spectrum is rotated by Phi_in = exp(-2 pi i (kbar r_B mod N) / N) (the phase
@@ -1414,16 +1555,17 @@ __host__ __device__ inline SpwLayout spw_layout(int Q, int R, int ncol, int jmax
 //   partials are the chunk's stream sums G^a = sum hat a_XK F_XK and G^b (4 doubles a bin), which
 //   the finishing kernel combines.
 // U: bins of a class per lane (class size <= 128 U); QM: detector bound of the register arrays.
-template <int U, int QM, bool ALLP>
+template <int NS, int U, int QM, bool ALLP>
 __device__ __forceinline__ void spectra_wide_body(const BandDev &B, const float2 *__restrict__ y, double *part,
                                                   int k_chunk, int n_chunks, int c, int p, int tb) {
     extern __shared__ __align__(16) unsigned char smem[];
+    constexpr int V = NS / 64;  // FFT values a lane
     const int Q = B.Q, n_k = B.n_k, R = B.R, N = B.n_fft, mask = B.nfft_mask;
-    const SpwLayout Ly = spw_layout(Q, R, B.wide_ncol, B.wide_jmax);
+    const SpwLayout Ly = spw_layout(Q, R, B.wide_ncol, B.wide_jmax, NS);
     // the wavefront index, uniform within the wavefront (readfirstlane makes that known to the
     // compiler, so that per-wavefront addresses and buffer descriptors stay in scalar registers)
     const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
-    float2 *fx = reinterpret_cast<float2 *>(smem + Ly.off_fx) + wv * (1024 + 64);
+    float2 *fx = reinterpret_cast<float2 *>(smem + Ly.off_fx) + wv * (NS + 64);
     float2 *ring = reinterpret_cast<float2 *>(smem + Ly.off_ring);
     int16_t *opos = reinterpret_cast<int16_t *>(smem + Ly.off_pos);
     float2 *meta = reinterpret_cast<float2 *>(smem + Ly.off_meta);
@@ -1439,14 +1581,14 @@ __device__ __forceinline__ void spectra_wide_body(const BandDev &B, const float2
     for (int e = threadIdx.x; e < slots * Q * ncol1; e += 64 * kSpwWaves) ring[e] = make_float2(0.f, 0.f);
     __syncthreads();
     for (int col = threadIdx.x; col < n_p; col += 64 * kSpwWaves) {
-        const int mm = (B.bin_m[B.col_bin[cs + col]] - m0) & 1023;
+        const int mm = (B.bin_m[B.col_bin[cs + col]] - m0) & (NS - 1);
         opos[mm] = (int16_t)col;
     }
     __syncthreads();
     // ring column of this lane's FFT outputs l + 64 J (J < jmax), two 16-bit columns a register
-    unsigned cpos[8];
+    unsigned cpos[(V + 1) / 2];
 #pragma unroll
-    for (int h = 0; h < 8; ++h) {
+    for (int h = 0; h < (V + 1) / 2; ++h) {
         const int J0 = 2 * h, J1 = 2 * h + 1;
         const unsigned c0 = J0 < jmax ? (unsigned)(uint16_t)opos[lane + 64 * J0] : (unsigned)(ncol1 - 1);
         const unsigned c1 = J1 < jmax ? (unsigned)(uint16_t)opos[lane + 64 * J1] : (unsigned)(ncol1 - 1);
@@ -1461,17 +1603,12 @@ __device__ __forceinline__ void spectra_wide_body(const BandDev &B, const float2
         kbc[u] = col < n_p ? B.bin_kb[binc[u]] : 0;
     }
     // pass twiddles and the class's input twiddles W_N^(q s), s = l + 64 r (N is a power of two)
-    const int st256 = N >> 8, st1024 = N >> 10;
-    float2 w2[15], w3[4][3], win[16];
-#pragma unroll
-    for (int r = 1; r < 16; ++r) w2[r - 1] = tw[(r * (lane & 15) * st256) & mask];
-#pragma unroll
-    for (int q = 0; q < 4; ++q)
-#pragma unroll
-        for (int r = 1; r < 4; ++r) w3[q][r - 1] = tw[(r * (lane + 64 * q) * st1024) & mask];
+    WaveTw<NS> wtw;
+    wtw.load(tw, N, mask, lane);
+    float2 win[V];
     const int qrot = (p + B.P * m0) & mask;
 #pragma unroll
-    for (int r = 0; r < 16; ++r) win[r] = tw[(int)(((unsigned)qrot * (unsigned)(lane + 64 * r)) & (unsigned)mask)];
+    for (int r = 0; r < V; ++r) win[r] = tw[(int)(((unsigned)qrot * (unsigned)(lane + 64 * r)) & (unsigned)mask)];
 
     const int K0 = c * k_chunk;
     const int K1 = min(B.n_seg, K0 + k_chunk);
@@ -1492,13 +1629,13 @@ __device__ __forceinline__ void spectra_wide_body(const BandDev &B, const float2
     // segment is loaded while the current one is transformed.  Buffer loads with the segment's
     // n_k samples as the buffer range read zero past it (no branches, no zero padding in memory).
     constexpr int NJ = (QM + kSpwWaves - 1) / kSpwWaves;
-    float2 nxt[NJ][16];
+    float2 nxt[NJ][V];
     auto load = [&](int e, int i) {
         const int X = wv + kSpwWaves * i;
         const float2 *ys = ybase + (size_t)X * nr + (size_t)ld_uniform(B.seg_any, e) * n_k;
         const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc((void *)ys, (short)0, n_k * 8, 0x00020000);
 #pragma unroll
-        for (int r = 0; r < 16; ++r)
+        for (int r = 0; r < V; ++r)
             nxt[i][r] = __builtin_bit_cast(float2, __builtin_amdgcn_raw_buffer_load_b64(rs, (lane + 64 * r) * 8, 0, 0));
     };
     if (lo < hi) {
@@ -1525,15 +1662,15 @@ __device__ __forceinline__ void spectra_wide_body(const BandDev &B, const float2
         for (int i = 0; i < NJ; ++i) {
             const int X = wv + kSpwWaves * i;
             if (X >= Q) continue;
-            float2 v[16];
+            float2 v[V];
 #pragma unroll
-            for (int r = 0; r < 16; ++r) v[r] = cmul<float>(nxt[i][r], win[r]);
+            for (int r = 0; r < V; ++r) v[r] = cmul<float>(nxt[i][r], win[r]);
             load(min(e + 1, hi - 1), i);  // unconditional (the last step reloads its own segment)
             if (ld_uniform(B.seg_work, X * B.n_seg + K) < 0) continue;  // no data of detector X in K
-            fft1024_wave(v, fx, w2, w3, lane);
+            fft_wave<NS>(v, fx, wtw, lane);
             float2 *row = ring + ((size_t)head * Q + X) * ncol1;
 #pragma unroll
-            for (int J = 0; J < 16; ++J)
+            for (int J = 0; J < V; ++J)
                 if (J < jmax) row[(cpos[J >> 1] >> (16 * (J & 1))) & 0xffffu] = v[J];
         }
         float wa[QM], wb[QM];
@@ -2306,7 +2443,7 @@ k_spectra_pairs_m(const BandDev *__restrict__ bands, const WorkItem *__restrict_
 // dispatcher hands workgroups to the 8 XCDs in turn, so block l runs on XCD l mod 8: the P class
 // workgroups of one (template, chunk) group are given indices with equal l mod 8, which puts
 // them on one XCD, where they read the group's resampled series through that XCD's L2.
-template <int U, int QM, bool ALLP>
+template <int NS, int U, int QM, bool ALLP>
 __global__ void __launch_bounds__(64 * kSpwWaves)
 k_spectra_wide_m(const BandDev *__restrict__ bands, const WorkItem *__restrict__ items, int n_items,
                  const float2 *__restrict__ y, double *__restrict__ part) {
@@ -2324,7 +2461,7 @@ k_spectra_wide_m(const BandDev *__restrict__ bands, const WorkItem *__restrict__
         g = (G >> 3) * 8 + (l - full) / P;
         p = (l - full) % P;
     }
-    spectra_wide_body<U, QM, ALLP>(B, y + it.y_off, part + it.part_off, it.k_chunk, it.n_chunks, g % it.n_chunks, p,
+    spectra_wide_body<NS, U, QM, ALLP>(B, y + it.y_off, part + it.part_off, it.k_chunk, it.n_chunks, g % it.n_chunks, p,
                                    g / it.n_chunks);
 }
 
@@ -2511,14 +2648,14 @@ hipError_t launch_zero(void *p, size_t bytes, hipStream_t stream) {
 
 size_t spectra_pairs_lds(const BandDev &B) { return spair_layout(B.Q, B.n_f, B.R, B.n_fft).total; }
 
-size_t spectra_wide_lds(const BandDev &B) { return spw_layout(B.Q, B.R, B.wide_ncol, B.wide_jmax).total; }
+size_t spectra_wide_lds(const BandDev &B) { return spw_layout(B.Q, B.R, B.wide_ncol, B.wide_jmax, B.n_s).total; }
 
 int spectra_wide_cols(const BandDev &B) { return B.wide_ncol <= 128 ? 1 : (B.wide_ncol <= 256 ? 2 : 4); }
 
 bool spectra_wide_ok(const BandDev &B, bool fp64, size_t limit) {
-    return !fp64 && B.n_s == 1024 && B.nfft_mask != 0 && B.bins_unique && B.Q >= 1 && B.Q <= 4 &&
-           B.wide_ncol <= 512 && B.wide_jmax >= 1 && B.wide_jmax <= 16 && B.cls_m0 != nullptr &&
-           spectra_wide_lds(B) <= limit;
+    return !fp64 && (B.n_s == 1024 || B.n_s == 512 || B.n_s == 256) && B.nfft_mask != 0 && B.bins_unique &&
+           B.Q >= 1 && B.Q <= 4 && B.wide_ncol <= 512 && B.wide_jmax >= 1 && B.wide_jmax <= B.n_s / 64 &&
+           B.cls_m0 != nullptr && spectra_wide_lds(B) <= limit;
 }
 
 int spectra_pairs_rounds(const BandDev &B) { return B.n_f <= 64 * 3 ? 3 : kSpairMaxRounds; }
@@ -2614,11 +2751,11 @@ hipError_t launch_spectra_pairs_m(const BandDev *bands, const WorkItem *items, i
     return hipGetLastError();
 }
 
-template <bool ALLP>
+template <int NS, bool ALLP>
 static void launch_spectra_wide_u(const BandDev *bands, const WorkItem *items, int n_items, int blocks, int cols,
                                   int qm, size_t lds, const void *y, double *part, hipStream_t stream) {
-#define CCR_WIDE(U_, QM_)                                                                                       \
-    hipLaunchKernelGGL((k_spectra_wide_m<U_, QM_, ALLP>), dim3(blocks), dim3(64 * kSpwWaves), lds, stream, bands, \
+#define CCR_WIDE(U_, QM_)                                                                                            \
+    hipLaunchKernelGGL((k_spectra_wide_m<NS, U_, QM_, ALLP>), dim3(blocks), dim3(64 * kSpwWaves), lds, stream, bands, \
                        items, n_items, (const float2 *)y, part)
     if (cols <= 1) {
         if (qm <= 2) CCR_WIDE(1, 2);
@@ -2633,11 +2770,20 @@ static void launch_spectra_wide_u(const BandDev *bands, const WorkItem *items, i
 #undef CCR_WIDE
 }
 
-hipError_t launch_spectra_wide_m(const BandDev *bands, const WorkItem *items, int n_items, int blocks, int cols,
-                                 int qm, bool allp, size_t lds, const void *y, double *part, hipStream_t stream) {
+hipError_t launch_spectra_wide_m(const BandDev *bands, const WorkItem *items, int n_items, int blocks, int ns,
+                                 int cols, int qm, bool allp, size_t lds, const void *y, double *part,
+                                 hipStream_t stream) {
     if (blocks == 0) return hipSuccess;
-    if (allp) launch_spectra_wide_u<true>(bands, items, n_items, blocks, cols, qm, lds, y, part, stream);
-    else launch_spectra_wide_u<false>(bands, items, n_items, blocks, cols, qm, lds, y, part, stream);
+#define CCR_WIDE_NS(NS_)                                                                                     \
+    do {                                                                                                     \
+        if (allp) launch_spectra_wide_u<NS_, true>(bands, items, n_items, blocks, cols, qm, lds, y, part, stream); \
+        else launch_spectra_wide_u<NS_, false>(bands, items, n_items, blocks, cols, qm, lds, y, part, stream);   \
+    } while (0)
+    if (ns == 1024) CCR_WIDE_NS(1024);
+    else if (ns == 512) CCR_WIDE_NS(512);
+    else if (ns == 256) CCR_WIDE_NS(256);
+    else return hipErrorInvalidValue;
+#undef CCR_WIDE_NS
     return hipGetLastError();
 }
 

@@ -301,8 +301,8 @@ def test_weighted_pair_sums(ccr, case):
     A.1-A.2) and per-sample antenna functions (Sec. III.B.3, eq. norm-a-eq: two spectra streams
     per segment), alone and combined, on 128-, 256- and 1024-point segments with gaps, against
     the oracle's stream form; FP64 and split, chunks of 5 segments with their halo, the fused
-    option set.  The split path runs the 1024-point spectra + pair-sum kernel for both weights
-    and all pairs with per-segment weights, the general kernels otherwise."""
+    option set.  The split path runs the spectra + pair-sum kernel of 256- to 1024-point segments
+    for both weights and all pairs with per-segment weights, the general kernels otherwise."""
     pairs, weight, per_sample, q, R, gaps, shape = WEIGHTED[case]
     ds = weighted_dataset(pairs, weight, per_sample, q, R, gaps, shape)
     o = oracle.Oracle(ds)
@@ -321,7 +321,8 @@ def test_weighted_pair_sums(ccr, case):
         ctx.set_option("template_batch", 1)
         r64b = ctx.compute_rho(bid, prec=ccr.PREC_FP64)
         r32b = ctx.compute_rho(bid, prec=ccr.PREC_SPLIT, out_fp64=False)
-    wide = shape == "1024" and not per_sample
+    ns = 1 << (info["n_k"] - 1).bit_length()
+    wide = ns in (256, 512, 1024) and not per_sample
     assert kt["spectra_pairs"][1] == 0, kt
     assert (kt["spectra_wide"][1] > 0) == wide and (kt["pairs"][1] > 0) != wide, kt
     e64, e32 = rho_err(r64, ref), rho_err(r32, ref)
@@ -347,6 +348,51 @@ def test_weighted_forms_reduce(ccr):
         err = np.max(np.abs(r_ps - r_seg)) / max(1.0, np.abs(r_seg).max())
         print(f"constant per-sample weights, weight {weight}: {err:.2e}")
         assert err < 1e-12
+
+
+WIDE_SMALLER = {
+    # (detectors, max lag, pair kinds, chunk length, T_short, f_band, weight): 512-point segments
+    # (N_K 257-512) and 256-point segments that the 256-point kernel does not take (more than 512
+    # bins, or the Gamma^circ weight)
+    "n512_q2_lag2_both": (2, 2, 3, 7, 1000.0, 0.06, 0),
+    "n512_q3_lag1_cross": (3, 1, 1, 256, 1000.0, 0.06, 0),
+    "n512_q1_lag3_same": (1, 3, 2, 5, 1000.0, 0.06, 0),
+    "n512_q4_lag1_circ": (4, 1, 3, 6, 1000.0, 0.06, 1),
+    "n256_q2_lag2_many_bins": (2, 2, 3, 7, 400.0, 0.2, 0),
+    "n256_q3_lag1_circ": (3, 1, 3, 5, 400.0, 0.06, 1),
+}
+
+
+@pytest.mark.parametrize("case", sorted(WIDE_SMALLER))
+def test_spectra_wide_512_256(ccr, case):
+    """The spectra + pair-sum kernel on 512-point segments (radix 8, 8, 8 in one wavefront) and on
+    256-point segments (radix 4, 4, 4, 4) where the 256-point kernel does not apply: 1-4
+    detectors, lags 1-3, 30 % gaps, chunks with their halo, both weights, against the oracle
+    (Sec. III.B.1 pairs, eq. final-formatted-rho, Sec. II.B Gamma^circ)."""
+    q, R, pairs, kc, ts, fb, weight = WIDE_SMALLER[case]
+    cfg = small_config(q=q, n_seg=26, t_short=ts, f_min=400.0, f_band=fb, max_lag=R, pairs=pairs,
+                       a_p_max=2.0, gap_fraction=0.3,
+                       templates=dict(a_p=(1.0, 2.0, 2), t_asc=(-200.0, 200.0, 2), period=[68023.70]),
+                       injections=[dict(f0=400.0 + 0.45 * fb, a_p=1.3, t_asc_off=0.0, period=68023.7, h0=0.3,
+                                        cosi=0.7, psi=0.4, phi0=2.0)])
+    cfg["band"]["weight"] = weight
+    ds = synth.make_dataset(cfg, sigma_wander=0.2)
+    ref = oracle.Oracle(ds).rho(ds.templates)
+    with ccr.Context(ds.sky, device=0) as ctx:
+        ctx.set_option("timing", 1)
+        ctx.set_option("k_chunk", kc)
+        bid = ctx.load(ds)
+        info = ctx.band_info(bid)
+        ns = 1 << (info["n_k"] - 1).bit_length()
+        assert ns == (512 if case.startswith("n512") else 256), info
+        r64 = ctx.compute_rho(bid, prec=ccr.PREC_FP64)
+        ctx.kernel_times(reset=True)
+        r32 = ctx.compute_rho(bid, prec=ccr.PREC_SPLIT, out_fp64=False)
+        kt = ctx.kernel_times(reset=True)
+    assert kt["spectra_wide"][1] > 0 and kt["spectra_pairs"][1] == 0, kt
+    e64, e32 = rho_err(r64, ref), rho_err(r32, ref)
+    print(f"{ns}-point {case}: n_f {info['n_f']} fp64 {e64:.2e} split {e32:.2e} max|rho| {np.abs(ref).max():.2f}")
+    assert e64 < TOL64 and e32 < TOL32
 
 
 def test_tiny_workload_full(ccr):
