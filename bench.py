@@ -231,6 +231,11 @@ def main():
                     help="templates per step of the weighting / pair-set / orbit / front-end lines")
     ap.add_argument("--graph", type=int, default=1)
     ap.add_argument("--autotune", type=int, default=1)
+    ap.add_argument("--k-chunk", type=int, default=0,
+                    help="segments per chunk of the spectra kernels (0: the library's choice, or the autotuner's); "
+                         "for --profile-steps, the value the autotuner picked in the timed run")
+    ap.add_argument("--template-batch", type=int, default=0,
+                    help="templates per launch round (0: the library's choice, or the autotuner's)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU. Templates (and bands) are independent, so N GPUs would each "
@@ -274,6 +279,10 @@ def main():
     def step():
         ctx.compute_rho(bid, prec=PREC_SPLIT, out_fp64=False, outputs=[out.data_ptr()], stream=stream.cuda_stream)
 
+    if args.k_chunk:
+        ctx.set_option("k_chunk", args.k_chunk)
+    if args.template_batch:
+        ctx.set_option("template_batch", args.template_batch)
     if args.profile_steps:
         for i in range(args.profile_steps):
             step()
