@@ -84,7 +84,7 @@ struct Band {
     int Q = 0;
     // device tables
     DevBuf d_x, d_mask, d_anchor, d_earth, d_win64, d_win32, d_cheb_x, d_mono, d_tw64, d_tw32, d_bin_m, d_bin_p,
-        d_bin_kb, d_bin_pos, d_segw, d_active, d_work, d_seg_work, d_tmpl, d_lagph, d_seg_any, d_col_bin, d_bin_col, d_zero256,
+        d_bin_kb, d_bin_pos, d_segw, d_segwf, d_active, d_work, d_seg_work, d_tmpl, d_lagph, d_seg_any, d_col_bin, d_bin_col, d_zero256,
         d_class_start, d_farrow, d_farrow_A, d_cls_m0, d_pw;
     bool per_sample = false;  // every detector has per-sample antenna functions (two spectra streams)
     int wide_jmax = 0, wide_ncol = 0;  // 1024-point spectra + pair-sum kernel (see BandDev)
@@ -737,6 +737,16 @@ ccr_status prepare(ccr_ctx *c, Band &B) {
     if ((st = upload(c, B.d_bin_pos, bpos))) return st;
     B.bins_unique = unique;
     if ((st = upload(c, B.d_segw, segw))) return st;
+    {
+        // the split path's pair weights: hat a scale and hat b scale rounded to FP32, zero for
+        // a segment that takes part in no pair (no spectrum)
+        std::vector<float2> segwf(segw.size());
+        for (size_t e = 0; e < segw.size(); ++e)
+            segwf[e] = seg_work[e] < 0 ? make_float2(0.f, 0.f)
+                                       : make_float2((float)(segw[e].ahat * segw[e].scale),
+                                                     (float)(segw[e].bhat * segw[e].scale));
+        if ((st = upload(c, B.d_segwf, segwf))) return st;
+    }
     // per-sample stream weights (a_r, b_r) / (sigma_XK^2 sqrt(N_K)): hat a_r times the spectra's
     // 1 / (sigma sqrt N_K)
     B.per_sample = per_sample;
@@ -1004,6 +1014,7 @@ BandDev band_dev(const Band &B) {
     d.bin_pos = B.d_bin_pos.as<int>();
     d.bins_unique = B.bins_unique;
     d.segw = B.d_segw.as<SegWeight>();
+    d.segwf = B.d_segwf.as<float2>();
     d.active = B.d_active.as<uint8_t>();
     d.work = B.d_work.as<int>();
     d.seg_work = B.d_seg_work.as<int>();
@@ -1158,7 +1169,7 @@ struct Variant {
     bool wallp = false;  // wide: every ordered pair (stream-sum partials)
     int wns = 0;         // wide: segment FFT length (256, 512 or 1024)
     int DT = 0, window = 0, n_s = 0, nr = 0, n_cheb = kCheb;
-    int wcols = 0, wqm = 0;  // wide: bins of a class per lane, detector bound (2 or 4)
+    int wcols = 0, wqm = 0;  // wide: bins of a class per lane, detector count
     bool operator==(const Variant &o) const {
         return sp == o.sp && reg16 == o.reg16 && z4 == o.z4 && ss == o.ss && far == o.far && wide == o.wide &&
                DT == o.DT && window == o.window && n_s == o.n_s && nr == o.nr && n_cheb == o.n_cheb &&
@@ -1218,7 +1229,7 @@ Variant variant_of(const BandDev &bd, bool fp64, bool short_series, bool farrow)
     if (v.wide) {
         v.wns = bd.n_s;
         v.wcols = spectra_wide_cols(bd);
-        v.wqm = bd.Q <= 2 ? 2 : 4;
+        v.wqm = bd.Q;
     } else if (v.sp) {
         v.nr = spectra_pairs_rounds(bd);
         v.z4 = bd.n_k <= 192;

@@ -81,6 +81,7 @@ struct BandDev {
     const int *bin_pos;       // [n_fft] output bin i of FFT index kbar mod n_fft, -1 if none
     int bins_unique;          // 1 when every output bin has its own FFT index
     const SegWeight *segw;    // [Q][n_seg]
+    const float2 *segwf;      // [Q][n_seg] (hat a scale, hat b scale) rounded to FP32
     const uint8_t *active;    // [Q][n_seg] 1 when the segment takes part in a pair
     const int *work;          // [n_work] det * n_seg + K of active segments
     const int *seg_work;      // [Q][n_seg] position of (det, K) in `work`, -1 if inactive
@@ -199,9 +200,9 @@ hipError_t launch_farrow_table(const float2 *x, int64_t n, int Q, int D, const d
 bool spectra_wide_ok(const BandDev &B, bool fp64, size_t limit);
 size_t spectra_wide_lds(const BandDev &B);
 int spectra_wide_cols(const BandDev &B);
-// cols: spectra_wide_cols of the round's bands; qm: their largest detector count.
+// cols: spectra_wide_cols of the round's bands; q: their detector count (1-4, the same for all).
 hipError_t launch_spectra_wide_m(const BandDev *bands, const WorkItem *items, int n_items, int blocks, int ns,
-                                 int cols, int qm, bool allp, size_t lds, const void *y, double *part,
+                                 int cols, int q, bool allp, size_t lds, const void *y, double *part,
                                  hipStream_t stream);
 // z4: N_K <= 192, so the last 4 of the 16 input rows of each 256-point FFT are zero padding.
 hipError_t launch_spectra_pairs_m(const BandDev *bands, const WorkItem *items, int n_items, int blocks, int rounds,

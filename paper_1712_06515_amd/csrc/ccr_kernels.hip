@@ -1314,6 +1314,10 @@ template <typename T> __device__ __forceinline__ T ld_uniform(const T *p, int i)
     i = __builtin_amdgcn_readfirstlane(i);
     return ((const __attribute__((address_space(4))) T *)p)[i];
 }
+__device__ __forceinline__ float2 ld_uniform_f2(const float2 *p, int i) {
+    const unsigned long long v = ld_uniform(reinterpret_cast<const unsigned long long *>(p), i);
+    return make_float2(__uint_as_float((unsigned)v), __uint_as_float((unsigned)(v >> 32)));
+}
 
 // 1024-point forward FFT held by one wavefront: on entry lane l holds x[l + 64 r] in v[r]
 // (r < 16), on return X[l + 64 J] in v[J].  Three self-sorting (Stockham) passes of radix 16,
@@ -1500,6 +1504,43 @@ __device__ __forceinline__ void fft_wave<256>(float2 *v, float2 *fx, const WaveT
     wave_sync();
 }
 
+// Pair term of segment K for one bin of the spectra + pair-sum kernel: sum over detectors X of
+// the weighted products of F_XK with its partners, the window sums G_Y (spectra of the last R
+// segments, weighted by hat a and hat b: Ga, Gb) of the detectors the pair set joins to X
+// (CROSS: Y != X; SAME: Y = X) and, across detectors, the same-time partners Y > X (their
+// weighted spectra w_Y F_YK, summed from the last detector down).  Gamma^ave:
+// hat a_X Re[conj(F_X) H^a] + hat b_X Re[conj(F_X) H^b]; Gamma^circ (CIRC):
+// hat b_X Im[conj(F_X) H^a] - hat a_X Im[conj(F_X) H^b].  Every unordered pair enters once.
+template <int Q, int U, bool CROSS, bool SAME, bool CIRC>
+__device__ __forceinline__ float wide_pair_term(const float2 (&f)[Q], const float (&wa)[Q], const float (&wb)[Q],
+                                                const float2 (&Ga)[Q][U], const float2 (&Gb)[Q][U], int u) {
+    float st = 0.f;
+    float2 ta = make_float2(0.f, 0.f), tb = make_float2(0.f, 0.f);  // sum over Y > X of w_Y F_Y
+#pragma unroll
+    for (int X = Q - 1; X >= 0; --X) {
+        float2 ha = ta, hb = tb;
+#pragma unroll
+        for (int Y = 0; Y < Q; ++Y) {
+            if ((Y != X && CROSS) || (Y == X && SAME)) {
+                ha.x += Ga[Y][u].x; ha.y += Ga[Y][u].y;
+                hb.x += Gb[Y][u].x; hb.y += Gb[Y][u].y;
+            }
+        }
+        if constexpr (CIRC) {
+            st = fmaf(wb[X], f[X].x * ha.y - f[X].y * ha.x, st);
+            st = fmaf(-wa[X], f[X].x * hb.y - f[X].y * hb.x, st);
+        } else {
+            st = fmaf(wa[X], f[X].x * ha.x + f[X].y * ha.y, st);
+            st = fmaf(wb[X], f[X].x * hb.x + f[X].y * hb.y, st);
+        }
+        if constexpr (CROSS) {
+            ta.x = fmaf(wa[X], f[X].x, ta.x); ta.y = fmaf(wa[X], f[X].y, ta.y);
+            tb.x = fmaf(wb[X], f[X].x, tb.x); tb.y = fmaf(wb[X], f[X].y, tb.y);
+        }
+    }
+    return st;
+}
+
 // Workgroup of the spectra + pair-sum kernel for 256- to 1024-point segments: kSpwWaves
 // wavefronts share one spectrum ring; wavefront w transforms the detectors X = w, w + kSpwWaves,
 // ... and sums the pairs of the bins (ring columns) w 64 + l + 128 u.
@@ -1508,7 +1549,7 @@ constexpr int kSpwWaves = 2;
 // LDS of the spectra + pair-sum kernel for ns-point segments (bytes).
 struct SpwLayout {
     int slots, ncol1;
-    size_t off_fx, off_ring, off_pos, off_meta, off_slotk, total;
+    size_t off_fx, off_ring, off_pos, total;
 };
 
 __host__ __device__ inline SpwLayout spw_layout(int Q, int R, int ncol, int jmax, int ns) {
@@ -1522,11 +1563,6 @@ __host__ __device__ inline SpwLayout spw_layout(int Q, int R, int ncol, int jmax
     o += (size_t)L.slots * Q * L.ncol1 * sizeof(float2);
     L.off_pos = o;
     o += (size_t)jmax * 64 * sizeof(int16_t);
-    o = (o + 15) & ~(size_t)15;
-    L.off_meta = o;
-    o += (size_t)L.slots * Q * sizeof(float2);
-    L.off_slotk = o;
-    o += (size_t)L.slots * sizeof(int);
     L.total = (o + 15) & ~(size_t)15;
     return L;
 }
@@ -1554,13 +1590,13 @@ __host__ __device__ inline SpwLayout spw_layout(int Q, int R, int ncol, int jmax
 //   from the same window sums.  ALLP (every ordered pair, autos included): no windows; the
 //   partials are the chunk's stream sums G^a = sum hat a_XK F_XK and G^b (4 doubles a bin), which
 //   the finishing kernel combines.
-// U: bins of a class per lane (class size <= 128 U); QM: detector bound of the register arrays.
-template <int NS, int U, int QM, bool ALLP>
+// U: bins of a class per lane (class size <= 128 U); Q: the band's detector count.
+template <int NS, int U, int Q, bool ALLP>
 __device__ __forceinline__ void spectra_wide_body(const BandDev &B, const float2 *__restrict__ y, double *part,
                                                   int k_chunk, int n_chunks, int c, int p, int tb) {
     extern __shared__ __align__(16) unsigned char smem[];
     constexpr int V = NS / 64;  // FFT values a lane
-    const int Q = B.Q, n_k = B.n_k, R = B.R, N = B.n_fft, mask = B.nfft_mask;
+    const int n_k = B.n_k, R = B.R, N = B.n_fft, mask = B.nfft_mask;
     const SpwLayout Ly = spw_layout(Q, R, B.wide_ncol, B.wide_jmax, NS);
     // the wavefront index, uniform within the wavefront (readfirstlane makes that known to the
     // compiler, so that per-wavefront addresses and buffer descriptors stay in scalar registers)
@@ -1568,8 +1604,6 @@ __device__ __forceinline__ void spectra_wide_body(const BandDev &B, const float2
     float2 *fx = reinterpret_cast<float2 *>(smem + Ly.off_fx) + wv * (NS + 64);
     float2 *ring = reinterpret_cast<float2 *>(smem + Ly.off_ring);
     int16_t *opos = reinterpret_cast<int16_t *>(smem + Ly.off_pos);
-    float2 *meta = reinterpret_cast<float2 *>(smem + Ly.off_meta);
-    int *slotk = reinterpret_cast<int *>(smem + Ly.off_slotk);
     const int slots = Ly.slots, ncol1 = Ly.ncol1, jmax = B.wide_jmax;
     const bool cross = (B.pairs & 1) != 0, same = (B.pairs & 2) != 0, circ = B.weight != 0;
     const float2 *tw = B.tw32;
@@ -1628,7 +1662,7 @@ __device__ __forceinline__ void spectra_wide_body(const BandDev &B, const float2
     // this wavefront's detectors X = wv + kSpwWaves i (i < NJ); the input of a detector's next
     // segment is loaded while the current one is transformed.  Buffer loads with the segment's
     // n_k samples as the buffer range read zero past it (no branches, no zero padding in memory).
-    constexpr int NJ = (QM + kSpwWaves - 1) / kSpwWaves;
+    constexpr int NJ = (Q + kSpwWaves - 1) / kSpwWaves;
     float2 nxt[NJ][V];
     auto load = [&](int e, int i) {
         const int X = wv + kSpwWaves * i;
@@ -1644,7 +1678,7 @@ __device__ __forceinline__ void spectra_wide_body(const BandDev &B, const float2
             if (wv + kSpwWaves * i < Q) load(lo, i);
     }
 
-    float2 Ga[QM][U], Gb[QM][U];
+    float2 Ga[Q][U], Gb[Q][U];
     double acc[U];
     double2 sa[ALLP ? U : 1], sb[ALLP ? U : 1];  // all pairs: the chunk's stream sums
 #pragma unroll
@@ -1652,9 +1686,10 @@ __device__ __forceinline__ void spectra_wide_body(const BandDev &B, const float2
         acc[u] = 0.0;
         if constexpr (ALLP) sa[u] = sb[u] = make_double2(0.0, 0.0);
 #pragma unroll
-        for (int X = 0; X < QM; ++X) Ga[X][u] = Gb[X][u] = make_float2(0.f, 0.f);
+        for (int X = 0; X < Q; ++X) Ga[X][u] = Gb[X][u] = make_float2(0.f, 0.f);
     }
-    int head = 0, tail = 0, count = 0;
+    int head = 0, tail = 0, tail_e = lo;
+    const int mode = (cross ? 1 : 0) | (same ? 2 : 0) | (circ ? 4 : 0);
     for (int e = lo; e < hi; ++e) {
         const int K = ld_uniform(B.seg_any, e);
         // this wavefront's transforms of step e
@@ -1673,27 +1708,13 @@ __device__ __forceinline__ void spectra_wide_body(const BandDev &B, const float2
             for (int J = 0; J < V; ++J)
                 if (J < jmax) row[(cpos[J >> 1] >> (16 * (J & 1))) & 0xffffu] = v[J];
         }
-        float wa[QM], wb[QM];
+        // pair weights of this step's spectra, zero where detector X has no data in segment K
+        float wa[Q], wb[Q];
 #pragma unroll
-        for (int X = 0; X < QM; ++X) {
-            wa[X] = wb[X] = 0.f;
-            if (X >= Q) continue;
-            const int ew = X * B.n_seg + K;
-            if (ld_uniform(B.seg_work, ew) < 0) continue;  // no data of detector X in segment K
-            static_assert(sizeof(SegWeight) == 3 * sizeof(double), "SegWeight is (ahat, bhat, scale)");
-            const double *swp = reinterpret_cast<const double *>(B.segw);
-            const double sc = ld_uniform(swp, 3 * ew + 2);
-            // products formed in vector registers: readfirstlane keeps them uniform (scalar)
-            wa[X] = __builtin_bit_cast(float, __builtin_amdgcn_readfirstlane(
-                                                  __builtin_bit_cast(int, (float)(ld_uniform(swp, 3 * ew) * sc))));
-            wb[X] = __builtin_bit_cast(float, __builtin_amdgcn_readfirstlane(
-                                                  __builtin_bit_cast(int, (float)(ld_uniform(swp, 3 * ew + 1) * sc))));
-        }
-        if (threadIdx.x == 0) {
-            slotk[head] = K;
-#pragma unroll
-            for (int X = 0; X < QM; ++X)
-                if (X < Q) meta[head * Q + X] = make_float2(wa[X], wb[X]);
+        for (int X = 0; X < Q; ++X) {
+            const float2 w2 = ld_uniform_f2(B.segwf, X * B.n_seg + K);
+            wa[X] = w2.x;
+            wb[X] = w2.y;
         }
         __syncthreads();
         // Phi_in and the pairs whose later member is segment K
@@ -1704,24 +1725,22 @@ __device__ __forceinline__ void spectra_wide_body(const BandDev &B, const float2
         for (int u = 0; u < U; ++u) {
             const int col = wv * 64 + lane + 128 * u;
             if (U > 1 && 128 * u >= n_p) break;  // uniform: no lane of the workgroup has a bin here
-            const int cc = col < n_p ? col : ncol1 - 1;
+            float2 *slot = ring + (size_t)head * Q * ncol1 + (col < n_p ? col : ncol1 - 1);
+            float2 f[Q];
+#pragma unroll
+            for (int X = 0; X < Q; ++X) f[X] = slot[X * ncol1];
             const float ph = -(float)(((unsigned)kbc[u] * rB) & (unsigned)mask) * invN;  // revolutions
             const float cph = __builtin_amdgcn_cosf(ph), sph = __builtin_amdgcn_sinf(ph);
-            float2 f[QM];
 #pragma unroll
-            for (int X = 0; X < QM; ++X) {
-                if (X >= Q) continue;
-                float2 *slotp = ring + ((size_t)head * Q + X) * ncol1 + cc;
-                const float2 g = *slotp;
-                f[X] = make_float2(g.x * cph - g.y * sph, g.x * sph + g.y * cph);
-                if (col < n_p) *slotp = f[X];
+            for (int X = 0; X < Q; ++X) {
+                f[X] = make_float2(f[X].x * cph - f[X].y * sph, f[X].x * sph + f[X].y * cph);
+                if (col < n_p) slot[X * ncol1] = f[X];
             }
             if constexpr (ALLP) {
                 // this step's share of G^a and G^b: FP32 over the detectors, FP64 over steps
                 float2 ta = make_float2(0.f, 0.f), tb2 = make_float2(0.f, 0.f);
 #pragma unroll
-                for (int X = 0; X < QM; ++X) {
-                    if (X >= Q) continue;
+                for (int X = 0; X < Q; ++X) {
                     ta.x = fmaf(wa[X], f[X].x, ta.x); ta.y = fmaf(wa[X], f[X].y, ta.y);
                     tb2.x = fmaf(wb[X], f[X].x, tb2.x); tb2.y = fmaf(wb[X], f[X].y, tb2.y);
                 }
@@ -1730,72 +1749,55 @@ __device__ __forceinline__ void spectra_wide_body(const BandDev &B, const float2
                 continue;
             }
             if (count_it) {
-                float st = 0.f;
-#pragma unroll
-                for (int X = 0; X < QM; ++X) {
-                    if (X >= Q || (wa[X] == 0.f && wb[X] == 0.f)) continue;
-                    float2 ha = make_float2(0.f, 0.f), hb = make_float2(0.f, 0.f);
-#pragma unroll
-                    for (int Y = 0; Y < QM; ++Y) {
-                        if (Y >= Q) continue;
-                        if ((Y != X) ? cross : same) {
-                            ha.x += Ga[Y][u].x; ha.y += Ga[Y][u].y;
-                            hb.x += Gb[Y][u].x; hb.y += Gb[Y][u].y;
-                        }
-                        if (cross && Y > X) {
-                            ha.x = fmaf(wa[Y], f[Y].x, ha.x); ha.y = fmaf(wa[Y], f[Y].y, ha.y);
-                            hb.x = fmaf(wb[Y], f[Y].x, hb.x); hb.y = fmaf(wb[Y], f[Y].y, hb.y);
-                        }
-                    }
-                    if (circ) {
-                        // hat b_K Im[conj(F_K) G^a] - hat a_K Im[conj(F_K) G^b]
-                        st = fmaf(wb[X], f[X].x * ha.y - f[X].y * ha.x, st);
-                        st = fmaf(-wa[X], f[X].x * hb.y - f[X].y * hb.x, st);
-                    } else {
-                        st = fmaf(wa[X], f[X].x * ha.x + f[X].y * ha.y, st);
-                        st = fmaf(wb[X], f[X].x * hb.x + f[X].y * hb.y, st);
-                    }
+                float st;
+                switch (mode) {  // uniform
+                    case 1: st = wide_pair_term<Q, U, true, false, false>(f, wa, wb, Ga, Gb, u); break;
+                    case 2: st = wide_pair_term<Q, U, false, true, false>(f, wa, wb, Ga, Gb, u); break;
+                    case 3: st = wide_pair_term<Q, U, true, true, false>(f, wa, wb, Ga, Gb, u); break;
+                    case 5: st = wide_pair_term<Q, U, true, false, true>(f, wa, wb, Ga, Gb, u); break;
+                    case 6: st = wide_pair_term<Q, U, false, true, true>(f, wa, wb, Ga, Gb, u); break;
+                    case 7: st = wide_pair_term<Q, U, true, true, true>(f, wa, wb, Ga, Gb, u); break;
+                    default: st = 0.f;
                 }
                 acc[u] += (double)st;
             }
 #pragma unroll
-            for (int X = 0; X < QM; ++X) {
-                if (X >= Q) continue;
+            for (int X = 0; X < Q; ++X) {
                 Ga[X][u].x = fmaf(wa[X], f[X].x, Ga[X][u].x); Ga[X][u].y = fmaf(wa[X], f[X].y, Ga[X][u].y);
                 Gb[X][u].x = fmaf(wb[X], f[X].x, Gb[X][u].x); Gb[X][u].y = fmaf(wb[X], f[X].y, Gb[X][u].y);
             }
         }
         head = head + 1 == slots ? 0 : head + 1;
-        ++count;
-        // spectra whose segment is more than R behind the next step's leave the window sums
-        if (ALLP) {
-            tail = head;
-            count = 0;
-        } else if (e + 1 < hi) {
+        // spectra whose segment is more than R behind the next step's leave the window sums: the
+        // ring holds the steps tail_e .. e; their segments and weights come from the (uniform)
+        // segment list and weight table
+        if (!ALLP && e + 1 < hi) {
             const int Kn = ld_uniform(B.seg_any, e + 1);
-            while (count > 0) {
-                const int Kt = __builtin_amdgcn_readfirstlane(slotk[tail]);
+            while (tail_e <= e) {
+                const int Kt = ld_uniform(B.seg_any, tail_e);
                 if (Kt >= Kn - R) break;
+                float wta[Q], wtb[Q];
 #pragma unroll
-                for (int X = 0; X < QM; ++X) {
-                    if (X >= Q) continue;
-                    const float2 wt0 = meta[tail * Q + X];
-                    const float2 wt = make_float2(
-                        __builtin_bit_cast(float, __builtin_amdgcn_readfirstlane(__builtin_bit_cast(int, wt0.x))),
-                        __builtin_bit_cast(float, __builtin_amdgcn_readfirstlane(__builtin_bit_cast(int, wt0.y))));
-                    if (wt.x == 0.f && wt.y == 0.f) continue;
-                    const float2 *rowt = ring + ((size_t)tail * Q + X) * ncol1;
+                for (int X = 0; X < Q; ++X) {
+                    const float2 w2 = ld_uniform_f2(B.segwf, X * B.n_seg + Kt);
+                    wta[X] = w2.x;
+                    wtb[X] = w2.y;
+                }
+                const float2 *rowt = ring + (size_t)tail * Q * ncol1;
 #pragma unroll
-                    for (int u = 0; u < U; ++u) {
-                        if (U > 1 && 128 * u >= n_p) break;
-                        const int col = wv * 64 + lane + 128 * u;
-                        const float2 g = rowt[col < n_p ? col : ncol1 - 1];
-                        Ga[X][u].x = fmaf(-wt.x, g.x, Ga[X][u].x); Ga[X][u].y = fmaf(-wt.x, g.y, Ga[X][u].y);
-                        Gb[X][u].x = fmaf(-wt.y, g.x, Gb[X][u].x); Gb[X][u].y = fmaf(-wt.y, g.y, Gb[X][u].y);
+                for (int u = 0; u < U; ++u) {
+                    if (U > 1 && 128 * u >= n_p) break;
+                    const int col = wv * 64 + lane + 128 * u;
+                    const float2 *gp = rowt + (col < n_p ? col : ncol1 - 1);
+#pragma unroll
+                    for (int X = 0; X < Q; ++X) {
+                        const float2 g = gp[X * ncol1];
+                        Ga[X][u].x = fmaf(-wta[X], g.x, Ga[X][u].x); Ga[X][u].y = fmaf(-wta[X], g.y, Ga[X][u].y);
+                        Gb[X][u].x = fmaf(-wtb[X], g.x, Gb[X][u].x); Gb[X][u].y = fmaf(-wtb[X], g.y, Gb[X][u].y);
                     }
                 }
                 tail = tail + 1 == slots ? 0 : tail + 1;
-                --count;
+                ++tail_e;
             }
         }
         __syncthreads();
@@ -2422,11 +2424,17 @@ k_resample_far_m(const BandDev *__restrict__ bands, const WorkItem *__restrict__
                  const double *__restrict__ coef, float2 *__restrict__ y) {
     const WorkItem &it = items[find_item(items, n_items, kStResample, blockIdx.x)];
     const BandDev B = global_view(bands[it.band], bands);
-    // a segment's template tiles are consecutive workgroups (its table slice stays in L2)
+    // A segment's template tiles are consecutive virtual indices v, and consecutive v run on
+    // one XCD: the dispatcher hands workgroups to the 8 XCDs in turn (block b on XCD b mod 8),
+    // so the item's blocks l with equal l mod 8 (one XCD) take the contiguous range of v
+    // starting at (l mod 8) full / 8, in order; the table slice of a segment is then fetched
+    // into that XCD's L2 once for all its tiles.  Blocks past the last multiple of 8 keep v = l.
     const int l = blockIdx.x - it.first[kStResample];
     const int tiles = (it.n_tmpl + kFarTemplates - 1) / kFarTemplates;
-    const int t0 = (l % tiles) * kFarTemplates;
-    resample_far_body<NC>(B, coef + it.coef_off, y + it.y_off, l / tiles, t0, min(it.n_tmpl, t0 + kFarTemplates));
+    const int full = (B.n_work * tiles) & ~7;  // the item's blocks: n_work segment entries x tiles
+    const int v = l < full ? (l & 7) * (full >> 3) + (l >> 3) : l;
+    const int t0 = (v % tiles) * kFarTemplates;
+    resample_far_body<NC>(B, coef + it.coef_off, y + it.y_off, v / tiles, t0, min(it.n_tmpl, t0 + kFarTemplates));
 }
 
 template <int NR, bool Z4>
@@ -2443,7 +2451,7 @@ k_spectra_pairs_m(const BandDev *__restrict__ bands, const WorkItem *__restrict_
 // dispatcher hands workgroups to the 8 XCDs in turn, so block l runs on XCD l mod 8: the P class
 // workgroups of one (template, chunk) group are given indices with equal l mod 8, which puts
 // them on one XCD, where they read the group's resampled series through that XCD's L2.
-template <int NS, int U, int QM, bool ALLP>
+template <int NS, int U, int Q, bool ALLP>
 __global__ void __launch_bounds__(64 * kSpwWaves)
 k_spectra_wide_m(const BandDev *__restrict__ bands, const WorkItem *__restrict__ items, int n_items,
                  const float2 *__restrict__ y, double *__restrict__ part) {
@@ -2461,7 +2469,7 @@ k_spectra_wide_m(const BandDev *__restrict__ bands, const WorkItem *__restrict__
         g = (G >> 3) * 8 + (l - full) / P;
         p = (l - full) % P;
     }
-    spectra_wide_body<NS, U, QM, ALLP>(B, y + it.y_off, part + it.part_off, it.k_chunk, it.n_chunks, g % it.n_chunks, p,
+    spectra_wide_body<NS, U, Q, ALLP>(B, y + it.y_off, part + it.part_off, it.k_chunk, it.n_chunks, g % it.n_chunks, p,
                                    g / it.n_chunks);
 }
 
@@ -2753,31 +2761,32 @@ hipError_t launch_spectra_pairs_m(const BandDev *bands, const WorkItem *items, i
 
 template <int NS, bool ALLP>
 static void launch_spectra_wide_u(const BandDev *bands, const WorkItem *items, int n_items, int blocks, int cols,
-                                  int qm, size_t lds, const void *y, double *part, hipStream_t stream) {
-#define CCR_WIDE(U_, QM_)                                                                                            \
-    hipLaunchKernelGGL((k_spectra_wide_m<NS, U_, QM_, ALLP>), dim3(blocks), dim3(64 * kSpwWaves), lds, stream, bands, \
+                                  int q, size_t lds, const void *y, double *part, hipStream_t stream) {
+#define CCR_WIDE(U_, Q_)                                                                                            \
+    hipLaunchKernelGGL((k_spectra_wide_m<NS, U_, Q_, ALLP>), dim3(blocks), dim3(64 * kSpwWaves), lds, stream, bands, \
                        items, n_items, (const float2 *)y, part)
-    if (cols <= 1) {
-        if (qm <= 2) CCR_WIDE(1, 2);
-        else CCR_WIDE(1, 4);
-    } else if (cols <= 2) {
-        if (qm <= 2) CCR_WIDE(2, 2);
-        else CCR_WIDE(2, 4);
-    } else {
-        if (qm <= 2) CCR_WIDE(4, 2);
-        else CCR_WIDE(4, 4);
-    }
+#define CCR_WIDE_Q(U_)          \
+    do {                        \
+        if (q == 1) CCR_WIDE(U_, 1); \
+        else if (q == 2) CCR_WIDE(U_, 2); \
+        else if (q == 3) CCR_WIDE(U_, 3); \
+        else CCR_WIDE(U_, 4);   \
+    } while (0)
+    if (cols <= 1) CCR_WIDE_Q(1);
+    else if (cols <= 2) CCR_WIDE_Q(2);
+    else CCR_WIDE_Q(4);
+#undef CCR_WIDE_Q
 #undef CCR_WIDE
 }
 
 hipError_t launch_spectra_wide_m(const BandDev *bands, const WorkItem *items, int n_items, int blocks, int ns,
-                                 int cols, int qm, bool allp, size_t lds, const void *y, double *part,
+                                 int cols, int q, bool allp, size_t lds, const void *y, double *part,
                                  hipStream_t stream) {
     if (blocks == 0) return hipSuccess;
 #define CCR_WIDE_NS(NS_)                                                                                     \
     do {                                                                                                     \
-        if (allp) launch_spectra_wide_u<NS_, true>(bands, items, n_items, blocks, cols, qm, lds, y, part, stream); \
-        else launch_spectra_wide_u<NS_, false>(bands, items, n_items, blocks, cols, qm, lds, y, part, stream);   \
+        if (allp) launch_spectra_wide_u<NS_, true>(bands, items, n_items, blocks, cols, q, lds, y, part, stream); \
+        else launch_spectra_wide_u<NS_, false>(bands, items, n_items, blocks, cols, q, lds, y, part, stream);   \
     } while (0)
     if (ns == 1024) CCR_WIDE_NS(1024);
     else if (ns == 512) CCR_WIDE_NS(512);
