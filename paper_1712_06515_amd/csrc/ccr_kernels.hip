@@ -1516,15 +1516,40 @@ __device__ __forceinline__ float wide_pair_term(const float2 (&f)[Q], const floa
                                                 const float2 (&Ga)[Q][U], const float2 (&Gb)[Q][U], int u) {
     float st = 0.f;
     float2 ta = make_float2(0.f, 0.f), tb = make_float2(0.f, 0.f);  // sum over Y > X of w_Y F_Y
+    // both pair kinds: every detector's window sum joins every X (summed once)
+    float2 sa = Ga[0][u], sb = Gb[0][u];
+    if constexpr (CROSS && SAME) {
+#pragma unroll
+        for (int Y = 1; Y < Q; ++Y) {
+            sa.x += Ga[Y][u].x; sa.y += Ga[Y][u].y;
+            sb.x += Gb[Y][u].x; sb.y += Gb[Y][u].y;
+        }
+    }
 #pragma unroll
     for (int X = Q - 1; X >= 0; --X) {
-        float2 ha = ta, hb = tb;
+        float2 ha = make_float2(0.f, 0.f), hb = make_float2(0.f, 0.f);
+        if constexpr (CROSS && SAME) {
+            ha = sa;
+            hb = sb;
+        } else {
+            bool first = true;
 #pragma unroll
-        for (int Y = 0; Y < Q; ++Y) {
-            if ((Y != X && CROSS) || (Y == X && SAME)) {
-                ha.x += Ga[Y][u].x; ha.y += Ga[Y][u].y;
-                hb.x += Gb[Y][u].x; hb.y += Gb[Y][u].y;
+            for (int Y = 0; Y < Q; ++Y) {
+                if ((Y != X && CROSS) || (Y == X && SAME)) {
+                    if (first) {
+                        ha = Ga[Y][u];
+                        hb = Gb[Y][u];
+                    } else {
+                        ha.x += Ga[Y][u].x; ha.y += Ga[Y][u].y;
+                        hb.x += Gb[Y][u].x; hb.y += Gb[Y][u].y;
+                    }
+                    first = false;
+                }
             }
+        }
+        if (CROSS && X < Q - 1) {
+            ha.x += ta.x; ha.y += ta.y;
+            hb.x += tb.x; hb.y += tb.y;
         }
         if constexpr (CIRC) {
             st = fmaf(wb[X], f[X].x * ha.y - f[X].y * ha.x, st);
