@@ -300,7 +300,8 @@ def main():
     log(f"split path {ms_per_step:.2f} ms/step ({value:.3e} rho/s)")
     rho = out.cpu().numpy()
     err = golden_error(ds, rho, n_t) if args.workload == "large" else None
-    tuned = {"k_chunk": ctx.get_option("tuned_k_chunk"), "template_batch": ctx.get_option("tuned_template_batch")}
+    tuned = {"k_chunk": ctx.get_option("tuned_k_chunk"), "template_batch": ctx.get_option("tuned_template_batch"),
+             "spectra_kernel": ctx.get_option("tuned_spectra_kernel")}
 
     # per-kernel device time (HIP events on the launch stream), separate eager pass with the
     # same launches (graph replays are not timed per kernel)
@@ -487,7 +488,10 @@ def extra_lines(args):
         sec = time_steps(lambda: ctx.compute_rho(bid, prec=PREC_SPLIT, out_fp64=False, outputs=[o.data_ptr()]),
                          10, 2)
         out["band"] = {"workload": WORKLOADS["band"], "value": info["n_templates"] * info["n_f"] / sec,
-                       "unit": "rho-evals/s", "ms_per_step": 1e3 * sec}
+                       "unit": "rho-evals/s", "ms_per_step": 1e3 * sec,
+                       "tuned": {"k_chunk": ctx.get_option("tuned_k_chunk"),
+                                 "template_batch": ctx.get_option("tuned_template_batch"),
+                                 "spectra_kernel": ctx.get_option("tuned_spectra_kernel")}}
     log(f"extra band: {out['band']['ms_per_step']:.1f} ms/step ({time.perf_counter() - t0:.0f} s)")
     t0 = time.perf_counter()
     dss = synth.make_multiband(synth.config("multiband"))
@@ -503,7 +507,9 @@ def extra_lines(args):
         n_eval = sum(i["n_templates"] * i["n_f"] for i in infos)
         out["multiband"] = {"workload": WORKLOADS["multiband"], "value": n_eval / sec, "unit": "rho-evals/s",
                             "ms_per_step": 1e3 * sec, "bands": len(ids), "rho_evals_per_step": n_eval,
-                            "tuned_k_chunk": ctx.get_option("tuned_k_chunk")}
+                            "tuned": {"k_chunk": ctx.get_option("tuned_k_chunk"),
+                                      "template_batch": ctx.get_option("tuned_template_batch"),
+                                      "spectra_kernel": ctx.get_option("tuned_spectra_kernel")}}
     log(f"extra multiband: {out['multiband']['ms_per_step']:.1f} ms/step")
     return out
 

@@ -173,9 +173,16 @@ const char *ccr_last_error(const ccr_ctx *ctx);
  *                     outputs) as a HIP graph on first use and replay it afterwards; a change
  *                     of data, templates, weights, workspace or launch options re-captures;
  *                     applies to device outputs only;
+ *   "spectra_kernel"  1: run the 256- to 1024-point spectra + pair-sum kernel on every band
+ *                     it takes, also where the 256-point one applies; 0 (default): the
+ *                     256-point kernel first;
  *   "autotune"        1: on the first call for a given band list and precision, time the
- *                     first launch round for k_chunk = 32 ... 1024 and keep the fastest
- *                     (an explicit "k_chunk" disables tuning);
+ *                     first launch round of each candidate launch shape and keep the fastest
+ *                     per template: the spectra kernel (where a band can take either) and
+ *                     k_chunk = 32 ... 1024 on a round of at most 64 templates a band, then
+ *                     the templates per launch round (the workspace budget's batch, its half
+ *                     and quarter) where timing those rounds stays below about 12 s (an
+ *                     explicit "k_chunk" disables tuning);
  *   "farrow"          1 (default): split-precision resampling in Farrow form where the band
  *                     has the table (see ccr_band_info.farrow_degree), 0: the direct
  *                     2D + 1-tap form.  FP64 always uses the direct form;
@@ -187,8 +194,9 @@ const char *ccr_last_error(const ccr_ctx *ctx);
  * Returns CCR_EUNSUP for an unknown name. */
 ccr_status ccr_set_option(ccr_ctx *ctx, const char *name, int64_t value);
 
-/* Read an option set with ccr_set_option, or "tuned_k_chunk" / "tuned_template_batch": the
- * launch shape the autotuner chose last (0 before any tuning), or "resample_templates": the
+/* Read an option set with ccr_set_option, or "tuned_k_chunk" / "tuned_template_batch" /
+ * "tuned_spectra_kernel": the launch shape the autotuner chose last (0, or -1 for the kernel,
+ * before any tuning), or "resample_templates": the
  * templates one resampling workgroup handles from one staged input window (a constant of the
  * build), "farrow_templates" / "farrow_degree": the same for the Farrow-form kernel and its
  * polynomial degree.  CCR_EUNSUP for an unknown name. */

@@ -111,6 +111,7 @@ struct ccr_ctx {
     int64_t opt_workspace_mb = 0;   // 0: automatic (see auto_budget)
     size_t auto_budget = 0;         // automatic workspace budget, fixed at the first compute call
     int64_t opt_k_chunk = 0;
+    int64_t opt_spectra_kernel = 0;  // 1: the 256- to 1024-point spectra + pair-sum kernel wherever it applies
     int64_t opt_fused = 0;
     int64_t opt_timing = 0;
     DevBuf ws_arena;                // workspace of the batched path: one arena, laid out per launch round
@@ -131,10 +132,11 @@ struct ccr_ctx {
     struct Tuned {
         std::vector<int> band_ids;
         int prec;
-        int64_t k_chunk, template_batch;
+        int64_t k_chunk, template_batch, round_templates;
+        int spectra;
     };
     std::vector<Tuned> tuned;
-    int64_t last_tuned_k_chunk = 0, last_tuned_template_batch = 0;
+    int64_t last_tuned_k_chunk = 0, last_tuned_template_batch = 0, last_tuned_spectra = -1;
     struct Timed {
         int kind;
         hipEvent_t a, b;
@@ -1189,6 +1191,7 @@ inline size_t arena_bytes_of(size_t coef, size_t y, size_t F, size_t part) {
 
 struct Round {
     int i0 = 0, n = 0;  // items [i0, i0 + n) of the call's item table
+    int64_t n_tmpl = 0;  // templates of those items
     Variant v;
     size_t lds = 0;     // dynamic LDS of the spectra + pair-sum kernel
     int64_t blocks[kStages] = {0, 0, 0, 0, 0};
@@ -1208,9 +1211,11 @@ struct CallPlan {
 // Launch shape parameters (0 = default): templates per item and segments per pair-sum chunk.
 struct BatchParams {
     int64_t template_batch = 0, k_chunk = 0;
+    int64_t round_templates = 0;  // at most this many templates in one launch round (0: no limit)
+    int spectra = 0;  // 1: the wide spectra + pair-sum kernel wherever it applies, 0: the 256-point one first
 };
 
-Variant variant_of(const BandDev &bd, bool fp64, bool short_series, bool farrow) {
+Variant variant_of(const BandDev &bd, bool fp64, bool short_series, bool farrow, bool prefer_wide) {
     Variant v;
     v.ss = short_series;
     v.far = farrow && !fp64 && bd.farrow != nullptr;
@@ -1220,8 +1225,9 @@ Variant variant_of(const BandDev &bd, bool fp64, bool short_series, bool farrow)
     // per-segment weights, the 1024-point one either weight and every ordered pair as well; the
     // other forms (per-sample antenna functions: two spectra streams) run on the general path
     const bool plain = bd.weight == CCR_WEIGHT_AVE && !bd.allp && bd.pw == nullptr;
-    v.sp = plain && spectra_pairs_ok(bd, fp64, kMaxLds);
-    v.wide = !v.sp && bd.pw == nullptr && spectra_wide_ok(bd, fp64, kMaxLds);
+    const bool wide_ok = bd.pw == nullptr && spectra_wide_ok(bd, fp64, kMaxLds);
+    v.sp = plain && spectra_pairs_ok(bd, fp64, kMaxLds) && !(prefer_wide && wide_ok);
+    v.wide = !v.sp && wide_ok;
     v.wallp = v.wide && bd.allp;
     v.DT = bd.D == 8 ? 8 : 0;
     v.window = bd.window;
@@ -1303,7 +1309,7 @@ ccr_status build_plan(ccr_ctx *c, bool fp64, int n_bands, const int *band_ids, v
         BandDev bd = band_dev(B);
         bd.far_stage = (int)c->opt_farrow_stage;
         cp.bands.push_back(bd);
-        const Variant v = variant_of(bd, fp64, B.short_series, c->opt_farrow != 0);
+        const Variant v = variant_of(bd, fp64, B.short_series, c->opt_farrow != 0, bp.spectra != 0);
         const int res_t = v.far ? kFarTemplates : kResTemplates;  // templates per resampler workgroup
         if (std::find(variants.begin(), variants.end(), v) == variants.end()) variants.push_back(v);
         int64_t kc = bp.k_chunk > 0 ? bp.k_chunk : std::min<int64_t>(pl.n_seg, 256);
@@ -1371,6 +1377,7 @@ ccr_status build_plan(ccr_ctx *c, bool fp64, int n_bands, const int *band_ids, v
             bool full = arena_bytes_of(r.coef_bytes + q.coef, r.y_bytes + q.y, r.F_bytes + q.F, r.part_bytes + q.part) > budget;
             for (int st = 0; st < kStages; ++st) full = full || r.blocks[st] + q.blk[st] > stage_max_blocks(v, st);
             if (c->opt_items_per_launch > 0 && r.n >= c->opt_items_per_launch) full = true;
+            if (bp.round_templates > 0 && r.n_tmpl + q.it.n_tmpl > bp.round_templates) full = true;
             if (r.n > 0 && full) {
                 close();
                 r = Round();
@@ -1391,6 +1398,7 @@ ccr_status build_plan(ccr_ctx *c, bool fp64, int n_bands, const int *band_ids, v
             r.part_bytes += q.part;
             r.coef_bytes += q.coef;
             r.lds = std::max(r.lds, q.lds);
+            r.n_tmpl += q.it.n_tmpl;
             r.n++;
             cp.items.push_back(it);
         }
@@ -1517,67 +1525,134 @@ ccr_status upload_tables(ccr_ctx *c, const CallPlan &cp, hipStream_t s, size_t *
 }
 
 
-// Launch shapes for a call: the tuned ones when autotuning is on (tuning on first use: the
-// first round of the call is timed for each candidate k_chunk and the fastest is kept).
+// Launch shapes for a call: the tuned ones when autotuning is on.  Tuning on first use for a
+// band list and precision times the first launch round of the call for each candidate and
+// keeps the fastest per template:
+//   1. the spectra kernel (where a band can take both the 256-point and the wide spectra +
+//      pair-sum kernel) and k_chunk = 32 ... 1024, with a tuning batch of at most 64 templates
+//      per band;
+//   2. the template batch: the workspace budget's (the largest) and its halves and quarters,
+//      when a round of that size is cheap enough to time (the estimate from step 1 for all
+//      candidates below about 12 s).
 ccr_status choose_params(ccr_ctx *c, ccr_precision prec, int n_bands, const int *band_ids, void *const *rho_out,
                          int out_on_device, int out_fp64, hipStream_t s, BatchParams &bp) {
     bp = BatchParams();
     bp.k_chunk = c->opt_k_chunk;
     bp.template_batch = c->opt_template_batch;
+    bp.spectra = (int)c->opt_spectra_kernel;
     if (!c->opt_autotune || c->opt_k_chunk > 0) return CCR_OK;
     const std::vector<int> ids(band_ids, band_ids + n_bands);
     for (const auto &t : c->tuned)
         if (t.band_ids == ids && t.prec == (int)prec) {
             bp.k_chunk = t.k_chunk;
             bp.template_batch = t.template_batch;
+            bp.round_templates = t.round_templates;
+            bp.spectra = t.spectra;
             return CCR_OK;
         }
     int64_t max_seg = 1;
-    for (int bi = 0; bi < n_bands; ++bi) max_seg = std::max<int64_t>(max_seg, get_band(c, band_ids[bi])->plan.n_seg);
+    bool both = false;  // some band can take either spectra kernel
     const bool fp64 = prec == CCR_PREC_FP64;
+    for (int bi = 0; bi < n_bands; ++bi) {
+        const Band &B = *get_band(c, band_ids[bi]);
+        max_seg = std::max<int64_t>(max_seg, B.plan.n_seg);
+        const BandDev bd = band_dev(B);
+        const Variant v0 = variant_of(bd, fp64, B.short_series, c->opt_farrow != 0, false);
+        const Variant v1 = variant_of(bd, fp64, B.short_series, c->opt_farrow != 0, true);
+        both = both || !(v0 == v1);
+    }
     hipEvent_t e0 = nullptr, e1 = nullptr;
     HIP_OK(c, hipEventCreate(&e0));
     HIP_OK(c, hipEventCreate(&e1));
-    float best = -1.0f;
-    int64_t best_kc = 0;
-    ccr_status st = CCR_OK;
-    for (int64_t kc = 32; kc <= 1024; kc *= 2) {
-        if (kc > 2 * max_seg && kc > 32) break;
-        BatchParams cand = bp;
-        cand.k_chunk = kc;
+    // per-template time of the first round of a candidate (one untimed pass, then a timed one);
+    // n_round: templates of that round
+    auto trial = [&](const BatchParams &cand, float &per, int64_t &n_round) -> ccr_status {
         CallPlan cp;
         size_t items_off = 0;
-        if ((st = build_plan(c, fp64, n_bands, band_ids, rho_out, out_on_device, out_fp64, cand, cp))) break;
-        if ((st = ensure_workspace(c, cp))) break;
-        if ((st = upload_tables(c, cp, s, &items_off))) break;
-        // one untimed pass of the round, then the timed one
-        for (int rep = 0; rep < 2 && !st; ++rep) {
-            if (rep == 1 && hipEventRecord(e0, s) != hipSuccess) st = fail(c, CCR_EDEVICE, "event record failed");
-            if (!st) st = run_rounds(c, cp, 0, std::min<size_t>(1, cp.rounds.size()), fp64, c->d_tables.p, items_off, s, false,
-                                     c->ws_arena.p);
+        ccr_status st;
+        if ((st = build_plan(c, fp64, n_bands, band_ids, rho_out, out_on_device, out_fp64, cand, cp))) return st;
+        if ((st = ensure_workspace(c, cp))) return st;
+        if ((st = upload_tables(c, cp, s, &items_off))) return st;
+        for (int rep = 0; rep < 2; ++rep) {
+            if (rep == 1 && hipEventRecord(e0, s) != hipSuccess) return fail(c, CCR_EDEVICE, "event record failed");
+            if ((st = run_rounds(c, cp, 0, std::min<size_t>(1, cp.rounds.size()), fp64, c->d_tables.p, items_off, s,
+                                 false, c->ws_arena.p)))
+                return st;
         }
-        if (st) break;
         HIP_OK(c, hipEventRecord(e1, s));
         HIP_OK(c, hipEventSynchronize(e1));
         float ms = 0.0f;
         HIP_OK(c, hipEventElapsedTime(&ms, e0, e1));
-        // normalise by the templates the first round covers
-        int64_t nt = 0;
+        n_round = 0;
         if (!cp.rounds.empty())
-            for (int i = 0; i < cp.rounds[0].n; ++i) nt += cp.items[cp.rounds[0].i0 + i].n_tmpl;
-        const float per = ms / (float)std::max<int64_t>(nt, 1);
-        if (best < 0.0f || per < best) {
-            best = per;
-            best_kc = kc;
-        }
+            for (int i = 0; i < cp.rounds[0].n; ++i) n_round += cp.items[cp.rounds[0].i0 + i].n_tmpl;
+        per = ms / (float)std::max<int64_t>(n_round, 1);
+        return CCR_OK;
+    };
+    ccr_status st = CCR_OK;
+    // the workspace budget's template batch: templates of the first item of an untuned plan
+    int64_t t_auto = 1;
+    {
+        CallPlan cp;
+        if ((st = build_plan(c, fp64, n_bands, band_ids, rho_out, out_on_device, out_fp64, bp, cp))) goto done;
+        if (!cp.items.empty()) t_auto = cp.items[0].n_tmpl;
     }
+    {
+        const int64_t t_tune = bp.template_batch > 0 ? bp.template_batch : std::min<int64_t>(t_auto, 64);
+        float best = -1.0f, best_round_ms = 0.0f;
+        BatchParams bestp = bp;
+        for (int sk = both ? 0 : bp.spectra; sk <= (both ? 1 : bp.spectra); ++sk)
+            for (int64_t kc = 32; kc <= 1024; kc *= 2) {
+                if (kc > 2 * max_seg && kc > 32) break;
+                BatchParams cand = bp;
+                cand.k_chunk = kc;
+                cand.spectra = sk;
+                cand.template_batch = t_tune;
+                cand.round_templates = t_tune;
+                float per = 0.0f;
+                int64_t nr = 0;
+                if ((st = trial(cand, per, nr))) goto done;
+                if (best < 0.0f || per < best) {
+                    best = per;
+                    bestp = cand;
+                    best_round_ms = per * (float)nr;
+                }
+            }
+        if (bp.template_batch <= 0 && t_auto > t_tune) {
+            // larger batches, if timing them stays cheap (the round time scales with the batch)
+            const float est_ms = best_round_ms * (float)t_auto / (float)t_tune;
+            if (est_ms * 2.0f * 1.75f < 12000.0f) {
+                for (int64_t tb = t_auto; tb > t_tune; tb /= 2) {
+                    BatchParams cand = bestp;
+                    cand.template_batch = tb;
+                    cand.round_templates = tb < t_auto ? tb : 0;
+                    float per = 0.0f;
+                    int64_t nr = 0;
+                    if ((st = trial(cand, per, nr))) goto done;
+                    if (per < best) {
+                        best = per;
+                        bestp = cand;
+                    }
+                    if (tb <= t_auto / 4) break;
+                }
+            } else {
+                bestp.template_batch = t_auto;  // too costly to time: the largest batch
+                bestp.round_templates = 0;
+            }
+        } else if (bp.template_batch <= 0) {
+            bestp.template_batch = t_auto;
+            bestp.round_templates = 0;
+        }
+        bp = bestp;
+    }
+done:
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
     if (st) return st;
-    bp.k_chunk = best_kc;
-    c->tuned.push_back({ids, (int)prec, bp.k_chunk, bp.template_batch});
+    c->tuned.push_back({ids, (int)prec, bp.k_chunk, bp.template_batch, bp.round_templates, bp.spectra});
     c->last_tuned_k_chunk = bp.k_chunk;
     c->last_tuned_template_batch = bp.template_batch;
+    c->last_tuned_spectra = bp.spectra;
     return CCR_OK;
 }
 
@@ -1736,6 +1811,7 @@ ccr_status ccr_set_option(ccr_ctx *c, const char *name, int64_t value) {
     if (k == "template_batch") c->opt_template_batch = value;
     else if (k == "workspace_mb") c->opt_workspace_mb = value == 0 ? 0 : std::max<int64_t>(value, 64);
     else if (k == "k_chunk") c->opt_k_chunk = value;
+    else if (k == "spectra_kernel") c->opt_spectra_kernel = value ? 1 : 0;
     else if (k == "fused") c->opt_fused = value;
     else if (k == "timing") c->opt_timing = value;
     else if (k == "graph") c->opt_graph = value;
@@ -1745,7 +1821,7 @@ ccr_status ccr_set_option(ccr_ctx *c, const char *name, int64_t value) {
     else if (k == "farrow_stage") c->opt_farrow_stage = value ? 1 : 0;
     else return fail(c, CCR_EUNSUP, "unknown option '%s'", name);
     if (k == "template_batch" || k == "workspace_mb" || k == "k_chunk" || k == "items_per_launch" || k == "farrow" ||
-        k == "farrow_stage" || k == "fused")
+        k == "farrow_stage" || k == "fused" || k == "spectra_kernel")
         c->gen++;
     return CCR_OK;
 }
@@ -1764,6 +1840,8 @@ ccr_status ccr_get_option(ccr_ctx *c, const char *name, int64_t *value) {
     else if (k == "items_per_launch") *value = c->opt_items_per_launch;
     else if (k == "tuned_k_chunk") *value = c->last_tuned_k_chunk;
     else if (k == "tuned_template_batch") *value = c->last_tuned_template_batch;
+    else if (k == "tuned_spectra_kernel") *value = c->last_tuned_spectra;
+    else if (k == "spectra_kernel") *value = c->opt_spectra_kernel;
     else if (k == "resample_templates") *value = kResTemplates;
     else if (k == "farrow") *value = c->opt_farrow;
     else if (k == "farrow_stage") *value = c->opt_farrow_stage;
@@ -2078,6 +2156,7 @@ ccr_status ccr_compute_rho_noalloc(ccr_ctx *c, ccr_precision prec, int n_bands, 
     BatchParams bp;
     bp.k_chunk = c->opt_k_chunk;
     bp.template_batch = c->opt_template_batch;
+    bp.spectra = (int)c->opt_spectra_kernel;
     CallPlan cp;
     ccr_status st = build_plan(c, fp64, n_bands, band_ids, rho_out, 1, out_fp64, bp, cp, budget);
     if (st) return st;

@@ -731,10 +731,50 @@ def test_autotune_picks_chunk(ccr):
         tuned = ctx.compute_rho(bid, prec=ccr.PREC_FP64)
         kc = ctx.get_option("tuned_k_chunk")
         assert kc in (32, 64, 128)
+        assert ctx.get_option("tuned_template_batch") > 0
+        assert ctx.get_option("tuned_spectra_kernel") in (0, 1)
         assert np.max(np.abs(tuned - base)) < 1e-12 * max(1.0, np.abs(base).max())
         again = ctx.compute_rho(bid, prec=ccr.PREC_FP64)
         assert np.array_equal(again, tuned)
         assert ctx.get_option("tuned_k_chunk") == kc
+
+
+def test_spectra_kernel_choice_and_tuning(ccr):
+    """A band of 256-point segments that both spectra + pair-sum kernels take (Gamma^ave, lagged
+    pairs of both kinds, 20 % gaps): option spectra_kernel selects the 256-point kernel (0) or
+    the 256- to 1024-point one (1), both match the oracle (Sec. III.B.1 pairs, eq.
+    final-formatted-rho), and the autotuner, timing both kernels, the chunk lengths and the
+    template batches, keeps one shape and gives the same rho to FP32 rounding."""
+    cfg = small_config(q=2, n_seg=40, t_short=400.0, f_min=400.0, f_band=0.06, max_lag=2, pairs=3,
+                       a_p_max=2.0, gap_fraction=0.2,
+                       templates=dict(a_p=(1.0, 2.0, 3), t_asc=(-200.0, 200.0, 3), period=[68023.70]),
+                       injections=[dict(f0=400.03, a_p=1.5, t_asc_off=0.0, period=68023.7, h0=0.3,
+                                        cosi=0.7, psi=0.4, phi0=2.0)])
+    ds = synth.make_dataset(cfg, sigma_wander=0.2)
+    ref = oracle.Oracle(ds).rho(ds.templates)
+    out = {}
+    with ccr.Context(ds.sky, device=0) as ctx:
+        ctx.set_option("timing", 1)
+        bid = ctx.load(ds)
+        info = ctx.band_info(bid)
+        assert 128 < info["n_k"] <= 256, info
+        for sk in (0, 1):
+            ctx.set_option("spectra_kernel", sk)
+            ctx.kernel_times(reset=True)
+            out[sk] = ctx.compute_rho(bid, prec=ccr.PREC_SPLIT, out_fp64=False)
+            kt = ctx.kernel_times(reset=True)
+            assert (kt["spectra_pairs"][1] > 0) == (sk == 0) and (kt["spectra_wide"][1] > 0) == (sk == 1), kt
+        ctx.set_option("spectra_kernel", 0)
+        ctx.set_option("autotune", 1)
+        tuned = ctx.compute_rho(bid, prec=ccr.PREC_SPLIT, out_fp64=False)
+        sk = ctx.get_option("tuned_spectra_kernel")
+        tb = ctx.get_option("tuned_template_batch")
+        kc = ctx.get_option("tuned_k_chunk")
+    e0, e1, et = rho_err(out[0], ref), rho_err(out[1], ref), rho_err(tuned, ref)
+    print(f"256-point kernel {e0:.2e}, wide kernel {e1:.2e}, tuned (kernel {sk}, k_chunk {kc}, batch {tb}) {et:.2e}")
+    assert e0 < TOL32 and e1 < TOL32 and et < TOL32
+    assert sk in (0, 1) and tb > 0 and kc >= 32
+    assert rho_err(tuned, out[sk]) < 1e-5
 
 
 # ------------------------------------------------------- eccentric orbits
