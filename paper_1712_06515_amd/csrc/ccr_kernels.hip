@@ -773,39 +773,52 @@ __device__ __forceinline__ void resample_far_body(const BandDev &B, const double
             m_b[p] = __builtin_amdgcn_ballot_w64(in && mk_[s]);
         }
         __syncthreads();
-        for (int i = 0; i < kFarPerWave; ++i) {
-            const int tb = tw0 + i;
-            if (tb >= t1) break;
-            float2 *yo = y + ((size_t)tb * B.Q + det) * nr + r0;
-            const double *cf = coef + ((size_t)tb * B.n_work + w) * kCheb;
-            double cl[NC];
+        // STAGED (uniform per chunk): j* lies in the staged range (j* is nondecreasing over the
+        // chunk and the range spans its first and last samples), so every lane reads LDS at a
+        // clamped index; lanes outside the range, if a wave has any (a uniform test), take the
+        // global-memory form instead.  Otherwise every sample reads the table in global memory.
+        auto walk = [&](auto staged_c) {
+            constexpr bool STAGED = decltype(staged_c)::value;
+            for (int i = 0; i < kFarPerWave; ++i) {
+                const int tb = tw0 + i;
+                if (tb >= t1) break;
+                float2 *yo = y + ((size_t)tb * B.Q + det) * nr + r0;
+                const double *cf = coef + ((size_t)tb * B.n_work + w) * kCheb;
+                double cl[NC];
 #pragma unroll
-            for (int k = 0; k < NC; ++k) cl[k] = cf[k];
-            cl[0] = uniform_f64(cl[0] - an.D_a);  // once per template, kept in scalar registers
+                for (int k = 0; k < NC; ++k) cl[k] = cf[k];
+                cl[0] = uniform_f64(cl[0] - an.D_a);  // once per template, kept in scalar registers
 #pragma unroll
-            for (int p = 0; p < kPasses; ++p) {
-                if (c0 + 64 * p >= c1) break;
-                const unsigned so = (unsigned)(c0 + 64 * p + lane);  // sample index (32-bit offset from yo)
-                // samples in gaps: zero (their own execution mask)
-                if (__builtin_amdgcn_inverse_ballot_w64(in_b[p] & ~m_b[p])) yo[so] = make_float2(0.f, 0.f);
-                if (__builtin_amdgcn_inverse_ballot_w64(m_b[p])) {
-                    int jr;
-                    float dc, psi;
-                    sample_time_far<NC>(cl, xs[p], B.inv_dt, B.f_het, psi_b, jr, dc, psi);
-                    jr += sj[p];  // j* - r0 - jlo
-                    float2 a;
-                    if (staged && (unsigned)jr < (unsigned)span) {
-                        a = farrow_eval_lds(sf + __umul24(jr, kES), dc);  // 0 <= jr < kFarCap
-                    } else {
-                        const int64_t jj = r0 + jlo + jr + B.D;
-                        a = (jj >= 0 && jj < B.far_len) ? farrow_eval_global(tab + jj, B.far_len, dc)
-                                                         : make_float2(0.f, 0.f);
+                for (int p = 0; p < kPasses; ++p) {
+                    if (c0 + 64 * p >= c1) break;
+                    const unsigned so = (unsigned)(c0 + 64 * p + lane);  // sample index (32-bit offset from yo)
+                    // samples in gaps: zero (their own execution mask)
+                    if (__builtin_amdgcn_inverse_ballot_w64(in_b[p] & ~m_b[p])) yo[so] = make_float2(0.f, 0.f);
+                    if (__builtin_amdgcn_inverse_ballot_w64(m_b[p])) {
+                        int jr;
+                        float dc, psi;
+                        sample_time_far<NC>(cl, xs[p], B.inv_dt, B.f_het, psi_b, jr, dc, psi);
+                        jr += sj[p];  // j* - r0 - jlo
+                        float2 a;
+                        bool far = true;
+                        if constexpr (STAGED) {
+                            const bool in_range = (unsigned)jr < (unsigned)span;
+                            a = farrow_eval_lds(sf + __umul24(min((unsigned)jr, (unsigned)span - 1u), kES), dc);
+                            far = __builtin_amdgcn_ballot_w64(!in_range) != 0 && !in_range;
+                        }
+                        if (far) {
+                            const int64_t jj = r0 + jlo + jr + B.D;
+                            a = (jj >= 0 && jj < B.far_len) ? farrow_eval_global(tab + jj, B.far_len, dc)
+                                                             : make_float2(0.f, 0.f);
+                        }
+                        const float c = __builtin_amdgcn_cosf(psi), sn = __builtin_amdgcn_sinf(psi);
+                        yo[so] = make_float2(c * a.x - sn * a.y, sn * a.x + c * a.y);
                     }
-                    const float c = __builtin_amdgcn_cosf(psi), sn = __builtin_amdgcn_sinf(psi);
-                    yo[so] = make_float2(c * a.x - sn * a.y, sn * a.x + c * a.y);
                 }
             }
-        }
+        };
+        if (staged) walk(std::integral_constant<bool, true>());
+        else walk(std::integral_constant<bool, false>());
         __syncthreads();  // the next chunk restages sf
     }
 }
