@@ -113,8 +113,7 @@ def roofline(name, avg_ms, tb, info, workload, streams=1):
     `streams` spectra per segment (2 with per-sample antenna functions)."""
     import numpy as np
     n_active = info["n_active"]
-    ns = 1 << (int(info["n_k"]) - 1).bit_length()
-    P = info["n_fft"] // ns
+    ns, P = int(info["n_s"]), int(info["P"])
     if name == "resample" and info.get("farrow_used"):
         # Farrow form: one complex64 sample written per resampled sample, plus the band's
         # table (kFarDeg + 1 complex64 planes per input sample and detector) read once
@@ -219,7 +218,9 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--workload", default="large", choices=["large", "band", "tiny"])
+    ap.add_argument("--workload", default="large", choices=["large", "band", "tiny", "multiband"],
+                    help="multiband: the 64-band batching workload, with --profile-steps only (its timed line "
+                         "is part of the default run)")
     ap.add_argument("--templates", type=int, default=1002,
                     help="templates per step (first N of the grid; 0: all)")
     ap.add_argument("--fp64-templates", type=int, default=32, help="templates timed on the plain FP64 path")
@@ -235,7 +236,11 @@ def main():
                     help="segments per chunk of the spectra kernels (0: the library's choice, or the autotuner's); "
                          "for --profile-steps, the value the autotuner picked in the timed run")
     ap.add_argument("--template-batch", type=int, default=0,
-                    help="templates per launch round (0: the library's choice, or the autotuner's)")
+                    help="templates per work item (0: the library's choice, or the autotuner's)")
+    ap.add_argument("--round-templates", type=int, default=0,
+                    help="templates per launch round at most (0: as many as the workspace holds)")
+    ap.add_argument("--spectra-kernel", type=int, default=0,
+                    help="1: the 256-1024-point spectra + pair-sum kernel wherever it applies")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU. Templates (and bands) are independent, so N GPUs would each "
@@ -258,6 +263,26 @@ def main():
     import synth
     from paper_1712_06515_amd import Context, PREC_FP64, PREC_SPLIT
 
+    if args.workload == "multiband":
+        if not args.profile_steps:
+            print("--workload multiband runs with --profile-steps only", file=sys.stderr)
+            sys.exit(2)
+        dss = synth.make_multiband(synth.config("multiband"))
+        ctx = Context(dss[0].sky, device=0)
+        ids = [ctx.load(d) for d in dss]
+        infos = [ctx.band_info(b) for b in ids]
+        outs = [torch.empty((i["n_templates"], i["n_f"]), dtype=torch.float32, device="cuda") for i in infos]
+        for opt in ("k_chunk", "template_batch", "round_templates", "spectra_kernel"):
+            v = getattr(args, opt)
+            if v:
+                ctx.set_option(opt, v)
+        log(f"multiband data: {len(ids)} bands")
+        for i in range(args.profile_steps):
+            ctx.compute_rho(ids, prec=PREC_SPLIT, out_fp64=False, outputs=[x.data_ptr() for x in outs])
+            torch.cuda.synchronize()
+            log(f"profile step {i} done")
+        return
+
     t_gen = time.perf_counter()
     cfg = synth.config(args.workload)
     ds = synth.make_dataset(cfg)
@@ -279,10 +304,9 @@ def main():
     def step():
         ctx.compute_rho(bid, prec=PREC_SPLIT, out_fp64=False, outputs=[out.data_ptr()], stream=stream.cuda_stream)
 
-    if args.k_chunk:
-        ctx.set_option("k_chunk", args.k_chunk)
-    if args.template_batch:
-        ctx.set_option("template_batch", args.template_batch)
+    for opt in ("k_chunk", "template_batch", "round_templates", "spectra_kernel"):
+        if getattr(args, opt):
+            ctx.set_option(opt, getattr(args, opt))
     if args.profile_steps:
         for i in range(args.profile_steps):
             step()
@@ -301,6 +325,7 @@ def main():
     rho = out.cpu().numpy()
     err = golden_error(ds, rho, n_t) if args.workload == "large" else None
     tuned = {"k_chunk": ctx.get_option("tuned_k_chunk"), "template_batch": ctx.get_option("tuned_template_batch"),
+             "round_templates": ctx.get_option("tuned_round_templates"),
              "spectra_kernel": ctx.get_option("tuned_spectra_kernel")}
 
     # per-kernel device time (HIP events on the launch stream), separate eager pass with the
@@ -491,6 +516,7 @@ def extra_lines(args):
                        "unit": "rho-evals/s", "ms_per_step": 1e3 * sec,
                        "tuned": {"k_chunk": ctx.get_option("tuned_k_chunk"),
                                  "template_batch": ctx.get_option("tuned_template_batch"),
+                                 "round_templates": ctx.get_option("tuned_round_templates"),
                                  "spectra_kernel": ctx.get_option("tuned_spectra_kernel")}}
     log(f"extra band: {out['band']['ms_per_step']:.1f} ms/step ({time.perf_counter() - t0:.0f} s)")
     t0 = time.perf_counter()
@@ -509,6 +535,7 @@ def extra_lines(args):
                             "ms_per_step": 1e3 * sec, "bands": len(ids), "rho_evals_per_step": n_eval,
                             "tuned": {"k_chunk": ctx.get_option("tuned_k_chunk"),
                                       "template_batch": ctx.get_option("tuned_template_batch"),
+                                      "round_templates": ctx.get_option("tuned_round_templates"),
                                       "spectra_kernel": ctx.get_option("tuned_spectra_kernel")}}
     log(f"extra multiband: {out['multiband']['ms_per_step']:.1f} ms/step")
     return out

@@ -48,7 +48,7 @@
 extern "C" {
 #endif
 
-#define CCR_ABI_VERSION 3
+#define CCR_ABI_VERSION 4
 #define CCR_MAX_DET 8
 #define CCR_PAIRS_CROSS 1 /* pairs across detectors, |K - L| <= R        */
 #define CCR_PAIRS_SAME 2  /* pairs within a detector, 0 < L - K <= R     */
@@ -144,6 +144,10 @@ typedef struct {
      * sum_n |fitted - exact tap weight| (relative to the input amplitude). */
     int64_t farrow_degree;
     double farrow_err;
+    /* The segment FFT as the kernels take it: N_FFT = P n_s, P transforms of n_s points per
+     * (template, detector, segment), one per residue class of the output bins (n_s the power of
+     * two holding N_K, at least 256 where N_FFT allows). */
+    int64_t n_s, P;
 } ccr_band_info;
 
 int ccr_abi_version(void);
@@ -173,6 +177,8 @@ const char *ccr_last_error(const ccr_ctx *ctx);
  *                     outputs) as a HIP graph on first use and replay it afterwards; a change
  *                     of data, templates, weights, workspace or launch options re-captures;
  *                     applies to device outputs only;
+ *   "round_templates" at most this many templates in one launch round (0, the default: as
+ *                     many as the workspace budget holds);
  *   "spectra_kernel"  1: run the 256- to 1024-point spectra + pair-sum kernel on every band
  *                     it takes, also where the 256-point one applies; 0 (default): the
  *                     256-point kernel first;
@@ -195,8 +201,8 @@ const char *ccr_last_error(const ccr_ctx *ctx);
 ccr_status ccr_set_option(ccr_ctx *ctx, const char *name, int64_t value);
 
 /* Read an option set with ccr_set_option, or "tuned_k_chunk" / "tuned_template_batch" /
- * "tuned_spectra_kernel": the launch shape the autotuner chose last (0, or -1 for the kernel,
- * before any tuning), or "resample_templates": the
+ * "tuned_round_templates" / "tuned_spectra_kernel": the launch shape the autotuner chose last
+ * (0, or -1 for the kernel, before any tuning), or "resample_templates": the
  * templates one resampling workgroup handles from one staged input window (a constant of the
  * build), "farrow_templates" / "farrow_degree": the same for the Farrow-form kernel and its
  * polynomial degree.  CCR_EUNSUP for an unknown name. */

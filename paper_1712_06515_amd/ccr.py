@@ -50,7 +50,7 @@ class BandInfo(ctypes.Structure):
                 ("dt", ctypes.c_double), ("f_het", ctypes.c_double), ("df_load", ctypes.c_double),
                 ("t_coh", ctypes.c_double), ("dlambda_f", ctypes.c_double), ("t_fft", ctypes.c_double),
                 ("nu_r", ctypes.c_double), ("norm", ctypes.c_double), ("farrow_degree", ctypes.c_int64),
-                ("farrow_err", ctypes.c_double)]
+                ("farrow_err", ctypes.c_double), ("n_s", ctypes.c_int64), ("P", ctypes.c_int64)]
 
     def as_dict(self):
         return {f[0]: getattr(self, f[0]) for f in self._fields_}

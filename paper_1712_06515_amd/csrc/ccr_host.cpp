@@ -112,6 +112,7 @@ struct ccr_ctx {
     size_t auto_budget = 0;         // automatic workspace budget, fixed at the first compute call
     int64_t opt_k_chunk = 0;
     int64_t opt_spectra_kernel = 0;  // 1: the 256- to 1024-point spectra + pair-sum kernel wherever it applies
+    int64_t opt_round_templates = 0;  // at most this many templates in one launch round (0: no limit)
     int64_t opt_fused = 0;
     int64_t opt_timing = 0;
     DevBuf ws_arena;                // workspace of the batched path: one arena, laid out per launch round
@@ -136,7 +137,7 @@ struct ccr_ctx {
         int spectra;
     };
     std::vector<Tuned> tuned;
-    int64_t last_tuned_k_chunk = 0, last_tuned_template_batch = 0, last_tuned_spectra = -1;
+    int64_t last_tuned_k_chunk = 0, last_tuned_template_batch = 0, last_tuned_spectra = -1, last_tuned_round_templates = 0;
     struct Timed {
         int kind;
         hipEvent_t a, b;
@@ -246,6 +247,9 @@ ccr_status make_plan(ccr_ctx *c, const Band &B, Plan &pl) {
         while ((double)nfft < nfft0) nfft *= 2;
         if (nfft < ns) nfft = ns;
     }
+    // segments of at most 128 samples are transformed as 256 points (zero-padded; P halves) where
+    // N_FFT allows: the same P n_s points per segment, on the kernels built for 256 to 1024 points
+    if (ns < 256 && nfft >= 256 && nfft % 256 == 0) ns = 256;
     pl.n_s = ns;
     pl.n_fft = nfft;
     pl.P = nfft / ns;
@@ -1539,6 +1543,7 @@ ccr_status choose_params(ccr_ctx *c, ccr_precision prec, int n_bands, const int 
     bp = BatchParams();
     bp.k_chunk = c->opt_k_chunk;
     bp.template_batch = c->opt_template_batch;
+    bp.round_templates = c->opt_round_templates;
     bp.spectra = (int)c->opt_spectra_kernel;
     if (!c->opt_autotune || c->opt_k_chunk > 0) return CCR_OK;
     const std::vector<int> ids(band_ids, band_ids + n_bands);
@@ -1653,6 +1658,7 @@ done:
     c->last_tuned_k_chunk = bp.k_chunk;
     c->last_tuned_template_batch = bp.template_batch;
     c->last_tuned_spectra = bp.spectra;
+    c->last_tuned_round_templates = bp.round_templates;
     return CCR_OK;
 }
 
@@ -1728,6 +1734,37 @@ ccr_status compute_batched(ccr_ctx *c, ccr_precision prec, int n_bands, const in
 }  // namespace
 
 // ====================================================================== ABI
+
+// Time base and resampled series of one template as the split-precision compute path makes
+// them: the band's node rule and small-angle series (cheb_split, short_series) and the
+// Farrow-form resampler where the band has its table, through the batched launchers on a plan
+// of one-template rounds.  The series, [Q][n_seg n_k] complex64, is left in the workspace
+// arena (*y_dev) until the next compute call.
+static ccr_status split_series_of(ccr_ctx *c, int band_id, int64_t template_index, hipStream_t s, const void **y_dev) {
+    BatchParams bp;
+    bp.template_batch = 1;
+    bp.round_templates = 1;
+    bp.k_chunk = get_band(c, band_id)->plan.n_seg;  // one chunk: no partial sums to hold
+    CallPlan cp;
+    void *none = nullptr;
+    ccr_status st = build_plan(c, false, 1, &band_id, &none, 1, 0, bp, cp);
+    if (st) return st;
+    if ((size_t)template_index >= cp.rounds.size()) return fail(c, CCR_EINVAL, "template index out of range");
+    if ((st = ensure_workspace(c, cp))) return st;
+    size_t items_off = 0;
+    if ((st = upload_tables(c, cp, s, &items_off))) return st;
+    const Round &r = cp.rounds[(size_t)template_index];
+    const Workspace ws = round_workspace(c->ws_arena.p, r);
+    const BandDev *db = static_cast<const BandDev *>(c->d_tables.p);
+    const WorkItem *di = reinterpret_cast<const WorkItem *>(static_cast<const char *>(c->d_tables.p) + items_off) + r.i0;
+    // segments without a spectrum are not resampled: zero first, as the stage output shows them
+    HIP_OK(c, launch_zero(ws.y, r.y_bytes, s));
+    HIP_OK(c, launch_timebase_m(db, di, r.n, (int)r.blocks[kStTimebase], r.v.n_cheb, r.v.ss, ws.coef, s));
+    HIP_OK(c, launch_resample_m(db, di, r.n, (int)r.blocks[kStResample], false, r.v.DT, r.v.window, r.v.n_cheb,
+                                r.v.far, ws.coef, ws.y, s));
+    *y_dev = ws.y;
+    return CCR_OK;
+}
 
 extern "C" {
 
@@ -1812,6 +1849,7 @@ ccr_status ccr_set_option(ccr_ctx *c, const char *name, int64_t value) {
     else if (k == "workspace_mb") c->opt_workspace_mb = value == 0 ? 0 : std::max<int64_t>(value, 64);
     else if (k == "k_chunk") c->opt_k_chunk = value;
     else if (k == "spectra_kernel") c->opt_spectra_kernel = value ? 1 : 0;
+    else if (k == "round_templates") c->opt_round_templates = value;
     else if (k == "fused") c->opt_fused = value;
     else if (k == "timing") c->opt_timing = value;
     else if (k == "graph") c->opt_graph = value;
@@ -1821,7 +1859,7 @@ ccr_status ccr_set_option(ccr_ctx *c, const char *name, int64_t value) {
     else if (k == "farrow_stage") c->opt_farrow_stage = value ? 1 : 0;
     else return fail(c, CCR_EUNSUP, "unknown option '%s'", name);
     if (k == "template_batch" || k == "workspace_mb" || k == "k_chunk" || k == "items_per_launch" || k == "farrow" ||
-        k == "farrow_stage" || k == "fused" || k == "spectra_kernel")
+        k == "farrow_stage" || k == "fused" || k == "spectra_kernel" || k == "round_templates")
         c->gen++;
     return CCR_OK;
 }
@@ -1842,6 +1880,8 @@ ccr_status ccr_get_option(ccr_ctx *c, const char *name, int64_t *value) {
     else if (k == "tuned_template_batch") *value = c->last_tuned_template_batch;
     else if (k == "tuned_spectra_kernel") *value = c->last_tuned_spectra;
     else if (k == "spectra_kernel") *value = c->opt_spectra_kernel;
+    else if (k == "round_templates") *value = c->opt_round_templates;
+    else if (k == "tuned_round_templates") *value = c->last_tuned_round_templates;
     else if (k == "resample_templates") *value = kResTemplates;
     else if (k == "farrow") *value = c->opt_farrow;
     else if (k == "farrow_stage") *value = c->opt_farrow_stage;
@@ -2085,6 +2125,8 @@ ccr_status ccr_get_band_info(ccr_ctx *c, int band_id, ccr_band_info *info, doubl
     info->norm = pl.norm;
     info->farrow_degree = B->far_len > 0 ? kFarDeg : 0;
     info->farrow_err = B->far_err;
+    info->n_s = B->plan.n_s;
+    info->P = B->plan.P;
     if (bin_freqs) std::memcpy(bin_freqs, B->freqs.data(), sizeof(double) * (size_t)pl.n_f);
     return CCR_OK;
 }
@@ -2156,6 +2198,7 @@ ccr_status ccr_compute_rho_noalloc(ccr_ctx *c, ccr_precision prec, int n_bands, 
     BatchParams bp;
     bp.k_chunk = c->opt_k_chunk;
     bp.template_batch = c->opt_template_batch;
+    bp.round_templates = c->opt_round_templates;
     bp.spectra = (int)c->opt_spectra_kernel;
     CallPlan cp;
     ccr_status st = build_plan(c, fp64, n_bands, band_ids, rho_out, 1, out_fp64, bp, cp, budget);
@@ -2284,17 +2327,24 @@ ccr_status ccr_resample_series(ccr_ctx *c, ccr_precision prec, int band_id, int6
     const Plan &pl = B->plan;
     const size_t cs = fp64 ? 16 : 8;
     const size_t bytes = (size_t)B->Q * pl.n_seg * pl.n_k * cs;
+    const size_t per = (size_t)pl.n_seg * pl.n_k * cs;
+    hipStream_t s = c->stream;
+    if (!fp64) {
+        const void *yd = nullptr;
+        if ((st = split_series_of(c, band_id, template_index, s, &yd))) return st;
+        HIP_OK(c, hipMemcpyAsync(y_out, static_cast<const char *>(yd) + det * per, per, hipMemcpyDeviceToHost, s));
+        HIP_OK(c, hipStreamSynchronize(s));
+        return CCR_OK;
+    }
     DevBuf y, cf;
     HIP_OK(c, y.ensure(bytes));
     HIP_OK(c, cf.ensure((size_t)std::max(B->n_work, 1) * kCheb * sizeof(double)));
-    hipStream_t s = c->stream;
     HIP_OK(c, launch_zero(y.p, bytes, s));
     BandDev bd = band_dev(*B);
     if (!c->opt_farrow) bd.farrow = nullptr;
     bd.far_stage = (int)c->opt_farrow_stage;
     HIP_OK(c, launch_timebase(bd, B->d_tmpl.as<double>() + (size_t)template_index * kTmplStride, 1, cf.as<double>(), s));
     HIP_OK(c, launch_resample(bd, cf.as<double>(), 1, fp64, y.p, s));
-    const size_t per = (size_t)pl.n_seg * pl.n_k * cs;
     HIP_OK(c, hipMemcpyAsync(y_out, y.as<char>() + det * per, per, hipMemcpyDeviceToHost, s));
     HIP_OK(c, hipStreamSynchronize(s));
     return CCR_OK;
@@ -2355,18 +2405,24 @@ ccr_status ccr_segment_spectra(ccr_ctx *c, ccr_precision prec, int band_id, int6
     DevBuf y, F, cf;
     HIP_OK(c, cf.ensure((size_t)std::max(B->n_work, 1) * kCheb * sizeof(double)));
     const size_t ybytes = (size_t)B->Q * pl.n_seg * pl.n_k * cs, fbytes = (size_t)B->Q * pl.n_seg * pl.n_f * cs;
-    HIP_OK(c, y.ensure(ybytes));
     HIP_OK(c, F.ensure(fbytes));
     hipStream_t s = c->stream;
-    HIP_OK(c, launch_zero(y.p, ybytes, s));
     HIP_OK(c, launch_zero(F.p, fbytes, s));
     BandDev bd = band_dev(*B);
     if (!c->opt_farrow) bd.farrow = nullptr;
     bd.far_stage = (int)c->opt_farrow_stage;
-    HIP_OK(c, launch_timebase(bd, B->d_tmpl.as<double>() + (size_t)template_index * kTmplStride, 1, cf.as<double>(), s));
-    HIP_OK(c, launch_resample(bd, cf.as<double>(), 1, fp64, y.p, s));
+    const void *ysrc = nullptr;
+    if (fp64) {
+        HIP_OK(c, y.ensure(ybytes));
+        HIP_OK(c, launch_zero(y.p, ybytes, s));
+        HIP_OK(c, launch_timebase(bd, B->d_tmpl.as<double>() + (size_t)template_index * kTmplStride, 1, cf.as<double>(), s));
+        HIP_OK(c, launch_resample(bd, cf.as<double>(), 1, fp64, y.p, s));
+        ysrc = y.p;
+    } else if ((st = split_series_of(c, band_id, template_index, s, &ysrc))) {
+        return st;
+    }
     bd.pw = nullptr;  // the unweighted spectra F
-    HIP_OK(c, launch_spectra(bd, 1, fp64, y.p, F.p, s));
+    HIP_OK(c, launch_spectra(bd, 1, fp64, ysrc, F.p, s));
     HIP_OK(c, hipMemcpyAsync(f_out, F.p, fbytes, hipMemcpyDeviceToHost, s));
     HIP_OK(c, hipStreamSynchronize(s));
     return CCR_OK;

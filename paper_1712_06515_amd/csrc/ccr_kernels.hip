@@ -1579,10 +1579,11 @@ __device__ __forceinline__ float wide_pair_term(const float2 (&f)[Q], const floa
     return st;
 }
 
-// Workgroup of the spectra + pair-sum kernel for 256- to 1024-point segments: kSpwWaves
-// wavefronts share one spectrum ring; wavefront w transforms the detectors X = w, w + kSpwWaves,
-// ... and sums the pairs of the bins (ring columns) w 64 + l + 128 u.
-constexpr int kSpwWaves = 2;
+// Workgroup of the spectra + pair-sum kernel for 256- to 1024-point segments: spw_waves(Q)
+// wavefronts share one spectrum ring; wavefront w transforms the detectors X = w, w + W, ...
+// (one each for up to 3 detectors, two each for 4) and sums the pairs of the bins (ring
+// columns) w 64 + l + 64 W u.
+__host__ __device__ constexpr int spw_waves(int q) { return q == 4 ? 2 : q; }
 
 // LDS of the spectra + pair-sum kernel for ns-point segments (bytes).
 struct SpwLayout {
@@ -1596,7 +1597,7 @@ __host__ __device__ inline SpwLayout spw_layout(int Q, int R, int ncol, int jmax
     L.ncol1 = ncol + 1;  // the last column of a ring row takes FFT outputs that are not output bins
     size_t o = 0;
     L.off_fx = o;  // one FFT exchange buffer per wavefront (ns values, padded)
-    o += (size_t)kSpwWaves * (ns + 64) * sizeof(float2);
+    o += (size_t)spw_waves(Q) * (ns + 64) * sizeof(float2);
     L.off_ring = o;
     o += (size_t)L.slots * Q * L.ncol1 * sizeof(float2);
     L.off_pos = o;
@@ -1606,7 +1607,7 @@ __host__ __device__ inline SpwLayout spw_layout(int Q, int R, int ncol, int jmax
 }
 
 // Spectra + pair sum for NS-point segments, NS = 256, 512 or 1024 (split precision, N_FFT a power
-// of two, distinct bins): one workgroup of kSpwWaves wavefronts per (template, residue class p of
+// of two, distinct bins): one workgroup of spw_waves(Q) wavefronts per (template, residue class p of
 // the output bins, chunk [K0, K1) of segments plus R halo segments before it).
 //   Spectra: for each segment K that some detector takes part in (the compacted list
 //   seg_any) and each detector with data there, the zero-padded segment is multiplied by
@@ -1634,6 +1635,7 @@ __device__ __forceinline__ void spectra_wide_body(const BandDev &B, const float2
                                                   int k_chunk, int n_chunks, int c, int p, int tb) {
     extern __shared__ __align__(16) unsigned char smem[];
     constexpr int V = NS / 64;  // FFT values a lane
+    constexpr int W = spw_waves(Q);  // wavefronts
     const int n_k = B.n_k, R = B.R, N = B.n_fft, mask = B.nfft_mask;
     const SpwLayout Ly = spw_layout(Q, R, B.wide_ncol, B.wide_jmax, NS);
     // the wavefront index, uniform within the wavefront (readfirstlane makes that known to the
@@ -1649,10 +1651,10 @@ __device__ __forceinline__ void spectra_wide_body(const BandDev &B, const float2
     const int m0 = B.cls_m0[p];
 
     // FFT output m' = l + 64 J (J < jmax) of the rotated class: its ring column, or the spare one
-    for (int e = threadIdx.x; e < jmax * 64; e += 64 * kSpwWaves) opos[e] = (int16_t)(ncol1 - 1);
-    for (int e = threadIdx.x; e < slots * Q * ncol1; e += 64 * kSpwWaves) ring[e] = make_float2(0.f, 0.f);
+    for (int e = threadIdx.x; e < jmax * 64; e += 64 * W) opos[e] = (int16_t)(ncol1 - 1);
+    for (int e = threadIdx.x; e < slots * Q * ncol1; e += 64 * W) ring[e] = make_float2(0.f, 0.f);
     __syncthreads();
-    for (int col = threadIdx.x; col < n_p; col += 64 * kSpwWaves) {
+    for (int col = threadIdx.x; col < n_p; col += 64 * W) {
         const int mm = (B.bin_m[B.col_bin[cs + col]] - m0) & (NS - 1);
         opos[mm] = (int16_t)col;
     }
@@ -1670,7 +1672,7 @@ __device__ __forceinline__ void spectra_wide_body(const BandDev &B, const float2
     int kbc[U], binc[U];
 #pragma unroll
     for (int u = 0; u < U; ++u) {
-        const int col = wv * 64 + lane + 128 * u;
+        const int col = wv * 64 + lane + 64 * W * u;
         binc[u] = col < n_p ? B.col_bin[cs + col] : -1;
         kbc[u] = col < n_p ? B.bin_kb[binc[u]] : 0;
     }
@@ -1697,13 +1699,13 @@ __device__ __forceinline__ void spectra_wide_body(const BandDev &B, const float2
     const int lo = lower(Kh), hi = lower(K1);
     const int64_t nr = (int64_t)B.n_seg * n_k;
     const float2 *ybase = y + (size_t)tb * Q * nr;
-    // this wavefront's detectors X = wv + kSpwWaves i (i < NJ); the input of a detector's next
+    // this wavefront's detectors X = wv + W i (i < NJ); the input of a detector's next
     // segment is loaded while the current one is transformed.  Buffer loads with the segment's
     // n_k samples as the buffer range read zero past it (no branches, no zero padding in memory).
-    constexpr int NJ = (Q + kSpwWaves - 1) / kSpwWaves;
+    constexpr int NJ = (Q + W - 1) / W;
     float2 nxt[NJ][V];
     auto load = [&](int e, int i) {
-        const int X = wv + kSpwWaves * i;
+        const int X = wv + W * i;
         const float2 *ys = ybase + (size_t)X * nr + (size_t)ld_uniform(B.seg_any, e) * n_k;
         const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc((void *)ys, (short)0, n_k * 8, 0x00020000);
 #pragma unroll
@@ -1713,7 +1715,7 @@ __device__ __forceinline__ void spectra_wide_body(const BandDev &B, const float2
     if (lo < hi) {
 #pragma unroll
         for (int i = 0; i < NJ; ++i)
-            if (wv + kSpwWaves * i < Q) load(lo, i);
+            if (wv + W * i < Q) load(lo, i);
     }
 
     float2 Ga[Q][U], Gb[Q][U];
@@ -1733,7 +1735,7 @@ __device__ __forceinline__ void spectra_wide_body(const BandDev &B, const float2
         // this wavefront's transforms of step e
 #pragma unroll
         for (int i = 0; i < NJ; ++i) {
-            const int X = wv + kSpwWaves * i;
+            const int X = wv + W * i;
             if (X >= Q) continue;
             float2 v[V];
 #pragma unroll
@@ -1761,8 +1763,8 @@ __device__ __forceinline__ void spectra_wide_body(const BandDev &B, const float2
         const float invN = 1.0f / (float)N;
 #pragma unroll
         for (int u = 0; u < U; ++u) {
-            const int col = wv * 64 + lane + 128 * u;
-            if (U > 1 && 128 * u >= n_p) break;  // uniform: no lane of the workgroup has a bin here
+            const int col = wv * 64 + lane + 64 * W * u;
+            if (U > 1 && 64 * W * u >= n_p) break;  // uniform: no lane of the workgroup has a bin here
             float2 *slot = ring + (size_t)head * Q * ncol1 + (col < n_p ? col : ncol1 - 1);
             float2 f[Q];
 #pragma unroll
@@ -1824,8 +1826,8 @@ __device__ __forceinline__ void spectra_wide_body(const BandDev &B, const float2
                 const float2 *rowt = ring + (size_t)tail * Q * ncol1;
 #pragma unroll
                 for (int u = 0; u < U; ++u) {
-                    if (U > 1 && 128 * u >= n_p) break;
-                    const int col = wv * 64 + lane + 128 * u;
+                    if (U > 1 && 64 * W * u >= n_p) break;
+                    const int col = wv * 64 + lane + 64 * W * u;
                     const float2 *gp = rowt + (col < n_p ? col : ncol1 - 1);
 #pragma unroll
                     for (int X = 0; X < Q; ++X) {
@@ -2490,7 +2492,7 @@ k_spectra_pairs_m(const BandDev *__restrict__ bands, const WorkItem *__restrict_
 // workgroups of one (template, chunk) group are given indices with equal l mod 8, which puts
 // them on one XCD, where they read the group's resampled series through that XCD's L2.
 template <int NS, int U, int Q, bool ALLP>
-__global__ void __launch_bounds__(64 * kSpwWaves)
+__global__ void __launch_bounds__(64 * spw_waves(Q))
 k_spectra_wide_m(const BandDev *__restrict__ bands, const WorkItem *__restrict__ items, int n_items,
                  const float2 *__restrict__ y, double *__restrict__ part) {
     const WorkItem &it = items[find_item(items, n_items, kStSpectra, blockIdx.x)];
@@ -2625,8 +2627,8 @@ hipError_t launch_spectra(const BandDev &B, int n_tmpl, bool fp64, const void *y
 
 bool spectra_pairs_ok(const BandDev &B, bool fp64, size_t limit) {
     const SpairLayout L = spair_layout(B.Q, B.n_f, B.R, B.n_fft);
-    return !fp64 && B.n_s == 256 && B.bins_unique && B.Q <= 4 && B.n_f <= 64 * kSpairMaxRounds && L.slots < 256 &&
-           L.total <= limit;
+    return !fp64 && B.n_s == 256 && B.n_k > 128 && B.bins_unique && B.Q <= 4 && B.n_f <= 64 * kSpairMaxRounds &&
+           L.slots < 256 && L.total <= limit;
 }
 
 
@@ -2696,11 +2698,15 @@ size_t spectra_pairs_lds(const BandDev &B) { return spair_layout(B.Q, B.n_f, B.R
 
 size_t spectra_wide_lds(const BandDev &B) { return spw_layout(B.Q, B.R, B.wide_ncol, B.wide_jmax, B.n_s).total; }
 
-int spectra_wide_cols(const BandDev &B) { return B.wide_ncol <= 128 ? 1 : (B.wide_ncol <= 256 ? 2 : 4); }
+int spectra_wide_cols(const BandDev &B) {
+    const int per = 64 * spw_waves(B.Q);  // bin columns a workgroup covers per U
+    return B.wide_ncol <= per ? 1 : (B.wide_ncol <= 2 * per ? 2 : 4);
+}
 
 bool spectra_wide_ok(const BandDev &B, bool fp64, size_t limit) {
     return !fp64 && (B.n_s == 1024 || B.n_s == 512 || B.n_s == 256) && B.nfft_mask != 0 && B.bins_unique &&
-           B.Q >= 1 && B.Q <= 4 && B.wide_ncol <= 512 && B.wide_jmax >= 1 && B.wide_jmax <= B.n_s / 64 &&
+           B.Q >= 1 && B.Q <= 4 && B.wide_ncol <= 4 * 64 * spw_waves(B.Q) && B.wide_jmax >= 1 &&
+           B.wide_jmax <= B.n_s / 64 &&
            B.cls_m0 != nullptr && spectra_wide_lds(B) <= limit;
 }
 
@@ -2801,7 +2807,7 @@ template <int NS, bool ALLP>
 static void launch_spectra_wide_u(const BandDev *bands, const WorkItem *items, int n_items, int blocks, int cols,
                                   int q, size_t lds, const void *y, double *part, hipStream_t stream) {
 #define CCR_WIDE(U_, Q_)                                                                                            \
-    hipLaunchKernelGGL((k_spectra_wide_m<NS, U_, Q_, ALLP>), dim3(blocks), dim3(64 * kSpwWaves), lds, stream, bands, \
+    hipLaunchKernelGGL((k_spectra_wide_m<NS, U_, Q_, ALLP>), dim3(blocks), dim3(64 * spw_waves(Q_)), lds, stream, bands, \
                        items, n_items, (const float2 *)y, part)
 #define CCR_WIDE_Q(U_)          \
     do {                        \

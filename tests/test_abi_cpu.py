@@ -38,7 +38,7 @@ def test_exports_every_declared_symbol(lib):
     for n in names:
         assert hasattr(lib, n), n
     assert set(names) == set(ccr.SIGNATURES), set(names) ^ set(ccr.SIGNATURES)
-    assert lib.ccr_abi_version() == 3
+    assert lib.ccr_abi_version() == 4
 
 
 def test_struct_layouts_match_header(lib):
@@ -47,7 +47,7 @@ def test_struct_layouts_match_header(lib):
     assert ctypes.sizeof(ccr.Site) == 16
     assert ctypes.sizeof(ccr.Band) == 3 * 8 + 4 * 4 + 8 + 8 + 8 + 8 + 8  # int32 pairs, weight padded to 8
     assert ccr.Band.weight.offset == 72
-    assert ctypes.sizeof(ccr.BandInfo) == 10 * 8 + 9 * 8
+    assert ctypes.sizeof(ccr.BandInfo) == 12 * 8 + 9 * 8  # 12 int64 (n_s, P last), 9 double
 
 
 def test_null_and_bad_arguments(lib):

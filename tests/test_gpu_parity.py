@@ -321,7 +321,7 @@ def test_weighted_pair_sums(ccr, case):
         ctx.set_option("template_batch", 1)
         r64b = ctx.compute_rho(bid, prec=ccr.PREC_FP64)
         r32b = ctx.compute_rho(bid, prec=ccr.PREC_SPLIT, out_fp64=False)
-    ns = 1 << (info["n_k"] - 1).bit_length()
+    ns = info["n_s"]
     wide = ns in (256, 512, 1024) and not per_sample
     assert kt["spectra_pairs"][1] == 0, kt
     assert (kt["spectra_wide"][1] > 0) == wide and (kt["pairs"][1] > 0) != wide, kt
@@ -383,7 +383,7 @@ def test_spectra_wide_512_256(ccr, case):
         ctx.set_option("k_chunk", kc)
         bid = ctx.load(ds)
         info = ctx.band_info(bid)
-        ns = 1 << (info["n_k"] - 1).bit_length()
+        ns = info["n_s"]
         assert ns == (512 if case.startswith("n512") else 256), info
         r64 = ctx.compute_rho(bid, prec=ccr.PREC_FP64)
         ctx.kernel_times(reset=True)
@@ -523,6 +523,49 @@ def test_workspace_rounds(ccr, band_workload):
 @pytest.fixture(scope="module")
 def large_workload():
     return synth.make_dataset(synth.config("large"))
+
+
+@pytest.mark.parametrize("which", ["band", "large"])
+def test_resampled_series_compute_path_time_base(ccr, which, band_workload, large_workload):
+    """The split stage output is made by the compute path's own time base and resampler: the
+    band's Chebyshev node rule and small-angle series (5 nodes and the short series on the
+    120-day band, 6 nodes on the 240-day one, chosen by the host's error bounds) and the Farrow
+    form; element by element over the full series of detector 0 against the oracle's
+    long-double Newton solve and direct sinc sum (Sec. III.A.1-2), 2e-6 of the peak, for a
+    template near an injection, over the first 3000 (120 days) or 400 (240 days) segments, on
+    the segments the compute path resamples (those that take part in a pair).""" 
+    import copy
+    full = band_workload if which == "band" else large_workload
+    inj = full.injections[0]
+    t = int(np.argmin((full.templates[:, 0] - inj["a_p"]) ** 2 + ((full.templates[:, 1] - inj["t_asc"]) / 1000.0) ** 2))
+    # the first segments of the workload (same band, lattice, gaps and templates; the time base
+    # of a sample depends only on its time), so that the oracle's per-sample solve stays short
+    m_sub = 3000 if which == "band" else 400
+    ds = copy.copy(full)
+    nsamp = m_sub * full.n_k
+    ds.x, ds.valid = full.x[:, :nsamp], full.valid[:, :nsamp]
+    ds.a, ds.b, ds.noise_var = full.a[:, :m_sub], full.b[:, :m_sub], full.noise_var[:, :m_sub]
+    ds.n, ds.n_seg = nsamp, m_sub
+    o = oracle.Oracle(ds)
+    y_ref, js, off, m0 = o.resample(0, ds.templates[t])
+    m1 = o.resample(1, ds.templates[t])[3]
+    with ccr.Context(ds.sky, device=0) as ctx:
+        bid = ctx.load(ds, templates=ds.templates[t:t + 1])
+        y32 = ctx.resample_series(bid, 0, 0, prec=ccr.PREC_SPLIT)
+    # the compute path resamples only segments that take part in a pair (Sec. III.B.1 with the
+    # band's lag and pair kinds): segment K of detector 0 has data and a partner with data
+    M, nk, R, pairs = ds.n_seg, ds.n_k, ds.band["max_lag"], ds.band.get("pairs", 3)
+    a0 = m0[:M * nk].reshape(M, nk).any(axis=1)
+    a1 = m1[:M * nk].reshape(M, nk).any(axis=1)
+    near = lambda a, same: np.array([a[max(0, K - R):K + R + 1].sum() - (a[K] if same else 0) > 0 for K in range(M)])
+    active = a0 & (((pairs & 1) != 0) & near(a1, False) | ((pairs & 2) != 0) & near(a0, True))
+    act = np.repeat(active, nk)
+    scale = np.abs(y_ref).max()
+    err = np.abs(y32[:M * nk][act] - y_ref[:M * nk][act]).max() / scale
+    print(f"{which}: split resampled series over {act.sum()} samples of {active.sum()} active segments "
+          f"(of {M}), template {t}: {err:.2e} of the peak")
+    assert err < 2e-6
+    assert not np.any(y32[:M * nk][~act])
 
 
 def test_large_workload_sampled(ccr, large_workload):
