@@ -1764,7 +1764,7 @@ __device__ __forceinline__ void spectra_wide_body(const BandDev &B, const float2
 #pragma unroll
         for (int u = 0; u < U; ++u) {
             const int col = wv * 64 + lane + 64 * W * u;
-            if (U > 1 && 64 * W * u >= n_p) break;  // uniform: no lane of the workgroup has a bin here
+            if (wv * 64 + 64 * W * u >= n_p) break;  // uniform: no lane of this wavefront has a bin here
             float2 *slot = ring + (size_t)head * Q * ncol1 + (col < n_p ? col : ncol1 - 1);
             float2 f[Q];
 #pragma unroll
@@ -1826,7 +1826,7 @@ __device__ __forceinline__ void spectra_wide_body(const BandDev &B, const float2
                 const float2 *rowt = ring + (size_t)tail * Q * ncol1;
 #pragma unroll
                 for (int u = 0; u < U; ++u) {
-                    if (U > 1 && 64 * W * u >= n_p) break;
+                    if (wv * 64 + 64 * W * u >= n_p) break;
                     const int col = wv * 64 + lane + 64 * W * u;
                     const float2 *gp = rowt + (col < n_p ? col : ncol1 - 1);
 #pragma unroll
