@@ -1216,6 +1216,7 @@ struct CallPlan {
 struct BatchParams {
     int64_t template_batch = 0, k_chunk = 0;
     int64_t round_templates = 0;  // at most this many templates in one launch round (0: no limit)
+    int64_t max_templates = 0;    // tuning: only the first this many templates of each band (0: all)
     int spectra = 0;  // 1: the wide spectra + pair-sum kernel wherever it applies, 0: the 256-point one first
 };
 
@@ -1348,10 +1349,11 @@ ccr_status build_plan(ccr_ctx *c, bool fp64, int n_bands, const int *band_ids, v
         }
         tb = std::max<int64_t>(1, std::min<int64_t>(tb, B.n_tmpl));
         char *dst = out_on_device ? static_cast<char *>(rho_out[bi]) : c->ws_out.as<char>() + cp.out_off[bi];
-        for (int64_t t = 0; t < B.n_tmpl; t += tb) {
+        const int64_t n_t = bp.max_templates > 0 ? std::min<int64_t>(B.n_tmpl, bp.max_templates) : B.n_tmpl;
+        for (int64_t t = 0; t < n_t; t += tb) {
             Pending q;
             q.it = proto;
-            const int nb = (int)std::min<int64_t>(tb, B.n_tmpl - t);
+            const int nb = (int)std::min<int64_t>(tb, n_t - t);
             q.it.n_tmpl = nb;
             q.it.tmpl_off = t;
             q.it.out = dst + (size_t)t * pl.n_f * osz;
@@ -1530,14 +1532,13 @@ ccr_status upload_tables(ccr_ctx *c, const CallPlan &cp, hipStream_t s, size_t *
 
 
 // Launch shapes for a call: the tuned ones when autotuning is on.  Tuning on first use for a
-// band list and precision times the first launch round of the call for each candidate and
-// keeps the fastest per template:
+// band list and precision times the call for each candidate and keeps the fastest per template:
 //   1. the spectra kernel (where a band can take both the 256-point and the wide spectra +
-//      pair-sum kernel) and k_chunk = 32 ... 1024, with a tuning batch of at most 64 templates
-//      per band;
-//   2. the template batch: the workspace budget's (the largest) and its halves and quarters,
-//      when a round of that size is cheap enough to time (the estimate from step 1 for all
-//      candidates below about 12 s).
+//      pair-sum kernel) and k_chunk = 32 ... 1024, on the first (at most) 64 templates of
+//      every band, in rounds of at most 64 templates;
+//   2. the templates per launch round: the workspace budget's batch (the largest) and its half
+//      and quarter, when the whole call is cheap enough to time (the estimate from step 1 for
+//      all candidates below about 12 s).
 ccr_status choose_params(ccr_ctx *c, ccr_precision prec, int n_bands, const int *band_ids, void *const *rho_out,
                          int out_on_device, int out_fp64, hipStream_t s, BatchParams &bp) {
     bp = BatchParams();
@@ -1569,8 +1570,8 @@ ccr_status choose_params(ccr_ctx *c, ccr_precision prec, int n_bands, const int 
     hipEvent_t e0 = nullptr, e1 = nullptr;
     HIP_OK(c, hipEventCreate(&e0));
     HIP_OK(c, hipEventCreate(&e1));
-    // per-template time of the first round of a candidate (one untimed pass, then a timed one);
-    // n_round: templates of that round
+    // per-template time of a candidate over every round of its plan (one untimed pass, then a
+    // timed one), so that calls over several bands compare like with like; n_round: templates
     auto trial = [&](const BatchParams &cand, float &per, int64_t &n_round) -> ccr_status {
         CallPlan cp;
         size_t items_off = 0;
@@ -1578,10 +1579,12 @@ ccr_status choose_params(ccr_ctx *c, ccr_precision prec, int n_bands, const int 
         if ((st = build_plan(c, fp64, n_bands, band_ids, rho_out, out_on_device, out_fp64, cand, cp))) return st;
         if ((st = ensure_workspace(c, cp))) return st;
         if ((st = upload_tables(c, cp, s, &items_off))) return st;
-        for (int rep = 0; rep < 2; ++rep) {
+        // an untimed pass first, unless the plan has enough rounds to warm up within the timed one
+        const int first = cp.rounds.size() >= 4 ? 1 : 0;
+        for (int rep = first; rep < 2; ++rep) {
             if (rep == 1 && hipEventRecord(e0, s) != hipSuccess) return fail(c, CCR_EDEVICE, "event record failed");
-            if ((st = run_rounds(c, cp, 0, std::min<size_t>(1, cp.rounds.size()), fp64, c->d_tables.p, items_off, s,
-                                 false, c->ws_arena.p)))
+            if ((st = run_rounds(c, cp, 0, cp.rounds.size(), fp64, c->d_tables.p, items_off, s, false,
+                                 c->ws_arena.p)))
                 return st;
         }
         HIP_OK(c, hipEventRecord(e1, s));
@@ -1589,8 +1592,7 @@ ccr_status choose_params(ccr_ctx *c, ccr_precision prec, int n_bands, const int 
         float ms = 0.0f;
         HIP_OK(c, hipEventElapsedTime(&ms, e0, e1));
         n_round = 0;
-        if (!cp.rounds.empty())
-            for (int i = 0; i < cp.rounds[0].n; ++i) n_round += cp.items[cp.rounds[0].i0 + i].n_tmpl;
+        for (const WorkItem &it : cp.items) n_round += it.n_tmpl;
         per = ms / (float)std::max<int64_t>(n_round, 1);
         return CCR_OK;
     };
@@ -1614,6 +1616,7 @@ ccr_status choose_params(ccr_ctx *c, ccr_precision prec, int n_bands, const int 
                 cand.spectra = sk;
                 cand.template_batch = t_tune;
                 cand.round_templates = t_tune;
+                cand.max_templates = t_tune;
                 float per = 0.0f;
                 int64_t nr = 0;
                 if ((st = trial(cand, per, nr))) goto done;
@@ -1631,6 +1634,7 @@ ccr_status choose_params(ccr_ctx *c, ccr_precision prec, int n_bands, const int 
                     BatchParams cand = bestp;
                     cand.template_batch = tb;
                     cand.round_templates = tb < t_auto ? tb : 0;
+                    cand.max_templates = 0;
                     float per = 0.0f;
                     int64_t nr = 0;
                     if ((st = trial(cand, per, nr))) goto done;
@@ -1647,7 +1651,11 @@ ccr_status choose_params(ccr_ctx *c, ccr_precision prec, int n_bands, const int 
         } else if (bp.template_batch <= 0) {
             bestp.template_batch = t_auto;
             bestp.round_templates = 0;
+        } else {
+            bestp.template_batch = bp.template_batch;  // the caller's batch and round limit
+            bestp.round_templates = bp.round_templates;
         }
+        bestp.max_templates = 0;  // the call itself covers every template
         bp = bestp;
     }
 done:
