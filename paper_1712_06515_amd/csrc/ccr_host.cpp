@@ -85,7 +85,7 @@ struct Band {
     // device tables
     DevBuf d_x, d_mask, d_anchor, d_earth, d_win64, d_win32, d_cheb_x, d_mono, d_tw64, d_tw32, d_bin_m, d_bin_p,
         d_bin_kb, d_bin_pos, d_segw, d_segwf, d_active, d_work, d_seg_work, d_tmpl, d_lagph, d_seg_any, d_col_bin, d_bin_col, d_zero256,
-        d_class_start, d_farrow, d_farrow_A, d_cls_m0, d_pw;
+        d_class_start, d_farrow, d_farrow_A, d_cls_m0, d_pw, d_pwf;
     bool per_sample = false;  // every detector has per-sample antenna functions (two spectra streams)
     int wide_jmax = 0, wide_ncol = 0;  // 1024-point spectra + pair-sum kernel (see BandDev)
     int64_t far_len = 0;  // plane length of the Farrow table, 0 when the band has none
@@ -768,8 +768,13 @@ ccr_status prepare(ccr_ctx *c, Band &B) {
             }
         });
         if ((st = upload(c, B.d_pw, pw))) return st;
+        // FP32 copy for the split path's two-stream resampling
+        std::vector<float2> pwf(pw.size());
+        for (size_t i = 0; i < pw.size(); ++i) pwf[i] = make_float2((float)pw[i].x, (float)pw[i].y);
+        if ((st = upload(c, B.d_pwf, pwf))) return st;
     } else {
         B.d_pw.release();
+        B.d_pwf.release();
     }
     if ((st = upload(c, B.d_active, B.active))) return st;
     if ((st = upload(c, B.d_work, work))) return st;
@@ -1045,6 +1050,8 @@ BandDev band_dev(const Band &B) {
     d.weight = B.p.weight;
     d.allp = B.p.pairs == CCR_PAIRS_ALL ? 1 : 0;
     d.pw = B.per_sample ? B.d_pw.as<double2>() : nullptr;
+    d.pwf = B.per_sample ? B.d_pwf.as<float2>() : nullptr;
+    d.ps2 = 0;
     return d;
 }
 
@@ -1173,13 +1180,14 @@ struct Variant {
     bool far = false;    // split-precision resampling in Farrow form
     bool wide = false;   // spectra + pair sum in one kernel, 1024-point segments
     bool wallp = false;  // wide: every ordered pair (stream-sum partials)
+    bool wps = false;    // wide: two spectra streams per segment (per-sample antenna functions)
     int wns = 0;         // wide: segment FFT length (256, 512 or 1024)
     int DT = 0, window = 0, n_s = 0, nr = 0, n_cheb = kCheb;
     int wcols = 0, wqm = 0;  // wide: bins of a class per lane, detector count
     bool operator==(const Variant &o) const {
         return sp == o.sp && reg16 == o.reg16 && z4 == o.z4 && ss == o.ss && far == o.far && wide == o.wide &&
                DT == o.DT && window == o.window && n_s == o.n_s && nr == o.nr && n_cheb == o.n_cheb &&
-               wcols == o.wcols && wqm == o.wqm && wallp == o.wallp && wns == o.wns;
+               wcols == o.wcols && wqm == o.wqm && wallp == o.wallp && wns == o.wns && wps == o.wps;
     }
 };
 
@@ -1217,10 +1225,12 @@ struct BatchParams {
     int64_t template_batch = 0, k_chunk = 0;
     int64_t round_templates = 0;  // at most this many templates in one launch round (0: no limit)
     int64_t max_templates = 0;    // tuning: only the first this many templates of each band (0: all)
+    bool no_streams = false;      // per-sample antenna functions stay on the general path
     int spectra = 0;  // 1: the wide spectra + pair-sum kernel wherever it applies, 0: the 256-point one first
 };
 
-Variant variant_of(const BandDev &bd, bool fp64, bool short_series, bool farrow, bool prefer_wide) {
+Variant variant_of(const BandDev &bd, bool fp64, bool short_series, bool farrow, bool prefer_wide,
+                   bool streams = true) {
     Variant v;
     v.ss = short_series;
     v.far = farrow && !fp64 && bd.farrow != nullptr;
@@ -1230,10 +1240,14 @@ Variant variant_of(const BandDev &bd, bool fp64, bool short_series, bool farrow,
     // per-segment weights, the 1024-point one either weight and every ordered pair as well; the
     // other forms (per-sample antenna functions: two spectra streams) run on the general path
     const bool plain = bd.weight == CCR_WEIGHT_AVE && !bd.allp && bd.pw == nullptr;
-    const bool wide_ok = bd.pw == nullptr && spectra_wide_ok(bd, fp64, kMaxLds);
+    // per-sample antenna functions: the wide kernel's two streams, written by the Farrow resampler
+    BandDev bw = bd;
+    bw.ps2 = bd.pw != nullptr ? 1 : 0;
+    const bool wide_ok = (bd.pw == nullptr || (streams && v.far && bd.pwf != nullptr)) && spectra_wide_ok(bw, fp64, kMaxLds);
     v.sp = plain && spectra_pairs_ok(bd, fp64, kMaxLds) && !(prefer_wide && wide_ok);
     v.wide = !v.sp && wide_ok;
     v.wallp = v.wide && bd.allp;
+    v.wps = v.wide && bd.pw != nullptr;
     v.DT = bd.D == 8 ? 8 : 0;
     v.window = bd.window;
     v.n_cheb = fp64 ? kCheb : bd.cheb_split;
@@ -1314,13 +1328,14 @@ ccr_status build_plan(ccr_ctx *c, bool fp64, int n_bands, const int *band_ids, v
         BandDev bd = band_dev(B);
         bd.far_stage = (int)c->opt_farrow_stage;
         cp.bands.push_back(bd);
-        const Variant v = variant_of(bd, fp64, B.short_series, c->opt_farrow != 0, bp.spectra != 0);
+        const Variant v = variant_of(bd, fp64, B.short_series, c->opt_farrow != 0, bp.spectra != 0, !bp.no_streams);
+        if (v.wps) cp.bands.back().ps2 = 1;
         const int res_t = v.far ? kFarTemplates : kResTemplates;  // templates per resampler workgroup
         if (std::find(variants.begin(), variants.end(), v) == variants.end()) variants.push_back(v);
         int64_t kc = bp.k_chunk > 0 ? bp.k_chunk : std::min<int64_t>(pl.n_seg, 256);
         kc = std::max<int64_t>(1, std::min<int64_t>(kc, pl.n_seg));
         const int nch = (int)((pl.n_seg + kc - 1) / kc);
-        const size_t y1 = (size_t)B.Q * pl.n_seg * pl.n_k * cs;
+        const size_t y1 = (size_t)B.Q * pl.n_seg * pl.n_k * cs * (v.wps ? 2 : 1);
         // two spectra streams per segment with per-sample weights; four partials per bin (the
         // stream sums) for every ordered pair
         const size_t F1 = (v.sp || v.wide) ? 0 : (size_t)B.Q * pl.n_seg * pl.n_f * cs * (bd.pw ? 2 : 1);
@@ -1362,7 +1377,7 @@ ccr_status build_plan(ccr_ctx *c, bool fp64, int n_bands, const int *band_ids, v
             q.F = F1 * nb;
             q.part = part1 * nb;
             q.coef = coef1 * nb;
-            q.lds = v.sp ? spectra_pairs_lds(bd) : (v.wide ? spectra_wide_lds(bd) : 0);
+            q.lds = v.sp ? spectra_pairs_lds(cp.bands.back()) : (v.wide ? spectra_wide_lds(cp.bands.back()) : 0);
             for (int st = 0; st < kStages; ++st) q.blk[st] = per_t[st] * nb;
             q.blk[kStResample] = per_t[kStResample] * ((nb + res_t - 1) / res_t);
             pend.push_back(q);
@@ -1490,7 +1505,7 @@ ccr_status run_rounds(ccr_ctx *c, const CallPlan &cp, size_t r0, size_t r1, bool
         } else if (r.v.wide) {
             LaunchTimer lt(c, 7, s, timing);
             HIP_OK(c, launch_spectra_wide_m(db, di, r.n, (int)r.blocks[kStSpectra], r.v.wns, r.v.wcols, r.v.wqm,
-                                            r.v.wallp, r.lds, ws.y, part, s));
+                                            r.v.wallp, r.v.wps, r.lds, ws.y, part, s));
         } else {
             {
                 LaunchTimer lt(c, 1, s, timing);
@@ -1753,6 +1768,7 @@ static ccr_status split_series_of(ccr_ctx *c, int band_id, int64_t template_inde
     bp.template_batch = 1;
     bp.round_templates = 1;
     bp.k_chunk = get_band(c, band_id)->plan.n_seg;  // one chunk: no partial sums to hold
+    bp.no_streams = true;                            // the series itself, not its weighted streams
     CallPlan cp;
     void *none = nullptr;
     ccr_status st = build_plan(c, false, 1, &band_id, &none, 1, 0, bp, cp);

@@ -118,6 +118,12 @@ struct BandDev {
     // per-sample antenna weights [Q][n_seg * n_k]: (a_r, b_r) / (sigma_K^2 sqrt(N_K)), or null
     // (per-segment weights: the two streams are hat a_K F and hat b_K F)
     const double2 *pw;
+    // the same weights in FP32, [Q][n_seg * n_k] (a_r, b_r) / (sigma_K^2 sqrt(N_K)), or null
+    const float2 *pwf;
+    // split path with per-sample weights on the wide spectra + pair-sum kernel: the resampler
+    // writes two series per detector, y a_r and y b_r (stream s of detector X at X 2 + s), that
+    // kernel transforms both
+    int ps2;
 };
 
 // One work item of a batched launch: a run of consecutive templates of one band.  A batched
@@ -202,7 +208,7 @@ size_t spectra_wide_lds(const BandDev &B);
 int spectra_wide_cols(const BandDev &B);
 // cols: spectra_wide_cols of the round's bands; q: their detector count (1-4, the same for all).
 hipError_t launch_spectra_wide_m(const BandDev *bands, const WorkItem *items, int n_items, int blocks, int ns,
-                                 int cols, int q, bool allp, size_t lds, const void *y, double *part,
+                                 int cols, int q, bool allp, bool ps, size_t lds, const void *y, double *part,
                                  hipStream_t stream);
 // z4: N_K <= 192, so the last 4 of the 16 input rows of each 256-point FFT are zero padding.
 hipError_t launch_spectra_pairs_m(const BandDev *bands, const WorkItem *items, int n_items, int blocks, int rounds,

@@ -782,7 +782,9 @@ __device__ __forceinline__ void resample_far_body(const BandDev &B, const double
             for (int i = 0; i < kFarPerWave; ++i) {
                 const int tb = tw0 + i;
                 if (tb >= t1) break;
-                float2 *yo = y + ((size_t)tb * B.Q + det) * nr + r0;
+                // the series, or with per-sample weights its two streams y a_r and y b_r
+                const int ns2 = B.ps2 ? 2 : 1;
+                float2 *yo = y + ((size_t)tb * B.Q + det) * ns2 * nr + r0;
                 const double *cf = coef + ((size_t)tb * B.n_work + w) * kCheb;
                 double cl[NC];
 #pragma unroll
@@ -793,7 +795,10 @@ __device__ __forceinline__ void resample_far_body(const BandDev &B, const double
                     if (c0 + 64 * p >= c1) break;
                     const unsigned so = (unsigned)(c0 + 64 * p + lane);  // sample index (32-bit offset from yo)
                     // samples in gaps: zero (their own execution mask)
-                    if (__builtin_amdgcn_inverse_ballot_w64(in_b[p] & ~m_b[p])) yo[so] = make_float2(0.f, 0.f);
+                    if (__builtin_amdgcn_inverse_ballot_w64(in_b[p] & ~m_b[p])) {
+                        yo[so] = make_float2(0.f, 0.f);
+                        if (B.ps2) yo[so + nr] = make_float2(0.f, 0.f);
+                    }
                     if (__builtin_amdgcn_inverse_ballot_w64(m_b[p])) {
                         int jr;
                         float dc, psi;
@@ -812,7 +817,14 @@ __device__ __forceinline__ void resample_far_body(const BandDev &B, const double
                                                              : make_float2(0.f, 0.f);
                         }
                         const float c = __builtin_amdgcn_cosf(psi), sn = __builtin_amdgcn_sinf(psi);
-                        yo[so] = make_float2(c * a.x - sn * a.y, sn * a.x + c * a.y);
+                        const float2 yv = make_float2(c * a.x - sn * a.y, sn * a.x + c * a.y);
+                        if (B.ps2) {
+                            const float2 wr = B.pwf[(size_t)det * nr + r0 + so];
+                            yo[so] = make_float2(yv.x * wr.x, yv.y * wr.x);
+                            yo[so + nr] = make_float2(yv.x * wr.y, yv.y * wr.y);
+                        } else {
+                            yo[so] = yv;
+                        }
                     }
                 }
             }
@@ -1518,17 +1530,19 @@ __device__ __forceinline__ void fft_wave<256>(float2 *v, float2 *fx, const WaveT
 }
 
 // Pair term of segment K for one bin of the spectra + pair-sum kernel: sum over detectors X of
-// the weighted products of F_XK with its partners, the window sums G_Y (spectra of the last R
-// segments, weighted by hat a and hat b: Ga, Gb) of the detectors the pair set joins to X
-// (CROSS: Y != X; SAME: Y = X) and, across detectors, the same-time partners Y > X (their
-// weighted spectra w_Y F_YK, summed from the last detector down).  Gamma^ave:
-// hat a_X Re[conj(F_X) H^a] + hat b_X Re[conj(F_X) H^b]; Gamma^circ (CIRC):
-// hat b_X Im[conj(F_X) H^a] - hat a_X Im[conj(F_X) H^b].  Every unordered pair enters once.
-template <int Q, int U, bool CROSS, bool SAME, bool CIRC>
-__device__ __forceinline__ float wide_pair_term(const float2 (&f)[Q], const float (&wa)[Q], const float (&wb)[Q],
-                                                const float2 (&Ga)[Q][U], const float2 (&Gb)[Q][U], int u) {
+// the products of F_XK's two streams with its partners', the window sums G_Y (the two streams of
+// the last R segments: Ga, Gb) of the detectors the pair set joins to X (CROSS: Y != X; SAME:
+// Y = X) and, across detectors, the same-time partners Y > X (summed from the last detector
+// down).  The streams of X are hat a_X F_X and hat b_X F_X (per-segment weights wa, wb), or with
+// per-sample antenna functions (PS) the two transforms fa_X, fb_X themselves.  Gamma^ave:
+// Re[conj(a_X) H^a] + Re[conj(b_X) H^b]; Gamma^circ (CIRC): Im[conj(b_X) H^a] - Im[conj(a_X) H^b].
+// Every unordered pair enters once.
+template <int Q, int U, bool CROSS, bool SAME, bool CIRC, bool PS>
+__device__ __forceinline__ float wide_pair_term(const float2 (&fa)[Q], const float2 (&fb)[Q], const float (&wa)[Q],
+                                                const float (&wb)[Q], const float2 (&Ga)[Q][U],
+                                                const float2 (&Gb)[Q][U], int u) {
     float st = 0.f;
-    float2 ta = make_float2(0.f, 0.f), tb = make_float2(0.f, 0.f);  // sum over Y > X of w_Y F_Y
+    float2 ta = make_float2(0.f, 0.f), tb = make_float2(0.f, 0.f);  // sum over Y > X of the streams
     // both pair kinds: every detector's window sum joins every X (summed once)
     float2 sa = Ga[0][u], sb = Gb[0][u];
     if constexpr (CROSS && SAME) {
@@ -1564,16 +1578,30 @@ __device__ __forceinline__ float wide_pair_term(const float2 (&f)[Q], const floa
             ha.x += ta.x; ha.y += ta.y;
             hb.x += tb.x; hb.y += tb.y;
         }
+        const float2 a = fa[X], b = PS ? fb[X] : fa[X];
         if constexpr (CIRC) {
-            st = fmaf(wb[X], f[X].x * ha.y - f[X].y * ha.x, st);
-            st = fmaf(-wa[X], f[X].x * hb.y - f[X].y * hb.x, st);
+            if constexpr (PS) {
+                st += (b.x * ha.y - b.y * ha.x) - (a.x * hb.y - a.y * hb.x);
+            } else {
+                st = fmaf(wb[X], a.x * ha.y - a.y * ha.x, st);
+                st = fmaf(-wa[X], a.x * hb.y - a.y * hb.x, st);
+            }
         } else {
-            st = fmaf(wa[X], f[X].x * ha.x + f[X].y * ha.y, st);
-            st = fmaf(wb[X], f[X].x * hb.x + f[X].y * hb.y, st);
+            if constexpr (PS) {
+                st += (a.x * ha.x + a.y * ha.y) + (b.x * hb.x + b.y * hb.y);
+            } else {
+                st = fmaf(wa[X], a.x * ha.x + a.y * ha.y, st);
+                st = fmaf(wb[X], a.x * hb.x + a.y * hb.y, st);
+            }
         }
         if constexpr (CROSS) {
-            ta.x = fmaf(wa[X], f[X].x, ta.x); ta.y = fmaf(wa[X], f[X].y, ta.y);
-            tb.x = fmaf(wb[X], f[X].x, tb.x); tb.y = fmaf(wb[X], f[X].y, tb.y);
+            if constexpr (PS) {
+                ta.x += a.x; ta.y += a.y;
+                tb.x += b.x; tb.y += b.y;
+            } else {
+                ta.x = fmaf(wa[X], a.x, ta.x); ta.y = fmaf(wa[X], a.y, ta.y);
+                tb.x = fmaf(wb[X], a.x, tb.x); tb.y = fmaf(wb[X], a.y, tb.y);
+            }
         }
     }
     return st;
@@ -1591,7 +1619,7 @@ struct SpwLayout {
     size_t off_fx, off_ring, off_pos, total;
 };
 
-__host__ __device__ inline SpwLayout spw_layout(int Q, int R, int ncol, int jmax, int ns) {
+__host__ __device__ inline SpwLayout spw_layout(int Q, int R, int ncol, int jmax, int ns, int streams) {
     SpwLayout L;
     L.slots = R + 1;
     L.ncol1 = ncol + 1;  // the last column of a ring row takes FFT outputs that are not output bins
@@ -1599,7 +1627,7 @@ __host__ __device__ inline SpwLayout spw_layout(int Q, int R, int ncol, int jmax
     L.off_fx = o;  // one FFT exchange buffer per wavefront (ns values, padded)
     o += (size_t)spw_waves(Q) * (ns + 64) * sizeof(float2);
     L.off_ring = o;
-    o += (size_t)L.slots * Q * L.ncol1 * sizeof(float2);
+    o += (size_t)L.slots * Q * streams * L.ncol1 * sizeof(float2);
     L.off_pos = o;
     o += (size_t)jmax * 64 * sizeof(int16_t);
     L.total = (o + 15) & ~(size_t)15;
@@ -1630,14 +1658,15 @@ __host__ __device__ inline SpwLayout spw_layout(int Q, int R, int ncol, int jmax
 //   partials are the chunk's stream sums G^a = sum hat a_XK F_XK and G^b (4 doubles a bin), which
 //   the finishing kernel combines.
 // U: bins of a class per lane (class size <= 128 U); Q: the band's detector count.
-template <int NS, int U, int Q, bool ALLP>
+template <int NS, int U, int Q, bool ALLP, bool PS>
 __device__ __forceinline__ void spectra_wide_body(const BandDev &B, const float2 *__restrict__ y, double *part,
                                                   int k_chunk, int n_chunks, int c, int p, int tb) {
     extern __shared__ __align__(16) unsigned char smem[];
     constexpr int V = NS / 64;  // FFT values a lane
     constexpr int W = spw_waves(Q);  // wavefronts
+    constexpr int S = PS ? 2 : 1;      // spectra streams per (detector, segment)
     const int n_k = B.n_k, R = B.R, N = B.n_fft, mask = B.nfft_mask;
-    const SpwLayout Ly = spw_layout(Q, R, B.wide_ncol, B.wide_jmax, NS);
+    const SpwLayout Ly = spw_layout(Q, R, B.wide_ncol, B.wide_jmax, NS, S);
     // the wavefront index, uniform within the wavefront (readfirstlane makes that known to the
     // compiler, so that per-wavefront addresses and buffer descriptors stay in scalar registers)
     const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
@@ -1652,7 +1681,7 @@ __device__ __forceinline__ void spectra_wide_body(const BandDev &B, const float2
 
     // FFT output m' = l + 64 J (J < jmax) of the rotated class: its ring column, or the spare one
     for (int e = threadIdx.x; e < jmax * 64; e += 64 * W) opos[e] = (int16_t)(ncol1 - 1);
-    for (int e = threadIdx.x; e < slots * Q * ncol1; e += 64 * W) ring[e] = make_float2(0.f, 0.f);
+    for (int e = threadIdx.x; e < slots * Q * S * ncol1; e += 64 * W) ring[e] = make_float2(0.f, 0.f);
     __syncthreads();
     for (int col = threadIdx.x; col < n_p; col += 64 * W) {
         const int mm = (B.bin_m[B.col_bin[cs + col]] - m0) & (NS - 1);
@@ -1698,25 +1727,24 @@ __device__ __forceinline__ void spectra_wide_body(const BandDev &B, const float2
     };
     const int lo = lower(Kh), hi = lower(K1);
     const int64_t nr = (int64_t)B.n_seg * n_k;
-    const float2 *ybase = y + (size_t)tb * Q * nr;
-    // this wavefront's detectors X = wv + W i (i < NJ); the input of a detector's next
-    // segment is loaded while the current one is transformed.  Buffer loads with the segment's
-    // n_k samples as the buffer range read zero past it (no branches, no zero padding in memory).
-    constexpr int NJ = (Q + W - 1) / W;
-    float2 nxt[NJ][V];
-    auto load = [&](int e, int i) {
-        const int X = wv + W * i;
-        const float2 *ys = ybase + (size_t)X * nr + (size_t)ld_uniform(B.seg_any, e) * n_k;
+    const float2 *ybase = y + (size_t)tb * Q * S * nr;
+    // this wavefront's transforms of a step: units j = S i + s, detector X = wv + W i (i < NJ;
+    // W divides Q, so X < Q), stream s (the series of stream s of detector X: X S + s); each
+    // unit's input is loaded while the previous unit is transformed.  Buffer loads with the
+    // segment's n_k samples as the buffer range read zero past it (no branches, no zero padding
+    // in memory).
+    constexpr int NJ = Q / W;
+    constexpr int NU = NJ * S;
+    float2 nxt[V];
+    auto load = [&](int e, int j) {
+        const int X = wv + W * (j / S);
+        const float2 *ys = ybase + (size_t)(X * S + j % S) * nr + (size_t)ld_uniform(B.seg_any, e) * n_k;
         const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc((void *)ys, (short)0, n_k * 8, 0x00020000);
 #pragma unroll
         for (int r = 0; r < V; ++r)
-            nxt[i][r] = __builtin_bit_cast(float2, __builtin_amdgcn_raw_buffer_load_b64(rs, (lane + 64 * r) * 8, 0, 0));
+            nxt[r] = __builtin_bit_cast(float2, __builtin_amdgcn_raw_buffer_load_b64(rs, (lane + 64 * r) * 8, 0, 0));
     };
-    if (lo < hi) {
-#pragma unroll
-        for (int i = 0; i < NJ; ++i)
-            if (wv + W * i < Q) load(lo, i);
-    }
+    if (lo < hi) load(lo, 0);
 
     float2 Ga[Q][U], Gb[Q][U];
     double acc[U];
@@ -1734,16 +1762,26 @@ __device__ __forceinline__ void spectra_wide_body(const BandDev &B, const float2
         const int K = ld_uniform(B.seg_any, e);
         // this wavefront's transforms of step e
 #pragma unroll
-        for (int i = 0; i < NJ; ++i) {
-            const int X = wv + W * i;
-            if (X >= Q) continue;
+        for (int j = 0; j < NU; ++j) {
+            const int X = wv + W * (j / S);
             float2 v[V];
 #pragma unroll
-            for (int r = 0; r < V; ++r) v[r] = cmul<float>(nxt[i][r], win[r]);
-            load(min(e + 1, hi - 1), i);  // unconditional (the last step reloads its own segment)
-            if (ld_uniform(B.seg_work, X * B.n_seg + K) < 0) continue;  // no data of detector X in K
+            for (int r = 0; r < V; ++r) v[r] = cmul<float>(nxt[r], win[r]);
+            // the next unit's input (unconditional: the last step's last unit reloads its own)
+            if (j + 1 < NU) load(e, j + 1);
+            else load(min(e + 1, hi - 1), 0);
+            float2 *row = ring + (((size_t)head * Q + X) * S + j % S) * ncol1;
+            if (ld_uniform(B.seg_work, X * B.n_seg + K) < 0) {
+                // no data of detector X in K: with per-sample streams the ring row is zeroed (they
+                // carry no weight of their own), else its weights are zero
+                if constexpr (PS) {
+#pragma unroll
+                    for (int J = 0; J < V; ++J)
+                        if (J < jmax) row[(cpos[J >> 1] >> (16 * (J & 1))) & 0xffffu] = make_float2(0.f, 0.f);
+                }
+                continue;
+            }
             fft_wave<NS>(v, fx, wtw, lane);
-            float2 *row = ring + ((size_t)head * Q + X) * ncol1;
 #pragma unroll
             for (int J = 0; J < V; ++J)
                 if (J < jmax) row[(cpos[J >> 1] >> (16 * (J & 1))) & 0xffffu] = v[J];
@@ -1765,24 +1803,36 @@ __device__ __forceinline__ void spectra_wide_body(const BandDev &B, const float2
         for (int u = 0; u < U; ++u) {
             const int col = wv * 64 + lane + 64 * W * u;
             if (wv * 64 + 64 * W * u >= n_p) break;  // uniform: no lane of this wavefront has a bin here
-            float2 *slot = ring + (size_t)head * Q * ncol1 + (col < n_p ? col : ncol1 - 1);
-            float2 f[Q];
+            float2 *slot = ring + (size_t)head * Q * S * ncol1 + (col < n_p ? col : ncol1 - 1);
+            float2 f[Q], g[Q];  // the step's spectra (stream a; g: stream b with per-sample streams)
 #pragma unroll
-            for (int X = 0; X < Q; ++X) f[X] = slot[X * ncol1];
+            for (int X = 0; X < Q; ++X) {
+                f[X] = slot[X * S * ncol1];
+                if constexpr (PS) g[X] = slot[(X * S + 1) * ncol1];
+            }
             const float ph = -(float)(((unsigned)kbc[u] * rB) & (unsigned)mask) * invN;  // revolutions
             const float cph = __builtin_amdgcn_cosf(ph), sph = __builtin_amdgcn_sinf(ph);
 #pragma unroll
             for (int X = 0; X < Q; ++X) {
                 f[X] = make_float2(f[X].x * cph - f[X].y * sph, f[X].x * sph + f[X].y * cph);
-                if (col < n_p) slot[X * ncol1] = f[X];
+                if (col < n_p) slot[X * S * ncol1] = f[X];
+                if constexpr (PS) {
+                    g[X] = make_float2(g[X].x * cph - g[X].y * sph, g[X].x * sph + g[X].y * cph);
+                    if (col < n_p) slot[(X * S + 1) * ncol1] = g[X];
+                }
             }
             if constexpr (ALLP) {
                 // this step's share of G^a and G^b: FP32 over the detectors, FP64 over steps
                 float2 ta = make_float2(0.f, 0.f), tb2 = make_float2(0.f, 0.f);
 #pragma unroll
                 for (int X = 0; X < Q; ++X) {
-                    ta.x = fmaf(wa[X], f[X].x, ta.x); ta.y = fmaf(wa[X], f[X].y, ta.y);
-                    tb2.x = fmaf(wb[X], f[X].x, tb2.x); tb2.y = fmaf(wb[X], f[X].y, tb2.y);
+                    if constexpr (PS) {
+                        ta.x += f[X].x; ta.y += f[X].y;
+                        tb2.x += g[X].x; tb2.y += g[X].y;
+                    } else {
+                        ta.x = fmaf(wa[X], f[X].x, ta.x); ta.y = fmaf(wa[X], f[X].y, ta.y);
+                        tb2.x = fmaf(wb[X], f[X].x, tb2.x); tb2.y = fmaf(wb[X], f[X].y, tb2.y);
+                    }
                 }
                 sa[u].x += (double)ta.x; sa[u].y += (double)ta.y;
                 sb[u].x += (double)tb2.x; sb[u].y += (double)tb2.y;
@@ -1791,20 +1841,25 @@ __device__ __forceinline__ void spectra_wide_body(const BandDev &B, const float2
             if (count_it) {
                 float st;
                 switch (mode) {  // uniform
-                    case 1: st = wide_pair_term<Q, U, true, false, false>(f, wa, wb, Ga, Gb, u); break;
-                    case 2: st = wide_pair_term<Q, U, false, true, false>(f, wa, wb, Ga, Gb, u); break;
-                    case 3: st = wide_pair_term<Q, U, true, true, false>(f, wa, wb, Ga, Gb, u); break;
-                    case 5: st = wide_pair_term<Q, U, true, false, true>(f, wa, wb, Ga, Gb, u); break;
-                    case 6: st = wide_pair_term<Q, U, false, true, true>(f, wa, wb, Ga, Gb, u); break;
-                    case 7: st = wide_pair_term<Q, U, true, true, true>(f, wa, wb, Ga, Gb, u); break;
+                    case 1: st = wide_pair_term<Q, U, true, false, false, PS>(f, g, wa, wb, Ga, Gb, u); break;
+                    case 2: st = wide_pair_term<Q, U, false, true, false, PS>(f, g, wa, wb, Ga, Gb, u); break;
+                    case 3: st = wide_pair_term<Q, U, true, true, false, PS>(f, g, wa, wb, Ga, Gb, u); break;
+                    case 5: st = wide_pair_term<Q, U, true, false, true, PS>(f, g, wa, wb, Ga, Gb, u); break;
+                    case 6: st = wide_pair_term<Q, U, false, true, true, PS>(f, g, wa, wb, Ga, Gb, u); break;
+                    case 7: st = wide_pair_term<Q, U, true, true, true, PS>(f, g, wa, wb, Ga, Gb, u); break;
                     default: st = 0.f;
                 }
                 acc[u] += (double)st;
             }
 #pragma unroll
             for (int X = 0; X < Q; ++X) {
-                Ga[X][u].x = fmaf(wa[X], f[X].x, Ga[X][u].x); Ga[X][u].y = fmaf(wa[X], f[X].y, Ga[X][u].y);
-                Gb[X][u].x = fmaf(wb[X], f[X].x, Gb[X][u].x); Gb[X][u].y = fmaf(wb[X], f[X].y, Gb[X][u].y);
+                if constexpr (PS) {
+                    Ga[X][u].x += f[X].x; Ga[X][u].y += f[X].y;
+                    Gb[X][u].x += g[X].x; Gb[X][u].y += g[X].y;
+                } else {
+                    Ga[X][u].x = fmaf(wa[X], f[X].x, Ga[X][u].x); Ga[X][u].y = fmaf(wa[X], f[X].y, Ga[X][u].y);
+                    Gb[X][u].x = fmaf(wb[X], f[X].x, Gb[X][u].x); Gb[X][u].y = fmaf(wb[X], f[X].y, Gb[X][u].y);
+                }
             }
         }
         head = head + 1 == slots ? 0 : head + 1;
@@ -1823,7 +1878,7 @@ __device__ __forceinline__ void spectra_wide_body(const BandDev &B, const float2
                     wta[X] = w2.x;
                     wtb[X] = w2.y;
                 }
-                const float2 *rowt = ring + (size_t)tail * Q * ncol1;
+                const float2 *rowt = ring + (size_t)tail * Q * S * ncol1;
 #pragma unroll
                 for (int u = 0; u < U; ++u) {
                     if (wv * 64 + 64 * W * u >= n_p) break;
@@ -1831,9 +1886,15 @@ __device__ __forceinline__ void spectra_wide_body(const BandDev &B, const float2
                     const float2 *gp = rowt + (col < n_p ? col : ncol1 - 1);
 #pragma unroll
                     for (int X = 0; X < Q; ++X) {
-                        const float2 g = gp[X * ncol1];
-                        Ga[X][u].x = fmaf(-wta[X], g.x, Ga[X][u].x); Ga[X][u].y = fmaf(-wta[X], g.y, Ga[X][u].y);
-                        Gb[X][u].x = fmaf(-wtb[X], g.x, Gb[X][u].x); Gb[X][u].y = fmaf(-wtb[X], g.y, Gb[X][u].y);
+                        const float2 ga = gp[X * S * ncol1];
+                        if constexpr (PS) {
+                            const float2 gb = gp[(X * S + 1) * ncol1];
+                            Ga[X][u].x -= ga.x; Ga[X][u].y -= ga.y;
+                            Gb[X][u].x -= gb.x; Gb[X][u].y -= gb.y;
+                        } else {
+                            Ga[X][u].x = fmaf(-wta[X], ga.x, Ga[X][u].x); Ga[X][u].y = fmaf(-wta[X], ga.y, Ga[X][u].y);
+                            Gb[X][u].x = fmaf(-wtb[X], ga.x, Gb[X][u].x); Gb[X][u].y = fmaf(-wtb[X], ga.y, Gb[X][u].y);
+                        }
                     }
                 }
                 tail = tail + 1 == slots ? 0 : tail + 1;
@@ -2491,7 +2552,7 @@ k_spectra_pairs_m(const BandDev *__restrict__ bands, const WorkItem *__restrict_
 // dispatcher hands workgroups to the 8 XCDs in turn, so block l runs on XCD l mod 8: the P class
 // workgroups of one (template, chunk) group are given indices with equal l mod 8, which puts
 // them on one XCD, where they read the group's resampled series through that XCD's L2.
-template <int NS, int U, int Q, bool ALLP>
+template <int NS, int U, int Q, bool ALLP, bool PS>
 __global__ void __launch_bounds__(64 * spw_waves(Q))
 k_spectra_wide_m(const BandDev *__restrict__ bands, const WorkItem *__restrict__ items, int n_items,
                  const float2 *__restrict__ y, double *__restrict__ part) {
@@ -2509,7 +2570,7 @@ k_spectra_wide_m(const BandDev *__restrict__ bands, const WorkItem *__restrict__
         g = (G >> 3) * 8 + (l - full) / P;
         p = (l - full) % P;
     }
-    spectra_wide_body<NS, U, Q, ALLP>(B, y + it.y_off, part + it.part_off, it.k_chunk, it.n_chunks, g % it.n_chunks, p,
+    spectra_wide_body<NS, U, Q, ALLP, PS>(B, y + it.y_off, part + it.part_off, it.k_chunk, it.n_chunks, g % it.n_chunks, p,
                                    g / it.n_chunks);
 }
 
@@ -2696,7 +2757,9 @@ hipError_t launch_zero(void *p, size_t bytes, hipStream_t stream) {
 
 size_t spectra_pairs_lds(const BandDev &B) { return spair_layout(B.Q, B.n_f, B.R, B.n_fft).total; }
 
-size_t spectra_wide_lds(const BandDev &B) { return spw_layout(B.Q, B.R, B.wide_ncol, B.wide_jmax, B.n_s).total; }
+size_t spectra_wide_lds(const BandDev &B) {
+    return spw_layout(B.Q, B.R, B.wide_ncol, B.wide_jmax, B.n_s, B.ps2 ? 2 : 1).total;
+}
 
 int spectra_wide_cols(const BandDev &B) {
     const int per = 64 * spw_waves(B.Q);  // bin columns a workgroup covers per U
@@ -2803,11 +2866,11 @@ hipError_t launch_spectra_pairs_m(const BandDev *bands, const WorkItem *items, i
     return hipGetLastError();
 }
 
-template <int NS, bool ALLP>
+template <int NS, bool ALLP, bool PS>
 static void launch_spectra_wide_u(const BandDev *bands, const WorkItem *items, int n_items, int blocks, int cols,
                                   int q, size_t lds, const void *y, double *part, hipStream_t stream) {
 #define CCR_WIDE(U_, Q_)                                                                                            \
-    hipLaunchKernelGGL((k_spectra_wide_m<NS, U_, Q_, ALLP>), dim3(blocks), dim3(64 * spw_waves(Q_)), lds, stream, bands, \
+    hipLaunchKernelGGL((k_spectra_wide_m<NS, U_, Q_, ALLP, PS>), dim3(blocks), dim3(64 * spw_waves(Q_)), lds, stream, bands, \
                        items, n_items, (const float2 *)y, part)
 #define CCR_WIDE_Q(U_)          \
     do {                        \
@@ -2824,13 +2887,15 @@ static void launch_spectra_wide_u(const BandDev *bands, const WorkItem *items, i
 }
 
 hipError_t launch_spectra_wide_m(const BandDev *bands, const WorkItem *items, int n_items, int blocks, int ns,
-                                 int cols, int q, bool allp, size_t lds, const void *y, double *part,
+                                 int cols, int q, bool allp, bool ps, size_t lds, const void *y, double *part,
                                  hipStream_t stream) {
     if (blocks == 0) return hipSuccess;
-#define CCR_WIDE_NS(NS_)                                                                                     \
-    do {                                                                                                     \
-        if (allp) launch_spectra_wide_u<NS_, true>(bands, items, n_items, blocks, cols, q, lds, y, part, stream); \
-        else launch_spectra_wide_u<NS_, false>(bands, items, n_items, blocks, cols, q, lds, y, part, stream);   \
+#define CCR_WIDE_NS(NS_)                                                                                          \
+    do {                                                                                                          \
+        if (allp && ps) launch_spectra_wide_u<NS_, true, true>(bands, items, n_items, blocks, cols, q, lds, y, part, stream); \
+        else if (allp) launch_spectra_wide_u<NS_, true, false>(bands, items, n_items, blocks, cols, q, lds, y, part, stream); \
+        else if (ps) launch_spectra_wide_u<NS_, false, true>(bands, items, n_items, blocks, cols, q, lds, y, part, stream); \
+        else launch_spectra_wide_u<NS_, false, false>(bands, items, n_items, blocks, cols, q, lds, y, part, stream); \
     } while (0)
     if (ns == 1024) CCR_WIDE_NS(1024);
     else if (ns == 512) CCR_WIDE_NS(512);

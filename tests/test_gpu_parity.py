@@ -277,6 +277,11 @@ WEIGHTED = {
     "all_1024_lag1": (4, 0, False, 2, 1, 0.3, "1024"),
     "all_circ_1024_q3": (4, 1, False, 3, 2, 0.3, "1024"),
     "ps_all_1024": (4, 0, True, 2, 1, 0.3, "1024"),
+    "ps_circ_1024_q3": (3, 1, True, 3, 2, 0.3, "1024"),
+    "ps_ave_1024_lag3": (3, 0, True, 2, 3, 0.2, "1024"),
+    "ps_same_1024_q1": (2, 0, True, 1, 3, 0.2, "1024"),
+    "ps_all_circ_256_q3": (4, 1, True, 3, 1, 0.2, "256"),
+    "ps_cross_256_q4": (1, 0, True, 4, 1, 0.2, "256"),
 }
 
 
@@ -302,7 +307,8 @@ def test_weighted_pair_sums(ccr, case):
     per segment), alone and combined, on 128-, 256- and 1024-point segments with gaps, against
     the oracle's stream form; FP64 and split, chunks of 5 segments with their halo, the fused
     option set.  The split path runs the spectra + pair-sum kernel of 256- to 1024-point segments
-    for both weights and all pairs with per-segment weights, the general kernels otherwise."""
+    for both weights, all pairs and per-sample antenna functions (the resampler writes the two
+    weighted series, the kernel transforms both; 1-4 detectors), the general kernels otherwise."""
     pairs, weight, per_sample, q, R, gaps, shape = WEIGHTED[case]
     ds = weighted_dataset(pairs, weight, per_sample, q, R, gaps, shape)
     o = oracle.Oracle(ds)
@@ -322,7 +328,7 @@ def test_weighted_pair_sums(ccr, case):
         r64b = ctx.compute_rho(bid, prec=ccr.PREC_FP64)
         r32b = ctx.compute_rho(bid, prec=ccr.PREC_SPLIT, out_fp64=False)
     ns = info["n_s"]
-    wide = ns in (256, 512, 1024) and not per_sample
+    wide = ns in (256, 512, 1024)  # per-sample antenna functions there too (two streams)
     assert kt["spectra_pairs"][1] == 0, kt
     assert (kt["spectra_wide"][1] > 0) == wide and (kt["pairs"][1] > 0) != wide, kt
     e64, e32 = rho_err(r64, ref), rho_err(r32, ref)
