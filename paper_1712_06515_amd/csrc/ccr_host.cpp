@@ -1272,7 +1272,7 @@ int64_t stage_max_blocks(const Variant &v, int st) {
     int threads = 64;
     if (st == kStTimebase) threads = tb_entries(v.n_cheb) * v.n_cheb;
     else if (st == kStResample) threads = v.far ? 256 : 64;
-    else if (st == kStSpectra) threads = v.sp ? 64 : (v.wide ? 128 : (v.reg16 ? 128 : spectra_threads(v.n_s)));
+    else if (st == kStSpectra) threads = v.sp ? 64 : (v.wide ? 64 * (v.wqm == 4 ? 2 : v.wqm) : (v.reg16 ? 128 : spectra_threads(v.n_s)));
     else if (st == kStPairs) threads = kPairsThreads;
     else if (st == kStFinish) threads = kFinishThreads;
     return std::min<int64_t>(kMaxBlocks, (((int64_t)1 << 32) - 1) / threads);

@@ -1657,7 +1657,7 @@ __host__ __device__ inline SpwLayout spw_layout(int Q, int R, int ncol, int jmax
 //   from the same window sums.  ALLP (every ordered pair, autos included): no windows; the
 //   partials are the chunk's stream sums G^a = sum hat a_XK F_XK and G^b (4 doubles a bin), which
 //   the finishing kernel combines.
-// U: bins of a class per lane (class size <= 128 U); Q: the band's detector count.
+// U: bins of a class per lane (class size <= 64 W U, W = spw_waves(Q)); Q: the band's detector count.
 template <int NS, int U, int Q, bool ALLP, bool PS>
 __device__ __forceinline__ void spectra_wide_body(const BandDev &B, const float2 *__restrict__ y, double *part,
                                                   int k_chunk, int n_chunks, int c, int p, int tb) {
@@ -2761,14 +2761,18 @@ size_t spectra_wide_lds(const BandDev &B) {
     return spw_layout(B.Q, B.R, B.wide_ncol, B.wide_jmax, B.n_s, B.ps2 ? 2 : 1).total;
 }
 
+// Bin columns of a class per lane: 1, 2 or 4, and 8 with one detector (one wavefront a
+// workgroup, so that a class of up to 512 bins still fits).
+static int spw_max_cols(int q) { return q == 1 ? 8 : 4; }
+
 int spectra_wide_cols(const BandDev &B) {
     const int per = 64 * spw_waves(B.Q);  // bin columns a workgroup covers per U
-    return B.wide_ncol <= per ? 1 : (B.wide_ncol <= 2 * per ? 2 : 4);
+    return B.wide_ncol <= per ? 1 : (B.wide_ncol <= 2 * per ? 2 : (B.wide_ncol <= 4 * per ? 4 : 8));
 }
 
 bool spectra_wide_ok(const BandDev &B, bool fp64, size_t limit) {
     return !fp64 && (B.n_s == 1024 || B.n_s == 512 || B.n_s == 256) && B.nfft_mask != 0 && B.bins_unique &&
-           B.Q >= 1 && B.Q <= 4 && B.wide_ncol <= 4 * 64 * spw_waves(B.Q) && B.wide_jmax >= 1 &&
+           B.Q >= 1 && B.Q <= 4 && B.wide_ncol <= spw_max_cols(B.Q) * 64 * spw_waves(B.Q) && B.wide_jmax >= 1 &&
            B.wide_jmax <= B.n_s / 64 &&
            B.cls_m0 != nullptr && spectra_wide_lds(B) <= limit;
 }
@@ -2881,7 +2885,8 @@ static void launch_spectra_wide_u(const BandDev *bands, const WorkItem *items, i
     } while (0)
     if (cols <= 1) CCR_WIDE_Q(1);
     else if (cols <= 2) CCR_WIDE_Q(2);
-    else CCR_WIDE_Q(4);
+    else if (cols <= 4) CCR_WIDE_Q(4);
+    else if (q == 1) CCR_WIDE(8, 1);  // spectra_wide_ok admits 8 columns a lane for one detector only
 #undef CCR_WIDE_Q
 #undef CCR_WIDE
 }

@@ -17,7 +17,7 @@ length and N_f its output bins; N_orb is the number of orbital templates of the 
 a nonnegative least-squares fit of the relative residuals.  The paper fits its constants
 separately below and above N_FFT = 2^18, where its CPU FFT slows down; on this GPU the cost per
 unit changes with the kernel that computes the segment spectra and pair sums (one fused kernel
-for 256-point segments, one for 1024-point segments, the general staged kernels otherwise), so
+for 256-point segments, one for 256- to 1024-point segments, the general staged kernels otherwise), so
 the constants are fitted per kernel path (a path with fewer than 4 measurements takes the fit
 over all of them).
 
@@ -76,7 +76,7 @@ def _fit_one(X, t):
     }
 
 
-PATHS = ("fused256", "fused1024", "general")
+PATHS = ("fused256", "wide", "general")
 
 
 def fit(rows):
@@ -169,7 +169,7 @@ def run_sweep(n_orb=2048, repeats=3, prec=1, progress=print):
             ctx.set_option("timing", 1)
             ctx.compute_rho(bid, prec=prec, out_fp64=False, outputs=[out.data_ptr()])
             kt = ctx.kernel_times(reset=True)
-            path = ("fused256" if kt["spectra_pairs"][1] else "fused1024" if kt["spectra_wide"][1] else "general")
+            path = ("fused256" if kt["spectra_pairs"][1] else "wide" if kt["spectra_wide"][1] else "general")
         row = dict(config=c, n_orb=len(tm), n_fft=int(info["n_fft"]), n_f=int(info["n_f"]), n_k=int(info["n_k"]),
                    n_seg=int(info["n_seg"]), seconds=best, path=path,
                    features=[float(v) for v in features(info, len(tm), c["D"])])

@@ -401,6 +401,49 @@ def test_spectra_wide_512_256(ccr, case):
     assert e64 < TOL64 and e32 < TOL32
 
 
+WIDE_ONE_DET = {
+    # (T_short, f_band, max lag, pair set, weight, per-sample antenna functions): one detector,
+    # 1024-point segments, classes of 371-429 bins (more than the 256 that four bin columns a
+    # lane of one wavefront cover: eight columns a lane)
+    "same_ave_429": (1000.0, 0.3, 2, 2, 0, False),
+    "same_circ_371": (1440.0, 0.3, 1, 2, 1, False),
+    "all_ave_429": (600.0, 0.5, 2, 4, 0, False),
+    "same_ps_429": (1000.0, 0.3, 2, 2, 0, True),
+}
+
+
+@pytest.mark.parametrize("case", sorted(WIDE_ONE_DET))
+def test_spectra_wide_one_detector_wide_classes(ccr, case):
+    """The spectra + pair-sum kernel with one detector and more than 256 bins in a residue class
+    (up to 8 bin columns a lane): same-detector pairs at lags 1-2, both weights, every ordered pair
+    with autos, per-sample antenna functions; 30 % gaps, chunks with their halo; FP64 (general
+    path) and split against the oracle (Sec. III.B.1 pairs, eq. final-formatted-rho)."""
+    ts, fb, R, pairs, weight, per_sample = WIDE_ONE_DET[case]
+    cfg = small_config(q=1, n_seg=26, t_short=ts, f_min=400.0, f_band=fb, max_lag=R, pairs=pairs,
+                       a_p_max=2.0, gap_fraction=0.3,
+                       templates=dict(a_p=(1.0, 2.0, 2), t_asc=(-200.0, 200.0, 2), period=[68023.70]),
+                       injections=[dict(f0=400.0 + 0.45 * fb, a_p=1.3, t_asc_off=0.0, period=68023.7, h0=0.3,
+                                        cosi=0.7, psi=0.4, phi0=2.0)])
+    cfg["band"]["weight"] = weight
+    ds = synth.make_dataset(cfg, sigma_wander=0.2, per_sample_antenna=per_sample)
+    ref = oracle.Oracle(ds).rho(ds.templates)
+    with ccr.Context(ds.sky, device=0) as ctx:
+        ctx.set_option("timing", 1)
+        ctx.set_option("k_chunk", 7)
+        bid = ctx.load(ds)
+        info = ctx.band_info(bid)
+        assert info["n_s"] == 1024 and info["n_f"] / info["P"] > 256, info
+        r64 = ctx.compute_rho(bid, prec=ccr.PREC_FP64)
+        ctx.kernel_times(reset=True)
+        r32 = ctx.compute_rho(bid, prec=ccr.PREC_SPLIT, out_fp64=False)
+        kt = ctx.kernel_times(reset=True)
+    assert kt["spectra_wide"][1] > 0, kt
+    e64, e32 = rho_err(r64, ref), rho_err(r32, ref)
+    print(f"one detector {case}: n_f {info['n_f']} P {info['P']} fp64 {e64:.2e} split {e32:.2e} "
+          f"max|rho| {np.abs(ref).max():.2f}")
+    assert e64 < TOL64 and e32 < TOL32
+
+
 def test_tiny_workload_full(ccr):
     """2 detectors, 2 days, T_short 360 s, 0.25 Hz at 100 Hz, 64 templates, same-time pairs."""
     ds = synth.make_dataset(synth.config("tiny"))

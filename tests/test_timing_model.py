@@ -42,9 +42,9 @@ def test_fit_recovers_known_constants():
                     n_fft=ns * int(rng.choice([1, 2, 4, 8, 16])))
         x = tmod.features(info, 256, c["D"])
         rows.append(dict(features=list(x), seconds=float(x @ tau) * (1 + 0.02 * rng.standard_normal()),
-                         path="general" if len(rows) % 8 else "fused1024"))
+                         path="general" if len(rows) % 8 else "wide"))
     m = tmod.fit(rows)
-    assert m["fused256"] is None and m["fused1024"] is not None
+    assert m["fused256"] is None and m["wide"] is not None
     low = m["general"]
     for i, n in enumerate(tmod.NAMES):
         assert abs(low["tau"][n] - tau[i]) < max(3 * low["sigma"][n], 1e-12)
