@@ -19,6 +19,9 @@
 namespace ccr {
 namespace {
 
+// Two 32-bit lanes: the data operand of the 64-bit buffer store builtin.
+typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
+
 // ------------------------------------------------------------------ complex helpers
 template <typename T> struct C2;
 template <> struct C2<float> { using type = float2; };
@@ -790,14 +793,21 @@ __device__ __forceinline__ void resample_far_body(const BandDev &B, const double
 #pragma unroll
                 for (int k = 0; k < NC; ++k) cl[k] = cf[k];
                 cl[0] = uniform_f64(cl[0] - an.D_a);  // once per template, kept in scalar registers
+                // buffer stores: a uniform resource per stream and the sample's byte offset (no
+                // 64-bit address arithmetic per pass); the range is the segment's n_k samples
+                const __amdgpu_buffer_rsrc_t yb0 = __builtin_amdgcn_make_buffer_rsrc(yo, (short)0, B.n_k * 8, 0x00020000);
+                const __amdgpu_buffer_rsrc_t yb1 = __builtin_amdgcn_make_buffer_rsrc(yo + nr, (short)0, B.n_k * 8, 0x00020000);
+                auto put = [](const __amdgpu_buffer_rsrc_t &rs, unsigned idx, float2 v) {
+                    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2, v), rs, (int)(idx * 8u), 0, 0);
+                };
 #pragma unroll
                 for (int p = 0; p < kPasses; ++p) {
                     if (c0 + 64 * p >= c1) break;
                     const unsigned so = (unsigned)(c0 + 64 * p + lane);  // sample index (32-bit offset from yo)
                     // samples in gaps: zero (their own execution mask)
                     if (__builtin_amdgcn_inverse_ballot_w64(in_b[p] & ~m_b[p])) {
-                        yo[so] = make_float2(0.f, 0.f);
-                        if (B.ps2) yo[so + nr] = make_float2(0.f, 0.f);
+                        put(yb0, so, make_float2(0.f, 0.f));
+                        if (B.ps2) put(yb1, so, make_float2(0.f, 0.f));
                     }
                     if (__builtin_amdgcn_inverse_ballot_w64(m_b[p])) {
                         int jr;
@@ -820,10 +830,10 @@ __device__ __forceinline__ void resample_far_body(const BandDev &B, const double
                         const float2 yv = make_float2(c * a.x - sn * a.y, sn * a.x + c * a.y);
                         if (B.ps2) {
                             const float2 wr = B.pwf[(size_t)det * nr + r0 + so];
-                            yo[so] = make_float2(yv.x * wr.x, yv.y * wr.x);
-                            yo[so + nr] = make_float2(yv.x * wr.y, yv.y * wr.y);
+                            put(yb0, so, make_float2(yv.x * wr.x, yv.y * wr.x));
+                            put(yb1, so, make_float2(yv.x * wr.y, yv.y * wr.y));
                         } else {
-                            yo[so] = yv;
+                            put(yb0, so, yv);
                         }
                     }
                 }
