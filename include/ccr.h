@@ -240,9 +240,9 @@ ccr_status ccr_set_weights(ccr_ctx *ctx, int band_id, int det, int64_t n_seg, co
 ccr_status ccr_set_antenna(ccr_ctx *ctx, int band_id, int det, int64_t n, const double *a, const double *b);
 
 /* Orbital templates of a band (the Doppler parameters lambda of Sec. II.A.2, circular orbit,
- * eq. tau-equation): n triples (a_p [s], T_asc [s after epoch], P [s]).  a_p >= 0, P > 0, all
- * finite; otherwise CCR_EINVAL and the band keeps its previous templates.  Replaces the band's
- * template list (copied). */
+ * eq. tau-equation): n >= 1 triples (a_p [s], T_asc [s after epoch], P [s]).  a_p >= 0, P > 0,
+ * all finite; otherwise (or n < 1, or a null array) CCR_EINVAL and the band keeps its previous
+ * templates.  Replaces the band's template list (copied). */
 ccr_status ccr_set_templates(ccr_ctx *ctx, int band_id, int64_t n, const double *a_p,
                              const double *t_asc, const double *period);
 

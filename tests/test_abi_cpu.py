@@ -148,6 +148,8 @@ def test_validation_errors(lib):
     # templates
     assert err(ctx.set_templates, bid, np.array([[1.0, 0.0, -5.0]])) == ccr.EINVAL
     assert err(ctx.set_templates, bid, np.array([[-1.0, 0.0, 68023.7]])) == ccr.EINVAL
+    assert err(ctx.set_templates, bid, np.zeros((0, 3))) == ccr.EINVAL  # no templates
+    assert err(ctx.set_templates, bid, np.zeros((0, 5))) == ccr.EINVAL
     # options
     assert err(ctx.set_option, "no_such_option", 1) == ccr.EUNSUP
     # band fields
