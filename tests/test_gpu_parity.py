@@ -781,8 +781,8 @@ def test_multiband_full_size_one_call(ccr):
 
 def test_graph_capture_replays(ccr, multiband_small):
     """With option graph = 1 a compute call is captured once and replayed: every replay, with
-    eager work and synchronisations between them, equals the eager result bitwise; changing the
-    templates re-captures."""
+    eager work and synchronisations between them, equals the eager result bitwise; a fused call
+    that grows the workspace, and new templates, make the next call re-capture."""
     import torch
     dss = multiband_small[:3]
     with ccr.Context(dss[0].sky, device=0) as ctx:
@@ -799,6 +799,23 @@ def test_graph_capture_replays(ccr, multiband_small):
             for o, e in zip(outs, eager):
                 assert np.array_equal(o.cpu().numpy(), e), rep
             ctx.compute_rho(ids[0], prec=ccr.PREC_FP64)  # eager work between replays
+        # a fused call that needs a larger workspace moves it: the next call re-captures instead
+        # of replaying launches that hold the old buffers
+        ctx.set_option("fused", 1)
+        ctx.set_option("timing", 1)
+        big = ctx.load(dss[0], templates=dss[0].templates[:48])
+        ctx.kernel_times(reset=True)
+        ctx.compute_rho(big, prec=ccr.PREC_SPLIT, out_fp64=False)
+        assert ctx.kernel_times(reset=True)["fused"][1] > 0  # the fused kernel ran
+        ctx.set_option("timing", 0)
+        ctx.set_option("fused", 0)
+        for o in outs:
+            o.fill_(float("nan"))
+        torch.cuda.synchronize()
+        ctx.compute_rho(ids, prec=ccr.PREC_SPLIT, out_fp64=False, outputs=[o.data_ptr() for o in outs])
+        ctx.sync()
+        for o, e in zip(outs, eager):
+            assert np.array_equal(o.cpu().numpy(), e)
         ctx.set_templates(ids[1], dss[1].templates[10:16])
         for o in outs:
             o.fill_(float("nan"))
