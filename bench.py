@@ -30,7 +30,7 @@ sys.path.insert(0, ROOT)
 METRIC = "ρ evaluations (templates×freq bins)/s, FP32-batched vs plain FP64 at ≤1e-4 rel err"
 HBM_PEAK_GBS = 8000.0
 # MI355X FP32 vector peak (published).  It counts packed FP32 (two lanes of arithmetic per
-# instruction); this build compiles without packed FP32, so its kernels can reach at most half.
+# instruction); the library is compiled without packed FP32, so its kernels can reach at most half.
 FP32_PEAK_TFLOPS = 157.3
 
 WORKLOADS = {
