@@ -1623,6 +1623,12 @@ __device__ __forceinline__ float wide_pair_term(const float2 (&fa)[Q], const flo
 // columns) w 64 + l + 64 W u.
 __host__ __device__ constexpr int spw_waves(int q) { return q == 4 ? 2 : q; }
 
+// Segments per step of that kernel (transformed together, then their pair sums in order: one
+// pair of barriers a step).  Two for 1024-point segments (2 % faster on the 240-day workload,
+// the ring's extra slot still leaves four workgroups a CU); one for shorter ones, where two to
+// eight measured 1-10 % slower on the 64-band workload.
+__host__ __device__ constexpr int spw_segs(int ns) { return ns == 1024 ? 2 : 1; }
+
 // LDS of the spectra + pair-sum kernel for ns-point segments (bytes).
 struct SpwLayout {
     int slots, ncol1;
@@ -1631,7 +1637,7 @@ struct SpwLayout {
 
 __host__ __device__ inline SpwLayout spw_layout(int Q, int R, int ncol, int jmax, int ns, int streams) {
     SpwLayout L;
-    L.slots = R + 1;
+    L.slots = R + spw_segs(ns);  // the window's R segments and a step's new ones
     L.ncol1 = ncol + 1;  // the last column of a ring row takes FFT outputs that are not output bins
     size_t o = 0;
     L.off_fx = o;  // one FFT exchange buffer per wavefront (ns values, padded)
@@ -1651,8 +1657,9 @@ __host__ __device__ inline SpwLayout spw_layout(int Q, int R, int ncol, int jmax
 //   seg_any) and each detector with data there, the zero-padded segment is multiplied by
 //   W_N^(q s), q = p + P m0 (class p, its bins rotated so that the class's output indices
 //   m0 .. m0 + span - 1 land on FFT outputs 0 .. span - 1), transformed by fft_wave<NS>, and its
-//   class-p bins are written to a ring of R + 1 spectra in LDS.  Each wavefront loads the input
-//   of its next transform while it computes the current one.
+//   class-p bins are written to a ring of R + TS spectra in LDS (TS = spw_segs(NS) segments a
+//   step).  Each wavefront loads the input of its next transform while it computes the current
+//   one.
 //   Pair sum: each spectrum is rotated by Phi_in = exp(-2 pi i (kbar r_B mod N) / N) (the phase
 //   reference after eq. phi-out-eq, absolute, so a pair's lag phase is the product of its two
 //   rotations), then the pairs whose later member is segment K enter: against the window sums
@@ -1660,9 +1667,10 @@ __host__ __device__ inline SpwLayout spw_layout(int Q, int R, int ncol, int jmax
 //   Y != X; same-detector pairs: Y = X) and, across detectors, the same-time partners Y > X.
 //   Each unordered pair of the pair set therefore enters once.  The window sums are kept in
 //   registers: a spectrum is added after its own step and subtracted when its segment falls R
-//   segments behind the next one.  Pair products of a step are summed in FP32, steps in FP64;
-//   one partial per (template, chunk, bin).  Two barriers a step: after the transforms (the ring
-//   holds the step's spectra) and after the pair sums (a ring slot is free again).
+//   segments behind the next one.  Pair products of a segment are summed in FP32, segments in
+//   FP64; one partial per (template, chunk, bin).  Two barriers a step: after the transforms of
+//   its TS segments (the ring holds their spectra) and after their pair sums, taken segment by
+//   segment (the step's ring slots are free again).
 //   Gamma^circ (B.weight): the pair term is (hat b_K hat a_L - hat a_K hat b_L) Im[conj(F_K) F_L],
 //   from the same window sums.  ALLP (every ordered pair, autos included): no windows; the
 //   partials are the chunk's stream sums G^a = sum hat a_XK F_XK and G^b (4 doubles a bin), which
@@ -1675,6 +1683,7 @@ __device__ __forceinline__ void spectra_wide_body(const BandDev &B, const float2
     constexpr int V = NS / 64;  // FFT values a lane
     constexpr int W = spw_waves(Q);  // wavefronts
     constexpr int S = PS ? 2 : 1;      // spectra streams per (detector, segment)
+    constexpr int TS = spw_segs(NS);   // segments per step
     const int n_k = B.n_k, R = B.R, N = B.n_fft, mask = B.nfft_mask;
     const SpwLayout Ly = spw_layout(Q, R, B.wide_ncol, B.wide_jmax, NS, S);
     // the wavefront index, uniform within the wavefront (readfirstlane makes that known to the
@@ -1768,147 +1777,162 @@ __device__ __forceinline__ void spectra_wide_body(const BandDev &B, const float2
     }
     int head = 0, tail = 0, tail_e = lo;
     const int mode = (cross ? 1 : 0) | (same ? 2 : 0) | (circ ? 4 : 0);
-    for (int e = lo; e < hi; ++e) {
-        const int K = ld_uniform(B.seg_any, e);
-        // this wavefront's transforms of step e
+    // steps of up to TS consecutive entries of the segment list: their transforms, one barrier,
+    // their pair sums in segment order, one barrier
+    for (int e0 = lo; e0 < hi; e0 += TS) {
+        const int nts = TS == 1 ? 1 : min(TS, hi - e0);  // uniform
+        // this wavefront's transforms of the step's segments; segment e0 + t goes to ring slot
+        // head + t (mod slots)
+#pragma unroll 1
+        for (int t = 0; t < nts; ++t) {
+            const int e = e0 + t;
+            const int K = ld_uniform(B.seg_any, e);
+            const int slot = head + t >= slots ? head + t - slots : head + t;
 #pragma unroll
-        for (int j = 0; j < NU; ++j) {
-            const int X = wv + W * (j / S);
-            float2 v[V];
+            for (int j = 0; j < NU; ++j) {
+                const int X = wv + W * (j / S);
+                float2 v[V];
 #pragma unroll
-            for (int r = 0; r < V; ++r) v[r] = cmul<float>(nxt[r], win[r]);
-            // the next unit's input (unconditional: the last step's last unit reloads its own)
-            if (j + 1 < NU) load(e, j + 1);
-            else load(min(e + 1, hi - 1), 0);
-            float2 *row = ring + (((size_t)head * Q + X) * S + j % S) * ncol1;
-            if (ld_uniform(B.seg_work, X * B.n_seg + K) < 0) {
-                // no data of detector X in K: with per-sample streams the ring row is zeroed (they
-                // carry no weight of their own), else its weights are zero
-                if constexpr (PS) {
+                for (int r = 0; r < V; ++r) v[r] = cmul<float>(nxt[r], win[r]);
+                // the next unit's input (unconditional: the last segment's last unit reloads its own)
+                if (j + 1 < NU) load(e, j + 1);
+                else load(min(e + 1, hi - 1), 0);
+                float2 *row = ring + (((size_t)slot * Q + X) * S + j % S) * ncol1;
+                if (ld_uniform(B.seg_work, X * B.n_seg + K) < 0) {
+                    // no data of detector X in K: with per-sample streams the ring row is zeroed
+                    // (they carry no weight of their own), else its weights are zero
+                    if constexpr (PS) {
 #pragma unroll
-                    for (int J = 0; J < V; ++J)
-                        if (J < jmax) row[(cpos[J >> 1] >> (16 * (J & 1))) & 0xffffu] = make_float2(0.f, 0.f);
+                        for (int J = 0; J < V; ++J)
+                            if (J < jmax) row[(cpos[J >> 1] >> (16 * (J & 1))) & 0xffffu] = make_float2(0.f, 0.f);
+                    }
+                    continue;
                 }
-                continue;
+                fft_wave<NS>(v, fx, wtw, lane);
+#pragma unroll
+                for (int J = 0; J < V; ++J)
+                    if (J < jmax) row[(cpos[J >> 1] >> (16 * (J & 1))) & 0xffffu] = v[J];
             }
-            fft_wave<NS>(v, fx, wtw, lane);
-#pragma unroll
-            for (int J = 0; J < V; ++J)
-                if (J < jmax) row[(cpos[J >> 1] >> (16 * (J & 1))) & 0xffffu] = v[J];
-        }
-        // pair weights of this step's spectra, zero where detector X has no data in segment K
-        float wa[Q], wb[Q];
-#pragma unroll
-        for (int X = 0; X < Q; ++X) {
-            const float2 w2 = ld_uniform_f2(B.segwf, X * B.n_seg + K);
-            wa[X] = w2.x;
-            wb[X] = w2.y;
         }
         __syncthreads();
-        // Phi_in and the pairs whose later member is segment K
-        const unsigned rB = (unsigned)(((int64_t)K * n_k) & mask);
-        const bool count_it = K >= K0;
-        const float invN = 1.0f / (float)N;
-#pragma unroll
-        for (int u = 0; u < U; ++u) {
-            const int col = wv * 64 + lane + 64 * W * u;
-            if (wv * 64 + 64 * W * u >= n_p) break;  // uniform: no lane of this wavefront has a bin here
-            float2 *slot = ring + (size_t)head * Q * S * ncol1 + (col < n_p ? col : ncol1 - 1);
-            float2 f[Q], g[Q];  // the step's spectra (stream a; g: stream b with per-sample streams)
+#pragma unroll 1
+        for (int t = 0; t < nts; ++t) {
+            const int e = e0 + t;
+            const int K = ld_uniform(B.seg_any, e);
+            // pair weights of this segment's spectra, zero where detector X has no data in it
+            float wa[Q], wb[Q];
 #pragma unroll
             for (int X = 0; X < Q; ++X) {
-                f[X] = slot[X * S * ncol1];
-                if constexpr (PS) g[X] = slot[(X * S + 1) * ncol1];
+                const float2 w2 = ld_uniform_f2(B.segwf, X * B.n_seg + K);
+                wa[X] = w2.x;
+                wb[X] = w2.y;
             }
-            const float ph = -(float)(((unsigned)kbc[u] * rB) & (unsigned)mask) * invN;  // revolutions
-            const float cph = __builtin_amdgcn_cosf(ph), sph = __builtin_amdgcn_sinf(ph);
+            // Phi_in and the pairs whose later member is segment K
+            const unsigned rB = (unsigned)(((int64_t)K * n_k) & mask);
+            const bool count_it = K >= K0;
+            const float invN = 1.0f / (float)N;
 #pragma unroll
-            for (int X = 0; X < Q; ++X) {
-                f[X] = make_float2(f[X].x * cph - f[X].y * sph, f[X].x * sph + f[X].y * cph);
-                if (col < n_p) slot[X * S * ncol1] = f[X];
-                if constexpr (PS) {
-                    g[X] = make_float2(g[X].x * cph - g[X].y * sph, g[X].x * sph + g[X].y * cph);
-                    if (col < n_p) slot[(X * S + 1) * ncol1] = g[X];
+            for (int u = 0; u < U; ++u) {
+                const int col = wv * 64 + lane + 64 * W * u;
+                if (wv * 64 + 64 * W * u >= n_p) break;  // uniform: no lane of this wavefront has a bin here
+                float2 *slot = ring + (size_t)head * Q * S * ncol1 + (col < n_p ? col : ncol1 - 1);
+                float2 f[Q], g[Q];  // the segment's spectra (stream a; g: stream b with per-sample streams)
+#pragma unroll
+                for (int X = 0; X < Q; ++X) {
+                    f[X] = slot[X * S * ncol1];
+                    if constexpr (PS) g[X] = slot[(X * S + 1) * ncol1];
                 }
-            }
-            if constexpr (ALLP) {
-                // this step's share of G^a and G^b: FP32 over the detectors, FP64 over steps
-                float2 ta = make_float2(0.f, 0.f), tb2 = make_float2(0.f, 0.f);
+                const float ph = -(float)(((unsigned)kbc[u] * rB) & (unsigned)mask) * invN;  // revolutions
+                const float cph = __builtin_amdgcn_cosf(ph), sph = __builtin_amdgcn_sinf(ph);
+#pragma unroll
+                for (int X = 0; X < Q; ++X) {
+                    f[X] = make_float2(f[X].x * cph - f[X].y * sph, f[X].x * sph + f[X].y * cph);
+                    if (col < n_p) slot[X * S * ncol1] = f[X];
+                    if constexpr (PS) {
+                        g[X] = make_float2(g[X].x * cph - g[X].y * sph, g[X].x * sph + g[X].y * cph);
+                        if (col < n_p) slot[(X * S + 1) * ncol1] = g[X];
+                    }
+                }
+                if constexpr (ALLP) {
+                    // this segment's share of G^a and G^b: FP32 over the detectors, FP64 over segments
+                    float2 ta = make_float2(0.f, 0.f), tb2 = make_float2(0.f, 0.f);
+#pragma unroll
+                    for (int X = 0; X < Q; ++X) {
+                        if constexpr (PS) {
+                            ta.x += f[X].x; ta.y += f[X].y;
+                            tb2.x += g[X].x; tb2.y += g[X].y;
+                        } else {
+                            ta.x = fmaf(wa[X], f[X].x, ta.x); ta.y = fmaf(wa[X], f[X].y, ta.y);
+                            tb2.x = fmaf(wb[X], f[X].x, tb2.x); tb2.y = fmaf(wb[X], f[X].y, tb2.y);
+                        }
+                    }
+                    sa[u].x += (double)ta.x; sa[u].y += (double)ta.y;
+                    sb[u].x += (double)tb2.x; sb[u].y += (double)tb2.y;
+                    continue;
+                }
+                if (count_it) {
+                    float st;
+                    switch (mode) {  // uniform
+                        case 1: st = wide_pair_term<Q, U, true, false, false, PS>(f, g, wa, wb, Ga, Gb, u); break;
+                        case 2: st = wide_pair_term<Q, U, false, true, false, PS>(f, g, wa, wb, Ga, Gb, u); break;
+                        case 3: st = wide_pair_term<Q, U, true, true, false, PS>(f, g, wa, wb, Ga, Gb, u); break;
+                        case 5: st = wide_pair_term<Q, U, true, false, true, PS>(f, g, wa, wb, Ga, Gb, u); break;
+                        case 6: st = wide_pair_term<Q, U, false, true, true, PS>(f, g, wa, wb, Ga, Gb, u); break;
+                        case 7: st = wide_pair_term<Q, U, true, true, true, PS>(f, g, wa, wb, Ga, Gb, u); break;
+                        default: st = 0.f;
+                    }
+                    acc[u] += (double)st;
+                }
 #pragma unroll
                 for (int X = 0; X < Q; ++X) {
                     if constexpr (PS) {
-                        ta.x += f[X].x; ta.y += f[X].y;
-                        tb2.x += g[X].x; tb2.y += g[X].y;
+                        Ga[X][u].x += f[X].x; Ga[X][u].y += f[X].y;
+                        Gb[X][u].x += g[X].x; Gb[X][u].y += g[X].y;
                     } else {
-                        ta.x = fmaf(wa[X], f[X].x, ta.x); ta.y = fmaf(wa[X], f[X].y, ta.y);
-                        tb2.x = fmaf(wb[X], f[X].x, tb2.x); tb2.y = fmaf(wb[X], f[X].y, tb2.y);
+                        Ga[X][u].x = fmaf(wa[X], f[X].x, Ga[X][u].x); Ga[X][u].y = fmaf(wa[X], f[X].y, Ga[X][u].y);
+                        Gb[X][u].x = fmaf(wb[X], f[X].x, Gb[X][u].x); Gb[X][u].y = fmaf(wb[X], f[X].y, Gb[X][u].y);
                     }
                 }
-                sa[u].x += (double)ta.x; sa[u].y += (double)ta.y;
-                sb[u].x += (double)tb2.x; sb[u].y += (double)tb2.y;
-                continue;
             }
-            if (count_it) {
-                float st;
-                switch (mode) {  // uniform
-                    case 1: st = wide_pair_term<Q, U, true, false, false, PS>(f, g, wa, wb, Ga, Gb, u); break;
-                    case 2: st = wide_pair_term<Q, U, false, true, false, PS>(f, g, wa, wb, Ga, Gb, u); break;
-                    case 3: st = wide_pair_term<Q, U, true, true, false, PS>(f, g, wa, wb, Ga, Gb, u); break;
-                    case 5: st = wide_pair_term<Q, U, true, false, true, PS>(f, g, wa, wb, Ga, Gb, u); break;
-                    case 6: st = wide_pair_term<Q, U, false, true, true, PS>(f, g, wa, wb, Ga, Gb, u); break;
-                    case 7: st = wide_pair_term<Q, U, true, true, true, PS>(f, g, wa, wb, Ga, Gb, u); break;
-                    default: st = 0.f;
-                }
-                acc[u] += (double)st;
-            }
-#pragma unroll
-            for (int X = 0; X < Q; ++X) {
-                if constexpr (PS) {
-                    Ga[X][u].x += f[X].x; Ga[X][u].y += f[X].y;
-                    Gb[X][u].x += g[X].x; Gb[X][u].y += g[X].y;
-                } else {
-                    Ga[X][u].x = fmaf(wa[X], f[X].x, Ga[X][u].x); Ga[X][u].y = fmaf(wa[X], f[X].y, Ga[X][u].y);
-                    Gb[X][u].x = fmaf(wb[X], f[X].x, Gb[X][u].x); Gb[X][u].y = fmaf(wb[X], f[X].y, Gb[X][u].y);
-                }
-            }
-        }
-        head = head + 1 == slots ? 0 : head + 1;
-        // spectra whose segment is more than R behind the next step's leave the window sums: the
-        // ring holds the steps tail_e .. e; their segments and weights come from the (uniform)
-        // segment list and weight table
-        if (!ALLP && e + 1 < hi) {
-            const int Kn = ld_uniform(B.seg_any, e + 1);
-            while (tail_e <= e) {
-                const int Kt = ld_uniform(B.seg_any, tail_e);
-                if (Kt >= Kn - R) break;
-                float wta[Q], wtb[Q];
-#pragma unroll
-                for (int X = 0; X < Q; ++X) {
-                    const float2 w2 = ld_uniform_f2(B.segwf, X * B.n_seg + Kt);
-                    wta[X] = w2.x;
-                    wtb[X] = w2.y;
-                }
-                const float2 *rowt = ring + (size_t)tail * Q * S * ncol1;
-#pragma unroll
-                for (int u = 0; u < U; ++u) {
-                    if (wv * 64 + 64 * W * u >= n_p) break;
-                    const int col = wv * 64 + lane + 64 * W * u;
-                    const float2 *gp = rowt + (col < n_p ? col : ncol1 - 1);
+            head = head + 1 == slots ? 0 : head + 1;
+            // spectra whose segment is more than R behind the next segment's leave the window
+            // sums: the ring holds the entries tail_e .. e; their segments and weights come from
+            // the (uniform) segment list and weight table.  A lane reads back only its own columns,
+            // which it rotated itself, so no barrier is needed within the step.
+            if (!ALLP && e + 1 < hi) {
+                const int Kn = ld_uniform(B.seg_any, e + 1);
+                while (tail_e <= e) {
+                    const int Kt = ld_uniform(B.seg_any, tail_e);
+                    if (Kt >= Kn - R) break;
+                    float wta[Q], wtb[Q];
 #pragma unroll
                     for (int X = 0; X < Q; ++X) {
-                        const float2 ga = gp[X * S * ncol1];
-                        if constexpr (PS) {
-                            const float2 gb = gp[(X * S + 1) * ncol1];
-                            Ga[X][u].x -= ga.x; Ga[X][u].y -= ga.y;
-                            Gb[X][u].x -= gb.x; Gb[X][u].y -= gb.y;
-                        } else {
-                            Ga[X][u].x = fmaf(-wta[X], ga.x, Ga[X][u].x); Ga[X][u].y = fmaf(-wta[X], ga.y, Ga[X][u].y);
-                            Gb[X][u].x = fmaf(-wtb[X], ga.x, Gb[X][u].x); Gb[X][u].y = fmaf(-wtb[X], ga.y, Gb[X][u].y);
+                        const float2 w2 = ld_uniform_f2(B.segwf, X * B.n_seg + Kt);
+                        wta[X] = w2.x;
+                        wtb[X] = w2.y;
+                    }
+                    const float2 *rowt = ring + (size_t)tail * Q * S * ncol1;
+#pragma unroll
+                    for (int u = 0; u < U; ++u) {
+                        if (wv * 64 + 64 * W * u >= n_p) break;
+                        const int col = wv * 64 + lane + 64 * W * u;
+                        const float2 *gp = rowt + (col < n_p ? col : ncol1 - 1);
+#pragma unroll
+                        for (int X = 0; X < Q; ++X) {
+                            const float2 ga = gp[X * S * ncol1];
+                            if constexpr (PS) {
+                                const float2 gb = gp[(X * S + 1) * ncol1];
+                                Ga[X][u].x -= ga.x; Ga[X][u].y -= ga.y;
+                                Gb[X][u].x -= gb.x; Gb[X][u].y -= gb.y;
+                            } else {
+                                Ga[X][u].x = fmaf(-wta[X], ga.x, Ga[X][u].x); Ga[X][u].y = fmaf(-wta[X], ga.y, Ga[X][u].y);
+                                Gb[X][u].x = fmaf(-wtb[X], ga.x, Gb[X][u].x); Gb[X][u].y = fmaf(-wtb[X], ga.y, Gb[X][u].y);
+                            }
                         }
                     }
+                    tail = tail + 1 == slots ? 0 : tail + 1;
+                    ++tail_e;
                 }
-                tail = tail + 1 == slots ? 0 : tail + 1;
-                ++tail_e;
             }
         }
         __syncthreads();
