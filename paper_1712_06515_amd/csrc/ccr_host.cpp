@@ -1183,11 +1183,11 @@ struct Variant {
     bool wps = false;    // wide: two spectra streams per segment (per-sample antenna functions)
     int wns = 0;         // wide: segment FFT length (256, 512 or 1024)
     int DT = 0, window = 0, n_s = 0, nr = 0, n_cheb = kCheb;
-    int wcols = 0, wqm = 0;  // wide: bins of a class per lane, detector count
+    int wcols = 0, wqm = 0, wts = 0;  // wide: bins of a class per lane, detector count, segments a step
     bool operator==(const Variant &o) const {
         return sp == o.sp && reg16 == o.reg16 && z4 == o.z4 && ss == o.ss && far == o.far && wide == o.wide &&
                DT == o.DT && window == o.window && n_s == o.n_s && nr == o.nr && n_cheb == o.n_cheb &&
-               wcols == o.wcols && wqm == o.wqm && wallp == o.wallp && wns == o.wns && wps == o.wps;
+               wcols == o.wcols && wqm == o.wqm && wts == o.wts && wallp == o.wallp && wns == o.wns && wps == o.wps;
     }
 };
 
@@ -1255,6 +1255,7 @@ Variant variant_of(const BandDev &bd, bool fp64, bool short_series, bool farrow,
         v.wns = bd.n_s;
         v.wcols = spectra_wide_cols(bd);
         v.wqm = bd.Q;
+        v.wts = spectra_wide_segs(bw);
     } else if (v.sp) {
         v.nr = spectra_pairs_rounds(bd);
         v.z4 = bd.n_k <= 192;
@@ -1504,7 +1505,7 @@ ccr_status run_rounds(ccr_ctx *c, const CallPlan &cp, size_t r0, size_t r1, bool
             HIP_OK(c, launch_spectra_pairs_m(db, di, r.n, (int)r.blocks[kStSpectra], r.v.nr, r.v.z4, r.lds, ws.y, part, s));
         } else if (r.v.wide) {
             LaunchTimer lt(c, 7, s, timing);
-            HIP_OK(c, launch_spectra_wide_m(db, di, r.n, (int)r.blocks[kStSpectra], r.v.wns, r.v.wcols, r.v.wqm,
+            HIP_OK(c, launch_spectra_wide_m(db, di, r.n, (int)r.blocks[kStSpectra], r.v.wns, r.v.wcols, r.v.wqm, r.v.wts,
                                             r.v.wallp, r.v.wps, r.lds, ws.y, part, s));
         } else {
             {

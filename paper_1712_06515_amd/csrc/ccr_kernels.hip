@@ -1623,21 +1623,16 @@ __device__ __forceinline__ float wide_pair_term(const float2 (&fa)[Q], const flo
 // columns) w 64 + l + 64 W u.
 __host__ __device__ constexpr int spw_waves(int q) { return q == 4 ? 2 : q; }
 
-// Segments per step of that kernel (transformed together, then their pair sums in order: one
-// pair of barriers a step).  Two for 1024-point segments (2 % faster on the 240-day workload,
-// the ring's extra slot still leaves four workgroups a CU); one for shorter ones, where two to
-// eight measured 1-10 % slower on the 64-band workload.
-__host__ __device__ constexpr int spw_segs(int ns) { return ns == 1024 ? 2 : 1; }
-
-// LDS of the spectra + pair-sum kernel for ns-point segments (bytes).
+// LDS of the spectra + pair-sum kernel for ns-point segments (bytes), with a ring of R + ts
+// spectra (the window's R segments and a step's ts new ones).
 struct SpwLayout {
     int slots, ncol1;
     size_t off_fx, off_ring, off_pos, total;
 };
 
-__host__ __device__ inline SpwLayout spw_layout(int Q, int R, int ncol, int jmax, int ns, int streams) {
+__host__ __device__ inline SpwLayout spw_layout(int Q, int R, int ncol, int jmax, int ns, int streams, int ts) {
     SpwLayout L;
-    L.slots = R + spw_segs(ns);  // the window's R segments and a step's new ones
+    L.slots = R + ts;
     L.ncol1 = ncol + 1;  // the last column of a ring row takes FFT outputs that are not output bins
     size_t o = 0;
     L.off_fx = o;  // one FFT exchange buffer per wavefront (ns values, padded)
@@ -1650,6 +1645,20 @@ __host__ __device__ inline SpwLayout spw_layout(int Q, int R, int ncol, int jmax
     return L;
 }
 
+// Segments per step of that kernel (transformed together, then their pair sums in order: one
+// pair of barriers a step).  Two for 1024-point segments when the ring's extra slot costs no
+// workgroup a CU (LDS of 160 KB a CU; at most 8 / W workgroups of W wavefronts at the kernel's
+// ~232 registers) and keeps within 64 KB: 2 % faster on the 240-day workload.  One otherwise,
+// and for shorter segments, where two to eight measured 1-10 % slower on the 64-band workload.
+__host__ __device__ inline int spw_segs(int Q, int R, int ncol, int jmax, int ns, int streams) {
+    if (ns != 1024) return 1;
+    const size_t l1 = spw_layout(Q, R, ncol, jmax, ns, streams, 1).total;
+    const size_t l2 = spw_layout(Q, R, ncol, jmax, ns, streams, 2).total;
+    const size_t cu = 160 * 1024, wmax = 8 / spw_waves(Q);
+    const size_t w1 = cu / l1 < wmax ? cu / l1 : wmax, w2 = cu / l2 < wmax ? cu / l2 : wmax;
+    return l2 <= 65536 && w2 >= w1 ? 2 : 1;
+}
+
 // Spectra + pair sum for NS-point segments, NS = 256, 512 or 1024 (split precision, N_FFT a power
 // of two, distinct bins): one workgroup of spw_waves(Q) wavefronts per (template, residue class p of
 // the output bins, chunk [K0, K1) of segments plus R halo segments before it).
@@ -1657,7 +1666,7 @@ __host__ __device__ inline SpwLayout spw_layout(int Q, int R, int ncol, int jmax
 //   seg_any) and each detector with data there, the zero-padded segment is multiplied by
 //   W_N^(q s), q = p + P m0 (class p, its bins rotated so that the class's output indices
 //   m0 .. m0 + span - 1 land on FFT outputs 0 .. span - 1), transformed by fft_wave<NS>, and its
-//   class-p bins are written to a ring of R + TS spectra in LDS (TS = spw_segs(NS) segments a
+//   class-p bins are written to a ring of R + TS spectra in LDS (TS = spw_segs(...) segments a
 //   step).  Each wavefront loads the input of its next transform while it computes the current
 //   one.
 //   Pair sum: each spectrum is rotated by Phi_in = exp(-2 pi i (kbar r_B mod N) / N) (the phase
@@ -1676,16 +1685,15 @@ __host__ __device__ inline SpwLayout spw_layout(int Q, int R, int ncol, int jmax
 //   partials are the chunk's stream sums G^a = sum hat a_XK F_XK and G^b (4 doubles a bin), which
 //   the finishing kernel combines.
 // U: bins of a class per lane (class size <= 64 W U, W = spw_waves(Q)); Q: the band's detector count.
-template <int NS, int U, int Q, bool ALLP, bool PS>
+template <int NS, int U, int Q, bool ALLP, bool PS, int TS>
 __device__ __forceinline__ void spectra_wide_body(const BandDev &B, const float2 *__restrict__ y, double *part,
                                                   int k_chunk, int n_chunks, int c, int p, int tb) {
     extern __shared__ __align__(16) unsigned char smem[];
     constexpr int V = NS / 64;  // FFT values a lane
     constexpr int W = spw_waves(Q);  // wavefronts
     constexpr int S = PS ? 2 : 1;      // spectra streams per (detector, segment)
-    constexpr int TS = spw_segs(NS);   // segments per step
     const int n_k = B.n_k, R = B.R, N = B.n_fft, mask = B.nfft_mask;
-    const SpwLayout Ly = spw_layout(Q, R, B.wide_ncol, B.wide_jmax, NS, S);
+    const SpwLayout Ly = spw_layout(Q, R, B.wide_ncol, B.wide_jmax, NS, S, TS);
     // the wavefront index, uniform within the wavefront (readfirstlane makes that known to the
     // compiler, so that per-wavefront addresses and buffer descriptors stay in scalar registers)
     const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
@@ -2586,7 +2594,7 @@ k_spectra_pairs_m(const BandDev *__restrict__ bands, const WorkItem *__restrict_
 // dispatcher hands workgroups to the 8 XCDs in turn, so block l runs on XCD l mod 8: the P class
 // workgroups of one (template, chunk) group are given indices with equal l mod 8, which puts
 // them on one XCD, where they read the group's resampled series through that XCD's L2.
-template <int NS, int U, int Q, bool ALLP, bool PS>
+template <int NS, int U, int Q, bool ALLP, bool PS, int TS>
 __global__ void __launch_bounds__(64 * spw_waves(Q))
 k_spectra_wide_m(const BandDev *__restrict__ bands, const WorkItem *__restrict__ items, int n_items,
                  const float2 *__restrict__ y, double *__restrict__ part) {
@@ -2604,7 +2612,7 @@ k_spectra_wide_m(const BandDev *__restrict__ bands, const WorkItem *__restrict__
         g = (G >> 3) * 8 + (l - full) / P;
         p = (l - full) % P;
     }
-    spectra_wide_body<NS, U, Q, ALLP, PS>(B, y + it.y_off, part + it.part_off, it.k_chunk, it.n_chunks, g % it.n_chunks, p,
+    spectra_wide_body<NS, U, Q, ALLP, PS, TS>(B, y + it.y_off, part + it.part_off, it.k_chunk, it.n_chunks, g % it.n_chunks, p,
                                    g / it.n_chunks);
 }
 
@@ -2792,12 +2800,16 @@ hipError_t launch_zero(void *p, size_t bytes, hipStream_t stream) {
 size_t spectra_pairs_lds(const BandDev &B) { return spair_layout(B.Q, B.n_f, B.R, B.n_fft).total; }
 
 size_t spectra_wide_lds(const BandDev &B) {
-    return spw_layout(B.Q, B.R, B.wide_ncol, B.wide_jmax, B.n_s, B.ps2 ? 2 : 1).total;
+    return spw_layout(B.Q, B.R, B.wide_ncol, B.wide_jmax, B.n_s, B.ps2 ? 2 : 1, spectra_wide_segs(B)).total;
 }
 
 // Bin columns of a class per lane: 1, 2 or 4, and 8 with one detector (one wavefront a
 // workgroup, so that a class of up to 512 bins still fits).
 static int spw_max_cols(int q) { return q == 1 ? 8 : 4; }
+
+int spectra_wide_segs(const BandDev &B) {
+    return spw_segs(B.Q, B.R, B.wide_ncol, B.wide_jmax, B.n_s, B.ps2 ? 2 : 1);
+}
 
 int spectra_wide_cols(const BandDev &B) {
     const int per = 64 * spw_waves(B.Q);  // bin columns a workgroup covers per U
@@ -2904,12 +2916,12 @@ hipError_t launch_spectra_pairs_m(const BandDev *bands, const WorkItem *items, i
     return hipGetLastError();
 }
 
-template <int NS, bool ALLP, bool PS>
+template <int NS, bool ALLP, bool PS, int TS>
 static void launch_spectra_wide_u(const BandDev *bands, const WorkItem *items, int n_items, int blocks, int cols,
                                   int q, size_t lds, const void *y, double *part, hipStream_t stream) {
 #define CCR_WIDE(U_, Q_)                                                                                            \
-    hipLaunchKernelGGL((k_spectra_wide_m<NS, U_, Q_, ALLP, PS>), dim3(blocks), dim3(64 * spw_waves(Q_)), lds, stream, bands, \
-                       items, n_items, (const float2 *)y, part)
+    hipLaunchKernelGGL((k_spectra_wide_m<NS, U_, Q_, ALLP, PS, TS>), dim3(blocks), dim3(64 * spw_waves(Q_)), lds, stream, \
+                       bands, items, n_items, (const float2 *)y, part)
 #define CCR_WIDE_Q(U_)          \
     do {                        \
         if (q == 1) CCR_WIDE(U_, 1); \
@@ -2925,22 +2937,25 @@ static void launch_spectra_wide_u(const BandDev *bands, const WorkItem *items, i
 #undef CCR_WIDE
 }
 
+template <int NS, int TS>
+static void launch_spectra_wide_f(const BandDev *bands, const WorkItem *items, int n_items, int blocks, int cols,
+                                  int q, bool allp, bool ps, size_t lds, const void *y, double *part,
+                                  hipStream_t stream) {
+    if (allp && ps) launch_spectra_wide_u<NS, true, true, TS>(bands, items, n_items, blocks, cols, q, lds, y, part, stream);
+    else if (allp) launch_spectra_wide_u<NS, true, false, TS>(bands, items, n_items, blocks, cols, q, lds, y, part, stream);
+    else if (ps) launch_spectra_wide_u<NS, false, true, TS>(bands, items, n_items, blocks, cols, q, lds, y, part, stream);
+    else launch_spectra_wide_u<NS, false, false, TS>(bands, items, n_items, blocks, cols, q, lds, y, part, stream);
+}
+
 hipError_t launch_spectra_wide_m(const BandDev *bands, const WorkItem *items, int n_items, int blocks, int ns,
-                                 int cols, int q, bool allp, bool ps, size_t lds, const void *y, double *part,
+                                 int cols, int q, int ts, bool allp, bool ps, size_t lds, const void *y, double *part,
                                  hipStream_t stream) {
     if (blocks == 0) return hipSuccess;
-#define CCR_WIDE_NS(NS_)                                                                                          \
-    do {                                                                                                          \
-        if (allp && ps) launch_spectra_wide_u<NS_, true, true>(bands, items, n_items, blocks, cols, q, lds, y, part, stream); \
-        else if (allp) launch_spectra_wide_u<NS_, true, false>(bands, items, n_items, blocks, cols, q, lds, y, part, stream); \
-        else if (ps) launch_spectra_wide_u<NS_, false, true>(bands, items, n_items, blocks, cols, q, lds, y, part, stream); \
-        else launch_spectra_wide_u<NS_, false, false>(bands, items, n_items, blocks, cols, q, lds, y, part, stream); \
-    } while (0)
-    if (ns == 1024) CCR_WIDE_NS(1024);
-    else if (ns == 512) CCR_WIDE_NS(512);
-    else if (ns == 256) CCR_WIDE_NS(256);
+    if (ns == 1024 && ts == 2) launch_spectra_wide_f<1024, 2>(bands, items, n_items, blocks, cols, q, allp, ps, lds, y, part, stream);
+    else if (ns == 1024 && ts == 1) launch_spectra_wide_f<1024, 1>(bands, items, n_items, blocks, cols, q, allp, ps, lds, y, part, stream);
+    else if (ns == 512 && ts == 1) launch_spectra_wide_f<512, 1>(bands, items, n_items, blocks, cols, q, allp, ps, lds, y, part, stream);
+    else if (ns == 256 && ts == 1) launch_spectra_wide_f<256, 1>(bands, items, n_items, blocks, cols, q, allp, ps, lds, y, part, stream);
     else return hipErrorInvalidValue;
-#undef CCR_WIDE_NS
     return hipGetLastError();
 }
 
