@@ -1183,11 +1183,12 @@ struct Variant {
     bool wps = false;    // wide: two spectra streams per segment (per-sample antenna functions)
     int wns = 0;         // wide: segment FFT length (256, 512 or 1024)
     int DT = 0, window = 0, n_s = 0, nr = 0, n_cheb = kCheb;
-    int wcols = 0, wqm = 0, wts = 0;  // wide: bins of a class per lane, detector count, segments a step
+    int wcols = 0, wqm = 0, wts = 0, wwv = 0;  // wide: bins of a class per lane, detector count,
+                                               // segments a step, wavefronts a workgroup
     bool operator==(const Variant &o) const {
         return sp == o.sp && reg16 == o.reg16 && z4 == o.z4 && ss == o.ss && far == o.far && wide == o.wide &&
                DT == o.DT && window == o.window && n_s == o.n_s && nr == o.nr && n_cheb == o.n_cheb &&
-               wcols == o.wcols && wqm == o.wqm && wts == o.wts && wallp == o.wallp && wns == o.wns && wps == o.wps;
+               wcols == o.wcols && wqm == o.wqm && wts == o.wts && wwv == o.wwv && wallp == o.wallp && wns == o.wns && wps == o.wps;
     }
 };
 
@@ -1256,6 +1257,7 @@ Variant variant_of(const BandDev &bd, bool fp64, bool short_series, bool farrow,
         v.wcols = spectra_wide_cols(bd);
         v.wqm = bd.Q;
         v.wts = spectra_wide_segs(bw);
+        v.wwv = spectra_wide_waves(bw);
     } else if (v.sp) {
         v.nr = spectra_pairs_rounds(bd);
         v.z4 = bd.n_k <= 192;
@@ -1273,7 +1275,7 @@ int64_t stage_max_blocks(const Variant &v, int st) {
     int threads = 64;
     if (st == kStTimebase) threads = tb_entries(v.n_cheb) * v.n_cheb;
     else if (st == kStResample) threads = v.far ? 256 : 64;
-    else if (st == kStSpectra) threads = v.sp ? 64 : (v.wide ? 64 * (v.wqm == 4 ? 2 : v.wqm) : (v.reg16 ? 128 : spectra_threads(v.n_s)));
+    else if (st == kStSpectra) threads = v.sp ? 64 : (v.wide ? 64 * v.wwv : (v.reg16 ? 128 : spectra_threads(v.n_s)));
     else if (st == kStPairs) threads = kPairsThreads;
     else if (st == kStFinish) threads = kFinishThreads;
     return std::min<int64_t>(kMaxBlocks, (((int64_t)1 << 32) - 1) / threads);
@@ -1505,7 +1507,7 @@ ccr_status run_rounds(ccr_ctx *c, const CallPlan &cp, size_t r0, size_t r1, bool
             HIP_OK(c, launch_spectra_pairs_m(db, di, r.n, (int)r.blocks[kStSpectra], r.v.nr, r.v.z4, r.lds, ws.y, part, s));
         } else if (r.v.wide) {
             LaunchTimer lt(c, 7, s, timing);
-            HIP_OK(c, launch_spectra_wide_m(db, di, r.n, (int)r.blocks[kStSpectra], r.v.wns, r.v.wcols, r.v.wqm, r.v.wts,
+            HIP_OK(c, launch_spectra_wide_m(db, di, r.n, (int)r.blocks[kStSpectra], r.v.wns, r.v.wcols, r.v.wqm, r.v.wts, r.v.wwv,
                                             r.v.wallp, r.v.wps, r.lds, ws.y, part, s));
         } else {
             {

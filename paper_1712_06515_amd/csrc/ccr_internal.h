@@ -202,17 +202,18 @@ hipError_t launch_farrow_table(const float2 *x, int64_t n, int Q, int D, const d
                                float2 *tab, hipStream_t stream);
 // Split-precision spectra + pair sum for 256- to 1024-point segments (N_FFT a power of two,
 // distinct bins, at most 4 detectors, classes of at most 64 W U bins, LDS within `limit`); its
-// LDS bytes, the bins of a class per lane it is instantiated for (1, 2, 4 or 8) and the
-// segments it transforms a step (1 or 2).
+// LDS bytes, the bins of a class per lane it is instantiated for (1, 2, 4 or 8), the segments
+// it transforms a step (1 or 2) and its wavefronts a workgroup.
 bool spectra_wide_ok(const BandDev &B, bool fp64, size_t limit);
 size_t spectra_wide_lds(const BandDev &B);
 int spectra_wide_cols(const BandDev &B);
 int spectra_wide_segs(const BandDev &B);
-// cols, ts: spectra_wide_cols and spectra_wide_segs of the round's bands; q: their detector
-// count (1-4, the same for all).
+int spectra_wide_waves(const BandDev &B);
+// cols, ts, waves: spectra_wide_cols, spectra_wide_segs and spectra_wide_waves of the round's
+// bands; q: their detector count (1-4, the same for all).
 hipError_t launch_spectra_wide_m(const BandDev *bands, const WorkItem *items, int n_items, int blocks, int ns,
-                                 int cols, int q, int ts, bool allp, bool ps, size_t lds, const void *y, double *part,
-                                 hipStream_t stream);
+                                 int cols, int q, int ts, int waves, bool allp, bool ps, size_t lds, const void *y,
+                                 double *part, hipStream_t stream);
 // z4: N_K <= 192, so the last 4 of the 16 input rows of each 256-point FFT are zero padding.
 hipError_t launch_spectra_pairs_m(const BandDev *bands, const WorkItem *items, int n_items, int blocks, int rounds,
                                   bool z4, size_t lds, const void *y, double *part, hipStream_t stream);

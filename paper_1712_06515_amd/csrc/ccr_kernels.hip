@@ -1617,10 +1617,12 @@ __device__ __forceinline__ float wide_pair_term(const float2 (&fa)[Q], const flo
     return st;
 }
 
-// Workgroup of the spectra + pair-sum kernel for 256- to 1024-point segments: spw_waves(Q)
-// wavefronts share one spectrum ring; wavefront w transforms the detectors X = w, w + W, ...
-// (one each for up to 3 detectors, two each for 4) and sums the pairs of the bins (ring
-// columns) w 64 + l + 64 W u.
+// Workgroup of the spectra + pair-sum kernel for 256- to 1024-point segments: W wavefronts share
+// one spectrum ring; wavefront w transforms the detectors X = w, w + W, ... and sums the pairs
+// of the bins (ring columns) w 64 + l + 64 W u.  W = spw_waves(Q) (one wavefront a detector up
+// to 3 detectors, two for 4), or one for 256-point segments whose classes one wavefront covers
+// (its short transforms then run back to back, and its barriers cost nothing: 13 % faster on
+// the 64-band workload).
 __host__ __device__ constexpr int spw_waves(int q) { return q == 4 ? 2 : q; }
 
 // LDS of the spectra + pair-sum kernel for ns-point segments (bytes), with a ring of R + ts
@@ -1630,13 +1632,13 @@ struct SpwLayout {
     size_t off_fx, off_ring, off_pos, total;
 };
 
-__host__ __device__ inline SpwLayout spw_layout(int Q, int R, int ncol, int jmax, int ns, int streams, int ts) {
+__host__ __device__ inline SpwLayout spw_layout(int Q, int R, int ncol, int jmax, int ns, int streams, int ts, int w) {
     SpwLayout L;
     L.slots = R + ts;
     L.ncol1 = ncol + 1;  // the last column of a ring row takes FFT outputs that are not output bins
     size_t o = 0;
     L.off_fx = o;  // one FFT exchange buffer per wavefront (ns values, padded)
-    o += (size_t)spw_waves(Q) * (ns + 64) * sizeof(float2);
+    o += (size_t)w * (ns + 64) * sizeof(float2);
     L.off_ring = o;
     o += (size_t)L.slots * Q * streams * L.ncol1 * sizeof(float2);
     L.off_pos = o;
@@ -1650,17 +1652,17 @@ __host__ __device__ inline SpwLayout spw_layout(int Q, int R, int ncol, int jmax
 // workgroup a CU (LDS of 160 KB a CU; at most 8 / W workgroups of W wavefronts at the kernel's
 // ~232 registers) and keeps within 64 KB: 2 % faster on the 240-day workload.  One otherwise,
 // and for shorter segments, where two to eight measured 1-10 % slower on the 64-band workload.
-__host__ __device__ inline int spw_segs(int Q, int R, int ncol, int jmax, int ns, int streams) {
+__host__ __device__ inline int spw_segs(int Q, int R, int ncol, int jmax, int ns, int streams, int w) {
     if (ns != 1024) return 1;
-    const size_t l1 = spw_layout(Q, R, ncol, jmax, ns, streams, 1).total;
-    const size_t l2 = spw_layout(Q, R, ncol, jmax, ns, streams, 2).total;
-    const size_t cu = 160 * 1024, wmax = 8 / spw_waves(Q);
+    const size_t l1 = spw_layout(Q, R, ncol, jmax, ns, streams, 1, w).total;
+    const size_t l2 = spw_layout(Q, R, ncol, jmax, ns, streams, 2, w).total;
+    const size_t cu = 160 * 1024, wmax = 8 / w;
     const size_t w1 = cu / l1 < wmax ? cu / l1 : wmax, w2 = cu / l2 < wmax ? cu / l2 : wmax;
     return l2 <= 65536 && w2 >= w1 ? 2 : 1;
 }
 
 // Spectra + pair sum for NS-point segments, NS = 256, 512 or 1024 (split precision, N_FFT a power
-// of two, distinct bins): one workgroup of spw_waves(Q) wavefronts per (template, residue class p of
+// of two, distinct bins): one workgroup of W wavefronts per (template, residue class p of
 // the output bins, chunk [K0, K1) of segments plus R halo segments before it).
 //   Spectra: for each segment K that some detector takes part in (the compacted list
 //   seg_any) and each detector with data there, the zero-padded segment is multiplied by
@@ -1684,16 +1686,15 @@ __host__ __device__ inline int spw_segs(int Q, int R, int ncol, int jmax, int ns
 //   from the same window sums.  ALLP (every ordered pair, autos included): no windows; the
 //   partials are the chunk's stream sums G^a = sum hat a_XK F_XK and G^b (4 doubles a bin), which
 //   the finishing kernel combines.
-// U: bins of a class per lane (class size <= 64 W U, W = spw_waves(Q)); Q: the band's detector count.
-template <int NS, int U, int Q, bool ALLP, bool PS, int TS>
+// U: bins of a class per lane (class size <= 64 W U); Q: the band's detector count; W: wavefronts.
+template <int NS, int U, int Q, bool ALLP, bool PS, int TS, int W>
 __device__ __forceinline__ void spectra_wide_body(const BandDev &B, const float2 *__restrict__ y, double *part,
                                                   int k_chunk, int n_chunks, int c, int p, int tb) {
     extern __shared__ __align__(16) unsigned char smem[];
     constexpr int V = NS / 64;  // FFT values a lane
-    constexpr int W = spw_waves(Q);  // wavefronts
     constexpr int S = PS ? 2 : 1;      // spectra streams per (detector, segment)
     const int n_k = B.n_k, R = B.R, N = B.n_fft, mask = B.nfft_mask;
-    const SpwLayout Ly = spw_layout(Q, R, B.wide_ncol, B.wide_jmax, NS, S, TS);
+    const SpwLayout Ly = spw_layout(Q, R, B.wide_ncol, B.wide_jmax, NS, S, TS, W);
     // the wavefront index, uniform within the wavefront (readfirstlane makes that known to the
     // compiler, so that per-wavefront addresses and buffer descriptors stay in scalar registers)
     const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
@@ -2594,8 +2595,8 @@ k_spectra_pairs_m(const BandDev *__restrict__ bands, const WorkItem *__restrict_
 // dispatcher hands workgroups to the 8 XCDs in turn, so block l runs on XCD l mod 8: the P class
 // workgroups of one (template, chunk) group are given indices with equal l mod 8, which puts
 // them on one XCD, where they read the group's resampled series through that XCD's L2.
-template <int NS, int U, int Q, bool ALLP, bool PS, int TS>
-__global__ void __launch_bounds__(64 * spw_waves(Q))
+template <int NS, int U, int Q, bool ALLP, bool PS, int TS, int W>
+__global__ void __launch_bounds__(64 * W)
 k_spectra_wide_m(const BandDev *__restrict__ bands, const WorkItem *__restrict__ items, int n_items,
                  const float2 *__restrict__ y, double *__restrict__ part) {
     const WorkItem &it = items[find_item(items, n_items, kStSpectra, blockIdx.x)];
@@ -2612,7 +2613,7 @@ k_spectra_wide_m(const BandDev *__restrict__ bands, const WorkItem *__restrict__
         g = (G >> 3) * 8 + (l - full) / P;
         p = (l - full) % P;
     }
-    spectra_wide_body<NS, U, Q, ALLP, PS, TS>(B, y + it.y_off, part + it.part_off, it.k_chunk, it.n_chunks, g % it.n_chunks, p,
+    spectra_wide_body<NS, U, Q, ALLP, PS, TS, W>(B, y + it.y_off, part + it.part_off, it.k_chunk, it.n_chunks, g % it.n_chunks, p,
                                    g / it.n_chunks);
 }
 
@@ -2799,20 +2800,26 @@ hipError_t launch_zero(void *p, size_t bytes, hipStream_t stream) {
 
 size_t spectra_pairs_lds(const BandDev &B) { return spair_layout(B.Q, B.n_f, B.R, B.n_fft).total; }
 
-size_t spectra_wide_lds(const BandDev &B) {
-    return spw_layout(B.Q, B.R, B.wide_ncol, B.wide_jmax, B.n_s, B.ps2 ? 2 : 1, spectra_wide_segs(B)).total;
-}
-
 // Bin columns of a class per lane: 1, 2 or 4, and 8 with one detector (one wavefront a
 // workgroup, so that a class of up to 512 bins still fits).
 static int spw_max_cols(int q) { return q == 1 ? 8 : 4; }
 
+int spectra_wide_waves(const BandDev &B) {
+    return B.n_s == 256 && B.wide_ncol <= spw_max_cols(B.Q) * 64 ? 1 : spw_waves(B.Q);
+}
+
 int spectra_wide_segs(const BandDev &B) {
-    return spw_segs(B.Q, B.R, B.wide_ncol, B.wide_jmax, B.n_s, B.ps2 ? 2 : 1);
+    return spw_segs(B.Q, B.R, B.wide_ncol, B.wide_jmax, B.n_s, B.ps2 ? 2 : 1, spectra_wide_waves(B));
+}
+
+size_t spectra_wide_lds(const BandDev &B) {
+    return spw_layout(B.Q, B.R, B.wide_ncol, B.wide_jmax, B.n_s, B.ps2 ? 2 : 1, spectra_wide_segs(B),
+                      spectra_wide_waves(B))
+        .total;
 }
 
 int spectra_wide_cols(const BandDev &B) {
-    const int per = 64 * spw_waves(B.Q);  // bin columns a workgroup covers per U
+    const int per = 64 * spectra_wide_waves(B);  // bin columns a workgroup covers per U
     return B.wide_ncol <= per ? 1 : (B.wide_ncol <= 2 * per ? 2 : (B.wide_ncol <= 4 * per ? 4 : 8));
 }
 
@@ -2916,12 +2923,13 @@ hipError_t launch_spectra_pairs_m(const BandDev *bands, const WorkItem *items, i
     return hipGetLastError();
 }
 
-template <int NS, bool ALLP, bool PS, int TS>
+template <int NS, bool ALLP, bool PS, int TS, bool ONE>
 static void launch_spectra_wide_u(const BandDev *bands, const WorkItem *items, int n_items, int blocks, int cols,
                                   int q, size_t lds, const void *y, double *part, hipStream_t stream) {
-#define CCR_WIDE(U_, Q_)                                                                                            \
-    hipLaunchKernelGGL((k_spectra_wide_m<NS, U_, Q_, ALLP, PS, TS>), dim3(blocks), dim3(64 * spw_waves(Q_)), lds, stream, \
-                       bands, items, n_items, (const float2 *)y, part)
+#define CCR_WIDE(U_, Q_)                                                                                              \
+    hipLaunchKernelGGL((k_spectra_wide_m<NS, U_, Q_, ALLP, PS, TS, ONE ? 1 : spw_waves(Q_)>),                       \
+                       dim3(blocks), dim3(64 * (ONE ? 1 : spw_waves(Q_))), lds, stream, bands, items, n_items,       \
+                       (const float2 *)y, part)
 #define CCR_WIDE_Q(U_)          \
     do {                        \
         if (q == 1) CCR_WIDE(U_, 1); \
@@ -2937,24 +2945,26 @@ static void launch_spectra_wide_u(const BandDev *bands, const WorkItem *items, i
 #undef CCR_WIDE
 }
 
-template <int NS, int TS>
+template <int NS, int TS, bool ONE>
 static void launch_spectra_wide_f(const BandDev *bands, const WorkItem *items, int n_items, int blocks, int cols,
                                   int q, bool allp, bool ps, size_t lds, const void *y, double *part,
                                   hipStream_t stream) {
-    if (allp && ps) launch_spectra_wide_u<NS, true, true, TS>(bands, items, n_items, blocks, cols, q, lds, y, part, stream);
-    else if (allp) launch_spectra_wide_u<NS, true, false, TS>(bands, items, n_items, blocks, cols, q, lds, y, part, stream);
-    else if (ps) launch_spectra_wide_u<NS, false, true, TS>(bands, items, n_items, blocks, cols, q, lds, y, part, stream);
-    else launch_spectra_wide_u<NS, false, false, TS>(bands, items, n_items, blocks, cols, q, lds, y, part, stream);
+    if (allp && ps) launch_spectra_wide_u<NS, true, true, TS, ONE>(bands, items, n_items, blocks, cols, q, lds, y, part, stream);
+    else if (allp) launch_spectra_wide_u<NS, true, false, TS, ONE>(bands, items, n_items, blocks, cols, q, lds, y, part, stream);
+    else if (ps) launch_spectra_wide_u<NS, false, true, TS, ONE>(bands, items, n_items, blocks, cols, q, lds, y, part, stream);
+    else launch_spectra_wide_u<NS, false, false, TS, ONE>(bands, items, n_items, blocks, cols, q, lds, y, part, stream);
 }
 
 hipError_t launch_spectra_wide_m(const BandDev *bands, const WorkItem *items, int n_items, int blocks, int ns,
-                                 int cols, int q, int ts, bool allp, bool ps, size_t lds, const void *y, double *part,
-                                 hipStream_t stream) {
+                                 int cols, int q, int ts, int waves, bool allp, bool ps, size_t lds, const void *y,
+                                 double *part, hipStream_t stream) {
     if (blocks == 0) return hipSuccess;
-    if (ns == 1024 && ts == 2) launch_spectra_wide_f<1024, 2>(bands, items, n_items, blocks, cols, q, allp, ps, lds, y, part, stream);
-    else if (ns == 1024 && ts == 1) launch_spectra_wide_f<1024, 1>(bands, items, n_items, blocks, cols, q, allp, ps, lds, y, part, stream);
-    else if (ns == 512 && ts == 1) launch_spectra_wide_f<512, 1>(bands, items, n_items, blocks, cols, q, allp, ps, lds, y, part, stream);
-    else if (ns == 256 && ts == 1) launch_spectra_wide_f<256, 1>(bands, items, n_items, blocks, cols, q, allp, ps, lds, y, part, stream);
+    const bool one = waves == 1 && q > 1;  // one detector has one wavefront either way
+    if (ns == 1024 && ts == 2 && !one) launch_spectra_wide_f<1024, 2, false>(bands, items, n_items, blocks, cols, q, allp, ps, lds, y, part, stream);
+    else if (ns == 1024 && ts == 1 && !one) launch_spectra_wide_f<1024, 1, false>(bands, items, n_items, blocks, cols, q, allp, ps, lds, y, part, stream);
+    else if (ns == 512 && ts == 1 && !one) launch_spectra_wide_f<512, 1, false>(bands, items, n_items, blocks, cols, q, allp, ps, lds, y, part, stream);
+    else if (ns == 256 && ts == 1 && !one) launch_spectra_wide_f<256, 1, false>(bands, items, n_items, blocks, cols, q, allp, ps, lds, y, part, stream);
+    else if (ns == 256 && ts == 1 && one) launch_spectra_wide_f<256, 1, true>(bands, items, n_items, blocks, cols, q, allp, ps, lds, y, part, stream);
     else return hipErrorInvalidValue;
     return hipGetLastError();
 }
