@@ -1620,9 +1620,9 @@ __device__ __forceinline__ float wide_pair_term(const float2 (&fa)[Q], const flo
 // Workgroup of the spectra + pair-sum kernel for 256- to 1024-point segments: W wavefronts share
 // one spectrum ring; wavefront w transforms the detectors X = w, w + W, ... and sums the pairs
 // of the bins (ring columns) w 64 + l + 64 W u.  W = spw_waves(Q) (one wavefront a detector up
-// to 3 detectors, two for 4), or one for 256-point segments whose classes one wavefront covers
-// (its short transforms then run back to back, and its barriers cost nothing: 13 % faster on
-// the 64-band workload).
+// to 3 detectors, two for 4), or one for 256- and 512-point segments whose classes one wavefront
+// covers (its short transforms then run back to back, and its barriers cost nothing: 15 %
+// faster on the 64-band workload).
 __host__ __device__ constexpr int spw_waves(int q) { return q == 4 ? 2 : q; }
 
 // LDS of the spectra + pair-sum kernel for ns-point segments (bytes), with a ring of R + ts
@@ -2805,7 +2805,7 @@ size_t spectra_pairs_lds(const BandDev &B) { return spair_layout(B.Q, B.n_f, B.R
 static int spw_max_cols(int q) { return q == 1 ? 8 : 4; }
 
 int spectra_wide_waves(const BandDev &B) {
-    return B.n_s == 256 && B.wide_ncol <= spw_max_cols(B.Q) * 64 ? 1 : spw_waves(B.Q);
+    return B.n_s <= 512 && B.wide_ncol <= spw_max_cols(B.Q) * 64 ? 1 : spw_waves(B.Q);
 }
 
 int spectra_wide_segs(const BandDev &B) {
@@ -2965,6 +2965,7 @@ hipError_t launch_spectra_wide_m(const BandDev *bands, const WorkItem *items, in
     else if (ns == 512 && ts == 1 && !one) launch_spectra_wide_f<512, 1, false>(bands, items, n_items, blocks, cols, q, allp, ps, lds, y, part, stream);
     else if (ns == 256 && ts == 1 && !one) launch_spectra_wide_f<256, 1, false>(bands, items, n_items, blocks, cols, q, allp, ps, lds, y, part, stream);
     else if (ns == 256 && ts == 1 && one) launch_spectra_wide_f<256, 1, true>(bands, items, n_items, blocks, cols, q, allp, ps, lds, y, part, stream);
+    else if (ns == 512 && ts == 1 && one) launch_spectra_wide_f<512, 1, true>(bands, items, n_items, blocks, cols, q, allp, ps, lds, y, part, stream);
     else return hipErrorInvalidValue;
     return hipGetLastError();
 }
